@@ -1,0 +1,143 @@
+"""Sequential parallel-Newton loop (test infrastructure): Alg. alg:deer, one step at a time.
+
+Each iteration, for the current guess s^(i):
+  1. residual r_t = s_t - f_t(s_{t-1}) for every t, with s_0 fixed (eq. r_def);
+  2. stop when max |r| < tol (the stopping quantity is left open by the thesis's
+     ComputeError; the oracle uses the infinity norm of the residual, or optionally the
+     infinity norm of the last update as in the Ch. 3 GRU experiments);
+  3. transition matrices A~_t chosen per Tab. fxd_pt_sum:
+        "dense"  (Newton / DEER)       A~_t = A_t = df_t/ds_{t-1}(s_{t-1})   (eq. lil_j)
+        "diag"   (quasi-Newton)        A~_t = diag(A_t)                      (eq. quasi_lds)
+        "picard"                        A~_t = I                              (Prop. prop:picard)
+        "jacobi"                        A~_t = 0                              (Prop. prop:jacobi)
+        "scale:k" (scale-ELK)           A~_t = (1 - k) A_t
+        "clip"   (clip-ELK)            A~_t = clip(diag(A_t), -1, 1)
+     or any callable returning them;
+  4. the Newton step solves J~ Delta = -r by forward substitution (eq. lin_rr):
+        Delta_1 = -r_1,   Delta_t = A~_t Delta_{t-1} - r_t;
+  5. s <- s + Delta, then the reset heuristic (Ch. 3 global-convergence discussion and the
+     trained AR-GRU experiment of Ch. 4): any time-step vector that is non-finite or has an
+     entry larger than ``reset_abs`` in magnitude is set to zero.
+
+The iteration count is the number of updates applied; the result is returned as soon as
+the stopping test passes on the current iterate.  By Prop. prop:global_convergence the
+loop ends within T updates for every choice of A~_t (exact arithmetic).
+"""
+import numpy as np
+
+
+def linearize(cell, x, s0, s):
+    """Residuals and the arguments every transition-matrix choice needs.
+
+    Returns (h, r) where h[t] = s_{t-1} (h[0] = s_0) and r[t] = s_t - f_t(s_{t-1}).
+    """
+    T = x.shape[0]
+    h = np.concatenate([np.asarray(s0, np.float64)[None], s[:-1]], axis=0)
+    tt = np.arange(T)
+    r = s - cell.f(h, x, t=tt)
+    return h, r
+
+
+def transition_matrices(cell, x, h, mode):
+    """A~_t for every t as dense [T, D, D] matrices (diagonal modes stored densely)."""
+    T, D = h.shape
+    tt = np.arange(T)
+    if callable(mode):
+        return np.asarray(mode(cell, x, h), np.float64)
+    if mode == "dense":
+        return cell.jac(h, x, t=tt)
+    if mode == "diag":
+        return np.einsum("ti,ij->tij", cell.jac_diag(h, x, t=tt), np.eye(D))
+    if mode == "picard":
+        return np.broadcast_to(np.eye(D), (T, D, D)).copy()
+    if mode == "jacobi":
+        return np.zeros((T, D, D))
+    if mode == "clip":
+        d = np.clip(cell.jac_diag(h, x, t=tt), -1.0, 1.0)
+        return np.einsum("ti,ij->tij", d, np.eye(D))
+    if isinstance(mode, str) and mode.startswith("scale:"):
+        k = float(mode.split(":", 1)[1])
+        return (1.0 - k) * cell.jac(h, x, t=tt)
+    raise ValueError(mode)
+
+
+def forward_substitution(At, r):
+    """Solve J~ Delta = -r for block-bidiagonal J~ (eq. big_j) by eq. lin_rr.
+
+    At [T, D, D] (At[0] is never used: Delta_0 = 0 because s_0 is fixed), r [T, D].
+    """
+    T, D = r.shape
+    delta = np.empty((T, D))
+    prev = np.zeros(D)
+    with np.errstate(over="ignore", invalid="ignore"):
+        for t in range(T):
+            prev = (At[t] @ prev if t > 0 else 0.0) - r[t]
+            delta[t] = prev
+    return delta
+
+
+def apply_reset(s, reset_abs):
+    """Reset heuristic: zero every time-step vector that is non-finite or too large."""
+    with np.errstate(invalid="ignore"):
+        bad = ~np.isfinite(s).all(axis=1) | (np.abs(s).max(axis=1) > reset_abs)
+    s[bad] = 0.0
+    return int(bad.sum())
+
+
+def newton(cell, x, s0, s_init=None, mode="dense", tol=1e-10, max_iters=None,
+           reset_abs=1e4, stop="resid", step=None, history=False):
+    """Run the loop on one sequence.  ``step`` replaces step 4 (used by ELK).
+
+    Returns a dict: s, iters, converged, resets, max_resid, and optionally the list of
+    iterates (``history``, s^(0) first) and residual norms.
+    """
+    x = np.asarray(x, np.float64)
+    T, D = x.shape[0], cell.D
+    s = np.zeros((T, D)) if s_init is None else np.array(s_init, np.float64)
+    max_iters = T if max_iters is None else int(max_iters)
+    hist = [s.copy()] if history else None
+    norms = []
+    resets = 0
+    i = 0
+    while True:
+        h, r = linearize(cell, x, s0, s)
+        with np.errstate(invalid="ignore"):
+            rn = float(np.max(np.abs(r))) if T else 0.0
+        norms.append(rn)
+        if stop == "resid" and rn < tol:
+            return dict(s=s, iters=i, converged=True, resets=resets, max_resid=rn,
+                        history=hist, resid_norms=norms)
+        if i >= max_iters:
+            return dict(s=s, iters=i, converged=False, resets=resets, max_resid=rn,
+                        history=hist, resid_norms=norms)
+        At = transition_matrices(cell, x, h, mode) if step is None else None
+        delta = forward_substitution(At, r) if step is None else step(cell, x, h, r)
+        with np.errstate(invalid="ignore", over="ignore"):
+            s = s + delta
+        resets += apply_reset(s, reset_abs)
+        i += 1
+        if history:
+            hist.append(s.copy())
+        if stop == "delta":
+            with np.errstate(invalid="ignore"):
+                dn = float(np.max(np.abs(delta)))
+            if dn < tol:
+                _, r2 = linearize(cell, x, s0, s)
+                return dict(s=s, iters=i, converged=True, resets=resets,
+                            max_resid=float(np.max(np.abs(r2))), history=hist,
+                            resid_norms=norms)
+
+
+def newton_batch(cell, x, s0, offsets, **kw):
+    """``newton`` on every sequence of a back-to-back batch; returns (s [N, D], infos)."""
+    offsets = np.asarray(offsets, np.int64)
+    s = np.empty((x.shape[0], cell.D))
+    infos = []
+    s_init = kw.pop("s_init", None)
+    for b in range(offsets.size - 1):
+        a, e = offsets[b], offsets[b + 1]
+        init = None if s_init is None else s_init[a:e]
+        out = newton(cell, x[a:e], s0[b], s_init=init, **kw)
+        s[a:e] = out["s"]
+        infos.append(out)
+    return s, infos
