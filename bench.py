@@ -1,0 +1,191 @@
+"""Benchmark: forward + backward of the parallel Newton path on one MI355X.
+
+One "step" is the whole hot path over the batch: quasi-DEER solve of the GRU recurrence
+(fused linearise + diagonal look-back scan per iteration, hipGraph-captured iterations),
+then the exact quasi adjoint for the loss sum_t ||s_t||^2 (iterated reverse scans) and the
+parameter / input / initial-state gradients.  Workload: GRU, D=64, Dx=32, B=16 sequences of
+T=65536 steps (1,048,576 sequence-steps), weights N(0, 1/D), inputs N(0, 1), s_0 = 0, guess 0.
+
+Printed: one JSON line with the throughput (sequence-steps/s), the sequential GPU baseline on
+the same inputs, the dominant kernel's roofline (its duration measured with HIP events on the
+library's stream), the CPU oracle baseline and the error of the result against it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--tol 1e-6] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd sequence-steps/sec, Newton-scan vs sequential rollout, same GPU, err≤1e-5"
+WORKLOAD = "gru64-quasi-f32"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+
+
+def gate_gemm_flops(D, Dx):
+    """Algorithmic MFMA flops per step of the gate GEMM: z, r on [h; x], U_n h, W_n x."""
+    return 2 * D * (2 * (D + Dx) + D + Dx)
+
+
+def vjp_gemm_flops(D):
+    """Algorithmic MFMA flops per step of the adjoint VJP [U_z; U_n; U_r]^T (3 D x D)."""
+    return 2 * 3 * D * D
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-6,
+                    help="residual stopping tolerance (1e-6 keeps the error under 1e-5)")
+    ap.add_argument("--seq-reps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(sequences would shard by batch with no communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2603_16850_amd as pn
+    from paper_2603_16850_amd import workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    pn.load()
+    work = workloads.ALL[WORKLOAD]
+    inst = workloads.make_instance(work, seed=0)
+    D, Dx, B, N = work.D, work.Dx, work.B, inst.N
+    dev = "cuda"
+    x = torch.tensor(inst.x, dtype=torch.float32, device=dev)
+    s0 = torch.tensor(inst.s0, dtype=torch.float32, device=dev)
+    p = torch.tensor(inst.params, dtype=torch.float32, device=dev)
+    kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol)
+
+    def step():
+        s, finfo = pn.deer_solve(x, s0, p, **kw)
+        gp, gx, g0, binfo = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw)
+        return s, gp, gx, g0, finfo, binfo
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K full steps, kernel durations by HIP events on the library stream
+    with pn.profile():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fam = {f: pn.profile.read(f) for f in
+               ("gru_quasi_iter", "gru_adj_iter", "gru_adj_prep", "gru_adj_grad")}
+    s, gp, gx, g0, finfo, binfo = out
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = N / (ms_per_step * 1e-3)
+
+    # ---- sequential GPU baseline on the same inputs
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    for _ in range(args.seq_reps):
+        s_seq = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
+        sg = pn.seq_bptt(x, s0, p, s_seq, 2.0 * s_seq, cell="gru", offsets=inst.offsets)
+    torch.cuda.synchronize()
+    ts1 = time.perf_counter()
+    seq_ms = (ts1 - ts0) * 1e3 / args.seq_reps
+    seq_value = N / (seq_ms * 1e-3)
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    # ---- roofline of the dominant kernel (largest share of the measured kernel time)
+    fwd_ms, fwd_n = fam["gru_quasi_iter"]
+    adj_ms, adj_n = fam["gru_adj_iter"]
+    it_f = [i["iters"] for i in finfo]
+    it_b = [i["iters"] for i in binfo]
+    if fwd_ms >= adj_ms:
+        dom, dms, dn = "gru_quasi_iter", fwd_ms, fwd_n
+        per_launch_flops = gate_gemm_flops(D, Dx) * N          # every step is active
+    else:
+        dom, dms, dn = "gru_adj_iter", adj_ms, adj_n
+        per_launch_flops = vjp_gemm_flops(D) * N
+    avg_ms = dms / max(dn, 1)
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "launches": dn,
+                "algorithmic_per_launch": per_launch_flops}
+
+    rec = {
+        "metric": METRIC, "value": round(value, 1), "unit": "sequence-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "cell": "gru", "D": D, "Dx": Dx, "B": B,
+                   "T": work.T, "N": N, "method": "quasi-DEER fwd + exact quasi adjoint",
+                   "tol": args.tol, "loss": "sum_t ||s_t||^2", "graph_iters": 4},
+        "iters_fwd": it_f, "iters_bwd": it_b,
+        "kernel_ms": {k: {"total": round(v[0], 3), "launches": v[1]} for k, v in fam.items()},
+        "sequential_gpu": {"value": round(seq_value, 1), "unit": "sequence-steps/s",
+                           "ms_per_step": round(seq_ms, 3)},
+        "speedup_vs_sequential": round(value / seq_value, 2),
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu:
+        rec["cpu_baseline"], err = cpu_leg(inst, s, gp, gx, g0, s_seq)
+        rec["err"] = err
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_leg(inst, s, gp, gx, g0, s_seq):
+    """The oracle (FP64 numpy rollout + sequential adjoint) timed on the host, and the
+    error of the GPU results against it."""
+    from oracle import adjoint, cells, rollout
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    w = inst.work
+    cell = cells.GRU(inst.params, w.D, w.Dx)
+    t0 = time.perf_counter()
+    sref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    _, wp, wx, w0 = adjoint.adjoint_batch(cell, inst.x, inst.s0, sref, 2 * sref, inst.offsets)
+    dt = time.perf_counter() - t0
+
+    def rel(a, b):
+        a = a.detach().cpu().double().numpy() if hasattr(a, "detach") else a
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+    err = {"s": rel(s, sref), "gparams": rel(gp, wp), "gx": rel(gx, wx), "gs0": rel(g0, w0),
+           "s_sequential_gpu": rel(s_seq, sref)}
+    base = {"value": round(inst.N / dt, 1), "unit": "sequence-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"whole workload ({inst.work.B} x {inst.work.T} steps): FP64 numpy "
+                      f"sequential rollout + sequential adjoint, {dt:.1f} s"}
+    return base, err
+
+
+if __name__ == "__main__":
+    main()

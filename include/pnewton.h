@@ -1,0 +1,207 @@
+/*
+ * pnewton.h -- C ABI of the MI355X (gfx950) parallel Newton library.
+ *
+ * The library evaluates a nonlinear recurrence s_t = f(s_{t-1}, x_t), t = 1..T, for many
+ * sequences at once by Newton iterations over the whole trajectory (DEER), by the diagonal
+ * quasi-Newton variant (quasi-DEER), or by the Levenberg-Marquardt / Kalman-filter variant
+ * (ELK), and differentiates the result by the reverse-time adjoint recurrence.
+ *
+ * What each call computes (thesis sections; "eq." names are the thesis's equation labels):
+ *   - residual r_t = s_t - f_t(s_{t-1})                       (Ch. 2, eq. r_def)
+ *   - Newton step: Delta_1 = -r_1, Delta_t = A~_t Delta_{t-1} - r_t, s <- s + Delta,
+ *     with A~_t = df/ds_{t-1} (DEER, eq. lin_rr) or its diagonal (quasi-DEER, eq. quasi_lds),
+ *     evaluated for all t by an associative scan of affine maps (eq. bin_op_affine)
+ *   - loop and stopping rule                                  (Alg. alg:deer)
+ *   - ELK step: the filtered means of the linear-Gaussian SSM of Prop. prop:ELK
+ *   - adjoint lambda_t = g_t + A_{t+1}^T lambda_{t+1} and the parameter gradient
+ *     sum_t (df_t/dtheta)^T lambda_t                         (Ch. 3, eqs. bptt..unrolled_bwds)
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments except `offsets`, `info` and the host result arrays are DEVICE
+ *     pointers, contiguous, row-major, in the dtype named by pn_cell_desc.dtype.  The caller
+ *     owns every buffer; the library never allocates device memory on these paths: scratch
+ *     space comes from the caller's workspace (size from pn_workspace_bytes).
+ *   - Sequences lie back to back: sequence b owns rows offsets[b] .. offsets[b+1]-1 of
+ *     x [N, Dx] and s [N, D]; s0 is [B, D].  `offsets` is a HOST array of B+1 int64 values
+ *     (offsets[0] = 0, non-decreasing, offsets[B] = N), or NULL for B sequences of N/B steps.
+ *   - Work is enqueued on `stream` (a hipStream_t, may be NULL for the default stream).
+ *     Solvers synchronise that stream to read their per-sequence convergence state once
+ *     every opts->graph_iters iterations; they return only after all their work finished.
+ *   - Arguments are validated before any HIP call.  A negative status means nothing was
+ *     written to the outputs.  PN_NOT_CONVERGED (> 0) means the outputs hold the last
+ *     iterate.  pn_last_error() gives a message for the last failing call on the thread.
+ *   - Calls are reentrant given distinct workspaces; calls sharing a workspace must be
+ *     ordered on one stream.
+ */
+#ifndef PNEWTON_H
+#define PNEWTON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PN_ABI_VERSION 1
+
+typedef enum {
+    PN_OK = 0,
+    PN_NOT_CONVERGED = 1,        /* outputs valid: the last iterate / last adjoint iterate */
+    PN_ERR_INVALID_ARG = -1,
+    PN_ERR_UNSUPPORTED = -2,     /* valid arguments, combination not built into the library */
+    PN_ERR_WORKSPACE = -3,       /* workspace NULL or smaller than pn_workspace_bytes */
+    PN_ERR_NONFINITE_INPUT = -4,
+    PN_ERR_HIP = -5,             /* a HIP runtime call failed */
+    PN_ERR_INTERNAL = -6         /* a device-side consistency check failed (e.g. look-back watchdog) */
+} pn_status;
+
+typedef enum {
+    PN_CELL_GRU = 0,    /* reset-after GRU (the thesis's GRU experiments cite the GRU paper):
+                           z = sig(W_z x + U_z h + b_z), r = sig(W_r x + U_r h + b_r),
+                           n = tanh(W_n x + b_n + r*(U_n h + b_hn)), f = (1-z)*n + z*h.
+                           params: [W_z;W_r;W_n] (3D x Dx) | [U_z;U_r;U_n] (3D x D) |
+                                   [b_z;b_r;b_n] (3D) | b_hn (D)                          */
+    PN_CELL_TANH = 1    /* f = tanh(W h + U x + b) (the mean-field RNN family of Ch. 5).
+                           params: W (D x D) | U (D x Dx) | b (D)                         */
+} pn_cell;
+
+typedef enum {
+    PN_JAC_DENSE = 0,   /* A~_t = A_t (DEER)                                             */
+    PN_JAC_DIAG = 1     /* A~_t = diag(A_t), closed form (quasi-DEER)                     */
+} pn_jac;
+
+typedef enum { PN_F32 = 0, PN_F64 = 1 } pn_dtype;
+
+typedef enum {
+    PN_COMPOSE_NATIVE = 0,  /* dense scan products in the solve dtype                      */
+    PN_COMPOSE_BF16 = 1     /* dense scan products on BF16 MFMA with FP32 accumulation;
+                               residuals stay FP32 so the iteration refines itself          */
+} pn_compose;
+
+typedef struct {
+    int32_t cell;           /* pn_cell */
+    int32_t D;              /* state size */
+    int32_t Dx;             /* input size */
+    int32_t dtype;          /* pn_dtype of x, s0, s, params and all gradients */
+    const void* params;     /* device, packed as documented in pn_cell */
+} pn_cell_desc;
+
+typedef struct {
+    int32_t B;              /* number of sequences (>= 1) */
+    int32_t pad_;
+    int64_t N;              /* total steps, = offsets[B] */
+    const int64_t* offsets; /* HOST [B+1], or NULL for uniform length N/B */
+} pn_batch;
+
+typedef struct {
+    int32_t jac;              /* pn_jac */
+    int32_t compose;          /* pn_compose */
+    double tol;               /* stop a sequence when max_t,d |r| < tol (forward), or when the
+                                 adjoint residual max |rho| <= tol * max(1, max |g|)        */
+    int32_t max_iters;        /* <= 0: the longest sequence length (Prop. global_convergence) */
+    int32_t graph_iters;      /* iterations per captured HIP graph between host checks (>= 1) */
+    double reset_abs;         /* reset a time-step vector of the iterate to 0 when any entry is
+                                 non-finite or exceeds this magnitude (<= 0: 1e4)             */
+    int32_t fp64_final_residual; /* ELK / F32: also report the FP64 residual of the result   */
+    int32_t use_graph;        /* 1: capture graph_iters iterations in a hipGraph; 0: launch */
+    int32_t tile;             /* scan tile length in steps; 0: autotuned / default          */
+    int32_t reserved[7];
+} pn_opts;
+
+typedef struct {
+    int32_t iters;          /* Newton (or adjoint) updates applied to the returned iterate */
+    int32_t converged;      /* 1 if the stopping test passed */
+    int32_t resets;         /* time-step vectors reset by the overflow guard (kept iterates) */
+    int32_t pad_;
+    double max_resid;       /* residual max-norm of the returned iterate (FP64 when requested) */
+} pn_seq_info;
+
+/* Operation codes for pn_workspace_bytes. */
+#define PN_OP_DEER 0
+#define PN_OP_ELK 1
+#define PN_OP_ADJOINT 2
+#define PN_OP_RESIDUAL64 3
+
+/* Fill *opts with defaults: quasi (diag), native compose, tol 1e-5, max_iters = T,
+   graph_iters 4, reset_abs 1e4, graph capture on, tile 0. */
+void pn_default_opts(pn_opts* opts);
+
+/* Bytes of device workspace `op` needs for these shapes (0 is possible).  *bytes is set on
+   PN_OK.  The workspace must be 256-byte aligned. */
+pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* batch,
+                             const pn_opts* opts, size_t* bytes);
+
+/* DEER / quasi-DEER (Alg. alg:deer with eq. lin_rr or eq. quasi_lds).
+   s [N, D] is read as the initial guess s^(0) and overwritten with the result.
+   info: HOST array [B] (may be NULL).  Built combinations:
+     GRU,  PN_JAC_DIAG,  F32, D in {16,32,48,64}, Dx a multiple of 8, 8 <= Dx <= 64
+     GRU,  PN_JAC_DENSE, F64, 1 <= D <= 8, 1 <= Dx <= 16
+     TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16 */
+pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                     const void* s0, void* s, const pn_opts* opts, void* workspace,
+                     size_t workspace_bytes, void* stream, pn_seq_info* info);
+
+/* ELK (Ch. 4): each iteration replaces the Newton step by the filtered means of the LGSSM
+   of Prop. prop:ELK with emission noise 1/lambda (lambda >= 0; lambda = 0 is DEER).
+   Built: TANH, PN_JAC_DENSE, F32, D = 16, Dx in {16}.  With fp64_final_residual the
+   reported max_resid is the FP64 residual of the FP32 iterate and the stopping test is
+   re-checked in FP64. */
+pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                    const void* s0, void* s, double lambda, const pn_opts* opts,
+                    void* workspace, size_t workspace_bytes, void* stream, pn_seq_info* info);
+
+/* Adjoint of the solution s (Ch. 3, "Training and the backwards pass"): given
+   gs = dL/ds [N, D] (partial derivative of the loss at each state), computes the total
+   derivatives lambda_t = dL/ds_t of the recurrence, then
+     gparams (packed like params, overwritten) = sum_t (df_t/dtheta)^T lambda_t,
+     gx [N, Dx] = (df_t/dx_t)^T lambda_t   (may be NULL),
+     gs0 [B, D] = A_1^T lambda_1           (may be NULL).
+   With PN_JAC_DIAG the reverse recurrence is solved by iterated reverse scans with
+   diag(A_t) and an exact VJP residual (converges to the exact adjoint); info reports the
+   adjoint iterations.  Built: GRU, PN_JAC_DIAG, F32 (same shapes as deer_solve). */
+pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                       const void* s0, const void* s, const void* gs, void* gx, void* gs0,
+                       void* gparams, const pn_opts* opts, void* workspace,
+                       size_t workspace_bytes, void* stream, pn_seq_info* info);
+
+/* Sequential baselines on the GPU (one workgroup per sequence walks the steps in order, the
+   input projections W x_t + b of all steps computed beforehand in parallel, as cuDNN-style
+   RNN layers do): the rollout s_t = f(s_{t-1}, x_t) (Ch. 2, eq. ssm), and backpropagation
+   through that rollout -- the reverse recurrence lambda_t = g_t + A_{t+1}^T lambda_{t+1} one
+   step at a time, then the parallel gradient reductions -- with the outputs of deer_adjoint.
+   Workspace from pn_workspace_bytes(PN_OP_SEQ, ...).  Built: GRU F32 (the deer_solve GRU
+   shapes), TANH F32 (D <= 64, Dx <= 64). seq_bptt: GRU only. */
+#define PN_OP_SEQ 4
+pn_status seq_rollout(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                      const void* s0, void* s, void* workspace, size_t workspace_bytes,
+                      void* stream);
+pn_status seq_bptt(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                   const void* s0, const void* s, const void* gs, void* gx, void* gs0,
+                   void* gparams, void* workspace, size_t workspace_bytes, void* stream);
+
+/* FP64 residual max-norm per sequence of an FP32 trajectory (inputs upcast to FP64):
+   max_resid: HOST array [B].  Built: TANH and GRU, F32. */
+pn_status pn_residual_f64(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                          const void* s0, const void* s, void* workspace,
+                          size_t workspace_bytes, void* stream, double* max_resid);
+
+/* Kernel timing with HIP events, for benchmarking.  Between pn_profile_begin() and
+   pn_profile_end() the solvers called on this thread launch their iterations directly (no
+   graph) and record a HIP event pair around every launch of their main kernels on the caller's
+   stream; pn_profile_read() returns the summed duration and launch count of a kernel family:
+   "gru_quasi_iter", "gru_adj_iter", "gru_adj_prep", "gru_adj_grad", "tanh_dense_iter",
+   "gru_dense64_solve", "elk_iter", "seq_rollout", "seq_adj".  Returns 0 if the family was
+   not launched. */
+void pn_profile_begin(void);
+void pn_profile_end(void);
+int pn_profile_read(const char* family, double* total_ms, int64_t* launches);
+
+const char* pn_status_str(int status);
+const char* pn_last_error(void);
+int pn_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PNEWTON_H */

@@ -1,0 +1,329 @@
+// Host helpers and control kernels shared by every iterative solver.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "pn_host.hpp"
+
+namespace pn {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
+pn_status hip_fail(hipError_t e, const char* what, const char* file, int line) {
+    set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    return PN_ERR_HIP;
+}
+
+int cu_count() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) n = p.multiProcessorCount;
+        if (n <= 0) n = 256;
+    }
+    return n;
+}
+
+// ---- event timing ------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+    bool on = false;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+};
+ProfRec& prof() {
+    static thread_local ProfRec r;
+    return r;
+}
+}  // namespace
+
+bool profiling() { return prof().on; }
+
+void prof_launch(const char* family, hipStream_t stream,
+                 const std::function<void(hipStream_t)>& launch) {
+    ProfRec& r = prof();
+    if (!r.on) {
+        launch(stream);
+        return;
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!r.pool.empty()) {
+        ev = r.pool.back();
+        r.pool.pop_back();
+    } else {
+        (void)hipEventCreate(&ev.first);
+        (void)hipEventCreate(&ev.second);
+    }
+    (void)hipEventRecord(ev.first, stream);
+    launch(stream);
+    (void)hipEventRecord(ev.second, stream);
+    r.pending.push_back({family, ev});
+}
+
+void prof_collect() {
+    ProfRec& r = prof();
+    for (auto& p : r.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            auto& t = r.totals[p.first];
+            t.first += ms;
+            t.second += 1;
+        }
+        r.pool.push_back(p.second);
+    }
+    r.pending.clear();
+}
+
+void profile_begin() {
+    ProfRec& r = prof();
+    r.on = true;
+    r.totals.clear();
+}
+void profile_end() { prof().on = false; }
+int profile_read(const char* family, double* ms, int64_t* n) {
+    ProfRec& r = prof();
+    auto it = r.totals.find(family);
+    if (it == r.totals.end()) return 0;
+    if (ms) *ms = it->second.first;
+    if (n) *n = it->second.second;
+    return 1;
+}
+
+std::vector<int32_t> tile_starts(const HostBatch& hb, int L) {
+    std::vector<int32_t> ts(hb.B + 1, 0);
+    for (int b = 0; b < hb.B; ++b) ts[b + 1] = ts[b] + (int32_t)((hb.len(b) + L - 1) / L);
+    return ts;
+}
+
+void carve_iter_state(Carver& c, IterState& st, int B) {
+    st.ctrl = c.take<Ctrl>(1);
+    st.seq = c.take<SeqState>(B);
+    st.offsets = c.take<int64_t>(B + 1);
+    st.tile_start = c.take<int32_t>(B + 1);
+}
+
+__global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offsets, int B,
+                                  int max_iters, float tol, float reset_abs) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        SeqState q;
+        const bool empty = offsets[b + 1] == offsets[b];
+        q.status = empty ? kConverged : kActive;
+        q.iters = 0;
+        q.resets = 0;
+        q.resets_pending = 0;
+        q.parity = 0;
+        q.maxr = 0;
+        q.final_resid = 0.0f;
+        q.pad_ = 0;
+        seq[b] = q;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctrl c;
+        c.iter = 0;
+        c.all_done = 0;
+        c.tile_counter = 0;
+        c.error = 0;
+        c.max_iters = max_iters;
+        c.tol = tol;
+        c.reset_abs = reset_abs;
+        c.pad_ = 0;
+        *ctrl = c;
+    }
+}
+
+pn_status init_iter_state(const IterState& st, const HostBatch& hb,
+                          const std::vector<int32_t>& tstart, int max_iters, float tol,
+                          float reset_abs, hipStream_t stream) {
+    PN_HIP(hipMemcpyAsync(st.offsets, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1),
+                          hipMemcpyHostToDevice, stream));
+    PN_HIP(hipMemcpyAsync(st.tile_start, tstart.data(), sizeof(int32_t) * (hb.B + 1),
+                          hipMemcpyHostToDevice, stream));
+    int blocks = std::min(64, (hb.B + 255) / 256);
+    hipLaunchKernelGGL(init_state_kernel, dim3(std::max(1, blocks)), dim3(256), 0, stream,
+                       st.ctrl, st.seq, st.offsets, hb.B, max_iters, tol, reset_abs);
+    PN_HIP(hipGetLastError());
+    return PN_OK;
+}
+
+// One workgroup: apply the stopping test of iteration k to every active sequence.
+__global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B) {
+    __shared__ int any_active;
+    const int k = ctrl->iter;
+    const float tol = ctrl->tol;
+    const int cap = ctrl->max_iters;
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        SeqState q = seq[b];
+        if (q.status == kActive) {
+            const float m = __uint_as_float(q.maxr);
+            if (m < tol || k >= cap) {
+                q.status = (m < tol) ? kConverged : kCapped;
+                q.iters = k;
+                q.parity = k & 1;
+                q.final_resid = m;
+            } else {
+                q.resets += q.resets_pending;
+                any_active = 1;
+            }
+            q.maxr = 0;
+            q.resets_pending = 0;
+            seq[b] = q;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctrl->iter = k + 1;
+        ctrl->tile_counter = 0;
+        ctrl->all_done = any_active ? 0 : 1;
+    }
+}
+
+void launch_decide(const IterState& st, int B, hipStream_t stream) {
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, stream, st.ctrl, st.seq, B);
+}
+
+// ---- iteration loop with optional graph capture -------------------------------------------
+
+namespace {
+struct GraphCache {
+    std::mutex mu;
+    std::map<std::vector<uintptr_t>, hipGraphExec_t> execs;
+    hipStream_t capture_stream = nullptr;
+};
+GraphCache& graph_cache() {
+    static GraphCache* c = new GraphCache();   // lives until process exit
+    return *c;
+}
+
+struct PinnedCtrl {
+    Ctrl* p = nullptr;
+    PinnedCtrl() { (void)hipHostMalloc((void**)&p, sizeof(Ctrl), hipHostMallocDefault); }
+};
+Ctrl* pinned_ctrl() {
+    static thread_local PinnedCtrl pc;
+    return pc.p;
+}
+}  // namespace
+
+pn_status run_iterations(const IterState& st, int max_launches, int graph_iters,
+                         bool use_graph, const std::vector<uintptr_t>& graph_key,
+                         const std::function<void(hipStream_t)>& one_iter,
+                         hipStream_t stream) {
+    Ctrl* hc = pinned_ctrl();
+    if (!hc) {
+        set_error("hipHostMalloc of the control readback buffer failed");
+        return PN_ERR_HIP;
+    }
+    graph_iters = std::max(1, graph_iters);
+    int launched = 0;
+    while (launched < max_launches) {
+        const int n = std::min(graph_iters, max_launches - launched);
+        if (use_graph && n == graph_iters && !profiling()) {
+            hipGraphExec_t exec = nullptr;
+            {
+                GraphCache& gc = graph_cache();
+                std::lock_guard<std::mutex> lock(gc.mu);
+                int dev = 0;
+                PN_HIP(hipGetDevice(&dev));
+                std::vector<uintptr_t> key = graph_key;
+                key.push_back((uintptr_t)n);
+                key.push_back((uintptr_t)dev);
+                auto it = gc.execs.find(key);
+                if (it != gc.execs.end()) {
+                    exec = it->second;
+                } else {
+                    if (!gc.capture_stream)
+                        PN_HIP(hipStreamCreateWithFlags(&gc.capture_stream, hipStreamNonBlocking));
+                    hipGraph_t graph;
+                    PN_HIP(hipStreamBeginCapture(gc.capture_stream, hipStreamCaptureModeThreadLocal));
+                    for (int i = 0; i < n; ++i) one_iter(gc.capture_stream);
+                    PN_HIP(hipStreamEndCapture(gc.capture_stream, &graph));
+                    PN_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                    PN_HIP(hipGraphDestroy(graph));
+                    if (gc.execs.size() > 64) {
+                        for (auto& kv : gc.execs) (void)hipGraphExecDestroy(kv.second);
+                        gc.execs.clear();
+                    }
+                    gc.execs[key] = exec;
+                }
+            }
+            PN_HIP(hipGraphLaunch(exec, stream));
+        } else {
+            for (int i = 0; i < n; ++i) one_iter(stream);
+            PN_HIP(hipGetLastError());
+        }
+        launched += n;
+        PN_HIP(hipMemcpyAsync(hc, st.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        PN_HIP(hipStreamSynchronize(stream));
+        if (hc->all_done || hc->error) break;
+    }
+    return PN_OK;
+}
+
+template <class T>
+__global__ void copy_odd_parity_kernel(const SeqState* seq, const int64_t* offsets, int D,
+                                       T* dst, const T* src) {
+    const int b = blockIdx.y;
+    if (seq[b].parity == 0) return;
+    const int64_t a = offsets[b] * D, e = offsets[b + 1] * D;
+    for (int64_t i = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < e;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+pn_status finish_iterations(const IterState& st, const HostBatch& hb, int D, size_t elem,
+                            void* s_user, const void* s_alt, hipStream_t stream,
+                            pn_seq_info* info, bool* all_converged, int* device_error) {
+    if (s_alt) {
+        const int64_t per = hb.Tmax * D;
+        int gx = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (per + 255) / 256));
+        dim3 grid(gx, hb.B);
+        if (elem == 4)
+            hipLaunchKernelGGL(copy_odd_parity_kernel<float>, grid, dim3(256), 0, stream,
+                               st.seq, st.offsets, D, (float*)s_user, (const float*)s_alt);
+        else
+            hipLaunchKernelGGL(copy_odd_parity_kernel<double>, grid, dim3(256), 0, stream,
+                               st.seq, st.offsets, D, (double*)s_user, (const double*)s_alt);
+        PN_HIP(hipGetLastError());
+    }
+    std::vector<SeqState> hs(hb.B);
+    Ctrl hc;
+    PN_HIP(hipMemcpyAsync(hs.data(), st.seq, sizeof(SeqState) * hb.B, hipMemcpyDeviceToHost,
+                          stream));
+    PN_HIP(hipMemcpyAsync(&hc, st.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    PN_HIP(hipStreamSynchronize(stream));
+    bool allc = true;
+    for (int b = 0; b < hb.B; ++b) {
+        const bool conv = hs[b].status == kConverged;
+        allc = allc && conv;
+        if (info) {
+            info[b].iters = hs[b].iters;
+            info[b].converged = conv ? 1 : 0;
+            info[b].resets = hs[b].resets;
+            info[b].pad_ = 0;
+            info[b].max_resid = hs[b].final_resid;
+        }
+    }
+    *all_converged = allc;
+    *device_error = hc.error;
+    prof_collect();
+    return PN_OK;
+}
+
+}  // namespace pn

@@ -1,0 +1,818 @@
+// Exact adjoint of the GRU recurrence by iterated reverse quasi-Newton scans, then the
+// parameter, input and initial-state gradients.
+//
+// Ch. 3 ("Training and the backwards pass"): backpropagation through s_t = f(s_{t-1}, x_t) is
+// the reverse-time linear recurrence lambda_t = g_t + A_{t+1}^T lambda_{t+1} (lambda_T = g_T),
+// and the thesis recommends an exact backward pass for quasi-DEER obtained by iterating
+// reverse scans whose transition is diag(A_t) while the true A_{t+1}^T lambda_{t+1} enters
+// through a vector-Jacobian product.  Written like the forward Newton step (eq. lin_rr):
+//   rho_t   = lambda_t - g_t - A_{t+1}^T lambda_{t+1}             (exact VJP residual)
+//   Delta_t = diag(A_{t+1}) Delta_{t+1} - rho_t,  Delta_{T+1} = 0  (reverse diagonal scan)
+//   lambda <- lambda + Delta,
+// repeated until max |rho| <= tol * max(1, max |g|) for the sequence.  Since the recurrence is
+// linear in lambda, the same global-convergence argument as Prop. global_convergence bounds it
+// by T iterations.  Then (eq. unrolled_bwds)
+//   dL/dtheta = sum_t (df_t/dtheta)^T lambda_t,  dL/dx_t = (df_t/dx_t)^T lambda_t,
+//   dL/ds_0 = A_1^T lambda_1.
+//
+// Kernels: prep (gate values at the solution, once), iter (one per adjoint iteration: VJP on
+// FP32 MFMA + reverse scan with decoupled look-back over tiles taken from the sequence end),
+// grad (per-workgroup partial parameter gradients on MFMA, dx), reduce, gs0.
+#include <algorithm>
+
+#include "gru_common.hpp"
+#include "pn_host.hpp"
+#include "pn_solvers.hpp"
+
+namespace pn {
+
+template <int D, int DX, int L>
+struct GruA {
+    static constexpr int NW = D / 16;
+    static constexpr int NT = 64 * NW;
+    static constexpr int HS = D + 4;
+    static constexpr int XS = DX + 4;
+    static constexpr int PS = 3 * D + 4;    // row stride of the VJP operand tile
+    static constexpr int MB = L / 16;
+    static constexpr int DXP = (DX + 15) / 16 * 16;
+};
+
+struct GruAdjArgs {
+    const float* x;
+    const float* s0;
+    const float* s;
+    const float* gs;
+    const float* params;
+    float* gates;            // [N][4][D]: z, alpha, beta, gamma at the solution
+    float* eps;              // [N][D]: (1 - z)(1 - n^2)
+    float* lam[2];           // ping-pong adjoint iterates
+    uint64_t* agg[2];
+    uint32_t* incl[2];
+    float* gmax;             // [B] max |g| per sequence (as float bits, via atomicMax)
+    Ctrl* ctrl;
+    SeqState* seq;
+    const int64_t* offsets;
+    const int32_t* tile_start;
+    int B;
+    int ntiles;
+    float* part;             // [grid][P] per-workgroup parameter-gradient partials
+    float* gx;
+    float* gs0;
+    float* gparams;
+};
+
+// Shared tile lookup: tile id -> (sequence, tile index from the sequence start, length).
+PN_DEV void tile_of(const GruAdjArgs& a, int tile, int L, bool reverse, int* b_out, int* lt_out,
+                    int* len_out) {
+    int lo = 0, hi = a.B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.tile_start[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const int b = lo;
+    const int nt_b = a.tile_start[b + 1] - a.tile_start[b];
+    int lt = tile - a.tile_start[b];
+    if (reverse) lt = nt_b - 1 - lt;
+    const int64_t len_seq = a.offsets[b + 1] - a.offsets[b];
+    *b_out = b;
+    *lt_out = lt;
+    *len_out = (int)std::min<int64_t>(L, len_seq - (int64_t)lt * L);
+}
+
+// ---- prep: gates at the solution, lambda^(0) = g, max |g| ---------------------------------
+template <int D, int DX, int L>
+__global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs a) {
+    using C = GruA<D, DX, L>;
+    __shared__ __attribute__((aligned(16))) float hs[L * C::HS];
+    __shared__ __attribute__((aligned(16))) float xs[L * C::XS];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
+    const int j = 16 * w + u;
+    GruGates<D, DX> wg;
+    wg.load(a.params, j, g);
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        int b, lt, len;
+        tile_of(a, tile, L, false, &b, &lt, &len);
+        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
+        const bool first = lt == 0;
+        __syncthreads();
+        constexpr int Q = D / 4, QX = DX / 4;
+        for (int idx = tid; idx < L * Q; idx += C::NT) {
+            const int r = idx / Q, c4 = idx % Q;     // stage row r <-> h of step t0 + r
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < len)
+                v = (r == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
+                                      : *(const float4*)(a.s + (size_t)(row0 + r - 1) * D + 4 * c4);
+            *(float4*)(hs + r * C::HS + 4 * c4) = v;
+        }
+        for (int idx = tid; idx < L * QX; idx += C::NT) {
+            const int r = idx / QX, c4 = idx % QX;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+            *(float4*)(xs + r * C::XS + 4 * c4) = v;
+        }
+        __syncthreads();
+        uint32_t gm = 0;
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb) {
+            floatx4 az, ar, aq, an;
+            wg.gemm(hs + (mb * 16 + u) * C::HS, xs + (mb * 16 + u) * C::XS, g, az, ar, aq, an);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tl = mb * 16 + 4 * g + i;
+                if (tl >= len) continue;
+                const GruPoint p = gru_point(az[i], ar[i], aq[i], an[i], wg.b_z, wg.b_r, wg.b_n,
+                                             wg.b_hn);
+                const float h = hs[tl * C::HS + j];
+                const float e = (1.f - p.z) * (1.f - p.n * p.n);
+                const size_t row = (size_t)(row0 + tl);
+                float* gr = a.gates + row * 4 * D;
+                gr[0 * D + j] = p.z;
+                gr[1 * D + j] = (h - p.n) * p.z * (1.f - p.z);
+                gr[2 * D + j] = e * p.r;
+                gr[3 * D + j] = e * p.q * p.r * (1.f - p.r);
+                a.eps[row * D + j] = e;
+                const float gv = a.gs[row * D + j];
+                a.lam[0][row * D + j] = gv;
+                gm = max(gm, absbits(gv));
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) gm = max(gm, (uint32_t)__shfl_xor((int)gm, off));
+        if (l == 0) atomicMax((uint32_t*)&a.gmax[b], gm);
+    }
+}
+
+// ---- one adjoint iteration ------------------------------------------------------------------
+template <int D, int DX, int L>
+__global__ void __launch_bounds__(64 * (D / 16)) gru_adj_iter_kernel(GruAdjArgs a) {
+    using C = GruA<D, DX, L>;
+    __shared__ __attribute__((aligned(16))) float ps[L * C::PS];
+    __shared__ int rowbad[L];
+    __shared__ int tinfo[4];
+
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int k = a.ctrl->iter;
+    const int par = k & 1;
+    const float reset_abs = a.ctrl->reset_abs;
+    const float* __restrict__ lin = a.lam[par];
+    float* __restrict__ lout = a.lam[par ^ 1];
+    uint64_t* aggc = a.agg[par];
+    uint32_t* inclc = a.incl[par];
+
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
+    const int j = 16 * w + u;
+
+    // B operands of [U_z; U_n; U_r] (3D x D), column j, same K permutation as GruGates
+    const float* U = a.params + 3 * D * DX;
+    float bu[3 * D / 16][4];
+#pragma unroll
+    for (int kb = 0; kb < 3 * D / 16; ++kb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = 16 * kb + 4 * g + i;     // 0..3D-1 over (z | n | r) blocks
+            const int mat = kk / D, ii = kk % D;
+            const int base = (mat == 0 ? 0 : (mat == 1 ? 2 : 1)) * D;   // U_z, U_n, U_r rows
+            bu[kb][i] = U[(base + ii) * D + j];
+        }
+    const float dUz = U[(0 * D + j) * D + j], dUr = U[(1 * D + j) * D + j],
+                dUn = U[(2 * D + j) * D + j];
+
+    for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            const int tile = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
+            tinfo[0] = tile;
+            if (tile < a.ntiles) {
+                int b, lt, len;
+                tile_of(a, tile, L, true, &b, &lt, &len);
+                tinfo[1] = b;
+                tinfo[2] = lt;
+                tinfo[3] = (a.seq[b].status == kActive) ? len : -1;
+            }
+        }
+        __syncthreads();
+        const int tile = tinfo[0];
+        if (tile >= a.ntiles) break;
+        const int b = tinfo[1];
+        const int lt = tinfo[2];
+        const int len = tinfo[3];
+        if (len < 0) continue;
+        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
+        const int64_t rend = a.offsets[b + 1];                 // one past the sequence's last row
+        const bool first = row0 + L >= rend;                   // tile at the sequence end
+        const float gscale = 1.f / fmaxf(1.f, a.gmax[b]);
+
+        if (g == 0) {
+            st_u64(&a.agg[par ^ 1][(size_t)tile * D + j], kSent64);
+            st_u32(&a.incl[par ^ 1][(size_t)tile * D + j], kSent32);
+        }
+        // VJP operand rows: ps[tl] = (alpha, beta, gamma)_{t+1} * lambda_{t+1}, zero when step
+        // t+1 is outside the sequence
+        for (int idx = tid; idx < L * D; idx += C::NT) {
+            const int tl = idx / D, ii = idx % D;
+            const int64_t nr = row0 + tl + 1;
+            float va = 0.f, vb = 0.f, vg = 0.f;
+            if (tl < len && nr < rend) {
+                const float lv = lin[(size_t)nr * D + ii];
+                const float* gr = a.gates + (size_t)nr * 4 * D;
+                va = gr[1 * D + ii] * lv;
+                vb = gr[2 * D + ii] * lv;
+                vg = gr[3 * D + ii] * lv;
+            }
+            float* pr = ps + tl * C::PS;
+            pr[ii] = va;           // pairs with U_z
+            pr[D + ii] = vb;       // pairs with U_n
+            pr[2 * D + ii] = vg;   // pairs with U_r
+        }
+        __syncthreads();
+
+        float la[C::MB][4], lc[C::MB][4], lcur[C::MB][4];
+        uint32_t rmax = 0;
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+            const float* prow = ps + (mb * 16 + u) * C::PS;
+#pragma unroll
+            for (int kb = 0; kb < 3 * D / 16; ++kb) {
+                const float4 p4 = *(const float4*)(prow + 16 * kb + 4 * g);
+                acc = mfma16x4(p4.x, bu[kb][0], acc);
+                acc = mfma16x4(p4.y, bu[kb][1], acc);
+                acc = mfma16x4(p4.z, bu[kb][2], acc);
+                acc = mfma16x4(p4.w, bu[kb][3], acc);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tl = mb * 16 + 4 * g + i;
+                const int64_t row = row0 + tl;
+                const bool valid = tl < len;
+                const bool has_next = valid && row + 1 < rend;
+                float lam_t = 0.f, g_t = 0.f, vjp = 0.f, dg = 0.f;
+                if (valid) {
+                    lam_t = lin[(size_t)row * D + j];
+                    g_t = a.gs[(size_t)row * D + j];
+                }
+                if (has_next) {
+                    const float* gr = a.gates + (size_t)(row + 1) * 4 * D;
+                    const float z = gr[j], al = gr[D + j], be = gr[2 * D + j], ga = gr[3 * D + j];
+                    vjp = z * lin[(size_t)(row + 1) * D + j] + acc[i];
+                    dg = z + al * dUz + be * dUn + ga * dUr;
+                }
+                const float rho = lam_t - g_t - vjp;
+                la[mb][i] = valid ? dg : 1.f;
+                lc[mb][i] = valid ? -rho : 0.f;
+                lcur[mb][i] = lam_t;
+                if (valid) rmax = max(rmax, absbits(rho * gscale));
+            }
+        }
+
+        // ---- reverse scan inside the tile (later steps first) ----
+        float Ra = 1.f, Rc = 0.f;
+#pragma unroll
+        for (int mb = C::MB - 1; mb >= 0; --mb) {
+            float pa = 1.f, pc = 0.f;
+#pragma unroll
+            for (int i = 3; i >= 0; --i) {
+                pa = la[mb][i] * pa;
+                pc = la[mb][i] * pc + lc[mb][i];
+                la[mb][i] = pa;
+                lc[mb][i] = pc;
+            }
+            float Ia = pa, Ic = pc;
+            {
+                const float qa = __shfl_down(Ia, 16), qc = __shfl_down(Ic, 16);
+                if (g <= 2) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
+            }
+            {
+                const float qa = __shfl_down(Ia, 32), qc = __shfl_down(Ic, 32);
+                if (g <= 1) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
+            }
+            float Ea = __shfl_down(Ia, 16), Ec = __shfl_down(Ic, 16);
+            if (g == 3) { Ea = 1.f; Ec = 0.f; }
+            const float Ta = __shfl(Ia, u), Tc = __shfl(Ic, u);
+            const float Xa = Ea * Ra, Xc = Ea * Rc + Ec;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                lc[mb][i] = la[mb][i] * Xc + lc[mb][i];
+                la[mb][i] = la[mb][i] * Xa;
+            }
+            Rc = Ta * Rc + Tc;
+            Ra = Ta * Ra;
+        }
+        float din = 0.f;
+        if (g == 0) din = lookback(aggc, inclc, tile, first, D, j, Ra, Rc, &a.ctrl->error);
+        din = __shfl(din, u);
+
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = lcur[mb][i] + (la[mb][i] * din + lc[mb][i]);
+                lc[mb][i] = v;
+                const int tl = mb * 16 + 4 * g + i;
+                const bool bad = (tl < len) && !(fabsf(v) <= reset_abs);
+                const uint64_t m = __ballot(bad);
+                if (u == 0 && ((m >> (16 * g)) & 0xFFFFull)) rowbad[tl] = 1;
+            }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
+        if (l == 0) atomicMax(&a.seq[b].maxr, rmax);
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tl = mb * 16 + 4 * g + i;
+                if (tl < len) lout[(size_t)(row0 + tl) * D + j] = rowbad[tl] ? 0.f : lc[mb][i];
+            }
+        if (w == 0) {
+            int nb = 0;
+            for (int base = 0; base < L; base += 64) {
+                const int t = base + l;
+                nb += __popcll(__ballot((t < L) && rowbad[t]));
+            }
+            if (l == 0 && nb) atomicAdd(&a.seq[b].resets_pending, nb);
+        }
+        __syncthreads();
+        for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
+    }
+}
+
+// ---- gradients: per-workgroup partials of dW, dU, db on MFMA; dx rows --------------------
+// Output tiles of the parameter GEMMs (16 x 16 each): for each gate block G in {z, r, n}
+// and unit block ib:  dU_G[ib] x (h blocks)  and  dW_G[ib] x (x blocks).  dU_n pairs with
+// delta_q = beta * lambda, dW_n with delta_n = eps * lambda.
+template <int D, int DX>
+struct GradTiles {
+    static constexpr int IB = D / 16;
+    static constexpr int HB = D / 16;
+    static constexpr int XB = (DX + 15) / 16;
+    static constexpr int PER_GATE = IB * (HB + XB);
+    static constexpr int TOTAL = 3 * PER_GATE;
+};
+
+template <int D, int DX, int L>
+__global__ void __launch_bounds__(64 * (D / 16)) gru_adj_grad_kernel(GruAdjArgs a) {
+    using C = GruA<D, DX, L>;
+    using TT = GradTiles<D, DX>;
+    constexpr int NW = C::NW;
+    constexpr int PER_W = (TT::TOTAL + NW - 1) / NW;
+    constexpr int DS = 4 * D + 4;        // delta tile stride: [dz | dr | dq | dn]
+    constexpr int XSP = C::DXP + 4;
+    __shared__ __attribute__((aligned(16))) float dl[L * DS];
+    __shared__ __attribute__((aligned(16))) float hsm[L * C::HS];
+    __shared__ __attribute__((aligned(16))) float xsm[L * XSP];
+
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
+    floatx4 acc[PER_W];
+#pragma unroll
+    for (int q = 0; q < PER_W; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bsum[4] = {0.f, 0.f, 0.f, 0.f};   // bias partials of unit tid % D (tid < D only)
+    const float* W = a.params;              // [W_z;W_r;W_n] (3D x DX)
+
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        int b, lt, len;
+        tile_of(a, tile, L, false, &b, &lt, &len);
+        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
+        const bool first = lt == 0;
+        const float* lam = a.lam[a.seq[b].parity];
+        __syncthreads();
+        for (int idx = tid; idx < L * D; idx += C::NT) {
+            const int tl = idx / D, ii = idx % D;
+            float dz = 0.f, dr = 0.f, dq = 0.f, dn = 0.f, hv = 0.f;
+            if (tl < len) {
+                const size_t row = (size_t)(row0 + tl);
+                const float lv = lam[row * D + ii];
+                const float* gr = a.gates + row * 4 * D;
+                dz = gr[1 * D + ii] * lv;
+                dq = gr[2 * D + ii] * lv;
+                dr = gr[3 * D + ii] * lv;
+                dn = a.eps[row * D + ii] * lv;
+                hv = (tl == 0 && first) ? a.s0[(size_t)b * D + ii] : a.s[(row - 1) * D + ii];
+            }
+            float* dr_ = dl + tl * DS;
+            dr_[ii] = dz;
+            dr_[D + ii] = dr;
+            dr_[2 * D + ii] = dq;
+            dr_[3 * D + ii] = dn;
+            hsm[tl * C::HS + ii] = hv;
+        }
+        for (int idx = tid; idx < L * C::DXP; idx += C::NT) {
+            const int tl = idx / C::DXP, c = idx % C::DXP;
+            xsm[tl * XSP + c] = (tl < len && c < DX) ? a.x[(size_t)(row0 + tl) * DX + c] : 0.f;
+        }
+        __syncthreads();
+        // bias partials: thread owns unit tid % D, steps tid / D + k * (NT / D)
+        if (tid < D) {
+            for (int tl = 0; tl < L; ++tl) {
+                const float* dr_ = dl + tl * DS;
+                bsum[0] += dr_[tid];
+                bsum[1] += dr_[D + tid];
+                bsum[2] += dr_[3 * D + tid];
+                bsum[3] += dr_[2 * D + tid];
+            }
+        }
+        // parameter GEMM: K = steps, 4 per MFMA
+#pragma unroll 2
+        for (int kq = 0; kq < L / 4; ++kq) {
+            const int tstep = 4 * kq + g;       // step of this lane's K slot
+#pragma unroll
+            for (int q = 0; q < PER_W; ++q) {
+                const int o = w + q * NW;
+                if (o >= TT::TOTAL) break;
+                const int gate = o / TT::PER_GATE;
+                const int rem = o % TT::PER_GATE;
+                const int ib = rem / (TT::HB + TT::XB);
+                const int cb = rem % (TT::HB + TT::XB);
+                const int dcol = (gate == 0 ? 0 : (gate == 1 ? D : (cb < TT::HB ? 2 * D : 3 * D)));
+                const float av = dl[tstep * DS + dcol + 16 * ib + u];
+                const float bv = cb < TT::HB ? hsm[tstep * C::HS + 16 * cb + u]
+                                             : xsm[tstep * XSP + 16 * (cb - TT::HB) + u];
+                acc[q] = mfma16x4(av, bv, acc[q]);
+            }
+        }
+        // dx rows: dx_t = W_z^T dz + W_r^T dr + W_n^T dn  (K = 3D, N = DX)
+        if (a.gx) {
+            for (int mb = w; mb < C::MB; mb += NW) {
+                for (int nb = 0; nb < C::DXP / 16; ++nb) {
+                    floatx4 o4 = {0.f, 0.f, 0.f, 0.f};
+                    const int n = 16 * nb + u;
+                    for (int kq = 0; kq < 3 * D / 4; ++kq) {
+                        const int kk = 4 * kq + g;                  // 0..3D-1 over z | r | n
+                        const int gate = kk / D, ii = kk % D;
+                        const int dcol = gate == 0 ? 0 : (gate == 1 ? D : 3 * D);
+                        const float av = dl[(mb * 16 + u) * DS + dcol + 4 * kq + g - gate * D];
+                        const float bv = n < DX ? W[(gate * D + ii) * DX + n] : 0.f;
+                        o4 = mfma16x4(av, bv, o4);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int tl = mb * 16 + 4 * g + i;
+                        if (tl < len && n < DX) a.gx[(size_t)(row0 + tl) * DX + n] = o4[i];
+                    }
+                }
+            }
+        }
+    }
+    // write this workgroup's partials in the packed gradient layout
+    constexpr int P = 3 * D * DX + 3 * D * D + 4 * D;
+    float* part = a.part + (size_t)blockIdx.x * P;
+#pragma unroll
+    for (int q = 0; q < PER_W; ++q) {
+        const int o = w + q * NW;
+        if (o >= TT::TOTAL) break;
+        const int gate = o / TT::PER_GATE;           // 0 z, 1 r, 2 n
+        const int rem = o % TT::PER_GATE;
+        const int ib = rem / (TT::HB + TT::XB);
+        const int cb = rem % (TT::HB + TT::XB);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * ib + 4 * g + i;      // unit
+            if (cb < TT::HB) {
+                const int col = 16 * cb + u;
+                part[3 * D * DX + (gate * D + row) * D + col] = acc[q][i];
+            } else {
+                const int col = 16 * (cb - TT::HB) + u;
+                if (col < DX) part[(gate * D + row) * DX + col] = acc[q][i];
+            }
+        }
+    }
+    if (tid < D) {
+        float* pb = part + 3 * D * DX + 3 * D * D;
+        pb[tid] = bsum[0];
+        pb[D + tid] = bsum[1];
+        pb[2 * D + tid] = bsum[2];
+        pb[3 * D + tid] = bsum[3];
+    }
+}
+
+__global__ void gru_adj_reduce_kernel(const float* part, int nparts, int P, float* out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int k = 0; k < nparts; ++k) acc += (double)part[(size_t)k * P + i];
+        out[i] = (float)acc;
+    }
+}
+
+// dL/ds_0 = A_1^T lambda_1 for every sequence (one workgroup per sequence).
+template <int D, int DX>
+__global__ void gru_adj_gs0_kernel(GruAdjArgs a) {
+    const int b = blockIdx.x;
+    const int j = threadIdx.x;
+    if (j >= D) return;
+    const int64_t r0 = a.offsets[b];
+    if (a.offsets[b + 1] == r0) { a.gs0[(size_t)b * D + j] = 0.f; return; }
+    const float* lam = a.lam[a.seq[b].parity] + (size_t)r0 * D;
+    const float* gr = a.gates + (size_t)r0 * 4 * D;
+    const float* U = a.params + 3 * D * DX;
+    float v = gr[j] * lam[j];
+    for (int i = 0; i < D; ++i) {
+        const float li = lam[i];
+        v += U[(0 * D + i) * D + j] * gr[D + i] * li      // U_z^T (alpha * lambda)
+           + U[(2 * D + i) * D + j] * gr[2 * D + i] * li  // U_n^T (beta * lambda)
+           + U[(1 * D + i) * D + j] * gr[3 * D + i] * li; // U_r^T (gamma * lambda)
+    }
+    a.gs0[(size_t)b * D + j] = v;
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// ---- sequential adjoint (baseline): lambda_t = g_t + A_{t+1}^T lambda_{t+1}, one step at a
+// time per sequence; lanes 4j..4j+3 of a wave serve unit j (U_z^T, U_n^T, U_r^T columns).
+template <int D>
+__global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, const float* gs,
+                                                            const float* U, float* lam,
+                                                            const int64_t* offsets) {
+    constexpr int CH = 32;
+    __shared__ float prod[2][3][D];
+    __shared__ float gch[CH][4 * D];
+    __shared__ float gsch[CH][D];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int j = tid >> 2, role = tid & 3, base = (tid & 63) & ~3;
+    const int64_t r0 = offsets[b], T = offsets[b + 1] - r0;
+    float w[D];
+    const int mrow = role == 0 ? 0 : (role == 1 ? 2 * D : D);   // U_z, U_n, U_r
+#pragma unroll
+    for (int i = 0; i < D; ++i) w[i] = role < 3 ? U[(mrow + i) * D + j] : 0.f;
+    const int plane = role + 1;                                  // alpha, beta, gamma
+    float v = 0.f;                                               // A_{t+1}^T lambda_{t+1}
+    for (int64_t t = T - 1; t >= 0; --t) {
+        const int64_t cb = t - (t % CH);                         // chunk [cb, cb + CH)
+        if (t % CH == CH - 1 || t == T - 1) {
+            __syncthreads();
+            for (int idx = tid; idx < CH * 4 * D; idx += blockDim.x) {
+                const int r = idx / (4 * D), c = idx % (4 * D);
+                gch[r][c] = (cb + r < T) ? gates[(size_t)(r0 + cb + r) * 4 * D + c] : 0.f;
+            }
+            for (int idx = tid; idx < CH * D; idx += blockDim.x) {
+                const int r = idx / D, c = idx % D;
+                gsch[r][c] = (cb + r < T) ? gs[(size_t)(r0 + cb + r) * D + c] : 0.f;
+            }
+            __syncthreads();
+        }
+        const int rr = (int)(t - cb);
+        const float lt = gsch[rr][j] + v;
+        const float z = gch[rr][j];
+        if (role == 0) lam[(size_t)(r0 + t) * D + j] = lt;
+        const int p = (int)(t & 1);
+        if (role < 3) prod[p][role][j] = gch[rr][plane * D + j] * lt;
+        __syncthreads();
+        float acc = 0.f;
+        if (role < 3) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) acc += w[i] * prod[p][role][i];
+        }
+        v = z * lt + __shfl(acc, base) + __shfl(acc, base + 1) + __shfl(acc, base + 2);
+    }
+}
+
+// ---- host driver ------------------------------------------------------------------------------
+
+struct GruALayout {
+    IterState st;
+    float *gates, *eps, *lam[2], *gmax, *part;
+    uint64_t* agg[2];
+    uint32_t* incl[2];
+    size_t bytes;
+};
+
+constexpr int kAdjL = 64;
+constexpr int kGradL = 32;
+
+static int grad_grid() { return cu_count(); }
+
+static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int ntiles) {
+    Carver c(ws);
+    GruALayout lay;
+    carve_iter_state(c, lay.st, hb.B);
+    lay.gates = c.take<float>((size_t)hb.N * 4 * D);
+    lay.eps = c.take<float>((size_t)hb.N * D);
+    for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
+    for (int p = 0; p < 2; ++p) lay.agg[p] = c.take<uint64_t>((size_t)ntiles * D);
+    for (int p = 0; p < 2; ++p) lay.incl[p] = c.take<uint32_t>((size_t)ntiles * D);
+    lay.gmax = c.take<float>(hb.B);
+    const size_t P = 3 * (size_t)D * Dx + 3 * (size_t)D * D + 4 * (size_t)D;
+    lay.part = c.take<float>((size_t)grad_grid() * P);
+    lay.bytes = c.bytes();
+    return lay;
+}
+
+size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts&) {
+    const int ntiles = tile_starts(hb, kAdjL)[hb.B];
+    return gruA_layout(nullptr, D, Dx, hb, ntiles).bytes;
+}
+
+__global__ void fill_sentinels_adj_kernel(uint64_t* agg, uint32_t* incl, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        agg[i] = kSent64;
+        incl[i] = kSent32;
+    }
+}
+
+struct GruAKernels {
+    void (*prep)(GruAdjArgs);
+    void (*iter)(GruAdjArgs);
+    void (*grad)(GruAdjArgs);
+    void (*gs0)(GruAdjArgs);
+    int nt;
+};
+
+template <int D, int DX>
+static GruAKernels gruA_get() {
+    GruAKernels k;
+    k.prep = gru_adj_prep_kernel<D, DX, kAdjL>;
+    k.iter = gru_adj_iter_kernel<D, DX, kAdjL>;
+    k.grad = gru_adj_grad_kernel<D, DX, kGradL>;
+    k.gs0 = gru_adj_gs0_kernel<D, DX>;
+    k.nt = 64 * (D / 16);
+    return k;
+}
+
+static bool gruA_lookup(int D, int Dx, GruAKernels* k) {
+#define PN_GA(d, dx) if (D == d && Dx == dx) { *k = gruA_get<d, dx>(); return true; }
+    PN_GA(64, 32) PN_GA(48, 24) PN_GA(32, 16) PN_GA(16, 8) PN_GA(16, 16) PN_GA(64, 64)
+    PN_GA(32, 32) PN_GA(48, 48) PN_GA(64, 16) PN_GA(32, 8)
+#undef PN_GA
+    return false;
+}
+
+pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                      const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                      float* gparams, const pn_opts& o, void* ws, hipStream_t stream,
+                      pn_seq_info* info, bool* all_conv) {
+    const int D = cd.D, Dx = cd.Dx;
+    GruAKernels kk;
+    if (!gruA_lookup(D, Dx, &kk)) {
+        set_error("GRU adjoint not built for D=%d Dx=%d", D, Dx);
+        return PN_ERR_UNSUPPORTED;
+    }
+    const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
+    const int ntiles = ts[hb.B];
+    const std::vector<int32_t> tsg = tile_starts(hb, kGradL);
+    const int ntiles_g = tsg[hb.B];
+    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles);
+    const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
+    PN_TRY(init_iter_state(lay.st, hb, ts, max_iters, (float)o.tol, (float)o.reset_abs, stream));
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
+    if (ntiles > 0) {
+        const size_t n = (size_t)ntiles * D;
+        hipLaunchKernelGGL(fill_sentinels_adj_kernel, dim3((unsigned)std::min<size_t>(4096, (n + 255) / 256)),
+                           dim3(256), 0, stream, lay.agg[0], lay.incl[0], n);
+    }
+    PN_HIP(hipGetLastError());
+
+    GruAdjArgs args;
+    args.x = x;
+    args.s0 = s0;
+    args.s = s;
+    args.gs = gs;
+    args.params = (const float*)cd.params;
+    args.gates = lay.gates;
+    args.eps = lay.eps;
+    for (int p = 0; p < 2; ++p) {
+        args.lam[p] = lay.lam[p];
+        args.agg[p] = lay.agg[p];
+        args.incl[p] = lay.incl[p];
+    }
+    args.gmax = lay.gmax;
+    args.ctrl = lay.st.ctrl;
+    args.seq = lay.st.seq;
+    args.offsets = lay.st.offsets;
+    args.tile_start = lay.st.tile_start;
+    args.B = hb.B;
+    args.ntiles = ntiles;
+    args.part = lay.part;
+    args.gx = gx;
+    args.gs0 = gs0;
+    args.gparams = gparams;
+
+    if (ntiles > 0) {
+        prof_launch("gru_adj_prep", stream, [&](hipStream_t s2) {
+            hipLaunchKernelGGL(kk.prep, dim3(std::max(1, std::min(ntiles, cu_count() * 2))),
+                               dim3(kk.nt), 0, s2, args);
+        });
+        PN_HIP(hipGetLastError());
+    }
+    int occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kk.iter, kk.nt, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    const int grid = std::max(1, std::min(ntiles, cu_count() * occ));
+    auto one_iter = [&](hipStream_t st) {
+        prof_launch("gru_adj_iter", st, [&](hipStream_t s2) {
+            hipLaunchKernelGGL(kk.iter, dim3(grid), dim3(kk.nt), 0, s2, args);
+        });
+        launch_decide(lay.st, hb.B, st);
+    };
+    std::vector<uintptr_t> key = {0x4144u, (uintptr_t)kk.iter, (uintptr_t)grid, (uintptr_t)x,
+                                  (uintptr_t)s0, (uintptr_t)s, (uintptr_t)gs,
+                                  (uintptr_t)cd.params, (uintptr_t)ws, (uintptr_t)hb.B,
+                                  (uintptr_t)ntiles};
+    PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
+                          stream));
+    int derr = 0;
+    PN_TRY(finish_iterations(lay.st, hb, D, sizeof(float), nullptr, nullptr, stream, info,
+                             all_conv, &derr));
+    if (derr) {
+        set_error("look-back watchdog expired in the adjoint scan");
+        return PN_ERR_INTERNAL;
+    }
+    // gradients from the final adjoint iterate
+    GruAdjArgs gargs = args;
+    gargs.tile_start = lay.st.tile_start;
+    PN_HIP(hipMemcpyAsync(lay.st.tile_start, tsg.data(), sizeof(int32_t) * (hb.B + 1),
+                          hipMemcpyHostToDevice, stream));
+    gargs.ntiles = ntiles_g;
+    const int gg = grad_grid();
+    prof_launch("gru_adj_grad", stream, [&](hipStream_t s2) {
+        hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, s2, gargs);
+    });
+    PN_HIP(hipGetLastError());
+    const int P = 3 * D * Dx + 3 * D * D + 4 * D;
+    hipLaunchKernelGGL(gru_adj_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, stream,
+                       (const float*)lay.part, gg, P, gparams);
+    PN_HIP(hipGetLastError());
+    if (gs0) {
+        hipLaunchKernelGGL(kk.gs0, dim3(hb.B), dim3(std::max(64, D)), 0, stream, args);
+        PN_HIP(hipGetLastError());
+    }
+    PN_HIP(hipStreamSynchronize(stream));
+    prof_collect();
+    return PN_OK;
+}
+
+// Sequential baseline of deer_adjoint: the same outputs, the reverse recurrence walked step by
+// step (the gate values and the gradient reductions are parallel kernels).
+pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                       const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                       float* gparams, void* ws, hipStream_t stream) {
+    const int D = cd.D, Dx = cd.Dx;
+    GruAKernels kk;
+    if (!gruA_lookup(D, Dx, &kk)) return PN_ERR_UNSUPPORTED;
+    void (*seqk)(const float*, const float*, const float*, float*, const int64_t*) = nullptr;
+    switch (D) {
+        case 16: seqk = gru_seq_adj_kernel<16>; break;
+        case 32: seqk = gru_seq_adj_kernel<32>; break;
+        case 48: seqk = gru_seq_adj_kernel<48>; break;
+        case 64: seqk = gru_seq_adj_kernel<64>; break;
+        default: return PN_ERR_UNSUPPORTED;
+    }
+    const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
+    const int ntiles = ts[hb.B];
+    const std::vector<int32_t> tsg = tile_starts(hb, kGradL);
+    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles);
+    PN_TRY(init_iter_state(lay.st, hb, ts, 1, 1.f, 1e4f, stream));
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
+    GruAdjArgs args{};
+    args.x = x;
+    args.s0 = s0;
+    args.s = s;
+    args.gs = gs;
+    args.params = (const float*)cd.params;
+    args.gates = lay.gates;
+    args.eps = lay.eps;
+    for (int p = 0; p < 2; ++p) {
+        args.lam[p] = lay.lam[p];
+        args.agg[p] = lay.agg[p];
+        args.incl[p] = lay.incl[p];
+    }
+    args.gmax = lay.gmax;
+    args.ctrl = lay.st.ctrl;
+    args.seq = lay.st.seq;
+    args.offsets = lay.st.offsets;
+    args.tile_start = lay.st.tile_start;
+    args.B = hb.B;
+    args.ntiles = ntiles;
+    args.part = lay.part;
+    args.gx = gx;
+    args.gs0 = gs0;
+    args.gparams = gparams;
+    if (ntiles > 0)
+        hipLaunchKernelGGL(kk.prep, dim3(std::max(1, std::min(ntiles, cu_count() * 2))),
+                           dim3(kk.nt), 0, stream, args);
+    const float* U = (const float*)cd.params + 3 * D * Dx;
+    prof_launch("seq_adj", stream, [&](hipStream_t s2) {
+        hipLaunchKernelGGL(seqk, dim3(hb.B), dim3(4 * D), 0, s2, (const float*)lay.gates, gs, U,
+                           lay.lam[0], (const int64_t*)lay.st.offsets);
+    });
+    PN_HIP(hipGetLastError());
+    PN_HIP(hipMemcpyAsync(lay.st.tile_start, tsg.data(), sizeof(int32_t) * (hb.B + 1),
+                          hipMemcpyHostToDevice, stream));
+    GruAdjArgs gargs = args;
+    gargs.ntiles = tsg[hb.B];
+    const int gg = grad_grid();
+    hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, stream, gargs);
+    const int P = 3 * D * Dx + 3 * D * D + 4 * D;
+    hipLaunchKernelGGL(gru_adj_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, stream,
+                       (const float*)lay.part, gg, P, gparams);
+    if (gs0) hipLaunchKernelGGL(kk.gs0, dim3(hb.B), dim3(std::max(64, D)), 0, stream, args);
+    PN_HIP(hipGetLastError());
+    PN_HIP(hipStreamSynchronize(stream));
+    prof_collect();
+    return PN_OK;
+}
+
+}  // namespace pn

@@ -1,0 +1,101 @@
+// Host-side helpers shared by the solver drivers: error reporting, workspace carving,
+// device properties, the per-iteration control kernels and the iteration loop with
+// optional hipGraph capture.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "pnewton.h"
+#include "pn_device.hpp"
+
+namespace pn {
+
+void set_error(const char* fmt, ...);
+pn_status hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define PN_HIP(call)                                                            \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) return ::pn::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define PN_TRY(expr)                        \
+    do {                                    \
+        pn_status s_ = (expr);              \
+        if (s_ < 0) return s_;              \
+    } while (0)
+
+struct HostBatch {
+    int B = 0;
+    int64_t N = 0;
+    std::vector<int64_t> offsets;   // B+1
+    int64_t Tmax = 0;
+    int64_t len(int b) const { return offsets[b + 1] - offsets[b]; }
+};
+
+// Carves 256-byte aligned pieces out of the caller's workspace (or only measures when
+// base is null).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
+int cu_count();
+
+// Event timing of kernel launches (pn_profile_begin / pn_profile_read).
+bool profiling();
+// Records an event pair around `launch(stream)` when profiling, else just launches.
+void prof_launch(const char* family, hipStream_t stream, const std::function<void(hipStream_t)>& launch);
+// Resolves the pending event pairs of this thread (after the stream was synchronised).
+void prof_collect();
+
+// Tile table: tile_start[b] = number of tiles of sequences < b, for tiles of L steps.
+std::vector<int32_t> tile_starts(const HostBatch& hb, int L);
+
+// State shared by every iterative solver (lives in the workspace).
+struct IterState {
+    Ctrl* ctrl;
+    SeqState* seq;
+    int64_t* offsets;      // device copy [B+1]
+    int32_t* tile_start;   // device [B+1]
+};
+void carve_iter_state(Carver& c, IterState& st, int B);
+
+// Uploads offsets / tile table, resets the per-sequence state and the control block.
+pn_status init_iter_state(const IterState& st, const HostBatch& hb,
+                          const std::vector<int32_t>& tstart, int max_iters, float tol,
+                          float reset_abs, hipStream_t stream);
+
+// Launches the end-of-iteration decision kernel (stop tests, counters).
+void launch_decide(const IterState& st, int B, hipStream_t stream);
+
+// Runs `one_iter` (which enqueues one iteration: main kernels + decide) until every
+// sequence is done, checking convergence on the host every `graph_iters` iterations;
+// with use_graph the batch of iterations is captured once and replayed.
+pn_status run_iterations(const IterState& st, int max_launches, int graph_iters,
+                         bool use_graph, const std::vector<uintptr_t>& graph_key,
+                         const std::function<void(hipStream_t)>& one_iter,
+                         hipStream_t stream);
+
+// Copies the final iterate from the alternate buffer for sequences whose final parity is
+// odd, and reads the per-sequence info back to the host.
+pn_status finish_iterations(const IterState& st, const HostBatch& hb, int D, size_t elem,
+                            void* s_user, const void* s_alt, hipStream_t stream,
+                            pn_seq_info* info, bool* all_converged, int* device_error);
+
+}  // namespace pn

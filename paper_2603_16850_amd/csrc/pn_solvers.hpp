@@ -1,0 +1,63 @@
+// Solver drivers behind the C ABI (one translation unit each).
+#pragma once
+#include "pn_host.hpp"
+
+namespace pn {
+
+const char* last_error();
+void profile_begin();
+void profile_end();
+int profile_read(const char* family, double* ms, int64_t* n);
+
+// quasi-DEER, GRU, FP32 (fused linearise + diagonal scan)
+bool gru_quasi_supported(int D, int Dx);
+size_t gru_quasi_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                            const float* s0, float* s, const pn_opts& o, void* ws,
+                            hipStream_t stream, pn_seq_info* info, bool* all_conv);
+
+// exact adjoint of the GRU by iterated reverse diagonal scans + parameter gradients
+size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                      const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                      float* gparams, const pn_opts& o, void* ws, hipStream_t stream,
+                      pn_seq_info* info, bool* all_conv);
+
+// DEER, GRU, FP64, small dense D (whole solve in one workgroup per sequence)
+bool gru_dense64_supported(int D, int Dx);
+size_t gru_dense64_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status gru_dense64_forward(const pn_cell_desc& cd, const HostBatch& hb, const double* x,
+                              const double* s0, double* s, const pn_opts& o, void* ws,
+                              hipStream_t stream, pn_seq_info* info, bool* all_conv);
+
+// DEER, tanh-RNN, FP32 residual, dense scan composed on MFMA (BF16 or FP32)
+bool tanh_dense_supported(int D, int Dx);
+size_t tanh_dense_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                             const float* s0, float* s, const pn_opts& o, void* ws,
+                             hipStream_t stream, pn_seq_info* info, bool* all_conv);
+
+// ELK, tanh-RNN, FP32
+bool elk_supported(int D, int Dx);
+size_t elk_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                      const float* s0, float* s, double lambda, const pn_opts& o, void* ws,
+                      hipStream_t stream, pn_seq_info* info, bool* all_conv);
+
+// sequential baselines
+bool seq_supported(int cell, int D, int Dx);
+size_t seq_workspace(int cell, int D, int Dx, const HostBatch& hb);
+pn_status seq_rollout_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                          const float* s0, float* s, void* ws, hipStream_t stream);
+pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                       const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                       float* gparams, void* ws, hipStream_t stream);
+
+// FP64 residual of an FP32 trajectory
+bool residual64_supported(int cell, int D, int Dx);
+size_t residual64_workspace(int cell, int D, int Dx, const HostBatch& hb);
+pn_status residual64_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                         const float* s0, const float* s, void* ws, hipStream_t stream,
+                         double* max_resid);
+
+}  // namespace pn
