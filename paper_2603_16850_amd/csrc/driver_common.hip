@@ -110,11 +110,13 @@ std::vector<int32_t> tile_starts(const HostBatch& hb, int L) {
     return ts;
 }
 
-void carve_iter_state(Carver& c, IterState& st, int B) {
+void carve_iter_state(Carver& c, IterState& st, int B, int ntiles) {
     st.ctrl = c.take<Ctrl>(1);
     st.seq = c.take<SeqState>(B);
     st.offsets = c.take<int64_t>(B + 1);
     st.tile_start = c.take<int32_t>(B + 1);
+    st.order = c.take<int32_t>(std::max(ntiles, 1));
+    st.tiles = c.take<TileInfo>(std::max(ntiles, 1));
 }
 
 __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offsets, int B,
@@ -147,12 +149,41 @@ __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offs
 }
 
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
-                          const std::vector<int32_t>& tstart, int max_iters, float tol,
-                          float reset_abs, hipStream_t stream) {
+                          const std::vector<int32_t>& tstart, int L, bool reverse,
+                          int max_iters, float tol, float reset_abs, hipStream_t stream) {
     PN_HIP(hipMemcpyAsync(st.offsets, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1),
                           hipMemcpyHostToDevice, stream));
     PN_HIP(hipMemcpyAsync(st.tile_start, tstart.data(), sizeof(int32_t) * (hb.B + 1),
                           hipMemcpyHostToDevice, stream));
+    // interleaved processing order and tile geometry (kept alive on the host until the next
+    // call on this thread, after which the copies have completed)
+    static thread_local std::vector<int32_t> order;
+    static thread_local std::vector<TileInfo> tiles;
+    order.clear();
+    tiles.clear();
+    int maxt = 0;
+    for (int b = 0; b < hb.B; ++b) maxt = std::max(maxt, tstart[b + 1] - tstart[b]);
+    for (int k = 0; k < maxt; ++k)
+        for (int b = 0; b < hb.B; ++b) {
+            const int nt = tstart[b + 1] - tstart[b];
+            if (k >= nt) continue;
+            TileInfo ti;
+            ti.slot = tstart[b] + k;
+            ti.b = b;
+            ti.lt = reverse ? nt - 1 - k : k;
+            ti.len = (int)std::min<int64_t>(L, hb.len(b) - (int64_t)ti.lt * L);
+            ti.row0 = hb.offsets[b] + (int64_t)ti.lt * L;
+            ti.first = tstart[b];
+            ti.pad_ = 0;
+            order.push_back(ti.slot);
+            tiles.push_back(ti);
+        }
+    if (!order.empty()) {
+        PN_HIP(hipMemcpyAsync(st.order, order.data(), sizeof(int32_t) * order.size(),
+                              hipMemcpyHostToDevice, stream));
+        PN_HIP(hipMemcpyAsync(st.tiles, tiles.data(), sizeof(TileInfo) * tiles.size(),
+                              hipMemcpyHostToDevice, stream));
+    }
     int blocks = std::min(64, (hb.B + 255) / 256);
     hipLaunchKernelGGL(init_state_kernel, dim3(std::max(1, blocks)), dim3(256), 0, stream,
                        st.ctrl, st.seq, st.offsets, hb.B, max_iters, tol, reset_abs);

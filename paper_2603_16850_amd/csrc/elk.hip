@@ -17,6 +17,7 @@
 //      publish the chunk's final (m, P).
 // lambda = 0 gives Gamma_t = I: the DEER step.
 #include <algorithm>
+#include <cstring>
 
 #include "pn_host.hpp"
 #include "pn_solvers.hpp"
@@ -163,9 +164,11 @@ struct ElkArgs {
     SeqState* seq;
     const int64_t* offsets;
     const int32_t* tile_start;
+    const int32_t* order;
     int B;
     int ntiles;
     float lam;
+    int res64;               // nonzero: the stopping residual is evaluated in FP64
 };
 
 template <int DX, int L>
@@ -180,7 +183,7 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
     __shared__ float aug[ED * 33];
     __shared__ float fac[ED];
     __shared__ float bi[ED], ei[ED], vx[ED], vy[ED], vz[ED];
-    __shared__ int tinfo[4];
+    __shared__ int tinfo[5];
 
     if (ld_i32(&a.ctrl->all_done)) return;
     const int k_it = a.ctrl->iter;
@@ -208,25 +211,27 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
     for (;;) {
         __syncthreads();
         if (l == 0) {
-            const int tile = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
-            tinfo[0] = tile;
-            if (tile < a.ntiles) {
+            const int idx = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
+            tinfo[0] = idx;
+            if (idx < a.ntiles) {
+                const int slot = a.order[idx];
                 int lo = 0, hi = a.B;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (a.tile_start[mid] <= tile) lo = mid; else hi = mid;
+                    if (a.tile_start[mid] <= slot) lo = mid; else hi = mid;
                 }
-                const int lt = tile - a.tile_start[lo];
+                const int lt = slot - a.tile_start[lo];
                 tinfo[1] = lo;
                 tinfo[2] = lt;
                 tinfo[3] = (a.seq[lo].status == kActive)
                                ? (int)std::min<int64_t>(L, a.offsets[lo + 1] - a.offsets[lo] - (int64_t)lt * L)
                                : -1;
+                tinfo[4] = slot;
             }
         }
         __syncthreads();
-        const int tile = tinfo[0];
-        if (tile >= a.ntiles) break;
+        if (tinfo[0] >= a.ntiles) break;
+        const int tile = tinfo[4];
         const int b = tinfo[1], lt = tinfo[2], len = tinfo[3];
         if (len < 0) continue;
         const bool first = lt == 0;
@@ -267,7 +272,29 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
                 const float res = sst[(t + 1) * SS + u] - f;
                 dsh[t * ED + u] = (first && t == 0) ? 0.f : 1.f - f * f;
                 rsh[t * ED + u] = res;
-                if (t < len) rmax = max(rmax, absbits(res));
+                if (t < len && !a.res64) rmax = max(rmax, absbits(res));
+            }
+        }
+        if (a.res64) {
+            // The stopping test of this iterate in FP64: s, x and the parameters upcast, the
+            // same quantity the final FP64 residual reports.  The FP32 residual above still
+            // drives the update; its rounding (~1e-7 here) would otherwise let an iterate
+            // pass a 1e-6 test that it fails in FP64.  The bound is rounded up to FP32.
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = 4 * g + i;
+                for (int tt = t; tt < L && tt < len; tt += 16) {
+                    double acc = (double)bias_u;
+                    for (int kk = 0; kk < ED; ++kk)
+                        acc += (double)Wm[u * ES + kk] * (double)sst[tt * SS + kk];
+                    for (int kk = 0; kk < DX; ++kk)
+                        acc += (double)U[u * DX + kk] * (double)xst[tt * XS + kk];
+                    const double r = (double)sst[(tt + 1) * SS + u] - tanh(acc);
+                    const double ar = fabs(r);
+                    float fr = (float)ar;
+                    if ((double)fr < ar) fr = nextafterf(fr, INFINITY);
+                    rmax = max(rmax, (r == r) ? absbits(fr) : 0x7F800000u);
+                }
             }
         }
         __syncthreads();
@@ -332,7 +359,7 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
             for (;;) {
                 if (words_ready(a.incl[par] + (size_t)pred * EINC, EINC)) break;
                 if (words_ready(a.agg[par] + (size_t)pred * EAGG, EAGG)) { --pred; continue; }
-                if (++spins > (1 << 22)) { if (l == 0) atomicExch(&a.ctrl->error, 1); break; }
+                if (++spins > (1 << 20) || ld_i32(&a.ctrl->error)) { if (l == 0) atomicExch(&a.ctrl->error, 1); break; }
                 __builtin_amdgcn_s_sleep(1);
             }
             load_mat(Ci, a.incl[par] + (size_t)pred * EINC);
@@ -420,7 +447,7 @@ struct ElkLayout {
 static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles) {
     Carver c(ws);
     ElkLayout lay;
-    carve_iter_state(c, lay.st, hb.B);
+    carve_iter_state(c, lay.st, hb.B, ntiles);
     lay.salt = c.take<float>((size_t)hb.N * ED);
     for (int p = 0; p < 2; ++p) lay.agg[p] = c.take<uint64_t>((size_t)ntiles * EAGG);
     for (int p = 0; p < 2; ++p) lay.incl[p] = c.take<uint64_t>((size_t)ntiles * EINC);
@@ -453,7 +480,8 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const int ntiles = ts[hb.B];
     ElkLayout lay = elk_layout(ws, hb, ntiles);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
-    PN_TRY(init_iter_state(lay.st, hb, ts, max_iters, (float)o.tol, (float)o.reset_abs, stream));
+    PN_TRY(init_iter_state(lay.st, hb, ts, kElkL, false, max_iters, (float)o.tol,
+                           (float)o.reset_abs, stream));
     if (ntiles > 0) {
         const size_t na = (size_t)ntiles * EAGG, ni = (size_t)ntiles * EINC;
         hipLaunchKernelGGL(elk_fill_kernel, dim3((unsigned)std::min<size_t>(4096, (na + 255) / 256)),
@@ -477,19 +505,23 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.seq = lay.st.seq;
     args.offsets = lay.st.offsets;
     args.tile_start = lay.st.tile_start;
+    args.order = lay.st.order;
     args.B = hb.B;
     args.ntiles = ntiles;
     args.lam = (float)lambda;
+    args.res64 = o.fp64_final_residual ? 1 : 0;
     auto one_iter = [&](hipStream_t st) {
         prof_launch("elk_iter", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
         });
         launch_decide(lay.st, hb.B, st);
     };
+    uint32_t lam_bits = 0;
+    std::memcpy(&lam_bits, &args.lam, sizeof lam_bits);
     std::vector<uintptr_t> key = {0x454Cu, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
                                   (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
-                                  (uintptr_t)(lambda * 1e9)};
+                                  (uintptr_t)lam_bits, (uintptr_t)args.res64};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;

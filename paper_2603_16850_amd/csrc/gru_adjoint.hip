@@ -53,6 +53,8 @@ struct GruAdjArgs {
     SeqState* seq;
     const int64_t* offsets;
     const int32_t* tile_start;
+    const int32_t* order;
+    const TileInfo* tiles;   // processing order with geometry (reverse scan)
     int B;
     int ntiles;
     float* part;             // [grid][P] per-workgroup parameter-gradient partials
@@ -144,11 +146,12 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs 
 
 // ---- one adjoint iteration ------------------------------------------------------------------
 template <int D, int DX, int L>
-__global__ void __launch_bounds__(64 * (D / 16)) gru_adj_iter_kernel(GruAdjArgs a) {
+__global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gru_adj_iter_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
     __shared__ __attribute__((aligned(16))) float ps[L * C::PS];
     __shared__ int rowbad[L];
-    __shared__ int tinfo[4];
+    __shared__ int tnext[2][8];
 
     if (ld_i32(&a.ctrl->all_done)) return;
     const int k = a.ctrl->iter;
@@ -178,29 +181,27 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_iter_kernel(GruAdjArgs 
                 dUn = U[(2 * D + j) * D + j];
 
     for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
-    for (;;) {
+    if (tid == 0) fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
+                             (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[0]);
+    for (int it = 0;; ++it) {
         __syncthreads();
-        if (tid == 0) {
-            const int tile = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
-            tinfo[0] = tile;
-            if (tile < a.ntiles) {
-                int b, lt, len;
-                tile_of(a, tile, L, true, &b, &lt, &len);
-                tinfo[1] = b;
-                tinfo[2] = lt;
-                tinfo[3] = (a.seq[b].status == kActive) ? len : -1;
-            }
+        const int* tn = tnext[it & 1];
+        if (tn[0] >= a.ntiles) break;
+        const int tile = tn[1];         // slot, numbered from the sequence end
+        const int b = tn[2];
+        const int lt = tn[3];
+        const int len = tn[4];
+        const int64_t row0 = ((int64_t)tn[6] << 32) | (uint32_t)tn[5];
+        if (tn[7] != kActive) {
+            if (tid == 0)
+                fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
+                           (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
+            continue;
         }
-        __syncthreads();
-        const int tile = tinfo[0];
-        if (tile >= a.ntiles) break;
-        const int b = tinfo[1];
-        const int lt = tinfo[2];
-        const int len = tinfo[3];
-        if (len < 0) continue;
-        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
-        const int64_t rend = a.offsets[b + 1];                 // one past the sequence's last row
-        const bool first = row0 + L >= rend;                   // tile at the sequence end
+        const int first_slot = a.tile_start[b];
+        const bool first = tile == first_slot;                 // tile at the sequence end
+        // one past the last row that has a successor step inside the sequence
+        const int64_t rend = first ? row0 + len : row0 + L + 1;
         const float gscale = 1.f / fmaxf(1.f, a.gmax[b]);
 
         if (g == 0) {
@@ -299,9 +300,12 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_iter_kernel(GruAdjArgs 
             Rc = Ta * Rc + Tc;
             Ra = Ta * Ra;
         }
-        float din = 0.f;
-        if (g == 0) din = lookback(aggc, inclc, tile, first, D, j, Ra, Rc, &a.ctrl->error);
-        din = __shfl(din, u);
+        const float din = lookback4(aggc, inclc, tile, first_slot, D, j, g, u, Ra, Rc,
+                                    &a.ctrl->error);
+        // claim the next tile only once this one's carry is known (as in the forward kernel)
+        if (tid == 0)
+            fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
+                       (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
 
 #pragma unroll
         for (int mb = 0; mb < C::MB; ++mb)
@@ -587,7 +591,7 @@ static int grad_grid() { return cu_count(); }
 static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int ntiles) {
     Carver c(ws);
     GruALayout lay;
-    carve_iter_state(c, lay.st, hb.B);
+    carve_iter_state(c, lay.st, hb.B, ntiles);
     lay.gates = c.take<float>((size_t)hb.N * 4 * D);
     lay.eps = c.take<float>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
@@ -656,7 +660,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const int ntiles_g = tsg[hb.B];
     GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
-    PN_TRY(init_iter_state(lay.st, hb, ts, max_iters, (float)o.tol, (float)o.reset_abs, stream));
+    PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, max_iters, (float)o.tol,
+                           (float)o.reset_abs, stream));
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
     if (ntiles > 0) {
         const size_t n = (size_t)ntiles * D;
@@ -683,6 +688,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.seq = lay.st.seq;
     args.offsets = lay.st.offsets;
     args.tile_start = lay.st.tile_start;
+    args.order = lay.st.order;
+    args.tiles = lay.st.tiles;
     args.B = hb.B;
     args.ntiles = ntiles;
     args.part = lay.part;
@@ -764,7 +771,7 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     const int ntiles = ts[hb.B];
     const std::vector<int32_t> tsg = tile_starts(hb, kGradL);
     GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles);
-    PN_TRY(init_iter_state(lay.st, hb, ts, 1, 1.f, 1e4f, stream));
+    PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, 1, 1.f, 1e4f, stream));
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
     GruAdjArgs args{};
     args.x = x;
@@ -784,6 +791,8 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.seq = lay.st.seq;
     args.offsets = lay.st.offsets;
     args.tile_start = lay.st.tile_start;
+    args.order = lay.st.order;
+    args.tiles = lay.st.tiles;
     args.B = hb.B;
     args.ntiles = ntiles;
     args.part = lay.part;

@@ -49,18 +49,20 @@ struct GruQArgs {
     SeqState* seq;
     const int64_t* offsets;
     const int32_t* tile_start;
+    const int32_t* order;
+    const TileInfo* tiles;   // processing order with geometry
     int B;
     int ntiles;
 };
 
 template <int D, int DX, int L>
-__global__ void __launch_bounds__(64 * (D / 16))
+__global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gru_quasi_iter_kernel(GruQArgs a) {
     using C = GruQ<D, DX, L>;
     __shared__ __attribute__((aligned(16))) float hs[(L + 1) * C::HS];
     __shared__ __attribute__((aligned(16))) float xs[L * C::XS];
     __shared__ int rowbad[L];
-    __shared__ int tinfo[6];
+    __shared__ int tnext[2][8];   // next tile, double-buffered by loop parity
 
     if (ld_i32(&a.ctrl->all_done)) return;
     const int k = a.ctrl->iter;
@@ -84,39 +86,25 @@ gru_quasi_iter_kernel(GruQArgs a) {
     wg.load(a.params, j, g);
 
     for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
+    if (tid == 0) fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
+                             (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[0]);
 
-    for (;;) {
-        __syncthreads();   // previous tile fully consumed (LDS reuse)
-        if (tid == 0) {
-            const int tile = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
-            int b = -1;
-            if (tile < a.ntiles) {
-                int lo = 0, hi = a.B;      // last b with tile_start[b] <= tile
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (a.tile_start[mid] <= tile) lo = mid; else hi = mid;
-                }
-                b = lo;
-            }
-            tinfo[0] = tile;
-            tinfo[1] = b;
-            if (b >= 0) {
-                const int lt = tile - a.tile_start[b];
-                const int64_t len_seq = a.offsets[b + 1] - a.offsets[b];
-                tinfo[2] = lt;
-                tinfo[3] = (int)std::min<int64_t>(L, len_seq - (int64_t)lt * L);
-                tinfo[4] = a.seq[b].status;
-            }
+    for (int it = 0;; ++it) {
+        __syncthreads();   // previous tile fully consumed (LDS reuse); tnext[it&1] published
+        const int* tn = tnext[it & 1];
+        if (tn[0] >= a.ntiles) break;
+        const int tile = tn[1];         // scan slot of this tile
+        const int b = tn[2];
+        const int lt = tn[3];
+        const int len = tn[4];
+        const int64_t row0 = ((int64_t)tn[6] << 32) | (uint32_t)tn[5];
+        if (tn[7] != kActive) {
+            if (tid == 0)
+                fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
+                           (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
+            continue;
         }
-        __syncthreads();
-        const int tile = tinfo[0];
-        if (tile >= a.ntiles) break;
-        const int b = tinfo[1];
-        if (tinfo[4] != kActive) continue;
-        const int lt = tinfo[2];
-        const int len = tinfo[3];
         const bool first = lt == 0;
-        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
 
         // this tile's slots of the next iteration start unpublished
         if (g == 0) {
@@ -149,7 +137,7 @@ gru_quasi_iter_kernel(GruQArgs a) {
         __syncthreads();
 
         // ---- gates by MFMA, then residual and leaves, per 16-step block ----
-        float la[C::MB][4], lc[C::MB][4], scur[C::MB][4];
+        float la[C::MB][4], lc[C::MB][4];
         uint32_t rmax = 0;
 #pragma unroll
         for (int mb = 0; mb < C::MB; ++mb) {
@@ -171,7 +159,7 @@ gru_quasi_iter_kernel(GruQArgs a) {
                 if (first && tl == 0) dg = 0.f;
                 la[mb][i] = valid ? dg : 1.f;
                 lc[mb][i] = valid ? -res : 0.f;
-                scur[mb][i] = sc;
+
                 if (valid) rmax = max(rmax, absbits(res));
             }
         }
@@ -214,16 +202,23 @@ gru_quasi_iter_kernel(GruQArgs a) {
         }
 
         // ---- decoupled look-back for the carry-in Delta_{t0-1} of unit j ----
-        float din = 0.f;
-        if (g == 0) din = lookback(aggc, inclc, tile, first, D, j, Ra, Rc, &a.ctrl->error);
-        din = __shfl(din, u);
+        const float din = lookback4(aggc, inclc, tile, tile - lt, D, j, g, u, Ra, Rc,
+                                    &a.ctrl->error);
+
+        // The next tile is claimed only now.  A claim made earlier would hand a tile to a
+        // workgroup that is still blocked in this look-back, and every later tile of that
+        // sequence would wait on it; claimed this late, its geometry is read while the new
+        // iterate is written.
+        if (tid == 0)
+            fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
+                       (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
 
         // ---- new iterate (kept in lc), overflow guard ----
 #pragma unroll
         for (int mb = 0; mb < C::MB; ++mb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float v = scur[mb][i] + (la[mb][i] * din + lc[mb][i]);
+                const float v = hs[(mb * 16 + 4 * g + i + 1) * C::HS + j] + (la[mb][i] * din + lc[mb][i]);
                 lc[mb][i] = v;
                 const int tl = mb * 16 + 4 * g + i;
                 const bool bad = (tl < len) && !(fabsf(v) <= reset_abs);
@@ -270,7 +265,7 @@ struct GruQLayout {
 static GruQLayout gruq_layout(void* ws, int D, const HostBatch& hb, int ntiles) {
     Carver c(ws);
     GruQLayout lay;
-    carve_iter_state(c, lay.st, hb.B);
+    carve_iter_state(c, lay.st, hb.B, ntiles);
     lay.salt = c.take<float>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.agg[p] = c.take<uint64_t>((size_t)ntiles * D);
     for (int p = 0; p < 2; ++p) lay.incl[p] = c.take<uint32_t>((size_t)ntiles * D);
@@ -336,7 +331,8 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     const int ntiles = ts[hb.B];
     GruQLayout lay = gruq_layout(ws, D, hb, ntiles);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
-    PN_TRY(init_iter_state(lay.st, hb, ts, max_iters, (float)o.tol, (float)o.reset_abs, stream));
+    PN_TRY(init_iter_state(lay.st, hb, ts, L, false, max_iters, (float)o.tol,
+                           (float)o.reset_abs, stream));
     if (ntiles > 0) {
         const size_t n = (size_t)ntiles * D;
         hipLaunchKernelGGL(fill_sentinels_kernel, dim3((unsigned)std::min<size_t>(4096, (n + 255) / 256)),
@@ -359,6 +355,8 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     args.seq = lay.st.seq;
     args.offsets = lay.st.offsets;
     args.tile_start = lay.st.tile_start;
+    args.order = lay.st.order;
+    args.tiles = lay.st.tiles;
     args.B = hb.B;
     args.ntiles = ntiles;
 

@@ -36,6 +36,17 @@ struct SeqState {
     int pad_;
 };
 
+// One entry per tile, in the order workgroups take them (see IterState::tiles).
+struct TileInfo {
+    int32_t slot;       // scan slot of the tile (consecutive within a sequence, scan order)
+    int32_t b;          // sequence
+    int32_t lt;         // tile index from the sequence start (rows row0 .. row0+len-1)
+    int32_t len;        // valid steps
+    int64_t row0;       // first row
+    int32_t first;      // slot of the sequence's first scanned tile
+    int32_t pad_;
+};
+
 struct Ctrl {
     int iter;           // index k of the iterate the next main kernel linearises
     int all_done;       // 1 when no sequence is active
@@ -46,6 +57,24 @@ struct Ctrl {
     float reset_abs;
     int pad_;
 };
+
+// Reads tile `idx` of the processing order (and its sequence's status) into out[0..7]:
+// idx, slot, b, lt, len, row0 low, row0 high, status.
+PN_DEV void fetch_tile(const Ctrl* ctrl, const TileInfo* tiles, const SeqState* seq, int ntiles,
+                       int idx, int* out) {
+    (void)ctrl;
+    out[0] = idx;
+    if (idx < ntiles) {
+        const TileInfo ti = tiles[idx];
+        out[1] = ti.slot;
+        out[2] = ti.b;
+        out[3] = ti.lt;
+        out[4] = ti.len;
+        out[5] = (int)(uint32_t)(uint64_t)ti.row0;
+        out[6] = (int)((uint64_t)ti.row0 >> 32);
+        out[7] = seq[ti.b].status;
+    }
+}
 
 // ---- atomics ------------------------------------------------------------------------------
 PN_DEV uint64_t ld_u64(const uint64_t* p) {

@@ -73,13 +73,21 @@ struct IterState {
     SeqState* seq;
     int64_t* offsets;      // device copy [B+1]
     int32_t* tile_start;   // device [B+1]
+    int32_t* order;        // device [ntiles]: processing order of tile slots
+    TileInfo* tiles;       // device [ntiles]: the same order with each tile's geometry
 };
-void carve_iter_state(Carver& c, IterState& st, int B);
+// Tile slots of sequence b are tile_start[b] .. tile_start[b+1]-1, numbered in the order a
+// sequence is scanned (from its start, or from its end for reverse scans).  Workgroups take
+// slots in `order`: every sequence's first slot, then every sequence's second slot, ... so the
+// tiles running at once spread over the sequences and look-back chains stay short.
+void carve_iter_state(Carver& c, IterState& st, int B, int ntiles);
 
 // Uploads offsets / tile table, resets the per-sequence state and the control block.
+// Tiles are L steps long; with `reverse` a sequence is scanned from its end (its last tile
+// gets the sequence's first slot).
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
-                          const std::vector<int32_t>& tstart, int max_iters, float tol,
-                          float reset_abs, hipStream_t stream);
+                          const std::vector<int32_t>& tstart, int L, bool reverse,
+                          int max_iters, float tol, float reset_abs, hipStream_t stream);
 
 // Launches the end-of-iteration decision kernel (stop tests, counters).
 void launch_decide(const IterState& st, int B, hipStream_t stream);

@@ -47,6 +47,7 @@ struct TanhDArgs {
     SeqState* seq;
     const int64_t* offsets;
     const int32_t* tile_start;
+    const int32_t* order;
     int B;
     int ntiles;
 };
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(64) tanh_dense_iter_kernel(TanhDArgs a) {
     __shared__ __attribute__((aligned(16))) float dsh[L * TD];
     __shared__ __attribute__((aligned(16))) float csh[L * TD];
     __shared__ __attribute__((aligned(16))) float vec[2][TD];
-    __shared__ int tinfo[4];
+    __shared__ int tinfo[5];
 
     if (ld_i32(&a.ctrl->all_done)) return;
     const int k_it = a.ctrl->iter;
@@ -107,25 +108,27 @@ __global__ void __launch_bounds__(64) tanh_dense_iter_kernel(TanhDArgs a) {
     for (;;) {
         __syncthreads();
         if (l == 0) {
-            const int tile = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
-            tinfo[0] = tile;
-            if (tile < a.ntiles) {
+            const int idx = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
+            tinfo[0] = idx;
+            if (idx < a.ntiles) {
+                const int slot = a.order[idx];
                 int lo = 0, hi = a.B;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (a.tile_start[mid] <= tile) lo = mid; else hi = mid;
+                    if (a.tile_start[mid] <= slot) lo = mid; else hi = mid;
                 }
-                const int lt = tile - a.tile_start[lo];
+                const int lt = slot - a.tile_start[lo];
                 tinfo[1] = lo;
                 tinfo[2] = lt;
                 tinfo[3] = (a.seq[lo].status == kActive)
                                ? (int)std::min<int64_t>(L, a.offsets[lo + 1] - a.offsets[lo] - (int64_t)lt * L)
                                : -1;
+                tinfo[4] = slot;
             }
         }
         __syncthreads();
-        const int tile = tinfo[0];
-        if (tile >= a.ntiles) break;
+        if (tinfo[0] >= a.ntiles) break;
+        const int tile = tinfo[4];
         const int b = tinfo[1], lt = tinfo[2], len = tinfo[3];
         if (len < 0) continue;
         const bool first = lt == 0;
@@ -226,12 +229,8 @@ __global__ void __launch_bounds__(64) tanh_dense_iter_kernel(TanhDArgs a) {
                 const float other = __shfl_down(pacc[e], 1);
                 if ((n & 1) == 0) st_u64(&ag[acc_row(g, e) * 16 + (n >> 1)], pack2(pacc[e], other));
             }
-            if (g == 0 && (n & 1) == 0) {
-                const float qo = __shfl_down(qend, 1);
-                st_u64(&ag[TD * 16 + (n >> 1)], pack2(qend, qo));
-            } else {
-                (void)__shfl_down(qend, 1);
-            }
+            const float qo = __shfl_down(qend, 1);     // all lanes take part in the shuffle
+            if (g == 0 && (n & 1) == 0) st_u64(&ag[TD * 16 + (n >> 1)], pack2(qend, qo));
             // walk back until an inclusive value is found
             int pred = tile - 1, spins = 0;
             for (;;) {
@@ -242,7 +241,7 @@ __global__ void __launch_bounds__(64) tanh_dense_iter_kernel(TanhDArgs a) {
                 for (int w = l; w < AGG_WORDS; w += 64)
                     aready = aready && ready64(ld_u64(&a.agg[par][(size_t)pred * AGG_WORDS + w]));
                 if (__all(aready)) { --pred; continue; }
-                if (++spins > (1 << 22)) { if (l == 0) atomicExch(&a.ctrl->error, 1); break; }
+                if (++spins > (1 << 20) || ld_i32(&a.ctrl->error)) { if (l == 0) atomicExch(&a.ctrl->error, 1); break; }
                 __builtin_amdgcn_s_sleep(1);
             }
             // Delta_end of `pred`, then forward through the aggregates of pred+1 .. tile-1
@@ -316,7 +315,7 @@ struct TanhDLayout {
 static TanhDLayout tanhd_layout(void* ws, const HostBatch& hb, int ntiles) {
     Carver c(ws);
     TanhDLayout lay;
-    carve_iter_state(c, lay.st, hb.B);
+    carve_iter_state(c, lay.st, hb.B, ntiles);
     lay.salt = c.take<float>((size_t)hb.N * TD);
     for (int p = 0; p < 2; ++p) lay.agg[p] = c.take<uint64_t>((size_t)ntiles * AGG_WORDS);
     for (int p = 0; p < 2; ++p) lay.incl[p] = c.take<uint64_t>((size_t)ntiles * INCL_WORDS);
@@ -350,7 +349,8 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
     const int ntiles = ts[hb.B];
     TanhDLayout lay = tanhd_layout(ws, hb, ntiles);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
-    PN_TRY(init_iter_state(lay.st, hb, ts, max_iters, (float)o.tol, (float)o.reset_abs, stream));
+    PN_TRY(init_iter_state(lay.st, hb, ts, kTanhL, false, max_iters, (float)o.tol,
+                           (float)o.reset_abs, stream));
     if (ntiles > 0) {
         const size_t na = (size_t)ntiles * AGG_WORDS, ni = (size_t)ntiles * INCL_WORDS;
         hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)std::min<size_t>(4096, (na + 255) / 256)),
@@ -374,6 +374,7 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
     args.seq = lay.st.seq;
     args.offsets = lay.st.offsets;
     args.tile_start = lay.st.tile_start;
+    args.order = lay.st.order;
     args.B = hb.B;
     args.ntiles = ntiles;
     auto one_iter = [&](hipStream_t st) {

@@ -1,0 +1,126 @@
+"""The C ABI on the CPU: the library loads, exports every function pnewton.h declares, and
+rejects invalid arguments before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2603_16850_amd as pn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pnewton.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pn.LIB_PATH):
+        pytest.skip("libpnewton.so not built")
+    return pn.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"deer_solve", "elk_solve", "deer_adjoint", "pn_workspace_bytes"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in pn.SIGNATURES}
+    assert set(names) == bound, set(names) ^ bound
+
+
+def test_version_and_status_strings(lib):
+    assert lib.pn_abi_version() == 1
+    assert lib.pn_status_str(0) == b"PN_OK"
+    assert lib.pn_status_str(-3) == b"PN_ERR_WORKSPACE"
+    assert lib.pn_status_str(99) == b"unknown status"
+
+
+def _desc(cell="gru", D=64, Dx=32, dtype="f32", params=1 << 20, B=2, N=200, offsets=None):
+    c = pn.CellDesc(pn.CELLS.get(cell, 7), D, Dx, pn.DTYPES.get(dtype, 9), params)
+    off = None if offsets is None else np.asarray(offsets, np.int64)
+    b = pn.Batch(B, 0, N, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if off is not None else None)
+    return c, b, off
+
+
+def _ws(lib, op, c, b, o):
+    n = ctypes.c_size_t(0)
+    st = lib.pn_workspace_bytes(op, ctypes.byref(c), ctypes.byref(b), ctypes.byref(o), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_query_on_host(lib):
+    o = pn.make_opts(jac="diag")
+    c, b, _ = _desc()
+    st, n = _ws(lib, pn.OP_DEER, c, b, o)
+    assert st == 0 and n > 200 * 64 * 4
+    st, n2 = _ws(lib, pn.OP_ADJOINT, c, b, o)
+    assert st == 0 and n2 > 0
+    c, b, _ = _desc(cell="tanh", D=32, Dx=16)
+    st, _ = _ws(lib, pn.OP_DEER, c, b, pn.make_opts(jac="dense", compose="bf16"))
+    assert st == 0
+    c, b, _ = _desc(cell="tanh", D=16, Dx=16)
+    st, _ = _ws(lib, pn.OP_ELK, c, b, pn.make_opts(jac="dense"))
+    assert st == 0
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(D=0), -1), (dict(Dx=0), -1), (dict(cell="bogus"), -1), (dict(dtype="f16"), -1),
+    (dict(params=0), -1), (dict(B=0), -1), (dict(N=201), -1),          # N not divisible by B
+    (dict(offsets=[0, 50, 40]), -1), (dict(offsets=[1, 100, 200]), -1),
+    (dict(offsets=[0, 100, 150]), -1),                                  # offsets[B] != N
+    (dict(D=40), -2), (dict(cell="tanh", D=64), -2),                   # valid but not built
+])
+def test_invalid_arguments_rejected_before_hip(lib, kw, expect):
+    c, b, _keep = _desc(**kw)
+    o = pn.make_opts(jac="diag")
+    st = lib.deer_solve(ctypes.byref(c), ctypes.byref(b), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                        ctypes.c_void_p(16), ctypes.byref(o), None, 0, None, None)
+    assert st == expect, (kw, st, lib.pn_last_error())
+    assert lib.pn_last_error()
+
+
+def test_bad_options_and_pointers(lib):
+    c, b, _ = _desc()
+    o = pn.make_opts(jac="diag")
+    o.tol = -1.0
+    args = (ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0, None, None) == -1
+    o = pn.make_opts(jac="diag")
+    o.jac = 5
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0, None, None) == -1
+    o = pn.make_opts(jac="diag")
+    # NULL and misaligned device pointers
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), None, *args[1:], ctypes.byref(o), None, 0, None, None) == -1
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), ctypes.c_void_p(18), *args[1:], ctypes.byref(o), None, 0, None, None) == -1
+    # workspace missing / too small / misaligned
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0, None, None) == -3
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), ctypes.c_void_p(256), 10, None, None) == -3
+    _, need = _ws(lib, pn.OP_DEER, c, b, o)
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), ctypes.c_void_p(260), need, None, None) == -3
+    # ELK: negative lambda, unsupported shape
+    c2, b2, _ = _desc(cell="tanh", D=16, Dx=16)
+    assert lib.elk_solve(ctypes.byref(c2), ctypes.byref(b2), *args, ctypes.c_double(-1.0), ctypes.byref(o), None, 0, None, None) == -1
+    c3, b3, _ = _desc(cell="tanh", D=32, Dx=16)
+    assert lib.elk_solve(ctypes.byref(c3), ctypes.byref(b3), *args, ctypes.c_double(1.0), ctypes.byref(o), None, 0, None, None) == -2
+    # adjoint needs gparams
+    assert lib.deer_adjoint(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_void_p(16), None, None, None,
+                            ctypes.byref(o), None, 0, None, None) == -1
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    x = torch.zeros(10, 8)
+    with pytest.raises(ValueError):
+        pn.deer_solve(x, torch.zeros(1, 16), torch.zeros(10))
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    with pytest.raises(ImportError):
+        pn.load(str(tmp_path / "missing.so"))

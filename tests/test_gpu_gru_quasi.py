@@ -6,7 +6,6 @@ rollout, iteration counts within one of the FP64 sequential Newton loop.  A resi
 the error checks stop the iteration at residual 1e-6 (ERR_TOL); runs at the stated 1e-5 are
 checked on the residual they report.
 """
-ERR_TOL = 1e-6
 import numpy as np
 import pytest
 
@@ -14,6 +13,8 @@ from oracle import cells, newton, rollout
 from paper_2603_16850_amd import workloads
 
 pytestmark = pytest.mark.gpu
+
+ERR_TOL = 1e-6
 
 
 def _to(t, torch):
