@@ -31,6 +31,17 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 
 
+# kernel families timed inside the solver calls (HIP events on the library's stream)
+FAMILIES = ("gru_quasi_local", "gru_adj_local", "carry_scan", "apply", "gru_adj_prep",
+            "gru_adj_grad")
+
+
+def apply_bytes(D):
+    """Algorithmic HBM bytes per step of the apply pass: read s (or lambda) and (la, lc),
+    write the new iterate (FP32)."""
+    return 4 * D + 8 * D + 4 * D
+
+
 def gate_gemm_flops(D, Dx):
     """Algorithmic MFMA flops per step of the gate GEMM: z, r on [h; x], U_n h, W_n x."""
     return 2 * D * (2 * (D + Dx) + D + Dx)
@@ -94,8 +105,7 @@ def main():
             out = step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        fam = {f: pn.profile.read(f) for f in
-               ("gru_quasi_iter", "gru_adj_iter", "gru_adj_prep", "gru_adj_grad")}
+        fam = {f: pn.profile.read(f) for f in FAMILIES}
     s, gp, gx, g0, finfo, binfo = out
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = N / (ms_per_step * 1e-3)
@@ -118,23 +128,25 @@ def main():
         torch.cuda.synchronize()
 
     # ---- roofline of the dominant kernel (largest share of the measured kernel time)
-    fwd_ms, fwd_n = fam["gru_quasi_iter"]
-    adj_ms, adj_n = fam["gru_adj_iter"]
+    dom = max(fam, key=lambda f: fam[f][0])
+    dms, dn = fam[dom]
+    avg_ms = dms / max(dn, 1)
     it_f = [i["iters"] for i in finfo]
     it_b = [i["iters"] for i in binfo]
-    if fwd_ms >= adj_ms:
-        dom, dms, dn = "gru_quasi_iter", fwd_ms, fwd_n
-        per_launch_flops = gate_gemm_flops(D, Dx) * N          # every step is active
+    if dom in ("gru_quasi_local", "gru_adj_local"):
+        per_launch = (gate_gemm_flops(D, Dx) if dom == "gru_quasi_local" else vjp_gemm_flops(D)) * N
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4)}
     else:
-        dom, dms, dn = "gru_adj_iter", adj_ms, adj_n
-        per_launch_flops = vjp_gemm_flops(D) * N
-    avg_ms = dms / max(dn, 1)
-    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "avg_launch_ms": round(avg_ms, 4), "launches": dn,
-                "algorithmic_per_launch": per_launch_flops}
+        per_launch = apply_bytes(D) * N          # apply (carry_scan is never dominant)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    roofline.update({"traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": dn,
+                     "algorithmic_per_launch": per_launch})
 
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "sequence-steps/s",

@@ -68,7 +68,11 @@ typedef enum {
 
 typedef enum {
     PN_JAC_DENSE = 0,   /* A~_t = A_t (DEER)                                             */
-    PN_JAC_DIAG = 1     /* A~_t = diag(A_t), closed form (quasi-DEER)                     */
+    PN_JAC_DIAG = 1,    /* A~_t = diag(A_t), closed form (quasi-DEER)                     */
+    PN_JAC_PICARD = 2,  /* A~_t = I: Picard iteration as quasi-DEER (Prop. picard)         */
+    PN_JAC_JACOBI = 3   /* A~_t = 0: Jacobi iteration, s_t <- f(s_{t-1}) for all t at once
+                           (Table fxd_pt_sum).  One Jacobi iteration from s = 0 is the
+                           initialisation s_t^(0) = f(0, x_t) discussed in Ch. 3          */
 } pn_jac;
 
 typedef enum { PN_F32 = 0, PN_F64 = 1 } pn_dtype;
@@ -135,9 +139,12 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
 /* DEER / quasi-DEER (Alg. alg:deer with eq. lin_rr or eq. quasi_lds).
    s [N, D] is read as the initial guess s^(0) and overwritten with the result.
    info: HOST array [B] (may be NULL).  Built combinations:
-     GRU,  PN_JAC_DIAG,  F32, D in {16,32,48,64}, Dx a multiple of 8, 8 <= Dx <= 64
-     GRU,  PN_JAC_DENSE, F64, 1 <= D <= 8, 1 <= Dx <= 16
-     TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16 */
+     GRU,  PN_JAC_DIAG / PN_JAC_PICARD / PN_JAC_JACOBI, F32, (D, Dx) in
+           {(16,8), (16,16), (32,8), (32,16), (32,32), (48,24), (48,48), (64,16), (64,32),
+            (64,64)}, tile 0 (default), 32, 64 or 128
+     GRU,  PN_JAC_DENSE, F64, 1 <= D <= 4, 1 <= Dx <= 16
+     TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16
+   Anything else returns PN_ERR_UNSUPPORTED. */
 pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                      const void* s0, void* s, const pn_opts* opts, void* workspace,
                      size_t workspace_bytes, void* stream, pn_seq_info* info);

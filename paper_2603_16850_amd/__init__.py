@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libpnewton.so")
 
 PN_OK, PN_NOT_CONVERGED = 0, 1
 CELLS = {"gru": 0, "tanh": 1}
-JACS = {"dense": 0, "diag": 1}
+JACS = {"dense": 0, "diag": 1, "picard": 2, "jacobi": 3}
 DTYPES = {"f32": 0, "f64": 1}
 COMPOSE = {"native": 0, "bf16": 1}
 OP_DEER, OP_ELK, OP_ADJOINT, OP_RESIDUAL64, OP_SEQ = 0, 1, 2, 3, 4

@@ -73,7 +73,7 @@ pn_status check_batch(const pn_batch* batch, HostBatch& hb) {
 }
 
 pn_status check_opts(const pn_opts& o) {
-    if (o.jac != PN_JAC_DENSE && o.jac != PN_JAC_DIAG) { set_error("unknown jac %d", o.jac); return PN_ERR_INVALID_ARG; }
+    if (o.jac < PN_JAC_DENSE || o.jac > PN_JAC_JACOBI) { set_error("unknown jac %d", o.jac); return PN_ERR_INVALID_ARG; }
     if (o.compose != PN_COMPOSE_NATIVE && o.compose != PN_COMPOSE_BF16) {
         set_error("unknown compose %d", o.compose);
         return PN_ERR_INVALID_ARG;
@@ -106,8 +106,9 @@ pn_status check_ws(void* ws, size_t have, size_t need) {
 enum class Route { None, GruQuasi, GruDense64, TanhDense, Elk };
 
 Route route_deer(const pn_cell_desc& c, const pn_opts& o) {
-    if (c.cell == PN_CELL_GRU && o.jac == PN_JAC_DIAG && c.dtype == PN_F32 &&
-        o.compose == PN_COMPOSE_NATIVE && gru_quasi_supported(c.D, c.Dx))
+    if (c.cell == PN_CELL_GRU && c.dtype == PN_F32 && o.compose == PN_COMPOSE_NATIVE &&
+        (o.jac == PN_JAC_DIAG || o.jac == PN_JAC_PICARD || o.jac == PN_JAC_JACOBI) &&
+        gru_quasi_supported(c.D, c.Dx))
         return Route::GruQuasi;
     if (c.cell == PN_CELL_GRU && o.jac == PN_JAC_DENSE && c.dtype == PN_F64 &&
         gru_dense64_supported(c.D, c.Dx))

@@ -110,13 +110,22 @@ std::vector<int32_t> tile_starts(const HostBatch& hb, int L) {
     return ts;
 }
 
-void carve_iter_state(Carver& c, IterState& st, int B, int ntiles) {
+void carve_iter_state(Carver& c, IterState& st, int B, int ntiles, int ngroups) {
     st.ctrl = c.take<Ctrl>(1);
     st.seq = c.take<SeqState>(B);
     st.offsets = c.take<int64_t>(B + 1);
     st.tile_start = c.take<int32_t>(B + 1);
     st.order = c.take<int32_t>(std::max(ntiles, 1));
     st.tiles = c.take<TileInfo>(std::max(ntiles, 1));
+    st.groups = c.take<GroupInfo>(std::max(ngroups, 1));
+    st.group_start = c.take<int32_t>(B + 1);
+    st.ngroups = ngroups;
+}
+
+int count_groups(const std::vector<int32_t>& tstart, int B, int gt) {
+    int n = 0;
+    for (int b = 0; b < B; ++b) n += (tstart[b + 1] - tstart[b] + gt - 1) / gt;
+    return n;
 }
 
 __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offsets, int B,
@@ -150,38 +159,61 @@ __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offs
 
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
                           const std::vector<int32_t>& tstart, int L, bool reverse,
-                          int max_iters, float tol, float reset_abs, hipStream_t stream) {
+                          int max_iters, float tol, float reset_abs, hipStream_t stream,
+                          int gt) {
     PN_HIP(hipMemcpyAsync(st.offsets, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1),
                           hipMemcpyHostToDevice, stream));
     PN_HIP(hipMemcpyAsync(st.tile_start, tstart.data(), sizeof(int32_t) * (hb.B + 1),
                           hipMemcpyHostToDevice, stream));
-    // interleaved processing order and tile geometry (kept alive on the host until the next
-    // call on this thread, after which the copies have completed)
+    // host staging of the tables, kept alive until the next call on this thread, after which
+    // the copies have completed (every solver synchronises its stream before returning)
     static thread_local std::vector<int32_t> order;
     static thread_local std::vector<TileInfo> tiles;
+    static thread_local std::vector<GroupInfo> groups;
+    static thread_local std::vector<int32_t> gstart;
+    const int ntiles = tstart[hb.B];
     order.clear();
-    tiles.clear();
-    int maxt = 0;
-    for (int b = 0; b < hb.B; ++b) maxt = std::max(maxt, tstart[b + 1] - tstart[b]);
-    for (int k = 0; k < maxt; ++k)
-        for (int b = 0; b < hb.B; ++b) {
-            const int nt = tstart[b + 1] - tstart[b];
-            if (k >= nt) continue;
-            TileInfo ti;
+    tiles.assign(ntiles, TileInfo{});
+    groups.clear();
+    gstart.assign(hb.B + 1, 0);
+    const int g = gt > 0 ? gt : 1;
+    for (int b = 0; b < hb.B; ++b) {
+        const int nt = tstart[b + 1] - tstart[b];
+        gstart[b + 1] = gstart[b] + (nt + g - 1) / g;
+        for (int k = 0; k < nt; ++k) {
+            TileInfo& ti = tiles[tstart[b] + k];
             ti.slot = tstart[b] + k;
             ti.b = b;
             ti.lt = reverse ? nt - 1 - k : k;
             ti.len = (int)std::min<int64_t>(L, hb.len(b) - (int64_t)ti.lt * L);
             ti.row0 = hb.offsets[b] + (int64_t)ti.lt * L;
             ti.first = tstart[b];
-            ti.pad_ = 0;
-            order.push_back(ti.slot);
-            tiles.push_back(ti);
+            ti.gslot = gstart[b] + k / g;
         }
-    if (!order.empty()) {
+        for (int k = 0; k < nt; k += g)
+            groups.push_back(GroupInfo{b, tstart[b] + k, std::min(g, nt - k), gstart[b]});
+    }
+    // interleaved processing order for the look-back scans
+    int maxt = 0;
+    for (int b = 0; b < hb.B; ++b) maxt = std::max(maxt, tstart[b + 1] - tstart[b]);
+    for (int k = 0; k < maxt; ++k)
+        for (int b = 0; b < hb.B; ++b)
+            if (k < tstart[b + 1] - tstart[b]) order.push_back(tstart[b] + k);
+    if (ntiles > 0) {
         PN_HIP(hipMemcpyAsync(st.order, order.data(), sizeof(int32_t) * order.size(),
                               hipMemcpyHostToDevice, stream));
         PN_HIP(hipMemcpyAsync(st.tiles, tiles.data(), sizeof(TileInfo) * tiles.size(),
+                              hipMemcpyHostToDevice, stream));
+    }
+    if (gt > 0) {
+        if ((int)groups.size() != st.ngroups) {
+            set_error("internal: group table size %d, carved %d", (int)groups.size(), st.ngroups);
+            return PN_ERR_INTERNAL;
+        }
+        if (!groups.empty())
+            PN_HIP(hipMemcpyAsync(st.groups, groups.data(), sizeof(GroupInfo) * groups.size(),
+                                  hipMemcpyHostToDevice, stream));
+        PN_HIP(hipMemcpyAsync(st.group_start, gstart.data(), sizeof(int32_t) * (hb.B + 1),
                               hipMemcpyHostToDevice, stream));
     }
     int blocks = std::min(64, (hb.B + 255) / 256);

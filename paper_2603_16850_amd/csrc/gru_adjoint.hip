@@ -20,6 +20,7 @@
 // grad (per-workgroup partial parameter gradients on MFMA, dx), reduce, gs0.
 #include <algorithm>
 
+#include "carry.hpp"
 #include "gru_common.hpp"
 #include "pn_host.hpp"
 #include "pn_solvers.hpp"
@@ -45,16 +46,19 @@ struct GruAdjArgs {
     const float* params;
     float* gates;            // [N][4][D]: z, alpha, beta, gamma at the solution
     float* eps;              // [N][D]: (1 - z)(1 - n^2)
-    float* lam[2];           // ping-pong adjoint iterates
-    uint64_t* agg[2];
-    uint32_t* incl[2];
+    float* dgs;              // [N][D]: diag(A_t) at the solution (the reverse scan's transition)
+    float* lam[2];           // ping-pong adjoint iterates; iteration k reads lam[k & 1]
+    float2* lac;             // [N][D] (la, lc) relative to the step's group (see carry.hpp)
+    float2* gagg;            // [ngroups][D] group maps
     float* gmax;             // [B] max |g| per sequence (as float bits, via atomicMax)
     Ctrl* ctrl;
     SeqState* seq;
     const int64_t* offsets;
     const int32_t* tile_start;
     const int32_t* order;
-    const TileInfo* tiles;   // processing order with geometry (reverse scan)
+    const TileInfo* tiles;   // by slot (reverse scan: slots from the sequence end)
+    const GroupInfo* groups;
+    int ngroups;
     int B;
     int ntiles;
     float* part;             // [grid][P] per-workgroup parameter-gradient partials
@@ -91,6 +95,9 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs 
     const int j = 16 * w + u;
     GruGates<D, DX> wg;
     wg.load(a.params, j, g);
+    const float* U = a.params + 3 * D * DX;
+    const float dUz = U[(0 * D + j) * D + j], dUr = U[(1 * D + j) * D + j],
+                dUn = U[(2 * D + j) * D + j];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         int b, lt, len;
         tile_of(a, tile, L, false, &b, &lt, &len);
@@ -133,6 +140,9 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs 
                 gr[2 * D + j] = e * p.r;
                 gr[3 * D + j] = e * p.q * p.r * (1.f - p.r);
                 a.eps[row * D + j] = e;
+                // diag(A_t)_j = z + alpha U_z[j][j] + beta U_n[j][j] + gamma U_r[j][j]
+                a.dgs[row * D + j] = p.z + gr[1 * D + j] * dUz + gr[2 * D + j] * dUn +
+                                     gr[3 * D + j] * dUr;
                 const float gv = a.gs[row * D + j];
                 a.lam[0][row * D + j] = gv;
                 gm = max(gm, absbits(gv));
@@ -147,20 +157,13 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs 
 // ---- one adjoint iteration ------------------------------------------------------------------
 template <int D, int DX, int L>
 __global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
-gru_adj_iter_kernel(GruAdjArgs a) {
+gru_adj_local_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
     __shared__ __attribute__((aligned(16))) float ps[L * C::PS];
-    __shared__ int rowbad[L];
-    __shared__ int tnext[2][8];
+    __shared__ __attribute__((aligned(16))) float lst[(L + 1) * C::HS];   // lambda rows t0 .. t0+L
 
     if (ld_i32(&a.ctrl->all_done)) return;
-    const int k = a.ctrl->iter;
-    const int par = k & 1;
-    const float reset_abs = a.ctrl->reset_abs;
-    const float* __restrict__ lin = a.lam[par];
-    float* __restrict__ lout = a.lam[par ^ 1];
-    uint64_t* aggc = a.agg[par];
-    uint32_t* inclc = a.incl[par];
+    const float* __restrict__ lin = a.lam[a.ctrl->iter & 1];
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
     const int j = 16 * w + u;
@@ -177,168 +180,155 @@ gru_adj_iter_kernel(GruAdjArgs a) {
             const int base = (mat == 0 ? 0 : (mat == 1 ? 2 : 1)) * D;   // U_z, U_n, U_r rows
             bu[kb][i] = U[(base + ii) * D + j];
         }
-    const float dUz = U[(0 * D + j) * D + j], dUr = U[(1 * D + j) * D + j],
-                dUn = U[(2 * D + j) * D + j];
 
-    for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
-    if (tid == 0) fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
-                             (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[0]);
-    for (int it = 0;; ++it) {
-        __syncthreads();
-        const int* tn = tnext[it & 1];
-        if (tn[0] >= a.ntiles) break;
-        const int tile = tn[1];         // slot, numbered from the sequence end
-        const int b = tn[2];
-        const int lt = tn[3];
-        const int len = tn[4];
-        const int64_t row0 = ((int64_t)tn[6] << 32) | (uint32_t)tn[5];
-        if (tn[7] != kActive) {
-            if (tid == 0)
-                fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
-                           (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
-            continue;
-        }
-        const int first_slot = a.tile_start[b];
-        const bool first = tile == first_slot;                 // tile at the sequence end
-        // one past the last row that has a successor step inside the sequence
-        const int64_t rend = first ? row0 + len : row0 + L + 1;
+    for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+        const GroupInfo gr = a.groups[gi];
+        if (a.seq[gr.b].status != kActive) continue;     // same on every thread
+        const int b = gr.b;
         const float gscale = 1.f / fmaxf(1.f, a.gmax[b]);
-
-        if (g == 0) {
-            st_u64(&a.agg[par ^ 1][(size_t)tile * D + j], kSent64);
-            st_u32(&a.incl[par ^ 1][(size_t)tile * D + j], kSent32);
-        }
-        // VJP operand rows: ps[tl] = (alpha, beta, gamma)_{t+1} * lambda_{t+1}, zero when step
-        // t+1 is outside the sequence
-        for (int idx = tid; idx < L * D; idx += C::NT) {
-            const int tl = idx / D, ii = idx % D;
-            const int64_t nr = row0 + tl + 1;
-            float va = 0.f, vb = 0.f, vg = 0.f;
-            if (tl < len && nr < rend) {
-                const float lv = lin[(size_t)nr * D + ii];
-                const float* gr = a.gates + (size_t)nr * 4 * D;
-                va = gr[1 * D + ii] * lv;
-                vb = gr[2 * D + ii] * lv;
-                vg = gr[3 * D + ii] * lv;
-            }
-            float* pr = ps + tl * C::PS;
-            pr[ii] = va;           // pairs with U_z
-            pr[D + ii] = vb;       // pairs with U_n
-            pr[2 * D + ii] = vg;   // pairs with U_r
-        }
-        __syncthreads();
-
-        float la[C::MB][4], lc[C::MB][4], lcur[C::MB][4];
+        float Pa = 1.f, Pc = 0.f;        // map of the group's tiles before the current one
         uint32_t rmax = 0;
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb) {
-            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-            const float* prow = ps + (mb * 16 + u) * C::PS;
-#pragma unroll
-            for (int kb = 0; kb < 3 * D / 16; ++kb) {
-                const float4 p4 = *(const float4*)(prow + 16 * kb + 4 * g);
-                acc = mfma16x4(p4.x, bu[kb][0], acc);
-                acc = mfma16x4(p4.y, bu[kb][1], acc);
-                acc = mfma16x4(p4.z, bu[kb][2], acc);
-                acc = mfma16x4(p4.w, bu[kb][3], acc);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int tl = mb * 16 + 4 * g + i;
-                const int64_t row = row0 + tl;
-                const bool valid = tl < len;
-                const bool has_next = valid && row + 1 < rend;
-                float lam_t = 0.f, g_t = 0.f, vjp = 0.f, dg = 0.f;
-                if (valid) {
-                    lam_t = lin[(size_t)row * D + j];
-                    g_t = a.gs[(size_t)row * D + j];
-                }
-                if (has_next) {
-                    const float* gr = a.gates + (size_t)(row + 1) * 4 * D;
-                    const float z = gr[j], al = gr[D + j], be = gr[2 * D + j], ga = gr[3 * D + j];
-                    vjp = z * lin[(size_t)(row + 1) * D + j] + acc[i];
-                    dg = z + al * dUz + be * dUn + ga * dUr;
-                }
-                const float rho = lam_t - g_t - vjp;
-                la[mb][i] = valid ? dg : 1.f;
-                lc[mb][i] = valid ? -rho : 0.f;
-                lcur[mb][i] = lam_t;
-                if (valid) rmax = max(rmax, absbits(rho * gscale));
-            }
-        }
+        for (int kt = 0; kt < gr.ntl; ++kt) {
+            const TileInfo ti = a.tiles[gr.tile0 + kt];    // scan order: later tiles first
+            const int len = ti.len;
+            const int64_t row0 = ti.row0;
+            const bool first = ti.slot == ti.first;       // tile at the sequence end
+            // one past the last row that has a successor step inside the sequence
+            const int64_t rend = first ? row0 + len : row0 + L + 1;
 
-        // ---- reverse scan inside the tile (later steps first) ----
-        float Ra = 1.f, Rc = 0.f;
+            // ---- stage lambda rows row0 .. row0+L and the VJP operand rows ----
+            // Item (r, c4): lambda_{t0+r}[4 c4 .. 4 c4 + 3] and, for r >= 1, step t0+r-1's
+            // operand (alpha, beta, gamma)_{t0+r} * lambda_{t0+r}.  All loads of a batch are
+            // issued before its LDS writes.
+            constexpr int Q = D / 4;
+            constexpr int NI = ((L + 1) * Q + C::NT - 1) / C::NT;
+            constexpr int NB = NI <= 3 ? NI : (NI + 1) / 2;
+            __syncthreads();                 // LDS of the previous tile consumed
 #pragma unroll
-        for (int mb = C::MB - 1; mb >= 0; --mb) {
-            float pa = 1.f, pc = 0.f;
+            for (int i0 = 0; i0 < NI; i0 += NB) {
+                float4 vl[NB], va[NB], vb[NB], vg[NB];
 #pragma unroll
-            for (int i = 3; i >= 0; --i) {
-                pa = la[mb][i] * pa;
-                pc = la[mb][i] * pc + lc[mb][i];
-                la[mb][i] = pa;
-                lc[mb][i] = pc;
-            }
-            float Ia = pa, Ic = pc;
-            {
-                const float qa = __shfl_down(Ia, 16), qc = __shfl_down(Ic, 16);
-                if (g <= 2) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
-            }
-            {
-                const float qa = __shfl_down(Ia, 32), qc = __shfl_down(Ic, 32);
-                if (g <= 1) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
-            }
-            float Ea = __shfl_down(Ia, 16), Ec = __shfl_down(Ic, 16);
-            if (g == 3) { Ea = 1.f; Ec = 0.f; }
-            const float Ta = __shfl(Ia, u), Tc = __shfl(Ic, u);
-            const float Xa = Ea * Ra, Xc = Ea * Rc + Ec;
+                for (int q = 0; q < NB; ++q) {
+                    const int idx = tid + (i0 + q) * C::NT;
+                    const int r = idx / Q, c4 = idx % Q;
+                    const int64_t nr = row0 + r;
+                    const bool okl = i0 + q < NI && idx < (L + 1) * Q && nr < rend;
+                    const bool okp = okl && r >= 1 && r - 1 < len;
+                    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    vl[q] = okl ? *(const float4*)(lin + (size_t)nr * D + 4 * c4) : z4;
+                    const float* gp = a.gates + (size_t)nr * 4 * D + 4 * c4;
+                    va[q] = okp ? *(const float4*)(gp + 1 * D) : z4;
+                    vb[q] = okp ? *(const float4*)(gp + 2 * D) : z4;
+                    vg[q] = okp ? *(const float4*)(gp + 3 * D) : z4;
+                }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                lc[mb][i] = la[mb][i] * Xc + lc[mb][i];
-                la[mb][i] = la[mb][i] * Xa;
+                for (int q = 0; q < NB; ++q) {
+                    const int idx = tid + (i0 + q) * C::NT;
+                    if (i0 + q >= NI || idx >= (L + 1) * Q) continue;
+                    const int r = idx / Q, c4 = idx % Q;
+                    *(float4*)(lst + r * C::HS + 4 * c4) = vl[q];
+                    if (r >= 1) {
+                        float* pr = ps + (r - 1) * C::PS + 4 * c4;
+                        const float4 l4 = vl[q];
+                        *(float4*)(pr) = make_float4(va[q].x * l4.x, va[q].y * l4.y,
+                                                     va[q].z * l4.z, va[q].w * l4.w);   // U_z
+                        *(float4*)(pr + D) = make_float4(vb[q].x * l4.x, vb[q].y * l4.y,
+                                                         vb[q].z * l4.z, vb[q].w * l4.w);  // U_n
+                        *(float4*)(pr + 2 * D) = make_float4(vg[q].x * l4.x, vg[q].y * l4.y,
+                                                             vg[q].z * l4.z, vg[q].w * l4.w);  // U_r
+                    }
+                }
             }
-            Rc = Ta * Rc + Tc;
-            Ra = Ta * Ra;
-        }
-        const float din = lookback4(aggc, inclc, tile, first_slot, D, j, g, u, Ra, Rc,
-                                    &a.ctrl->error);
-        // claim the next tile only once this one's carry is known (as in the forward kernel)
-        if (tid == 0)
-            fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
-                       (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
+            __syncthreads();
 
+            float la[C::MB][4], lc[C::MB][4];
 #pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb)
+            for (int mb = 0; mb < C::MB; ++mb) {
+                // this block's per-element operands, loaded before its MFMAs so they overlap
+                float zn[4], dn[4], gt[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float v = lcur[mb][i] + (la[mb][i] * din + lc[mb][i]);
-                lc[mb][i] = v;
-                const int tl = mb * 16 + 4 * g + i;
-                const bool bad = (tl < len) && !(fabsf(v) <= reset_abs);
-                const uint64_t m = __ballot(bad);
-                if (u == 0 && ((m >> (16 * g)) & 0xFFFFull)) rowbad[tl] = 1;
+                for (int i = 0; i < 4; ++i) {
+                    const int tl = mb * 16 + 4 * g + i;
+                    const int64_t row = row0 + tl;
+                    const bool valid = tl < len;
+                    const bool has_next = valid && row + 1 < rend;
+                    zn[i] = has_next ? a.gates[(size_t)(row + 1) * 4 * D + j] : 0.f;
+                    dn[i] = has_next ? a.dgs[(size_t)(row + 1) * D + j] : 0.f;
+                    gt[i] = valid ? a.gs[(size_t)row * D + j] : 0.f;
+                }
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                const float* prow = ps + (mb * 16 + u) * C::PS;
+#pragma unroll
+                for (int kb = 0; kb < 3 * D / 16; ++kb) {
+                    const float4 p4 = *(const float4*)(prow + 16 * kb + 4 * g);
+                    acc = mfma16x4(p4.x, bu[kb][0], acc);
+                    acc = mfma16x4(p4.y, bu[kb][1], acc);
+                    acc = mfma16x4(p4.z, bu[kb][2], acc);
+                    acc = mfma16x4(p4.w, bu[kb][3], acc);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int tl = mb * 16 + 4 * g + i;
+                    const bool valid = tl < len;
+                    const float lam_t = lst[tl * C::HS + j];
+                    // (A_{t+1}^T lambda_{t+1})_j = z_j lambda_j + [U_z; U_n; U_r]^T part (MFMA)
+                    const float vjp = zn[i] * lst[(tl + 1) * C::HS + j] + acc[i];
+                    const float rho = lam_t - gt[i] - vjp;
+                    la[mb][i] = valid ? dn[i] : 1.f;
+                    lc[mb][i] = valid ? -rho : 0.f;
+                    if (valid) rmax = max(rmax, absbits(rho * gscale));
+                }
             }
+
+            // ---- reverse scan inside the tile (later steps first), composed with the map
+            // of the group's earlier (later-in-time) tiles ----
+            float Ra = Pa, Rc = Pc;
+#pragma unroll
+            for (int mb = C::MB - 1; mb >= 0; --mb) {
+                float pa = 1.f, pc = 0.f;
+#pragma unroll
+                for (int i = 3; i >= 0; --i) {
+                    pa = la[mb][i] * pa;
+                    pc = la[mb][i] * pc + lc[mb][i];
+                    la[mb][i] = pa;
+                    lc[mb][i] = pc;
+                }
+                float Ia = pa, Ic = pc;
+                {
+                    const float qa = __shfl_down(Ia, 16), qc = __shfl_down(Ic, 16);
+                    if (g <= 2) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
+                }
+                {
+                    const float qa = __shfl_down(Ia, 32), qc = __shfl_down(Ic, 32);
+                    if (g <= 1) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
+                }
+                float Ea = __shfl_down(Ia, 16), Ec = __shfl_down(Ic, 16);
+                if (g == 3) { Ea = 1.f; Ec = 0.f; }
+                const float Ta = __shfl(Ia, u), Tc = __shfl(Ic, u);
+                const float Xa = Ea * Ra, Xc = Ea * Rc + Ec;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    lc[mb][i] = la[mb][i] * Xc + lc[mb][i];
+                    la[mb][i] = la[mb][i] * Xa;
+                }
+                Rc = Ta * Rc + Tc;
+                Ra = Ta * Ra;
+            }
+            Pa = Ra;
+            Pc = Rc;
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int tl = mb * 16 + 4 * g + i;
+                    if (tl < len)
+                        a.lac[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
+                }
+        }
+        if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) atomicMax(&a.seq[b].maxr, rmax);
-        __syncthreads();
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int tl = mb * 16 + 4 * g + i;
-                if (tl < len) lout[(size_t)(row0 + tl) * D + j] = rowbad[tl] ? 0.f : lc[mb][i];
-            }
-        if (w == 0) {
-            int nb = 0;
-            for (int base = 0; base < L; base += 64) {
-                const int t = base + l;
-                nb += __popcll(__ballot((t < L) && rowbad[t]));
-            }
-            if (l == 0 && nb) atomicAdd(&a.seq[b].resets_pending, nb);
-        }
-        __syncthreads();
-        for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
     }
 }
 
@@ -577,9 +567,8 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
 
 struct GruALayout {
     IterState st;
-    float *gates, *eps, *lam[2], *gmax, *part;
-    uint64_t* agg[2];
-    uint32_t* incl[2];
+    float *gates, *eps, *dgs, *lam[2], *gmax, *part, *gcarry;
+    float2 *lac, *gagg;
     size_t bytes;
 };
 
@@ -588,33 +577,23 @@ constexpr int kGradL = 32;
 
 static int grad_grid() { return cu_count(); }
 
-static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int ntiles) {
+static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int ntiles,
+                              int ngroups) {
     Carver c(ws);
     GruALayout lay;
-    carve_iter_state(c, lay.st, hb.B, ntiles);
+    carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.gates = c.take<float>((size_t)hb.N * 4 * D);
     lay.eps = c.take<float>((size_t)hb.N * D);
+    lay.dgs = c.take<float>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
-    for (int p = 0; p < 2; ++p) lay.agg[p] = c.take<uint64_t>((size_t)ntiles * D);
-    for (int p = 0; p < 2; ++p) lay.incl[p] = c.take<uint32_t>((size_t)ntiles * D);
+    lay.lac = c.take<float2>((size_t)hb.N * D);
+    lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
+    lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
     lay.gmax = c.take<float>(hb.B);
     const size_t P = 3 * (size_t)D * Dx + 3 * (size_t)D * D + 4 * (size_t)D;
     lay.part = c.take<float>((size_t)grad_grid() * P);
     lay.bytes = c.bytes();
     return lay;
-}
-
-size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts&) {
-    const int ntiles = tile_starts(hb, kAdjL)[hb.B];
-    return gruA_layout(nullptr, D, Dx, hb, ntiles).bytes;
-}
-
-__global__ void fill_sentinels_adj_kernel(uint64_t* agg, uint32_t* incl, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        agg[i] = kSent64;
-        incl[i] = kSent32;
-    }
 }
 
 struct GruAKernels {
@@ -629,7 +608,7 @@ template <int D, int DX>
 static GruAKernels gruA_get() {
     GruAKernels k;
     k.prep = gru_adj_prep_kernel<D, DX, kAdjL>;
-    k.iter = gru_adj_iter_kernel<D, DX, kAdjL>;
+    k.iter = gru_adj_local_kernel<D, DX, kAdjL>;
     k.grad = gru_adj_grad_kernel<D, DX, kGradL>;
     k.gs0 = gru_adj_gs0_kernel<D, DX>;
     k.nt = 64 * (D / 16);
@@ -642,6 +621,23 @@ static bool gruA_lookup(int D, int Dx, GruAKernels* k) {
     PN_GA(32, 32) PN_GA(48, 48) PN_GA(64, 16) PN_GA(32, 8)
 #undef PN_GA
     return false;
+}
+
+// Tile groups of the adjoint iteration for this batch.
+static int gruA_groups(const GruAKernels& kk, const std::vector<int32_t>& ts, int B, int* gt,
+                       int* resident) {
+    *resident = gru_resident((const void*)kk.iter, kk.nt);
+    *gt = gru_group_tiles(ts[B], *resident);
+    return count_groups(ts, B, *gt);
+}
+
+size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts&) {
+    GruAKernels kk;
+    if (!gruA_lookup(D, Dx, &kk)) return 0;
+    const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
+    int gt, resident;
+    const int ngroups = gruA_groups(kk, ts, hb.B, &gt, &resident);
+    return gruA_layout(nullptr, D, Dx, hb, ts[hb.B], ngroups).bytes;
 }
 
 pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
@@ -658,16 +654,13 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const int ntiles = ts[hb.B];
     const std::vector<int32_t> tsg = tile_starts(hb, kGradL);
     const int ntiles_g = tsg[hb.B];
-    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles);
+    int gt, resident;
+    const int ngroups = gruA_groups(kk, ts, hb.B, &gt, &resident);
+    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, ngroups);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, max_iters, (float)o.tol,
-                           (float)o.reset_abs, stream));
+                           (float)o.reset_abs, stream, gt));
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
-    if (ntiles > 0) {
-        const size_t n = (size_t)ntiles * D;
-        hipLaunchKernelGGL(fill_sentinels_adj_kernel, dim3((unsigned)std::min<size_t>(4096, (n + 255) / 256)),
-                           dim3(256), 0, stream, lay.agg[0], lay.incl[0], n);
-    }
     PN_HIP(hipGetLastError());
 
     GruAdjArgs args;
@@ -678,11 +671,10 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
     args.eps = lay.eps;
-    for (int p = 0; p < 2; ++p) {
-        args.lam[p] = lay.lam[p];
-        args.agg[p] = lay.agg[p];
-        args.incl[p] = lay.incl[p];
-    }
+    args.dgs = lay.dgs;
+    for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
+    args.lac = lay.lac;
+    args.gagg = lay.gagg;
     args.gmax = lay.gmax;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
@@ -690,6 +682,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.tile_start = lay.st.tile_start;
     args.order = lay.st.order;
     args.tiles = lay.st.tiles;
+    args.groups = lay.st.groups;
+    args.ngroups = ngroups;
     args.B = hb.B;
     args.ntiles = ntiles;
     args.part = lay.part;
@@ -704,27 +698,32 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         });
         PN_HIP(hipGetLastError());
     }
-    int occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kk.iter, kk.nt, 0) != hipSuccess || occ < 1)
-        occ = 1;
-    const int grid = std::max(1, std::min(ntiles, cu_count() * occ));
+    const int grid = std::max(1, std::min(ngroups, resident));
+    // iteration k reads lam[k & 1] and writes lam[(k + 1) & 1] (k from the control block)
     auto one_iter = [&](hipStream_t st) {
-        prof_launch("gru_adj_iter", st, [&](hipStream_t s2) {
+        prof_launch("gru_adj_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kk.iter, dim3(grid), dim3(kk.nt), 0, s2, args);
+        });
+        prof_launch("carry_scan", st, [&](hipStream_t s2) {
+            launch_carry_scan(lay.gagg, lay.gcarry, lay.st, hb.B, D, s2);
+        });
+        prof_launch("apply", st, [&](hipStream_t s2) {
+            launch_apply(lay.lam[0], lay.lam[1], lay.lac, lay.gcarry, lay.st, ntiles, D, kAdjL,
+                         s2);
         });
         launch_decide(lay.st, hb.B, st);
     };
-    std::vector<uintptr_t> key = {0x4144u, (uintptr_t)kk.iter, (uintptr_t)grid, (uintptr_t)x,
+    std::vector<uintptr_t> key = {0x4145u, (uintptr_t)kk.iter, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)gs,
                                   (uintptr_t)cd.params, (uintptr_t)ws, (uintptr_t)hb.B,
-                                  (uintptr_t)ntiles};
+                                  (uintptr_t)ntiles, (uintptr_t)ngroups};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;
     PN_TRY(finish_iterations(lay.st, hb, D, sizeof(float), nullptr, nullptr, stream, info,
                              all_conv, &derr));
     if (derr) {
-        set_error("look-back watchdog expired in the adjoint scan");
+        set_error("device-side check failed in the adjoint iteration");
         return PN_ERR_INTERNAL;
     }
     // gradients from the final adjoint iterate
@@ -770,7 +769,7 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     const int ntiles = ts[hb.B];
     const std::vector<int32_t> tsg = tile_starts(hb, kGradL);
-    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles);
+    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, 0);
     PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, 1, 1.f, 1e4f, stream));
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
     GruAdjArgs args{};
@@ -781,11 +780,8 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
     args.eps = lay.eps;
-    for (int p = 0; p < 2; ++p) {
-        args.lam[p] = lay.lam[p];
-        args.agg[p] = lay.agg[p];
-        args.incl[p] = lay.incl[p];
-    }
+    args.dgs = lay.dgs;
+    for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     args.gmax = lay.gmax;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;

@@ -1,7 +1,6 @@
 // GRU pieces shared by the quasi-DEER forward kernel and the adjoint kernels:
 //   * GruGates: the gate pre-activations of 16 steps x 16 units per wave on FP32 MFMA, with
-//     the recurrent and input weights held in registers as B operands;
-//   * lookback(): the single-pass decoupled look-back of a scalar affine scan.
+//     the recurrent and input weights held in registers as B operands.
 #pragma once
 #include "pn_device.hpp"
 
@@ -112,109 +111,6 @@ PN_DEV GruPoint gru_point(float az, float ar, float aq, float an, float b_z, flo
     p.q = aq + b_hn;
     p.n = tanhf_(an + b_n + p.r * p.q);
     return p;
-}
-
-// Decoupled look-back of a scalar affine scan, one lane per (tile, unit) slot.
-// The tile's own composed map is Delta_out = Ra * Delta_in + Rc.  `first` tiles have no
-// predecessor (Delta_in = 0).  Predecessors are tile-1, tile-2, ... of the same chain; each
-// publishes its aggregate (agg) before looking back and its inclusive value (incl) after.
-// Returns Delta_in; sets ctrl->error if the spin watchdog expires.
-PN_DEV float lookback(uint64_t* agg, uint32_t* incl, int tile, bool first, int stride, int j,
-                      float Ra, float Rc, int* err) {
-    const size_t slot = (size_t)tile * stride + j;
-    if (first) {
-        st_u32(&incl[slot], __float_as_uint(canon(Rc)));
-        return 0.f;
-    }
-    st_u64(&agg[slot], pack2(Ra, Rc));
-    float Aa = 1.f, Ac = 0.f;   // composed maps of the tiles between `pred` and this one
-    float din = 0.f;
-    int pred = tile - 1;
-    int spins = 0;
-    for (;;) {
-        const uint32_t iv = ld_u32(&incl[(size_t)pred * stride + j]);
-        if (ready32(iv)) {
-            din = Aa * __uint_as_float(iv) + Ac;
-            break;
-        }
-        const uint64_t av = ld_u64(&agg[(size_t)pred * stride + j]);
-        if (ready64(av)) {
-            Ac = Aa * hi_of(av) + Ac;
-            Aa = Aa * lo_of(av);
-            --pred;
-            continue;
-        }
-        if (++spins > (1 << 20) || ld_i32(err)) {
-            atomicExch(err, 1);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    st_u32(&incl[slot], __float_as_uint(canon(Ra * din + Rc)));
-    return din;
-}
-
-// Look-back with four predecessors per round: the four lanes g = 0..3 of unit u (lanes
-// u, u+16, u+32, u+48) inspect slots base, base-1, base-2, base-3 at once.  Called by all 64
-// lanes; returns Delta_in of unit j on every lane.  Slots of one sequence are consecutive,
-// `first` is the sequence's first slot (it publishes only its inclusive value).
-PN_DEV float lookback4(uint64_t* agg, uint32_t* incl, int slot, int first, int stride, int j,
-                       int g, int u, float Ra, float Rc, int* err) {
-    const size_t own = (size_t)slot * stride + j;
-    if (slot == first) {
-        if (g == 0) st_u32(&incl[own], __float_as_uint(canon(Rc)));
-        return 0.f;
-    }
-    if (g == 0) st_u64(&agg[own], pack2(Ra, Rc));
-    float Aa = 1.f, Ac = 0.f;     // composed maps of slots base+1 .. slot-1
-    float din = 0.f;
-    int base = slot - 1;
-    int spins = 0;
-    for (;;) {
-        const int p = base - g;
-        const bool valid = p >= first;
-        const uint32_t iv = valid ? ld_u32(&incl[(size_t)p * stride + j]) : kSent32;
-        const uint64_t av = valid ? ld_u64(&agg[(size_t)p * stride + j]) : kSent64;
-        const uint64_t im = __ballot(valid && ready32(iv));
-        const uint64_t am = __ballot(valid && ready64(av));
-        int gs = -1;
-#pragma unroll
-        for (int gg = 3; gg >= 0; --gg)
-            if ((im >> (16 * gg + u)) & 1ull) gs = gg;
-        // aggregates needed: slots base .. base-gs+1 (all four when no inclusive value seen)
-        const int need = gs >= 0 ? gs : 4;
-        bool ok = gs >= 0 || base - 3 >= first;
-#pragma unroll
-        for (int gg = 0; gg < 4; ++gg)
-            if (gg < need && !((am >> (16 * gg + u)) & 1ull)) ok = false;
-        // compose the needed aggregates, nearest first: map from Delta_end(base-need) to
-        // Delta_end(base) is a_0 (a_1 (... ) + c_1) + c_0
-        const float a_own = lo_of(av), c_own = hi_of(av);
-        float pa = 1.f, pc = 0.f;
-#pragma unroll
-        for (int gg = 3; gg >= 0; --gg) {
-            const float ag = __shfl(a_own, 16 * gg + u), cg = __shfl(c_own, 16 * gg + u);
-            if (gg < need) { pc = ag * pc + cg; pa = ag * pa; }
-        }
-        const float ival = __uint_as_float(__shfl((int)iv, 16 * (gs < 0 ? 0 : gs) + u));
-        if (ok) {
-            if (gs >= 0) {
-                din = Aa * (pa * ival + pc) + Ac;
-                break;
-            }
-            Ac = Aa * pc + Ac;
-            Aa = Aa * pa;
-            base -= 4;
-            continue;
-        }
-        if (++spins > (1 << 20) || ld_i32(err)) {
-            atomicExch(err, 1);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    if (g == 0) st_u32(&incl[own], __float_as_uint(canon(Ra * din + Rc)));
-    return din;
 }
 
 }  // namespace pn

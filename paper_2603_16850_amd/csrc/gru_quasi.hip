@@ -1,23 +1,27 @@
-// quasi-DEER for the GRU cell: one fused kernel per Newton iteration.
+// quasi-DEER for the GRU cell: one Newton iteration as three passes over HBM.
 //
-// For iterate s^(k) each workgroup takes tiles of L consecutive steps of one sequence (dynamic
-// tile ids, in sequence order) and, in one pass over HBM:
-//   1. stages s_{t-1}, s_t (L+1 rows) and x_t (L rows) in LDS;
-//   2. evaluates the three gate pre-activations of f(s_{t-1}, x_t) for the L steps as a
-//      small GEMM [L x (D+Dx)] x [(D+Dx) x 4 gate blocks] on FP32 MFMA (16x16x4), the
-//      weights held in registers for the whole kernel;
-//   3. forms the residual r_t = s_t - f_t(s_{t-1}) (Ch. 2, eq. r_def), the scan leaf
-//      (a_t, c_t) = (diag A_t, -r_t) with the closed-form GRU diagonal (quasi-DEER,
-//      eq. quasi_lds), and the per-sequence max |r| that the stopping test reads;
-//   4. scans Delta_t = a_t Delta_{t-1} + c_t (eq. lin_rr with a diagonal transition) over
-//      the tile: in registers, across lane groups by shuffles, across 16-step blocks serially;
-//   5. publishes the tile aggregate, looks back over preceding tiles of the same sequence
-//      for the carry-in Delta_{t0-1} (single-pass decoupled look-back), publishes its own
-//      inclusive prefix, and
-//   6. writes s^(k+1)_t = s_t + Delta_t with the overflow reset guard.
-// At a sequence head a_t = 0, so the carry-in is Delta_0 = 0 (s_0 is fixed).
+// For iterate s^(k) (tiles of L consecutive steps, groups of consecutive tiles of one
+// sequence, see IterState):
+//   local pass (gru_quasi_local_kernel), one workgroup per group of tiles, tile by tile:
+//     1. stages s_{t-1}, s_t (L+1 rows) and x_t (L rows) in LDS;
+//     2. evaluates the gate pre-activations of f(s_{t-1}, x_t) for the L steps as a small
+//        GEMM [L x (D+Dx)] x [(D+Dx) x 4 gate blocks] on FP32 MFMA (16x16x4), the weights
+//        held in registers for the whole kernel;
+//     3. forms the residual r_t = s_t - f_t(s_{t-1}) (Ch. 2, eq. r_def), the scan leaf
+//        (a_t, c_t) = (diag A_t, -r_t) with the closed-form GRU diagonal (quasi-DEER,
+//        eq. quasi_lds), and the per-sequence max |r| that the stopping test reads;
+//     4. scans Delta_t = a_t Delta_{t-1} + c_t (eq. lin_rr with a diagonal transition) over
+//        the tile (in registers, across lane groups by shuffles, across 16-step blocks
+//        serially) and composes the result with the map of the group's earlier tiles, so
+//        that lac_t = (la_t, lc_t) gives Delta_t = la_t Delta_in(group) + lc_t;
+//     5. writes lac for the tile's steps and, after the last tile, the group's map;
+//   carry pass (carry_scan.hip): the carry Delta_in of every group from the group maps;
+//   apply pass (carry_scan.hip): s^(k+1)_t = s_t + la_t Delta_in + lc_t, reset guard.
+// At a sequence head a_t = 0, so the carry into a sequence is Delta_0 = 0 (s_0 is fixed).
+// No workgroup waits for another: the passes are ordered by the stream.
 #include <algorithm>
 
+#include "carry.hpp"
 #include "gru_common.hpp"
 #include "pn_host.hpp"
 
@@ -38,42 +42,37 @@ struct GruQ {
     static constexpr int MB = L / 16;       // 16-step blocks per tile
 };
 
+// The transition matrix A~_t of the linear recurrence solved each iteration (the fixed-point
+// methods of Ch. "Convergence Rates of quasi-Newton methods", Table fxd_pt_sum):
+//   kTransDiag      diag(df/ds) in closed form: quasi-DEER (eq. quasi_lds)
+//   kTransIdentity  I: Picard iteration (Prop. picard); the scan is a prefix sum of -r
+//   kTransZero      0: Jacobi iteration; s_t <- f(s_{t-1}) for every t at once, no scan
+enum GruTrans : int { kTransDiag = 0, kTransIdentity = 1, kTransZero = 2 };
+
 struct GruQArgs {
     const float* x;
     const float* s0;
-    float* sbuf[2];          // ping-pong iterates; iteration k reads sbuf[k&1]
+    float* sbuf[2];          // ping-pong iterates; iteration k reads sbuf[k & 1]
     const float* params;
-    uint64_t* agg[2];        // tile aggregates (a, c) per unit, by iteration parity
-    uint32_t* incl[2];       // tile inclusive prefixes Delta_end per unit
+    float2* lac;             // [N][D] (la, lc) of every step, relative to its group's start
+    float2* gagg;            // [ngroups][D] map of every group
     Ctrl* ctrl;
     SeqState* seq;
-    const int64_t* offsets;
-    const int32_t* tile_start;
-    const int32_t* order;
-    const TileInfo* tiles;   // processing order with geometry
-    int B;
-    int ntiles;
+    const TileInfo* tiles;   // by slot
+    const GroupInfo* groups; // by group slot
+    int ngroups;
+    int mode;                // transition matrix: kTransDiag, kTransIdentity or kTransZero
 };
 
 template <int D, int DX, int L>
 __global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
-gru_quasi_iter_kernel(GruQArgs a) {
+gru_quasi_local_kernel(GruQArgs a) {
     using C = GruQ<D, DX, L>;
     __shared__ __attribute__((aligned(16))) float hs[(L + 1) * C::HS];
     __shared__ __attribute__((aligned(16))) float xs[L * C::XS];
-    __shared__ int rowbad[L];
-    __shared__ int tnext[2][8];   // next tile, double-buffered by loop parity
 
     if (ld_i32(&a.ctrl->all_done)) return;
-    const int k = a.ctrl->iter;
-    const int par = k & 1;
-    const float reset_abs = a.ctrl->reset_abs;
-    const float* __restrict__ sin = a.sbuf[par];
-    float* __restrict__ sout = a.sbuf[par ^ 1];
-    uint64_t* aggc = a.agg[par];
-    uint32_t* inclc = a.incl[par];
-    uint64_t* aggn = a.agg[par ^ 1];
-    uint32_t* incln = a.incl[par ^ 1];
+    const float* __restrict__ sin = a.sbuf[a.ctrl->iter & 1];
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -85,170 +84,146 @@ gru_quasi_iter_kernel(GruQArgs a) {
     GruGates<D, DX> wg;   // this wave's weights (units j) as MFMA B operands
     wg.load(a.params, j, g);
 
-    for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
-    if (tid == 0) fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
-                             (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[0]);
-
-    for (int it = 0;; ++it) {
-        __syncthreads();   // previous tile fully consumed (LDS reuse); tnext[it&1] published
-        const int* tn = tnext[it & 1];
-        if (tn[0] >= a.ntiles) break;
-        const int tile = tn[1];         // scan slot of this tile
-        const int b = tn[2];
-        const int lt = tn[3];
-        const int len = tn[4];
-        const int64_t row0 = ((int64_t)tn[6] << 32) | (uint32_t)tn[5];
-        if (tn[7] != kActive) {
-            if (tid == 0)
-                fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
-                           (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
-            continue;
-        }
-        const bool first = lt == 0;
-
-        // this tile's slots of the next iteration start unpublished
-        if (g == 0) {
-            st_u64(&aggn[(size_t)tile * D + j], kSent64);
-            st_u32(&incln[(size_t)tile * D + j], kSent32);
-        }
-
-        // ---- stage s rows row0-1 .. row0+L-1 (stage row r <-> s_{t0-1+r}) and x rows ----
-        {
-            constexpr int Q = D / 4;
-            for (int idx = tid; idx < (L + 1) * Q; idx += C::NT) {
-                const int r = idx / Q, c4 = idx % Q;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (r == 0) {
-                    v = first ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
-                              : *(const float4*)(sin + (size_t)(row0 - 1) * D + 4 * c4);
-                } else if (r - 1 < len) {
-                    v = *(const float4*)(sin + (size_t)(row0 + r - 1) * D + 4 * c4);
-                }
-                *(float4*)(hs + r * C::HS + 4 * c4) = v;
-            }
-            constexpr int QX = DX / 4;
-            for (int idx = tid; idx < L * QX; idx += C::NT) {
-                const int r = idx / QX, c4 = idx % QX;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
-                *(float4*)(xs + r * C::XS + 4 * c4) = v;
-            }
-        }
-        __syncthreads();
-
-        // ---- gates by MFMA, then residual and leaves, per 16-step block ----
-        float la[C::MB][4], lc[C::MB][4];
+    for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+        const GroupInfo gr = a.groups[gi];
+        if (a.seq[gr.b].status != kActive) continue;     // same on every thread
+        const int b = gr.b;
+        float Pa = 1.f, Pc = 0.f;        // map of the group's tiles before the current one
         uint32_t rmax = 0;
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb) {
-            floatx4 az, ar, aq, an;
-            wg.gemm(hs + (mb * 16 + u) * C::HS, xs + (mb * 16 + u) * C::XS, g, az, ar, aq, an);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int tl = mb * 16 + 4 * g + i;      // step index within the tile
-                const float h = hs[tl * C::HS + j];      // s_{t-1}
-                const float sc = hs[(tl + 1) * C::HS + j];   // s_t (current iterate)
-                const GruPoint p = gru_point(az[i], ar[i], aq[i], an[i], wg.b_z, wg.b_r,
-                                             wg.b_n, wg.b_hn);
-                const float f = (1.f - p.z) * p.n + p.z * h;
-                const float res = sc - f;
-                const float e = (1.f - p.z) * (1.f - p.n * p.n);
-                float dg = p.z + (h - p.n) * p.z * (1.f - p.z) * wg.dUz + e * p.r * wg.dUn
-                         + e * p.q * p.r * (1.f - p.r) * wg.dUr;
-                const bool valid = tl < len;
-                if (first && tl == 0) dg = 0.f;
-                la[mb][i] = valid ? dg : 1.f;
-                lc[mb][i] = valid ? -res : 0.f;
+        for (int kt = 0; kt < gr.ntl; ++kt) {
+            const TileInfo ti = a.tiles[gr.tile0 + kt];
+            const int len = ti.len;
+            const int64_t row0 = ti.row0;
+            const bool first = ti.lt == 0;
 
-                if (valid) rmax = max(rmax, absbits(res));
+            // ---- stage s rows row0-1 .. row0+L-1 (stage row r <-> s_{t0-1+r}) and x rows.
+            // Items 0 .. NSV-1 of a thread are float4s of s, the rest float4s of x, in
+            // batches whose loads are all issued before their LDS writes.
+            constexpr int Q = D / 4, QX = DX / 4;
+            constexpr int NSV = ((L + 1) * Q + C::NT - 1) / C::NT;
+            constexpr int NXV = (L * QX + C::NT - 1) / C::NT;
+            constexpr int NI = NSV + NXV;
+            constexpr int NB = 4;
+            __syncthreads();                 // LDS of the previous tile consumed
+#pragma unroll
+            for (int i0 = 0; i0 < NI; i0 += NB) {
+                float4 v[NB];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const int i = i0 + q;
+                    v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (i < NSV) {
+                        const int idx = tid + i * C::NT;
+                        const int r = idx / Q, c4 = idx % Q;
+                        const float* src = r == 0 ? (first ? a.s0 + (size_t)b * D
+                                                           : sin + (size_t)(row0 - 1) * D)
+                                                  : sin + (size_t)(row0 + r - 1) * D;
+                        if (idx < (L + 1) * Q && (r == 0 || r - 1 < len))
+                            v[q] = *(const float4*)(src + 4 * c4);
+                    } else if (i < NI) {
+                        const int idx = tid + (i - NSV) * C::NT;
+                        const int r = idx / QX, c4 = idx % QX;
+                        if (idx < L * QX && r < len)
+                            v[q] = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const int i = i0 + q;
+                    if (i < NSV) {
+                        const int idx = tid + i * C::NT;
+                        if (idx < (L + 1) * Q)
+                            *(float4*)(hs + (idx / Q) * C::HS + 4 * (idx % Q)) = v[q];
+                    } else if (i < NI) {
+                        const int idx = tid + (i - NSV) * C::NT;
+                        if (idx < L * QX)
+                            *(float4*)(xs + (idx / QX) * C::XS + 4 * (idx % QX)) = v[q];
+                    }
+                }
             }
+            __syncthreads();
+
+            // ---- gates by MFMA, then residual and leaves, per 16-step block ----
+            float la[C::MB][4], lc[C::MB][4];
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb) {
+                floatx4 az, ar, aq, an;
+                wg.gemm(hs + (mb * 16 + u) * C::HS, xs + (mb * 16 + u) * C::XS, g, az, ar, aq, an);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int tl = mb * 16 + 4 * g + i;      // step index within the tile
+                    const float h = hs[tl * C::HS + j];      // s_{t-1}
+                    const float sc = hs[(tl + 1) * C::HS + j];   // s_t (current iterate)
+                    const GruPoint p = gru_point(az[i], ar[i], aq[i], an[i], wg.b_z, wg.b_r,
+                                                 wg.b_n, wg.b_hn);
+                    const float f = (1.f - p.z) * p.n + p.z * h;
+                    const float res = sc - f;
+                    const float e = (1.f - p.z) * (1.f - p.n * p.n);
+                    float dg = p.z + (h - p.n) * p.z * (1.f - p.z) * wg.dUz + e * p.r * wg.dUn
+                             + e * p.q * p.r * (1.f - p.r) * wg.dUr;
+                    const bool valid = tl < len;
+                    if (a.mode != kTransDiag) dg = (a.mode == kTransIdentity) ? 1.f : 0.f;
+                    if (first && tl == 0) dg = 0.f;
+                    la[mb][i] = valid ? dg : 1.f;
+                    lc[mb][i] = valid ? -res : 0.f;
+                    if (valid) rmax = max(rmax, absbits(res));
+                }
+            }
+
+            // ---- scan inside the tile ----
+            // lane-local over the 4 steps of each block
+            float Ra = Pa, Rc = Pc;    // map from the group start to the current block's start
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb) {
+                float pa = 1.f, pc = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    pa = la[mb][i] * pa;
+                    pc = la[mb][i] * pc + lc[mb][i];
+                    la[mb][i] = pa;
+                    lc[mb][i] = pc;
+                }
+                // inclusive scan of lane aggregates over the 4 lane groups of a unit
+                float Ia = pa, Ic = pc;
+                {
+                    const float qa = __shfl_up(Ia, 16), qc = __shfl_up(Ic, 16);
+                    if (g >= 1) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
+                }
+                {
+                    const float qa = __shfl_up(Ia, 32), qc = __shfl_up(Ic, 32);
+                    if (g >= 2) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
+                }
+                float Ea = __shfl_up(Ia, 16), Ec = __shfl_up(Ic, 16);
+                if (g == 0) { Ea = 1.f; Ec = 0.f; }
+                const float Ta = __shfl(Ia, 48 + u), Tc = __shfl(Ic, 48 + u);
+                // prefix of this lane group's start = E o R
+                const float Xa = Ea * Ra, Xc = Ea * Rc + Ec;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    lc[mb][i] = la[mb][i] * Xc + lc[mb][i];
+                    la[mb][i] = la[mb][i] * Xa;
+                }
+                Rc = Ta * Rc + Tc;
+                Ra = Ta * Ra;
+            }
+            Pa = Ra;
+            Pc = Rc;
+
+            // ---- (la, lc) of every step of the tile ----
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int tl = mb * 16 + 4 * g + i;
+                    if (tl < len)
+                        a.lac[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
+                }
         }
-
-        // ---- scan inside the tile ----
-        // lane-local over the 4 steps of each block
-        float Ra = 1.f, Rc = 0.f;      // composed map of all blocks before the current one
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb) {
-            float pa = 1.f, pc = 0.f;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                pa = la[mb][i] * pa;
-                pc = la[mb][i] * pc + lc[mb][i];
-                la[mb][i] = pa;
-                lc[mb][i] = pc;
-            }
-            // inclusive scan of lane aggregates over the 4 lane groups of a unit
-            float Ia = pa, Ic = pc;
-            {
-                const float qa = __shfl_up(Ia, 16), qc = __shfl_up(Ic, 16);
-                if (g >= 1) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
-            }
-            {
-                const float qa = __shfl_up(Ia, 32), qc = __shfl_up(Ic, 32);
-                if (g >= 2) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
-            }
-            float Ea = __shfl_up(Ia, 16), Ec = __shfl_up(Ic, 16);
-            if (g == 0) { Ea = 1.f; Ec = 0.f; }
-            const float Ta = __shfl(Ia, 48 + u), Tc = __shfl(Ic, 48 + u);
-            // prefix of this lane group's start = E o R
-            const float Xa = Ea * Ra, Xc = Ea * Rc + Ec;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                lc[mb][i] = la[mb][i] * Xc + lc[mb][i];
-                la[mb][i] = la[mb][i] * Xa;
-            }
-            Rc = Ta * Rc + Tc;
-            Ra = Ta * Ra;
-        }
-
-        // ---- decoupled look-back for the carry-in Delta_{t0-1} of unit j ----
-        const float din = lookback4(aggc, inclc, tile, tile - lt, D, j, g, u, Ra, Rc,
-                                    &a.ctrl->error);
-
-        // The next tile is claimed only now.  A claim made earlier would hand a tile to a
-        // workgroup that is still blocked in this look-back, and every later tile of that
-        // sequence would wait on it; claimed this late, its geometry is read while the new
-        // iterate is written.
-        if (tid == 0)
-            fetch_tile(a.ctrl, a.tiles, a.seq, a.ntiles,
-                       (int)atomicAdd(&a.ctrl->tile_counter, 1u), tnext[(it + 1) & 1]);
-
-        // ---- new iterate (kept in lc), overflow guard ----
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float v = hs[(mb * 16 + 4 * g + i + 1) * C::HS + j] + (la[mb][i] * din + lc[mb][i]);
-                lc[mb][i] = v;
-                const int tl = mb * 16 + 4 * g + i;
-                const bool bad = (tl < len) && !(fabsf(v) <= reset_abs);
-                const uint64_t m = __ballot(bad);
-                if (u == 0 && ((m >> (16 * g)) & 0xFFFFull)) rowbad[tl] = 1;
-            }
-        // residual max of the current iterate, one atomic per wave
+        if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
+        // residual max of the current iterate over the group, one atomic per wave
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) atomicMax(&a.seq[b].maxr, rmax);
-        __syncthreads();
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int tl = mb * 16 + 4 * g + i;
-                if (tl < len) sout[(size_t)(row0 + tl) * D + j] = rowbad[tl] ? 0.f : lc[mb][i];
-            }
-        if (w == 0) {
-            int nb = 0;
-#pragma unroll
-            for (int base = 0; base < L; base += 64) {
-                const int t = base + l;
-                const bool bad = (t < L) && rowbad[t];
-                nb += __popcll(__ballot(bad));
-            }
-            if (l == 0 && nb) atomicAdd(&a.seq[b].resets_pending, nb);
-        }
-        __syncthreads();
-        for (int t = tid; t < L; t += C::NT) rowbad[t] = 0;
     }
 }
 
@@ -257,35 +232,29 @@ gru_quasi_iter_kernel(GruQArgs a) {
 struct GruQLayout {
     IterState st;
     float* salt;
-    uint64_t* agg[2];
-    uint32_t* incl[2];
+    float2* lac;
+    float2* gagg;
+    float* gcarry;
     size_t bytes;
 };
 
-static GruQLayout gruq_layout(void* ws, int D, const HostBatch& hb, int ntiles) {
+static GruQLayout gruq_layout(void* ws, int D, const HostBatch& hb, int ntiles, int ngroups) {
     Carver c(ws);
     GruQLayout lay;
-    carve_iter_state(c, lay.st, hb.B, ntiles);
+    carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.salt = c.take<float>((size_t)hb.N * D);
-    for (int p = 0; p < 2; ++p) lay.agg[p] = c.take<uint64_t>((size_t)ntiles * D);
-    for (int p = 0; p < 2; ++p) lay.incl[p] = c.take<uint32_t>((size_t)ntiles * D);
+    lay.lac = c.take<float2>((size_t)hb.N * D);
+    lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
+    lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
     lay.bytes = c.bytes();
     return lay;
-}
-
-__global__ void fill_sentinels_kernel(uint64_t* agg, uint32_t* incl, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        agg[i] = kSent64;
-        incl[i] = kSent32;
-    }
 }
 
 typedef void (*GruQKernel)(GruQArgs);
 
 template <int D, int DX, int L>
 static void gruq_get(GruQKernel* k, int* nt) {
-    *k = gru_quasi_iter_kernel<D, DX, L>;
+    *k = gru_quasi_local_kernel<D, DX, L>;
     *nt = GruQ<D, DX, L>::NT;
 }
 
@@ -306,14 +275,33 @@ bool gru_quasi_supported(int D, int Dx) {
 }
 
 int gru_quasi_tile(int D, int Dx, const pn_opts& o) {
+    (void)D; (void)Dx;
     if (o.tile == 32 || o.tile == 64 || o.tile == 128) return o.tile;
     return 64;
 }
 
+// Tiles per group: enough groups to give every resident workgroup about two of them, at most
+// 16 tiles (a longer group only shortens the carry scan, which is already cheap).
+int gru_group_tiles(int ntiles, int resident) {
+    return std::max(1, std::min(16, ntiles / std::max(1, 2 * resident)));
+}
+
+int gru_resident(const void* kern, int nt) {
+    int occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, nt, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    return cu_count() * occ;
+}
+
 size_t gru_quasi_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o) {
     const int L = gru_quasi_tile(D, Dx, o);
-    const int ntiles = tile_starts(hb, L)[hb.B];
-    return gruq_layout(nullptr, D, hb, ntiles).bytes;
+    GruQKernel kern;
+    int nt;
+    if (!gruq_lookup(D, Dx, L, &kern, &nt)) return 0;
+    const std::vector<int32_t> ts = tile_starts(hb, L);
+    const int ntiles = ts[hb.B];
+    const int gt = gru_group_tiles(ntiles, gru_resident((const void*)kern, nt));
+    return gruq_layout(nullptr, D, hb, ntiles, count_groups(ts, hb.B, gt)).bytes;
 }
 
 pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
@@ -329,53 +317,56 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     }
     const std::vector<int32_t> ts = tile_starts(hb, L);
     const int ntiles = ts[hb.B];
-    GruQLayout lay = gruq_layout(ws, D, hb, ntiles);
+    const int resident = gru_resident((const void*)kern, nt);
+    const int gt = gru_group_tiles(ntiles, resident);
+    const int ngroups = count_groups(ts, hb.B, gt);
+    GruQLayout lay = gruq_layout(ws, D, hb, ntiles, ngroups);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, L, false, max_iters, (float)o.tol,
-                           (float)o.reset_abs, stream));
-    if (ntiles > 0) {
-        const size_t n = (size_t)ntiles * D;
-        hipLaunchKernelGGL(fill_sentinels_kernel, dim3((unsigned)std::min<size_t>(4096, (n + 255) / 256)),
-                           dim3(256), 0, stream, lay.agg[0], lay.incl[0], n);
-        PN_HIP(hipGetLastError());
-    }
-    int occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, nt, 0) != hipSuccess || occ < 1)
-        occ = 1;
-    const int grid = std::max(1, std::min(ntiles, cu_count() * occ));
+                           (float)o.reset_abs, stream, gt));
+    const int grid = std::max(1, std::min(ngroups, resident));
 
     GruQArgs args;
     args.x = x;
     args.s0 = s0;
-    args.sbuf[0] = s;
-    args.sbuf[1] = lay.salt;
     args.params = (const float*)cd.params;
-    for (int p = 0; p < 2; ++p) { args.agg[p] = lay.agg[p]; args.incl[p] = lay.incl[p]; }
+    args.lac = lay.lac;
+    args.gagg = lay.gagg;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
-    args.offsets = lay.st.offsets;
-    args.tile_start = lay.st.tile_start;
-    args.order = lay.st.order;
     args.tiles = lay.st.tiles;
-    args.B = hb.B;
-    args.ntiles = ntiles;
+    args.groups = lay.st.groups;
+    args.ngroups = ngroups;
+    args.mode = o.jac == PN_JAC_PICARD ? kTransIdentity
+              : o.jac == PN_JAC_JACOBI ? kTransZero : kTransDiag;
+    args.sbuf[0] = s;
+    args.sbuf[1] = lay.salt;
 
+    // iteration k reads sbuf[k & 1] and writes sbuf[(k + 1) & 1] (k from the control block,
+    // so a captured graph of iterations replays from any k)
     auto one_iter = [&](hipStream_t st) {
-        prof_launch("gru_quasi_iter", st, [&](hipStream_t s2) {
+        prof_launch("gru_quasi_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), 0, s2, args);
+        });
+        prof_launch("carry_scan", st, [&](hipStream_t s2) {
+            launch_carry_scan(lay.gagg, lay.gcarry, lay.st, hb.B, D, s2);
+        });
+        prof_launch("apply", st, [&](hipStream_t s2) {
+            launch_apply(s, lay.salt, lay.lac, lay.gcarry, lay.st, ntiles, D, L, s2);
         });
         launch_decide(lay.st, hb.B, st);
     };
-    std::vector<uintptr_t> key = {0x6751u, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
+    std::vector<uintptr_t> key = {0x6752u, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
-                                  (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles};
-    PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
-                          stream));
+                                  (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
+                                  (uintptr_t)ngroups, (uintptr_t)args.mode};
+    PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key,
+                          one_iter, stream));
     int derr = 0;
     PN_TRY(finish_iterations(lay.st, hb, D, sizeof(float), s, lay.salt, stream, info, all_conv,
                              &derr));
     if (derr) {
-        set_error("look-back watchdog expired in the GRU quasi-DEER scan");
+        set_error("device-side check failed in the GRU quasi-DEER iteration");
         return PN_ERR_INTERNAL;
     }
     return PN_OK;

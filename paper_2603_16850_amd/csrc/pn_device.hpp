@@ -36,7 +36,7 @@ struct SeqState {
     int pad_;
 };
 
-// One entry per tile, in the order workgroups take them (see IterState::tiles).
+// One entry per tile, indexed by scan slot (see IterState::tiles).
 struct TileInfo {
     int32_t slot;       // scan slot of the tile (consecutive within a sequence, scan order)
     int32_t b;          // sequence
@@ -44,7 +44,16 @@ struct TileInfo {
     int32_t len;        // valid steps
     int64_t row0;       // first row
     int32_t first;      // slot of the sequence's first scanned tile
-    int32_t pad_;
+    int32_t gslot;      // group of the tile (see GroupInfo)
+};
+
+// A group is a run of consecutive tiles of one sequence, in scan order, that one workgroup
+// scans one after the other (IterState::groups, indexed by group slot).
+struct GroupInfo {
+    int32_t b;          // sequence
+    int32_t tile0;      // slot of the group's first tile
+    int32_t ntl;        // tiles in the group
+    int32_t gfirst;     // group slot of the sequence's first group
 };
 
 struct Ctrl {
@@ -57,24 +66,6 @@ struct Ctrl {
     float reset_abs;
     int pad_;
 };
-
-// Reads tile `idx` of the processing order (and its sequence's status) into out[0..7]:
-// idx, slot, b, lt, len, row0 low, row0 high, status.
-PN_DEV void fetch_tile(const Ctrl* ctrl, const TileInfo* tiles, const SeqState* seq, int ntiles,
-                       int idx, int* out) {
-    (void)ctrl;
-    out[0] = idx;
-    if (idx < ntiles) {
-        const TileInfo ti = tiles[idx];
-        out[1] = ti.slot;
-        out[2] = ti.b;
-        out[3] = ti.lt;
-        out[4] = ti.len;
-        out[5] = (int)(uint32_t)(uint64_t)ti.row0;
-        out[6] = (int)((uint64_t)ti.row0 >> 32);
-        out[7] = seq[ti.b].status;
-    }
-}
 
 // ---- atomics ------------------------------------------------------------------------------
 PN_DEV uint64_t ld_u64(const uint64_t* p) {

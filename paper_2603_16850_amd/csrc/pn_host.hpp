@@ -74,20 +74,29 @@ struct IterState {
     int64_t* offsets;      // device copy [B+1]
     int32_t* tile_start;   // device [B+1]
     int32_t* order;        // device [ntiles]: processing order of tile slots
-    TileInfo* tiles;       // device [ntiles]: the same order with each tile's geometry
+    TileInfo* tiles;       // device [ntiles]: every tile's geometry, indexed by slot
+    GroupInfo* groups;     // device [ngroups], indexed by group slot
+    int32_t* group_start;  // device [B+1]: group slots of sequence b
+    int ngroups;
 };
 // Tile slots of sequence b are tile_start[b] .. tile_start[b+1]-1, numbered in the order a
-// sequence is scanned (from its start, or from its end for reverse scans).  Workgroups take
-// slots in `order`: every sequence's first slot, then every sequence's second slot, ... so the
-// tiles running at once spread over the sequences and look-back chains stay short.
-void carve_iter_state(Carver& c, IterState& st, int B, int ntiles);
+// sequence is scanned (from its start, or from its end for reverse scans).  Look-back scans
+// take slots in `order`: every sequence's first slot, then every sequence's second slot, ...
+// so the tiles running at once spread over the sequences and look-back chains stay short.
+// Groups cut each sequence's slots into runs of `gt` tiles (the last one shorter).
+void carve_iter_state(Carver& c, IterState& st, int B, int ntiles, int ngroups = 0);
+// Number of groups of `gt` tiles over the sequences of a batch.
+int count_groups(const std::vector<int32_t>& tstart, int B, int gt);
 
 // Uploads offsets / tile table, resets the per-sequence state and the control block.
 // Tiles are L steps long; with `reverse` a sequence is scanned from its end (its last tile
 // gets the sequence's first slot).
+// `gt` > 0 also fills the group table (the state must have been carved with
+// count_groups(tstart, B, gt) groups).
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
                           const std::vector<int32_t>& tstart, int L, bool reverse,
-                          int max_iters, float tol, float reset_abs, hipStream_t stream);
+                          int max_iters, float tol, float reset_abs, hipStream_t stream,
+                          int gt = 0);
 
 // Launches the end-of-iteration decision kernel (stop tests, counters).
 void launch_decide(const IterState& st, int B, hipStream_t stream);

@@ -9,8 +9,13 @@ void profile_begin();
 void profile_end();
 int profile_read(const char* family, double* ms, int64_t* n);
 
-// quasi-DEER, GRU, FP32 (fused linearise + diagonal scan)
+// quasi-DEER (and Picard / Jacobi), GRU, FP32: per-group linearise + scan, carry, apply
 bool gru_quasi_supported(int D, int Dx);
+int gru_quasi_tile(int D, int Dx, const pn_opts& o);
+// tiles per group for a launch of `resident` workgroups over `ntiles` tiles
+int gru_group_tiles(int ntiles, int resident);
+// workgroups of `kern` (nt threads) resident on the device at once
+int gru_resident(const void* kern, int nt);
 size_t gru_quasi_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
 pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
                             const float* s0, float* s, const pn_opts& o, void* ws,
