@@ -1,14 +1,12 @@
-// The two kernels that complete a diagonal scan after the per-group pass, shared by the GRU
+// The carry pass that completes a diagonal scan after the per-group pass, shared by the GRU
 // quasi-DEER forward iteration and the adjoint iteration.
 //
 // The per-group pass leaves, for every step t and unit d, the map composed from the first
-// scanned step of t's group to t:  Delta_t = la_t Delta_in + lc_t  (lac[t][d] = (la_t, lc_t)),
-// and the group's whole map (agg[group][d]).  With the groups of a sequence numbered by scan
-// order (group slots group_start[b] .. group_start[b+1]-1):
-//   carry scan:  carry[first] = 0,  carry[g+1] = agg_a[g] carry[g] + agg_c[g]
-//                (eq. bin_op_affine over the group maps)
-//   apply:       out_t = in_t + la_t carry[group(t)] + lc_t, then the overflow reset guard
-//                (a row with a non-finite entry or one above reset_abs becomes 0).
+// scanned step of t's group to t:  Delta_t = la_t Delta_in + lc_t  ((la_t, lc_t) stored per
+// step), and the group's whole map (agg[group][d]).  With the groups of a sequence numbered
+// by scan order (group slots group_start[b] .. group_start[b+1]-1):
+//   carry[first] = 0,  carry[g+1] = agg_a[g] carry[g] + agg_c[g]   (eq. bin_op_affine)
+// and the next iteration's per-group pass applies  out_t = in_t + la_t carry[group(t)] + lc_t.
 #pragma once
 #include "pn_host.hpp"
 
@@ -18,11 +16,5 @@ namespace pn {
 // active are skipped; nothing runs when ctrl->all_done is set.
 void launch_carry_scan(const float2* agg, float* carry, const IterState& st, int B, int D,
                        hipStream_t stream);
-
-// out = in + la * carry + lc with the reset guard, one workgroup per tile (tiles table),
-// adding the number of reset rows of each sequence to seq[b].resets_pending.  Iteration k
-// (ctrl->iter) reads buf[k & 1] and writes buf[(k + 1) & 1].
-void launch_apply(float* buf0, float* buf1, const float2* lac, const float* carry,
-                  const IterState& st, int ntiles, int D, int L, hipStream_t stream);
 
 }  // namespace pn

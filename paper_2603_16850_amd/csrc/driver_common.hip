@@ -224,7 +224,10 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
 }
 
 // One workgroup: apply the stopping test of iteration k to every active sequence.
-__global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B) {
+// resets_pending counts the rows reset while this iteration produced an iterate: the next
+// iterate s^(k+1) (kept only if the sequence goes on), or with `pending_current` the iterate
+// s^(k) just tested (always kept).
+__global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B, int pending_current) {
     __shared__ int any_active;
     const int k = ctrl->iter;
     const float tol = ctrl->tol;
@@ -240,6 +243,7 @@ __global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B) {
                 q.iters = k;
                 q.parity = k & 1;
                 q.final_resid = m;
+                if (pending_current) q.resets += q.resets_pending;
             } else {
                 q.resets += q.resets_pending;
                 any_active = 1;
@@ -257,8 +261,9 @@ __global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B) {
     }
 }
 
-void launch_decide(const IterState& st, int B, hipStream_t stream) {
-    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, stream, st.ctrl, st.seq, B);
+void launch_decide(const IterState& st, int B, hipStream_t stream, bool pending_current) {
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(256), 0, stream, st.ctrl, st.seq, B,
+                       pending_current ? 1 : 0);
 }
 
 // ---- iteration loop with optional graph capture -------------------------------------------

@@ -48,8 +48,10 @@ struct GruAdjArgs {
     float* eps;              // [N][D]: (1 - z)(1 - n^2)
     float* dgs;              // [N][D]: diag(A_t) at the solution (the reverse scan's transition)
     float* lam[2];           // ping-pong adjoint iterates; iteration k reads lam[k & 1]
-    float2* lac;             // [N][D] (la, lc) relative to the step's group (see carry.hpp)
+    float2* lac[2];          // [N][D] (la, lc) relative to the step's group; iteration k
+                             // writes lac[k & 1]
     float2* gagg;            // [ngroups][D] group maps
+    const float* gcarry;     // [ngroups][D] carry into every group (previous iteration)
     float* gmax;             // [B] max |g| per sequence (as float bits, via atomicMax)
     Ctrl* ctrl;
     SeqState* seq;
@@ -87,7 +89,8 @@ PN_DEV void tile_of(const GruAdjArgs& a, int tile, int L, bool reverse, int* b_o
 
 // ---- prep: gates at the solution, lambda^(0) = g, max |g| ---------------------------------
 template <int D, int DX, int L>
-__global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs a) {
+__global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gru_adj_prep_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
     __shared__ __attribute__((aligned(16))) float hs[L * C::HS];
     __shared__ __attribute__((aligned(16))) float xs[L * C::XS];
@@ -104,23 +107,56 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs 
         const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
         const bool first = lt == 0;
         __syncthreads();
+        // stage row r <-> h of step t0 + r, and the x rows; all loads of a batch are issued
+        // before its LDS writes
         constexpr int Q = D / 4, QX = DX / 4;
-        for (int idx = tid; idx < L * Q; idx += C::NT) {
-            const int r = idx / Q, c4 = idx % Q;     // stage row r <-> h of step t0 + r
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r < len)
-                v = (r == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
-                                      : *(const float4*)(a.s + (size_t)(row0 + r - 1) * D + 4 * c4);
-            *(float4*)(hs + r * C::HS + 4 * c4) = v;
-        }
-        for (int idx = tid; idx < L * QX; idx += C::NT) {
-            const int r = idx / QX, c4 = idx % QX;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
-            *(float4*)(xs + r * C::XS + 4 * c4) = v;
+        constexpr int NSV = (L * Q + C::NT - 1) / C::NT;
+        constexpr int NXV = (L * QX + C::NT - 1) / C::NT;
+        constexpr int NI = NSV + NXV;
+        constexpr int NB = 4;
+#pragma unroll
+        for (int i0 = 0; i0 < NI; i0 += NB) {
+            float4 v[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int i = i0 + q;
+                v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (i < NSV) {
+                    const int idx = tid + i * C::NT;
+                    const int r = idx / Q, c4 = idx % Q;
+                    if (idx < L * Q && r < len)
+                        v[q] = (r == 0 && first)
+                                   ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
+                                   : *(const float4*)(a.s + (size_t)(row0 + r - 1) * D + 4 * c4);
+                } else if (i < NI) {
+                    const int idx = tid + (i - NSV) * C::NT;
+                    const int r = idx / QX, c4 = idx % QX;
+                    if (idx < L * QX && r < len)
+                        v[q] = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int i = i0 + q;
+                if (i < NSV) {
+                    const int idx = tid + i * C::NT;
+                    if (idx < L * Q) *(float4*)(hs + (idx / Q) * C::HS + 4 * (idx % Q)) = v[q];
+                } else if (i < NI) {
+                    const int idx = tid + (i - NSV) * C::NT;
+                    if (idx < L * QX) *(float4*)(xs + (idx / QX) * C::XS + 4 * (idx % QX)) = v[q];
+                }
+            }
         }
         __syncthreads();
         uint32_t gm = 0;
+        float gvs[C::MB][4];       // g_t of this lane's steps, loaded ahead of the MFMAs
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tl = mb * 16 + 4 * g + i;
+                gvs[mb][i] = tl < len ? a.gs[(size_t)(row0 + tl) * D + j] : 0.f;
+            }
 #pragma unroll
         for (int mb = 0; mb < C::MB; ++mb) {
             floatx4 az, ar, aq, an;
@@ -143,7 +179,7 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_prep_kernel(GruAdjArgs 
                 // diag(A_t)_j = z + alpha U_z[j][j] + beta U_n[j][j] + gamma U_r[j][j]
                 a.dgs[row * D + j] = p.z + gr[1 * D + j] * dUz + gr[2 * D + j] * dUn +
                                      gr[3 * D + j] * dUr;
-                const float gv = a.gs[row * D + j];
+                const float gv = gvs[mb][i];
                 a.lam[0][row * D + j] = gv;
                 gm = max(gm, absbits(gv));
             }
@@ -162,11 +198,22 @@ gru_adj_local_kernel(GruAdjArgs a) {
     __shared__ __attribute__((aligned(16))) float ps[L * C::PS];
     __shared__ __attribute__((aligned(16))) float lst[(L + 1) * C::HS];   // lambda rows t0 .. t0+L
 
+    __shared__ int rowbad[L + 1];
+
     if (ld_i32(&a.ctrl->all_done)) return;
-    const float* __restrict__ lin = a.lam[a.ctrl->iter & 1];
+    // Iteration k first forms lambda^(k) = lambda^(k-1) + la carry + lc from the previous
+    // iteration's maps (k >= 1; lambda^(0) = g) with the reset guard, then linearises there.
+    const int k = a.ctrl->iter;
+    const bool fuse = k > 0;
+    const float reset_abs = a.ctrl->reset_abs;
+    const float* __restrict__ lprev = a.lam[(k + 1) & 1];    // lambda^(k-1)
+    float* __restrict__ lcur = a.lam[k & 1];                 // lambda^(k)
+    const float2* __restrict__ lacp = a.lac[(k + 1) & 1];
+    float2* __restrict__ lacn = a.lac[k & 1];
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
     const int j = 16 * w + u;
+    for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
 
     // B operands of [U_z; U_n; U_r] (3D x D), column j, same K permutation as GruGates
     const float* U = a.params + 3 * D * DX;
@@ -196,26 +243,71 @@ gru_adj_local_kernel(GruAdjArgs a) {
             // one past the last row that has a successor step inside the sequence
             const int64_t rend = first ? row0 + len : row0 + L + 1;
 
-            // ---- stage lambda rows row0 .. row0+L and the VJP operand rows ----
-            // Item (r, c4): lambda_{t0+r}[4 c4 .. 4 c4 + 3] and, for r >= 1, step t0+r-1's
-            // operand (alpha, beta, gamma)_{t0+r} * lambda_{t0+r}.  All loads of a batch are
-            // issued before its LDS writes.
+            // ---- stage lambda rows row0 .. row0+L, then the VJP operand rows ----
+            // Item (r, c4): lambda_{t0+r}[4 c4 .. 4 c4 + 3]; row L (when the tile is not the
+            // sequence's last) belongs to the next tile in time, scanned just before this one.
+            // A thread's float4 column c4 is the same for all its items.
             constexpr int Q = D / 4;
+            static_assert(C::NT % Q == 0, "column per thread");
             constexpr int NI = ((L + 1) * Q + C::NT - 1) / C::NT;
-            constexpr int NB = NI <= 3 ? NI : (NI + 1) / 2;
+            constexpr int NB = NI;     // one round trip per pass
+            const int c4 = tid % Q;
+            float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
+            if (fuse) {
+                cown = *(const float4*)(a.gcarry + (size_t)ti.gslot * D + 4 * c4);
+                if (!first)
+                    chalo = *(const float4*)(a.gcarry + (size_t)a.tiles[ti.slot - 1].gslot * D +
+                                             4 * c4);
+            }
             __syncthreads();                 // LDS of the previous tile consumed
 #pragma unroll
             for (int i0 = 0; i0 < NI; i0 += NB) {
-                float4 vl[NB], va[NB], vb[NB], vg[NB];
+                float4 vl[NB], p0[NB], p1[NB];
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
                     const int idx = tid + (i0 + q) * C::NT;
-                    const int r = idx / Q, c4 = idx % Q;
+                    const int r = idx / Q;
                     const int64_t nr = row0 + r;
                     const bool okl = i0 + q < NI && idx < (L + 1) * Q && nr < rend;
-                    const bool okp = okl && r >= 1 && r - 1 < len;
                     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    vl[q] = okl ? *(const float4*)(lin + (size_t)nr * D + 4 * c4) : z4;
+                    const size_t e = (size_t)nr * D + 4 * c4;
+                    vl[q] = okl ? *(const float4*)((fuse ? lprev : lcur) + e) : z4;
+                    p0[q] = (okl && fuse) ? *(const float4*)(lacp + e) : z4;
+                    p1[q] = (okl && fuse) ? *(const float4*)(lacp + e + 2) : z4;
+                }
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const int idx = tid + (i0 + q) * C::NT;
+                    if (i0 + q >= NI || idx >= (L + 1) * Q) continue;
+                    const int r = idx / Q;
+                    float4 w4 = vl[q];
+                    if (fuse) {
+                        const float4 cv = r < L ? cown : chalo;
+                        w4.x += p0[q].x * cv.x + p0[q].y;
+                        w4.y += p0[q].z * cv.y + p0[q].w;
+                        w4.z += p1[q].x * cv.z + p1[q].y;
+                        w4.w += p1[q].z * cv.w + p1[q].w;
+                        if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
+                            !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
+                            rowbad[r] = 1;
+                    }
+                    *(float4*)(lst + r * C::HS + 4 * c4) = w4;
+                }
+            }
+            __syncthreads();
+            // reset guard, lambda^(k) of the own rows to HBM, and the VJP operand rows:
+            // ps[r-1] = (alpha, beta, gamma)_{t0+r} * lambda_{t0+r} (zero past the sequence)
+#pragma unroll
+            for (int i0 = 0; i0 < NI; i0 += NB) {
+                float4 va[NB], vb[NB], vg[NB];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const int idx = tid + (i0 + q) * C::NT;
+                    const int r = idx / Q;
+                    const int64_t nr = row0 + r;
+                    const bool okp = i0 + q < NI && idx < (L + 1) * Q && nr < rend && r >= 1 &&
+                                     r - 1 < len;
+                    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                     const float* gp = a.gates + (size_t)nr * 4 * D + 4 * c4;
                     va[q] = okp ? *(const float4*)(gp + 1 * D) : z4;
                     vb[q] = okp ? *(const float4*)(gp + 2 * D) : z4;
@@ -225,11 +317,16 @@ gru_adj_local_kernel(GruAdjArgs a) {
                 for (int q = 0; q < NB; ++q) {
                     const int idx = tid + (i0 + q) * C::NT;
                     if (i0 + q >= NI || idx >= (L + 1) * Q) continue;
-                    const int r = idx / Q, c4 = idx % Q;
-                    *(float4*)(lst + r * C::HS + 4 * c4) = vl[q];
+                    const int r = idx / Q;
+                    float* lp = lst + r * C::HS + 4 * c4;
+                    if (fuse) {
+                        if (rowbad[r]) *(float4*)lp = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (r < len) *(float4*)(lcur + (size_t)(row0 + r) * D + 4 * c4) =
+                                         *(const float4*)lp;
+                    }
                     if (r >= 1) {
+                        const float4 l4 = *(const float4*)lp;
                         float* pr = ps + (r - 1) * C::PS + 4 * c4;
-                        const float4 l4 = vl[q];
                         *(float4*)(pr) = make_float4(va[q].x * l4.x, va[q].y * l4.y,
                                                      va[q].z * l4.z, va[q].w * l4.w);   // U_z
                         *(float4*)(pr + D) = make_float4(vb[q].x * l4.x, vb[q].y * l4.y,
@@ -239,7 +336,17 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     }
                 }
             }
+            if (fuse && tid < 64) {
+                int nb = 0;
+                for (int base = 0; base < L; base += 64) {
+                    const int r = base + tid;
+                    nb += __popcll(__ballot(r < len && rowbad[r]));
+                }
+                if (tid == 0 && nb) atomicAdd(&a.seq[b].resets_pending, nb);
+            }
             __syncthreads();
+            if (fuse)
+                for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
 
             float la[C::MB][4], lc[C::MB][4];
 #pragma unroll
@@ -322,7 +429,7 @@ gru_adj_local_kernel(GruAdjArgs a) {
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
                     if (tl < len)
-                        a.lac[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
+                        lacn[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
                 }
         }
         if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
@@ -346,16 +453,19 @@ struct GradTiles {
 };
 
 template <int D, int DX, int L>
-__global__ void __launch_bounds__(64 * (D / 16)) gru_adj_grad_kernel(GruAdjArgs a) {
+__global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gru_adj_grad_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
     using TT = GradTiles<D, DX>;
     constexpr int NW = C::NW;
     constexpr int PER_W = (TT::TOTAL + NW - 1) / NW;
     constexpr int DS = 4 * D + 4;        // delta tile stride: [dz | dr | dq | dn]
     constexpr int XSP = C::DXP + 4;
+    constexpr int WS = C::DXP + 4;       // row stride of W in LDS
     __shared__ __attribute__((aligned(16))) float dl[L * DS];
     __shared__ __attribute__((aligned(16))) float hsm[L * C::HS];
     __shared__ __attribute__((aligned(16))) float xsm[L * XSP];
+    __shared__ __attribute__((aligned(16))) float wsm[3 * D * WS];   // [W_z;W_r;W_n], for dx
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
     floatx4 acc[PER_W];
@@ -363,6 +473,10 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_grad_kernel(GruAdjArgs 
     for (int q = 0; q < PER_W; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bsum[4] = {0.f, 0.f, 0.f, 0.f};   // bias partials of unit tid % D (tid < D only)
     const float* W = a.params;              // [W_z;W_r;W_n] (3D x DX)
+    for (int idx = tid; idx < 3 * D * C::DXP; idx += C::NT) {
+        const int r = idx / C::DXP, c = idx % C::DXP;
+        wsm[r * WS + c] = c < DX ? W[r * DX + c] : 0.f;
+    }
 
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         int b, lt, len;
@@ -371,29 +485,62 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_grad_kernel(GruAdjArgs 
         const bool first = lt == 0;
         const float* lam = a.lam[a.seq[b].parity];
         __syncthreads();
-        for (int idx = tid; idx < L * D; idx += C::NT) {
-            const int tl = idx / D, ii = idx % D;
-            float dz = 0.f, dr = 0.f, dq = 0.f, dn = 0.f, hv = 0.f;
-            if (tl < len) {
-                const size_t row = (size_t)(row0 + tl);
-                const float lv = lam[row * D + ii];
-                const float* gr = a.gates + row * 4 * D;
-                dz = gr[1 * D + ii] * lv;
-                dq = gr[2 * D + ii] * lv;
-                dr = gr[3 * D + ii] * lv;
-                dn = a.eps[row * D + ii] * lv;
-                hv = (tl == 0 && first) ? a.s0[(size_t)b * D + ii] : a.s[(row - 1) * D + ii];
-            }
-            float* dr_ = dl + tl * DS;
-            dr_[ii] = dz;
-            dr_[D + ii] = dr;
-            dr_[2 * D + ii] = dq;
-            dr_[3 * D + ii] = dn;
-            hsm[tl * C::HS + ii] = hv;
+        // stage the delta rows [dz | dr | dq | dn] = (alpha, gamma, beta, eps) * lambda, the
+        // h_{t-1} rows and the x rows; every load is issued before the LDS writes
+        constexpr int Q = D / 4, QX = C::DXP / 4;
+        constexpr int NS = (L * Q + C::NT - 1) / C::NT;
+        constexpr int NX = (L * QX + C::NT - 1) / C::NT;
+        float4 vl[NS], va[NS], vb[NS], vg[NS], ve[NS], vh[NS], vx[NX];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const int idx = tid + i * C::NT;
+            const int tl = idx / Q, c4 = idx % Q;
+            const bool ok = idx < L * Q && tl < len;
+            const size_t row = (size_t)(row0 + tl);
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float* gr = a.gates + row * 4 * D + 4 * c4;
+            vl[i] = ok ? *(const float4*)(lam + row * D + 4 * c4) : z4;
+            va[i] = ok ? *(const float4*)(gr + 1 * D) : z4;
+            vb[i] = ok ? *(const float4*)(gr + 2 * D) : z4;
+            vg[i] = ok ? *(const float4*)(gr + 3 * D) : z4;
+            ve[i] = ok ? *(const float4*)(a.eps + row * D + 4 * c4) : z4;
+            vh[i] = !ok ? z4
+                        : (tl == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
+                                             : *(const float4*)(a.s + (row - 1) * D + 4 * c4);
         }
-        for (int idx = tid; idx < L * C::DXP; idx += C::NT) {
-            const int tl = idx / C::DXP, c = idx % C::DXP;
-            xsm[tl * XSP + c] = (tl < len && c < DX) ? a.x[(size_t)(row0 + tl) * DX + c] : 0.f;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            const int idx = tid + i * C::NT;
+            const int tl = idx / QX, c4 = idx % QX;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (idx < L * QX && tl < len) {
+                const float* xr = a.x + (size_t)(row0 + tl) * DX;
+                // DX is a multiple of 8; the padded columns past DX stay zero
+                if (4 * c4 < DX) v = *(const float4*)(xr + 4 * c4);
+            }
+            vx[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const int idx = tid + i * C::NT;
+            if (idx >= L * Q) continue;
+            const int tl = idx / Q, c4 = idx % Q;
+            const float4 lv = vl[i];
+            float* dr_ = dl + tl * DS + 4 * c4;
+            *(float4*)(dr_) = make_float4(va[i].x * lv.x, va[i].y * lv.y, va[i].z * lv.z,
+                                          va[i].w * lv.w);                         // dz
+            *(float4*)(dr_ + D) = make_float4(vg[i].x * lv.x, vg[i].y * lv.y, vg[i].z * lv.z,
+                                              vg[i].w * lv.w);                     // dr
+            *(float4*)(dr_ + 2 * D) = make_float4(vb[i].x * lv.x, vb[i].y * lv.y,
+                                                  vb[i].z * lv.z, vb[i].w * lv.w);  // dq
+            *(float4*)(dr_ + 3 * D) = make_float4(ve[i].x * lv.x, ve[i].y * lv.y,
+                                                  ve[i].z * lv.z, ve[i].w * lv.w);  // dn
+            *(float4*)(hsm + tl * C::HS + 4 * c4) = vh[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            const int idx = tid + i * C::NT;
+            if (idx < L * QX) *(float4*)(xsm + (idx / QX) * XSP + 4 * (idx % QX)) = vx[i];
         }
         __syncthreads();
         // bias partials: thread owns unit tid % D, steps tid / D + k * (NT / D)
@@ -436,7 +583,7 @@ __global__ void __launch_bounds__(64 * (D / 16)) gru_adj_grad_kernel(GruAdjArgs 
                         const int gate = kk / D, ii = kk % D;
                         const int dcol = gate == 0 ? 0 : (gate == 1 ? D : 3 * D);
                         const float av = dl[(mb * 16 + u) * DS + dcol + 4 * kq + g - gate * D];
-                        const float bv = n < DX ? W[(gate * D + ii) * DX + n] : 0.f;
+                        const float bv = wsm[(gate * D + ii) * WS + n];
                         o4 = mfma16x4(av, bv, o4);
                     }
 #pragma unroll
@@ -568,14 +715,14 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
 struct GruALayout {
     IterState st;
     float *gates, *eps, *dgs, *lam[2], *gmax, *part, *gcarry;
-    float2 *lac, *gagg;
+    float2 *lac[2], *gagg;
     size_t bytes;
 };
 
 constexpr int kAdjL = 64;
 constexpr int kGradL = 32;
 
-static int grad_grid() { return cu_count(); }
+static int grad_grid() { return 2 * cu_count(); }
 
 static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int ntiles,
                               int ngroups) {
@@ -586,7 +733,7 @@ static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int 
     lay.eps = c.take<float>((size_t)hb.N * D);
     lay.dgs = c.take<float>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
-    lay.lac = c.take<float2>((size_t)hb.N * D);
+    for (int p = 0; p < 2; ++p) lay.lac[p] = c.take<float2>((size_t)hb.N * D);
     lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
     lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
     lay.gmax = c.take<float>(hb.B);
@@ -673,8 +820,9 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.eps = lay.eps;
     args.dgs = lay.dgs;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
-    args.lac = lay.lac;
+    for (int p = 0; p < 2; ++p) args.lac[p] = lay.lac[p];
     args.gagg = lay.gagg;
+    args.gcarry = lay.gcarry;
     args.gmax = lay.gmax;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
@@ -699,7 +847,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         PN_HIP(hipGetLastError());
     }
     const int grid = std::max(1, std::min(ngroups, resident));
-    // iteration k reads lam[k & 1] and writes lam[(k + 1) & 1] (k from the control block)
+    // iteration k forms lambda^(k) in lam[k & 1] from lam[(k + 1) & 1] (k from the control
+    // block), then the carries
     auto one_iter = [&](hipStream_t st) {
         prof_launch("gru_adj_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kk.iter, dim3(grid), dim3(kk.nt), 0, s2, args);
@@ -707,11 +856,7 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         prof_launch("carry_scan", st, [&](hipStream_t s2) {
             launch_carry_scan(lay.gagg, lay.gcarry, lay.st, hb.B, D, s2);
         });
-        prof_launch("apply", st, [&](hipStream_t s2) {
-            launch_apply(lay.lam[0], lay.lam[1], lay.lac, lay.gcarry, lay.st, ntiles, D, kAdjL,
-                         s2);
-        });
-        launch_decide(lay.st, hb.B, st);
+        launch_decide(lay.st, hb.B, st, true);
     };
     std::vector<uintptr_t> key = {0x4145u, (uintptr_t)kk.iter, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)gs,

@@ -1,9 +1,12 @@
-// quasi-DEER for the GRU cell: one Newton iteration as three passes over HBM.
+// quasi-DEER for the GRU cell: one Newton iteration as two passes over HBM.
 //
-// For iterate s^(k) (tiles of L consecutive steps, groups of consecutive tiles of one
-// sequence, see IterState):
+// Tiles are L consecutive steps; groups are runs of consecutive tiles of one sequence (see
+// IterState).  Iteration k:
 //   local pass (gru_quasi_local_kernel), one workgroup per group of tiles, tile by tile:
-//     1. stages s_{t-1}, s_t (L+1 rows) and x_t (L rows) in LDS;
+//     1. stages s_{t-1}, s_t (L+1 rows) and x_t (L rows) in LDS.  For k >= 1 the rows of
+//        s^(k) are formed on the way in from s^(k-1) and the previous iteration's maps,
+//        s^(k)_t = s^(k-1)_t + la_t carry + lc_t, the reset guard applied (a row with a
+//        non-finite entry or one above reset_abs becomes 0), and written back;
 //     2. evaluates the gate pre-activations of f(s_{t-1}, x_t) for the L steps as a small
 //        GEMM [L x (D+Dx)] x [(D+Dx) x 4 gate blocks] on FP32 MFMA (16x16x4), the weights
 //        held in registers for the whole kernel;
@@ -13,12 +16,13 @@
 //     4. scans Delta_t = a_t Delta_{t-1} + c_t (eq. lin_rr with a diagonal transition) over
 //        the tile (in registers, across lane groups by shuffles, across 16-step blocks
 //        serially) and composes the result with the map of the group's earlier tiles, so
-//        that lac_t = (la_t, lc_t) gives Delta_t = la_t Delta_in(group) + lc_t;
-//     5. writes lac for the tile's steps and, after the last tile, the group's map;
-//   carry pass (carry_scan.hip): the carry Delta_in of every group from the group maps;
-//   apply pass (carry_scan.hip): s^(k+1)_t = s_t + la_t Delta_in + lc_t, reset guard.
-// At a sequence head a_t = 0, so the carry into a sequence is Delta_0 = 0 (s_0 is fixed).
-// No workgroup waits for another: the passes are ordered by the stream.
+//        that (la_t, lc_t) gives Delta_t = la_t Delta_in(group) + lc_t;
+//     5. writes (la, lc) for the tile's steps and, after the last tile, the group's map;
+//   carry pass (carry_scan.hip): the carry Delta_in of every group from the group maps.
+// The update s^(k+1) = s^(k) + Delta is thus applied by the next iteration's local pass,
+// which is also where its residual is tested.  At a sequence head a_t = 0, so the carry into
+// a sequence is Delta_0 = 0 (s_0 is fixed).  No workgroup waits for another: the passes are
+// ordered by the stream.
 #include <algorithm>
 
 #include "carry.hpp"
@@ -52,10 +56,12 @@ enum GruTrans : int { kTransDiag = 0, kTransIdentity = 1, kTransZero = 2 };
 struct GruQArgs {
     const float* x;
     const float* s0;
-    float* sbuf[2];          // ping-pong iterates; iteration k reads sbuf[k & 1]
+    float* sbuf[2];          // ping-pong iterates: s^(k) lives in sbuf[k & 1]
     const float* params;
-    float2* lac;             // [N][D] (la, lc) of every step, relative to its group's start
+    float2* lac[2];          // [N][D] (la, lc) of every step relative to its group's start,
+                             // iteration k writes lac[k & 1]
     float2* gagg;            // [ngroups][D] map of every group
+    const float* gcarry;     // [ngroups][D] carry into every group (previous iteration)
     Ctrl* ctrl;
     SeqState* seq;
     const TileInfo* tiles;   // by slot
@@ -71,8 +77,18 @@ gru_quasi_local_kernel(GruQArgs a) {
     __shared__ __attribute__((aligned(16))) float hs[(L + 1) * C::HS];
     __shared__ __attribute__((aligned(16))) float xs[L * C::XS];
 
+    __shared__ int rowbad[L + 1];
+
     if (ld_i32(&a.ctrl->all_done)) return;
-    const float* __restrict__ sin = a.sbuf[a.ctrl->iter & 1];
+    // Iteration k first forms s^(k) = s^(k-1) + la carry + lc from the previous iteration's
+    // maps (k >= 1; s^(0) is the caller's guess) with the reset guard, then linearises there.
+    const int k = a.ctrl->iter;
+    const bool fuse = k > 0;
+    const float reset_abs = a.ctrl->reset_abs;
+    const float* __restrict__ sprev = a.sbuf[(k + 1) & 1];   // s^(k-1)
+    float* __restrict__ scur = a.sbuf[k & 1];                 // s^(k)
+    const float2* __restrict__ lacp = a.lac[(k + 1) & 1];
+    float2* __restrict__ lacn = a.lac[k & 1];
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -83,6 +99,7 @@ gru_quasi_local_kernel(GruQArgs a) {
 
     GruGates<D, DX> wg;   // this wave's weights (units j) as MFMA B operands
     wg.load(a.params, j, g);
+    for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
 
     for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
         const GroupInfo gr = a.groups[gi];
@@ -98,33 +115,53 @@ gru_quasi_local_kernel(GruQArgs a) {
 
             // ---- stage s rows row0-1 .. row0+L-1 (stage row r <-> s_{t0-1+r}) and x rows.
             // Items 0 .. NSV-1 of a thread are float4s of s, the rest float4s of x, in
-            // batches whose loads are all issued before their LDS writes.
+            // batches whose loads are all issued before their LDS writes.  A thread's float4
+            // column c4 is the same for all its s items (NT is a multiple of D / 4).
             constexpr int Q = D / 4, QX = DX / 4;
+            static_assert(C::NT % Q == 0, "column per thread");
             constexpr int NSV = ((L + 1) * Q + C::NT - 1) / C::NT;
             constexpr int NXV = (L * QX + C::NT - 1) / C::NT;
             constexpr int NI = NSV + NXV;
             constexpr int NB = 4;
+            const int c4 = tid % Q;
+            float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
+            if (fuse) {
+                cown = *(const float4*)(a.gcarry + (size_t)ti.gslot * D + 4 * c4);
+                if (!first && tid < Q)
+                    chalo = *(const float4*)(a.gcarry + (size_t)a.tiles[ti.slot - 1].gslot * D +
+                                             4 * c4);
+            }
             __syncthreads();                 // LDS of the previous tile consumed
 #pragma unroll
             for (int i0 = 0; i0 < NI; i0 += NB) {
-                float4 v[NB];
+                float4 v[NB], p0[NB], p1[NB];
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
                     const int i = i0 + q;
-                    v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    v[q] = z4;
+                    p0[q] = z4;
+                    p1[q] = z4;
                     if (i < NSV) {
                         const int idx = tid + i * C::NT;
-                        const int r = idx / Q, c4 = idx % Q;
-                        const float* src = r == 0 ? (first ? a.s0 + (size_t)b * D
-                                                           : sin + (size_t)(row0 - 1) * D)
-                                                  : sin + (size_t)(row0 + r - 1) * D;
-                        if (idx < (L + 1) * Q && (r == 0 || r - 1 < len))
-                            v[q] = *(const float4*)(src + 4 * c4);
+                        const int r = idx / Q;
+                        const int64_t row = r == 0 ? row0 - 1 : row0 + r - 1;
+                        const bool ok = idx < (L + 1) * Q && (r == 0 || r - 1 < len);
+                        if (r == 0 && first) {
+                            v[q] = *(const float4*)(a.s0 + (size_t)b * D + 4 * c4);
+                        } else if (ok) {
+                            const size_t e = (size_t)row * D + 4 * c4;
+                            v[q] = *(const float4*)((fuse ? sprev : scur) + e);
+                            if (fuse) {
+                                p0[q] = *(const float4*)(lacp + e);
+                                p1[q] = *(const float4*)(lacp + e + 2);
+                            }
+                        }
                     } else if (i < NI) {
                         const int idx = tid + (i - NSV) * C::NT;
-                        const int r = idx / QX, c4 = idx % QX;
+                        const int r = idx / QX, cx = idx % QX;
                         if (idx < L * QX && r < len)
-                            v[q] = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+                            v[q] = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * cx);
                     }
                 }
 #pragma unroll
@@ -132,8 +169,21 @@ gru_quasi_local_kernel(GruQArgs a) {
                     const int i = i0 + q;
                     if (i < NSV) {
                         const int idx = tid + i * C::NT;
-                        if (idx < (L + 1) * Q)
-                            *(float4*)(hs + (idx / Q) * C::HS + 4 * (idx % Q)) = v[q];
+                        if (idx < (L + 1) * Q) {
+                            const int r = idx / Q;
+                            float4 w4 = v[q];
+                            if (fuse && !(r == 0 && first)) {
+                                const float4 cv = r == 0 ? chalo : cown;
+                                w4.x += p0[q].x * cv.x + p0[q].y;
+                                w4.y += p0[q].z * cv.y + p0[q].w;
+                                w4.z += p1[q].x * cv.z + p1[q].y;
+                                w4.w += p1[q].z * cv.w + p1[q].w;
+                                if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
+                                    !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
+                                    rowbad[r] = 1;
+                            }
+                            *(float4*)(hs + r * C::HS + 4 * c4) = w4;
+                        }
                     } else if (i < NI) {
                         const int idx = tid + (i - NSV) * C::NT;
                         if (idx < L * QX)
@@ -142,6 +192,30 @@ gru_quasi_local_kernel(GruQArgs a) {
                 }
             }
             __syncthreads();
+            if (fuse) {
+                // reset guard on the formed rows, then s^(k) of the tile's own rows to HBM
+#pragma unroll
+                for (int i = 0; i < NSV; ++i) {
+                    const int idx = tid + i * C::NT;
+                    const int r = idx / Q;
+                    if (idx < (L + 1) * Q && (r == 0 || r - 1 < len)) {
+                        float* hp = hs + r * C::HS + 4 * c4;
+                        if (rowbad[r]) *(float4*)hp = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (r >= 1) *(float4*)(scur + (size_t)(row0 + r - 1) * D + 4 * c4) =
+                                        *(const float4*)hp;
+                    }
+                }
+                if (tid < 64) {
+                    int nb = 0;
+                    for (int base = 1; base <= L; base += 64) {
+                        const int r = base + tid;
+                        nb += __popcll(__ballot(r <= len && rowbad[r]));
+                    }
+                    if (tid == 0 && nb) atomicAdd(&a.seq[b].resets_pending, nb);
+                }
+                __syncthreads();
+                for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
+            }
 
             // ---- gates by MFMA, then residual and leaves, per 16-step block ----
             float la[C::MB][4], lc[C::MB][4];
@@ -216,7 +290,7 @@ gru_quasi_local_kernel(GruQArgs a) {
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
                     if (tl < len)
-                        a.lac[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
+                        lacn[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
                 }
         }
         if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
@@ -232,7 +306,7 @@ gru_quasi_local_kernel(GruQArgs a) {
 struct GruQLayout {
     IterState st;
     float* salt;
-    float2* lac;
+    float2* lac[2];
     float2* gagg;
     float* gcarry;
     size_t bytes;
@@ -243,7 +317,7 @@ static GruQLayout gruq_layout(void* ws, int D, const HostBatch& hb, int ntiles, 
     GruQLayout lay;
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.salt = c.take<float>((size_t)hb.N * D);
-    lay.lac = c.take<float2>((size_t)hb.N * D);
+    for (int p = 0; p < 2; ++p) lay.lac[p] = c.take<float2>((size_t)hb.N * D);
     lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
     lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
     lay.bytes = c.bytes();
@@ -330,8 +404,9 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     args.x = x;
     args.s0 = s0;
     args.params = (const float*)cd.params;
-    args.lac = lay.lac;
+    for (int p = 0; p < 2; ++p) args.lac[p] = lay.lac[p];
     args.gagg = lay.gagg;
+    args.gcarry = lay.gcarry;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
     args.tiles = lay.st.tiles;
@@ -342,8 +417,8 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     args.sbuf[0] = s;
     args.sbuf[1] = lay.salt;
 
-    // iteration k reads sbuf[k & 1] and writes sbuf[(k + 1) & 1] (k from the control block,
-    // so a captured graph of iterations replays from any k)
+    // iteration k forms s^(k) in sbuf[k & 1] from sbuf[(k + 1) & 1] (k from the control
+    // block, so a captured graph of iterations replays from any k), then the carries
     auto one_iter = [&](hipStream_t st) {
         prof_launch("gru_quasi_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), 0, s2, args);
@@ -351,10 +426,7 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
         prof_launch("carry_scan", st, [&](hipStream_t s2) {
             launch_carry_scan(lay.gagg, lay.gcarry, lay.st, hb.B, D, s2);
         });
-        prof_launch("apply", st, [&](hipStream_t s2) {
-            launch_apply(s, lay.salt, lay.lac, lay.gcarry, lay.st, ntiles, D, L, s2);
-        });
-        launch_decide(lay.st, hb.B, st);
+        launch_decide(lay.st, hb.B, st, true);
     };
     std::vector<uintptr_t> key = {0x6752u, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,

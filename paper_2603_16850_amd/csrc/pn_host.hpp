@@ -99,7 +99,9 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
                           int gt = 0);
 
 // Launches the end-of-iteration decision kernel (stop tests, counters).
-void launch_decide(const IterState& st, int B, hipStream_t stream);
+// `pending_current`: the resets counted during the iteration belong to the iterate that was
+// tested (solvers that form s^(k) at the start of iteration k), not to the next one.
+void launch_decide(const IterState& st, int B, hipStream_t stream, bool pending_current = false);
 
 // Runs `one_iter` (which enqueues one iteration: main kernels + decide) until every
 // sequence is done, checking convergence on the host every `graph_iters` iterations;
