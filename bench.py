@@ -58,6 +58,36 @@ def adj_local_bytes(D):
     return 4 * D + 8 * D + 16 * D + 4 * D + 4 * D + 4 * D + 8 * D
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gru64_hbm_traffic.txt")
+SOURCES = {"gru_quasi_local": ["gru_quasi.hip", "gru_common.hpp", "pn_device.hpp"],
+           "gru_adj_local": ["gru_adjoint.hip", "gru_common.hpp", "pn_device.hpp"]}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the kernel's sources changed after the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2603_16850_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha, cur = h.hexdigest()[:16], None
+    for line in text.splitlines():
+        line = line.strip()
+        if line.startswith("kernel:"):
+            cur = line.split(":", 1)[1].strip().split("<")[0].replace("_kernel", "")
+        elif line.startswith("source_sha:") and cur == kernel:
+            if line.split()[1] != sha:
+                return None
+        elif line.startswith("traffic_bytes:") and cur == kernel:
+            return int(line.split()[1])
+    return None
+
+
 def roofline_of(kernel, D, Dx, N, avg_ms):
     """Both ceilings of a launch over N steps; the binding one (longer time at peak) wins."""
     if kernel == "gru_quasi_local":
@@ -86,6 +116,8 @@ def main():
                     help="residual stopping tolerance (1e-6 keeps the error under 1e-5)")
     ap.add_argument("--seq-reps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--graphs", action="store_true",
+                    help="also time the step with graph-captured iterations (not the value)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -111,7 +143,9 @@ def main():
     x = torch.tensor(inst.x, dtype=torch.float32, device=dev)
     s0 = torch.tensor(inst.s0, dtype=torch.float32, device=dev)
     p = torch.tensor(inst.params, dtype=torch.float32, device=dev)
-    kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol)
+    # graph_iters=1: the host checks the stopping state after every iteration, so no launch
+    # after convergence is timed (each launch of the iteration kernels does a full pass)
+    kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol, graph_iters=1)
 
     def step():
         s, finfo = pn.deer_solve(x, s0, p, **kw)
@@ -160,11 +194,23 @@ def main():
     it_b = [i["iters"] for i in binfo]
     dom = max(("gru_quasi_local", "gru_adj_local"), key=lambda f: fam[f][0])
     dms, dn = fam[dom]
-    real = args.steps * ((max(it_f) if dom == "gru_quasi_local" else max(it_b)) + 1)
-    avg_ms = dms / max(real, 1)
+    avg_ms = dms / max(dn, 1)
     roofline = roofline_of(dom, D, Dx, N, avg_ms)
-    roofline.update({"traffic": None, "avg_launch_ms": round(avg_ms, 4),
-                     "launches_timed": dn, "launches_working": real})
+    roofline.update({"traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 4),
+                     "launches": dn})
+
+    # optionally the same step with the library's defaults (iterations captured in HIP graphs,
+    # stopping state read every 4 iterations), outside the timed region
+    ms_graph = None
+    if args.graphs:
+        kw_graph = dict(kw, graph_iters=4)
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        for _ in range(args.steps):
+            pn.deer_solve(x, s0, p, **kw_graph)
+            pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw_graph)
+        torch.cuda.synchronize()
+        ms_graph = round((time.perf_counter() - tg0) * 1e3 / args.steps, 3)
 
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "sequence-steps/s",
@@ -173,12 +219,13 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD, "cell": "gru", "D": D, "Dx": Dx, "B": B,
                    "T": work.T, "N": N, "method": "quasi-DEER fwd + exact quasi adjoint",
-                   "tol": args.tol, "loss": "sum_t ||s_t||^2", "graph_iters": 4},
+                   "tol": args.tol, "loss": "sum_t ||s_t||^2", "graph_iters": 1},
         "iters_fwd": it_f, "iters_bwd": it_b,
         "kernel_ms": {k: {"total": round(v[0], 3), "launches": v[1]} for k, v in fam.items()},
         "sequential_gpu": {"value": round(seq_value, 1), "unit": "sequence-steps/s",
                            "ms_per_step": round(seq_ms, 3)},
         "speedup_vs_sequential": round(value / seq_value, 2),
+        "ms_per_step_graphs": ms_graph,
         "roofline": roofline,
     }
 
