@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--graphs", action="store_true",
                     help="also time the step with graph-captured iterations (not the value)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a 1 GiB device copy (reference for HBM counters)")
+                    help="accepted for older command lines; the 1 GiB copy always runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -128,17 +128,21 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    from paper_2603_16850_amd import workloads
+    work = workloads.ALL[WORKLOAD]
+    inst = workloads.make_instance(work, seed=0)
+    D, Dx, B, N = work.D, work.Dx, work.B, inst.N
+
+    # the CPU oracle runs first, in worker processes forked before anything touches the GPU
+    cpu = None if args.no_cpu else cpu_oracle(inst)
+
     import torch
     import paper_2603_16850_amd as pn
-    from paper_2603_16850_amd import workloads
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     pn.load()
-    work = workloads.ALL[WORKLOAD]
-    inst = workloads.make_instance(work, seed=0)
-    D, Dx, B, N = work.D, work.Dx, work.B, inst.N
     dev = "cuda"
     x = torch.tensor(inst.x, dtype=torch.float32, device=dev)
     s0 = torch.tensor(inst.s0, dtype=torch.float32, device=dev)
@@ -157,11 +161,14 @@ def main():
     torch.cuda.synchronize()
 
     # ---- timed region: K full steps, kernel durations by HIP events on the library stream
+    step_ms = []
     with pn.profile():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            out = step()
+            ts = time.perf_counter()
+            out = step()          # the solvers return after their work finished
+            step_ms.append((time.perf_counter() - ts) * 1e3)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         fam = {f: pn.profile.read(f) for f in FAMILIES}
@@ -180,11 +187,18 @@ def main():
     seq_ms = (ts1 - ts0) * 1e3 / args.seq_reps
     seq_value = N / (seq_ms * 1e-3)
 
-    if args.copy_probe:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
+    # device-to-device copy of 1 GiB: the achievable HBM rate on this machine (read + write), and
+    # the reference dispatch for the FETCH_SIZE / WRITE_SIZE counter scaling
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    tc0 = time.perf_counter()
+    for _ in range(3):
         b.copy_(a)
-        torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 2 * a.numel() * 4 / (time.perf_counter() - tc0) / 1e9
+    del a, b
 
     # ---- roofline of the dominant kernel (largest share of the measured kernel time).
     # Launches that find every sequence stopped return at once; the average is taken over
@@ -198,6 +212,8 @@ def main():
     roofline = roofline_of(dom, D, Dx, N, avg_ms)
     roofline.update({"traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 4),
                      "launches": dn})
+    if roofline["bound"] == "hbm":
+        roofline["frac_of_measured_copy"] = round(roofline["achieved"] / copy_gbs, 4)
 
     # optionally the same step with the library's defaults (iterations captured in HIP graphs,
     # stopping state read every 4 iterations), outside the timed region
@@ -225,43 +241,98 @@ def main():
         "sequential_gpu": {"value": round(seq_value, 1), "unit": "sequence-steps/s",
                            "ms_per_step": round(seq_ms, 3)},
         "speedup_vs_sequential": round(value / seq_value, 2),
+        "step_ms_median": round(float(np.median(step_ms)), 3),
+        "step_ms_iqr": round(float(np.percentile(step_ms, 75) - np.percentile(step_ms, 25)), 3),
+        "copy_bandwidth_gbs": round(copy_gbs, 1),
         "ms_per_step_graphs": ms_graph,
         "roofline": roofline,
     }
 
-    if not args.no_cpu:
-        rec["cpu_baseline"], err = cpu_leg(inst, s, gp, gx, g0, s_seq)
-        rec["err"] = err
+    if cpu is not None:
+        rec["cpu_baseline"] = cpu["baseline"]
+        rec["cpu_single_core"] = cpu["single_core"]
+        rec["err"] = errors(cpu, s, gp, gx, g0, s_seq)
     print(json.dumps(rec), flush=True)
 
 
-def cpu_leg(inst, s, gp, gx, g0, s_seq):
-    """The oracle (FP64 numpy rollout + sequential adjoint) timed on the host, and the
-    error of the GPU results against it."""
-    from oracle import adjoint, cells, rollout
+def _one_thread():
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
+
+
+def _oracle_one(job):
+    """Forward rollout + sequential adjoint of one sequence in FP64 (one worker, one thread)."""
+    cell, x, s0 = job
+    from oracle import adjoint, rollout
+    s = rollout.rollout(cell, x, s0)
+    _, gp, gx, g0 = adjoint.adjoint(cell, x, s0, s, 2.0 * s)
+    return s, gp, gx, g0
+
+
+def cpu_oracle(inst):
+    """The oracle (FP64 numpy rollout + sequential adjoint) on the host: one sequence on one
+    core, then every sequence over a pool of single-threaded workers (one per core, at most
+    16).  Returns the results for the error check and the two rates."""
+    import multiprocessing as mp
+    from oracle import cells
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        threadpool_limits = None
     w = inst.work
     cell = cells.GRU(inst.params, w.D, w.Dx)
+    off = inst.offsets
+    jobs = [(cell, inst.x[off[b]:off[b + 1]], inst.s0[b]) for b in range(w.B)]
+    ncores = max(1, min(16, os.cpu_count() or 1))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    if threadpool_limits is not None:
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            _oracle_one(jobs[0])
+            dt1 = time.perf_counter() - t0
+    else:
+        t0 = time.perf_counter()
+        _oracle_one(jobs[0])
+        dt1 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    sref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
-    _, wp, wx, w0 = adjoint.adjoint_batch(cell, inst.x, inst.s0, sref, 2 * sref, inst.offsets)
+    with mp.get_context("fork").Pool(processes=ncores, initializer=_one_thread) as pool:
+        res = pool.map(_oracle_one, jobs)
     dt = time.perf_counter() - t0
+    s = np.concatenate([r[0] for r in res])
+    gp = sum(r[1] for r in res)
+    gx = np.concatenate([r[2] for r in res])
+    g0 = np.stack([r[3] for r in res])
+    t_b = int(off[1] - off[0])
+    return {
+        "s": s, "gp": gp, "gx": gx, "g0": g0,
+        "baseline": {"value": round(inst.N / dt, 1), "unit": "sequence-steps/s",
+                     "cores": ncores, "kind": "oracle",
+                     "sample": f"whole workload ({w.B} x {w.T} steps): FP64 numpy sequential "
+                               f"rollout + sequential adjoint, one sequence per single-threaded "
+                               f"worker, {ncores} workers, {dt:.1f} s; CPU {model}"},
+        "single_core": {"value": round(t_b / dt1, 1), "unit": "sequence-steps/s", "cores": 1,
+                        "sample": f"one sequence ({t_b} steps), {dt1:.1f} s"},
+    }
 
+
+def errors(cpu, s, gp, gx, g0, s_seq):
+    """Relative max errors of the GPU results against the oracle's."""
     def rel(a, b):
         a = a.detach().cpu().double().numpy() if hasattr(a, "detach") else a
         return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
 
-    err = {"s": rel(s, sref), "gparams": rel(gp, wp), "gx": rel(gx, wx), "gs0": rel(g0, w0),
-           "s_sequential_gpu": rel(s_seq, sref)}
-    base = {"value": round(inst.N / dt, 1), "unit": "sequence-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"whole workload ({inst.work.B} x {inst.work.T} steps): FP64 numpy "
-                      f"sequential rollout + sequential adjoint, {dt:.1f} s"}
-    return base, err
+    return {"s": rel(s, cpu["s"]), "gparams": rel(gp, cpu["gp"]), "gx": rel(gx, cpu["gx"]),
+            "gs0": rel(g0, cpu["g0"]), "s_sequential_gpu": rel(s_seq, cpu["s"])}
 
 
 if __name__ == "__main__":

@@ -182,13 +182,14 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
         gstart[b + 1] = gstart[b] + (nt + g - 1) / g;
         for (int k = 0; k < nt; ++k) {
             TileInfo& ti = tiles[tstart[b] + k];
+            const int lt = reverse ? nt - 1 - k : k;      // tile index in time
             ti.slot = tstart[b] + k;
             ti.b = b;
-            ti.lt = reverse ? nt - 1 - k : k;
-            ti.len = (int)std::min<int64_t>(L, hb.len(b) - (int64_t)ti.lt * L);
-            ti.row0 = hb.offsets[b] + (int64_t)ti.lt * L;
-            ti.first = tstart[b];
+            ti.len = (int)std::min<int64_t>(L, hb.len(b) - (int64_t)lt * L);
+            ti.flags = (k == 0 ? kTileScanFirst : 0) | (lt == 0 ? kTileTimeFirst : 0);
+            ti.row0 = hb.offsets[b] + (int64_t)lt * L;
             ti.gslot = gstart[b] + k / g;
+            ti.hgslot = k > 0 ? gstart[b] + (k - 1) / g : -1;
         }
         for (int k = 0; k < nt; k += g)
             groups.push_back(GroupInfo{b, tstart[b] + k, std::min(g, nt - k), gstart[b]});

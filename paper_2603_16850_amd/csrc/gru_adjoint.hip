@@ -46,7 +46,8 @@ struct GruAdjArgs {
     const float* params;
     float* gates;            // [N][4][D]: z, alpha, beta, gamma at the solution
     float* eps;              // [N][D]: (1 - z)(1 - n^2)
-    float* dgs;              // [N][D]: diag(A_t) at the solution (the reverse scan's transition)
+    float2* zd;              // [N][D]: (z_t, diag(A_t)) at the solution (the reverse scan's
+                             // per-step operands)
     float* lam[2];           // ping-pong adjoint iterates; iteration k reads lam[k & 1]
     float2* lac[2];          // [N][D] (la, lc) relative to the step's group; iteration k
                              // writes lac[k & 1]
@@ -177,8 +178,9 @@ gru_adj_prep_kernel(GruAdjArgs a) {
                 gr[3 * D + j] = e * p.q * p.r * (1.f - p.r);
                 a.eps[row * D + j] = e;
                 // diag(A_t)_j = z + alpha U_z[j][j] + beta U_n[j][j] + gamma U_r[j][j]
-                a.dgs[row * D + j] = p.z + gr[1 * D + j] * dUz + gr[2 * D + j] * dUn +
-                                     gr[3 * D + j] * dUr;
+                a.zd[row * D + j] = make_float2(p.z, p.z + gr[1 * D + j] * dUz +
+                                                         gr[2 * D + j] * dUn +
+                                                         gr[3 * D + j] * dUr);
                 const float gv = gvs[mb][i];
                 a.lam[0][row * D + j] = gv;
                 gm = max(gm, absbits(gv));
@@ -235,11 +237,13 @@ gru_adj_local_kernel(GruAdjArgs a) {
         const float gscale = 1.f / fmaxf(1.f, a.gmax[b]);
         float Pa = 1.f, Pc = 0.f;        // map of the group's tiles before the current one
         uint32_t rmax = 0;
+        TileInfo tnext = a.tiles[gr.tile0];
         for (int kt = 0; kt < gr.ntl; ++kt) {
-            const TileInfo ti = a.tiles[gr.tile0 + kt];    // scan order: later tiles first
+            const TileInfo ti = tnext;                     // scan order: later tiles first
+            if (kt + 1 < gr.ntl) tnext = a.tiles[gr.tile0 + kt + 1];   // read ahead
             const int len = ti.len;
             const int64_t row0 = ti.row0;
-            const bool first = ti.slot == ti.first;       // tile at the sequence end
+            const bool first = (ti.flags & kTileScanFirst) != 0;   // tile at the sequence end
             // one past the last row that has a successor step inside the sequence
             const int64_t rend = first ? row0 + len : row0 + L + 1;
 
@@ -253,11 +257,10 @@ gru_adj_local_kernel(GruAdjArgs a) {
             constexpr int NB = NI;     // one round trip per pass
             const int c4 = tid % Q;
             float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
-            if (fuse) {
+            if (fuse) {      // in flight together with the staging loads below
                 cown = *(const float4*)(a.gcarry + (size_t)ti.gslot * D + 4 * c4);
                 if (!first)
-                    chalo = *(const float4*)(a.gcarry + (size_t)a.tiles[ti.slot - 1].gslot * D +
-                                             4 * c4);
+                    chalo = *(const float4*)(a.gcarry + (size_t)ti.hgslot * D + 4 * c4);
             }
             __syncthreads();                 // LDS of the previous tile consumed
 #pragma unroll
@@ -349,20 +352,25 @@ gru_adj_local_kernel(GruAdjArgs a) {
                 for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
 
             float la[C::MB][4], lc[C::MB][4];
-#pragma unroll
-            for (int mb = 0; mb < C::MB; ++mb) {
-                // this block's per-element operands, loaded before its MFMAs so they overlap
-                float zn[4], dn[4], gt[4];
+            // per-element operands of a 16-step block: (z, diag A) of step t+1 and g_t, loaded
+            // one block ahead so that their latency hides behind the previous block's MFMAs
+            float2 zdc[4], zdn[4];
+            float gtc[4], gtn[4];
+            auto load_block = [&](int mb, float2* zd, float* gt) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
                     const int64_t row = row0 + tl;
                     const bool valid = tl < len;
                     const bool has_next = valid && row + 1 < rend;
-                    zn[i] = has_next ? a.gates[(size_t)(row + 1) * 4 * D + j] : 0.f;
-                    dn[i] = has_next ? a.dgs[(size_t)(row + 1) * D + j] : 0.f;
+                    zd[i] = has_next ? a.zd[(size_t)(row + 1) * D + j] : make_float2(0.f, 0.f);
                     gt[i] = valid ? a.gs[(size_t)row * D + j] : 0.f;
                 }
+            };
+            load_block(0, zdc, gtc);
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb) {
+                if (mb + 1 < C::MB) load_block(mb + 1, zdn, gtn);
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                 const float* prow = ps + (mb * 16 + u) * C::PS;
 #pragma unroll
@@ -379,11 +387,16 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     const bool valid = tl < len;
                     const float lam_t = lst[tl * C::HS + j];
                     // (A_{t+1}^T lambda_{t+1})_j = z_j lambda_j + [U_z; U_n; U_r]^T part (MFMA)
-                    const float vjp = zn[i] * lst[(tl + 1) * C::HS + j] + acc[i];
-                    const float rho = lam_t - gt[i] - vjp;
-                    la[mb][i] = valid ? dn[i] : 1.f;
+                    const float vjp = zdc[i].x * lst[(tl + 1) * C::HS + j] + acc[i];
+                    const float rho = lam_t - gtc[i] - vjp;
+                    la[mb][i] = valid ? zdc[i].y : 1.f;
                     lc[mb][i] = valid ? -rho : 0.f;
                     if (valid) rmax = max(rmax, absbits(rho * gscale));
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    zdc[i] = zdn[i];
+                    gtc[i] = gtn[i];
                 }
             }
 
@@ -714,8 +727,8 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
 
 struct GruALayout {
     IterState st;
-    float *gates, *eps, *dgs, *lam[2], *gmax, *part, *gcarry;
-    float2 *lac[2], *gagg;
+    float *gates, *eps, *lam[2], *gmax, *part, *gcarry;
+    float2 *zd, *lac[2], *gagg;
     size_t bytes;
 };
 
@@ -731,7 +744,7 @@ static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int 
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.gates = c.take<float>((size_t)hb.N * 4 * D);
     lay.eps = c.take<float>((size_t)hb.N * D);
-    lay.dgs = c.take<float>((size_t)hb.N * D);
+    lay.zd = c.take<float2>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lac[p] = c.take<float2>((size_t)hb.N * D);
     lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
@@ -818,7 +831,7 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
     args.eps = lay.eps;
-    args.dgs = lay.dgs;
+    args.zd = lay.zd;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     for (int p = 0; p < 2; ++p) args.lac[p] = lay.lac[p];
     args.gagg = lay.gagg;
@@ -925,7 +938,7 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
     args.eps = lay.eps;
-    args.dgs = lay.dgs;
+    args.zd = lay.zd;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     args.gmax = lay.gmax;
     args.ctrl = lay.st.ctrl;

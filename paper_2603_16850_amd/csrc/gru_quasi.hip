@@ -107,11 +107,13 @@ gru_quasi_local_kernel(GruQArgs a) {
         const int b = gr.b;
         float Pa = 1.f, Pc = 0.f;        // map of the group's tiles before the current one
         uint32_t rmax = 0;
+        TileInfo tnext = a.tiles[gr.tile0];
         for (int kt = 0; kt < gr.ntl; ++kt) {
-            const TileInfo ti = a.tiles[gr.tile0 + kt];
+            const TileInfo ti = tnext;
+            if (kt + 1 < gr.ntl) tnext = a.tiles[gr.tile0 + kt + 1];   // read ahead
             const int len = ti.len;
             const int64_t row0 = ti.row0;
-            const bool first = ti.lt == 0;
+            const bool first = (ti.flags & kTileTimeFirst) != 0;
 
             // ---- stage s rows row0-1 .. row0+L-1 (stage row r <-> s_{t0-1+r}) and x rows.
             // Items 0 .. NSV-1 of a thread are float4s of s, the rest float4s of x, in
@@ -125,11 +127,10 @@ gru_quasi_local_kernel(GruQArgs a) {
             constexpr int NB = 4;
             const int c4 = tid % Q;
             float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
-            if (fuse) {
+            if (fuse) {      // in flight together with the staging loads below
                 cown = *(const float4*)(a.gcarry + (size_t)ti.gslot * D + 4 * c4);
                 if (!first && tid < Q)
-                    chalo = *(const float4*)(a.gcarry + (size_t)a.tiles[ti.slot - 1].gslot * D +
-                                             4 * c4);
+                    chalo = *(const float4*)(a.gcarry + (size_t)ti.hgslot * D + 4 * c4);
             }
             __syncthreads();                 // LDS of the previous tile consumed
 #pragma unroll

@@ -37,14 +37,16 @@ struct SeqState {
 };
 
 // One entry per tile, indexed by scan slot (see IterState::tiles).
+constexpr int kTileScanFirst = 1;   // the sequence's first scanned tile
+constexpr int kTileTimeFirst = 2;   // the sequence's first tile in time (rows from its start)
 struct TileInfo {
     int32_t slot;       // scan slot of the tile (consecutive within a sequence, scan order)
     int32_t b;          // sequence
-    int32_t lt;         // tile index from the sequence start (rows row0 .. row0+len-1)
-    int32_t len;        // valid steps
+    int32_t len;        // valid steps (rows row0 .. row0+len-1)
+    int32_t flags;      // kTileScanFirst | kTileTimeFirst
     int64_t row0;       // first row
-    int32_t first;      // slot of the sequence's first scanned tile
     int32_t gslot;      // group of the tile (see GroupInfo)
+    int32_t hgslot;     // group of the tile scanned just before it in its sequence, -1 if none
 };
 
 // A group is a run of consecutive tiles of one sequence, in scan order, that one workgroup
