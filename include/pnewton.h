@@ -75,6 +75,16 @@ typedef enum {
                            initialisation s_t^(0) = f(0, x_t) discussed in Ch. 3          */
 } pn_jac;
 
+typedef enum {
+    PN_DAMP_NONE = 0,
+    PN_DAMP_SCALE = 1,  /* scale-ELK (Sec. "Further extensions: scale- and clip-ELK"):
+                           A~_t <- (1 - k) A~_t with k = damp_k in [0, 1]; k = 0 is the
+                           undamped method, k = 1 makes every iteration a Jacobi step       */
+    PN_DAMP_CLIP = 2    /* clip-ELK (same section): every entry of a diagonal A~_t clipped to
+                           [clip_lo, clip_hi], -1 <= clip_lo <= clip_hi <= 1 (the thesis's
+                           default is [-1, 1]); diagonal transitions only                   */
+} pn_damping;
+
 typedef enum { PN_F32 = 0, PN_F64 = 1 } pn_dtype;
 
 typedef enum {
@@ -110,7 +120,11 @@ typedef struct {
     int32_t fp64_final_residual; /* ELK / F32: also report the FP64 residual of the result   */
     int32_t use_graph;        /* 1: capture graph_iters iterations in a hipGraph; 0: launch */
     int32_t tile;             /* scan tile length in steps; 0: autotuned / default          */
-    int32_t reserved[7];
+    int32_t damping;          /* pn_damping (deer_solve only; ELK damps through lambda)     */
+    float damp_k;             /* PN_DAMP_SCALE: k                                            */
+    float clip_lo;            /* PN_DAMP_CLIP: bounds                                        */
+    float clip_hi;
+    int32_t reserved[3];
 } pn_opts;
 
 typedef struct {
@@ -128,7 +142,7 @@ typedef struct {
 #define PN_OP_RESIDUAL64 3
 
 /* Fill *opts with defaults: quasi (diag), native compose, tol 1e-5, max_iters = T,
-   graph_iters 4, reset_abs 1e4, graph capture on, tile 0. */
+   graph_iters 4, reset_abs 1e4, graph capture on, tile 0, no damping (k = 0, clip [-1, 1]). */
 void pn_default_opts(pn_opts* opts);
 
 /* Bytes of device workspace `op` needs for these shapes (0 is possible).  *bytes is set on
@@ -141,19 +155,21 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
    info: HOST array [B] (may be NULL).  Built combinations:
      GRU,  PN_JAC_DIAG / PN_JAC_PICARD / PN_JAC_JACOBI, F32, (D, Dx) in
            {(16,8), (16,16), (32,8), (32,16), (32,32), (48,24), (48,48), (64,16), (64,32),
-            (64,64)}, tile 0 (default), 32, 64 or 128
-     GRU,  PN_JAC_DENSE, F64, 1 <= D <= 4, 1 <= Dx <= 16
-     TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16
+            (64,64)}, tile 0 (default), 32, 64 or 128, any damping
+     GRU,  PN_JAC_DENSE, F64, 1 <= D <= 4, 1 <= Dx <= 16, no damping
+     TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16, no damping or
+           PN_DAMP_SCALE
    Anything else returns PN_ERR_UNSUPPORTED. */
 pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                      const void* s0, void* s, const pn_opts* opts, void* workspace,
                      size_t workspace_bytes, void* stream, pn_seq_info* info);
 
 /* ELK (Ch. 4): each iteration replaces the Newton step by the filtered means of the LGSSM
-   of Prop. prop:ELK with emission noise 1/lambda (lambda >= 0; lambda = 0 is DEER).
-   Built: TANH, PN_JAC_DENSE, F32, D = 16, Dx in {16}.  With fp64_final_residual the
-   reported max_resid is the FP64 residual of the FP32 iterate and the stopping test is
-   re-checked in FP64. */
+   of Prop. prop:ELK with emission noise 1/lambda (lambda >= 0; lambda = 0 is DEER).  With
+   PN_JAC_DIAG the LGSSM uses diag(A_t): quasi-ELK (Ch. 4, "quasi-ELK").
+   Built: TANH, PN_JAC_DENSE or PN_JAC_DIAG, F32, D = 16, Dx in {16}, no damping.  With
+   fp64_final_residual the stopping test of every iterate is evaluated in FP64 and the
+   reported max_resid is the FP64 residual of the returned FP32 iterate. */
 pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                     const void* s0, void* s, double lambda, const pn_opts* opts,
                     void* workspace, size_t workspace_bytes, void* stream, pn_seq_info* info);

@@ -52,12 +52,20 @@ def transition_matrices(cell, x, h, mode):
         return np.broadcast_to(np.eye(D), (T, D, D)).copy()
     if mode == "jacobi":
         return np.zeros((T, D, D))
-    if mode == "clip":
-        d = np.clip(cell.jac_diag(h, x, t=tt), -1.0, 1.0)
+    if isinstance(mode, str) and (mode == "clip" or mode.startswith("clip:")):
+        # clip-ELK (Sec. "Further extensions: scale- and clip-ELK"): each diagonal entry
+        # clipped to [lo, hi], by default [-1, 1]
+        lo, hi = (-1.0, 1.0) if mode == "clip" else map(float, mode.split(":")[1:3])
+        d = np.clip(cell.jac_diag(h, x, t=tt), lo, hi)
         return np.einsum("ti,ij->tij", d, np.eye(D))
     if isinstance(mode, str) and mode.startswith("scale:"):
+        # scale-ELK (same section): A~_t = (1 - k) A_t
         k = float(mode.split(":", 1)[1])
         return (1.0 - k) * cell.jac(h, x, t=tt)
+    if isinstance(mode, str) and mode.startswith("diagscale:"):
+        # scale-ELK on the quasi (diagonal) approximation: A~_t = (1 - k) diag(A_t)
+        k = float(mode.split(":", 1)[1])
+        return np.einsum("ti,ij->tij", (1.0 - k) * cell.jac_diag(h, x, t=tt), np.eye(D))
     raise ValueError(mode)
 
 

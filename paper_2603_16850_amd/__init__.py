@@ -36,7 +36,9 @@ class Opts(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("graph_iters", ctypes.c_int32),
                 ("reset_abs", ctypes.c_double), ("fp64_final_residual", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("damping", ctypes.c_int32), ("damp_k", ctypes.c_float),
+                ("clip_lo", ctypes.c_float), ("clip_hi", ctypes.c_float),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class SeqInfo(ctypes.Structure):
@@ -137,10 +139,19 @@ def _dev(t, name):
     return t
 
 
+DAMPING = {"none": 0, "scale": 1, "clip": 2}
+
+
 def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4,
-              reset_abs=1e4, fp64_final_residual=False, use_graph=True, tile=0):
+              reset_abs=1e4, fp64_final_residual=False, use_graph=True, tile=0,
+              damping="none", damp_k=0.0, clip=(-1.0, 1.0)):
+    """pn_opts; damping "scale" (scale-ELK, A~ <- (1 - damp_k) A~) or "clip" (clip-ELK,
+    diagonal A~ clipped to `clip`)."""
     o = Opts()
     load().pn_default_opts(ctypes.byref(o))
+    o.damping = DAMPING[damping]
+    o.damp_k = float(damp_k)
+    o.clip_lo, o.clip_hi = float(clip[0]), float(clip[1])
     o.jac = JACS[jac]
     o.compose = COMPOSE[compose]
     o.tol = float(tol)

@@ -9,6 +9,11 @@ using namespace pn;
 
 namespace {
 
+// layouts the Python binding mirrors with ctypes
+static_assert(sizeof(pn_opts) == 72, "pn_opts layout");
+static_assert(sizeof(pn_cell_desc) == 24 && sizeof(pn_batch) == 24 && sizeof(pn_seq_info) == 24,
+              "struct layouts");
+
 pn_opts resolve_opts(const pn_opts* o) {
     pn_opts r;
     pn_default_opts(&r);
@@ -80,6 +85,24 @@ pn_status check_opts(const pn_opts& o) {
     }
     if (!(o.tol > 0) || !std::isfinite(o.tol)) { set_error("tol must be positive and finite"); return PN_ERR_INVALID_ARG; }
     if (o.tile < 0) { set_error("tile must be >= 0"); return PN_ERR_INVALID_ARG; }
+    if (o.damping < PN_DAMP_NONE || o.damping > PN_DAMP_CLIP) {
+        set_error("unknown damping %d", o.damping);
+        return PN_ERR_INVALID_ARG;
+    }
+    if (o.damping == PN_DAMP_SCALE && !(o.damp_k >= 0.f && o.damp_k <= 1.f)) {
+        set_error("damp_k must lie in [0, 1]");
+        return PN_ERR_INVALID_ARG;
+    }
+    if (o.damping == PN_DAMP_CLIP) {
+        if (!(o.clip_lo >= -1.f && o.clip_lo <= o.clip_hi && o.clip_hi <= 1.f)) {
+            set_error("clip bounds must satisfy -1 <= clip_lo <= clip_hi <= 1");
+            return PN_ERR_INVALID_ARG;
+        }
+        if (o.jac == PN_JAC_DENSE) {
+            set_error("clip damping applies to diagonal transitions only");
+            return PN_ERR_INVALID_ARG;
+        }
+    }
     return PN_OK;
 }
 
@@ -111,10 +134,10 @@ Route route_deer(const pn_cell_desc& c, const pn_opts& o) {
         gru_quasi_supported(c.D, c.Dx))
         return Route::GruQuasi;
     if (c.cell == PN_CELL_GRU && o.jac == PN_JAC_DENSE && c.dtype == PN_F64 &&
-        gru_dense64_supported(c.D, c.Dx))
+        o.damping == PN_DAMP_NONE && gru_dense64_supported(c.D, c.Dx))
         return Route::GruDense64;
     if (c.cell == PN_CELL_TANH && o.jac == PN_JAC_DENSE && c.dtype == PN_F32 &&
-        tanh_dense_supported(c.D, c.Dx))
+        o.damping != PN_DAMP_CLIP && tanh_dense_supported(c.D, c.Dx))
         return Route::TanhDense;
     return Route::None;
 }
@@ -135,6 +158,10 @@ void pn_default_opts(pn_opts* o) {
     o->fp64_final_residual = 0;
     o->use_graph = 1;
     o->tile = 0;
+    o->damping = PN_DAMP_NONE;
+    o->damp_k = 0.f;
+    o->clip_lo = -1.f;
+    o->clip_hi = 1.f;
 }
 
 int pn_abi_version(void) { return PN_ABI_VERSION; }
@@ -259,9 +286,17 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
     HostBatch hb;
     PN_TRY(check_batch(batch, hb));
     pn_opts o = resolve_opts(opts);
-    o.jac = PN_JAC_DENSE;
+    if (!opts) o.jac = PN_JAC_DENSE;          // ELK proper unless quasi-ELK is asked for
     PN_TRY(check_opts(o));
     if (!(lambda >= 0) || !std::isfinite(lambda)) { set_error("lambda must be finite and >= 0"); return PN_ERR_INVALID_ARG; }
+    if (o.jac != PN_JAC_DENSE && o.jac != PN_JAC_DIAG) {
+        set_error("elk_solve takes PN_JAC_DENSE (ELK) or PN_JAC_DIAG (quasi-ELK)");
+        return PN_ERR_UNSUPPORTED;
+    }
+    if (o.damping != PN_DAMP_NONE) {
+        set_error("elk_solve damps through lambda; damping must be PN_DAMP_NONE");
+        return PN_ERR_UNSUPPORTED;
+    }
     PN_TRY(check_ptrs({x, s0, s, cell->params}, hb));
     if (!(cell->cell == PN_CELL_TANH && cell->dtype == PN_F32 && elk_supported(cell->D, cell->Dx))) {
         set_error("elk_solve not built for cell=%d D=%d Dx=%d dtype=%d", cell->cell, cell->D,

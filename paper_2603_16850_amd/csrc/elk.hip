@@ -169,6 +169,7 @@ struct ElkArgs {
     int ntiles;
     float lam;
     int res64;               // nonzero: the stopping residual is evaluated in FP64
+    int diag;                // nonzero: quasi-ELK, the LGSSM uses diag(A_t)
 };
 
 template <int DX, int L>
@@ -302,7 +303,7 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
         auto build_At = [&](int t) {
             for (int idx = l; idx < ED * ED; idx += 64) {
                 const int r = idx / ED, c = idx % ED;
-                At[r * ES + c] = dsh[t * ED + r] * Wm[r * ES + c];
+                At[r * ES + c] = (a.diag && r != c) ? 0.f : dsh[t * ED + r] * Wm[r * ES + c];
             }
             __syncthreads();
         };
@@ -510,6 +511,7 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.ntiles = ntiles;
     args.lam = (float)lambda;
     args.res64 = o.fp64_final_residual ? 1 : 0;
+    args.diag = o.jac == PN_JAC_DIAG ? 1 : 0;
     auto one_iter = [&](hipStream_t st) {
         prof_launch("elk_iter", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
@@ -521,7 +523,8 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     std::vector<uintptr_t> key = {0x454Cu, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
                                   (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
-                                  (uintptr_t)lam_bits, (uintptr_t)args.res64};
+                                  (uintptr_t)lam_bits, (uintptr_t)args.res64,
+                                  (uintptr_t)args.diag};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;

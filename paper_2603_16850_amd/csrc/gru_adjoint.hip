@@ -64,6 +64,9 @@ struct GruAdjArgs {
     int ngroups;
     int B;
     int ntiles;
+    float dscale;            // damping of the reverse scan's transition (as the forward)
+    int clip;
+    float clo, chi;
     float* part;             // [grid][P] per-workgroup parameter-gradient partials
     float* gx;
     float* gs0;
@@ -389,7 +392,9 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     // (A_{t+1}^T lambda_{t+1})_j = z_j lambda_j + [U_z; U_n; U_r]^T part (MFMA)
                     const float vjp = zdc[i].x * lst[(tl + 1) * C::HS + j] + acc[i];
                     const float rho = lam_t - gtc[i] - vjp;
-                    la[mb][i] = valid ? zdc[i].y : 1.f;
+                    float dg = zdc[i].y * a.dscale;
+                    if (a.clip) dg = fminf(fmaxf(dg, a.clo), a.chi);
+                    la[mb][i] = valid ? dg : 1.f;
                     lc[mb][i] = valid ? -rho : 0.f;
                     if (valid) rmax = max(rmax, absbits(rho * gscale));
                 }
@@ -845,6 +850,10 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.tiles = lay.st.tiles;
     args.groups = lay.st.groups;
     args.ngroups = ngroups;
+    args.dscale = o.damping == PN_DAMP_SCALE ? 1.f - o.damp_k : 1.f;
+    args.clip = o.damping == PN_DAMP_CLIP ? 1 : 0;
+    args.clo = o.clip_lo;
+    args.chi = o.clip_hi;
     args.B = hb.B;
     args.ntiles = ntiles;
     args.part = lay.part;
@@ -874,7 +883,9 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     std::vector<uintptr_t> key = {0x4145u, (uintptr_t)kk.iter, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)gs,
                                   (uintptr_t)cd.params, (uintptr_t)ws, (uintptr_t)hb.B,
-                                  (uintptr_t)ntiles, (uintptr_t)ngroups};
+                                  (uintptr_t)ntiles, (uintptr_t)ngroups,
+                                  (uintptr_t)o.damping, float_bits(args.dscale),
+                                  float_bits(args.clo), float_bits(args.chi)};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;

@@ -68,6 +68,9 @@ struct GruQArgs {
     const GroupInfo* groups; // by group slot
     int ngroups;
     int mode;                // transition matrix: kTransDiag, kTransIdentity or kTransZero
+    float dscale;            // scale damping: A~ <- dscale A~ (1 - k; 1 without damping)
+    int clip;                // clip damping on: A~ <- min(max(A~, clo), chi)
+    float clo, chi;
 };
 
 template <int D, int DX, int L>
@@ -238,6 +241,8 @@ gru_quasi_local_kernel(GruQArgs a) {
                              + e * p.q * p.r * (1.f - p.r) * wg.dUr;
                     const bool valid = tl < len;
                     if (a.mode != kTransDiag) dg = (a.mode == kTransIdentity) ? 1.f : 0.f;
+                    dg *= a.dscale;                              // scale-ELK
+                    if (a.clip) dg = fminf(fmaxf(dg, a.clo), a.chi);   // clip-ELK
                     if (first && tl == 0) dg = 0.f;
                     la[mb][i] = valid ? dg : 1.f;
                     lc[mb][i] = valid ? -res : 0.f;
@@ -417,6 +422,10 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
               : o.jac == PN_JAC_JACOBI ? kTransZero : kTransDiag;
     args.sbuf[0] = s;
     args.sbuf[1] = lay.salt;
+    args.dscale = o.damping == PN_DAMP_SCALE ? 1.f - o.damp_k : 1.f;
+    args.clip = o.damping == PN_DAMP_CLIP ? 1 : 0;
+    args.clo = o.clip_lo;
+    args.chi = o.clip_hi;
 
     // iteration k forms s^(k) in sbuf[k & 1] from sbuf[(k + 1) & 1] (k from the control
     // block, so a captured graph of iterations replays from any k), then the carries
@@ -432,7 +441,9 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     std::vector<uintptr_t> key = {0x6752u, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
                                   (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
-                                  (uintptr_t)ngroups, (uintptr_t)args.mode};
+                                  (uintptr_t)ngroups, (uintptr_t)args.mode,
+                                  (uintptr_t)o.damping, float_bits(args.dscale),
+                                  float_bits(args.clo), float_bits(args.chi)};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key,
                           one_iter, stream));
     int derr = 0;

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <functional>
 #include <string>
 #include <vector>
@@ -30,6 +31,13 @@ pn_status hip_fail(hipError_t e, const char* what, const char* file, int line);
         pn_status s_ = (expr);              \
         if (s_ < 0) return s_;              \
     } while (0)
+
+// Bit pattern of a float (graph-cache keys).
+inline uintptr_t float_bits(float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, sizeof u);
+    return (uintptr_t)u;
+}
 
 struct HostBatch {
     int B = 0;

@@ -50,6 +50,7 @@ struct TanhDArgs {
     const int32_t* order;
     int B;
     int ntiles;
+    float dscale;             // scale damping: A_t <- dscale A_t (1 - k; 1 without damping)
 };
 
 template <int DX, int L, bool BF16>
@@ -172,7 +173,7 @@ __global__ void __launch_bounds__(64) tanh_dense_iter_kernel(TanhDArgs a) {
                 const float sc = sst[(t + 1) * SS + n];
                 const float res = sc - f;
                 const bool valid = t < len;
-                dsh[t * TD + n] = (first && t == 0) ? 0.f : (1.f - f * f);
+                dsh[t * TD + n] = (first && t == 0) ? 0.f : a.dscale * (1.f - f * f);
                 csh[t * TD + n] = -res;
                 if (valid) rmax = max(rmax, absbits(res));
             }
@@ -377,6 +378,7 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
     args.order = lay.st.order;
     args.B = hb.B;
     args.ntiles = ntiles;
+    args.dscale = o.damping == PN_DAMP_SCALE ? 1.f - o.damp_k : 1.f;
     auto one_iter = [&](hipStream_t st) {
         prof_launch("tanh_dense_iter", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
@@ -385,7 +387,8 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
     };
     std::vector<uintptr_t> key = {0x7444u, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
-                                  (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles};
+                                  (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
+                                  float_bits(args.dscale)};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;

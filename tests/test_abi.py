@@ -124,3 +124,53 @@ def test_binding_refuses_cpu_tensors():
 def test_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(ImportError):
         pn.load(str(tmp_path / "missing.so"))
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(pn.Opts) == 72
+    assert ctypes.sizeof(pn.CellDesc) == 24 and ctypes.sizeof(pn.Batch) == 24
+    assert ctypes.sizeof(pn.SeqInfo) == 24
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(damping="scale", damp_k=-0.1), -1), (dict(damping="scale", damp_k=1.5), -1),
+    (dict(damping="clip", clip=(0.5, 0.2)), -1), (dict(damping="clip", clip=(-2.0, 1.0)), -1),
+    (dict(damping="clip", jac="dense"), -1),
+])
+def test_damping_validation(lib, kw, expect):
+    c, b, _ = _desc()
+    o = pn.make_opts(**{"jac": "diag", **kw})
+    args = (ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0,
+                          None, None) == expect
+    o = pn.make_opts(jac="diag")
+    o.damping = 7
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0,
+                          None, None) == -1
+
+
+def test_damping_routes(lib):
+    """Combinations that validate but are not built: clip on the dense tanh path is rejected
+    as invalid (clip is diagonal only), damping on the FP64 dense GRU path and on ELK is
+    unsupported, ELK with a Picard transition is unsupported."""
+    args = (ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    c, b, _ = _desc(D=4, Dx=4, dtype="f64")
+    o = pn.make_opts(jac="dense", damping="scale", damp_k=0.2)
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0,
+                          None, None) == -2
+    c, b, _ = _desc(cell="tanh", D=16, Dx=16)
+    o = pn.make_opts(jac="dense", damping="scale", damp_k=0.2)
+    assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
+                         ctypes.byref(o), None, 0, None, None) == -2
+    o = pn.make_opts(jac="picard")
+    assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
+                         ctypes.byref(o), None, 0, None, None) == -2
+    # quasi-ELK and scale damping on the tanh dense path are built: they fail only later,
+    # on the missing workspace
+    o = pn.make_opts(jac="diag")
+    assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
+                         ctypes.byref(o), None, 0, None, None) == -3
+    c, b, _ = _desc(cell="tanh", D=32, Dx=16)
+    o = pn.make_opts(jac="dense", damping="scale", damp_k=0.2)
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0,
+                          None, None) == -3

@@ -98,3 +98,37 @@ def test_residual_f64_matches_oracle(lib, kind):
             continue
         _, r = newton.linearize(c32, x32[a:e], inst.s0[b], s[a:e].astype(np.float64))
         assert abs(got[b] - np.abs(r).max()) < 1e-12
+
+
+@pytest.mark.parametrize("lam", [0.0, 1e-2, 1.0])
+def test_quasi_elk_iterates_match_sequential_filter(lib, lam):
+    """quasi-ELK (Ch. 4): the LGSSM built on diag(A_t); per-iteration iterates equal the
+    oracle's filter with the diagonal transition, lambda = 0 is quasi-DEER."""
+    w = workloads.TANH16_ELK.scaled(B=3, T=0)
+    inst = workloads.make_instance(w, seed=34, lengths=np.array([64, 1, 40]))
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    for k in (1, 2, 4):
+        s, info = _elk(lib, inst, lam, tol=1e-12, max_iters=k, jac="diag")
+        for b in range(3):
+            a, e = inst.offsets[b], inst.offsets[b + 1]
+            out = elk.elk(cell, inst.x[a:e], inst.s0[b], lam, mode="diag", tol=1e-12,
+                          max_iters=k)
+            assert np.abs(s[a:e] - out["s"]).max() < 2e-5, (lam, k, b)
+            if lam == 0.0:
+                qd = newton.newton(cell, inst.x[a:e], inst.s0[b], mode="diag", tol=1e-12,
+                                   max_iters=k)
+                assert np.abs(s[a:e] - qd["s"]).max() < 2e-5
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1.0])
+def test_quasi_elk_full_size(lib, lam):
+    """quasi-ELK at full size: converges with an FP64 residual below 1e-6 (bar as
+    test_full_size)."""
+    w = workloads.TANH16_ELK
+    inst = workloads.make_instance(w, seed=0)
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    s, info = _elk(lib, inst, lam, tol=w.tol, fp64_final_residual=True, jac="diag")
+    assert all(i["converged"] for i in info), [i["iters"] for i in info]
+    assert max(i["max_resid"] for i in info) < w.tol
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    assert _rel(s, ref) < 5e-5

@@ -88,3 +88,23 @@ def test_full_size_fwd_bwd(lib, name):
     want = adjoint.adjoint_batch(cell, inst.x, inst.s0, sref, 2 * sref, inst.offsets)[1:]
     got = tuple(v.cpu().double().numpy() for v in (gp, gx, g0))
     _check_grads(cell, got, want, 1e-5)
+
+
+@pytest.mark.parametrize("damp", [dict(damping="scale", damp_k=0.5), dict(damping="clip", clip=(-0.3, 0.6))])
+def test_damped_adjoint_gives_the_same_gradients(lib, damp):
+    """The damping changes the reverse scans' transition only; the exact VJP residual fixes
+    the result, so the gradients equal the oracle's."""
+    import torch
+    from oracle import adjoint
+    w = workloads.GRU64_QUASI.scaled(B=3, T=0)
+    inst = workloads.make_instance(w, seed=44, lengths=np.array([250, 64, 129]))
+    cell = cells.GRU(inst.params, w.D, w.Dx)
+    sref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    _, wp, wx, w0 = adjoint.adjoint_batch(cell, inst.x, inst.s0, sref, 2 * sref, inst.offsets)
+    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    gp, gx, g0, info = lib.deer_adjoint(t(inst.x), t(inst.s0), t(inst.params), t(sref),
+                                        t(2 * sref), cell="gru", offsets=inst.offsets,
+                                        tol=1e-6, **damp)
+    assert all(i["converged"] for i in info), info
+    rel = lambda a, b: np.abs(a.cpu().double().numpy() - b).max() / np.abs(b).max()
+    assert rel(gp, wp) < 1e-5 and rel(gx, wx) < 1e-5 and rel(g0, w0) < 1e-5

@@ -199,3 +199,29 @@ def test_jacobi_initialisation(lib):
                                tol=ERR_TOL, s_init=guess)
     ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
     assert _rel(out.cpu().double().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("damp,mode", [(dict(damping="scale", damp_k=0.3), "diagscale:0.3"),
+                                       (dict(damping="clip", clip=(-0.5, 0.8)), "clip:-0.5:0.8"),
+                                       (dict(damping="clip"), "clip")])
+def test_damped_transitions_match_sequential_loop(lib, damp, mode):
+    """scale-ELK and clip-ELK on the diagonal path (Sec. "Further extensions: scale- and
+    clip-ELK"): iterates equal the oracle loop with the same damped transition, the first k
+    steps are exact after k updates, and the loop converges to the rollout."""
+    w = workloads.GRU64_QUASI.scaled(B=4, T=0)
+    inst = workloads.make_instance(w, seed=24, lengths=np.array([300, 65, 1, 130]))
+    cell = cells.GRU(inst.params, w.D, w.Dx)
+    for k in (1, 2, 5):
+        s, info = _run(lib, inst, max_iters=k, tol=1e-12, **damp)
+        for b in range(4):
+            a, e = inst.offsets[b], inst.offsets[b + 1]
+            out = newton.newton(cell, inst.x[a:e], inst.s0[b], mode=mode, tol=1e-12,
+                                max_iters=k)
+            assert np.abs(s[a:e] - out["s"]).max() < 2e-5, (mode, k, b)
+            ref = rollout.rollout(cell, inst.x[a:e], inst.s0[b])
+            kk = min(k, e - a)
+            assert np.abs(s[a:a + kk] - ref[:kk]).max() < 1e-6
+    s, info = _run(lib, inst, tol=ERR_TOL, **damp)
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    assert all(i["converged"] for i in info)
+    assert _rel(s, ref) < 1e-5

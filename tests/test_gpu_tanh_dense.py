@@ -67,3 +67,26 @@ def test_full_size(lib, compose):
     ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
     assert all(i["converged"] for i in info)
     assert _rel(s, ref) < 1e-5, _rel(s, ref)
+
+
+@pytest.mark.parametrize("compose", ["native", "bf16"])
+def test_scale_damping(lib, compose):
+    """scale-ELK on the dense path: A~_t = (1 - k) A_t (Sec. "Further extensions: scale- and
+    clip-ELK"); FP32 iterates equal the oracle loop with the same transition; both composes
+    converge to the rollout."""
+    w = workloads.TANH32_DENSE_BF16.scaled(B=2, T=300)
+    inst = workloads.make_instance(w, seed=23)
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    if compose == "native":
+        for k in (1, 2, 3):
+            s, _ = _solve(lib, inst, compose, tol=1e-12, max_iters=k, damping="scale",
+                          damp_k=0.25)
+            for b in range(2):
+                a, e = inst.offsets[b], inst.offsets[b + 1]
+                out = newton.newton(cell, inst.x[a:e], inst.s0[b], mode="scale:0.25",
+                                    tol=1e-12, max_iters=k)
+                assert np.abs(s[a:e] - out["s"]).max() < 1e-5
+    s, info = _solve(lib, inst, compose, tol=1e-6, damping="scale", damp_k=0.25)
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    assert all(i["converged"] for i in info)
+    assert _rel(s, ref) < 1e-5

@@ -97,7 +97,8 @@ def test_diagonal_affine_converges_in_one_quasi_iteration():
 
 # ---- global convergence in <= T iterations, prefix exactness (Prop. global_convergence) --
 
-@pytest.mark.parametrize("mode", ["dense", "diag", "picard", "jacobi", "clip", "scale:0.5"])
+@pytest.mark.parametrize("mode", ["dense", "diag", "picard", "jacobi", "clip", "scale:0.5",
+                                  "diagscale:0.3", "clip:-0.5:0.8"])
 @pytest.mark.parametrize("kind", ["gru", "chaotic_tanh"])
 def test_at_most_T_iterations_and_prefix(mode, kind):
     rng = np.random.default_rng(15)
@@ -220,3 +221,34 @@ def test_reset_keeps_global_convergence():
     out = newton.newton(cell, x, s0, s_init=init, mode="dense", tol=1e-12)
     assert out["converged"] and out["iters"] <= T
     np.testing.assert_allclose(out["s"], rollout.rollout(cell, x, s0), atol=1e-12)
+
+
+# ---- damped transitions reduce to the undamped ones at their end points ------------------
+
+@pytest.mark.parametrize("kind", ["gru", "tanh"])
+def test_damping_end_points(kind):
+    """scale:0 is DEER and diagscale:0 quasi-DEER; scale:1, diagscale:1 and clip:0:0 are Jacobi;
+    clip with bounds wider than every diagonal entry is quasi-DEER (Sec. "Further extensions:
+    scale- and clip-ELK").  Compared by the matrices and by two iterates of the loop."""
+    rng = np.random.default_rng(16)
+    T = 30
+    cell = _gru(rng, 5, 3) if kind == "gru" else _tanh(rng, 5, 3, g=0.8)
+    x = rng.normal(size=(T, cell.Dx))
+    s0 = rng.normal(size=5)
+    h = np.concatenate([s0[None], rng.normal(size=(T - 1, 5))])
+    M = lambda m: newton.transition_matrices(cell, x, h, m)
+    np.testing.assert_array_equal(M("scale:0"), M("dense"))
+    np.testing.assert_array_equal(M("diagscale:0"), M("diag"))
+    for m in ("scale:1", "diagscale:1", "clip:0:0"):
+        np.testing.assert_array_equal(M(m), M("jacobi"))
+    d = np.abs(np.einsum("tii->ti", M("diag"))).max()
+    np.testing.assert_array_equal(M(f"clip:{-(d + 1)}:{d + 1}"), M("diag"))
+    # clip really clips: every entry inside the bounds, the off-diagonal zero
+    C = M("clip:-0.2:0.1")
+    dd = np.einsum("tii->ti", C)
+    assert dd.min() >= -0.2 and dd.max() <= 0.1
+    np.testing.assert_array_equal(C - np.einsum("ti,ij->tij", dd, np.eye(5)), 0.0)
+    for m, ref in (("diagscale:1", "jacobi"), ("scale:0", "dense")):
+        a = newton.newton(cell, x, s0, mode=m, tol=1e-14, max_iters=2)["s"]
+        b = newton.newton(cell, x, s0, mode=ref, tol=1e-14, max_iters=2)["s"]
+        np.testing.assert_array_equal(a, b)
