@@ -116,6 +116,9 @@ def main():
                     help="residual stopping tolerance (1e-6 keeps the error under 1e-5)")
     ap.add_argument("--seq-reps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--rows", action="store_true",
+                    help="also measure the other workloads and method variants (adds a 'rows' "
+                         "object to the line; a few minutes)")
     ap.add_argument("--graphs", action="store_true",
                     help="also time the step with graph-captured iterations (not the value)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -252,7 +255,135 @@ def main():
         rec["cpu_baseline"] = cpu["baseline"]
         rec["cpu_single_core"] = cpu["single_core"]
         rec["err"] = errors(cpu, s, gp, gx, g0, s_seq)
+    if args.rows:
+        rec["rows"] = measure_rows(torch, pn, workloads)
     print(json.dumps(rec), flush=True)
+
+
+def _timed(torch, fn, reps=3):
+    """Median wall time (ms) of fn() over reps calls after one warm-up call."""
+    out = fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts)), out
+
+
+def measure_rows(torch, pn, workloads):
+    """The other workloads and method variants: wall time per call, iterations, and the error
+    against the oracle's sequential rollout (or the FP64 residual where the trajectory is the
+    unique answer only up to FP32 round-off).  Inputs are seed 0 of each workload."""
+    from oracle import cells, rollout
+    rows = {}
+    dev = "cuda"
+
+    def tens(inst, dtype=torch.float32):
+        return tuple(torch.tensor(v, dtype=dtype, device=dev) for v in (inst.x, inst.s0, inst.params))
+
+    def rel(a, b):
+        return float(np.abs(a.detach().cpu().double().numpy() - b).max() / max(np.abs(b).max(), 1e-30))
+
+    # dense DEER, GRU D = 4, FP64 (one workgroup per sequence, whole loop on chip)
+    w = workloads.GRU4_DENSE_F64
+    inst = workloads.make_instance(w, seed=0)
+    x, s0, p = tens(inst, torch.float64)
+    ms, (s, info) = _timed(torch, lambda: pn.deer_solve(x, s0, p, cell="gru", offsets=inst.offsets,
+                                                        jac="dense", tol=w.tol))
+    ref = rollout.rollout_batch(cells.GRU(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
+    rows[w.name] = {"ms": round(ms, 3), "iters": [i["iters"] for i in info], "err": rel(s, ref),
+                    "steps_per_s": round(inst.N / (ms * 1e-3), 1)}
+
+    # dense DEER, tanh D = 32: BF16 and FP32 compose, vs the sequential GPU rollout
+    w = workloads.TANH32_DENSE_BF16
+    inst = workloads.make_instance(w, seed=0)
+    x, s0, p = tens(inst)
+    ref = rollout.rollout_batch(cells.TanhRNN(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
+    seq_ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="tanh", offsets=inst.offsets))
+    r = {"sequential_ms": round(seq_ms, 3), "sequential_err": rel(s_seq, ref)}
+    for comp in ("bf16", "native"):
+        ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
+            x, s0, p, cell="tanh", offsets=inst.offsets, jac="dense", compose=comp, tol=1e-6))
+        r[comp] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
+                   "err": rel(s, ref), "steps_per_s": round(inst.N / (ms * 1e-3), 1),
+                   "speedup_vs_sequential": round(seq_ms / ms, 2)}
+    ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
+        x, s0, p, cell="tanh", offsets=inst.offsets, jac="dense", tol=1e-6, damping="scale",
+        damp_k=0.2))
+    r["scale_elk_k0.2"] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
+                           "err": rel(s, ref)}
+    rows[w.name] = r
+
+    # ELK and quasi-ELK, tanh D = 16, FP64 stopping residual
+    w = workloads.TANH16_ELK
+    inst = workloads.make_instance(w, seed=0)
+    x, s0, p = tens(inst)
+    ref = rollout.rollout_batch(cells.TanhRNN(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
+    seq_ms, _ = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="tanh", offsets=inst.offsets))
+    r = {"sequential_ms": round(seq_ms, 3)}
+    for jac, name in (("dense", "elk"), ("diag", "quasi_elk")):
+        for lam in w.lambdas:
+            ms, (s, info) = _timed(torch, lambda: pn.elk_solve(
+                x, s0, p, lam, cell="tanh", offsets=inst.offsets, jac=jac, tol=w.tol,
+                fp64_final_residual=True), reps=1)
+            r[f"{name}_lambda{lam:g}"] = {
+                "ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
+                "converged": all(i["converged"] for i in info),
+                "max_resid_f64": max(i["max_resid"] for i in info), "err": rel(s, ref)}
+    rows[w.name] = r
+
+    # ragged GRU batch: forward + backward as the main line
+    w = workloads.GRU48_RAGGED
+    inst = workloads.make_instance(w, seed=0)
+    x, s0, p = tens(inst)
+    kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=1e-6)
+
+    def fb():
+        s, fi = pn.deer_solve(x, s0, p, **kw)
+        gp, gx, g0, bi = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw)
+        return s, fi, bi
+    ms, (s, fi, bi) = _timed(torch, fb, reps=2)
+
+    def seqfb():
+        s = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
+        pn.seq_bptt(x, s0, p, s, 2.0 * s, cell="gru", offsets=inst.offsets)
+        return s
+    seq_ms, _ = _timed(torch, seqfb, reps=1)
+    rows[w.name] = {"fwd_bwd_ms": round(ms, 3), "steps_per_s": round(inst.N / (ms * 1e-3), 1),
+                    "sequential_ms": round(seq_ms, 3), "speedup_vs_sequential": round(seq_ms / ms, 2),
+                    "iters_fwd_max": max(i["iters"] for i in fi),
+                    "iters_bwd_max": max(i["iters"] for i in bi), "N": int(inst.N)}
+
+    # transition variants on the GRU path (benchmark shapes, forward only)
+    w = workloads.GRU64_QUASI
+    inst = workloads.make_instance(w, seed=0)
+    x, s0, p = tens(inst)
+    ref = rollout.rollout_batch(cells.GRU(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
+    r = {}
+    for name, extra in (("quasi", {}), ("scale_k0.2", dict(damping="scale", damp_k=0.2)),
+                        ("clip", dict(damping="clip"))):
+        ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
+            x, s0, p, cell="gru", offsets=inst.offsets, jac="diag", tol=1e-6, **extra), reps=2)
+        r[name] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
+                   "err": rel(s, ref)}
+    rows["gru64 transitions"] = r
+
+    # Picard / Jacobi / quasi-DEER iteration counts (Table fxd_pt_sum) on a short GRU batch
+    w = workloads.GRU64_QUASI.scaled(B=16, T=512)
+    inst = workloads.make_instance(w, seed=0)
+    x, s0, p = tens(inst)
+    ref = rollout.rollout_batch(cells.GRU(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
+    r = {}
+    for jac in ("diag", "picard", "jacobi"):
+        ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
+            x, s0, p, cell="gru", offsets=inst.offsets, jac=jac, tol=1e-6), reps=1)
+        r[jac] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
+                  "converged": all(i["converged"] for i in info), "err": rel(s, ref)}
+    rows["gru64 T=512 fixed-point methods"] = r
+    return rows
 
 
 def _one_thread():

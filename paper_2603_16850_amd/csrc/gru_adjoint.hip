@@ -73,24 +73,6 @@ struct GruAdjArgs {
     float* gparams;
 };
 
-// Shared tile lookup: tile id -> (sequence, tile index from the sequence start, length).
-PN_DEV void tile_of(const GruAdjArgs& a, int tile, int L, bool reverse, int* b_out, int* lt_out,
-                    int* len_out) {
-    int lo = 0, hi = a.B;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.tile_start[mid] <= tile) lo = mid; else hi = mid;
-    }
-    const int b = lo;
-    const int nt_b = a.tile_start[b + 1] - a.tile_start[b];
-    int lt = tile - a.tile_start[b];
-    if (reverse) lt = nt_b - 1 - lt;
-    const int64_t len_seq = a.offsets[b + 1] - a.offsets[b];
-    *b_out = b;
-    *lt_out = lt;
-    *len_out = (int)std::min<int64_t>(L, len_seq - (int64_t)lt * L);
-}
-
 // ---- prep: gates at the solution, lambda^(0) = g, max |g| ---------------------------------
 template <int D, int DX, int L>
 __global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
@@ -105,11 +87,14 @@ gru_adj_prep_kernel(GruAdjArgs a) {
     const float* U = a.params + 3 * D * DX;
     const float dUz = U[(0 * D + j) * D + j], dUr = U[(1 * D + j) * D + j],
                 dUn = U[(2 * D + j) * D + j];
+    TileInfo tnext{};
+    if ((int)blockIdx.x < a.ntiles) tnext = a.tiles[blockIdx.x];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        int b, lt, len;
-        tile_of(a, tile, L, false, &b, &lt, &len);
-        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
-        const bool first = lt == 0;
+        const TileInfo ti = tnext;
+        if (tile + (int)gridDim.x < a.ntiles) tnext = a.tiles[tile + gridDim.x];   // read ahead
+        const int b = ti.b, len = ti.len;
+        const int64_t row0 = ti.row0;
+        const bool first = (ti.flags & kTileTimeFirst) != 0;
         __syncthreads();
         // stage row r <-> h of step t0 + r, and the x rows; all loads of a batch are issued
         // before its LDS writes
@@ -470,7 +455,8 @@ struct GradTiles {
     static constexpr int TOTAL = 3 * PER_GATE;
 };
 
-template <int D, int DX, int L>
+// L: steps per pass; the tile table has tiles of LT = SUB * L steps, each done in SUB passes.
+template <int D, int DX, int L, int SUB>
 __global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gru_adj_grad_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
@@ -496,12 +482,18 @@ gru_adj_grad_kernel(GruAdjArgs a) {
         wsm[r * WS + c] = c < DX ? W[r * DX + c] : 0.f;
     }
 
+    TileInfo tnext{};
+    if ((int)blockIdx.x < a.ntiles) tnext = a.tiles[blockIdx.x];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        int b, lt, len;
-        tile_of(a, tile, L, false, &b, &lt, &len);
-        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
-        const bool first = lt == 0;
-        const float* lam = a.lam[a.seq[b].parity];
+      const TileInfo ti = tnext;
+      if (tile + (int)gridDim.x < a.ntiles) tnext = a.tiles[tile + gridDim.x];   // read ahead
+      const int b = ti.b;
+      const float* lam = a.lam[a.seq[b].parity];
+      for (int sub = 0; sub < SUB; ++sub) {
+        const int len = min(L, ti.len - sub * L);
+        if (len <= 0) break;
+        const int64_t row0 = ti.row0 + (int64_t)sub * L;
+        const bool first = sub == 0 && (ti.flags & kTileTimeFirst) != 0;
         __syncthreads();
         // stage the delta rows [dz | dr | dq | dn] = (alpha, gamma, beta, eps) * lambda, the
         // h_{t-1} rows and the x rows; every load is issued before the LDS writes
@@ -612,6 +604,7 @@ gru_adj_grad_kernel(GruAdjArgs a) {
                 }
             }
         }
+      }
     }
     // write this workgroup's partials in the packed gradient layout
     constexpr int P = 3 * D * DX + 3 * D * D + 4 * D;
@@ -774,7 +767,7 @@ static GruAKernels gruA_get() {
     GruAKernels k;
     k.prep = gru_adj_prep_kernel<D, DX, kAdjL>;
     k.iter = gru_adj_local_kernel<D, DX, kAdjL>;
-    k.grad = gru_adj_grad_kernel<D, DX, kGradL>;
+    k.grad = gru_adj_grad_kernel<D, DX, kGradL, kAdjL / kGradL>;
     k.gs0 = gru_adj_gs0_kernel<D, DX>;
     k.nt = 64 * (D / 16);
     return k;
@@ -817,8 +810,6 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     }
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     const int ntiles = ts[hb.B];
-    const std::vector<int32_t> tsg = tile_starts(hb, kGradL);
-    const int ntiles_g = tsg[hb.B];
     int gt, resident;
     const int ngroups = gruA_groups(kk, ts, hb.B, &gt, &resident);
     GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, ngroups);
@@ -895,15 +886,10 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         set_error("device-side check failed in the adjoint iteration");
         return PN_ERR_INTERNAL;
     }
-    // gradients from the final adjoint iterate
-    GruAdjArgs gargs = args;
-    gargs.tile_start = lay.st.tile_start;
-    PN_HIP(hipMemcpyAsync(lay.st.tile_start, tsg.data(), sizeof(int32_t) * (hb.B + 1),
-                          hipMemcpyHostToDevice, stream));
-    gargs.ntiles = ntiles_g;
+    // gradients from the final adjoint iterate (the same tile table, two passes per tile)
     const int gg = grad_grid();
     prof_launch("gru_adj_grad", stream, [&](hipStream_t s2) {
-        hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, s2, gargs);
+        hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, s2, args);
     });
     PN_HIP(hipGetLastError());
     const int P = 3 * D * Dx + 3 * D * D + 4 * D;
@@ -937,7 +923,6 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     }
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     const int ntiles = ts[hb.B];
-    const std::vector<int32_t> tsg = tile_starts(hb, kGradL);
     GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, 0);
     PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, 1, 1.f, 1e4f, stream));
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
@@ -973,12 +958,8 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
                            lay.lam[0], (const int64_t*)lay.st.offsets);
     });
     PN_HIP(hipGetLastError());
-    PN_HIP(hipMemcpyAsync(lay.st.tile_start, tsg.data(), sizeof(int32_t) * (hb.B + 1),
-                          hipMemcpyHostToDevice, stream));
-    GruAdjArgs gargs = args;
-    gargs.ntiles = tsg[hb.B];
     const int gg = grad_grid();
-    hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, stream, gargs);
+    hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, stream, args);
     const int P = 3 * D * Dx + 3 * D * D + 4 * D;
     hipLaunchKernelGGL(gru_adj_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, stream,
                        (const float*)lay.part, gg, P, gparams);
