@@ -167,8 +167,9 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
 /* ELK (Ch. 4): each iteration replaces the Newton step by the filtered means of the LGSSM
    of Prop. prop:ELK with emission noise 1/lambda (lambda >= 0; lambda = 0 is DEER).  With
    PN_JAC_DIAG the LGSSM uses diag(A_t): quasi-ELK (Ch. 4, "quasi-ELK").
-   Built: TANH, PN_JAC_DENSE or PN_JAC_DIAG, F32, D = 16, Dx in {16}, no damping.  With
-   fp64_final_residual the stopping test of every iterate is evaluated in FP64 and the
+   Built: TANH, PN_JAC_DENSE or PN_JAC_DIAG, F32, D = 16, Dx in {16}, no damping; tile 0
+   (chosen from the shapes) or a multiple of 16 up to 1024: the steps one workgroup folds
+   into one filter element.  With fp64_final_residual the stopping test of every iterate is evaluated in FP64 and the
    reported max_resid is the FP64 residual of the returned FP32 iterate. */
 pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                     const void* s0, void* s, double lambda, const pn_opts* opts,

@@ -297,6 +297,10 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
         set_error("elk_solve damps through lambda; damping must be PN_DAMP_NONE");
         return PN_ERR_UNSUPPORTED;
     }
+    if (o.tile % 16 != 0 || o.tile > 1024) {
+        set_error("elk_solve tile must be 0 or a multiple of 16 up to 1024");
+        return PN_ERR_UNSUPPORTED;
+    }
     PN_TRY(check_ptrs({x, s0, s, cell->params}, hb));
     if (!(cell->cell == PN_CELL_TANH && cell->dtype == PN_F32 && elk_supported(cell->D, cell->Dx))) {
         set_error("elk_solve not built for cell=%d D=%d Dx=%d dtype=%d", cell->cell, cell->D,

@@ -3,20 +3,25 @@
 //   Delta_t = A_t Delta_{t-1} - r_t + w_t, w_t ~ N(0, I);   0 = Delta_t + v_t, v_t ~ N(0, I/lambda)
 // whose Kalman filter (Sec. "Dynamics perspective on ELK") is
 //   P- = A_t P A_t^T + I,  Gamma_t = (lambda P- + I)^-1,  P = Gamma_t P-,  m = Gamma_t (A_t m - r_t).
-// For the tanh-RNN (D = 16) A_t = diag(1 - f_t^2) W is rebuilt on chip from the iterate.
+// For the tanh-RNN (D = 16) A_t = diag(1 - f_t^2) W is rebuilt on chip from the iterate (its
+// diagonal only for quasi-ELK).
 //
-// The filter is parallelised over time as an associative scan of 5-tuple elements
-// (A, b, C, eta, J) -- the parallel Kalman filter the thesis cites (Ch. 2).  One single-wave
-// workgroup takes a chunk of L steps:
-//   1. linearise the chunk (FP32 MFMA GEMM for the pre-activations, residual, d_t);
-//   2. fold the chunk's leaves into its aggregate element (one 16x16 inverse and nine 16x16
-//      products per step, products on FP32 MFMA 16x16x4, the inverse by Gauss-Jordan with
-//      partial pivoting in LDS) and publish it;
-//   3. look back over the preceding chunks for the filtered (m, P) at the chunk boundary;
-//   4. run the exact filter over the chunk from that (m, P), write s + m (reset guard) and
-//      publish the chunk's final (m, P).
+// The filter is parallelised over time through 5-tuple elements (A, b, C, eta, J) -- the
+// parallel Kalman filter the thesis cites (Ch. 2) -- with the same two-pass structure as the
+// diagonal and dense DEER paths.  Steps are cut into chunks of 16 and the chunks of a sequence
+// into groups of consecutive chunks (see IterState).  Iteration k:
+//   local pass, one single-wave workgroup per group, chunk by chunk:
+//     1. (k >= 1) apply the previous step: re-linearise at s^(k-1) and run the exact filter
+//        from the filtered state (m, P) entering the group, s^(k) = s^(k-1) + m (reset guard);
+//     2. linearise at s^(k) (FP32 MFMA GEMM for the pre-activations, residual, d_t);
+//     3. fold the steps' leaves into the group's element (one 16x16 inverse and nine 16x16
+//        products per step, products on FP32 MFMA 16x16x4, the inverse by Gauss-Jordan with
+//        partial pivoting in LDS);
+//   carry pass, one workgroup per sequence: the filtered state entering every group, by
+//   applying the group elements in order from (m, P) = (0, 0).
 // lambda = 0 gives Gamma_t = I: the DEER step.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "pn_host.hpp"
@@ -27,9 +32,9 @@ namespace pn {
 constexpr int ED = 16;                 // state size
 constexpr int ES = 17;                 // LDS row stride of a 16x16 matrix
 constexpr int EM = ED * ES;            // floats per stored matrix
-constexpr int MW = ED * ED / 2;        // u64 words per published matrix
-constexpr int EAGG = 3 * MW + ED;      // A, C, J, b, eta
-constexpr int EINC = MW + ED / 2;      // P, m
+constexpr int EL = 16;                 // chunk length
+constexpr int EGEL = 3 * ED * ED + 2 * ED;   // group element: A, C, J (row-major), b, eta
+constexpr int ECAR = ED * ED + ED;           // filtered state: P (row-major), m
 
 // C = alpha * op(X) op(Y) + [Add] + addI * I (16x16, LDS, C may alias X, Y or Add)
 PN_DEV void mm16(float* C, const float* X, bool tx, const float* Y, bool ty, float alpha,
@@ -74,127 +79,106 @@ PN_DEV void mv16(float* y, const float* M, bool tm, const float* x, float alpha,
     __syncthreads();
 }
 
-// G = M^-1 by Gauss-Jordan with partial pivoting on [M | I] (aug: 16 x 33 floats).
-PN_DEV void inv16(float* G, const float* M, float* aug, float* fac) {
-    const int l = threadIdx.x & 63;
-    constexpr int AS = 33;
-    for (int idx = l; idx < ED * 32; idx += 64) {
-        const int r = idx / 32, c = idx % 32;
-        aug[r * AS + c] = c < ED ? M[r * ES + c] : (c - ED == r ? 1.f : 0.f);
-    }
-    __syncthreads();
-    for (int k = 0; k < ED; ++k) {
-        float v = (l < ED && l >= k) ? fabsf(aug[l * AS + k]) : -1.f;
-        int idx = l;
+// G = M^-1 (16x16 in LDS) by Gauss-Jordan with partial pivoting, held in registers: lane l
+// keeps row r = l & 15 of [M | I], columns 8q .. 8q + 7 (q = l >> 4).  Rows are not swapped:
+// the pivot of column k is the unused row of largest |entry| (found by a rotate-and-max over
+// each 16-lane row of the wave; ties and the last 4 mantissa bits go to the higher row), and
+// the row that pivoted column k ends holding row k of the inverse in its right half.
+PN_DEV void inv16(float* G, const float* M) {
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    float a[8];
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const float ov = __shfl_xor(v, off);
-            const int oi = __shfl_xor(idx, off);
-            if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-        }
-        const int p = __shfl(idx, 0);
-        if (p != k && l < 32) {
-            const float a0 = aug[k * AS + l], a1 = aug[p * AS + l];
-            aug[k * AS + l] = a1;
-            aug[p * AS + l] = a0;
-        }
-        __syncthreads();
-        if (l < ED) fac[l] = aug[l * AS + k];
-        __syncthreads();
-        const float inv = 1.f / fac[k];
-        if (l < 32) aug[k * AS + l] *= inv;
-        __syncthreads();
-        {
-            const int c = l & 31;
-            for (int r = l >> 5; r < ED; r += 2)
-                if (r != k) aug[r * AS + c] -= fac[r] * aug[k * AS + c];
-        }
-        __syncthreads();
+    for (int j = 0; j < 8; ++j) {
+        const int c = 8 * q + j;
+        a[j] = c < ED ? M[r * ES + c] : (c - ED == r ? 1.f : 0.f);
     }
-    for (int idx = l; idx < ED * ED; idx += 64) {
-        const int r = idx / ED, c = idx % ED;
-        G[r * ES + c] = aug[r * AS + ED + c];
+    bool used = false;
+    int myk = 0;
+#pragma unroll 2
+    for (int k = 0; k < ED; ++k) {
+        const int kq = k >> 3, kc = k & 7;
+        float ak = a[0];
+#pragma unroll
+        for (int j = 1; j < 8; ++j) ak = kc == j ? a[j] : ak;
+        uint32_t key = used ? 0u
+                            : ((max(__float_as_uint(fabsf(ak)), 0x10u) & ~0xFu) | (uint32_t)r);
+        key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x121, 0xF, 0xF, false));
+        key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x122, 0xF, 0xF, false));
+        key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x124, 0xF, 0xF, false));
+        key = max(key, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x128, 0xF, 0xF, false));
+        const int p = __builtin_amdgcn_readlane((int)key, 16 * kq) & 15;
+        const float piv = __int_as_float(
+            __builtin_amdgcn_readlane(__float_as_int(ak), 16 * kq + p));
+        const float fk = __int_as_float(
+            __builtin_amdgcn_ds_bpermute((r + 16 * kq) << 2, __float_as_int(ak)));
+        float prow[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            prow[j] = __int_as_float(
+                __builtin_amdgcn_ds_bpermute((16 * q + p) << 2, __float_as_int(a[j])));
+        const float inv = 1.f / piv;
+        const float g = -fk * inv;
+        const bool me = r == p;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = me ? a[j] * inv : fmaf(g, prow[j], a[j]);
+        if (me) { used = true; myk = k; }
+    }
+    if (q >= 2) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) G[myk * ES + 8 * (q - 2) + j] = a[j];
     }
     __syncthreads();
 }
 
-PN_DEV void publish_mat(uint64_t* dst, const float* M) {
+PN_DEV void store_mat(float* dst, const float* M) {       // LDS (stride ES) -> row-major
     const int l = threadIdx.x & 63;
-    for (int w = l; w < MW; w += 64) {
-        const int r = w / 8, c = 2 * (w % 8);
-        st_u64(&dst[w], pack2(M[r * ES + c], M[r * ES + c + 1]));
-    }
+    for (int w = l; w < ED * ED; w += 64) dst[w] = M[(w / ED) * ES + w % ED];
 }
-PN_DEV void publish_vec(uint64_t* dst, const float* v) {
+PN_DEV void fetch_mat(float* M, const float* src) {       // row-major -> LDS (stride ES)
     const int l = threadIdx.x & 63;
-    if (l < ED / 2) st_u64(&dst[l], pack2(v[2 * l], v[2 * l + 1]));
-}
-PN_DEV void load_mat(float* M, const uint64_t* src) {
-    const int l = threadIdx.x & 63;
-    for (int w = l; w < MW; w += 64) {
-        const uint64_t v = ld_u64(&src[w]);
-        const int r = w / 8, c = 2 * (w % 8);
-        M[r * ES + c] = lo_of(v);
-        M[r * ES + c + 1] = hi_of(v);
-    }
-}
-PN_DEV void load_vec(float* x, const uint64_t* src) {
-    const int l = threadIdx.x & 63;
-    if (l < ED / 2) {
-        const uint64_t v = ld_u64(&src[l]);
-        x[2 * l] = lo_of(v);
-        x[2 * l + 1] = hi_of(v);
-    }
-}
-PN_DEV bool words_ready(const uint64_t* src, int n) {
-    const int l = threadIdx.x & 63;
-    bool ok = true;
-    for (int w = l; w < n; w += 64) ok = ok && ready64(ld_u64(&src[w]));
-    return __all(ok);
+    for (int w = l; w < ED * ED; w += 64) M[(w / ED) * ES + w % ED] = src[w];
 }
 
 struct ElkArgs {
     const float* x;
     const float* s0;
-    float* sbuf[2];
+    float* sbuf[2];          // ping-pong iterates: s^(k) lives in sbuf[k & 1]
     const float* params;     // W (16x16) | U (16xDx) | b (16)
-    uint64_t* agg[2];
-    uint64_t* incl[2];
+    float* gel;              // [ngroups][EGEL] group elements of this iteration
+    const float* gcar;       // [ngroups][ECAR] filtered state entering every group (previous)
     Ctrl* ctrl;
     SeqState* seq;
-    const int64_t* offsets;
-    const int32_t* tile_start;
-    const int32_t* order;
-    int B;
-    int ntiles;
+    const TileInfo* tiles;   // by slot (chunks)
+    const GroupInfo* groups;
+    int ngroups;
     float lam;
     int res64;               // nonzero: the stopping residual is evaluated in FP64
     int diag;                // nonzero: quasi-ELK, the LGSSM uses diag(A_t)
 };
 
-template <int DX, int L>
-__global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
+template <int DX>
+__global__ void __launch_bounds__(64) elk_local_kernel(ElkArgs a) {
+    constexpr int L = EL;
     constexpr int KT = ED + DX;
     constexpr int SS = ED + 4, XS = DX + 4;
-    static_assert(L % 16 == 0 && KT % 4 == 0, "shape");
+    static_assert(KT % 4 == 0, "shape");
     __shared__ __attribute__((aligned(16))) float sst[(L + 1) * SS];
     __shared__ __attribute__((aligned(16))) float xst[L * XS];
     __shared__ float dsh[L * ED], rsh[L * ED];
     __shared__ float Wm[EM], Ai[EM], Ci[EM], Ji[EM], At[EM], Jj[EM], Gm[EM], T1[EM], T2[EM];
-    __shared__ float aug[ED * 33];
-    __shared__ float fac[ED];
-    __shared__ float bi[ED], ei[ED], vx[ED], vy[ED], vz[ED];
-    __shared__ int tinfo[5];
+    __shared__ float Pr[EM];                  // replay: filtered covariance
+    __shared__ float bi[ED], ei[ED], vx[ED], vy[ED], vz[ED], mr[ED];
+    __shared__ int badrow[L + 1];
 
     if (ld_i32(&a.ctrl->all_done)) return;
     const int k_it = a.ctrl->iter;
-    const int par = k_it & 1;
+    const bool fuse = k_it > 0;
     const float reset_abs = a.ctrl->reset_abs;
     const float lam = a.lam;
     const float s1 = 1.f / (1.f + lam);           // 1 / (1 + lambda)
     const float kap = lam / (1.f + lam);         // kappa
-    const float* __restrict__ sin = a.sbuf[par];
-    float* __restrict__ sout = a.sbuf[par ^ 1];
+    const float* __restrict__ sprev = a.sbuf[(k_it + 1) & 1];   // s^(k-1)
+    float* __restrict__ scur = a.sbuf[k_it & 1];                 // s^(k)
     const int l = threadIdx.x, g = l >> 4, u = l & 15;
 
     const float* W = a.params;
@@ -209,126 +193,166 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
     }
     const float bias_u = bvec[u];
 
-    for (;;) {
-        __syncthreads();
-        if (l == 0) {
-            const int idx = (int)atomicAdd(&a.ctrl->tile_counter, 1u);
-            tinfo[0] = idx;
-            if (idx < a.ntiles) {
-                const int slot = a.order[idx];
-                int lo = 0, hi = a.B;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (a.tile_start[mid] <= slot) lo = mid; else hi = mid;
-                }
-                const int lt = slot - a.tile_start[lo];
-                tinfo[1] = lo;
-                tinfo[2] = lt;
-                tinfo[3] = (a.seq[lo].status == kActive)
-                               ? (int)std::min<int64_t>(L, a.offsets[lo + 1] - a.offsets[lo] - (int64_t)lt * L)
-                               : -1;
-                tinfo[4] = slot;
-            }
-        }
-        __syncthreads();
-        if (tinfo[0] >= a.ntiles) break;
-        const int tile = tinfo[4];
-        const int b = tinfo[1], lt = tinfo[2], len = tinfo[3];
-        if (len < 0) continue;
-        const bool first = lt == 0;
-        const int64_t row0 = a.offsets[b] + (int64_t)lt * L;
-        for (int w = l; w < EAGG; w += 64) st_u64(&a.agg[par ^ 1][(size_t)tile * EAGG + w], kSent64);
-        for (int w = l; w < EINC; w += 64) st_u64(&a.incl[par ^ 1][(size_t)tile * EINC + w], kSent64);
-
-        // ---- stage and linearise
-        for (int idx = l; idx < (L + 1) * (ED / 4); idx += 64) {
-            const int r = idx / (ED / 4), c4 = idx % (ED / 4);
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r == 0) v = first ? *(const float4*)(a.s0 + (size_t)b * ED + 4 * c4)
-                                  : *(const float4*)(sin + (size_t)(row0 - 1) * ED + 4 * c4);
-            else if (r - 1 < len) v = *(const float4*)(sin + (size_t)(row0 + r - 1) * ED + 4 * c4);
-            *(float4*)(sst + r * SS + 4 * c4) = v;
-        }
-        for (int idx = l; idx < L * (DX / 4); idx += 64) {
-            const int r = idx / (DX / 4), c4 = idx % (DX / 4);
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
-            *(float4*)(xst + r * XS + 4 * c4) = v;
-        }
-        __syncthreads();
-        uint32_t rmax = 0;
+    // residual, d_t of the staged rows (FP64 stopping residual when asked for)
+    auto linearise = [&](bool first, int len, bool track) -> uint32_t {
+        uint32_t rm = 0;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int mb = 0; mb < L / 16; ++mb) {
-            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < KT / 4; ++kb) {
-                const int kk = 4 * kb + g, tr = mb * 16 + u;
-                const float av = kk < ED ? sst[tr * SS + kk] : xst[tr * XS + (kk - ED)];
-                acc = mfma16x4(av, blin[kb], acc);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int t = mb * 16 + 4 * g + i;
-                const float f = tanhf_(acc[i] + bias_u);
-                const float res = sst[(t + 1) * SS + u] - f;
-                dsh[t * ED + u] = (first && t == 0) ? 0.f : 1.f - f * f;
-                rsh[t * ED + u] = res;
-                if (t < len && !a.res64) rmax = max(rmax, absbits(res));
-            }
+        for (int kb = 0; kb < KT / 4; ++kb) {
+            const int kk = 4 * kb + g;
+            const float av = kk < ED ? sst[u * SS + kk] : xst[u * XS + (kk - ED)];
+            acc = mfma16x4(av, blin[kb], acc);
         }
-        if (a.res64) {
-            // The stopping test of this iterate in FP64: s, x and the parameters upcast, the
-            // same quantity the final FP64 residual reports.  The FP32 residual above still
-            // drives the update; its rounding (~1e-7 here) would otherwise let an iterate
-            // pass a 1e-6 test that it fails in FP64.  The bound is rounded up to FP32.
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = 4 * g + i;
+            const float f = tanhf_(acc[i] + bias_u);
+            const float res = sst[(t + 1) * SS + u] - f;
+            dsh[t * ED + u] = (first && t == 0) ? 0.f : 1.f - f * f;
+            rsh[t * ED + u] = res;
+            if (track && t < len && !a.res64) rm = max(rm, absbits(res));
+        }
+        if (track && a.res64) {
+            // The stopping test in FP64: s, x and the parameters upcast, the quantity the final
+            // FP64 residual reports.  The FP32 residual still drives the update; its rounding
+            // (~1e-7 here) would otherwise let an iterate pass a 1e-6 test it fails in FP64.
+            // The bound is rounded up to FP32.
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int t = 4 * g + i;
-                for (int tt = t; tt < L && tt < len; tt += 16) {
-                    double acc = (double)bias_u;
+                if (t < len) {
+                    double acc64 = (double)bias_u;
                     for (int kk = 0; kk < ED; ++kk)
-                        acc += (double)Wm[u * ES + kk] * (double)sst[tt * SS + kk];
+                        acc64 += (double)Wm[u * ES + kk] * (double)sst[t * SS + kk];
                     for (int kk = 0; kk < DX; ++kk)
-                        acc += (double)U[u * DX + kk] * (double)xst[tt * XS + kk];
-                    const double r = (double)sst[(tt + 1) * SS + u] - tanh(acc);
+                        acc64 += (double)U[u * DX + kk] * (double)xst[t * XS + kk];
+                    const double r = (double)sst[(t + 1) * SS + u] - tanh(acc64);
                     const double ar = fabs(r);
                     float fr = (float)ar;
                     if ((double)fr < ar) fr = nextafterf(fr, INFINITY);
-                    rmax = max(rmax, (r == r) ? absbits(fr) : 0x7F800000u);
+                    rm = max(rm, (r == r) ? absbits(fr) : 0x7F800000u);
                 }
             }
         }
         __syncthreads();
+        return rm;
+    };
+    auto build_At = [&](int t) {
+        for (int idx = l; idx < ED * ED; idx += 64) {
+            const int r = idx / ED, c = idx % ED;
+            At[r * ES + c] = (a.diag && r != c) ? 0.f : dsh[t * ED + r] * Wm[r * ES + c];
+        }
+        __syncthreads();
+    };
 
-        auto build_At = [&](int t) {
-            for (int idx = l; idx < ED * ED; idx += 64) {
-                const int r = idx / ED, c = idx % ED;
-                At[r * ES + c] = (a.diag && r != c) ? 0.f : dsh[t * ED + r] * Wm[r * ES + c];
-            }
+    for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+        const GroupInfo gr = a.groups[gi];
+        if (a.seq[gr.b].status != kActive) continue;
+        const int b = gr.b;
+        uint32_t rmax = 0;
+        int nreset = 0;
+        bool have = false;                       // the group's element holds at least one step
+        if (fuse) {                              // filtered state entering the group
+            const float* cr = a.gcar + (size_t)gi * ECAR;
+            fetch_mat(Pr, cr);
+            if (l < ED) mr[l] = cr[ED * ED + l];
+        }
+        for (int kt = 0; kt < gr.ntl; ++kt) {
+            const TileInfo ti = a.tiles[gr.tile0 + kt];
+            const int len = ti.len;
+            const int64_t row0 = ti.row0;
+            const bool first = (ti.flags & kTileTimeFirst) != 0;
             __syncthreads();
-        };
+            // ---- stage s_{t-1}, s_t (of s^(k-1), or the guess s^(0)) and x_t
+            const float* src = fuse ? sprev : scur;
+            for (int idx = l; idx < (L + 1) * (ED / 4); idx += 64) {
+                const int r = idx / (ED / 4), c4 = idx % (ED / 4);
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r == 0) v = first ? *(const float4*)(a.s0 + (size_t)b * ED + 4 * c4)
+                                      : *(const float4*)(src + (size_t)(row0 - 1) * ED + 4 * c4);
+                else if (r - 1 < len) v = *(const float4*)(src + (size_t)(row0 + r - 1) * ED + 4 * c4);
+                *(float4*)(sst + r * SS + 4 * c4) = v;
+            }
+            for (int idx = l; idx < L * (DX / 4); idx += 64) {
+                const int r = idx / (DX / 4), c4 = idx % (DX / 4);
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+                *(float4*)(xst + r * XS + 4 * c4) = v;
+            }
+            if (l <= L) badrow[l] = 0;
+            __syncthreads();
 
-        // ---- fold the chunk into its aggregate element and publish it
-        if (!first) {
-            // leaf of the chunk's first step
-            build_At(0);
-            for (int idx = l; idx < ED * ED; idx += 64) {
-                const int r = idx / ED, c = idx % ED;
-                Ai[r * ES + c] = s1 * At[r * ES + c];
-                Ci[r * ES + c] = (r == c) ? s1 : 0.f;
+            if (fuse) {
+                // ---- the previous iteration's step: the exact filter from the entering (m, P)
+                linearise(first, len, false);
+                float hv = 0.f;
+                if (!first && l < ED) {
+                    hv = sst[l] + mr[l];               // s^(k) of the row before the chunk
+                    if (!(fabsf(hv) <= reset_abs)) badrow[0] = 1;
+                }
+                for (int t = 0; t < len; ++t) {
+                    build_At(t);
+                    mm16(T1, At, false, Pr, false, 1.f, nullptr, 0.f);        // A P
+                    mm16(T2, T1, false, At, true, 1.f, nullptr, 1.f);         // P- = A P A^T + I
+                    for (int idx = l; idx < ED * ED; idx += 64) {
+                        const int r = idx / ED, c = idx % ED;
+                        Jj[r * ES + c] = lam * T2[r * ES + c] + (r == c ? 1.f : 0.f);
+                    }
+                    __syncthreads();
+                    inv16(Gm, Jj);                                  // Gamma
+                    mm16(Pr, Gm, false, T2, false, 1.f, nullptr, 0.f);        // P = Gamma P-
+                    for (int idx = l; idx < ED * ED; idx += 64) {              // symmetrise
+                        const int r = idx / ED, c = idx % ED;
+                        if (r < c) {
+                            const float v = 0.5f * (Pr[r * ES + c] + Pr[c * ES + r]);
+                            Pr[r * ES + c] = v;
+                            Pr[c * ES + r] = v;
+                        }
+                    }
+                    if (l < ED) vx[l] = -rsh[t * ED + l];
+                    __syncthreads();
+                    mv16(vy, At, false, mr, 1.f, vx, 1.f);                    // A m - r
+                    mv16(mr, Gm, false, vy, 1.f, nullptr, 0.f);               // m = Gamma (.)
+                    const float v = l < ED ? sst[(t + 1) * SS + l] + mr[l] : 0.f;
+                    const bool rb = __any(l < ED && !(fabsf(v) <= reset_abs));
+                    if (l < ED) sst[(t + 1) * SS + l] = rb ? 0.f : v;
+                    nreset += rb ? 1 : 0;
+                    __syncthreads();
+                }
+                if (!first && l < ED) sst[l] = badrow[0] ? 0.f : hv;
+                __syncthreads();
+                for (int idx = l; idx < len * (ED / 4); idx += 64) {
+                    const int r = idx / (ED / 4), c4 = idx % (ED / 4);
+                    *(float4*)(scur + (size_t)(row0 + r) * ED + 4 * c4) =
+                        *(const float4*)(sst + (r + 1) * SS + 4 * c4);
+                }
             }
-            if (l < ED) { bi[l] = -s1 * rsh[l]; vx[l] = rsh[l]; }
-            __syncthreads();
-            mv16(ei, At, true, vx, kap, nullptr, 0.f);            // eta = kappa A^T r
-            mm16(Ji, At, true, At, false, kap, nullptr, 0.f);     // J = kappa A^T A
-            for (int t = 1; t < len; ++t) {
+
+            // ---- linearise at s^(k), then fold the chunk's leaves into the group's element
+            rmax = max(rmax, linearise(first, len, true));
+            for (int t = 0; t < len; ++t) {
                 build_At(t);
                 if (l < ED) vx[l] = rsh[t * ED + l];
                 __syncthreads();
+                if (!have) {
+                    // leaf (A/(1+lambda), -r/(1+lambda), I/(1+lambda), kappa A^T r, kappa A^T A);
+                    // at a sequence head A = 0, which folds in the prior Delta_0 = 0
+                    for (int idx = l; idx < ED * ED; idx += 64) {
+                        const int r = idx / ED, c = idx % ED;
+                        Ai[r * ES + c] = s1 * At[r * ES + c];
+                        Ci[r * ES + c] = (r == c) ? s1 : 0.f;
+                    }
+                    if (l < ED) bi[l] = -s1 * vx[l];
+                    __syncthreads();
+                    mv16(ei, At, true, vx, kap, nullptr, 0.f);            // eta = kappa A^T r
+                    mm16(Ji, At, true, At, false, kap, nullptr, 0.f);     // J = kappa A^T A
+                    have = true;
+                    continue;
+                }
                 mm16(Jj, At, true, At, false, kap, nullptr, 0.f);     // J_j
                 mv16(vy, At, true, vx, kap, nullptr, 0.f);            // eta_j
                 mm16(T1, Ci, false, Jj, false, 1.f, nullptr, 1.f);    // I + C_i J_j
-                inv16(Gm, T1, aug, fac);                              // G
+                inv16(Gm, T1);                              // G
                 mm16(T2, At, false, Gm, false, s1, nullptr, 0.f);     // A_j G
                 // eta, J use the old A_i
                 mv16(vz, Jj, false, bi, -1.f, vy, 1.f);               // eta_j - J_j b_i
@@ -343,86 +367,16 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
                 mm16(Ci, T1, false, At, true, s1, nullptr, s1);       // C = (.) A_j^T + C_j
                 mm16(Ai, T2, false, Ai, false, 1.f, nullptr, 0.f);    // A = A_j G A_i
             }
-            uint64_t* ag = a.agg[par] + (size_t)tile * EAGG;
-            publish_mat(ag, Ai);
-            publish_mat(ag + MW, Ci);
-            publish_mat(ag + 2 * MW, Ji);
-            publish_vec(ag + 3 * MW, bi);
-            publish_vec(ag + 3 * MW + ED / 2, ei);
         }
-
-        // ---- filtered state (m, P) at the chunk boundary: Ci <- P, bi <- m
-        for (int idx = l; idx < ED * ED; idx += 64) Ci[(idx / ED) * ES + idx % ED] = 0.f;
-        if (l < ED) bi[l] = 0.f;
-        __syncthreads();
-        if (!first) {
-            int pred = tile - 1, spins = 0;
-            for (;;) {
-                if (words_ready(a.incl[par] + (size_t)pred * EINC, EINC)) break;
-                if (words_ready(a.agg[par] + (size_t)pred * EAGG, EAGG)) { --pred; continue; }
-                if (++spins > (1 << 20) || ld_i32(&a.ctrl->error)) { if (l == 0) atomicExch(&a.ctrl->error, 1); break; }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            load_mat(Ci, a.incl[par] + (size_t)pred * EINC);
-            load_vec(bi, a.incl[par] + (size_t)pred * EINC + MW);
-            __syncthreads();
-            for (int p2 = pred + 1; p2 < tile; ++p2) {
-                const uint64_t* ag = a.agg[par] + (size_t)p2 * EAGG;
-                load_mat(Ai, ag);
-                load_mat(T2, ag + MW);       // C_p
-                load_mat(Jj, ag + 2 * MW);   // J_p
-                load_vec(vx, ag + 3 * MW);   // b_p
-                load_vec(vy, ag + 3 * MW + ED / 2);  // eta_p
-                __syncthreads();
-                mm16(T1, Ci, false, Jj, false, 1.f, nullptr, 1.f);    // I + P J_p
-                inv16(Gm, T1, aug, fac);
-                mm16(T1, Ai, false, Gm, false, 1.f, nullptr, 0.f);    // A_p G
-                mv16(vz, Ci, false, vy, 1.f, bi, 1.f);                // m + P eta_p
-                mv16(bi, T1, false, vz, 1.f, vx, 1.f);                // m' = A_p G (.) + b_p
-                mm16(Gm, T1, false, Ci, false, 1.f, nullptr, 0.f);    // A_p G P
-                mm16(Ci, Gm, false, Ai, true, 1.f, T2, 0.f);          // P' = (.) A_p^T + C_p
-            }
+        // ---- the group's element
+        float* ge = a.gel + (size_t)gi * EGEL;
+        store_mat(ge, Ai);
+        store_mat(ge + ED * ED, Ci);
+        store_mat(ge + 2 * ED * ED, Ji);
+        if (l < ED) {
+            ge[3 * ED * ED + l] = bi[l];
+            ge[3 * ED * ED + ED + l] = ei[l];
         }
-
-        // ---- exact filter over the chunk from (m, P); write s + m; publish (m, P)
-        int nreset = 0;
-        for (int t = 0; t < len; ++t) {
-            build_At(t);
-            mm16(T1, At, false, Ci, false, 1.f, nullptr, 0.f);        // A P
-            mm16(T2, T1, false, At, true, 1.f, nullptr, 1.f);         // P- = A P A^T + I
-            mm16(T1, T2, false, T2, false, 0.f, T2, 0.f);             // copy P- (alpha 0 + add)
-            for (int idx = l; idx < ED * ED; idx += 64) {
-                const int r = idx / ED, c = idx % ED;
-                Jj[r * ES + c] = lam * T2[r * ES + c] + (r == c ? 1.f : 0.f);   // lambda P- + I
-            }
-            __syncthreads();
-            inv16(Gm, Jj, aug, fac);                                  // Gamma
-            mm16(Ci, Gm, false, T1, false, 1.f, nullptr, 0.f);        // P = Gamma P-
-            for (int idx = l; idx < ED * ED; idx += 64) {              // symmetrise
-                const int r = idx / ED, c = idx % ED;
-                if (r < c) {
-                    const float v = 0.5f * (Ci[r * ES + c] + Ci[c * ES + r]);
-                    Ci[r * ES + c] = v;
-                    Ci[c * ES + r] = v;
-                }
-            }
-            __syncthreads();
-            if (l < ED) vx[l] = -rsh[t * ED + l];
-            __syncthreads();
-            mv16(vy, At, false, bi, 1.f, vx, 1.f);                    // A m - r
-            mv16(bi, Gm, false, vy, 1.f, nullptr, 0.f);               // m = Gamma (.)
-            if (l < ED) {
-                const float v = sst[(t + 1) * SS + l] + bi[l];
-                vz[l] = v;
-            }
-            __syncthreads();
-            const bool bad = (l < ED) && !(fabsf(vz[l]) <= reset_abs);
-            const bool rowbad = __any(bad);
-            if (l < ED) sout[(size_t)(row0 + t) * ED + l] = rowbad ? 0.f : vz[l];
-            nreset += rowbad ? 1 : 0;
-        }
-        publish_mat(a.incl[par] + (size_t)tile * EINC, Ci);
-        publish_vec(a.incl[par] + (size_t)tile * EINC + MW, bi);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) {
@@ -432,26 +386,83 @@ __global__ void __launch_bounds__(64) elk_iter_kernel(ElkArgs a) {
     }
 }
 
-// ---- host ---------------------------------------------------------------------------------------
+// ---- carry pass: the filtered state entering every group ------------------------------------
+// One single-wave workgroup per sequence: (m, P) = (0, 0) before the first group; a group's
+// element maps it on by  G = (I + P J)^-1,  m' = A G (m + P eta) + b,  P' = A G P A^T + C.
+// The next group's element is fetched into registers while the current one is applied.
+__global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__ gel,
+                                                       float* __restrict__ gcar,
+                                                       const Ctrl* ctrl, const SeqState* seq,
+                                                       const int32_t* group_start, int B) {
+    __shared__ float Ae[EM], Ce[EM], Je[EM], P[EM], T1[EM], Gm[EM];
+    __shared__ float be[ED], ee[ED], m[ED], vz[ED];
+    if (ld_i32(&ctrl->all_done)) return;
+    const int b = blockIdx.x;
+    if (b >= B || seq[b].status != kActive) return;
+    const int l = threadIdx.x;
+    const int g0 = group_start[b], G = group_start[b + 1] - g0;
+    constexpr int PER = (EGEL + 63) / 64;
+    float nxt[PER];
+    auto prefetch = [&](int gg) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int w = l + 64 * i;
+            nxt[i] = (gg < G && w < EGEL) ? gel[(size_t)(g0 + gg) * EGEL + w] : 0.f;
+        }
+    };
+    for (int idx = l; idx < EM; idx += 64) P[idx] = 0.f;
+    if (l < ED) m[l] = 0.f;
+    prefetch(0);
+    __syncthreads();
+    for (int gg = 0; gg < G; ++gg) {
+        // carry into group gg
+        float* cr = gcar + (size_t)(g0 + gg) * ECAR;
+        store_mat(cr, P);
+        if (l < ED) cr[ED * ED + l] = m[l];
+        // this group's element into LDS, the next one into registers
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int w = l + 64 * i;
+            if (w < 3 * ED * ED) {
+                float* M = w < ED * ED ? Ae : (w < 2 * ED * ED ? Ce : Je);
+                const int v = w % (ED * ED);
+                M[(v / ED) * ES + v % ED] = nxt[i];
+            } else if (w < 3 * ED * ED + ED) {
+                be[w - 3 * ED * ED] = nxt[i];
+            } else if (w < EGEL) {
+                ee[w - 3 * ED * ED - ED] = nxt[i];
+            }
+        }
+        prefetch(gg + 1);
+        __syncthreads();
+        mm16(T1, P, false, Je, false, 1.f, nullptr, 1.f);     // I + P J
+        inv16(Gm, T1);                              // G
+        mm16(T1, Ae, false, Gm, false, 1.f, nullptr, 0.f);    // A G
+        mv16(vz, P, false, ee, 1.f, m, 1.f);                  // m + P eta
+        mv16(m, T1, false, vz, 1.f, be, 1.f);                 // m' = A G (.) + b
+        mm16(Gm, T1, false, P, false, 1.f, nullptr, 0.f);     // A G P
+        mm16(P, Gm, false, Ae, true, 1.f, Ce, 0.f);           // P' = (.) A^T + C
+    }
+}
 
-constexpr int kElkL = 16;
+// ---- host ---------------------------------------------------------------------------------------
 
 struct ElkLayout {
     IterState st;
     float* salt;
-    uint64_t* agg[2];
-    uint64_t* incl[2];
+    float* gel;
+    float* gcar;
     char* r64;
     size_t bytes;
 };
 
-static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles) {
+static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngroups) {
     Carver c(ws);
     ElkLayout lay;
-    carve_iter_state(c, lay.st, hb.B, ntiles);
+    carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.salt = c.take<float>((size_t)hb.N * ED);
-    for (int p = 0; p < 2; ++p) lay.agg[p] = c.take<uint64_t>((size_t)ntiles * EAGG);
-    for (int p = 0; p < 2; ++p) lay.incl[p] = c.take<uint64_t>((size_t)ntiles * EINC);
+    lay.gel = c.take<float>((size_t)std::max(ngroups, 1) * EGEL);
+    lay.gcar = c.take<float>((size_t)std::max(ngroups, 1) * ECAR);
     lay.r64 = c.take<char>(residual64_workspace(PN_CELL_TANH, ED, 16, hb));   // FP64 residual
     lay.bytes = c.bytes();
     return lay;
@@ -459,14 +470,39 @@ static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles) {
 
 bool elk_supported(int D, int Dx) { return D == ED && Dx == 16; }
 
-size_t elk_workspace(int, int, const HostBatch& hb, const pn_opts&) {
-    return elk_layout(nullptr, hb, tile_starts(hb, kElkL)[hb.B]).bytes;
+static int elk_resident() {
+    int occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)elk_local_kernel<16>, 64, 0) !=
+            hipSuccess || occ < 1)
+        occ = 1;
+    return cu_count() * occ;
 }
 
-__global__ void elk_fill_kernel(uint64_t* p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        p[i] = kSent64;
+// Chunks per group.  An explicit tile (a multiple of 16 steps) fixes it.  Otherwise a cost
+// model picks it: the local pass takes rounds * gt chunks of latency (rounds = groups per
+// resident workgroup), the carry pass one element application per group of the longest
+// sequence; a chunk of the local pass (replay and fold) costs about kLocalPerCarry carry steps.
+static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, int tile) {
+    if (tile > 0) return tile / EL;
+    constexpr double kLocalPerCarry = 36.0;
+    const int resident = elk_resident();
+    int maxc = 0;
+    for (int b = 0; b < hb.B; ++b) maxc = std::max(maxc, ts[b + 1] - ts[b]);
+    int best = 1;
+    double best_cost = 1e300;
+    for (int gt = 1; gt <= 64; gt *= 2) {
+        const int ng = count_groups(ts, hb.B, gt);
+        const double rounds = std::ceil((double)ng / resident);
+        const double cost = rounds * gt * kLocalPerCarry + std::ceil((double)maxc / gt);
+        if (cost < best_cost) { best_cost = cost; best = gt; }
+    }
+    return best;
+}
+
+size_t elk_workspace(int, int, const HostBatch& hb, const pn_opts& o) {
+    const std::vector<int32_t> ts = tile_starts(hb, EL);
+    const int gt = elk_group_tiles(hb, ts, o.tile);
+    return elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt)).bytes;
 }
 
 pn_status residual64_device(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
@@ -476,66 +512,61 @@ pn_status residual64_device(const pn_cell_desc& cd, const HostBatch& hb, const f
 pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
                       const float* s0, float* s, double lambda, const pn_opts& o, void* ws,
                       hipStream_t stream, pn_seq_info* info, bool* all_conv) {
-    void (*kern)(ElkArgs) = elk_iter_kernel<16, kElkL>;
-    const std::vector<int32_t> ts = tile_starts(hb, kElkL);
+    void (*kern)(ElkArgs) = elk_local_kernel<16>;
+    const std::vector<int32_t> ts = tile_starts(hb, EL);
     const int ntiles = ts[hb.B];
-    ElkLayout lay = elk_layout(ws, hb, ntiles);
+    const int resident = elk_resident();
+    const int gt = elk_group_tiles(hb, ts, o.tile);
+    const int ngroups = count_groups(ts, hb.B, gt);
+    ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
-    PN_TRY(init_iter_state(lay.st, hb, ts, kElkL, false, max_iters, (float)o.tol,
-                           (float)o.reset_abs, stream));
-    if (ntiles > 0) {
-        const size_t na = (size_t)ntiles * EAGG, ni = (size_t)ntiles * EINC;
-        hipLaunchKernelGGL(elk_fill_kernel, dim3((unsigned)std::min<size_t>(4096, (na + 255) / 256)),
-                           dim3(256), 0, stream, lay.agg[0], na);
-        hipLaunchKernelGGL(elk_fill_kernel, dim3((unsigned)std::min<size_t>(4096, (ni + 255) / 256)),
-                           dim3(256), 0, stream, lay.incl[0], ni);
-        PN_HIP(hipGetLastError());
-    }
-    int occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, 64, 0) != hipSuccess || occ < 1)
-        occ = 1;
-    const int grid = std::max(1, std::min(ntiles, cu_count() * occ));
+    PN_TRY(init_iter_state(lay.st, hb, ts, EL, false, max_iters, (float)o.tol,
+                           (float)o.reset_abs, stream, gt));
+    const int grid = std::max(1, std::min(ngroups, resident));
     ElkArgs args;
     args.x = x;
     args.s0 = s0;
     args.sbuf[0] = s;
     args.sbuf[1] = lay.salt;
     args.params = (const float*)cd.params;
-    for (int p = 0; p < 2; ++p) { args.agg[p] = lay.agg[p]; args.incl[p] = lay.incl[p]; }
+    args.gel = lay.gel;
+    args.gcar = lay.gcar;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
-    args.offsets = lay.st.offsets;
-    args.tile_start = lay.st.tile_start;
-    args.order = lay.st.order;
-    args.B = hb.B;
-    args.ntiles = ntiles;
+    args.tiles = lay.st.tiles;
+    args.groups = lay.st.groups;
+    args.ngroups = ngroups;
     args.lam = (float)lambda;
     args.res64 = o.fp64_final_residual ? 1 : 0;
     args.diag = o.jac == PN_JAC_DIAG ? 1 : 0;
     auto one_iter = [&](hipStream_t st) {
-        prof_launch("elk_iter", st, [&](hipStream_t s2) {
+        prof_launch("elk_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
         });
-        launch_decide(lay.st, hb.B, st);
+        prof_launch("elk_carry", st, [&](hipStream_t s2) {
+            hipLaunchKernelGGL(elk_carry_kernel, dim3(std::max(1, hb.B)), dim3(64), 0, s2,
+                               (const float*)lay.gel, lay.gcar, (const Ctrl*)lay.st.ctrl,
+                               (const SeqState*)lay.st.seq, (const int32_t*)lay.st.group_start,
+                               hb.B);
+        });
+        launch_decide(lay.st, hb.B, st, true);
     };
-    uint32_t lam_bits = 0;
-    std::memcpy(&lam_bits, &args.lam, sizeof lam_bits);
-    std::vector<uintptr_t> key = {0x454Cu, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
+    std::vector<uintptr_t> key = {0x454Du, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
                                   (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
-                                  (uintptr_t)lam_bits, (uintptr_t)args.res64,
-                                  (uintptr_t)args.diag};
+                                  (uintptr_t)ngroups, float_bits(args.lam),
+                                  (uintptr_t)args.res64, (uintptr_t)args.diag};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;
     PN_TRY(finish_iterations(lay.st, hb, ED, sizeof(float), s, lay.salt, stream, info, all_conv,
                              &derr));
     if (derr) {
-        set_error("look-back watchdog expired in the ELK scan");
+        set_error("device-side check failed in the ELK iteration");
         return PN_ERR_INTERNAL;
     }
     if (o.fp64_final_residual && info) {
-        // the reported residual is the FP64 one; the stopping test is re-checked in FP64
+        // the reported residual is the FP64 one of the returned iterate
         std::vector<double> r64(hb.B);
         PN_TRY(residual64_device(cd, hb, x, s0, s, lay.r64, stream, r64.data()));
         bool allc = true;

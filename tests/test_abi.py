@@ -165,6 +165,10 @@ def test_damping_routes(lib):
     o = pn.make_opts(jac="picard")
     assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
                          ctypes.byref(o), None, 0, None, None) == -2
+    for tile in (8, 24, 2048):          # ELK groups whole 16-step chunks, at most 64 of them
+        o = pn.make_opts(jac="dense", tile=tile)
+        assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
+                             ctypes.byref(o), None, 0, None, None) == -2
     # quasi-ELK and scale damping on the tanh dense path are built: they fail only later,
     # on the missing workspace
     o = pn.make_opts(jac="diag")

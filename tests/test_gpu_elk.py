@@ -48,6 +48,24 @@ def test_iterates_match_sequential_filter(lib, lam):
                 assert np.abs(s[a:e] - dn["s"]).max() < 2e-5
 
 
+@pytest.mark.parametrize("tile,jac", [(16, "dense"), (48, "dense"), (128, "dense"),
+                                      (64, "diag"), (0, "dense")])
+def test_grouped_iterates_match_sequential_filter(lib, tile, jac):
+    """Groups of several 16-step chunks (tile = steps per group; 0 = chosen from the shapes),
+    with ragged tails: the group elements, the carry pass and the replay from the carried
+    filter state give the sequential filter's iterates after 1, 2 and 3 iterations."""
+    w = workloads.TANH16_ELK.scaled(B=4, T=0)
+    inst = workloads.make_instance(w, seed=35, lengths=np.array([413, 16, 129, 200]))
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    for k in (1, 2, 3):
+        s, info = _elk(lib, inst, 0.05, tol=1e-12, max_iters=k, jac=jac, tile=tile)
+        for b in range(4):
+            a, e = inst.offsets[b], inst.offsets[b + 1]
+            out = elk.elk(cell, inst.x[a:e], inst.s0[b], 0.05, mode=jac, tol=1e-12,
+                          max_iters=k)
+            assert np.abs(s[a:e] - out["s"]).max() < 2e-5, (tile, k, b)
+
+
 def test_multichunk_converges_to_rollout(lib):
     w = workloads.TANH16_ELK.scaled(B=2, T=0)
     inst = workloads.make_instance(w, seed=32, lengths=np.array([300, 77]))
