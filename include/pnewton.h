@@ -124,7 +124,10 @@ typedef struct {
     float damp_k;             /* PN_DAMP_SCALE: k                                            */
     float clip_lo;            /* PN_DAMP_CLIP: bounds                                        */
     float clip_hi;
-    int32_t reserved[3];
+    int32_t freeze_prefix;    /* elk_solve: 1 = stop updating each sequence's converged prefix
+                                 (whole groups of `tile` steps whose residual is below tol,
+                                 counted from the start; the filter restarts after them) */
+    int32_t reserved[2];
 } pn_opts;
 
 typedef struct {

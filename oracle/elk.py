@@ -58,9 +58,10 @@ def filter_step(At, r, lam):
 
 def elk(cell, x, s0, lam, mode="dense", **kw):
     """The Newton loop of ``oracle.newton`` with its step replaced by the ELK filter."""
-    def step(cell_, x_, h, r):
+    def step(cell_, x_, h, r, t0):
+        # the filter runs on steps t0.. from m = 0, P = 0 (t0 > 0: a frozen prefix)
         At = _newton.transition_matrices(cell_, x_, h, mode)
-        return filter_step(At, r, lam)[0]
+        return filter_step(At[t0:], r[t0:], lam)[0]
     return _newton.newton(cell, x, s0, step=step, **kw)
 
 

@@ -19,6 +19,13 @@ Each iteration, for the current guess s^(i):
      trained AR-GRU experiment of Ch. 4): any time-step vector that is non-finite or has an
      entry larger than ``reset_abs`` in magnitude is set to zero.
 
+Converged-prefix skipping (``freeze`` = a block length in steps, optional): convergence is
+causal (the induction in the proof of Prop. prop:global_convergence), so after step 2 the
+leading blocks of ``freeze`` steps whose residual is below tol are frozen: the step is
+taken as exactly zero there, and steps 3-5 run on the rest of the sequence only, with
+Delta = 0 entering it (the solve restarts at the first open block, like a sequence head).
+Frozen states never change again, so their residuals stay below tol.
+
 The iteration count is the number of updates applied; the result is returned as soon as
 the stopping test passes on the current iterate.  By Prop. prop:global_convergence the
 loop ends within T updates for every choice of A~_t (exact arithmetic).
@@ -92,9 +99,24 @@ def apply_reset(s, reset_abs):
     return int(bad.sum())
 
 
+def frozen_prefix(r, block, tol):
+    """Start of the open part: ``block`` times the number of leading blocks of ``block``
+    steps whose max |r| is below tol (NaN is not below)."""
+    T = r.shape[0]
+    t0 = 0
+    while t0 < T:
+        with np.errstate(invalid="ignore"):
+            ok = bool(np.max(np.abs(r[t0:t0 + block])) < tol)
+        if not ok:
+            break
+        t0 += block
+    return min(t0, T)
+
+
 def newton(cell, x, s0, s_init=None, mode="dense", tol=1e-10, max_iters=None,
-           reset_abs=1e4, stop="resid", step=None, history=False):
-    """Run the loop on one sequence.  ``step`` replaces step 4 (used by ELK).
+           reset_abs=1e4, stop="resid", step=None, history=False, freeze=0):
+    """Run the loop on one sequence.  ``step(cell, x, h, r, t0)`` replaces steps 3-4 on
+    steps t0.. (used by ELK); ``freeze`` > 0 turns on converged-prefix skipping.
 
     Returns a dict: s, iters, converged, resets, max_resid, and optionally the list of
     iterates (``history``, s^(0) first) and residual norms.
@@ -118,8 +140,13 @@ def newton(cell, x, s0, s_init=None, mode="dense", tol=1e-10, max_iters=None,
         if i >= max_iters:
             return dict(s=s, iters=i, converged=False, resets=resets, max_resid=rn,
                         history=hist, resid_norms=norms)
-        At = transition_matrices(cell, x, h, mode) if step is None else None
-        delta = forward_substitution(At, r) if step is None else step(cell, x, h, r)
+        t0 = frozen_prefix(r, int(freeze), tol) if freeze else 0
+        delta = np.zeros_like(s)
+        if step is None:
+            At = transition_matrices(cell, x, h, mode)
+            delta[t0:] = forward_substitution(At[t0:], r[t0:])
+        else:
+            delta[t0:] = step(cell, x, h, r, t0)
         with np.errstate(invalid="ignore", over="ignore"):
             s = s + delta
         resets += apply_reset(s, reset_abs)

@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("damping", ctypes.c_int32), ("damp_k", ctypes.c_float),
                 ("clip_lo", ctypes.c_float), ("clip_hi", ctypes.c_float),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("freeze_prefix", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class SeqInfo(ctypes.Structure):
@@ -144,7 +144,7 @@ DAMPING = {"none": 0, "scale": 1, "clip": 2}
 
 def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4,
               reset_abs=1e4, fp64_final_residual=False, use_graph=True, tile=0,
-              damping="none", damp_k=0.0, clip=(-1.0, 1.0)):
+              damping="none", damp_k=0.0, clip=(-1.0, 1.0), freeze_prefix=False):
     """pn_opts; damping "scale" (scale-ELK, A~ <- (1 - damp_k) A~) or "clip" (clip-ELK,
     diagonal A~ clipped to `clip`)."""
     o = Opts()
@@ -161,6 +161,7 @@ def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4
     o.fp64_final_residual = int(bool(fp64_final_residual))
     o.use_graph = int(bool(use_graph))
     o.tile = int(tile)
+    o.freeze_prefix = int(bool(freeze_prefix))
     return o
 
 

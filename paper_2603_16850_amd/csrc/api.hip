@@ -85,6 +85,10 @@ pn_status check_opts(const pn_opts& o) {
     }
     if (!(o.tol > 0) || !std::isfinite(o.tol)) { set_error("tol must be positive and finite"); return PN_ERR_INVALID_ARG; }
     if (o.tile < 0) { set_error("tile must be >= 0"); return PN_ERR_INVALID_ARG; }
+    if (o.freeze_prefix != 0 && o.freeze_prefix != 1) {
+        set_error("freeze_prefix must be 0 or 1");
+        return PN_ERR_INVALID_ARG;
+    }
     if (o.damping < PN_DAMP_NONE || o.damping > PN_DAMP_CLIP) {
         set_error("unknown damping %d", o.damping);
         return PN_ERR_INVALID_ARG;
@@ -250,6 +254,10 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
     PN_TRY(check_opts(o));
     PN_TRY(check_ptrs({x, s0, s, cell->params}, hb));
     const Route r = route_deer(*cell, o);
+    if (o.freeze_prefix) {
+        set_error("converged-prefix skipping is built for elk_solve only");
+        return PN_ERR_UNSUPPORTED;
+    }
     if (r == Route::None) {
         set_error("deer_solve not built for cell=%d D=%d Dx=%d dtype=%d jac=%d compose=%d",
                   cell->cell, cell->D, cell->Dx, cell->dtype, o.jac, o.compose);
@@ -330,6 +338,10 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
     if ((gx && !aligned16(gx)) || (gs0 && !aligned16(gs0)) || !aligned16(gparams)) {
         set_error("gradient arrays must be 16-byte aligned");
         return PN_ERR_INVALID_ARG;
+    }
+    if (o.freeze_prefix) {
+        set_error("converged-prefix skipping is built for elk_solve only");
+        return PN_ERR_UNSUPPORTED;
     }
     if (!(cell->cell == PN_CELL_GRU && cell->dtype == PN_F32 && o.jac == PN_JAC_DIAG &&
           gru_quasi_supported(cell->D, cell->Dx))) {

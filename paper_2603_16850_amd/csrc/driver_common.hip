@@ -140,6 +140,8 @@ __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offs
         q.parity = 0;
         q.maxr = 0;
         q.final_resid = 0.0f;
+        q.frozen = 0;
+        q.frozen_prev = 0;
         q.pad_ = 0;
         seq[b] = q;
     }

@@ -19,6 +19,11 @@
 //        partial pivoting in LDS);
 //   carry pass, one workgroup per sequence: the filtered state entering every group, by
 //   applying the group elements in order from (m, P) = (0, 0).
+// Converged-prefix skipping (optional; convergence is causal, Prop. global_convergence): the
+// carry pass also finds the sequence's leading groups whose residual is below tol.  Those are
+// frozen: the step there is taken as exactly zero, so the filter restarts after them from
+// (m, P) = (0, 0), the next local pass copies each newly frozen group once into the other
+// iterate buffer, and later passes skip it.
 // lambda = 0 gives Gamma_t = I: the DEER step.
 #include <algorithm>
 #include <cmath>
@@ -150,7 +155,10 @@ struct ElkArgs {
     SeqState* seq;
     const TileInfo* tiles;   // by slot (chunks)
     const GroupInfo* groups;
+    const int32_t* group_start;
+    uint32_t* grmax;         // [ngroups] residual bound of every group's latest iterate (bits)
     int ngroups;
+    int freeze;              // converged-prefix skipping
     float lam;
     int res64;               // nonzero: the stopping residual is evaluated in FP64
     int diag;                // nonzero: quasi-ELK, the LGSSM uses diag(A_t)
@@ -249,6 +257,22 @@ __global__ void __launch_bounds__(64) elk_local_kernel(ElkArgs a) {
         const GroupInfo gr = a.groups[gi];
         if (a.seq[gr.b].status != kActive) continue;
         const int b = gr.b;
+        if (a.freeze) {
+            const int gg = gi - a.group_start[b];
+            if (gg < a.seq[b].frozen_prev) continue;            // frozen, both buffers hold it
+            if (gg < a.seq[b].frozen) {                         // frozen by the last carry pass
+                if (fuse) {
+                    for (int kt = 0; kt < gr.ntl; ++kt) {
+                        const TileInfo ti = a.tiles[gr.tile0 + kt];
+                        for (int idx = l; idx < ti.len * (ED / 4); idx += 64) {
+                            const size_t o = (size_t)ti.row0 * ED + 4 * idx;
+                            *(float4*)(scur + o) = *(const float4*)(sprev + o);
+                        }
+                    }
+                }
+                continue;
+            }
+        }
         uint32_t rmax = 0;
         int nreset = 0;
         bool have = false;                       // the group's element holds at least one step
@@ -380,6 +404,7 @@ __global__ void __launch_bounds__(64) elk_local_kernel(ElkArgs a) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) {
+            a.grmax[gi] = rmax;
             atomicMax(&a.seq[b].maxr, rmax);
             if (nreset) atomicAdd(&a.seq[b].resets_pending, nreset);
         }
@@ -392,8 +417,10 @@ __global__ void __launch_bounds__(64) elk_local_kernel(ElkArgs a) {
 // The next group's element is fetched into registers while the current one is applied.
 __global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__ gel,
                                                        float* __restrict__ gcar,
-                                                       const Ctrl* ctrl, const SeqState* seq,
-                                                       const int32_t* group_start, int B) {
+                                                       const Ctrl* ctrl, SeqState* seq,
+                                                       const int32_t* group_start,
+                                                       const uint32_t* grmax, int freeze,
+                                                       int B) {
     __shared__ float Ae[EM], Ce[EM], Je[EM], P[EM], T1[EM], Gm[EM];
     __shared__ float be[ED], ee[ED], m[ED], vz[ED];
     if (ld_i32(&ctrl->all_done)) return;
@@ -401,6 +428,27 @@ __global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__
     if (b >= B || seq[b].status != kActive) return;
     const int l = threadIdx.x;
     const int g0 = group_start[b], G = group_start[b + 1] - g0;
+    int gstart = 0;                      // first group the step is taken on
+    if (freeze) {
+        // leading groups whose residual bound is below tol (NaN bounds are not)
+        const uint32_t tolb = __float_as_uint(ctrl->tol);
+        int fz = G;
+        for (int base = 0; base < G; base += 64) {
+            const bool open = base + l < G && !(grmax[g0 + base + l] < tolb);
+            const uint64_t m = __ballot(open);
+            if (m) {
+                fz = base + __ffsll((unsigned long long)m) - 1;
+                break;
+            }
+        }
+        const int old = seq[b].frozen;
+        gstart = max(fz, old);
+        __syncthreads();
+        if (l == 0) {
+            seq[b].frozen_prev = old;
+            seq[b].frozen = gstart;
+        }
+    }
     constexpr int PER = (EGEL + 63) / 64;
     float nxt[PER];
     auto prefetch = [&](int gg) {
@@ -412,9 +460,9 @@ __global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__
     };
     for (int idx = l; idx < EM; idx += 64) P[idx] = 0.f;
     if (l < ED) m[l] = 0.f;
-    prefetch(0);
+    prefetch(gstart);
     __syncthreads();
-    for (int gg = 0; gg < G; ++gg) {
+    for (int gg = gstart; gg < G; ++gg) {
         // carry into group gg
         float* cr = gcar + (size_t)(g0 + gg) * ECAR;
         store_mat(cr, P);
@@ -452,6 +500,7 @@ struct ElkLayout {
     float* salt;
     float* gel;
     float* gcar;
+    uint32_t* grmax;
     char* r64;
     size_t bytes;
 };
@@ -463,6 +512,7 @@ static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngrou
     lay.salt = c.take<float>((size_t)hb.N * ED);
     lay.gel = c.take<float>((size_t)std::max(ngroups, 1) * EGEL);
     lay.gcar = c.take<float>((size_t)std::max(ngroups, 1) * ECAR);
+    lay.grmax = c.take<uint32_t>((size_t)std::max(ngroups, 1));
     lay.r64 = c.take<char>(residual64_workspace(PN_CELL_TANH, ED, 16, hb));   // FP64 residual
     lay.bytes = c.bytes();
     return lay;
@@ -535,7 +585,10 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.seq = lay.st.seq;
     args.tiles = lay.st.tiles;
     args.groups = lay.st.groups;
+    args.group_start = lay.st.group_start;
+    args.grmax = lay.grmax;
     args.ngroups = ngroups;
+    args.freeze = o.freeze_prefix ? 1 : 0;
     args.lam = (float)lambda;
     args.res64 = o.fp64_final_residual ? 1 : 0;
     args.diag = o.jac == PN_JAC_DIAG ? 1 : 0;
@@ -546,8 +599,8 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         prof_launch("elk_carry", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(elk_carry_kernel, dim3(std::max(1, hb.B)), dim3(64), 0, s2,
                                (const float*)lay.gel, lay.gcar, (const Ctrl*)lay.st.ctrl,
-                               (const SeqState*)lay.st.seq, (const int32_t*)lay.st.group_start,
-                               hb.B);
+                               lay.st.seq, (const int32_t*)lay.st.group_start,
+                               (const uint32_t*)lay.grmax, args.freeze, hb.B);
         });
         launch_decide(lay.st, hb.B, st, true);
     };
@@ -555,7 +608,8 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
                                   (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
                                   (uintptr_t)ngroups, float_bits(args.lam),
-                                  (uintptr_t)args.res64, (uintptr_t)args.diag};
+                                  (uintptr_t)args.res64, (uintptr_t)args.diag,
+                                  (uintptr_t)args.freeze};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;

@@ -33,6 +33,8 @@ struct SeqState {
     int parity;         // which ping-pong buffer holds the final iterate
     uint32_t maxr;      // running max |r| of the current iterate (float bits, >= 0)
     float final_resid;  // max |r| of the final iterate
+    int frozen;         // converged-prefix skipping: groups of the sequence frozen so far
+    int frozen_prev;    // ... and before the latest update of `frozen`
     int pad_;
 };
 

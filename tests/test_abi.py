@@ -165,6 +165,14 @@ def test_damping_routes(lib):
     o = pn.make_opts(jac="picard")
     assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
                          ctypes.byref(o), None, 0, None, None) == -2
+    o = pn.make_opts(jac="diag")
+    o.freeze_prefix = 2
+    assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
+                         ctypes.byref(o), None, 0, None, None) == -1
+    o = pn.make_opts(jac="diag", freeze_prefix=True)   # converged-prefix skipping: ELK only
+    c2, b2, _ = _desc(D=64, Dx=32)
+    assert lib.deer_solve(ctypes.byref(c2), ctypes.byref(b2), *args, ctypes.byref(o), None, 0,
+                          None, None) == -2
     for tile in (8, 24, 2048):          # ELK groups whole 16-step chunks, at most 64 of them
         o = pn.make_opts(jac="dense", tile=tile)
         assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),

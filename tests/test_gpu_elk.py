@@ -150,3 +150,65 @@ def test_quasi_elk_full_size(lib, lam):
     assert max(i["max_resid"] for i in info) < w.tol
     ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
     assert _rel(s, ref) < 5e-5
+
+
+def _safe_iters(cell, inst, lam, jac, tol, tile):
+    """Oracle iterates with converged-prefix skipping, and the iterations whose freeze
+    decisions all lie at least 3% away from tol (FP32 and FP64 residuals then agree on
+    them): the parity comparison is made on those."""
+    hist, last, events = [], 10 ** 9, 0
+    for b in range(inst.offsets.size - 1):
+        a, e = inst.offsets[b], inst.offsets[b + 1]
+        out = elk.elk(cell, inst.x[a:e], inst.s0[b], lam, mode=jac, tol=tol,
+                      history=True, freeze=tile)
+        hist.append(out["history"])
+        for i, s in enumerate(out["history"]):
+            _, r = newton.linearize(cell, inst.x[a:e], inst.s0[b], s)
+            t0 = newton.frozen_prefix(r, tile, tol)
+            margin = min(abs(np.log(np.abs(r[j:j + tile]).max() / tol))
+                         for j in range(0, r.shape[0], tile))
+            if margin < 0.03:
+                last = min(last, i)
+                break
+            events += 0 < t0 < r.shape[0]
+    return hist, last, events
+
+
+@pytest.mark.parametrize("lam,jac,tile,tol", [(0.0, "dense", 16, 1e-3),
+                                              (0.05, "dense", 48, 1e-3),
+                                              (0.05, "diag", 32, 1.2e-3)])
+def test_freeze_prefix_iterates_match_oracle(lib, lam, jac, tile, tol):
+    """Converged-prefix skipping: per-iteration iterates equal the oracle's loop with the
+    same block length (tile) while the freeze decisions are unambiguous in FP32; the bar is
+    2e-5 relative to max(1, max |s|)."""
+    w = workloads.TANH16_ELK.scaled(B=3, T=0)
+    inst = workloads.make_instance(w, seed=36, lengths=np.array([300, 77, 160]))
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    hist, last, events = _safe_iters(cell, inst, lam, jac, tol, tile)
+    nmax = max(len(h) for h in hist) - 1
+    ks = [k for k in range(1, nmax + 1) if k <= last]
+    assert events > 0 and ks, (events, last)
+    for k in ks:
+        s, info = _elk(lib, inst, lam, tol=tol, max_iters=k, jac=jac, tile=tile,
+                       freeze_prefix=True)
+        for b in range(3):
+            a, e = inst.offsets[b], inst.offsets[b + 1]
+            ref = hist[b][min(k, len(hist[b]) - 1)]
+            # early DEER iterates of this unstable system reach |s| ~ 15: FP32 error there
+            # scales with the magnitude
+            assert np.abs(s[a:e] - ref).max() < 2e-5 * max(1.0, np.abs(ref).max()), (k, b)
+            assert info[b]["iters"] == min(k, len(hist[b]) - 1)
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1.0])
+def test_freeze_prefix_full_size(lib, lam):
+    """Full size with converged-prefix skipping: FP64 residual below tol = 1e-6 and the
+    trajectory within the bar of test_full_size."""
+    w = workloads.TANH16_ELK
+    inst = workloads.make_instance(w, seed=0)
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    s, info = _elk(lib, inst, lam, tol=w.tol, fp64_final_residual=True, freeze_prefix=True)
+    assert all(i["converged"] for i in info), [i["iters"] for i in info]
+    assert max(i["max_resid"] for i in info) < w.tol
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    assert _rel(s, ref) < 5e-5
