@@ -56,11 +56,57 @@ def filter_step(At, r, lam):
     return delta, covs, gammas
 
 
-def elk(cell, x, s0, lam, mode="dense", **kw):
-    """The Newton loop of ``oracle.newton`` with its step replaced by the ELK filter."""
+def smoother_step(At, r, lam):
+    """The exact Levenberg-Marquardt step: the posterior mode of the same LGSSM (Prop.
+    prop:ELK), by the Kalman filter followed by the Rauch-Tung-Striebel backward pass
+    (Sec. "Bayesian inference for linear Gaussian SSMs"):
+        E_t = P_t A~_{t+1}^T (P-_{t+1})^-1,   m^s_t = m_t + E_t (m^s_{t+1} - m-_{t+1}),
+    with m^s_T = m_T.  The means alone are needed, so the smoothed covariances are not formed.
+    Returns Delta [T, D]."""
+    T, D = r.shape
+    eye = np.eye(D)
+    m = np.zeros(D)
+    P = np.zeros((D, D))
+    ms, Ps, mp, Pp = (np.empty((T, D)), np.empty((T, D, D)), np.empty((T, D)),
+                      np.empty((T, D, D)))
+    with np.errstate(over="ignore", invalid="ignore"):
+        for t in range(T):                                   # filter, keeping the predictions
+            A = At[t] if t > 0 else np.zeros((D, D))
+            mp[t] = A @ m - r[t]
+            Pp[t] = A @ P @ A.T + eye
+            G = np.linalg.inv(lam * Pp[t] + eye)
+            m = G @ mp[t]
+            P = G @ Pp[t]
+            P = 0.5 * (P + P.T)
+            ms[t], Ps[t] = m, P
+        out = np.empty((T, D))
+        if T:
+            out[T - 1] = ms[T - 1]
+        for t in range(T - 2, -1, -1):                       # backward pass
+            E = Ps[t] @ At[t + 1].T @ np.linalg.inv(Pp[t + 1])
+            out[t] = ms[t] + E @ (out[t + 1] - mp[t + 1])
+    return out
+
+
+def lm_step_dense(At, r, lam):
+    """The same step by its definition: -(J^T J + lambda I)^-1 J^T r with the block
+    bidiagonal Jacobian of the residual (identity blocks on the diagonal, -A~_t below)."""
+    T, D = r.shape
+    J = np.eye(T * D)
+    for t in range(1, T):
+        J[t * D:(t + 1) * D, (t - 1) * D:t * D] = -At[t]
+    rhs = -J.T @ r.reshape(-1)
+    return np.linalg.solve(J.T @ J + lam * np.eye(T * D), rhs).reshape(T, D)
+
+
+def elk(cell, x, s0, lam, mode="dense", smoother=False, **kw):
+    """The Newton loop of ``oracle.newton`` with its step replaced by the ELK filter (or,
+    with ``smoother``, by the exact LM step)."""
     def step(cell_, x_, h, r, t0):
-        # the filter runs on steps t0.. from m = 0, P = 0 (t0 > 0: a frozen prefix)
+        # the step runs on steps t0.. from m = 0, P = 0 (t0 > 0: a frozen prefix)
         At = _newton.transition_matrices(cell_, x_, h, mode)
+        if smoother:
+            return smoother_step(At[t0:], r[t0:], lam)
         return filter_step(At[t0:], r[t0:], lam)[0]
     return _newton.newton(cell, x, s0, step=step, **kw)
 
