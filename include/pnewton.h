@@ -127,7 +127,10 @@ typedef struct {
     int32_t freeze_prefix;    /* elk_solve: 1 = stop updating each sequence's converged prefix
                                  (whole groups of `tile` steps whose residual is below tol,
                                  counted from the start; the filter restarts after them) */
-    int32_t reserved[2];
+    int32_t smooth;           /* elk_solve: 1 = take the smoothed means (the exact LM step of
+                                 Prop. ELK, Kalman filter plus RTS backward pass); 0 = the
+                                 filtered means                                            */
+    int32_t reserved[1];
 } pn_opts;
 
 typedef struct {

@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("damping", ctypes.c_int32), ("damp_k", ctypes.c_float),
                 ("clip_lo", ctypes.c_float), ("clip_hi", ctypes.c_float),
-                ("freeze_prefix", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("freeze_prefix", ctypes.c_int32), ("smooth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class SeqInfo(ctypes.Structure):
@@ -144,7 +145,8 @@ DAMPING = {"none": 0, "scale": 1, "clip": 2}
 
 def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4,
               reset_abs=1e4, fp64_final_residual=False, use_graph=True, tile=0,
-              damping="none", damp_k=0.0, clip=(-1.0, 1.0), freeze_prefix=False):
+              damping="none", damp_k=0.0, clip=(-1.0, 1.0), freeze_prefix=False,
+              smooth=False):
     """pn_opts; damping "scale" (scale-ELK, A~ <- (1 - damp_k) A~) or "clip" (clip-ELK,
     diagonal A~ clipped to `clip`)."""
     o = Opts()
@@ -162,6 +164,7 @@ def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4
     o.use_graph = int(bool(use_graph))
     o.tile = int(tile)
     o.freeze_prefix = int(bool(freeze_prefix))
+    o.smooth = int(bool(smooth))
     return o
 
 

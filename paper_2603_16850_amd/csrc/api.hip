@@ -89,6 +89,10 @@ pn_status check_opts(const pn_opts& o) {
         set_error("freeze_prefix must be 0 or 1");
         return PN_ERR_INVALID_ARG;
     }
+    if (o.smooth != 0 && o.smooth != 1) {
+        set_error("smooth must be 0 or 1");
+        return PN_ERR_INVALID_ARG;
+    }
     if (o.damping < PN_DAMP_NONE || o.damping > PN_DAMP_CLIP) {
         set_error("unknown damping %d", o.damping);
         return PN_ERR_INVALID_ARG;
@@ -254,8 +258,8 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
     PN_TRY(check_opts(o));
     PN_TRY(check_ptrs({x, s0, s, cell->params}, hb));
     const Route r = route_deer(*cell, o);
-    if (o.freeze_prefix) {
-        set_error("converged-prefix skipping is built for elk_solve only");
+    if (o.freeze_prefix || o.smooth) {
+        set_error("converged-prefix skipping and the smoother are built for elk_solve only");
         return PN_ERR_UNSUPPORTED;
     }
     if (r == Route::None) {
@@ -305,6 +309,10 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
         set_error("elk_solve damps through lambda; damping must be PN_DAMP_NONE");
         return PN_ERR_UNSUPPORTED;
     }
+    if (o.smooth && o.freeze_prefix) {
+        set_error("the smoother does not combine with converged-prefix skipping");
+        return PN_ERR_UNSUPPORTED;
+    }
     if (o.tile % 16 != 0 || o.tile > 1024) {
         set_error("elk_solve tile must be 0 or a multiple of 16 up to 1024");
         return PN_ERR_UNSUPPORTED;
@@ -339,8 +347,8 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
         set_error("gradient arrays must be 16-byte aligned");
         return PN_ERR_INVALID_ARG;
     }
-    if (o.freeze_prefix) {
-        set_error("converged-prefix skipping is built for elk_solve only");
+    if (o.freeze_prefix || o.smooth) {
+        set_error("converged-prefix skipping and the smoother are built for elk_solve only");
         return PN_ERR_UNSUPPORTED;
     }
     if (!(cell->cell == PN_CELL_GRU && cell->dtype == PN_F32 && o.jac == PN_JAC_DIAG &&

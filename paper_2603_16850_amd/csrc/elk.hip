@@ -144,6 +144,111 @@ PN_DEV void fetch_mat(float* M, const float* src) {       // row-major -> LDS (s
     for (int w = l; w < ED * ED; w += 64) M[(w / ED) * ES + w % ED] = src[w];
 }
 
+// ---- staging and linearisation of one chunk (at most 16 steps), shared by the passes ---------
+
+// sst rows 0..len: s_{row0-1} (s_0 at a sequence head), then s_{row0} .. s_{row0+len-1} of the
+// iterate `src` (zero rows past len); xst rows: x_{row0} .. (zero past len)
+template <int DX>
+PN_DEV void elk_stage(float* sst, float* xst, const float* __restrict__ src,
+                      const float* __restrict__ s0, const float* __restrict__ x, int b,
+                      int64_t row0, int len, bool first) {
+    constexpr int SS = ED + 4, XS = DX + 4;
+    const int l = threadIdx.x & 63;
+    for (int idx = l; idx < (EL + 1) * (ED / 4); idx += 64) {
+        const int r = idx / (ED / 4), c4 = idx % (ED / 4);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r == 0) v = first ? *(const float4*)(s0 + (size_t)b * ED + 4 * c4)
+                              : *(const float4*)(src + (size_t)(row0 - 1) * ED + 4 * c4);
+        else if (r - 1 < len) v = *(const float4*)(src + (size_t)(row0 + r - 1) * ED + 4 * c4);
+        *(float4*)(sst + r * SS + 4 * c4) = v;
+    }
+    for (int idx = l; idx < EL * (DX / 4); idx += 64) {
+        const int r = idx / (DX / 4), c4 = idx % (DX / 4);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < len) v = *(const float4*)(x + (size_t)(row0 + r) * DX + 4 * c4);
+        *(float4*)(xst + r * XS + 4 * c4) = v;
+    }
+}
+
+// For the staged chunk: d_t = 1 - f_t^2 (0 at a sequence head, which makes A_t = 0 and folds
+// in Delta_0 = 0) and r_t = s_t - f_t, f_t = tanh(W s_{t-1} + U x_t + b) with the
+// pre-activations on FP32 MFMA (blin: lane's B operand [W | U]^T).  With `track`, returns the
+// residual bound of the rows < len as float bits, evaluated in FP64 when `res64`: s, x and
+// the parameters upcast, the quantity the final FP64 residual reports.  The FP32 residual
+// still drives the update; its rounding (~1e-7 here) would otherwise let an iterate pass a
+// 1e-6 test it fails in FP64.  The FP64 bound is rounded up to FP32.
+template <int DX>
+PN_DEV uint32_t elk_linearise(const float* sst, const float* xst, float* dsh, float* rsh,
+                              const float (&blin)[(ED + DX) / 4], float bias_u, const float* Wm,
+                              const float* __restrict__ U, bool first, int len, bool track,
+                              bool res64) {
+    constexpr int KT = ED + DX, SS = ED + 4, XS = DX + 4;
+    const int l = threadIdx.x & 63, g = l >> 4, u = l & 15;
+    uint32_t rm = 0;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KT / 4; ++kb) {
+        const int kk = 4 * kb + g;
+        const float av = kk < ED ? sst[u * SS + kk] : xst[u * XS + (kk - ED)];
+        acc = mfma16x4(av, blin[kb], acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = 4 * g + i;
+        const float f = tanhf_(acc[i] + bias_u);
+        const float res = sst[(t + 1) * SS + u] - f;
+        dsh[t * ED + u] = (first && t == 0) ? 0.f : 1.f - f * f;
+        rsh[t * ED + u] = res;
+        if (track && t < len && !res64) rm = max(rm, absbits(res));
+    }
+    if (track && res64) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = 4 * g + i;
+            if (t < len) {
+                double acc64 = (double)bias_u;
+                for (int kk = 0; kk < ED; ++kk)
+                    acc64 += (double)Wm[u * ES + kk] * (double)sst[t * SS + kk];
+                for (int kk = 0; kk < DX; ++kk)
+                    acc64 += (double)U[u * DX + kk] * (double)xst[t * XS + kk];
+                const double r = (double)sst[(t + 1) * SS + u] - tanh(acc64);
+                const double ar = fabs(r);
+                float fr = (float)ar;
+                if ((double)fr < ar) fr = nextafterf(fr, INFINITY);
+                rm = max(rm, (r == r) ? absbits(fr) : 0x7F800000u);
+            }
+        }
+    }
+    __syncthreads();
+    return rm;
+}
+
+// A~_t = diag(d_t) W (its diagonal only for quasi-ELK) into At
+PN_DEV void elk_build_At(float* At, const float* dsh, const float* Wm, int t, bool diag) {
+    const int l = threadIdx.x & 63;
+    for (int idx = l; idx < ED * ED; idx += 64) {
+        const int r = idx / ED, c = idx % ED;
+        At[r * ES + c] = (diag && r != c) ? 0.f : dsh[t * ED + r] * Wm[r * ES + c];
+    }
+    __syncthreads();
+}
+
+// the lane's B operand [W | U]^T for the pre-activation GEMM (unit u, k = 4 kb + g)
+template <int DX>
+PN_DEV void elk_load_weights(float* Wm, float (&blin)[(ED + DX) / 4], float& bias_u,
+                             const float* __restrict__ params) {
+    const int l = threadIdx.x & 63, g = l >> 4, u = l & 15;
+    const float* W = params;
+    const float* U = W + ED * ED;
+    for (int idx = l; idx < ED * ED; idx += 64) Wm[(idx / ED) * ES + idx % ED] = W[idx];
+#pragma unroll
+    for (int kb = 0; kb < (ED + DX) / 4; ++kb) {
+        const int kk = 4 * kb + g;
+        blin[kb] = kk < ED ? W[u * ED + kk] : U[u * DX + (kk - ED)];
+    }
+    bias_u = (U + ED * DX)[u];
+}
+
 struct ElkArgs {
     const float* x;
     const float* s0;
@@ -162,10 +267,11 @@ struct ElkArgs {
     float lam;
     int res64;               // nonzero: the stopping residual is evaluated in FP64
     int diag;                // nonzero: quasi-ELK, the LGSSM uses diag(A_t)
+    int smooth;              // nonzero: the smoother passes apply the step (no replay here)
 };
 
 template <int DX>
-__global__ void __launch_bounds__(64) elk_local_kernel(ElkArgs a) {
+__global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
     constexpr int L = EL;
     constexpr int KT = ED + DX;
     constexpr int SS = ED + 4, XS = DX + 4;
@@ -180,78 +286,23 @@ __global__ void __launch_bounds__(64) elk_local_kernel(ElkArgs a) {
 
     if (ld_i32(&a.ctrl->all_done)) return;
     const int k_it = a.ctrl->iter;
-    const bool fuse = k_it > 0;
+    const bool fuse = k_it > 0 && !a.smooth;      // the smoother applies its step itself
     const float reset_abs = a.ctrl->reset_abs;
     const float lam = a.lam;
     const float s1 = 1.f / (1.f + lam);           // 1 / (1 + lambda)
     const float kap = lam / (1.f + lam);         // kappa
     const float* __restrict__ sprev = a.sbuf[(k_it + 1) & 1];   // s^(k-1)
     float* __restrict__ scur = a.sbuf[k_it & 1];                 // s^(k)
-    const int l = threadIdx.x, g = l >> 4, u = l & 15;
-
-    const float* W = a.params;
-    const float* U = W + ED * ED;
-    const float* bvec = U + ED * DX;
-    for (int idx = l; idx < ED * ED; idx += 64) Wm[(idx / ED) * ES + idx % ED] = W[idx];
-    float blin[KT / 4];                          // B operand [W | U]^T, unit u, k = 4kb + g
-#pragma unroll
-    for (int kb = 0; kb < KT / 4; ++kb) {
-        const int kk = 4 * kb + g;
-        blin[kb] = kk < ED ? W[u * ED + kk] : U[u * DX + (kk - ED)];
-    }
-    const float bias_u = bvec[u];
-
-    // residual, d_t of the staged rows (FP64 stopping residual when asked for)
+    const int l = threadIdx.x;
+    const float* U = a.params + ED * ED;
+    float blin[KT / 4];
+    float bias_u;
+    elk_load_weights<DX>(Wm, blin, bias_u, a.params);
     auto linearise = [&](bool first, int len, bool track) -> uint32_t {
-        uint32_t rm = 0;
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < KT / 4; ++kb) {
-            const int kk = 4 * kb + g;
-            const float av = kk < ED ? sst[u * SS + kk] : xst[u * XS + (kk - ED)];
-            acc = mfma16x4(av, blin[kb], acc);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int t = 4 * g + i;
-            const float f = tanhf_(acc[i] + bias_u);
-            const float res = sst[(t + 1) * SS + u] - f;
-            dsh[t * ED + u] = (first && t == 0) ? 0.f : 1.f - f * f;
-            rsh[t * ED + u] = res;
-            if (track && t < len && !a.res64) rm = max(rm, absbits(res));
-        }
-        if (track && a.res64) {
-            // The stopping test in FP64: s, x and the parameters upcast, the quantity the final
-            // FP64 residual reports.  The FP32 residual still drives the update; its rounding
-            // (~1e-7 here) would otherwise let an iterate pass a 1e-6 test it fails in FP64.
-            // The bound is rounded up to FP32.
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int t = 4 * g + i;
-                if (t < len) {
-                    double acc64 = (double)bias_u;
-                    for (int kk = 0; kk < ED; ++kk)
-                        acc64 += (double)Wm[u * ES + kk] * (double)sst[t * SS + kk];
-                    for (int kk = 0; kk < DX; ++kk)
-                        acc64 += (double)U[u * DX + kk] * (double)xst[t * XS + kk];
-                    const double r = (double)sst[(t + 1) * SS + u] - tanh(acc64);
-                    const double ar = fabs(r);
-                    float fr = (float)ar;
-                    if ((double)fr < ar) fr = nextafterf(fr, INFINITY);
-                    rm = max(rm, (r == r) ? absbits(fr) : 0x7F800000u);
-                }
-            }
-        }
-        __syncthreads();
-        return rm;
+        return elk_linearise<DX>(sst, xst, dsh, rsh, blin, bias_u, Wm, U, first, len, track,
+                                 a.res64 != 0);
     };
-    auto build_At = [&](int t) {
-        for (int idx = l; idx < ED * ED; idx += 64) {
-            const int r = idx / ED, c = idx % ED;
-            At[r * ES + c] = (a.diag && r != c) ? 0.f : dsh[t * ED + r] * Wm[r * ES + c];
-        }
-        __syncthreads();
-    };
+    auto build_At = [&](int t) { elk_build_At(At, dsh, Wm, t, a.diag != 0); };
 
     for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
         const GroupInfo gr = a.groups[gi];
@@ -287,22 +338,8 @@ __global__ void __launch_bounds__(64) elk_local_kernel(ElkArgs a) {
             const int64_t row0 = ti.row0;
             const bool first = (ti.flags & kTileTimeFirst) != 0;
             __syncthreads();
-            // ---- stage s_{t-1}, s_t (of s^(k-1), or the guess s^(0)) and x_t
-            const float* src = fuse ? sprev : scur;
-            for (int idx = l; idx < (L + 1) * (ED / 4); idx += 64) {
-                const int r = idx / (ED / 4), c4 = idx % (ED / 4);
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (r == 0) v = first ? *(const float4*)(a.s0 + (size_t)b * ED + 4 * c4)
-                                      : *(const float4*)(src + (size_t)(row0 - 1) * ED + 4 * c4);
-                else if (r - 1 < len) v = *(const float4*)(src + (size_t)(row0 + r - 1) * ED + 4 * c4);
-                *(float4*)(sst + r * SS + 4 * c4) = v;
-            }
-            for (int idx = l; idx < L * (DX / 4); idx += 64) {
-                const int r = idx / (DX / 4), c4 = idx % (DX / 4);
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
-                *(float4*)(xst + r * XS + 4 * c4) = v;
-            }
+            // ---- stage s_{t-1}, s_t (of s^(k-1), or the current iterate) and x_t
+            elk_stage<DX>(sst, xst, fuse ? sprev : scur, a.s0, a.x, b, row0, len, first);
             if (l <= L) badrow[l] = 0;
             __syncthreads();
 
@@ -493,6 +530,223 @@ __global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__
     }
 }
 
+// ---- smoother (the exact LM step): RTS backward pass -----------------------------------------
+// With the filtered means and covariances (m_t, P_t) and the predictions (m-_t, P-_t),
+//   E_t = P_t A_{t+1}^T (P-_{t+1})^-1,   g_t = m_t - E_t m-_{t+1},   m^s_t = E_t m^s_{t+1} + g_t,
+// m^s at a sequence's last step = its filtered mean.  For a group of steps [a, b) of a
+// sequence the smoother pass replays the filter from the state entering the group and stores
+// (E_t, g_t) for t = a-1 .. b-2 (t >= the sequence start) by row, with the affine map they
+// compose, m^s_{a-1} = Q m^s_{b-1} + v (the group's backward element).  The backward carry
+// pass walks the groups from the sequence's end; the apply pass then unrolls every group from
+// m^s_{b-1} and writes s^(k+1) = s^(k) + m^s with the reset guard.
+constexpr int ESM = ED * ED + ED;             // per row: E_t (row-major), g_t
+
+struct ElkSmArgs {
+    const float* x;
+    const float* s0;
+    const float* sbuf[2];
+    const float* params;
+    const float* gcar;       // [ngroups][ECAR] filtered state entering every group
+    float* esm;              // [N][ESM] (E_t, g_t) by row
+    float* gbel;             // [ngroups][ESM] backward element (Q, v) of every group
+    float* bcar;             // [ngroups][ED] m^s at every group's last step
+    const Ctrl* ctrl;
+    const SeqState* seq;
+    const TileInfo* tiles;
+    const GroupInfo* groups;
+    const int32_t* group_start;
+    int ngroups;
+    float lam;
+    int diag;
+};
+
+template <int DX>
+__global__ void __launch_bounds__(64) elk_smooth_kernel(ElkSmArgs a) {
+    constexpr int KT = ED + DX;
+    constexpr int SS = ED + 4, XS = DX + 4;
+    __shared__ __attribute__((aligned(16))) float sst[(EL + 1) * SS];
+    __shared__ __attribute__((aligned(16))) float xst[EL * XS];
+    __shared__ float dsh[EL * ED], rsh[EL * ED];
+    __shared__ float Wm[EM], At[EM], P[EM], Pp[EM], Pi[EM], T1[EM], E[EM], Q[EM], Gm[EM];
+    __shared__ float m[ED], mp[ED], gv[ED], vv[ED], vx[ED];
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int k_it = a.ctrl->iter;
+    const float* __restrict__ scur = a.sbuf[k_it & 1];
+    const float lam = a.lam;
+    const int l = threadIdx.x;
+    const float* U = a.params + ED * ED;
+    float blin[KT / 4];
+    float bias_u;
+    elk_load_weights<DX>(Wm, blin, bias_u, a.params);
+
+    for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+        const GroupInfo gr = a.groups[gi];
+        const int b = gr.b;
+        if (a.seq[b].status != kActive) continue;
+        const float* cr = a.gcar + (size_t)gi * ECAR;
+        fetch_mat(P, cr);
+        if (l < ED) m[l] = cr[ED * ED + l];
+        bool haveq = false;
+        for (int kt = 0; kt < gr.ntl; ++kt) {
+            const TileInfo ti = a.tiles[gr.tile0 + kt];
+            const int len = ti.len;
+            const int64_t row0 = ti.row0;
+            const bool first = (ti.flags & kTileTimeFirst) != 0;
+            __syncthreads();
+            elk_stage<DX>(sst, xst, scur, a.s0, a.x, b, row0, len, first);
+            __syncthreads();
+            elk_linearise<DX>(sst, xst, dsh, rsh, blin, bias_u, Wm, U, first, len, false, false);
+            for (int t = 0; t < len; ++t) {
+                elk_build_At(At, dsh, Wm, t, a.diag != 0);
+                if (l < ED) vx[l] = -rsh[t * ED + l];
+                mm16(T1, At, false, P, false, 1.f, nullptr, 0.f);         // A P
+                mm16(Pp, T1, false, At, true, 1.f, nullptr, 1.f);         // P- = A P A^T + I
+                mv16(mp, At, false, m, 1.f, vx, 1.f);                     // m- = A m - r
+                if (!(first && t == 0)) {
+                    inv16(Pi, Pp);
+                    mm16(T1, P, false, At, true, 1.f, nullptr, 0.f);      // P A^T
+                    mm16(E, T1, false, Pi, false, 1.f, nullptr, 0.f);     // E_{t-1}
+                    mv16(gv, E, false, mp, -1.f, m, 1.f);                 // g = m - E m-
+                    float* dst = a.esm + (size_t)(row0 + t - 1) * ESM;
+                    store_mat(dst, E);
+                    if (l < ED) dst[ED * ED + l] = gv[l];
+                    if (haveq) {
+                        mv16(vv, Q, false, gv, 1.f, vv, 1.f);             // v += Q g
+                        mm16(Q, Q, false, E, false, 1.f, nullptr, 0.f);   // Q = Q E
+                    } else {
+                        for (int idx = l; idx < EM; idx += 64) Q[idx] = E[idx];
+                        if (l < ED) vv[l] = gv[l];
+                        __syncthreads();
+                        haveq = true;
+                    }
+                }
+                for (int idx = l; idx < ED * ED; idx += 64) {
+                    const int r = idx / ED, c = idx % ED;
+                    T1[r * ES + c] = lam * Pp[r * ES + c] + (r == c ? 1.f : 0.f);
+                }
+                __syncthreads();
+                inv16(Gm, T1);                                            // Gamma
+                mm16(P, Gm, false, Pp, false, 1.f, nullptr, 0.f);         // P = Gamma P-
+                for (int idx = l; idx < ED * ED; idx += 64) {
+                    const int r = idx / ED, c = idx % ED;
+                    if (r < c) {
+                        const float v = 0.5f * (P[r * ES + c] + P[c * ES + r]);
+                        P[r * ES + c] = v;
+                        P[c * ES + r] = v;
+                    }
+                }
+                __syncthreads();
+                mv16(m, Gm, false, mp, 1.f, nullptr, 0.f);                // m = Gamma m-
+            }
+        }
+        const bool gfirst = gi == gr.gfirst;
+        const bool glast = gi == a.group_start[b + 1] - 1;
+        if (glast && l < ED) a.bcar[(size_t)gi * ED + l] = m[l];        // m^s = m at the end
+        if (!gfirst) {
+            float* dst = a.gbel + (size_t)gi * ESM;
+            store_mat(dst, Q);
+            if (l < ED) dst[ED * ED + l] = vv[l];
+        }
+    }
+}
+
+// m^s at every group's last step, from the sequence's end (one single-wave workgroup per
+// sequence); the next element is fetched while the current one is applied
+__global__ void __launch_bounds__(64) elk_back_carry_kernel(const float* __restrict__ gbel,
+                                                            float* __restrict__ bcar,
+                                                            const Ctrl* ctrl, const SeqState* seq,
+                                                            const int32_t* group_start, int B) {
+    if (ld_i32(&ctrl->all_done)) return;
+    const int b = blockIdx.x;
+    if (b >= B || seq[b].status != kActive) return;
+    const int l = threadIdx.x, r = l & 15, q = l >> 4;
+    const int g0 = group_start[b], G = group_start[b + 1] - g0;
+    if (G <= 1) return;
+    // lane (r, q): columns 4q .. 4q+3 of row r
+    float right = bcar[(size_t)(g0 + G - 1) * ED + r];
+    auto load = [&](int gg, float4& qrow, float& vr) {
+        const float* e = gbel + (size_t)(g0 + gg) * ESM;
+        qrow = *(const float4*)(e + r * ED + 4 * q);
+        vr = e[ED * ED + r];
+    };
+    float4 qn;
+    float vn;
+    load(G - 1, qn, vn);
+    for (int gg = G - 1; gg >= 1; --gg) {
+        const float4 qc = qn;
+        const float vc = vn;
+        if (gg > 1) load(gg - 1, qn, vn);
+        float acc = qc.x * __shfl(right, 4 * q) + qc.y * __shfl(right, 4 * q + 1) +
+                    qc.z * __shfl(right, 4 * q + 2) + qc.w * __shfl(right, 4 * q + 3);
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        right = acc + vc;                                  // m^s at the end of group gg - 1
+        if (q == 0) bcar[(size_t)(g0 + gg - 1) * ED + r] = right;
+    }
+}
+
+// s^(k+1) = s^(k) + m^s over every group, walking its rows from the last one
+struct ElkBackArgs {
+    const float* esm;
+    const float* bcar;
+    float* sbuf[2];
+    Ctrl* ctrl;
+    SeqState* seq;
+    const TileInfo* tiles;
+    const GroupInfo* groups;
+    int ngroups;
+};
+
+__global__ void __launch_bounds__(64) elk_back_apply_kernel(ElkBackArgs a) {
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int k_it = a.ctrl->iter;
+    const float* __restrict__ scur = a.sbuf[k_it & 1];
+    float* __restrict__ snext = a.sbuf[(k_it + 1) & 1];
+    const float reset_abs = a.ctrl->reset_abs;
+    const int l = threadIdx.x, r = l & 15, q = l >> 4;
+    for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+        const GroupInfo gr = a.groups[gi];
+        const int b = gr.b;
+        if (a.seq[b].status != kActive) continue;
+        const TileInfo tl = a.tiles[gr.tile0 + gr.ntl - 1];
+        const TileInfo tf = a.tiles[gr.tile0];
+        const int64_t ra = tf.row0, rb = tl.row0 + tl.len;   // rows [ra, rb)
+        float right = a.bcar[(size_t)gi * ED + r];         // m^s_{rb-1}
+        int nreset = 0;
+        // row rb-1
+        {
+            const float v = scur[(size_t)(rb - 1) * ED + r] + right;
+            const bool bad = __any(q == 0 && !(fabsf(v) <= reset_abs));
+            if (q == 0) snext[(size_t)(rb - 1) * ED + r] = bad ? 0.f : v;
+            nreset += bad ? 1 : 0;
+        }
+        float4 en = make_float4(0.f, 0.f, 0.f, 0.f);
+        float gn = 0.f, sn = 0.f;
+        auto load = [&](int64_t t, float4& e, float& gvv, float& sv) {
+            const float* p = a.esm + (size_t)t * ESM;
+            e = *(const float4*)(p + r * ED + 4 * q);
+            gvv = p[ED * ED + r];
+            sv = scur[(size_t)t * ED + r];
+        };
+        if (rb - 2 >= ra) load(rb - 2, en, gn, sn);
+        for (int64_t t = rb - 2; t >= ra; --t) {
+            const float4 ec = en;
+            const float gc = gn, sc = sn;
+            if (t - 1 >= ra) load(t - 1, en, gn, sn);
+            float acc = ec.x * __shfl(right, 4 * q) + ec.y * __shfl(right, 4 * q + 1) +
+                        ec.z * __shfl(right, 4 * q + 2) + ec.w * __shfl(right, 4 * q + 3);
+            acc += __shfl_xor(acc, 16);
+            acc += __shfl_xor(acc, 32);
+            right = acc + gc;                              // m^s_t
+            const float v = sc + right;
+            const bool bad = __any(q == 0 && !(fabsf(v) <= reset_abs));
+            if (q == 0) snext[(size_t)t * ED + r] = bad ? 0.f : v;
+            nreset += bad ? 1 : 0;
+        }
+        if (l == 0 && nreset) atomicAdd(&a.seq[b].resets_pending, nreset);
+    }
+}
+
 // ---- host ---------------------------------------------------------------------------------------
 
 struct ElkLayout {
@@ -501,11 +755,15 @@ struct ElkLayout {
     float* gel;
     float* gcar;
     uint32_t* grmax;
+    float* esm;              // smoother only
+    float* gbel;
+    float* bcar;
     char* r64;
     size_t bytes;
 };
 
-static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngroups) {
+static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngroups,
+                            bool smooth) {
     Carver c(ws);
     ElkLayout lay;
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
@@ -513,6 +771,9 @@ static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngrou
     lay.gel = c.take<float>((size_t)std::max(ngroups, 1) * EGEL);
     lay.gcar = c.take<float>((size_t)std::max(ngroups, 1) * ECAR);
     lay.grmax = c.take<uint32_t>((size_t)std::max(ngroups, 1));
+    lay.esm = smooth ? c.take<float>((size_t)std::max<int64_t>(hb.N, 1) * ESM) : nullptr;
+    lay.gbel = smooth ? c.take<float>((size_t)std::max(ngroups, 1) * ESM) : nullptr;
+    lay.bcar = smooth ? c.take<float>((size_t)std::max(ngroups, 1) * ED) : nullptr;
     lay.r64 = c.take<char>(residual64_workspace(PN_CELL_TANH, ED, 16, hb));   // FP64 residual
     lay.bytes = c.bytes();
     return lay;
@@ -552,7 +813,7 @@ static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, 
 size_t elk_workspace(int, int, const HostBatch& hb, const pn_opts& o) {
     const std::vector<int32_t> ts = tile_starts(hb, EL);
     const int gt = elk_group_tiles(hb, ts, o.tile);
-    return elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt)).bytes;
+    return elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt), o.smooth != 0).bytes;
 }
 
 pn_status residual64_device(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
@@ -568,7 +829,8 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const int resident = elk_resident();
     const int gt = elk_group_tiles(hb, ts, o.tile);
     const int ngroups = count_groups(ts, hb.B, gt);
-    ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups);
+    const bool smooth = o.smooth != 0;
+    ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups, smooth);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, EL, false, max_iters, (float)o.tol,
                            (float)o.reset_abs, stream, gt));
@@ -592,6 +854,35 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.lam = (float)lambda;
     args.res64 = o.fp64_final_residual ? 1 : 0;
     args.diag = o.jac == PN_JAC_DIAG ? 1 : 0;
+    args.smooth = smooth ? 1 : 0;
+    ElkSmArgs sm;
+    sm.x = x;
+    sm.s0 = s0;
+    sm.sbuf[0] = s;
+    sm.sbuf[1] = lay.salt;
+    sm.params = (const float*)cd.params;
+    sm.gcar = lay.gcar;
+    sm.esm = lay.esm;
+    sm.gbel = lay.gbel;
+    sm.bcar = lay.bcar;
+    sm.ctrl = lay.st.ctrl;
+    sm.seq = lay.st.seq;
+    sm.tiles = lay.st.tiles;
+    sm.groups = lay.st.groups;
+    sm.group_start = lay.st.group_start;
+    sm.ngroups = ngroups;
+    sm.lam = args.lam;
+    sm.diag = args.diag;
+    ElkBackArgs ba;
+    ba.esm = lay.esm;
+    ba.bcar = lay.bcar;
+    ba.sbuf[0] = s;
+    ba.sbuf[1] = lay.salt;
+    ba.ctrl = lay.st.ctrl;
+    ba.seq = lay.st.seq;
+    ba.tiles = lay.st.tiles;
+    ba.groups = lay.st.groups;
+    ba.ngroups = ngroups;
     auto one_iter = [&](hipStream_t st) {
         prof_launch("elk_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
@@ -602,14 +893,30 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
                                lay.st.seq, (const int32_t*)lay.st.group_start,
                                (const uint32_t*)lay.grmax, args.freeze, hb.B);
         });
-        launch_decide(lay.st, hb.B, st, true);
+        if (smooth) {
+            prof_launch("elk_smooth", st, [&](hipStream_t s2) {
+                hipLaunchKernelGGL(elk_smooth_kernel<16>, dim3(grid), dim3(64), 0, s2, sm);
+            });
+            prof_launch("elk_back_carry", st, [&](hipStream_t s2) {
+                hipLaunchKernelGGL(elk_back_carry_kernel, dim3(std::max(1, hb.B)), dim3(64), 0,
+                                   s2, (const float*)lay.gbel, lay.bcar,
+                                   (const Ctrl*)lay.st.ctrl, (const SeqState*)lay.st.seq,
+                                   (const int32_t*)lay.st.group_start, hb.B);
+            });
+            prof_launch("elk_back_apply", st, [&](hipStream_t s2) {
+                hipLaunchKernelGGL(elk_back_apply_kernel, dim3(grid), dim3(64), 0, s2, ba);
+            });
+        }
+        // the filter forms the iterate in the next local pass (its resets belong to the
+        // current iterate); the smoother has written the next iterate already
+        launch_decide(lay.st, hb.B, st, !smooth);
     };
     std::vector<uintptr_t> key = {0x454Du, (uintptr_t)kern, (uintptr_t)grid, (uintptr_t)x,
                                   (uintptr_t)s0, (uintptr_t)s, (uintptr_t)cd.params,
                                   (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
                                   (uintptr_t)ngroups, float_bits(args.lam),
                                   (uintptr_t)args.res64, (uintptr_t)args.diag,
-                                  (uintptr_t)args.freeze};
+                                  (uintptr_t)args.freeze, (uintptr_t)args.smooth};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
     int derr = 0;

@@ -169,6 +169,17 @@ def test_damping_routes(lib):
     o.freeze_prefix = 2
     assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
                          ctypes.byref(o), None, 0, None, None) == -1
+    o = pn.make_opts(jac="diag", freeze_prefix=True, smooth=True)   # not together
+    assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
+                         ctypes.byref(o), None, 0, None, None) == -2
+    o = pn.make_opts(jac="diag")
+    o.smooth = 3
+    assert lib.elk_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_double(1.0),
+                         ctypes.byref(o), None, 0, None, None) == -1
+    o = pn.make_opts(jac="diag", smooth=True)                       # smoother: ELK only
+    c3, b3, _ = _desc(D=64, Dx=32)
+    assert lib.deer_solve(ctypes.byref(c3), ctypes.byref(b3), *args, ctypes.byref(o), None, 0,
+                          None, None) == -2
     o = pn.make_opts(jac="diag", freeze_prefix=True)   # converged-prefix skipping: ELK only
     c2, b2, _ = _desc(D=64, Dx=32)
     assert lib.deer_solve(ctypes.byref(c2), ctypes.byref(b2), *args, ctypes.byref(o), None, 0,
