@@ -123,6 +123,10 @@ def main():
                     help="also time the step with graph-captured iterations (not the value)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="accepted for older command lines; the 1 GiB copy always runs")
+    ap.add_argument("--sweep-lle", action="store_true",
+                    help="instead of the step: the mean-field RNN LLE-threshold sweep (one "
+                         "JSON line per gain and length)")
+    ap.add_argument("--sweep-seeds", type=int, default=3)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -132,6 +136,11 @@ def main():
         sys.exit(2)
 
     from paper_2603_16850_amd import workloads
+    if args.sweep_lle:
+        import torch
+        import paper_2603_16850_amd as pn
+        sweep_lle(torch, pn, workloads, args.sweep_seeds)
+        return
     work = workloads.ALL[WORKLOAD]
     inst = workloads.make_instance(work, seed=0)
     D, Dx, B, N = work.D, work.Dx, work.B, inst.N
@@ -258,6 +267,51 @@ def main():
     if args.rows:
         rec["rows"] = measure_rows(torch, pn, workloads)
     print(json.dumps(rec), flush=True)
+
+
+def sweep_lle(torch, pn, workloads, seeds):
+    """The LLE-threshold experiment of Ch. 5 on the mean-field RNN (D = 16): for every gain g
+    and length T, each seed draws its own W; the sequential GPU rollout gives the trajectory,
+    the LLE is estimated along it on the GPU from three random unit vectors (averaged), and
+    DEER (ELK with lambda = 0, dense, tol 1e-5) solves the same sequence from s = 0.  Chaotic
+    cases are capped at `cap` iterations (reported as not converged)."""
+    dev = "cuda"
+    gains = [round(0.5 + 0.125 * i, 3) for i in range(13)]
+    for T, cap in ((1000, 1000), (10000, 400)):
+        for g in gains:
+            lles, iters, conv, deer_ms, seq_ms, errs = [], [], [], [], [], []
+            for seed in range(seeds):
+                w = workloads.MEANFIELD16.scaled(gain=g, T=T)
+                inst = workloads.make_instance(w, seed=seed)
+                x, s0, p = (torch.tensor(v, dtype=torch.float32, device=dev)
+                            for v in (inst.x, inst.s0, inst.params))
+                ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="meanfield",
+                                                                 offsets=inst.offsets))
+                seq_ms.append(ms)
+                u = torch.tensor(np.random.default_rng(100 + seed).standard_normal((3, 16)),
+                                 dtype=torch.float32, device=dev)
+                lles.append(float(np.mean([pn.lle_estimate(x, s0, p, s_seq, u[i:i + 1],
+                                                           cell="meanfield",
+                                                           offsets=inst.offsets)[0]
+                                           for i in range(3)])))
+                ms, (s, info) = _timed(torch, lambda: pn.elk_solve(
+                    x, s0, p, 0.0, cell="meanfield", offsets=inst.offsets, jac="dense",
+                    tol=w.tol, max_iters=cap), reps=1)
+                deer_ms.append(ms)
+                iters.append(info[0]["iters"])
+                conv.append(bool(info[0]["converged"]))
+                ref = s_seq.double()
+                errs.append(float((s.double() - ref).abs().max() / ref.abs().max()))
+            print(json.dumps({
+                "sweep": "meanfield16-lle", "T": T, "g": g, "seeds": seeds,
+                "lle_mean": round(float(np.mean(lles)), 4),
+                "lle_min": round(float(np.min(lles)), 4), "lle_max": round(float(np.max(lles)), 4),
+                "deer_iters_mean": round(float(np.mean(iters)), 1), "deer_iters_max": max(iters),
+                "converged": sum(conv), "cap": cap,
+                "deer_ms_mean": round(float(np.mean(deer_ms)), 3),
+                "seq_ms_mean": round(float(np.mean(seq_ms)), 3),
+                "speedup_vs_sequential": round(float(np.mean(seq_ms) / np.mean(deer_ms)), 3),
+                "err_vs_sequential_max": float(np.max(errs))}), flush=True)
 
 
 def _timed(torch, fn, reps=3):

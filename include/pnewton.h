@@ -62,8 +62,11 @@ typedef enum {
                            n = tanh(W_n x + b_n + r*(U_n h + b_hn)), f = (1-z)*n + z*h.
                            params: [W_z;W_r;W_n] (3D x Dx) | [U_z;U_r;U_n] (3D x D) |
                                    [b_z;b_r;b_n] (3D) | b_hn (D)                          */
-    PN_CELL_TANH = 1    /* f = tanh(W h + U x + b) (the mean-field RNN family of Ch. 5).
+    PN_CELL_TANH = 1,   /* f = tanh(W h + U x + b).
                            params: W (D x D) | U (D x Dx) | b (D)                         */
+    PN_CELL_MEANFIELD = 2 /* f = W tanh(h) + U x + b: the mean-field RNN of the
+                           predictability experiments (Ch. 5), whose state is a current;
+                           A = W diag(1 - tanh(h)^2).  params as PN_CELL_TANH           */
 } pn_cell;
 
 typedef enum {
@@ -173,7 +176,8 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
 /* ELK (Ch. 4): each iteration replaces the Newton step by the filtered means of the LGSSM
    of Prop. prop:ELK with emission noise 1/lambda (lambda >= 0; lambda = 0 is DEER).  With
    PN_JAC_DIAG the LGSSM uses diag(A_t): quasi-ELK (Ch. 4, "quasi-ELK").
-   Built: TANH, PN_JAC_DENSE or PN_JAC_DIAG, F32, D = 16, Dx in {16}, no damping; tile 0
+   Built: TANH or MEANFIELD, PN_JAC_DENSE or PN_JAC_DIAG, F32, D = 16, Dx = 16, no damping;
+   (lambda = 0 with PN_JAC_DENSE is DEER on these cells); tile 0
    (chosen from the shapes) or a multiple of 16 up to 1024: the steps one workgroup folds
    into one filter element.  With fp64_final_residual the stopping test of every iterate is evaluated in FP64 and the
    reported max_resid is the FP64 residual of the returned FP32 iterate. */
@@ -201,7 +205,8 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
    through that rollout -- the reverse recurrence lambda_t = g_t + A_{t+1}^T lambda_{t+1} one
    step at a time, then the parallel gradient reductions -- with the outputs of deer_adjoint.
    Workspace from pn_workspace_bytes(PN_OP_SEQ, ...).  Built: GRU F32 (the deer_solve GRU
-   shapes), TANH F32 (D <= 64, Dx <= 64). seq_bptt: GRU only. */
+   shapes), TANH F32 ((D, Dx) in {(16,16), (32,16), (32,32), (64,32), (16,8), (4,4)}),
+   MEANFIELD F32 (D = Dx = 16). seq_bptt: GRU only. */
 #define PN_OP_SEQ 4
 pn_status seq_rollout(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                       const void* s0, void* s, void* workspace, size_t workspace_bytes,
@@ -211,10 +216,22 @@ pn_status seq_bptt(const pn_cell_desc* cell, const pn_batch* batch, const void* 
                    void* gparams, void* workspace, size_t workspace_bytes, void* stream);
 
 /* FP64 residual max-norm per sequence of an FP32 trajectory (inputs upcast to FP64):
-   max_resid: HOST array [B].  Built: TANH and GRU, F32. */
+   max_resid: HOST array [B].  Built: TANH, MEANFIELD and GRU, F32. */
 pn_status pn_residual_f64(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                           const void* s0, const void* s, void* workspace,
                           size_t workspace_bytes, void* stream, double* max_resid);
+
+/* Largest Lyapunov exponent along a trajectory (Alg. LLE_estimate, Ch. 5): per sequence,
+   u_t = A_t u_{t-1} with A_t = df/ds_{t-1} at the trajectory's previous state (s_0 first),
+   lambda_t = ||u_t||, u_t <- u_t / lambda_t, lle = (1/T) sum_t log lambda_t.
+   s [N, D]: the trajectory (device); u0 [B, D]: starting vectors (device, normalised here,
+   nonzero); lle: HOST array [B] (0 for an empty sequence).  Log stretches are summed in FP64.
+   Workspace from pn_workspace_bytes(PN_OP_LLE, ...).  Built: TANH and MEANFIELD, F32,
+   D = Dx = 16.  A zero stretch (u mapped to 0) gives -inf for that sequence. */
+#define PN_OP_LLE 5
+pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                          const void* s0, const void* s, const void* u0, void* workspace,
+                          size_t workspace_bytes, void* stream, double* lle);
 
 /* Kernel timing with HIP events, for benchmarking.  Between pn_profile_begin() and
    pn_profile_end() the solvers called on this thread launch their iterations directly (no

@@ -24,14 +24,17 @@ paper; the equations sat in a figure).  The oracle fixes the "reset-after" GRU:
 Its Jacobian, written with a = (h - n) z (1 - z), b = (1 - z)(1 - n^2) r and
 c = (1 - z)(1 - n^2) q r (1 - r), is
     A = diag(z) + diag(a) U_z + diag(b) U_n + diag(c) U_r.
-The tanh-RNN is f = tanh(W h + U x + bias), A = diag(1 - f^2) W, as in the mean-field RNN
-family the thesis uses for its predictability experiments.  The affine cell
+The tanh-RNN is f = tanh(W h + U x + bias), A = diag(1 - f^2) W.  The mean-field RNN of
+the predictability experiments (Ch. 5, "Experiments") places the nonlinearity before the
+coupling, f = W tanh(h) + U x + bias (the state is a current), so A = W diag(1 - tanh(h)^2).
+The affine cell
 f = M h + N x + c (optionally with a per-step M_t) is a linear dynamical system (eq. lds),
 used to pin the one-iteration properties.
 
 Parameter packing (row-major, one flat float64 vector):
   GRU:    [W_z; W_r; W_n] (3D x Dx) | [U_z; U_r; U_n] (3D x D) | [b_z; b_r; b_n] (3D) | b_hn (D)
   tanh:   W (D x D) | U (D x Dx) | b (D)
+  meanfield: W (D x D) | U (D x Dx) | b (D)
   affine: M (D x D) | N (D x Dx) | c (D)
 """
 import numpy as np
@@ -173,6 +176,34 @@ class TanhRNN:
         return np.concatenate([g["W"].ravel(), g["U"].ravel(), g["b"]])
 
 
+class MeanFieldRNN:
+    """f(h, x) = W tanh(h) + U x + b;  A = W diag(1 - tanh(h)^2)."""
+
+    name = "meanfield"
+
+    def __init__(self, params, D, Dx):
+        p = np.asarray(params, dtype=np.float64).ravel()
+        assert p.size == tanh_param_count(D, Dx), (p.size, D, Dx)
+        self.D, self.Dx = D, Dx
+        o = 0
+        self.W = p[o:o + D * D].reshape(D, D).copy(); o += D * D
+        self.U = p[o:o + D * Dx].reshape(D, Dx).copy(); o += D * Dx
+        self.b = p[o:o + D].copy()
+
+    def f(self, h, x, t=None):
+        return np.tanh(h) @ self.W.T + x @ self.U.T + self.b
+
+    def jac(self, h, x, t=None):
+        d = 1.0 - np.tanh(h) ** 2
+        return self.W * d[..., None, :]
+
+    def jac_diag(self, h, x, t=None):
+        return np.diag(self.W) * (1.0 - np.tanh(h) ** 2)
+
+    def vjp(self, h, x, v, t=None):
+        return (v @ self.W) * (1.0 - np.tanh(h) ** 2)
+
+
 class Affine:
     """f(h, x) = M h + N x + c: a linear dynamical system (eq. lds).
 
@@ -217,6 +248,8 @@ def make_cell(kind, params, D, Dx, **kw):
         return GRU(params, D, Dx)
     if kind == "tanh":
         return TanhRNN(params, D, Dx)
+    if kind == "meanfield":
+        return MeanFieldRNN(params, D, Dx)
     if kind == "affine":
         return Affine(params, D, Dx, **kw)
     raise ValueError(kind)

@@ -28,6 +28,13 @@ def lle_average(jacobians, n_vectors=3, seed=0):
     return float(np.mean(vals))
 
 
+def trajectory_jacobians(cell, x, s0, s):
+    """A_t = df/ds_{t-1} along the trajectory s (s_0 first)."""
+    h = np.concatenate([np.asarray(s0, np.float64)[None], np.asarray(s, np.float64)[:-1]],
+                       axis=0)
+    return cell.jac(h, np.asarray(x, np.float64), t=np.arange(len(x)))
+
+
 def trajectory_lle(cell, x, s0, s, n_vectors=3, seed=0):
     """LLE along a trajectory s (the Jacobians A_t evaluated at s_{t-1})."""
     h = np.concatenate([np.asarray(s0, np.float64)[None], s[:-1]], axis=0)

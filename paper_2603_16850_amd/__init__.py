@@ -14,11 +14,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpnewton.so")
 
 PN_OK, PN_NOT_CONVERGED = 0, 1
-CELLS = {"gru": 0, "tanh": 1}
+CELLS = {"gru": 0, "tanh": 1, "meanfield": 2}
 JACS = {"dense": 0, "diag": 1, "picard": 2, "jacobi": 3}
 DTYPES = {"f32": 0, "f64": 1}
 COMPOSE = {"native": 0, "bf16": 1}
-OP_DEER, OP_ELK, OP_ADJOINT, OP_RESIDUAL64, OP_SEQ = 0, 1, 2, 3, 4
+OP_DEER, OP_ELK, OP_ADJOINT, OP_RESIDUAL64, OP_SEQ, OP_LLE = 0, 1, 2, 3, 4, 5
 
 
 class CellDesc(ctypes.Structure):
@@ -65,6 +65,8 @@ SIGNATURES = [
     ("seq_bptt", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, _V, _V, _V, _V, _V,
                                 ctypes.c_size_t, _V]),
     ("pn_residual_f64", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, _V,
+                                       ctypes.c_size_t, _V, _P(ctypes.c_double)]),
+    ("pn_lle_estimate", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, _V, _V,
                                        ctypes.c_size_t, _V, _P(ctypes.c_double)]),
     ("pn_profile_begin", None, []),
     ("pn_profile_end", None, []),
@@ -311,6 +313,18 @@ class profile:
         if not load().pn_profile_read(family.encode(), ctypes.byref(ms), ctypes.byref(n)):
             return 0.0, 0
         return ms.value, n.value
+
+
+def lle_estimate(x, s0, params, s, u0, cell="meanfield", offsets=None):
+    """Largest Lyapunov exponent along the trajectory s per sequence (list of floats)."""
+    for t, n in ((x, "x"), (s0, "s0"), (params, "params"), (s, "s"), (u0, "u0")):
+        _dev(t, n)
+    sh = _shapes(cell, params, x, s0, offsets)
+    ws, nb = _workspace(OP_LLE, sh, make_opts(), x.device)
+    out = (ctypes.c_double * sh.batch.B)()
+    _check(load().pn_lle_estimate(ctypes.byref(sh.cell), ctypes.byref(sh.batch), _ptr(x),
+                                  _ptr(s0), _ptr(s), _ptr(u0), _aligned(ws), nb, _stream(), out))
+    return list(out)
 
 
 def residual_f64(x, s0, params, s, cell="tanh", offsets=None):

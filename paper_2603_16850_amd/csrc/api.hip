@@ -27,7 +27,8 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 pn_status check_cell(const pn_cell_desc* cell) {
     if (!cell) { set_error("cell descriptor is NULL"); return PN_ERR_INVALID_ARG; }
-    if (cell->cell != PN_CELL_GRU && cell->cell != PN_CELL_TANH) {
+    if (cell->cell != PN_CELL_GRU && cell->cell != PN_CELL_TANH &&
+        cell->cell != PN_CELL_MEANFIELD) {
         set_error("unknown cell kind %d", cell->cell);
         return PN_ERR_INVALID_ARG;
     }
@@ -215,7 +216,8 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
             }
             break;
         case PN_OP_ELK:
-            if (cell->cell == PN_CELL_TANH && cell->dtype == PN_F32 && elk_supported(cell->D, cell->Dx)) {
+            if ((cell->cell == PN_CELL_TANH || cell->cell == PN_CELL_MEANFIELD) &&
+                cell->dtype == PN_F32 && elk_supported(cell->D, cell->Dx)) {
                 *bytes = elk_workspace(cell->D, cell->Dx, hb, o);
                 return PN_OK;
             }
@@ -236,6 +238,12 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
         case PN_OP_RESIDUAL64:
             if (cell->dtype == PN_F32 && residual64_supported(cell->cell, cell->D, cell->Dx)) {
                 *bytes = residual64_workspace(cell->cell, cell->D, cell->Dx, hb);
+                return PN_OK;
+            }
+            break;
+        case PN_OP_LLE:
+            if (cell->dtype == PN_F32 && lle_supported(cell->cell, cell->D, cell->Dx)) {
+                *bytes = lle_workspace(hb);
                 return PN_OK;
             }
             break;
@@ -318,7 +326,8 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
         return PN_ERR_UNSUPPORTED;
     }
     PN_TRY(check_ptrs({x, s0, s, cell->params}, hb));
-    if (!(cell->cell == PN_CELL_TANH && cell->dtype == PN_F32 && elk_supported(cell->D, cell->Dx))) {
+    if (!((cell->cell == PN_CELL_TANH || cell->cell == PN_CELL_MEANFIELD) &&
+          cell->dtype == PN_F32 && elk_supported(cell->D, cell->Dx))) {
         set_error("elk_solve not built for cell=%d D=%d Dx=%d dtype=%d", cell->cell, cell->D,
                   cell->Dx, cell->dtype);
         return PN_ERR_UNSUPPORTED;
@@ -424,6 +433,24 @@ pn_status pn_residual_f64(const pn_cell_desc* cell, const pn_batch* batch, const
     PN_TRY(check_ws(workspace, workspace_bytes, need));
     return residual64_run(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
                           workspace, (hipStream_t)stream, max_resid);
+}
+
+pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                          const void* s0, const void* s, const void* u0, void* workspace,
+                          size_t workspace_bytes, void* stream, double* lle) {
+    PN_TRY(check_cell(cell));
+    HostBatch hb;
+    PN_TRY(check_batch(batch, hb));
+    PN_TRY(check_ptrs({x, s0, s, u0, cell->params}, hb));
+    if (!lle) { set_error("lle is NULL"); return PN_ERR_INVALID_ARG; }
+    if (cell->dtype != PN_F32 || !lle_supported(cell->cell, cell->D, cell->Dx)) {
+        set_error("pn_lle_estimate not built for cell=%d D=%d Dx=%d", cell->cell, cell->D,
+                  cell->Dx);
+        return PN_ERR_UNSUPPORTED;
+    }
+    PN_TRY(check_ws(workspace, workspace_bytes, lle_workspace(hb)));
+    return lle_run(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
+                   (const float*)u0, workspace, (hipStream_t)stream, lle);
 }
 
 }  // extern "C"

@@ -170,14 +170,17 @@ PN_DEV void elk_stage(float* sst, float* xst, const float* __restrict__ src,
     }
 }
 
-// For the staged chunk: d_t = 1 - f_t^2 (0 at a sequence head, which makes A_t = 0 and folds
-// in Delta_0 = 0) and r_t = s_t - f_t, f_t = tanh(W s_{t-1} + U x_t + b) with the
-// pre-activations on FP32 MFMA (blin: lane's B operand [W | U]^T).  With `track`, returns the
+// For the staged chunk: the scale vector d_t of A_t (0 at a sequence head, which makes A_t = 0
+// and folds in Delta_0 = 0) and r_t = s_t - f_t, with the GEMM on FP32 MFMA (blin: lane's B
+// operand [W | U]^T):
+//   tanh-RNN (MF = false):   f_t = tanh(W s_{t-1} + U x_t + b),  d_t = 1 - f_t^2 (rows of W);
+//   mean-field (MF = true):  f_t = W tanh(s_{t-1}) + U x_t + b,  d_t = 1 - tanh(s_{t-1})^2
+//                            (columns of W).  With `track`, returns the
 // residual bound of the rows < len as float bits, evaluated in FP64 when `res64`: s, x and
 // the parameters upcast, the quantity the final FP64 residual reports.  The FP32 residual
 // still drives the update; its rounding (~1e-7 here) would otherwise let an iterate pass a
 // 1e-6 test it fails in FP64.  The FP64 bound is rounded up to FP32.
-template <int DX>
+template <int DX, bool MF>
 PN_DEV uint32_t elk_linearise(const float* sst, const float* xst, float* dsh, float* rsh,
                               const float (&blin)[(ED + DX) / 4], float bias_u, const float* Wm,
                               const float* __restrict__ U, bool first, int len, bool track,
@@ -189,15 +192,23 @@ PN_DEV uint32_t elk_linearise(const float* sst, const float* xst, float* dsh, fl
 #pragma unroll
     for (int kb = 0; kb < KT / 4; ++kb) {
         const int kk = 4 * kb + g;
-        const float av = kk < ED ? sst[u * SS + kk] : xst[u * XS + (kk - ED)];
+        float av = kk < ED ? sst[u * SS + kk] : xst[u * XS + (kk - ED)];
+        if (MF && kk < ED) av = tanhf_(av);
         acc = mfma16x4(av, blin[kb], acc);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int t = 4 * g + i;
-        const float f = tanhf_(acc[i] + bias_u);
+        const float f = MF ? acc[i] + bias_u : tanhf_(acc[i] + bias_u);
         const float res = sst[(t + 1) * SS + u] - f;
-        dsh[t * ED + u] = (first && t == 0) ? 0.f : 1.f - f * f;
+        float d;
+        if (MF) {
+            const float th = tanhf_(sst[t * SS + u]);
+            d = 1.f - th * th;
+        } else {
+            d = 1.f - f * f;
+        }
+        dsh[t * ED + u] = (first && t == 0) ? 0.f : d;
         rsh[t * ED + u] = res;
         if (track && t < len && !res64) rm = max(rm, absbits(res));
     }
@@ -207,11 +218,13 @@ PN_DEV uint32_t elk_linearise(const float* sst, const float* xst, float* dsh, fl
             const int t = 4 * g + i;
             if (t < len) {
                 double acc64 = (double)bias_u;
-                for (int kk = 0; kk < ED; ++kk)
-                    acc64 += (double)Wm[u * ES + kk] * (double)sst[t * SS + kk];
+                for (int kk = 0; kk < ED; ++kk) {
+                    const double sv = (double)sst[t * SS + kk];
+                    acc64 += (double)Wm[u * ES + kk] * (MF ? tanh(sv) : sv);
+                }
                 for (int kk = 0; kk < DX; ++kk)
                     acc64 += (double)U[u * DX + kk] * (double)xst[t * XS + kk];
-                const double r = (double)sst[(t + 1) * SS + u] - tanh(acc64);
+                const double r = (double)sst[(t + 1) * SS + u] - (MF ? acc64 : tanh(acc64));
                 const double ar = fabs(r);
                 float fr = (float)ar;
                 if ((double)fr < ar) fr = nextafterf(fr, INFINITY);
@@ -223,12 +236,13 @@ PN_DEV uint32_t elk_linearise(const float* sst, const float* xst, float* dsh, fl
     return rm;
 }
 
-// A~_t = diag(d_t) W (its diagonal only for quasi-ELK) into At
+// A~_t = diag(d_t) W (tanh-RNN) or W diag(d_t) (mean-field), its diagonal only for quasi-ELK
+template <bool MF>
 PN_DEV void elk_build_At(float* At, const float* dsh, const float* Wm, int t, bool diag) {
     const int l = threadIdx.x & 63;
     for (int idx = l; idx < ED * ED; idx += 64) {
         const int r = idx / ED, c = idx % ED;
-        At[r * ES + c] = (diag && r != c) ? 0.f : dsh[t * ED + r] * Wm[r * ES + c];
+        At[r * ES + c] = (diag && r != c) ? 0.f : dsh[t * ED + (MF ? c : r)] * Wm[r * ES + c];
     }
     __syncthreads();
 }
@@ -270,7 +284,9 @@ struct ElkArgs {
     int smooth;              // nonzero: the smoother passes apply the step (no replay here)
 };
 
-template <int DX>
+// KF = false: lambda = 0, the filter is the DEER step (Gamma = I): the replay is
+// m = A m - r, the elements are the affine maps (A, b) alone.
+template <int DX, bool MF, bool KF>
 __global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
     constexpr int L = EL;
     constexpr int KT = ED + DX;
@@ -299,10 +315,10 @@ __global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
     float bias_u;
     elk_load_weights<DX>(Wm, blin, bias_u, a.params);
     auto linearise = [&](bool first, int len, bool track) -> uint32_t {
-        return elk_linearise<DX>(sst, xst, dsh, rsh, blin, bias_u, Wm, U, first, len, track,
-                                 a.res64 != 0);
+        return elk_linearise<DX, MF>(sst, xst, dsh, rsh, blin, bias_u, Wm, U, first, len, track,
+                                     a.res64 != 0);
     };
-    auto build_At = [&](int t) { elk_build_At(At, dsh, Wm, t, a.diag != 0); };
+    auto build_At = [&](int t) { elk_build_At<MF>(At, dsh, Wm, t, a.diag != 0); };
 
     for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
         const GroupInfo gr = a.groups[gi];
@@ -329,7 +345,7 @@ __global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
         bool have = false;                       // the group's element holds at least one step
         if (fuse) {                              // filtered state entering the group
             const float* cr = a.gcar + (size_t)gi * ECAR;
-            fetch_mat(Pr, cr);
+            if (KF) fetch_mat(Pr, cr);
             if (l < ED) mr[l] = cr[ED * ED + l];
         }
         for (int kt = 0; kt < gr.ntl; ++kt) {
@@ -353,6 +369,11 @@ __global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
                 }
                 for (int t = 0; t < len; ++t) {
                     build_At(t);
+                    if (!KF) {
+                        if (l < ED) vx[l] = -rsh[t * ED + l];
+                        __syncthreads();
+                        mv16(mr, At, false, mr, 1.f, vx, 1.f);                // m = A m - r
+                    } else {
                     mm16(T1, At, false, Pr, false, 1.f, nullptr, 0.f);        // A P
                     mm16(T2, T1, false, At, true, 1.f, nullptr, 1.f);         // P- = A P A^T + I
                     for (int idx = l; idx < ED * ED; idx += 64) {
@@ -374,6 +395,7 @@ __global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
                     __syncthreads();
                     mv16(vy, At, false, mr, 1.f, vx, 1.f);                    // A m - r
                     mv16(mr, Gm, false, vy, 1.f, nullptr, 0.f);               // m = Gamma (.)
+                    }
                     const float v = l < ED ? sst[(t + 1) * SS + l] + mr[l] : 0.f;
                     const bool rb = __any(l < ED && !(fabsf(v) <= reset_abs));
                     if (l < ED) sst[(t + 1) * SS + l] = rb ? 0.f : v;
@@ -395,6 +417,19 @@ __global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
                 build_At(t);
                 if (l < ED) vx[l] = rsh[t * ED + l];
                 __syncthreads();
+                if (!KF) {
+                    // (A, b) of the step is (A_t, -r_t); composed: A = A_t A, b = A_t b - r_t
+                    if (!have) {
+                        for (int idx = l; idx < EM; idx += 64) Ai[idx] = At[idx];
+                        if (l < ED) bi[l] = -vx[l];
+                        __syncthreads();
+                        have = true;
+                    } else {
+                        mv16(bi, At, false, bi, 1.f, vx, -1.f);
+                        mm16(Ai, At, false, Ai, false, 1.f, nullptr, 0.f);
+                    }
+                    continue;
+                }
                 if (!have) {
                     // leaf (A/(1+lambda), -r/(1+lambda), I/(1+lambda), kappa A^T r, kappa A^T A);
                     // at a sequence head A = 0, which folds in the prior Delta_0 = 0
@@ -432,11 +467,13 @@ __global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
         // ---- the group's element
         float* ge = a.gel + (size_t)gi * EGEL;
         store_mat(ge, Ai);
-        store_mat(ge + ED * ED, Ci);
-        store_mat(ge + 2 * ED * ED, Ji);
+        if (KF) {
+            store_mat(ge + ED * ED, Ci);
+            store_mat(ge + 2 * ED * ED, Ji);
+        }
         if (l < ED) {
             ge[3 * ED * ED + l] = bi[l];
-            ge[3 * ED * ED + ED + l] = ei[l];
+            if (KF) ge[3 * ED * ED + ED + l] = ei[l];
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
@@ -530,6 +567,62 @@ __global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__
     }
 }
 
+// ---- carry pass of the DEER step (lambda = 0): m' = A m + b per group -------------------------
+// One wave per sequence; lane (r, q) = (l & 15, l >> 4) holds A[r][4q .. 4q+3] of the group
+// being applied, every lane m[r]; the next group's (A, b) is fetched one group ahead.
+__global__ void __launch_bounds__(64) elk_deer_carry_kernel(const float* __restrict__ gel,
+                                                            float* __restrict__ gcar,
+                                                            const Ctrl* ctrl, SeqState* seq,
+                                                            const int32_t* group_start,
+                                                            const uint32_t* grmax, int freeze,
+                                                            int B) {
+    if (ld_i32(&ctrl->all_done)) return;
+    const int b = blockIdx.x;
+    if (b >= B || seq[b].status != kActive) return;
+    const int l = threadIdx.x, r = l & 15, q = l >> 4;
+    const int g0 = group_start[b], G = group_start[b + 1] - g0;
+    int gstart = 0;
+    if (freeze) {
+        const uint32_t tolb = __float_as_uint(ctrl->tol);
+        int fz = G;
+        for (int base = 0; base < G; base += 64) {
+            const bool open = base + l < G && !(grmax[g0 + base + l] < tolb);
+            const uint64_t mk = __ballot(open);
+            if (mk) {
+                fz = base + __ffsll((unsigned long long)mk) - 1;
+                break;
+            }
+        }
+        const int old = seq[b].frozen;
+        gstart = max(fz, old);
+        __syncthreads();
+        if (l == 0) {
+            seq[b].frozen_prev = old;
+            seq[b].frozen = gstart;
+        }
+    }
+    float m = 0.f;
+    float4 an = make_float4(0.f, 0.f, 0.f, 0.f);
+    float bn = 0.f;
+    auto load = [&](int gg, float4& av, float& bv) {
+        const float* e = gel + (size_t)(g0 + gg) * EGEL;
+        av = *(const float4*)(e + r * ED + 4 * q);
+        bv = e[3 * ED * ED + r];
+    };
+    if (gstart < G) load(gstart, an, bn);
+    for (int gg = gstart; gg < G; ++gg) {
+        const float4 ac = an;
+        const float bc = bn;
+        if (gg + 1 < G) load(gg + 1, an, bn);
+        if (q == 0) gcar[(size_t)(g0 + gg) * ECAR + ED * ED + r] = m;
+        float acc = ac.x * __shfl(m, 4 * q) + ac.y * __shfl(m, 4 * q + 1) +
+                    ac.z * __shfl(m, 4 * q + 2) + ac.w * __shfl(m, 4 * q + 3);
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        m = acc + bc;
+    }
+}
+
 // ---- smoother (the exact LM step): RTS backward pass -----------------------------------------
 // With the filtered means and covariances (m_t, P_t) and the predictions (m-_t, P-_t),
 //   E_t = P_t A_{t+1}^T (P-_{t+1})^-1,   g_t = m_t - E_t m-_{t+1},   m^s_t = E_t m^s_{t+1} + g_t,
@@ -560,7 +653,7 @@ struct ElkSmArgs {
     int diag;
 };
 
-template <int DX>
+template <int DX, bool MF>
 __global__ void __launch_bounds__(64) elk_smooth_kernel(ElkSmArgs a) {
     constexpr int KT = ED + DX;
     constexpr int SS = ED + 4, XS = DX + 4;
@@ -595,9 +688,10 @@ __global__ void __launch_bounds__(64) elk_smooth_kernel(ElkSmArgs a) {
             __syncthreads();
             elk_stage<DX>(sst, xst, scur, a.s0, a.x, b, row0, len, first);
             __syncthreads();
-            elk_linearise<DX>(sst, xst, dsh, rsh, blin, bias_u, Wm, U, first, len, false, false);
+            elk_linearise<DX, MF>(sst, xst, dsh, rsh, blin, bias_u, Wm, U, first, len, false,
+                                  false);
             for (int t = 0; t < len; ++t) {
-                elk_build_At(At, dsh, Wm, t, a.diag != 0);
+                elk_build_At<MF>(At, dsh, Wm, t, a.diag != 0);
                 if (l < ED) vx[l] = -rsh[t * ED + l];
                 mm16(T1, At, false, P, false, 1.f, nullptr, 0.f);         // A P
                 mm16(Pp, T1, false, At, true, 1.f, nullptr, 1.f);         // P- = A P A^T + I
@@ -781,10 +875,11 @@ static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngrou
 
 bool elk_supported(int D, int Dx) { return D == ED && Dx == 16; }
 
-static int elk_resident() {
+static int elk_resident(bool kf) {
+    const void* k = kf ? (const void*)elk_local_kernel<16, false, true>
+                       : (const void*)elk_local_kernel<16, false, false>;
     int occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)elk_local_kernel<16>, 64, 0) !=
-            hipSuccess || occ < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 64, 0) != hipSuccess || occ < 1)
         occ = 1;
     return cu_count() * occ;
 }
@@ -792,11 +887,13 @@ static int elk_resident() {
 // Chunks per group.  An explicit tile (a multiple of 16 steps) fixes it.  Otherwise a cost
 // model picks it: the local pass takes rounds * gt chunks of latency (rounds = groups per
 // resident workgroup), the carry pass one element application per group of the longest
-// sequence; a chunk of the local pass (replay and fold) costs about kLocalPerCarry carry steps.
-static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, int tile) {
+// sequence; a chunk of the local pass (replay and fold) costs about kLocalPerCarry carry steps
+// (measured: the Kalman passes, and the DEER passes of lambda = 0).
+static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, int tile,
+                           bool kf) {
     if (tile > 0) return tile / EL;
-    constexpr double kLocalPerCarry = 36.0;
-    const int resident = elk_resident();
+    const double kLocalPerCarry = kf ? 36.0 : 100.0;
+    const int resident = elk_resident(kf);
     int maxc = 0;
     for (int b = 0; b < hb.B; ++b) maxc = std::max(maxc, ts[b + 1] - ts[b]);
     int best = 1;
@@ -810,10 +907,16 @@ static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, 
     return best;
 }
 
+// lambda is not known here: room for the grouping of either pass family
 size_t elk_workspace(int, int, const HostBatch& hb, const pn_opts& o) {
     const std::vector<int32_t> ts = tile_starts(hb, EL);
-    const int gt = elk_group_tiles(hb, ts, o.tile);
-    return elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt), o.smooth != 0).bytes;
+    size_t n = 0;
+    for (int kf = 0; kf < 2; ++kf) {
+        const int gt = elk_group_tiles(hb, ts, o.tile, kf != 0);
+        n = std::max(n, elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt),
+                                   o.smooth != 0).bytes);
+    }
+    return n;
 }
 
 pn_status residual64_device(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
@@ -823,11 +926,17 @@ pn_status residual64_device(const pn_cell_desc& cd, const HostBatch& hb, const f
 pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
                       const float* s0, float* s, double lambda, const pn_opts& o, void* ws,
                       hipStream_t stream, pn_seq_info* info, bool* all_conv) {
-    void (*kern)(ElkArgs) = elk_local_kernel<16>;
+    const bool mf = cd.cell == PN_CELL_MEANFIELD;
+    // the Kalman machinery is needed unless lambda = 0 (the smoother needs the covariances)
+    const bool kf = lambda > 0 || o.smooth != 0;
+    void (*kern)(ElkArgs) =
+        mf ? (kf ? elk_local_kernel<16, true, true> : elk_local_kernel<16, true, false>)
+           : (kf ? elk_local_kernel<16, false, true> : elk_local_kernel<16, false, false>);
+    void (*skern)(ElkSmArgs) = mf ? elk_smooth_kernel<16, true> : elk_smooth_kernel<16, false>;
     const std::vector<int32_t> ts = tile_starts(hb, EL);
     const int ntiles = ts[hb.B];
-    const int resident = elk_resident();
-    const int gt = elk_group_tiles(hb, ts, o.tile);
+    const int resident = elk_resident(kf);
+    const int gt = elk_group_tiles(hb, ts, o.tile, kf);
     const int ngroups = count_groups(ts, hb.B, gt);
     const bool smooth = o.smooth != 0;
     ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups, smooth);
@@ -888,14 +997,15 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
         });
         prof_launch("elk_carry", st, [&](hipStream_t s2) {
-            hipLaunchKernelGGL(elk_carry_kernel, dim3(std::max(1, hb.B)), dim3(64), 0, s2,
+            hipLaunchKernelGGL(kf ? elk_carry_kernel : elk_deer_carry_kernel,
+                               dim3(std::max(1, hb.B)), dim3(64), 0, s2,
                                (const float*)lay.gel, lay.gcar, (const Ctrl*)lay.st.ctrl,
                                lay.st.seq, (const int32_t*)lay.st.group_start,
                                (const uint32_t*)lay.grmax, args.freeze, hb.B);
         });
         if (smooth) {
             prof_launch("elk_smooth", st, [&](hipStream_t s2) {
-                hipLaunchKernelGGL(elk_smooth_kernel<16>, dim3(grid), dim3(64), 0, s2, sm);
+                hipLaunchKernelGGL(skern, dim3(grid), dim3(64), 0, s2, sm);
             });
             prof_launch("elk_back_carry", st, [&](hipStream_t s2) {
                 hipLaunchKernelGGL(elk_back_carry_kernel, dim3(std::max(1, hb.B)), dim3(64), 0,

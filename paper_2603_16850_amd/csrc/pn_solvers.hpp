@@ -58,6 +58,12 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
                        const float* s0, const float* s, const float* gs, float* gx, float* gs0,
                        float* gparams, void* ws, hipStream_t stream);
 
+// largest Lyapunov exponent along a trajectory
+bool lle_supported(int cell, int D, int Dx);
+size_t lle_workspace(const HostBatch& hb);
+pn_status lle_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x, const float* s0,
+                  const float* s, const float* u0, void* ws, hipStream_t stream, double* lle);
+
 // FP64 residual of an FP32 trajectory
 bool residual64_supported(int cell, int D, int Dx);
 size_t residual64_workspace(int cell, int D, int Dx, const HostBatch& hb);

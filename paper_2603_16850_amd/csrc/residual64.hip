@@ -29,14 +29,16 @@ __global__ void residual64_kernel(const float* x, const float* s0, const float* 
         double rmax = 0.0;
         for (int j = 0; j < D; ++j) {
             double f;
-            if (CELL == PN_CELL_TANH) {
+            if (CELL == PN_CELL_TANH || CELL == PN_CELL_MEANFIELD) {
                 const float* W = params;
                 const float* U = W + D * D;
                 const float* bb = U + D * Dx;
                 double acc = bb[j];
-                for (int k = 0; k < D; ++k) acc += (double)W[j * D + k] * (double)h[k];
+                for (int k = 0; k < D; ++k)
+                    acc += (double)W[j * D + k] *
+                           (CELL == PN_CELL_TANH ? (double)h[k] : tanh((double)h[k]));
                 for (int k = 0; k < Dx; ++k) acc += (double)U[j * Dx + k] * (double)xv[k];
-                f = tanh(acc);
+                f = CELL == PN_CELL_TANH ? tanh(acc) : acc;
             } else {
                 const float* W = params;
                 const float* U = W + 3 * D * Dx;
@@ -68,7 +70,8 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 }
 
 bool residual64_supported(int cell, int D, int Dx) {
-    return (cell == PN_CELL_TANH || cell == PN_CELL_GRU) && D >= 1 && D <= 256 && Dx >= 1 &&
+    return (cell == PN_CELL_TANH || cell == PN_CELL_GRU || cell == PN_CELL_MEANFIELD) && D >= 1 &&
+           D <= 256 && Dx >= 1 &&
            Dx <= 256;
 }
 
@@ -94,6 +97,10 @@ pn_status residual64_device(const pn_cell_desc& cd, const HostBatch& hb, const f
             hipLaunchKernelGGL(residual64_kernel<PN_CELL_TANH>, dim3(grid), dim3(256), 0, stream, x,
                                s0, s, (const float*)cd.params, (const int64_t*)doff, hb.B, cd.D,
                                cd.Dx, out);
+        else if (cd.cell == PN_CELL_MEANFIELD)
+            hipLaunchKernelGGL(residual64_kernel<PN_CELL_MEANFIELD>, dim3(grid), dim3(256), 0,
+                               stream, x, s0, s, (const float*)cd.params, (const int64_t*)doff,
+                               hb.B, cd.D, cd.Dx, out);
         else
             hipLaunchKernelGGL(residual64_kernel<PN_CELL_GRU>, dim3(grid), dim3(256), 0, stream, x,
                                s0, s, (const float*)cd.params, (const int64_t*)doff, hb.B, cd.D,

@@ -94,7 +94,9 @@ __global__ void __launch_bounds__(4 * D) gru_seq_kernel(const float* P, const fl
     }
 }
 
-template <int D>
+// tanh-RNN (MF = false): s_t = tanh(W s_{t-1} + P_t); mean-field RNN (MF = true):
+// s_t = W tanh(s_{t-1}) + P_t, with tanh(s) kept in LDS as the next step's operand
+template <int D, bool MF>
 __global__ void __launch_bounds__(D < 64 ? 64 : D) tanh_seq_kernel(const float* P,
                                                                    const float* s0,
                                                                    const float* W, float* s,
@@ -108,7 +110,7 @@ __global__ void __launch_bounds__(D < 64 ? 64 : D) tanh_seq_kernel(const float* 
     float w[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) w[k] = j < D ? W[j * D + k] : 0.f;
-    if (j < D) hbuf[0][j] = s0[(size_t)b * D + j];
+    if (j < D) hbuf[0][j] = MF ? tanhf_(s0[(size_t)b * D + j]) : s0[(size_t)b * D + j];
     __syncthreads();
     for (int64_t t = 0; t < T; ++t) {
         if (t % CH == 0) {
@@ -127,9 +129,14 @@ __global__ void __launch_bounds__(D < 64 ? 64 : D) tanh_seq_kernel(const float* 
                 const float4 h4 = *(const float4*)(h + k);
                 acc += w[k] * h4.x + w[k + 1] * h4.y + w[k + 2] * h4.z + w[k + 3] * h4.w;
             }
-            const float hn = tanhf_(acc);
-            hbuf[cur ^ 1][j] = hn;
-            s[(size_t)(r0 + t) * D + j] = hn;
+            if (MF) {
+                hbuf[cur ^ 1][j] = tanhf_(acc);
+                s[(size_t)(r0 + t) * D + j] = acc;
+            } else {
+                const float hn = tanhf_(acc);
+                hbuf[cur ^ 1][j] = hn;
+                s[(size_t)(r0 + t) * D + j] = hn;
+            }
         }
         __syncthreads();
     }
@@ -154,12 +161,12 @@ static SeqKern seq_gru_get() {
     k.nt = 4 * D;
     return k;
 }
-template <int D, int DX>
+template <int D, int DX, bool MF = false>
 static SeqKern seq_tanh_get() {
     SeqKern k{};
     k.xproj = xproj_kernel<D, DX>;
     k.O = D;
-    k.tanh = tanh_seq_kernel<D>;
+    k.tanh = tanh_seq_kernel<D, MF>;
     k.nt = D < 64 ? 64 : D;
     return k;
 }
@@ -174,6 +181,8 @@ static bool seq_lookup(int cell, int D, int Dx, SeqKern* k) {
 #define PN_ST(d, dx) if (D == d && Dx == dx) { *k = seq_tanh_get<d, dx>(); return true; }
         PN_ST(16, 16) PN_ST(32, 16) PN_ST(32, 32) PN_ST(64, 32) PN_ST(16, 8) PN_ST(4, 4)
 #undef PN_ST
+    } else if (cell == PN_CELL_MEANFIELD) {
+        if (D == 16 && Dx == 16) { *k = seq_tanh_get<16, 16, true>(); return true; }
     }
     return false;
 }

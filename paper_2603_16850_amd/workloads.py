@@ -11,6 +11,11 @@ Every draw uses ``numpy.random.default_rng(seed)`` (PCG64) in float64 and a fixe
   4. inputs x [N, Dx] ~ N(0, 1), sequences back to back.
 The initial state s_0 and the initial guess are zero.
 
+The mean-field RNN (cell "meanfield", Ch. 5 predictability experiments) draws W (D x D) ~
+N(0, g^2/D) with its diagonal then set to zero (no self-coupling), takes U = I (Dx = D) and
+zero biases, drives every sequence by the mild sinusoid x_t[i] = 0.1 sin(0.05 t + i) (t the
+step within the sequence, no draw), and draws s_0 [B, D] ~ N(0, 1) after W.
+
 These are the shapes of the thesis's synthetic "untrained GRU" evaluation benchmark (a
 randomly initialised GRU, Ch. 3) and of its mean-field tanh RNN family, whose gain g sets
 the regime (predictable for g < 1, chaotic above; Ch. 5).
@@ -24,7 +29,7 @@ import numpy as np
 @dataclass(frozen=True)
 class Workload:
     name: str
-    cell: str                 # "gru" | "tanh"
+    cell: str                 # "gru" | "tanh" | "meanfield"
     D: int
     Dx: int
     B: int
@@ -56,6 +61,11 @@ TANH16_ELK = Workload("tanh16-elk-chaotic", "tanh", D=16, Dx=16, B=8, T=8192,
                       lambdas=(1e-2, 1e-1, 1.0))
 GRU48_RAGGED = Workload("gru48-ragged-quasi", "gru", D=48, Dx=24, B=256,
                         t_min=512, t_max=32768, jac="diag", tol=1e-5, backward=True)
+
+# The mean-field RNN of the LLE-threshold sweep (Ch. 5): DEER (ELK with lambda = 0), T = 1000
+# (the length the thesis highlights), the gain g swept per run.
+MEANFIELD16 = Workload("meanfield16-lle-sweep", "meanfield", D=16, Dx=16, B=1, T=1000,
+                       gain=1.0, method="deer", jac="dense", tol=1e-5)
 
 ALL = {w.name: w for w in (GRU4_DENSE_F64, GRU64_QUASI, TANH32_DENSE_BF16, TANH16_ELK,
                            GRU48_RAGGED)}
@@ -93,6 +103,10 @@ def draw_params(rng, work: Workload):
         U = [rng.normal(0.0, sd, size=(D, D)) for _ in range(3)]
         return np.concatenate([w.ravel() for w in W] + [u.ravel() for u in U]
                               + [np.zeros(3 * D), np.zeros(D)])
+    if work.cell == "meanfield":
+        W = rng.normal(0.0, work.gain / np.sqrt(D), size=(D, D))
+        np.fill_diagonal(W, 0.0)
+        return np.concatenate([W.ravel(), np.eye(D, Dx).ravel(), np.zeros(D)])
     if work.cell == "tanh":
         W = rng.normal(0.0, work.gain / np.sqrt(D), size=(D, D))
         U = rng.normal(0.0, np.sqrt(1.0 / D), size=(D, Dx))
@@ -108,6 +122,11 @@ def make_instance(work: Workload, seed: int = 0, lengths: Optional[np.ndarray] =
     params = draw_params(rng, work)
     offsets = np.zeros(lens.size + 1, dtype=np.int64)
     np.cumsum(lens, out=offsets[1:])
+    if work.cell == "meanfield":
+        steps = np.concatenate([np.arange(n) for n in lens]) if lens.size else np.zeros(0)
+        x = 0.1 * np.sin(0.05 * steps[:, None] + np.arange(work.Dx)[None, :])
+        s0 = rng.standard_normal(size=(lens.size, work.D))
+        return Instance(work, params, x, s0, offsets, seed)
     x = rng.standard_normal(size=(int(offsets[-1]), work.Dx))
     s0 = np.zeros((lens.size, work.D))
     return Instance(work, params, x, s0, offsets, seed)
