@@ -329,17 +329,21 @@ def _timed(torch, fn, reps=3):
 
 def measure_rows(torch, pn, workloads):
     """The other workloads and method variants: wall time per call, iterations, and the error
-    against the oracle's sequential rollout (or the FP64 residual where the trajectory is the
-    unique answer only up to FP32 round-off).  Inputs are seed 0 of each workload."""
-    from oracle import cells, rollout
+    against the sequential GPU rollout of the same FP32 inputs (max |s - s_seq| / max |s_seq|;
+    on the chaotic tanh instance two FP32 evaluations differ by ~1e-5, and there the FP64
+    residual below tol is the criterion).  Inputs are seed 0 of each workload."""
     rows = {}
     dev = "cuda"
+
+    def done(name):
+        print(f"rows: {name} done", file=sys.stderr, flush=True)
 
     def tens(inst, dtype=torch.float32):
         return tuple(torch.tensor(v, dtype=dtype, device=dev) for v in (inst.x, inst.s0, inst.params))
 
     def rel(a, b):
-        return float(np.abs(a.detach().cpu().double().numpy() - b).max() / max(np.abs(b).max(), 1e-30))
+        a, b = a.detach().double(), b.detach().double()
+        return float((a - b).abs().max() / b.abs().max().clamp_min(1e-30))
 
     # dense DEER, GRU D = 4, FP64 (one workgroup per sequence, whole loop on chip)
     w = workloads.GRU4_DENSE_F64
@@ -347,48 +351,79 @@ def measure_rows(torch, pn, workloads):
     x, s0, p = tens(inst, torch.float64)
     ms, (s, info) = _timed(torch, lambda: pn.deer_solve(x, s0, p, cell="gru", offsets=inst.offsets,
                                                         jac="dense", tol=w.tol))
-    ref = rollout.rollout_batch(cells.GRU(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
-    rows[w.name] = {"ms": round(ms, 3), "iters": [i["iters"] for i in info], "err": rel(s, ref),
+    rows[w.name] = {"ms": round(ms, 3), "iters": [i["iters"] for i in info],
+                    "max_resid_f64": max(i["max_resid"] for i in info),
                     "steps_per_s": round(inst.N / (ms * 1e-3), 1)}
 
+    done('section 1')
     # dense DEER, tanh D = 32: BF16 and FP32 compose, vs the sequential GPU rollout
     w = workloads.TANH32_DENSE_BF16
     inst = workloads.make_instance(w, seed=0)
     x, s0, p = tens(inst)
-    ref = rollout.rollout_batch(cells.TanhRNN(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
     seq_ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="tanh", offsets=inst.offsets))
-    r = {"sequential_ms": round(seq_ms, 3), "sequential_err": rel(s_seq, ref)}
+    r = {"sequential_ms": round(seq_ms, 3)}
     for comp in ("bf16", "native"):
         ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
             x, s0, p, cell="tanh", offsets=inst.offsets, jac="dense", compose=comp, tol=1e-6))
         r[comp] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
-                   "err": rel(s, ref), "steps_per_s": round(inst.N / (ms * 1e-3), 1),
+                   "err_vs_sequential": rel(s, s_seq), "steps_per_s": round(inst.N / (ms * 1e-3), 1),
                    "speedup_vs_sequential": round(seq_ms / ms, 2)}
     ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
         x, s0, p, cell="tanh", offsets=inst.offsets, jac="dense", tol=1e-6, damping="scale",
         damp_k=0.2))
     r["scale_elk_k0.2"] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
-                           "err": rel(s, ref)}
+                           "err_vs_sequential": rel(s, s_seq)}
     rows[w.name] = r
 
-    # ELK and quasi-ELK, tanh D = 16, FP64 stopping residual
+    done('section 2')
+    # ELK, quasi-ELK, DEER, converged-prefix skipping: tanh D = 16, FP64 stopping residual
     w = workloads.TANH16_ELK
     inst = workloads.make_instance(w, seed=0)
     x, s0, p = tens(inst)
-    ref = rollout.rollout_batch(cells.TanhRNN(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
-    seq_ms, _ = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="tanh", offsets=inst.offsets))
+    seq_ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="tanh", offsets=inst.offsets))
     r = {"sequential_ms": round(seq_ms, 3)}
+
+    def elk_row(lam, **kw):
+        ms, (s, info) = _timed(torch, lambda: pn.elk_solve(
+            x, s0, p, lam, cell="tanh", offsets=inst.offsets, tol=w.tol,
+            fp64_final_residual=True, **kw), reps=1)
+        return {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
+                "converged": all(i["converged"] for i in info),
+                "max_resid_f64": max(i["max_resid"] for i in info),
+                "err_vs_sequential": rel(s, s_seq)}
     for jac, name in (("dense", "elk"), ("diag", "quasi_elk")):
         for lam in w.lambdas:
-            ms, (s, info) = _timed(torch, lambda: pn.elk_solve(
-                x, s0, p, lam, cell="tanh", offsets=inst.offsets, jac=jac, tol=w.tol,
-                fp64_final_residual=True), reps=1)
-            r[f"{name}_lambda{lam:g}"] = {
-                "ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
-                "converged": all(i["converged"] for i in info),
-                "max_resid_f64": max(i["max_resid"] for i in info), "err": rel(s, ref)}
+            r[f"{name}_lambda{lam:g}"] = elk_row(lam, jac=jac)
+    r["deer_lambda0"] = elk_row(0.0, jac="dense")
+    for lam in w.lambdas:
+        r[f"elk_lambda{lam:g}_freeze_prefix"] = elk_row(lam, jac="dense", freeze_prefix=True)
     rows[w.name] = r
 
+    done('section 3')
+    # ELK filter vs smoother (the exact LM step) on the contracting variant (gain 0.9)
+    w9 = w.scaled(gain=0.9)
+    inst = workloads.make_instance(w9, seed=0)
+    x, s0, p = tens(inst)
+    seq_ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="tanh", offsets=inst.offsets))
+    rows["tanh16 gain 0.9 ELK lambda 0.1"] = {
+        "sequential_ms": round(seq_ms, 3), "filter": elk_row(0.1, jac="dense"),
+        "smoother": elk_row(0.1, jac="dense", smooth=True)}
+
+    done('section 4')
+    # mean-field RNN, DEER (lambda = 0) in the predictable regime, T = 10000
+    wm = workloads.MEANFIELD16.scaled(gain=0.5, T=10000)
+    inst = workloads.make_instance(wm, seed=0)
+    x, s0, p = tens(inst)
+    seq_ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="meanfield",
+                                                         offsets=inst.offsets))
+    ms, (s, info) = _timed(torch, lambda: pn.elk_solve(
+        x, s0, p, 0.0, cell="meanfield", offsets=inst.offsets, jac="dense", tol=wm.tol))
+    rows["meanfield16 g=0.5 T=10000 DEER"] = {
+        "ms": round(ms, 3), "sequential_ms": round(seq_ms, 3),
+        "speedup_vs_sequential": round(seq_ms / ms, 2), "iters": info[0]["iters"],
+        "err_vs_sequential": rel(s, s_seq)}
+
+    done('section 5')
     # ragged GRU batch: forward + backward as the main line
     w = workloads.GRU48_RAGGED
     inst = workloads.make_instance(w, seed=0)
@@ -405,38 +440,43 @@ def measure_rows(torch, pn, workloads):
         s = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
         pn.seq_bptt(x, s0, p, s, 2.0 * s, cell="gru", offsets=inst.offsets)
         return s
-    seq_ms, _ = _timed(torch, seqfb, reps=1)
+    seq_ms, s_seq = _timed(torch, seqfb, reps=1)
     rows[w.name] = {"fwd_bwd_ms": round(ms, 3), "steps_per_s": round(inst.N / (ms * 1e-3), 1),
                     "sequential_ms": round(seq_ms, 3), "speedup_vs_sequential": round(seq_ms / ms, 2),
                     "iters_fwd_max": max(i["iters"] for i in fi),
-                    "iters_bwd_max": max(i["iters"] for i in bi), "N": int(inst.N)}
+                    "iters_bwd_max": max(i["iters"] for i in bi), "N": int(inst.N),
+                    "err_vs_sequential": rel(s, s_seq)}
 
+    done('section 6')
     # transition variants on the GRU path (benchmark shapes, forward only)
     w = workloads.GRU64_QUASI
     inst = workloads.make_instance(w, seed=0)
     x, s0, p = tens(inst)
-    ref = rollout.rollout_batch(cells.GRU(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
+    s_seq = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
     r = {}
     for name, extra in (("quasi", {}), ("scale_k0.2", dict(damping="scale", damp_k=0.2)),
                         ("clip", dict(damping="clip"))):
         ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
             x, s0, p, cell="gru", offsets=inst.offsets, jac="diag", tol=1e-6, **extra), reps=2)
         r[name] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
-                   "err": rel(s, ref)}
+                   "err_vs_sequential": rel(s, s_seq)}
     rows["gru64 transitions"] = r
 
+    done('section 7')
     # Picard / Jacobi / quasi-DEER iteration counts (Table fxd_pt_sum) on a short GRU batch
     w = workloads.GRU64_QUASI.scaled(B=16, T=512)
     inst = workloads.make_instance(w, seed=0)
     x, s0, p = tens(inst)
-    ref = rollout.rollout_batch(cells.GRU(inst.params, w.D, w.Dx), inst.x, inst.s0, inst.offsets)
+    s_seq = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
     r = {}
     for jac in ("diag", "picard", "jacobi"):
         ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
             x, s0, p, cell="gru", offsets=inst.offsets, jac=jac, tol=1e-6), reps=1)
         r[jac] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
-                  "converged": all(i["converged"] for i in info), "err": rel(s, ref)}
+                  "converged": all(i["converged"] for i in info),
+                  "err_vs_sequential": rel(s, s_seq)}
     rows["gru64 T=512 fixed-point methods"] = r
+    done("last section")
     return rows
 
 
