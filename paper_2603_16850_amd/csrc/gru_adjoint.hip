@@ -445,7 +445,9 @@ gru_adj_local_kernel(GruAdjArgs a) {
 // ---- gradients: per-workgroup partials of dW, dU, db on MFMA; dx rows --------------------
 // Output tiles of the parameter GEMMs (16 x 16 each): for each gate block G in {z, r, n}
 // and unit block ib:  dU_G[ib] x (h blocks)  and  dW_G[ib] x (x blocks).  dU_n pairs with
-// delta_q = beta * lambda, dW_n with delta_n = eps * lambda.
+// delta_q = beta * lambda, dW_n with delta_n = eps * lambda.  Wave w owns unit block ib = w
+// (D / 16 waves, D / 16 blocks): per 4-step K slice it reads its four delta operands and the
+// h / x operands once and issues all 3 (HB + XB) MFMAs of its tiles.
 template <int D, int DX>
 struct GradTiles {
     static constexpr int IB = D / 16;
@@ -462,7 +464,6 @@ gru_adj_grad_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
     using TT = GradTiles<D, DX>;
     constexpr int NW = C::NW;
-    constexpr int PER_W = (TT::TOTAL + NW - 1) / NW;
     constexpr int DS = 4 * D + 4;        // delta tile stride: [dz | dr | dq | dn]
     constexpr int XSP = C::DXP + 4;
     constexpr int WS = C::DXP + 4;       // row stride of W in LDS
@@ -471,11 +472,20 @@ gru_adj_grad_kernel(GruAdjArgs a) {
     __shared__ __attribute__((aligned(16))) float xsm[L * XSP];
     __shared__ __attribute__((aligned(16))) float wsm[3 * D * WS];   // [W_z;W_r;W_n], for dx
 
+    static_assert(TT::IB == NW, "one unit block per wave");
+    constexpr int HB = TT::HB, XB = TT::XB;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
-    floatx4 acc[PER_W];
+    floatx4 acc[3][HB + XB];                // [gate][h blocks | x blocks] of unit block w
 #pragma unroll
-    for (int q = 0; q < PER_W; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bsum[4] = {0.f, 0.f, 0.f, 0.f};   // bias partials of unit tid % D (tid < D only)
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int c = 0; c < HB + XB; ++c) acc[q][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // bias partial of (delta column bcol, unit bu): threads cover the 4 D bias entries
+    // [z | r | n | q-part of n]: entry e = tid, tid + NT, ... reads delta column {0, D, 3D, 2D}
+    constexpr int NBE = (4 * D + C::NT - 1) / C::NT;
+    float bsum[NBE];
+#pragma unroll
+    for (int i = 0; i < NBE; ++i) bsum[i] = 0.f;
     const float* W = a.params;              // [W_z;W_r;W_n] (3D x DX)
     for (int idx = tid; idx < 3 * D * C::DXP; idx += C::NT) {
         const int r = idx / C::DXP, c = idx % C::DXP;
@@ -553,54 +563,65 @@ gru_adj_grad_kernel(GruAdjArgs a) {
             if (idx < L * QX) *(float4*)(xsm + (idx / QX) * XSP + 4 * (idx % QX)) = vx[i];
         }
         __syncthreads();
-        // bias partials: thread owns unit tid % D, steps tid / D + k * (NT / D)
-        if (tid < D) {
-            for (int tl = 0; tl < L; ++tl) {
-                const float* dr_ = dl + tl * DS;
-                bsum[0] += dr_[tid];
-                bsum[1] += dr_[D + tid];
-                bsum[2] += dr_[3 * D + tid];
-                bsum[3] += dr_[2 * D + tid];
+        // bias partials (every thread, its NBE entries)
+#pragma unroll
+        for (int i = 0; i < NBE; ++i) {
+            const int e = tid + i * C::NT;
+            if (e < 4 * D) {
+                const int k4 = e / D, bu = e % D;
+                const int bcol = k4 == 0 ? 0 : (k4 == 1 ? D : (k4 == 2 ? 3 * D : 2 * D));
+                float sacc = 0.f;
+#pragma unroll 8
+                for (int tl = 0; tl < L; ++tl) sacc += dl[tl * DS + bcol + bu];
+                bsum[i] += sacc;
             }
         }
-        // parameter GEMM: K = steps, 4 per MFMA
+        // parameter GEMM of unit block w: K = steps, 4 per MFMA
+        const float* dlw = dl + 16 * w + u;
 #pragma unroll 2
         for (int kq = 0; kq < L / 4; ++kq) {
             const int tstep = 4 * kq + g;       // step of this lane's K slot
+            const float* dr_ = dlw + tstep * DS;
+            const float az = dr_[0], ar = dr_[D], aq = dr_[2 * D], an = dr_[3 * D];
+            float bh[HB], bx[XB];
 #pragma unroll
-            for (int q = 0; q < PER_W; ++q) {
-                const int o = w + q * NW;
-                if (o >= TT::TOTAL) break;
-                const int gate = o / TT::PER_GATE;
-                const int rem = o % TT::PER_GATE;
-                const int ib = rem / (TT::HB + TT::XB);
-                const int cb = rem % (TT::HB + TT::XB);
-                const int dcol = (gate == 0 ? 0 : (gate == 1 ? D : (cb < TT::HB ? 2 * D : 3 * D)));
-                const float av = dl[tstep * DS + dcol + 16 * ib + u];
-                const float bv = cb < TT::HB ? hsm[tstep * C::HS + 16 * cb + u]
-                                             : xsm[tstep * XSP + 16 * (cb - TT::HB) + u];
-                acc[q] = mfma16x4(av, bv, acc[q]);
+            for (int c = 0; c < HB; ++c) bh[c] = hsm[tstep * C::HS + 16 * c + u];
+#pragma unroll
+            for (int c = 0; c < XB; ++c) bx[c] = xsm[tstep * XSP + 16 * c + u];
+#pragma unroll
+            for (int c = 0; c < HB; ++c) {
+                acc[0][c] = mfma16x4(az, bh[c], acc[0][c]);
+                acc[1][c] = mfma16x4(ar, bh[c], acc[1][c]);
+                acc[2][c] = mfma16x4(aq, bh[c], acc[2][c]);
+            }
+#pragma unroll
+            for (int c = 0; c < XB; ++c) {
+                acc[0][HB + c] = mfma16x4(az, bx[c], acc[0][HB + c]);
+                acc[1][HB + c] = mfma16x4(ar, bx[c], acc[1][HB + c]);
+                acc[2][HB + c] = mfma16x4(an, bx[c], acc[2][HB + c]);
             }
         }
-        // dx rows: dx_t = W_z^T dz + W_r^T dr + W_n^T dn  (K = 3D, N = DX)
+        // dx rows: dx_t = W_z^T dz + W_r^T dr + W_n^T dn  (K = 3D, N = DX); one 16 x 16 output
+        // tile (step block mb, column block nb) per wave
         if (a.gx) {
-            for (int mb = w; mb < C::MB; mb += NW) {
-                for (int nb = 0; nb < C::DXP / 16; ++nb) {
-                    floatx4 o4 = {0.f, 0.f, 0.f, 0.f};
-                    const int n = 16 * nb + u;
-                    for (int kq = 0; kq < 3 * D / 4; ++kq) {
-                        const int kk = 4 * kq + g;                  // 0..3D-1 over z | r | n
-                        const int gate = kk / D, ii = kk % D;
-                        const int dcol = gate == 0 ? 0 : (gate == 1 ? D : 3 * D);
-                        const float av = dl[(mb * 16 + u) * DS + dcol + 4 * kq + g - gate * D];
-                        const float bv = wsm[(gate * D + ii) * WS + n];
-                        o4 = mfma16x4(av, bv, o4);
-                    }
+            constexpr int NBX = C::DXP / 16;
+            for (int ot = w; ot < C::MB * NBX; ot += NW) {
+                const int mb = ot / NBX, nb = ot % NBX;
+                floatx4 o4 = {0.f, 0.f, 0.f, 0.f};
+                const int n = 16 * nb + u;
+                const float* arow = dl + (mb * 16 + u) * DS + g;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int tl = mb * 16 + 4 * g + i;
-                        if (tl < len && n < DX) a.gx[(size_t)(row0 + tl) * DX + n] = o4[i];
-                    }
+                for (int gate = 0; gate < 3; ++gate) {
+                    const float* ag = arow + (gate == 0 ? 0 : (gate == 1 ? D : 3 * D));
+                    const float* bg = wsm + (gate * D + g) * WS + n;
+#pragma unroll 4
+                    for (int kq = 0; kq < D / 4; ++kq)
+                        o4 = mfma16x4(ag[4 * kq], bg[4 * kq * WS], o4);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int tl = mb * 16 + 4 * g + i;
+                    if (tl < len && n < DX) a.gx[(size_t)(row0 + tl) * DX + n] = o4[i];
                 }
             }
         }
@@ -610,31 +631,24 @@ gru_adj_grad_kernel(GruAdjArgs a) {
     constexpr int P = 3 * D * DX + 3 * D * D + 4 * D;
     float* part = a.part + (size_t)blockIdx.x * P;
 #pragma unroll
-    for (int q = 0; q < PER_W; ++q) {
-        const int o = w + q * NW;
-        if (o >= TT::TOTAL) break;
-        const int gate = o / TT::PER_GATE;           // 0 z, 1 r, 2 n
-        const int rem = o % TT::PER_GATE;
-        const int ib = rem / (TT::HB + TT::XB);
-        const int cb = rem % (TT::HB + TT::XB);
+    for (int gate = 0; gate < 3; ++gate)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 16 * ib + 4 * g + i;      // unit
-            if (cb < TT::HB) {
-                const int col = 16 * cb + u;
-                part[3 * D * DX + (gate * D + row) * D + col] = acc[q][i];
-            } else {
-                const int col = 16 * (cb - TT::HB) + u;
-                if (col < DX) part[(gate * D + row) * DX + col] = acc[q][i];
+        for (int cb = 0; cb < HB + XB; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * w + 4 * g + i;      // unit
+                if (cb < HB) {
+                    part[3 * D * DX + (gate * D + row) * D + 16 * cb + u] = acc[gate][cb][i];
+                } else {
+                    const int col = 16 * (cb - HB) + u;
+                    if (col < DX) part[(gate * D + row) * DX + col] = acc[gate][cb][i];
+                }
             }
-        }
-    }
-    if (tid < D) {
-        float* pb = part + 3 * D * DX + 3 * D * D;
-        pb[tid] = bsum[0];
-        pb[D + tid] = bsum[1];
-        pb[2 * D + tid] = bsum[2];
-        pb[3 * D + tid] = bsum[3];
+    float* pb = part + 3 * D * DX + 3 * D * D;
+#pragma unroll
+    for (int i = 0; i < NBE; ++i) {
+        const int e = tid + i * C::NT;
+        if (e < 4 * D) pb[e] = bsum[i];
     }
 }
 
@@ -826,8 +840,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.gs = gs;
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
-    args.eps = lay.eps;
     args.zd = lay.zd;
+    args.eps = lay.eps;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     for (int p = 0; p < 2; ++p) args.lac[p] = lay.lac[p];
     args.gagg = lay.gagg;
@@ -933,8 +947,8 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.gs = gs;
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
-    args.eps = lay.eps;
     args.zd = lay.zd;
+    args.eps = lay.eps;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     args.gmax = lay.gmax;
     args.ctrl = lay.st.ctrl;
