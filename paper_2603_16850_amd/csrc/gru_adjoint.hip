@@ -44,11 +44,13 @@ struct GruAdjArgs {
     const float* s;
     const float* gs;
     const float* params;
-    float* gates;            // [N][4][D]: z, alpha, beta, gamma at the solution
-    float* eps;              // [N][D]: (1 - z)(1 - n^2)
+    float* gates;            // [N][4][D]: alpha, beta, gamma, eps = (1 - z)(1 - n^2) at the
+                             // solution (z lives in zd)
     float2* zd;              // [N][D]: (z_t, diag(A_t)) at the solution (the reverse scan's
                              // per-step operands)
     float* lam[2];           // ping-pong adjoint iterates; iteration k reads lam[k & 1]
+                             // (lambda^(0) = g is read from gs, not stored)
+    int lam0_is_g;           // nonzero: a sequence stopped at iteration 0 has lambda = g
     float2* lac[2];          // [N][D] (la, lc) relative to the step's group; iteration k
                              // writes lac[k & 1]
     float2* gagg;            // [ngroups][D] group maps
@@ -73,7 +75,7 @@ struct GruAdjArgs {
     float* gparams;
 };
 
-// ---- prep: gates at the solution, lambda^(0) = g, max |g| ---------------------------------
+// ---- prep: gate values and (z, diag A) at the solution, max |g| -------------------------
 template <int D, int DX, int L>
 __global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gru_adj_prep_kernel(GruAdjArgs a) {
@@ -160,18 +162,16 @@ gru_adj_prep_kernel(GruAdjArgs a) {
                 const float e = (1.f - p.z) * (1.f - p.n * p.n);
                 const size_t row = (size_t)(row0 + tl);
                 float* gr = a.gates + row * 4 * D;
-                gr[0 * D + j] = p.z;
-                gr[1 * D + j] = (h - p.n) * p.z * (1.f - p.z);
-                gr[2 * D + j] = e * p.r;
-                gr[3 * D + j] = e * p.q * p.r * (1.f - p.r);
-                a.eps[row * D + j] = e;
+                const float al = (h - p.n) * p.z * (1.f - p.z);
+                const float be = e * p.r;
+                const float ga = e * p.q * p.r * (1.f - p.r);
+                gr[0 * D + j] = al;
+                gr[1 * D + j] = be;
+                gr[2 * D + j] = ga;
+                gr[3 * D + j] = e;
                 // diag(A_t)_j = z + alpha U_z[j][j] + beta U_n[j][j] + gamma U_r[j][j]
-                a.zd[row * D + j] = make_float2(p.z, p.z + gr[1 * D + j] * dUz +
-                                                         gr[2 * D + j] * dUn +
-                                                         gr[3 * D + j] * dUr);
-                const float gv = gvs[mb][i];
-                a.lam[0][row * D + j] = gv;
-                gm = max(gm, absbits(gv));
+                a.zd[row * D + j] = make_float2(p.z, p.z + al * dUz + be * dUn + ga * dUr);
+                gm = max(gm, absbits(gvs[mb][i]));
             }
         }
 #pragma unroll
@@ -196,7 +196,8 @@ gru_adj_local_kernel(GruAdjArgs a) {
     const int k = a.ctrl->iter;
     const bool fuse = k > 0;
     const float reset_abs = a.ctrl->reset_abs;
-    const float* __restrict__ lprev = a.lam[(k + 1) & 1];    // lambda^(k-1)
+    // lambda^(k-1) (lambda^(0) = g)
+    const float* __restrict__ lprev = k == 1 ? a.gs : a.lam[(k + 1) & 1];
     float* __restrict__ lcur = a.lam[k & 1];                 // lambda^(k)
     const float2* __restrict__ lacp = a.lac[(k + 1) & 1];
     float2* __restrict__ lacn = a.lac[k & 1];
@@ -262,7 +263,7 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     const bool okl = i0 + q < NI && idx < (L + 1) * Q && nr < rend;
                     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                     const size_t e = (size_t)nr * D + 4 * c4;
-                    vl[q] = okl ? *(const float4*)((fuse ? lprev : lcur) + e) : z4;
+                    vl[q] = okl ? *(const float4*)((fuse ? lprev : a.gs) + e) : z4;
                     p0[q] = (okl && fuse) ? *(const float4*)(lacp + e) : z4;
                     p1[q] = (okl && fuse) ? *(const float4*)(lacp + e + 2) : z4;
                 }
@@ -300,9 +301,9 @@ gru_adj_local_kernel(GruAdjArgs a) {
                                      r - 1 < len;
                     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                     const float* gp = a.gates + (size_t)nr * 4 * D + 4 * c4;
-                    va[q] = okp ? *(const float4*)(gp + 1 * D) : z4;
-                    vb[q] = okp ? *(const float4*)(gp + 2 * D) : z4;
-                    vg[q] = okp ? *(const float4*)(gp + 3 * D) : z4;
+                    va[q] = okp ? *(const float4*)(gp + 0 * D) : z4;
+                    vb[q] = okp ? *(const float4*)(gp + 1 * D) : z4;
+                    vg[q] = okp ? *(const float4*)(gp + 2 * D) : z4;
                 }
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
@@ -498,7 +499,7 @@ gru_adj_grad_kernel(GruAdjArgs a) {
       const TileInfo ti = tnext;
       if (tile + (int)gridDim.x < a.ntiles) tnext = a.tiles[tile + gridDim.x];   // read ahead
       const int b = ti.b;
-      const float* lam = a.lam[a.seq[b].parity];
+      const float* lam = (a.lam0_is_g && a.seq[b].iters == 0) ? a.gs : a.lam[a.seq[b].parity];
       for (int sub = 0; sub < SUB; ++sub) {
         const int len = min(L, ti.len - sub * L);
         if (len <= 0) break;
@@ -520,10 +521,10 @@ gru_adj_grad_kernel(GruAdjArgs a) {
             const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
             const float* gr = a.gates + row * 4 * D + 4 * c4;
             vl[i] = ok ? *(const float4*)(lam + row * D + 4 * c4) : z4;
-            va[i] = ok ? *(const float4*)(gr + 1 * D) : z4;
-            vb[i] = ok ? *(const float4*)(gr + 2 * D) : z4;
-            vg[i] = ok ? *(const float4*)(gr + 3 * D) : z4;
-            ve[i] = ok ? *(const float4*)(a.eps + row * D + 4 * c4) : z4;
+            va[i] = ok ? *(const float4*)(gr + 0 * D) : z4;
+            vb[i] = ok ? *(const float4*)(gr + 1 * D) : z4;
+            vg[i] = ok ? *(const float4*)(gr + 2 * D) : z4;
+            ve[i] = ok ? *(const float4*)(gr + 3 * D) : z4;
             vh[i] = !ok ? z4
                         : (tl == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
                                              : *(const float4*)(a.s + (row - 1) * D + 4 * c4);
@@ -668,15 +669,16 @@ __global__ void gru_adj_gs0_kernel(GruAdjArgs a) {
     if (j >= D) return;
     const int64_t r0 = a.offsets[b];
     if (a.offsets[b + 1] == r0) { a.gs0[(size_t)b * D + j] = 0.f; return; }
-    const float* lam = a.lam[a.seq[b].parity] + (size_t)r0 * D;
+    const float* lam = ((a.lam0_is_g && a.seq[b].iters == 0) ? a.gs : a.lam[a.seq[b].parity]) +
+                       (size_t)r0 * D;
     const float* gr = a.gates + (size_t)r0 * 4 * D;
     const float* U = a.params + 3 * D * DX;
-    float v = gr[j] * lam[j];
+    float v = a.zd[(size_t)r0 * D + j].x * lam[j];
     for (int i = 0; i < D; ++i) {
         const float li = lam[i];
-        v += U[(0 * D + i) * D + j] * gr[D + i] * li      // U_z^T (alpha * lambda)
-           + U[(2 * D + i) * D + j] * gr[2 * D + i] * li  // U_n^T (beta * lambda)
-           + U[(1 * D + i) * D + j] * gr[3 * D + i] * li; // U_r^T (gamma * lambda)
+        v += U[(0 * D + i) * D + j] * gr[i] * li          // U_z^T (alpha * lambda)
+           + U[(2 * D + i) * D + j] * gr[D + i] * li      // U_n^T (beta * lambda)
+           + U[(1 * D + i) * D + j] * gr[2 * D + i] * li; // U_r^T (gamma * lambda)
     }
     a.gs0[(size_t)b * D + j] = v;
 }
@@ -688,12 +690,13 @@ __global__ void zero_u32_kernel(uint32_t* p, int n) {
 // ---- sequential adjoint (baseline): lambda_t = g_t + A_{t+1}^T lambda_{t+1}, one step at a
 // time per sequence; lanes 4j..4j+3 of a wave serve unit j (U_z^T, U_n^T, U_r^T columns).
 template <int D>
-__global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, const float* gs,
-                                                            const float* U, float* lam,
-                                                            const int64_t* offsets) {
+__global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, const float2* zd,
+                                                            const float* gs, const float* U,
+                                                            float* lam, const int64_t* offsets) {
     constexpr int CH = 32;
     __shared__ float prod[2][3][D];
     __shared__ float gch[CH][4 * D];
+    __shared__ float zch[CH][D];
     __shared__ float gsch[CH][D];
     const int b = blockIdx.x;
     const int tid = threadIdx.x;
@@ -703,7 +706,7 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
     const int mrow = role == 0 ? 0 : (role == 1 ? 2 * D : D);   // U_z, U_n, U_r
 #pragma unroll
     for (int i = 0; i < D; ++i) w[i] = role < 3 ? U[(mrow + i) * D + j] : 0.f;
-    const int plane = role + 1;                                  // alpha, beta, gamma
+    const int plane = role;                                      // alpha, beta, gamma
     float v = 0.f;                                               // A_{t+1}^T lambda_{t+1}
     for (int64_t t = T - 1; t >= 0; --t) {
         const int64_t cb = t - (t % CH);                         // chunk [cb, cb + CH)
@@ -716,12 +719,13 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
             for (int idx = tid; idx < CH * D; idx += blockDim.x) {
                 const int r = idx / D, c = idx % D;
                 gsch[r][c] = (cb + r < T) ? gs[(size_t)(r0 + cb + r) * D + c] : 0.f;
+                zch[r][c] = (cb + r < T) ? zd[(size_t)(r0 + cb + r) * D + c].x : 0.f;
             }
             __syncthreads();
         }
         const int rr = (int)(t - cb);
         const float lt = gsch[rr][j] + v;
-        const float z = gch[rr][j];
+        const float z = zch[rr][j];
         if (role == 0) lam[(size_t)(r0 + t) * D + j] = lt;
         const int p = (int)(t & 1);
         if (role < 3) prod[p][role][j] = gch[rr][plane * D + j] * lt;
@@ -739,7 +743,7 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
 
 struct GruALayout {
     IterState st;
-    float *gates, *eps, *lam[2], *gmax, *part, *gcarry;
+    float *gates, *lam[2], *gmax, *part, *gcarry;
     float2 *zd, *lac[2], *gagg;
     size_t bytes;
 };
@@ -755,7 +759,6 @@ static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int 
     GruALayout lay;
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.gates = c.take<float>((size_t)hb.N * 4 * D);
-    lay.eps = c.take<float>((size_t)hb.N * D);
     lay.zd = c.take<float2>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lac[p] = c.take<float2>((size_t)hb.N * D);
@@ -841,7 +844,7 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
     args.zd = lay.zd;
-    args.eps = lay.eps;
+    args.lam0_is_g = 1;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     for (int p = 0; p < 2; ++p) args.lac[p] = lay.lac[p];
     args.gagg = lay.gagg;
@@ -927,7 +930,8 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     const int D = cd.D, Dx = cd.Dx;
     GruAKernels kk;
     if (!gruA_lookup(D, Dx, &kk)) return PN_ERR_UNSUPPORTED;
-    void (*seqk)(const float*, const float*, const float*, float*, const int64_t*) = nullptr;
+    void (*seqk)(const float*, const float2*, const float*, const float*, float*,
+                 const int64_t*) = nullptr;
     switch (D) {
         case 16: seqk = gru_seq_adj_kernel<16>; break;
         case 32: seqk = gru_seq_adj_kernel<32>; break;
@@ -948,7 +952,6 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
     args.zd = lay.zd;
-    args.eps = lay.eps;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     args.gmax = lay.gmax;
     args.ctrl = lay.st.ctrl;
@@ -968,8 +971,9 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
                            dim3(kk.nt), 0, stream, args);
     const float* U = (const float*)cd.params + 3 * D * Dx;
     prof_launch("seq_adj", stream, [&](hipStream_t s2) {
-        hipLaunchKernelGGL(seqk, dim3(hb.B), dim3(4 * D), 0, s2, (const float*)lay.gates, gs, U,
-                           lay.lam[0], (const int64_t*)lay.st.offsets);
+        hipLaunchKernelGGL(seqk, dim3(hb.B), dim3(4 * D), 0, s2, (const float*)lay.gates,
+                           (const float2*)lay.zd, gs, U, lay.lam[0],
+                           (const int64_t*)lay.st.offsets);
     });
     PN_HIP(hipGetLastError());
     const int gg = grad_grid();
