@@ -106,10 +106,10 @@ struct GruPoint {
 PN_DEV GruPoint gru_point(float az, float ar, float aq, float an, float b_z, float b_r,
                           float b_n, float b_hn) {
     GruPoint p;
-    p.z = sigmoidf_(az + b_z);
-    p.r = sigmoidf_(ar + b_r);
+    p.z = sigmoid_rcp(az + b_z);
+    p.r = sigmoid_rcp(ar + b_r);
     p.q = aq + b_hn;
-    p.n = tanhf_(an + b_n + p.r * p.q);
+    p.n = tanh_rcp(an + b_n + p.r * p.q);
     return p;
 }
 
