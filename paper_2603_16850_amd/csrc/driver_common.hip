@@ -39,11 +39,17 @@ int cu_count() {
 
 // ---- event timing ------------------------------------------------------------------------
 namespace {
+struct ProfPending {
+    std::string family;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    int iter;               // iteration the launch belongs to (-1: outside an iteration loop)
+};
 struct ProfRec {
     bool on = false;
+    int cur_iter = -1;
     std::map<std::string, std::pair<double, int64_t>> totals;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
-    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<ProfPending> pending;
 };
 ProfRec& prof() {
     static thread_local ProfRec r;
@@ -71,22 +77,39 @@ void prof_launch(const char* family, hipStream_t stream,
     (void)hipEventRecord(ev.first, stream);
     launch(stream);
     (void)hipEventRecord(ev.second, stream);
-    r.pending.push_back({family, ev});
+    r.pending.push_back({family, ev, r.cur_iter});
+}
+
+// Launches of iterations after `last` found every sequence stopped and returned at once: they
+// are not counted.
+static void prof_drop_after(int last) {
+    ProfRec& r = prof();
+    std::vector<ProfPending> keep;
+    for (auto& p : r.pending) {
+        if (p.iter > last) {
+            (void)hipEventSynchronize(p.ev.second);
+            r.pool.push_back(p.ev);
+        } else {
+            keep.push_back(p);
+        }
+    }
+    r.pending.swap(keep);
 }
 
 void prof_collect() {
     ProfRec& r = prof();
     for (auto& p : r.pending) {
         float ms = 0.f;
-        if (hipEventSynchronize(p.second.second) == hipSuccess &&
-            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
-            auto& t = r.totals[p.first];
+        if (hipEventSynchronize(p.ev.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.ev.first, p.ev.second) == hipSuccess) {
+            auto& t = r.totals[p.family];
             t.first += ms;
             t.second += 1;
         }
-        r.pool.push_back(p.second);
+        r.pool.push_back(p.ev);
     }
     r.pending.clear();
+    r.cur_iter = -1;
 }
 
 void profile_begin() {
@@ -154,7 +177,7 @@ __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offs
         c.max_iters = max_iters;
         c.tol = tol;
         c.reset_abs = reset_abs;
-        c.pad_ = 0;
+        c.done_iter = -1;
         *ctrl = c;
     }
 }
@@ -258,6 +281,7 @@ __global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B, int pending_curr
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (!any_active && !ctrl->all_done) ctrl->done_iter = k;
         ctrl->iter = k + 1;
         ctrl->tile_counter = 0;
         ctrl->all_done = any_active ? 0 : 1;
@@ -336,12 +360,17 @@ pn_status run_iterations(const IterState& st, int max_launches, int graph_iters,
             }
             PN_HIP(hipGraphLaunch(exec, stream));
         } else {
-            for (int i = 0; i < n; ++i) one_iter(stream);
+            for (int i = 0; i < n; ++i) {
+                prof().cur_iter = launched + i;
+                one_iter(stream);
+            }
+            prof().cur_iter = -1;
             PN_HIP(hipGetLastError());
         }
         launched += n;
         PN_HIP(hipMemcpyAsync(hc, st.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
         PN_HIP(hipStreamSynchronize(stream));
+        if (hc->all_done && profiling()) prof_drop_after(hc->done_iter);
         if (hc->all_done || hc->error) break;
     }
     return PN_OK;

@@ -68,7 +68,7 @@ struct Ctrl {
     int max_iters;
     float tol;
     float reset_abs;
-    int pad_;
+    int done_iter;      // the iteration whose decision stopped the last sequence (-1 before)
 };
 
 // ---- atomics ------------------------------------------------------------------------------
