@@ -53,10 +53,10 @@ def fwd_local_bytes(D, Dx):
 
 
 def adj_local_bytes(D):
-    """Algorithmic HBM bytes per step of one adjoint iteration (FP32): read lambda^(k-1), the
-    previous maps, the gate values (z, alpha, beta, gamma), diag A and g; write lambda^(k) and
-    the new maps."""
-    return 4 * D + 8 * D + 16 * D + 4 * D + 4 * D + 4 * D + 8 * D
+    """Algorithmic HBM bytes per step of one adjoint iteration after the first (FP32): read
+    lambda^(k-1), the step map (la, written once, and lc of the previous iteration), the gate
+    values alpha, beta, gamma, the pair (z, diag A) and g; write lambda^(k) and the new lc."""
+    return 4 * D + 8 * D + 12 * D + 8 * D + 4 * D + 4 * D + 4 * D
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gru64_hbm_traffic.txt")

@@ -51,8 +51,11 @@ struct GruAdjArgs {
     float* lam[2];           // ping-pong adjoint iterates; iteration k reads lam[k & 1]
                              // (lambda^(0) = g is read from gs, not stored)
     int lam0_is_g;           // nonzero: a sequence stopped at iteration 0 has lambda = g
-    float2* lac[2];          // [N][D] (la, lc) relative to the step's group; iteration k
-                             // writes lac[k & 1]
+    float* la;               // [N][D] multiplicative part of every step's map relative to its
+                             // group.  The transitions diag(A_{t+1}) of the adjoint scan are
+                             // those of the solution and do not change between iterations, so
+                             // la is the same in every iteration: written by iteration 0 only.
+    float* lc[2];            // [N][D] additive part; iteration k writes lc[k & 1]
     float2* gagg;            // [ngroups][D] group maps
     const float* gcarry;     // [ngroups][D] carry into every group (previous iteration)
     float* gmax;             // [B] max |g| per sequence (as float bits, via atomicMax)
@@ -199,8 +202,9 @@ gru_adj_local_kernel(GruAdjArgs a) {
     // lambda^(k-1) (lambda^(0) = g)
     const float* __restrict__ lprev = k == 1 ? a.gs : a.lam[(k + 1) & 1];
     float* __restrict__ lcur = a.lam[k & 1];                 // lambda^(k)
-    const float2* __restrict__ lacp = a.lac[(k + 1) & 1];
-    float2* __restrict__ lacn = a.lac[k & 1];
+    const float* __restrict__ lap = a.la;
+    const float* __restrict__ lcp = a.lc[(k + 1) & 1];
+    float* __restrict__ lcn = a.lc[k & 1];
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
     const int j = 16 * w + u;
@@ -264,8 +268,8 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                     const size_t e = (size_t)nr * D + 4 * c4;
                     vl[q] = okl ? *(const float4*)((fuse ? lprev : a.gs) + e) : z4;
-                    p0[q] = (okl && fuse) ? *(const float4*)(lacp + e) : z4;
-                    p1[q] = (okl && fuse) ? *(const float4*)(lacp + e + 2) : z4;
+                    p0[q] = (okl && fuse) ? *(const float4*)(lap + e) : z4;
+                    p1[q] = (okl && fuse) ? *(const float4*)(lcp + e) : z4;
                 }
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
@@ -275,10 +279,10 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     float4 w4 = vl[q];
                     if (fuse) {
                         const float4 cv = r < L ? cown : chalo;
-                        w4.x += p0[q].x * cv.x + p0[q].y;
-                        w4.y += p0[q].z * cv.y + p0[q].w;
-                        w4.z += p1[q].x * cv.z + p1[q].y;
-                        w4.w += p1[q].z * cv.w + p1[q].w;
+                        w4.x += p0[q].x * cv.x + p1[q].x;
+                        w4.y += p0[q].y * cv.y + p1[q].y;
+                        w4.z += p0[q].z * cv.z + p1[q].z;
+                        w4.w += p0[q].w * cv.w + p1[q].w;
                         if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
                             !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
                             rowbad[r] = 1;
@@ -432,8 +436,11 @@ gru_adj_local_kernel(GruAdjArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
-                    if (tl < len)
-                        lacn[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
+                    if (tl < len) {
+                        const size_t e = (size_t)(row0 + tl) * D + j;
+                        if (!fuse) a.la[e] = la[mb][i];
+                        lcn[e] = lc[mb][i];
+                    }
                 }
         }
         if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
@@ -744,7 +751,8 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
 struct GruALayout {
     IterState st;
     float *gates, *lam[2], *gmax, *part, *gcarry;
-    float2 *zd, *lac[2], *gagg;
+    float2 *zd, *gagg;
+    float *la, *lc[2];
     size_t bytes;
 };
 
@@ -761,7 +769,8 @@ static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int 
     lay.gates = c.take<float>((size_t)hb.N * 4 * D);
     lay.zd = c.take<float2>((size_t)hb.N * D);
     for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
-    for (int p = 0; p < 2; ++p) lay.lac[p] = c.take<float2>((size_t)hb.N * D);
+    lay.la = c.take<float>((size_t)hb.N * D);
+    for (int p = 0; p < 2; ++p) lay.lc[p] = c.take<float>((size_t)hb.N * D);
     lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
     lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
     lay.gmax = c.take<float>(hb.B);
@@ -846,7 +855,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.zd = lay.zd;
     args.lam0_is_g = 1;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
-    for (int p = 0; p < 2; ++p) args.lac[p] = lay.lac[p];
+    args.la = lay.la;
+    for (int p = 0; p < 2; ++p) args.lc[p] = lay.lc[p];
     args.gagg = lay.gagg;
     args.gcarry = lay.gcarry;
     args.gmax = lay.gmax;
