@@ -567,6 +567,214 @@ __global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__
     }
 }
 
+// ---- carry pass in three phases (long sequences) -----------------------------------------------
+// The groups of a sequence from its first open group on are cut into runs of RQ groups.
+//   fold:   one wave per run composes the run's group elements into one element;
+//   walk:   one wave per sequence applies the run elements in order from (m, P) = (0, 0) and
+//           writes the state entering every run;
+//   expand: one wave per run applies its group elements from the run's entering state and
+//           writes the state entering every group.
+// A sequence of G open groups then costs about (RQ - 1) compositions, G / RQ and RQ
+// applications of dependent work instead of G applications.
+
+// Leading groups whose residual bound is below tol (NaN bounds are not), at least `old`.
+PN_DEV int elk_open_start(const uint32_t* grmax, int g0, int G, float tol, int old) {
+    const int l = threadIdx.x & 63;
+    const uint32_t tolb = __float_as_uint(tol);
+    int fz = G;
+    for (int base = 0; base < G; base += 64) {
+        const bool open = base + l < G && !(grmax[g0 + base + l] < tolb);
+        const uint64_t m = __ballot(open);
+        if (m) {
+            fz = base + __ffsll((unsigned long long)m) - 1;
+            break;
+        }
+    }
+    return max(fz, old);
+}
+
+// An element held in LDS (stride-ES matrices)
+struct ElkElem {
+    float* A;
+    float* C;
+    float* J;
+    float* b;
+    float* e;
+};
+
+// lane's share of an element in memory (EGEL floats), to registers and from registers to LDS
+constexpr int kElemPer = (EGEL + 63) / 64;
+PN_DEV void elem_fetch(float (&r)[kElemPer], const float* src) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < kElemPer; ++i) {
+        const int w = l + 64 * i;
+        r[i] = w < EGEL ? src[w] : 0.f;
+    }
+}
+PN_DEV void elem_to_lds(const ElkElem& d, const float (&r)[kElemPer]) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < kElemPer; ++i) {
+        const int w = l + 64 * i;
+        if (w < 3 * ED * ED) {
+            float* M = w < ED * ED ? d.A : (w < 2 * ED * ED ? d.C : d.J);
+            const int v = w % (ED * ED);
+            M[(v / ED) * ES + v % ED] = r[i];
+        } else if (w < 3 * ED * ED + ED) {
+            d.b[w - 3 * ED * ED] = r[i];
+        } else if (w < EGEL) {
+            d.e[w - 3 * ED * ED - ED] = r[i];
+        }
+    }
+}
+PN_DEV void elem_store(float* dst, const ElkElem& d) {
+    const int l = threadIdx.x & 63;
+    store_mat(dst, d.A);
+    store_mat(dst + ED * ED, d.C);
+    store_mat(dst + 2 * ED * ED, d.J);
+    if (l < ED) {
+        dst[3 * ED * ED + l] = d.b[l];
+        dst[3 * ED * ED + ED + l] = d.e[l];
+    }
+}
+
+// i <- i (x) j: the earlier element i followed by j (T1, T2, Gm, vz: LDS scratch)
+PN_DEV void elem_compose(const ElkElem& i, const ElkElem& j, float* T1, float* T2, float* Gm,
+                         float* vz) {
+    mm16(T1, i.C, false, j.J, false, 1.f, nullptr, 1.f);       // I + C_i J_j
+    inv16(Gm, T1);                                              // G
+    mm16(T2, j.A, false, Gm, false, 1.f, nullptr, 0.f);        // A_j G
+    mv16(vz, j.J, false, i.b, -1.f, j.e, 1.f);                 // eta_j - J_j b_i
+    mv16(vz, Gm, true, vz, 1.f, nullptr, 0.f);                 // G^T (.)
+    mv16(i.e, i.A, true, vz, 1.f, i.e, 1.f);                   // eta = A_i^T (.) + eta_i
+    mm16(T1, j.J, false, i.A, false, 1.f, nullptr, 0.f);       // J_j A_i
+    mm16(T1, Gm, true, T1, false, 1.f, nullptr, 0.f);          // G^T J_j A_i
+    mm16(i.J, i.A, true, T1, false, 1.f, i.J, 0.f);            // J = A_i^T (.) + J_i
+    mv16(vz, i.C, false, j.e, 1.f, i.b, 1.f);                  // b_i + C_i eta_j
+    mv16(i.b, T2, false, vz, 1.f, j.b, 1.f);                   // b = A_j G (.) + b_j
+    mm16(T1, T2, false, i.C, false, 1.f, nullptr, 0.f);        // A_j G C_i
+    mm16(i.C, T1, false, j.A, true, 1.f, j.C, 0.f);            // C = (.) A_j^T + C_j
+    mm16(i.A, T2, false, i.A, false, 1.f, nullptr, 0.f);       // A = A_j G A_i
+}
+
+// (m, P) <- element e applied: G = (I + P J)^-1, m' = A G (m + P eta) + b, P' = A G P A^T + C
+PN_DEV void elem_apply(const ElkElem& e, float* m, float* P, float* T1, float* Gm, float* vz) {
+    mm16(T1, P, false, e.J, false, 1.f, nullptr, 1.f);         // I + P J
+    inv16(Gm, T1);                                              // G
+    mm16(T1, e.A, false, Gm, false, 1.f, nullptr, 0.f);        // A G
+    mv16(vz, P, false, e.e, 1.f, m, 1.f);                      // m + P eta
+    mv16(m, T1, false, vz, 1.f, e.b, 1.f);                     // m' = A G (.) + b
+    mm16(Gm, T1, false, P, false, 1.f, nullptr, 0.f);          // A G P
+    mm16(P, Gm, false, e.A, true, 1.f, e.C, 0.f);              // P' = (.) A^T + C
+}
+
+struct ElkRunArgs {
+    const float* gel;        // [ngroups][EGEL]
+    float* gcar;             // [ngroups][ECAR]
+    float* rel;              // [B * nrun][EGEL] run elements
+    float* rcar;             // [B * nrun][ECAR] state entering every run
+    const Ctrl* ctrl;
+    SeqState* seq;
+    const int32_t* group_start;
+    const uint32_t* grmax;
+    int freeze;
+    int B;
+    int nrun;                // runs per sequence slot (longest sequence)
+    int rq;                  // groups per run
+};
+
+__global__ void __launch_bounds__(64) elk_run_fold_kernel(ElkRunArgs a) {
+    __shared__ float A0[EM], C0[EM], J0[EM], A1[EM], C1[EM], J1[EM], T1[EM], T2[EM], Gm[EM];
+    __shared__ float b0[ED], e0[ED], b1[ED], e1[ED], vz[ED];
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int b = blockIdx.x / a.nrun, ri = blockIdx.x % a.nrun;
+    if (b >= a.B || a.seq[b].status != kActive) return;
+    const int g0 = a.group_start[b], G = a.group_start[b + 1] - g0;
+    const int gs = a.freeze ? elk_open_start(a.grmax, g0, G, a.ctrl->tol, a.seq[b].frozen) : 0;
+    const int lo = gs + ri * a.rq, hi = min(G, lo + a.rq);
+    if (lo >= hi) return;
+    const ElkElem acc{A0, C0, J0, b0, e0}, nx{A1, C1, J1, b1, e1};
+    float r[kElemPer];
+    elem_fetch(r, a.gel + (size_t)(g0 + lo) * EGEL);
+    elem_to_lds(acc, r);
+    if (lo + 1 < hi) elem_fetch(r, a.gel + (size_t)(g0 + lo + 1) * EGEL);
+    __syncthreads();
+    for (int gg = lo + 1; gg < hi; ++gg) {
+        elem_to_lds(nx, r);
+        if (gg + 1 < hi) elem_fetch(r, a.gel + (size_t)(g0 + gg + 1) * EGEL);
+        __syncthreads();
+        elem_compose(acc, nx, T1, T2, Gm, vz);
+    }
+    elem_store(a.rel + (size_t)blockIdx.x * EGEL, acc);
+}
+
+__global__ void __launch_bounds__(64) elk_run_walk_kernel(ElkRunArgs a) {
+    __shared__ float Ae[EM], Ce[EM], Je[EM], P[EM], T1[EM], Gm[EM];
+    __shared__ float be[ED], ee[ED], m[ED], vz[ED];
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int b = blockIdx.x;
+    if (b >= a.B || a.seq[b].status != kActive) return;
+    const int l = threadIdx.x;
+    const int g0 = a.group_start[b], G = a.group_start[b + 1] - g0;
+    int gs = 0;
+    if (a.freeze) {
+        const int old = a.seq[b].frozen;
+        gs = elk_open_start(a.grmax, g0, G, a.ctrl->tol, old);
+        __syncthreads();
+        if (l == 0) {
+            a.seq[b].frozen_prev = old;
+            a.seq[b].frozen = gs;
+        }
+    }
+    const int nr = (G - gs + a.rq - 1) / a.rq;
+    const ElkElem e{Ae, Ce, Je, be, ee};
+    for (int idx = l; idx < EM; idx += 64) P[idx] = 0.f;
+    if (l < ED) m[l] = 0.f;
+    float r[kElemPer];
+    const size_t base = (size_t)b * a.nrun;
+    if (nr > 0) elem_fetch(r, a.rel + base * EGEL);
+    __syncthreads();
+    for (int ri = 0; ri < nr; ++ri) {
+        float* cr = a.rcar + (base + ri) * ECAR;
+        store_mat(cr, P);
+        if (l < ED) cr[ED * ED + l] = m[l];
+        elem_to_lds(e, r);
+        if (ri + 1 < nr) elem_fetch(r, a.rel + (base + ri + 1) * EGEL);
+        __syncthreads();
+        elem_apply(e, m, P, T1, Gm, vz);
+    }
+}
+
+__global__ void __launch_bounds__(64) elk_run_expand_kernel(ElkRunArgs a) {
+    __shared__ float Ae[EM], Ce[EM], Je[EM], P[EM], T1[EM], Gm[EM];
+    __shared__ float be[ED], ee[ED], m[ED], vz[ED];
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int b = blockIdx.x / a.nrun, ri = blockIdx.x % a.nrun;
+    if (b >= a.B || a.seq[b].status != kActive) return;
+    const int l = threadIdx.x;
+    const int g0 = a.group_start[b], G = a.group_start[b + 1] - g0;
+    const int gs = a.freeze ? a.seq[b].frozen : 0;      // written by the walk
+    const int lo = gs + ri * a.rq, hi = min(G, lo + a.rq);
+    if (lo >= hi) return;
+    const ElkElem e{Ae, Ce, Je, be, ee};
+    fetch_mat(P, a.rcar + (size_t)blockIdx.x * ECAR);
+    if (l < ED) m[l] = a.rcar[(size_t)blockIdx.x * ECAR + ED * ED + l];
+    float r[kElemPer];
+    elem_fetch(r, a.gel + (size_t)(g0 + lo) * EGEL);
+    __syncthreads();
+    for (int gg = lo; gg < hi; ++gg) {
+        float* cr = a.gcar + (size_t)(g0 + gg) * ECAR;
+        store_mat(cr, P);
+        if (l < ED) cr[ED * ED + l] = m[l];
+        if (gg + 1 == hi) break;                 // the run's last state is not needed
+        elem_to_lds(e, r);
+        if (gg + 1 < hi) elem_fetch(r, a.gel + (size_t)(g0 + gg + 1) * EGEL);
+        __syncthreads();
+        elem_apply(e, m, P, T1, Gm, vz);
+    }
+}
+
 // ---- carry pass of the DEER step (lambda = 0): m' = A m + b per group -------------------------
 // One wave per sequence; lane (r, q) = (l & 15, l >> 4) holds A[r][4q .. 4q+3] of the group
 // being applied, every lane m[r]; the next group's (A, b) is fetched one group ahead.
@@ -852,12 +1060,23 @@ struct ElkLayout {
     float* esm;              // smoother only
     float* gbel;
     float* bcar;
+    float* rel;              // three-phase carry: run elements and entering states
+    float* rcar;
     char* r64;
     size_t bytes;
 };
 
+// Groups per run of the three-phase carry for sequences of at most gmax groups (0: the
+// single-pass carry).  The run length balances the fold (RQ - 1 compositions, a composition
+// costing about 1.4 applications) and the expansion (RQ applications) against the walk
+// (gmax / RQ applications).
+static int elk_run_len(int gmax) {
+    if (gmax < 16) return 0;
+    return std::max(2, (int)std::lround(std::sqrt(gmax / 2.4)));
+}
+
 static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngroups,
-                            bool smooth) {
+                            bool smooth, int nrun_total) {
     Carver c(ws);
     ElkLayout lay;
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
@@ -868,6 +1087,8 @@ static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngrou
     lay.esm = smooth ? c.take<float>((size_t)std::max<int64_t>(hb.N, 1) * ESM) : nullptr;
     lay.gbel = smooth ? c.take<float>((size_t)std::max(ngroups, 1) * ESM) : nullptr;
     lay.bcar = smooth ? c.take<float>((size_t)std::max(ngroups, 1) * ED) : nullptr;
+    lay.rel = nrun_total ? c.take<float>((size_t)nrun_total * EGEL) : nullptr;
+    lay.rcar = nrun_total ? c.take<float>((size_t)nrun_total * ECAR) : nullptr;
     lay.r64 = c.take<char>(residual64_workspace(PN_CELL_TANH, ED, 16, hb));   // FP64 residual
     lay.bytes = c.bytes();
     return lay;
@@ -887,8 +1108,9 @@ static int elk_resident(bool kf) {
 // Chunks per group.  An explicit tile (a multiple of 16 steps) fixes it.  Otherwise a cost
 // model picks it: the local pass takes rounds * gt chunks of latency (rounds = groups per
 // resident workgroup), the carry pass one element application per group of the longest
-// sequence; a chunk of the local pass (replay and fold) costs about kLocalPerCarry carry steps
-// (measured: the Kalman passes, and the DEER passes of lambda = 0).
+// sequence (the three-phase carry's dependent work for the Kalman passes); a chunk of the local
+// pass (replay and fold) costs about kLocalPerCarry carry steps (measured: the Kalman passes,
+// and the DEER passes of lambda = 0).
 static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, int tile,
                            bool kf) {
     if (tile > 0) return tile / EL;
@@ -901,10 +1123,21 @@ static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, 
     for (int gt = 1; gt <= 64; gt *= 2) {
         const int ng = count_groups(ts, hb.B, gt);
         const double rounds = std::ceil((double)ng / resident);
-        const double cost = rounds * gt * kLocalPerCarry + std::ceil((double)maxc / gt);
+        const int gmax = (maxc + gt - 1) / gt;
+        const int rq = kf ? elk_run_len(gmax) : 0;
+        const double carry = rq ? 2.4 * rq + std::ceil((double)gmax / rq) : gmax;
+        const double cost = rounds * gt * kLocalPerCarry + carry;
         if (cost < best_cost) { best_cost = cost; best = gt; }
     }
     return best;
+}
+
+// lambda is not known here: room for the grouping of either pass family
+// longest sequence in groups of gt chunks
+static int elk_max_groups(const HostBatch& hb, const std::vector<int32_t>& ts, int gt) {
+    int g = 0;
+    for (int b = 0; b < hb.B; ++b) g = std::max(g, (ts[b + 1] - ts[b] + gt - 1) / gt);
+    return g;
 }
 
 // lambda is not known here: room for the grouping of either pass family
@@ -913,8 +1146,11 @@ size_t elk_workspace(int, int, const HostBatch& hb, const pn_opts& o) {
     size_t n = 0;
     for (int kf = 0; kf < 2; ++kf) {
         const int gt = elk_group_tiles(hb, ts, o.tile, kf != 0);
+        const int gmax = elk_max_groups(hb, ts, gt);
+        const int rq = kf ? elk_run_len(gmax) : 0;
+        const int nrun = rq ? (gmax + rq - 1) / rq : 0;
         n = std::max(n, elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt),
-                                   o.smooth != 0).bytes);
+                                   o.smooth != 0, nrun * hb.B).bytes);
     }
     return n;
 }
@@ -939,7 +1175,10 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const int gt = elk_group_tiles(hb, ts, o.tile, kf);
     const int ngroups = count_groups(ts, hb.B, gt);
     const bool smooth = o.smooth != 0;
-    ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups, smooth);
+    const int gmax = elk_max_groups(hb, ts, gt);
+    const int rq = kf ? elk_run_len(gmax) : 0;      // three-phase carry for long sequences
+    const int nrun = rq ? (gmax + rq - 1) / rq : 0;
+    ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups, smooth, nrun * hb.B);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, EL, false, max_iters, (float)o.tol,
                            (float)o.reset_abs, stream, gt));
@@ -992,10 +1231,30 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     ba.tiles = lay.st.tiles;
     ba.groups = lay.st.groups;
     ba.ngroups = ngroups;
+    ElkRunArgs ra;
+    ra.gel = lay.gel;
+    ra.gcar = lay.gcar;
+    ra.rel = lay.rel;
+    ra.rcar = lay.rcar;
+    ra.ctrl = lay.st.ctrl;
+    ra.seq = lay.st.seq;
+    ra.group_start = lay.st.group_start;
+    ra.grmax = lay.grmax;
+    ra.freeze = args.freeze;
+    ra.B = hb.B;
+    ra.nrun = nrun;
+    ra.rq = rq;
     auto one_iter = [&](hipStream_t st) {
         prof_launch("elk_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
         });
+        if (rq) {
+            prof_launch("elk_carry", st, [&](hipStream_t s2) {
+                hipLaunchKernelGGL(elk_run_fold_kernel, dim3(hb.B * nrun), dim3(64), 0, s2, ra);
+                hipLaunchKernelGGL(elk_run_walk_kernel, dim3(hb.B), dim3(64), 0, s2, ra);
+                hipLaunchKernelGGL(elk_run_expand_kernel, dim3(hb.B * nrun), dim3(64), 0, s2, ra);
+            });
+        } else
         prof_launch("elk_carry", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kf ? elk_carry_kernel : elk_deer_carry_kernel,
                                dim3(std::max(1, hb.B)), dim3(64), 0, s2,
