@@ -213,15 +213,18 @@ PN_DEV uint32_t elk_linearise(const float* sst, const float* xst, float* dsh, fl
         if (track && t < len && !res64) rm = max(rm, absbits(res));
     }
     if (track && res64) {
-#pragma unroll
+        // rolled loops: this branch runs once per iterate and must not cost registers
+#pragma unroll 1
         for (int i = 0; i < 4; ++i) {
             const int t = 4 * g + i;
             if (t < len) {
                 double acc64 = (double)bias_u;
+#pragma unroll 2
                 for (int kk = 0; kk < ED; ++kk) {
                     const double sv = (double)sst[t * SS + kk];
                     acc64 += (double)Wm[u * ES + kk] * (MF ? tanh(sv) : sv);
                 }
+#pragma unroll 2
                 for (int kk = 0; kk < DX; ++kk)
                     acc64 += (double)U[u * DX + kk] * (double)xst[t * XS + kk];
                 const double r = (double)sst[(t + 1) * SS + u] - (MF ? acc64 : tanh(acc64));
@@ -287,7 +290,7 @@ struct ElkArgs {
 // KF = false: lambda = 0, the filter is the DEER step (Gamma = I): the replay is
 // m = A m - r, the elements are the affine maps (A, b) alone.
 template <int DX, bool MF, bool KF>
-__global__ void __launch_bounds__(64, 2) elk_local_kernel(ElkArgs a) {
+__global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
     constexpr int L = EL;
     constexpr int KT = ED + DX;
     constexpr int SS = ED + 4, XS = DX + 4;
