@@ -488,6 +488,302 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
     }
 }
 
+// Leading groups whose residual bound is below tol (NaN bounds are not), at least `old`.
+PN_DEV int elk_open_start(const uint32_t* grmax, int g0, int G, float tol, int old) {
+    const int l = threadIdx.x & 63;
+    const uint32_t tolb = __float_as_uint(tol);
+    int fz = G;
+    for (int base = 0; base < G; base += 64) {
+        const bool open = base + l < G && !(grmax[g0 + base + l] < tolb);
+        const uint64_t m = __ballot(open);
+        if (m) {
+            fz = base + __ffsll((unsigned long long)m) - 1;
+            break;
+        }
+    }
+    return max(fz, old);
+}
+
+// ---- quasi-ELK: the LGSSM on diag(A_t) (Ch. 4, "quasi-ELK") ----------------------------------
+// With a diagonal transition every unit is its own scalar LGSSM, so every quantity of the
+// filter -- the elements (A, b, C, eta, J), the filtered (m, P), Gamma -- is one number per unit
+// and the 16x16 products and inverses become scalar arithmetic.  Lane l works on unit l & 15
+// (the four 16-lane quarters of the wave hold the same values; the first writes them).
+// Stored element: A, b, C, eta, J (16 each); filtered state: P, m.  KF = false (lambda = 0):
+// the element is (A, b) and the filter is m = a m - r (quasi-DEER).
+constexpr int EQ = 5 * ED;
+constexpr int EQC = 2 * ED;
+
+template <int DX, bool MF, bool KF>
+__global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
+    constexpr int L = EL;
+    constexpr int KT = ED + DX;
+    constexpr int SS = ED + 4;
+    static_assert(KT % 4 == 0, "shape");
+    __shared__ __attribute__((aligned(16))) float sst[(L + 1) * SS];
+    __shared__ __attribute__((aligned(16))) float xst[L * (DX + 4)];
+    __shared__ float dsh[L * ED], rsh[L * ED];
+    __shared__ float Wm[EM];
+    __shared__ int badrow;
+
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int k_it = a.ctrl->iter;
+    const bool fuse = k_it > 0;
+    const float reset_abs = a.ctrl->reset_abs;
+    const float lam = a.lam;
+    const float s1 = 1.f / (1.f + lam);           // 1 / (1 + lambda)
+    const float kap = lam / (1.f + lam);         // kappa
+    const float* __restrict__ sprev = a.sbuf[(k_it + 1) & 1];   // s^(k-1)
+    float* __restrict__ scur = a.sbuf[k_it & 1];                 // s^(k)
+    const int l = threadIdx.x, u = l & 15;
+    const float* U = a.params + ED * ED;
+    float blin[KT / 4];
+    float bias_u;
+    elk_load_weights<DX>(Wm, blin, bias_u, a.params);
+    __syncthreads();
+    const float wd = Wm[u * ES + u];              // diag(A_t)_u = d_t[u] W_uu for both cells
+    auto linearise = [&](bool first, int len, bool track) -> uint32_t {
+        return elk_linearise<DX, MF>(sst, xst, dsh, rsh, blin, bias_u, Wm, U, first, len, track,
+                                     a.res64 != 0);
+    };
+
+    for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+        const GroupInfo gr = a.groups[gi];
+        if (a.seq[gr.b].status != kActive) continue;
+        const int b = gr.b;
+        if (a.freeze) {
+            const int gg = gi - a.group_start[b];
+            if (gg < a.seq[b].frozen_prev) continue;            // frozen, both buffers hold it
+            if (gg < a.seq[b].frozen) {                         // frozen by the last carry pass
+                if (fuse) {
+                    for (int kt = 0; kt < gr.ntl; ++kt) {
+                        const TileInfo ti = a.tiles[gr.tile0 + kt];
+                        for (int idx = l; idx < ti.len * (ED / 4); idx += 64) {
+                            const size_t o = (size_t)ti.row0 * ED + 4 * idx;
+                            *(float4*)(scur + o) = *(const float4*)(sprev + o);
+                        }
+                    }
+                }
+                continue;
+            }
+        }
+        uint32_t rmax = 0;
+        int nreset = 0;
+        float m = 0.f, P = 0.f;                 // filtered state (replay)
+        if (fuse) {
+            const float* cr = a.gcar + (size_t)gi * EQC;
+            m = cr[ED + u];
+            if (KF) P = cr[u];
+        }
+        // the group's element, from the identity (A, b, C, eta, J) = (1, 0, 0, 0, 0)
+        float eA = 1.f, eb = 0.f, eC = 0.f, ee = 0.f, eJ = 0.f;
+        for (int kt = 0; kt < gr.ntl; ++kt) {
+            const TileInfo ti = a.tiles[gr.tile0 + kt];
+            const int len = ti.len;
+            const int64_t row0 = ti.row0;
+            const bool first = (ti.flags & kTileTimeFirst) != 0;
+            __syncthreads();
+            elk_stage<DX>(sst, xst, fuse ? sprev : scur, a.s0, a.x, b, row0, len, first);
+            if (l == 0) badrow = 0;
+            __syncthreads();
+
+            if (fuse) {
+                // ---- the previous iteration's step: the scalar filters from the entering (m, P)
+                linearise(first, len, false);
+                float hv = 0.f;
+                if (!first && l < ED) {
+                    hv = sst[u] + m;                  // s^(k) of the row before the chunk
+                    if (!(fabsf(hv) <= reset_abs)) badrow = 1;
+                }
+                for (int t = 0; t < len; ++t) {
+                    const float at = dsh[t * ED + u] * wd, rt = rsh[t * ED + u];
+                    if (KF) {
+                        const float pm = at * at * P + 1.f;             // P- = a^2 P + 1
+                        const float gam = 1.f / (lam * pm + 1.f);       // Gamma
+                        P = gam * pm;
+                        m = gam * (at * m - rt);
+                    } else {
+                        m = at * m - rt;
+                    }
+                    const float v = sst[(t + 1) * SS + u] + m;
+                    const bool rb = __any(!(fabsf(v) <= reset_abs));
+                    if (l < ED) sst[(t + 1) * SS + u] = rb ? 0.f : v;
+                    nreset += rb ? 1 : 0;
+                }
+                __syncthreads();
+                if (!first && l < ED) sst[u] = badrow ? 0.f : hv;
+                __syncthreads();
+                for (int idx = l; idx < len * (ED / 4); idx += 64) {
+                    const int r = idx / (ED / 4), c4 = idx % (ED / 4);
+                    *(float4*)(scur + (size_t)(row0 + r) * ED + 4 * c4) =
+                        *(const float4*)(sst + (r + 1) * SS + 4 * c4);
+                }
+            }
+
+            // ---- linearise at s^(k), then fold the chunk's leaves into the group's element
+            rmax = max(rmax, linearise(first, len, true));
+            for (int t = 0; t < len; ++t) {
+                const float at = dsh[t * ED + u] * wd, rt = rsh[t * ED + u];
+                if (!KF) {                            // (A, b) <- (a A, a b - r)
+                    eA = at * eA;
+                    eb = at * eb - rt;
+                    continue;
+                }
+                // leaf j = (s1 a, -s1 r, s1, kappa a r, kappa a^2), composed after the element
+                const float ja = s1 * at, jb = -s1 * rt, je = kap * at * rt, jj = kap * at * at;
+                const float g = 1.f / (1.f + eC * jj);
+                const float ag = ja * g;
+                const float ne = eA * g * (je - jj * eb) + ee;
+                const float nj = eA * g * jj * eA + eJ;
+                const float nb = ag * (eb + eC * je) + jb;
+                const float nc = ag * eC * ja + s1;
+                eA = ag * eA;
+                eb = nb;
+                eC = nc;
+                ee = ne;
+                eJ = nj;
+            }
+        }
+        float* ge = a.gel + (size_t)gi * EQ;
+        if (l < ED) {
+            ge[u] = eA;
+            ge[ED + u] = eb;
+            if (KF) {
+                ge[2 * ED + u] = eC;
+                ge[3 * ED + u] = ee;
+                ge[4 * ED + u] = eJ;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
+        if (l == 0) {
+            a.grmax[gi] = rmax;
+            atomicMax(&a.seq[b].maxr, rmax);
+            if (nreset) atomicAdd(&a.seq[b].resets_pending, nreset);
+        }
+    }
+}
+
+// Quasi carry pass: one 1024-thread workgroup per sequence, thread (unit u, segment sg).  The
+// open groups of the sequence are cut into kQSeg segments; every thread composes its segment's
+// elements, an inclusive scan over the segments (in LDS, log2 kQSeg levels) gives the element of
+// every prefix, whose (b, C) is the filtered state the prefix leaves from (m, P) = (0, 0); every
+// thread then walks its segment again from that state and writes the state entering each group.
+constexpr int kQSeg = 64;
+constexpr int kQBatch = 8;                        // elements fetched together
+
+struct QElem {
+    float A, b, C, e, J;
+};
+
+template <bool KF>
+PN_DEV QElem qcompose(const QElem& i, const QElem& j) {     // i followed by j
+    if (!KF) return QElem{j.A * i.A, j.A * i.b + j.b, 0.f, 0.f, 0.f};
+    const float g = 1.f / (1.f + i.C * j.J);
+    const float ag = j.A * g;
+    QElem o;
+    o.A = ag * i.A;
+    o.b = ag * (i.b + i.C * j.e) + j.b;
+    o.C = ag * i.C * j.A + j.C;
+    o.e = i.A * g * (j.e - j.J * i.b) + i.e;
+    o.J = i.A * g * j.J * i.A + i.J;
+    return o;
+}
+
+template <bool KF>
+__global__ void __launch_bounds__(1024) elk_quasi_carry_kernel(const float* __restrict__ gel,
+                                                               float* __restrict__ gcar,
+                                                               const Ctrl* ctrl, SeqState* seq,
+                                                               const int32_t* group_start,
+                                                               const uint32_t* grmax,
+                                                               int freeze, int B) {
+    __shared__ QElem sc[kQSeg][ED];
+    __shared__ int gs_sh;
+    if (ld_i32(&ctrl->all_done)) return;
+    const int b = blockIdx.x;
+    if (b >= B || seq[b].status != kActive) return;
+    const int tid = threadIdx.x, u = tid & 15, sg = tid >> 4;
+    const int g0 = group_start[b], G = group_start[b + 1] - g0;
+    int gstart = 0;
+    if (freeze) {
+        if (tid < 64) {
+            const int old = seq[b].frozen;
+            const int gs = elk_open_start(grmax, g0, G, ctrl->tol, old);
+            if (tid == 0) {
+                seq[b].frozen_prev = old;
+                seq[b].frozen = gs;
+                gs_sh = gs;
+            }
+        }
+        __syncthreads();
+        gstart = gs_sh;
+    }
+    const int per = (G - gstart + kQSeg - 1) / kQSeg;
+    const int lo = gstart + sg * per, hi = min(G, lo + per);
+    auto fetch = [&](int gg) {
+        const float* e = gel + (size_t)(g0 + gg) * EQ;
+        QElem q{e[u], e[ED + u], 0.f, 0.f, 0.f};
+        if (KF) {
+            q.C = e[2 * ED + u];
+            q.e = e[3 * ED + u];
+            q.J = e[4 * ED + u];
+        }
+        return q;
+    };
+    // 1. the segment's element
+    QElem acc{1.f, 0.f, 0.f, 0.f, 0.f};
+    for (int base = lo; base < hi; base += kQBatch) {
+        QElem e[kQBatch];
+#pragma unroll
+        for (int k = 0; k < kQBatch; ++k)
+            if (base + k < hi) e[k] = fetch(base + k);
+#pragma unroll
+        for (int k = 0; k < kQBatch; ++k)
+            if (base + k < hi) acc = qcompose<KF>(acc, e[k]);
+    }
+    // 2. inclusive scan over the segments
+    sc[sg][u] = acc;
+    __syncthreads();
+    for (int d = 1; d < kQSeg; d <<= 1) {
+        QElem prev{1.f, 0.f, 0.f, 0.f, 0.f};
+        if (sg >= d) prev = sc[sg - d][u];
+        __syncthreads();
+        if (sg >= d) {
+            acc = qcompose<KF>(prev, acc);
+            sc[sg][u] = acc;
+        }
+        __syncthreads();
+    }
+    // 3. walk the segment from the state the earlier segments leave
+    float m = 0.f, P = 0.f;
+    if (sg > 0) {
+        m = sc[sg - 1][u].b;
+        P = sc[sg - 1][u].C;
+    }
+    for (int base = lo; base < hi; base += kQBatch) {
+        QElem e[kQBatch];
+#pragma unroll
+        for (int k = 0; k < kQBatch; ++k)
+            if (base + k < hi) e[k] = fetch(base + k);
+#pragma unroll
+        for (int k = 0; k < kQBatch; ++k) {
+            if (base + k < hi) {
+                float* cr = gcar + (size_t)(g0 + base + k) * EQC;
+                cr[u] = P;
+                cr[ED + u] = m;
+                if (KF) {             // G = 1 / (1 + P J), m' = A G (m + P eta) + b, P' = A G P A + C
+                    const float g = 1.f / (1.f + P * e[k].J);
+                    const float ag = e[k].A * g;
+                    m = ag * (m + P * e[k].e) + e[k].b;
+                    P = ag * P * e[k].A + e[k].C;
+                } else {
+                    m = e[k].A * m + e[k].b;
+                }
+            }
+        }
+    }
+}
+
 // ---- carry pass: the filtered state entering every group ------------------------------------
 // One single-wave workgroup per sequence: (m, P) = (0, 0) before the first group; a group's
 // element maps it on by  G = (I + P J)^-1,  m' = A G (m + P eta) + b,  P' = A G P A^T + C.
@@ -579,22 +875,6 @@ __global__ void __launch_bounds__(64) elk_carry_kernel(const float* __restrict__
 //           writes the state entering every group.
 // A sequence of G open groups then costs about (RQ - 1) compositions, G / RQ and RQ
 // applications of dependent work instead of G applications.
-
-// Leading groups whose residual bound is below tol (NaN bounds are not), at least `old`.
-PN_DEV int elk_open_start(const uint32_t* grmax, int g0, int G, float tol, int old) {
-    const int l = threadIdx.x & 63;
-    const uint32_t tolb = __float_as_uint(tol);
-    int fz = G;
-    for (int base = 0; base < G; base += 64) {
-        const bool open = base + l < G && !(grmax[g0 + base + l] < tolb);
-        const uint64_t m = __ballot(open);
-        if (m) {
-            fz = base + __ffsll((unsigned long long)m) - 1;
-            break;
-        }
-    }
-    return max(fz, old);
-}
 
 // An element held in LDS (stride-ES matrices)
 struct ElkElem {
@@ -1099,9 +1379,11 @@ static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngrou
 
 bool elk_supported(int D, int Dx) { return D == ED && Dx == 16; }
 
-static int elk_resident(bool kf) {
-    const void* k = kf ? (const void*)elk_local_kernel<16, false, true>
-                       : (const void*)elk_local_kernel<16, false, false>;
+static int elk_resident(bool kf, bool quasi = false) {
+    const void* k = quasi ? (kf ? (const void*)elk_quasi_local_kernel<16, false, true>
+                                : (const void*)elk_quasi_local_kernel<16, false, false>)
+                          : (kf ? (const void*)elk_local_kernel<16, false, true>
+                                : (const void*)elk_local_kernel<16, false, false>);
     int occ = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 64, 0) != hipSuccess || occ < 1)
         occ = 1;
@@ -1135,6 +1417,21 @@ static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, 
     return best;
 }
 
+// Chunks per group of the quasi passes: the local pass takes rounds * gt chunks of latency;
+// the segmented carry is a few element fetches per segment, so the fewest rounds win, and
+// among equal rounds * gt the larger groups (fewer elements).
+static int elk_quasi_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, int tile) {
+    if (tile > 0) return tile / EL;
+    const int resident = elk_resident(true, true);
+    int best = 1;
+    double best_cost = 1e300;
+    for (int gt = 1; gt <= 64; gt *= 2) {
+        const double cost = std::ceil((double)count_groups(ts, hb.B, gt) / resident) * gt;
+        if (cost <= best_cost) { best_cost = cost; best = gt; }
+    }
+    return best;
+}
+
 // lambda is not known here: room for the grouping of either pass family
 // longest sequence in groups of gt chunks
 static int elk_max_groups(const HostBatch& hb, const std::vector<int32_t>& ts, int gt) {
@@ -1147,6 +1444,10 @@ static int elk_max_groups(const HostBatch& hb, const std::vector<int32_t>& ts, i
 size_t elk_workspace(int, int, const HostBatch& hb, const pn_opts& o) {
     const std::vector<int32_t> ts = tile_starts(hb, EL);
     size_t n = 0;
+    if (o.jac == PN_JAC_DIAG && !o.smooth) {
+        const int gt = elk_quasi_group_tiles(hb, ts, o.tile);
+        n = elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt), false, 0).bytes;
+    }
     for (int kf = 0; kf < 2; ++kf) {
         const int gt = elk_group_tiles(hb, ts, o.tile, kf != 0);
         const int gmax = elk_max_groups(hb, ts, gt);
@@ -1168,18 +1469,24 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const bool mf = cd.cell == PN_CELL_MEANFIELD;
     // the Kalman machinery is needed unless lambda = 0 (the smoother needs the covariances)
     const bool kf = lambda > 0 || o.smooth != 0;
+    const bool smooth = o.smooth != 0;
+    // quasi-ELK filter passes: scalar per unit (the smoother keeps the matrix passes)
+    const bool quasi = o.jac == PN_JAC_DIAG && !smooth;
     void (*kern)(ElkArgs) =
-        mf ? (kf ? elk_local_kernel<16, true, true> : elk_local_kernel<16, true, false>)
-           : (kf ? elk_local_kernel<16, false, true> : elk_local_kernel<16, false, false>);
+        quasi ? (mf ? (kf ? elk_quasi_local_kernel<16, true, true>
+                          : elk_quasi_local_kernel<16, true, false>)
+                    : (kf ? elk_quasi_local_kernel<16, false, true>
+                          : elk_quasi_local_kernel<16, false, false>))
+        : mf ? (kf ? elk_local_kernel<16, true, true> : elk_local_kernel<16, true, false>)
+             : (kf ? elk_local_kernel<16, false, true> : elk_local_kernel<16, false, false>);
     void (*skern)(ElkSmArgs) = mf ? elk_smooth_kernel<16, true> : elk_smooth_kernel<16, false>;
     const std::vector<int32_t> ts = tile_starts(hb, EL);
     const int ntiles = ts[hb.B];
-    const int resident = elk_resident(kf);
-    const int gt = elk_group_tiles(hb, ts, o.tile, kf);
+    const int resident = elk_resident(kf, quasi);
+    const int gt = quasi ? elk_quasi_group_tiles(hb, ts, o.tile) : elk_group_tiles(hb, ts, o.tile, kf);
     const int ngroups = count_groups(ts, hb.B, gt);
-    const bool smooth = o.smooth != 0;
     const int gmax = elk_max_groups(hb, ts, gt);
-    const int rq = kf ? elk_run_len(gmax) : 0;      // three-phase carry for long sequences
+    const int rq = kf && !quasi ? elk_run_len(gmax) : 0;    // three-phase carry, long sequences
     const int nrun = rq ? (gmax + rq - 1) / rq : 0;
     ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups, smooth, nrun * hb.B);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
@@ -1251,7 +1558,15 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         prof_launch("elk_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
         });
-        if (rq) {
+        if (quasi) {
+            prof_launch("elk_carry", st, [&](hipStream_t s2) {
+                hipLaunchKernelGGL(kf ? elk_quasi_carry_kernel<true> : elk_quasi_carry_kernel<false>,
+                                   dim3(std::max(1, hb.B)), dim3(1024), 0, s2,
+                                   (const float*)lay.gel, lay.gcar, (const Ctrl*)lay.st.ctrl,
+                                   lay.st.seq, (const int32_t*)lay.st.group_start,
+                                   (const uint32_t*)lay.grmax, args.freeze, hb.B);
+            });
+        } else if (rq) {
             prof_launch("elk_carry", st, [&](hipStream_t s2) {
                 hipLaunchKernelGGL(elk_run_fold_kernel, dim3(hb.B * nrun), dim3(64), 0, s2, ra);
                 hipLaunchKernelGGL(elk_run_walk_kernel, dim3(hb.B), dim3(64), 0, s2, ra);
