@@ -1114,6 +1114,118 @@ __global__ void __launch_bounds__(64) elk_deer_carry_kernel(const float* __restr
     }
 }
 
+// The same carry for long sequences, in segments: a 1024-thread workgroup per sequence, wave w
+// composes the maps of segment w of the open groups (A <- A_g A, b <- A_g b + b_g), wave 0
+// walks the 16 segment maps from m = 0, and every wave then walks its segment from the state
+// entering it.
+constexpr int kDSeg = 16;
+constexpr int kDStr = ED + 4;                 // LDS row stride (float4-aligned rows)
+constexpr int kDBatch = 8;                    // group maps fetched together
+
+__global__ void __launch_bounds__(1024) elk_deer_seg_carry_kernel(
+    const float* __restrict__ gel, float* __restrict__ gcar, const Ctrl* ctrl, SeqState* seq,
+    const int32_t* group_start, const uint32_t* grmax, int freeze, int B) {
+    __shared__ __attribute__((aligned(16))) float Sm[kDSeg][ED * kDStr];
+    __shared__ float Sb[kDSeg][ED];
+    __shared__ float Me[kDSeg][ED];
+    __shared__ int gs_sh;
+    if (ld_i32(&ctrl->all_done)) return;
+    const int b = blockIdx.x;
+    if (b >= B || seq[b].status != kActive) return;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, r = l & 15, q = l >> 4;
+    const int g0 = group_start[b], G = group_start[b + 1] - g0;
+    int gstart = 0;
+    if (freeze) {
+        if (w == 0) {
+            const int old = seq[b].frozen;
+            const int gs = elk_open_start(grmax, g0, G, ctrl->tol, old);
+            if (l == 0) {
+                seq[b].frozen_prev = old;
+                seq[b].frozen = gs;
+                gs_sh = gs;
+            }
+        }
+        __syncthreads();
+        gstart = gs_sh;
+    }
+    const int per = (G - gstart + kDSeg - 1) / kDSeg;
+    const int lo = gstart + w * per, hi = min(G, lo + per);
+    float* M = Sm[w];
+    float* bv = Sb[w];
+    // lane (r, q)'s share of a group's map: A[r][4q .. 4q+3] and b[r]; fetched kDBatch at a time
+    auto load = [&](int gg, float4& av, float& bb) {
+        const float* e = gel + (size_t)(g0 + gg) * EGEL;
+        av = *(const float4*)(e + r * ED + 4 * q);
+        bb = e[3 * ED * ED + r];
+    };
+    // 1. the segment's map on FP32 MFMA 16x16x4: lane (r, q) holds A[4q + i][r] (i = 0..3, the
+    //    product's output layout) and b[r].  Taking the K index of step kb as 4q + kb, the A
+    //    operand of A_g A is the lane's own A_g[r][4q + kb] and the B operand its own
+    //    accumulator entry i = kb, so only b needs data from other lanes.
+    floatx4 acc = {r == 4 * q ? 1.f : 0.f, r == 4 * q + 1 ? 1.f : 0.f,
+                   r == 4 * q + 2 ? 1.f : 0.f, r == 4 * q + 3 ? 1.f : 0.f};
+    float bacc = 0.f;
+    for (int base = lo; base < hi; base += kDBatch) {
+        float4 ea[kDBatch];
+        float eb[kDBatch];
+#pragma unroll
+        for (int k = 0; k < kDBatch; ++k)
+            if (base + k < hi) load(base + k, ea[k], eb[k]);
+#pragma unroll
+        for (int k = 0; k < kDBatch; ++k) {
+            if (base + k >= hi) break;
+            floatx4 o = {0.f, 0.f, 0.f, 0.f};
+            o = mfma16x4(ea[k].x, acc[0], o);
+            o = mfma16x4(ea[k].y, acc[1], o);
+            o = mfma16x4(ea[k].z, acc[2], o);
+            o = mfma16x4(ea[k].w, acc[3], o);
+            float pb = ea[k].x * __shfl(bacc, 4 * q) + ea[k].y * __shfl(bacc, 4 * q + 1) +
+                       ea[k].z * __shfl(bacc, 4 * q + 2) + ea[k].w * __shfl(bacc, 4 * q + 3);
+            pb += __shfl_xor(pb, 16);
+            pb += __shfl_xor(pb, 32);
+            bacc = pb + eb[k];
+            acc = o;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) M[(4 * q + i) * kDStr + r] = acc[i];
+    if (q == 0) bv[r] = bacc;
+    __syncthreads();
+    // 2. the state entering every segment
+    if (w == 0) {
+        float m = 0.f;
+        for (int s = 0; s < kDSeg; ++s) {
+            if (q == 0) Me[s][r] = m;
+            const float4 as = *(const float4*)(Sm[s] + r * kDStr + 4 * q);
+            float v = as.x * __shfl(m, 4 * q) + as.y * __shfl(m, 4 * q + 1) +
+                      as.z * __shfl(m, 4 * q + 2) + as.w * __shfl(m, 4 * q + 3);
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            m = v + Sb[s][r];
+        }
+    }
+    __syncthreads();
+    // 3. every group's entering state
+    float m = Me[w][r];
+    for (int base = lo; base < hi; base += kDBatch) {
+        float4 ea[kDBatch];
+        float eb[kDBatch];
+#pragma unroll
+        for (int k = 0; k < kDBatch; ++k)
+            if (base + k < hi) load(base + k, ea[k], eb[k]);
+#pragma unroll
+        for (int k = 0; k < kDBatch; ++k) {
+            if (base + k >= hi) break;
+            if (q == 0) gcar[(size_t)(g0 + base + k) * ECAR + ED * ED + r] = m;
+            float v = ea[k].x * __shfl(m, 4 * q) + ea[k].y * __shfl(m, 4 * q + 1) +
+                      ea[k].z * __shfl(m, 4 * q + 2) + ea[k].w * __shfl(m, 4 * q + 3);
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            m = v + eb[k];
+        }
+    }
+}
+
 // ---- smoother (the exact LM step): RTS backward pass -----------------------------------------
 // With the filtered means and covariances (m_t, P_t) and the predictions (m-_t, P-_t),
 //   E_t = P_t A_{t+1}^T (P-_{t+1})^-1,   g_t = m_t - E_t m-_{t+1},   m^s_t = E_t m^s_{t+1} + g_t,
@@ -1390,6 +1502,9 @@ static int elk_resident(bool kf, bool quasi = false) {
     return cu_count() * occ;
 }
 
+// The DEER carry (lambda = 0) runs in segments once a sequence has this many groups.
+static bool elk_deer_segmented(int gmax) { return gmax >= 2 * kDSeg; }
+
 // Chunks per group.  An explicit tile (a multiple of 16 steps) fixes it.  Otherwise a cost
 // model picks it: the local pass takes rounds * gt chunks of latency (rounds = groups per
 // resident workgroup), the carry pass one element application per group of the longest
@@ -1410,7 +1525,10 @@ static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, 
         const double rounds = std::ceil((double)ng / resident);
         const int gmax = (maxc + gt - 1) / gt;
         const int rq = kf ? elk_run_len(gmax) : 0;
-        const double carry = rq ? 2.4 * rq + std::ceil((double)gmax / rq) : gmax;
+        const double seg = std::ceil((double)gmax / kDSeg);      // segmented DEER carry
+        const double carry = rq                           ? 2.4 * rq + std::ceil((double)gmax / rq)
+                             : (!kf && elk_deer_segmented(gmax)) ? 4.0 * seg + kDSeg
+                                                              : gmax;
         const double cost = rounds * gt * kLocalPerCarry + carry;
         if (cost < best_cost) { best_cost = cost; best = gt; }
     }
@@ -1574,8 +1692,10 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
             });
         } else
         prof_launch("elk_carry", st, [&](hipStream_t s2) {
-            hipLaunchKernelGGL(kf ? elk_carry_kernel : elk_deer_carry_kernel,
-                               dim3(std::max(1, hb.B)), dim3(64), 0, s2,
+            const bool segd = !kf && elk_deer_segmented(gmax);
+            hipLaunchKernelGGL(kf ? elk_carry_kernel
+                                  : segd ? elk_deer_seg_carry_kernel : elk_deer_carry_kernel,
+                               dim3(std::max(1, hb.B)), dim3(segd ? 1024 : 64), 0, s2,
                                (const float*)lay.gel, lay.gcar, (const Ctrl*)lay.st.ctrl,
                                lay.st.seq, (const int32_t*)lay.st.group_start,
                                (const uint32_t*)lay.grmax, args.freeze, hb.B);

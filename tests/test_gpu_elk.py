@@ -66,6 +66,24 @@ def test_grouped_iterates_match_sequential_filter(lib, tile, jac):
             assert np.abs(s[a:e] - out["s"]).max() < 2e-5, (tile, k, b)
 
 
+@pytest.mark.parametrize("jac", ["dense", "diag"])
+def test_deer_long_groups_match_oracle(lib, jac):
+    """lambda = 0 with one 16-step chunk per group on long ragged sequences: at least 32
+    groups per sequence take the segmented carry (dense), more than 64 groups several groups
+    per carry segment (diag); iterates equal the oracle's DEER / quasi-DEER after 1-3
+    iterations (bar 2e-5 relative to max(1, max |s|): early DEER iterates grow)."""
+    w = workloads.TANH16_ELK.scaled(B=4, T=0)
+    inst = workloads.make_instance(w, seed=37, lengths=np.array([1100, 530, 16, 1700]))
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    for k in (1, 2, 3):
+        s, info = _elk(lib, inst, 0.0, tol=1e-12, max_iters=k, jac=jac, tile=16)
+        for b in range(4):
+            a, e = inst.offsets[b], inst.offsets[b + 1]
+            ref = newton.newton(cell, inst.x[a:e], inst.s0[b], mode=jac, tol=1e-12,
+                                max_iters=k)["s"]
+            assert np.abs(s[a:e] - ref).max() < 2e-5 * max(1.0, np.abs(ref).max()), (k, b)
+
+
 def test_multichunk_converges_to_rollout(lib):
     w = workloads.TANH16_ELK.scaled(B=2, T=0)
     inst = workloads.make_instance(w, seed=32, lengths=np.array([300, 77]))
@@ -174,15 +192,21 @@ def _safe_iters(cell, inst, lam, jac, tol, tile):
     return hist, last, events
 
 
-@pytest.mark.parametrize("lam,jac,tile,tol", [(0.0, "dense", 16, 1e-3),
-                                              (0.05, "dense", 48, 1e-3),
-                                              (0.05, "diag", 32, 1.2e-3)])
-def test_freeze_prefix_iterates_match_oracle(lib, lam, jac, tile, tol):
+@pytest.mark.parametrize("lam,jac,tile,tol,lengths,gain", [
+    (0.0, "dense", 16, 1e-3, (300, 77, 160), None),
+    (0.0, "dense", 16, 1e-3, (1100, 77, 600), 0.9),  # >= 32 groups: segmented DEER carry
+    (0.05, "dense", 48, 1e-3, (300, 77, 160), None),
+    (0.05, "diag", 32, 1.2e-3, (300, 77, 160), None),
+    (0.05, "diag", 16, 1.2e-3, (1400, 77, 600), None)])  # > 64 groups: several per segment
+def test_freeze_prefix_iterates_match_oracle(lib, lam, jac, tile, tol, lengths, gain):
     """Converged-prefix skipping: per-iteration iterates equal the oracle's loop with the
     same block length (tile) while the freeze decisions are unambiguous in FP32; the bar is
-    2e-5 relative to max(1, max |s|)."""
-    w = workloads.TANH16_ELK.scaled(B=3, T=0)
-    inst = workloads.make_instance(w, seed=36, lengths=np.array([300, 77, 160]))
+    2e-5 relative to max(1, max |s|).  The long DEER case uses a contracting instance
+    (gain 0.9): on the chaotic one a DEER step from a 600-step iterate moves by up to 2e-4
+    under FP32 rounding of that iterate alone (oracle, perturbed input), above any bar that
+    would still catch an error."""
+    w = workloads.TANH16_ELK.scaled(B=3, T=0, **({} if gain is None else {"gain": gain}))
+    inst = workloads.make_instance(w, seed=36, lengths=np.array(lengths))
     cell = cells.TanhRNN(inst.params, w.D, w.Dx)
     hist, last, events = _safe_iters(cell, inst, lam, jac, tol, tile)
     nmax = max(len(h) for h in hist) - 1
