@@ -133,7 +133,12 @@ typedef struct {
     int32_t smooth;           /* elk_solve: 1 = take the smoothed means (the exact LM step of
                                  Prop. ELK, Kalman filter plus RTS backward pass); 0 = the
                                  filtered means                                            */
-    int32_t reserved[1];
+    int32_t group;            /* chunks of `tile` steps per group of the two-pass scans (the
+                                 local pass works a group at a time, the carry pass walks the
+                                 groups): 1..64, or 0 = chosen by the library's cost model.
+                                 Used by deer_solve (GRU diagonal, tanh dense) and
+                                 deer_adjoint; elk_solve takes its group length as `tile`
+                                 and requires 0 here.  pn_autotune measures it.            */
 } pn_opts;
 
 typedef struct {
@@ -240,6 +245,48 @@ pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const
    "gru_quasi_iter", "gru_adj_iter", "gru_adj_prep", "gru_adj_grad", "tanh_dense_iter",
    "gru_dense64_solve", "elk_iter", "seq_rollout", "seq_adj".  Returns 0 if the family was
    not launched. */
+/* Scan-tile autotuner (batching, "scan tile sizes chosen by a project-written autotuner").
+   pn_autotune times op (PN_OP_DEER, PN_OP_ELK or PN_OP_ADJOINT) on the caller's own inputs
+   once per candidate (tile, group) -- a warm-up call, then a timed call of probe_iters
+   iterations with tol ~ 0 so that every candidate runs them all, HIP events on `stream`
+   around the whole call (host checks included) -- and returns the fastest in *out.
+   Candidates: deer_solve GRU diagonal: tile in {32, 64, 128} x group in {0, 1, 2, 4, 8, 16};
+   deer_solve tanh dense and deer_adjoint: group in {0, 1, 2, 4, 8, 16}; elk_solve: tile in
+   {0, 16, 32, 64, 128, 256}; other routes: the single candidate (0, 0).
+   Results are kept per process under a key of the route's shapes and options (cell, D, Dx,
+   dtype, jac, compose, damping, lambda > 0, smooth, freeze_prefix, graph options, B and
+   the bit lengths of N and of the longest sequence); a known key returns at once with
+   out->from_cache = 1 and runs nothing.  When the environment variable PN_AUTOTUNE_CACHE
+   names a file, a key missing in the process is looked up in that file (JSON object of
+   "key": [tile, group] entries) and every newly measured key is written back to it.
+   bufs: the op's device buffers in the order of its solve call --
+     PN_OP_DEER, PN_OP_ELK: {x, s0, s}; s is restored before return (the workspace keeps a
+       copy), so it may hold the caller's initial guess;
+     PN_OP_ADJOINT: {x, s0, s, gs, gx, gs0, gparams}; gx, gs0 may be NULL; the outputs
+       gx, gs0, gparams hold unspecified values afterwards.
+   lambda: elk_solve's lambda (ignored otherwise).  probe_iters: 1..64 (<= 0: 3).
+   workspace: at least pn_workspace_bytes(op | PN_OP_TUNE, ...) bytes (256-byte aligned).
+   Errors: those of the solve call (a candidate that the route rejects is skipped);
+   PN_ERR_HIP if timing fails. */
+#define PN_OP_TUNE 0x100
+#define PN_TUNE_MAX_CAND 32
+typedef struct {
+    int32_t tile;             /* best candidate's pn_opts.tile */
+    int32_t group;            /* best candidate's pn_opts.group */
+    double ms_per_iter;       /* its time per iteration (0 when from_cache) */
+    int32_t from_cache;       /* 1: taken from the process or file cache, nothing was run */
+    int32_t ncand;            /* candidates timed (0 when from_cache) */
+    int32_t cand_tile[PN_TUNE_MAX_CAND];
+    int32_t cand_group[PN_TUNE_MAX_CAND];
+    float cand_ms[PN_TUNE_MAX_CAND];   /* ms per iteration; < 0: the route rejected it */
+} pn_tuned;
+pn_status pn_autotune(int op, const pn_cell_desc* cell, const pn_batch* batch,
+                      const void* const* bufs, double lambda, const pn_opts* opts,
+                      int32_t probe_iters, void* workspace, size_t workspace_bytes,
+                      void* stream, pn_tuned* out);
+/* Forget the in-process autotune results (the cache file is left as it is). */
+void pn_autotune_reset(void);
+
 void pn_profile_begin(void);
 void pn_profile_end(void);
 int pn_profile_read(const char* family, double* total_ms, int64_t* launches);

@@ -39,7 +39,19 @@ class Opts(ctypes.Structure):
                 ("damping", ctypes.c_int32), ("damp_k", ctypes.c_float),
                 ("clip_lo", ctypes.c_float), ("clip_hi", ctypes.c_float),
                 ("freeze_prefix", ctypes.c_int32), ("smooth", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("group", ctypes.c_int32)]
+
+
+TUNE_MAX_CAND = 32
+OP_TUNE = 0x100
+
+
+class Tuned(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("ms_per_iter", ctypes.c_double), ("from_cache", ctypes.c_int32),
+                ("ncand", ctypes.c_int32), ("cand_tile", ctypes.c_int32 * TUNE_MAX_CAND),
+                ("cand_group", ctypes.c_int32 * TUNE_MAX_CAND),
+                ("cand_ms", ctypes.c_float * TUNE_MAX_CAND)]
 
 
 class SeqInfo(ctypes.Structure):
@@ -68,6 +80,10 @@ SIGNATURES = [
                                        ctypes.c_size_t, _V, _P(ctypes.c_double)]),
     ("pn_lle_estimate", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, _V, _V,
                                        ctypes.c_size_t, _V, _P(ctypes.c_double)]),
+    ("pn_autotune", ctypes.c_int, [ctypes.c_int, _P(CellDesc), _P(Batch), _P(_V),
+                                   ctypes.c_double, _P(Opts), ctypes.c_int32, _V,
+                                   ctypes.c_size_t, _V, _P(Tuned)]),
+    ("pn_autotune_reset", None, []),
     ("pn_profile_begin", None, []),
     ("pn_profile_end", None, []),
     ("pn_profile_read", ctypes.c_int, [ctypes.c_char_p, _P(ctypes.c_double),
@@ -148,7 +164,7 @@ DAMPING = {"none": 0, "scale": 1, "clip": 2}
 def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4,
               reset_abs=1e4, fp64_final_residual=False, use_graph=True, tile=0,
               damping="none", damp_k=0.0, clip=(-1.0, 1.0), freeze_prefix=False,
-              smooth=False):
+              smooth=False, group=0):
     """pn_opts; damping "scale" (scale-ELK, A~ <- (1 - damp_k) A~) or "clip" (clip-ELK,
     diagonal A~ clipped to `clip`)."""
     o = Opts()
@@ -167,6 +183,7 @@ def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4
     o.tile = int(tile)
     o.freeze_prefix = int(bool(freeze_prefix))
     o.smooth = int(bool(smooth))
+    o.group = int(group)
     return o
 
 
@@ -217,13 +234,64 @@ def _infos(arr):
 
 # ---- public functions (names follow the C ABI) ------------------------------------------------
 
+_OPS = {"deer": OP_DEER, "elk": OP_ELK, "adjoint": OP_ADJOINT}
+
+
+def autotune(op, x, s0, params, cell="gru", offsets=None, lam=0.0, s=None, gs=None,
+             probe_iters=3, **opt_kw):
+    """pn_autotune: the fastest (tile, group) of `op` ("deer", "elk" or "adjoint") for these
+    inputs and options.  For "deer" / "elk", `s` (default zeros) is the initial guess the
+    probes start from and is left unchanged; for "adjoint", `s` is the trajectory and `gs`
+    the loss gradient.  Returns dict(tile, group, ms_per_iter, from_cache, candidates =
+    [(tile, group, ms per iteration or None if rejected)])."""
+    torch = _torch()
+    code = _OPS[op]
+    for t, n in ((x, "x"), (s0, "s0"), (params, "params")):
+        _dev(t, n)
+    sh = _shapes(cell, params, x, s0, offsets)
+    if op == "elk":
+        opt_kw.setdefault("jac", "dense")
+    opts = make_opts(**opt_kw)
+    if s is None:
+        s = torch.zeros((x.shape[0], s0.shape[1]), dtype=x.dtype, device=x.device)
+    _dev(s, "s")
+    keep = []
+    if op == "adjoint":
+        _dev(gs, "gs")
+        keep = [torch.empty_like(x), torch.empty_like(s0), torch.empty_like(params)]
+        ptrs = [x, s0, s, gs] + keep
+    else:
+        ptrs = [x, s0, s]
+    bufs = (_V * len(ptrs))(*[t.data_ptr() for t in ptrs])
+    ws, nb = _workspace(code | OP_TUNE, sh, opts, x.device)
+    out = Tuned()
+    _check(load().pn_autotune(code, ctypes.byref(sh.cell), ctypes.byref(sh.batch), bufs,
+                              ctypes.c_double(lam), ctypes.byref(opts), int(probe_iters),
+                              _aligned(ws), nb, _stream(), ctypes.byref(out)))
+    cands = [(out.cand_tile[i], out.cand_group[i],
+              None if out.cand_ms[i] < 0 else float(out.cand_ms[i])) for i in range(out.ncand)]
+    return dict(tile=out.tile, group=out.group, ms_per_iter=out.ms_per_iter,
+                from_cache=bool(out.from_cache), candidates=cands)
+
+
+def _auto_tile(op, opt_kw, x, s0, params, cell, offsets, **extra):
+    """tile="auto": the autotuned (tile, group) replace the two options."""
+    if opt_kw.get("tile") != "auto":
+        return opt_kw
+    kw = dict(opt_kw)
+    kw.pop("tile")
+    kw.pop("group", None)
+    t = autotune(op, x, s0, params, cell=cell, offsets=offsets, **extra, **kw)
+    kw["tile"], kw["group"] = t["tile"], t["group"]
+    return kw
+
 def deer_solve(x, s0, params, cell="gru", offsets=None, s_init=None, **opt_kw):
     """DEER / quasi-DEER solve; returns (s [N, D], per-sequence info list)."""
     torch = _torch()
     for t, n in ((x, "x"), (s0, "s0"), (params, "params")):
         _dev(t, n)
     sh = _shapes(cell, params, x, s0, offsets)
-    opts = make_opts(**opt_kw)
+    opts = make_opts(**_auto_tile("deer", opt_kw, x, s0, params, cell, offsets, s=s_init))
     s = (torch.zeros((x.shape[0], s0.shape[1]), dtype=x.dtype, device=x.device)
          if s_init is None else _dev(s_init, "s_init").clone())
     ws, nb = _workspace(OP_DEER, sh, opts, x.device)
@@ -240,7 +308,8 @@ def elk_solve(x, s0, params, lam, cell="tanh", offsets=None, s_init=None, **opt_
         _dev(t, n)
     sh = _shapes(cell, params, x, s0, offsets)
     opt_kw.setdefault("jac", "dense")
-    opts = make_opts(**opt_kw)
+    opts = make_opts(**_auto_tile("elk", opt_kw, x, s0, params, cell, offsets, lam=lam,
+                                  s=s_init))
     s = (torch.zeros((x.shape[0], s0.shape[1]), dtype=x.dtype, device=x.device)
          if s_init is None else _dev(s_init, "s_init").clone())
     ws, nb = _workspace(OP_ELK, sh, opts, x.device)
@@ -258,7 +327,7 @@ def deer_adjoint(x, s0, params, s, gs, cell="gru", offsets=None, need_gx=True, n
     for t, n in ((x, "x"), (s0, "s0"), (params, "params"), (s, "s"), (gs, "gs")):
         _dev(t, n)
     sh = _shapes(cell, params, x, s0, offsets)
-    opts = make_opts(**opt_kw)
+    opts = make_opts(**_auto_tile("adjoint", opt_kw, x, s0, params, cell, offsets, s=s, gs=gs))
     gp = torch.empty_like(params)
     gx = torch.empty_like(x) if need_gx else None
     g0 = torch.empty_like(s0) if need_gs0 else None

@@ -7,12 +7,13 @@
 
 using namespace pn;
 
-namespace {
-
 // layouts the Python binding mirrors with ctypes
 static_assert(sizeof(pn_opts) == 72, "pn_opts layout");
 static_assert(sizeof(pn_cell_desc) == 24 && sizeof(pn_batch) == 24 && sizeof(pn_seq_info) == 24,
               "struct layouts");
+
+// validation shared with the autotuner
+namespace pn {
 
 pn_opts resolve_opts(const pn_opts* o) {
     pn_opts r;
@@ -22,8 +23,6 @@ pn_opts resolve_opts(const pn_opts* o) {
     if (!(r.reset_abs > 0)) r.reset_abs = 1e4;
     return r;
 }
-
-bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 pn_status check_cell(const pn_cell_desc* cell) {
     if (!cell) { set_error("cell descriptor is NULL"); return PN_ERR_INVALID_ARG; }
@@ -86,6 +85,7 @@ pn_status check_opts(const pn_opts& o) {
     }
     if (!(o.tol > 0) || !std::isfinite(o.tol)) { set_error("tol must be positive and finite"); return PN_ERR_INVALID_ARG; }
     if (o.tile < 0) { set_error("tile must be >= 0"); return PN_ERR_INVALID_ARG; }
+    if (o.group < 0 || o.group > 64) { set_error("group must be 0..64"); return PN_ERR_INVALID_ARG; }
     if (o.freeze_prefix != 0 && o.freeze_prefix != 1) {
         set_error("freeze_prefix must be 0 or 1");
         return PN_ERR_INVALID_ARG;
@@ -114,6 +114,12 @@ pn_status check_opts(const pn_opts& o) {
     }
     return PN_OK;
 }
+
+}  // namespace pn
+
+namespace {
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 pn_status check_ptrs(std::initializer_list<const void*> must, const HostBatch& hb) {
     if (hb.N == 0) return PN_OK;
@@ -167,6 +173,7 @@ void pn_default_opts(pn_opts* o) {
     o->fp64_final_residual = 0;
     o->use_graph = 1;
     o->tile = 0;
+    o->group = 0;
     o->damping = PN_DAMP_NONE;
     o->damp_k = 0.f;
     o->clip_lo = -1.f;
@@ -206,6 +213,7 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
     PN_TRY(check_batch(batch, hb));
     const pn_opts o = resolve_opts(opts);
     PN_TRY(check_opts(o));
+    if (op & PN_OP_TUNE) return autotune_workspace(op & ~PN_OP_TUNE, *cell, *batch, hb, o, bytes);
     switch (op) {
         case PN_OP_DEER:
             switch (route_deer(*cell, o)) {
@@ -320,6 +328,10 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
     if (o.smooth && o.freeze_prefix) {
         set_error("the smoother does not combine with converged-prefix skipping");
         return PN_ERR_UNSUPPORTED;
+    }
+    if (o.group != 0) {
+        set_error("elk_solve takes its group length as tile (group must be 0)");
+        return PN_ERR_INVALID_ARG;
     }
     if (o.tile % 16 != 0 || o.tile > 1024) {
         set_error("elk_solve tile must be 0 or a multiple of 16 up to 1024");

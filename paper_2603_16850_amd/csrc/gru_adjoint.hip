@@ -808,19 +808,19 @@ static bool gruA_lookup(int D, int Dx, GruAKernels* k) {
 }
 
 // Tile groups of the adjoint iteration for this batch.
-static int gruA_groups(const GruAKernels& kk, const std::vector<int32_t>& ts, int B, int* gt,
-                       int* resident) {
+static int gruA_groups(const GruAKernels& kk, const std::vector<int32_t>& ts, int B, int group,
+                       int* gt, int* resident) {
     *resident = gru_resident((const void*)kk.iter, kk.nt);
-    *gt = gru_group_tiles(ts[B], *resident);
+    *gt = group > 0 ? group : gru_group_tiles(ts[B], *resident);
     return count_groups(ts, B, *gt);
 }
 
-size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts&) {
+size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o) {
     GruAKernels kk;
     if (!gruA_lookup(D, Dx, &kk)) return 0;
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     int gt, resident;
-    const int ngroups = gruA_groups(kk, ts, hb.B, &gt, &resident);
+    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident);
     return gruA_layout(nullptr, D, Dx, hb, ts[hb.B], ngroups).bytes;
 }
 
@@ -837,7 +837,7 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     const int ntiles = ts[hb.B];
     int gt, resident;
-    const int ngroups = gruA_groups(kk, ts, hb.B, &gt, &resident);
+    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident);
     GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, ngroups);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, max_iters, (float)o.tol,

@@ -380,7 +380,7 @@ size_t gru_quasi_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o)
     if (!gruq_lookup(D, Dx, L, &kern, &nt)) return 0;
     const std::vector<int32_t> ts = tile_starts(hb, L);
     const int ntiles = ts[hb.B];
-    const int gt = gru_group_tiles(ntiles, gru_resident((const void*)kern, nt));
+    const int gt = o.group > 0 ? o.group : gru_group_tiles(ntiles, gru_resident((const void*)kern, nt));
     return gruq_layout(nullptr, D, hb, ntiles, count_groups(ts, hb.B, gt)).bytes;
 }
 
@@ -398,7 +398,7 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     const std::vector<int32_t> ts = tile_starts(hb, L);
     const int ntiles = ts[hb.B];
     const int resident = gru_resident((const void*)kern, nt);
-    const int gt = gru_group_tiles(ntiles, resident);
+    const int gt = o.group > 0 ? o.group : gru_group_tiles(ntiles, resident);
     const int ngroups = count_groups(ts, hb.B, gt);
     GruQLayout lay = gruq_layout(ws, D, hb, ntiles, ngroups);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);

@@ -75,6 +75,15 @@ void prof_collect();
 // Tile table: tile_start[b] = number of tiles of sequences < b, for tiles of L steps.
 std::vector<int32_t> tile_starts(const HostBatch& hb, int L);
 
+// argument validation of the entry points (api.hip)
+pn_opts resolve_opts(const pn_opts* o);
+pn_status check_cell(const pn_cell_desc* cell);
+pn_status check_batch(const pn_batch* batch, HostBatch& hb);
+pn_status check_opts(const pn_opts& o);
+// workspace of pn_autotune (autotune.hip)
+pn_status autotune_workspace(int op, const pn_cell_desc& c, const pn_batch& b,
+                             const HostBatch& hb, const pn_opts& o, size_t* bytes);
+
 // State shared by every iterative solver (lives in the workspace).
 struct IterState {
     Ctrl* ctrl;

@@ -354,7 +354,7 @@ size_t tanh_dense_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o
     TanhDKernel k = tanhd_kernel(Dx, o.compose == PN_COMPOSE_BF16);
     if (!k || D != TD) return 0;
     const std::vector<int32_t> ts = tile_starts(hb, TL);
-    const int gt = tanhd_group_tiles(ts[hb.B], tanhd_resident(k));
+    const int gt = o.group > 0 ? o.group : tanhd_group_tiles(ts[hb.B], tanhd_resident(k));
     return tanhd_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt)).bytes;
 }
 
@@ -366,7 +366,7 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
     const std::vector<int32_t> ts = tile_starts(hb, TL);
     const int ntiles = ts[hb.B];
     const int resident = tanhd_resident(kern);
-    const int gt = tanhd_group_tiles(ntiles, resident);
+    const int gt = o.group > 0 ? o.group : tanhd_group_tiles(ntiles, resident);
     const int ngroups = count_groups(ts, hb.B, gt);
     TanhDLayout lay = tanhd_layout(ws, hb, ntiles, ngroups);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);

@@ -114,6 +114,40 @@ def test_bad_options_and_pointers(lib):
                             ctypes.byref(o), None, 0, None, None) == -1
 
 
+def test_group_option_and_tuner_arguments(lib):
+    """The group length option and pn_autotune's argument checks (no HIP call is made)."""
+    c, b, _ = _desc()
+    args = (ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    for g in (-1, 65):
+        o = pn.make_opts(jac="diag", group=g)
+        assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0,
+                              None, None) == -1
+    c2, b2, _ = _desc(cell="tanh", D=16, Dx=16)
+    o = pn.make_opts(jac="dense", group=2)
+    assert lib.elk_solve(ctypes.byref(c2), ctypes.byref(b2), *args, ctypes.c_double(0.1),
+                         ctypes.byref(o), None, 0, None, None) == -1
+    assert "tile" in lib.pn_last_error().decode()
+    # tuning workspace: the largest candidate's plus a copy of the iterate (deer / elk)
+    o = pn.make_opts(jac="diag")
+    st, n = _ws(lib, pn.OP_DEER | pn.OP_TUNE, c, b, o)
+    _, n1 = _ws(lib, pn.OP_DEER, c, b, o)
+    assert st == 0 and n >= n1 + b.N * c.D * 4
+    st, _ = _ws(lib, pn.OP_ADJOINT | pn.OP_TUNE, c, b, o)
+    assert st == 0
+    st, _ = _ws(lib, pn.OP_SEQ | pn.OP_TUNE, c, b, o)
+    assert st == -1
+    bufs = (ctypes.c_void_p * 7)(16, 16, 16, 16, 16, 16, 16)
+    out = pn.Tuned()
+    call = lambda op, probe=3, bb=bufs, ob=out: lib.pn_autotune(
+        op, ctypes.byref(c), ctypes.byref(b), bb, ctypes.c_double(0.0), ctypes.byref(o), probe,
+        None, 0, None, ctypes.byref(ob) if ob is not None else None)
+    assert call(pn.OP_SEQ) == -1
+    assert call(pn.OP_DEER, probe=65) == -1
+    assert call(pn.OP_DEER, ob=None) == -1
+    nulls = (ctypes.c_void_p * 7)(16, None, 16, 16, 16, 16, 16)
+    assert call(pn.OP_DEER, bb=nulls) == -1
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
     x = torch.zeros(10, 8)
