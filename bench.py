@@ -128,6 +128,12 @@ def main():
                     help="instead of the step: the mean-field RNN LLE-threshold sweep (one "
                          "JSON line per gain and length)")
     ap.add_argument("--sweep-seeds", type=int, default=3)
+    ap.add_argument("--tile", default="auto",
+                    help="'auto': the forward and adjoint tile / group lengths chosen by the "
+                         "library's autotuner before the warmup (reported, not timed); "
+                         "'default': the cost-model choice; 'L,G,GA': forward tile L and group "
+                         "G, adjoint group GA as given (e.g. to replay a tuned choice under a "
+                         "profiler without the tuning launches)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -165,10 +171,32 @@ def main():
     # kernel; launches of iterations after the last sequence stopped return at once and are
     # not counted in the per-kernel averages.
     kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol, graph_iters=GRAPH_ITERS)
+    kw_f, kw_b, tuned = dict(kw), dict(kw), None
+    if args.tile == "auto":
+        # one-time plan: the autotuner times the candidate tile / group lengths of both passes
+        # on these inputs (8 iterations each); excluded from the timed region, reported
+        torch.cuda.synchronize()
+        tt0 = time.perf_counter()
+        tf = pn.autotune("deer", x, s0, p, probe_iters=8, **kw)
+        s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
+        tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8, **kw)
+        torch.cuda.synchronize()
+        tuned = {"tune_ms": round((time.perf_counter() - tt0) * 1e3, 1),
+                 "fwd": {k: tf[k] for k in ("tile", "group", "ms_per_iter", "from_cache")},
+                 "adj": {k: tb[k] for k in ("group", "ms_per_iter", "from_cache")},
+                 "fwd_candidates": tf["candidates"], "adj_candidates": tb["candidates"]}
+        kw_f.update(tile=tf["tile"], group=tf["group"])
+        kw_b.update(group=tb["group"])
+        del s_tr
+    elif args.tile != "default":
+        L, G, GA = (int(v) for v in args.tile.split(","))
+        kw_f.update(tile=L, group=G)
+        kw_b.update(group=GA)
+        tuned = {"given": {"fwd_tile": L, "fwd_group": G, "adj_group": GA}}
 
     def step():
-        s, finfo = pn.deer_solve(x, s0, p, **kw)
-        gp, gx, g0, binfo = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw)
+        s, finfo = pn.deer_solve(x, s0, p, **kw_f)
+        gp, gx, g0, binfo = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw_b)
         return s, gp, gx, g0, finfo, binfo
 
     for _ in range(args.warmup):
@@ -234,12 +262,11 @@ def main():
     # stopping state read every 4 iterations), outside the timed region
     ms_graph = None
     if args.graphs:
-        kw_graph = dict(kw, graph_iters=4)
         torch.cuda.synchronize()
         tg0 = time.perf_counter()
         for _ in range(args.steps):
-            pn.deer_solve(x, s0, p, **kw_graph)
-            pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw_graph)
+            pn.deer_solve(x, s0, p, **dict(kw_f, graph_iters=4))
+            pn.deer_adjoint(x, s0, p, s, 2.0 * s, **dict(kw_b, graph_iters=4))
         torch.cuda.synchronize()
         ms_graph = round((time.perf_counter() - tg0) * 1e3 / args.steps, 3)
 
@@ -261,6 +288,7 @@ def main():
         "copy_bandwidth_gbs": round(copy_gbs, 1),
         "ms_per_step_graphs": ms_graph,
         "roofline": roofline,
+        "autotune": tuned,
     }
 
     if cpu is not None:
@@ -432,12 +460,28 @@ def measure_rows(torch, pn, workloads):
     inst = workloads.make_instance(w, seed=0)
     x, s0, p = tens(inst)
     kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=1e-6)
+    # autotuned tile / group lengths of both passes (one-time plan, not timed)
+    tt0 = time.perf_counter()
+    tf = pn.autotune("deer", x, s0, p, probe_iters=6, **kw)
+    kw_f = dict(kw, tile=tf["tile"], group=tf["group"])
+    s_tr, _ = pn.deer_solve(x, s0, p, **kw_f)
+    tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=6, **kw)
+    kw_b = dict(kw, group=tb["group"])
+    torch.cuda.synchronize()
+    tune_ms = (time.perf_counter() - tt0) * 1e3
+    del s_tr
 
     def fb():
-        s, fi = pn.deer_solve(x, s0, p, **kw)
-        gp, gx, g0, bi = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw)
+        s, fi = pn.deer_solve(x, s0, p, **kw_f)
+        gp, gx, g0, bi = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw_b)
         return s, fi, bi
     ms, (s, fi, bi) = _timed(torch, fb, reps=2)
+
+    def fb_default():
+        s, fi = pn.deer_solve(x, s0, p, **kw)
+        pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw)
+        return s
+    ms_default, _ = _timed(torch, fb_default, reps=2)
 
     def seqfb():
         s = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
@@ -448,7 +492,10 @@ def measure_rows(torch, pn, workloads):
                     "sequential_ms": round(seq_ms, 3), "speedup_vs_sequential": round(seq_ms / ms, 2),
                     "iters_fwd_max": max(i["iters"] for i in fi),
                     "iters_bwd_max": max(i["iters"] for i in bi), "N": int(inst.N),
-                    "err_vs_sequential": rel(s, s_seq)}
+                    "err_vs_sequential": rel(s, s_seq),
+                    "autotuned": {"fwd_tile": tf["tile"], "fwd_group": tf["group"],
+                                  "adj_group": tb["group"], "tune_ms": round(tune_ms, 1)},
+                    "fwd_bwd_ms_cost_model_tiles": round(ms_default, 3)}
 
     done('section 6')
     # transition variants on the GRU path (benchmark shapes, forward only)
