@@ -297,7 +297,8 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
     static_assert(KT % 4 == 0, "shape");
     __shared__ __attribute__((aligned(16))) float sst[(L + 1) * SS];
     __shared__ __attribute__((aligned(16))) float xst[L * XS];
-    __shared__ float dsh[L * ED], rsh[L * ED];
+    __shared__ __attribute__((aligned(16))) float dsh[L * ED];
+    __shared__ float rsh[L * ED];
     __shared__ float Wm[EM], Ai[EM], Ci[EM], Ji[EM], At[EM], Jj[EM], Gm[EM], T1[EM], T2[EM];
     __shared__ float Pr[EM];                  // replay: filtered covariance
     __shared__ float bi[ED], ei[ED], vx[ED], vy[ED], vz[ED], mr[ED];
@@ -322,6 +323,40 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
                                      a.res64 != 0);
     };
     auto build_At = [&](int t) { elk_build_At<MF>(At, dsh, Wm, t, a.diag != 0); };
+    // lambda = 0: the step's transition A_t and the group's map stay in registers.  Lane
+    // (u, q) = (l & 15, l >> 4) holds W[u][4q .. 4q+3], the map A in the output layout of the
+    // FP32 MFMA 16x16x4 product (A[4q + i][u], i = 0..3) and b[u]; taking the K index of MFMA
+    // step kb as 4q + kb, the operands of A_t A are the lane's own A_t[u][4q + kb] and map
+    // entry kb, and A_t m needs m[4q .. 4q+3] from lanes 4q .. 4q+3.
+    const int u = l & 15, q = l >> 4;
+    __syncthreads();
+    float wr[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) wr[kb] = Wm[u * ES + 4 * q + kb];
+    auto step_row = [&](int t, float (&av)[4]) {   // A_t[u][4q + kb]
+        if (MF) {
+            const float4 dq = *(const float4*)(dsh + t * ED + 4 * q);
+            av[0] = wr[0] * dq.x;
+            av[1] = wr[1] * dq.y;
+            av[2] = wr[2] * dq.z;
+            av[3] = wr[3] * dq.w;
+        } else {
+            const float du = dsh[t * ED + u];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) av[kb] = du * wr[kb];
+        }
+        if (a.diag) {
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) av[kb] = (4 * q + kb == u) ? av[kb] : 0.f;
+        }
+    };
+    auto row_dot = [&](const float (&av)[4], float v) {     // (A_t v)[u], v[k] held by lane k
+        float p = av[0] * __shfl(v, 4 * q) + av[1] * __shfl(v, 4 * q + 1) +
+                  av[2] * __shfl(v, 4 * q + 2) + av[3] * __shfl(v, 4 * q + 3);
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        return p;
+    };
 
     for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
         const GroupInfo gr = a.groups[gi];
@@ -346,10 +381,18 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
         uint32_t rmax = 0;
         int nreset = 0;
         bool have = false;                       // the group's element holds at least one step
+        float mreg = 0.f;                        // lambda = 0: m[u]
+        floatx4 macc = {u == 4 * q ? 1.f : 0.f, u == 4 * q + 1 ? 1.f : 0.f,
+                        u == 4 * q + 2 ? 1.f : 0.f, u == 4 * q + 3 ? 1.f : 0.f};
+        float mb = 0.f;
         if (fuse) {                              // filtered state entering the group
             const float* cr = a.gcar + (size_t)gi * ECAR;
-            if (KF) fetch_mat(Pr, cr);
-            if (l < ED) mr[l] = cr[ED * ED + l];
+            if (KF) {
+                fetch_mat(Pr, cr);
+                if (l < ED) mr[l] = cr[ED * ED + l];
+            } else {
+                mreg = cr[ED * ED + u];
+            }
         }
         for (int kt = 0; kt < gr.ntl; ++kt) {
             const TileInfo ti = a.tiles[gr.tile0 + kt];
@@ -367,16 +410,23 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
                 linearise(first, len, false);
                 float hv = 0.f;
                 if (!first && l < ED) {
-                    hv = sst[l] + mr[l];               // s^(k) of the row before the chunk
+                    hv = sst[l] + (KF ? mr[l] : mreg);  // s^(k) of the row before the chunk
                     if (!(fabsf(hv) <= reset_abs)) badrow[0] = 1;
                 }
-                for (int t = 0; t < len; ++t) {
+                if (!KF) {
+                    for (int t = 0; t < len; ++t) {
+                        float av[4];
+                        step_row(t, av);
+                        mreg = row_dot(av, mreg) - rsh[t * ED + u];           // m = A m - r
+                        const float v = sst[(t + 1) * SS + u] + mreg;
+                        const bool rb = __any(!(fabsf(v) <= reset_abs));
+                        if (l < ED) sst[(t + 1) * SS + u] = rb ? 0.f : v;
+                        nreset += rb ? 1 : 0;
+                    }
+                    __syncthreads();
+                }
+                for (int t = 0; KF && t < len; ++t) {
                     build_At(t);
-                    if (!KF) {
-                        if (l < ED) vx[l] = -rsh[t * ED + l];
-                        __syncthreads();
-                        mv16(mr, At, false, mr, 1.f, vx, 1.f);                // m = A m - r
-                    } else {
                     mm16(T1, At, false, Pr, false, 1.f, nullptr, 0.f);        // A P
                     mm16(T2, T1, false, At, true, 1.f, nullptr, 1.f);         // P- = A P A^T + I
                     for (int idx = l; idx < ED * ED; idx += 64) {
@@ -398,7 +448,6 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
                     __syncthreads();
                     mv16(vy, At, false, mr, 1.f, vx, 1.f);                    // A m - r
                     mv16(mr, Gm, false, vy, 1.f, nullptr, 0.f);               // m = Gamma (.)
-                    }
                     const float v = l < ED ? sst[(t + 1) * SS + l] + mr[l] : 0.f;
                     const bool rb = __any(l < ED && !(fabsf(v) <= reset_abs));
                     if (l < ED) sst[(t + 1) * SS + l] = rb ? 0.f : v;
@@ -416,23 +465,25 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
 
             // ---- linearise at s^(k), then fold the chunk's leaves into the group's element
             rmax = max(rmax, linearise(first, len, true));
+            if (!KF) {
+                // (A, b) of the step is (A_t, -r_t); composed: A = A_t A, b = A_t b - r_t
+                for (int t = 0; t < len; ++t) {
+                    float av[4];
+                    step_row(t, av);
+                    floatx4 o = {0.f, 0.f, 0.f, 0.f};
+                    o = mfma16x4(av[0], macc[0], o);
+                    o = mfma16x4(av[1], macc[1], o);
+                    o = mfma16x4(av[2], macc[2], o);
+                    o = mfma16x4(av[3], macc[3], o);
+                    mb = row_dot(av, mb) - rsh[t * ED + u];
+                    macc = o;
+                }
+                continue;
+            }
             for (int t = 0; t < len; ++t) {
                 build_At(t);
                 if (l < ED) vx[l] = rsh[t * ED + l];
                 __syncthreads();
-                if (!KF) {
-                    // (A, b) of the step is (A_t, -r_t); composed: A = A_t A, b = A_t b - r_t
-                    if (!have) {
-                        for (int idx = l; idx < EM; idx += 64) Ai[idx] = At[idx];
-                        if (l < ED) bi[l] = -vx[l];
-                        __syncthreads();
-                        have = true;
-                    } else {
-                        mv16(bi, At, false, bi, 1.f, vx, -1.f);
-                        mm16(Ai, At, false, Ai, false, 1.f, nullptr, 0.f);
-                    }
-                    continue;
-                }
                 if (!have) {
                     // leaf (A/(1+lambda), -r/(1+lambda), I/(1+lambda), kappa A^T r, kappa A^T A);
                     // at a sequence head A = 0, which folds in the prior Delta_0 = 0
@@ -469,14 +520,18 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
         }
         // ---- the group's element
         float* ge = a.gel + (size_t)gi * EGEL;
-        store_mat(ge, Ai);
         if (KF) {
+            store_mat(ge, Ai);
             store_mat(ge + ED * ED, Ci);
             store_mat(ge + 2 * ED * ED, Ji);
-        }
-        if (l < ED) {
-            ge[3 * ED * ED + l] = bi[l];
-            if (KF) ge[3 * ED * ED + ED + l] = ei[l];
+            if (l < ED) {
+                ge[3 * ED * ED + l] = bi[l];
+                ge[3 * ED * ED + ED + l] = ei[l];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ge[(4 * q + i) * ED + u] = macc[i];
+            if (q == 0) ge[3 * ED * ED + u] = mb;
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
@@ -1514,7 +1569,7 @@ static bool elk_deer_segmented(int gmax) { return gmax >= 2 * kDSeg; }
 static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, int tile,
                            bool kf) {
     if (tile > 0) return tile / EL;
-    const double kLocalPerCarry = kf ? 36.0 : 100.0;
+    const double kLocalPerCarry = kf ? 36.0 : 27.0;
     const int resident = elk_resident(kf);
     int maxc = 0;
     for (int b = 0; b < hb.B; ++b) maxc = std::max(maxc, ts[b + 1] - ts[b]);
