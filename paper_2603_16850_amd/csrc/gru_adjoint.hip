@@ -256,6 +256,23 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     chalo = *(const float4*)(a.gcarry + (size_t)ti.hgslot * D + 4 * c4);
             }
             __syncthreads();                 // LDS of the previous tile consumed
+            // The gate planes (alpha, beta, gamma) of rows row0 + 1 .. row0 + L go straight
+            // from HBM into ps (row r - 1 for row row0 + r), one 3D-float row per instruction of
+            // 3D / 4 lanes (16 B each, lane i to byte 16 i of the row), issued before the lambda
+            // loads so that both are in flight together and no register holds them.  Rows past
+            // the sequence's last row with a successor read that row instead: their lambda row
+            // is zero, so the products formed from them vanish.
+            {
+                const int64_t last = rend - 1;
+                for (int r = w + 1; r <= L; r += C::NW) {
+                    const int64_t nr = min(row0 + r, last);
+                    if (l < 3 * D / 4)
+                        __builtin_amdgcn_global_load_lds(
+                            (const void*)(a.gates + (size_t)nr * 4 * D + 4 * l),
+                            (__attribute__((address_space(3))) void*)(ps + (r - 1) * C::PS), 16,
+                            0, 0);
+                }
+            }
 #pragma unroll
             for (int i0 = 0; i0 < NI; i0 += NB) {
                 float4 vl[NB], p0[NB], p1[NB];
@@ -290,46 +307,21 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     *(float4*)(lst + r * C::HS + 4 * c4) = w4;
                 }
             }
+            // the gate rows were issued before the lambda loads, so they have landed once those
+            // have; the explicit wait also covers them for the barrier
+            __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt(0)
             __syncthreads();
-            // reset guard, lambda^(k) of the own rows to HBM, and the VJP operand rows:
-            // ps[r-1] = (alpha, beta, gamma)_{t0+r} * lambda_{t0+r} (zero past the sequence)
+            // reset guard and lambda^(k) of the own rows to HBM
+            if (fuse) {
 #pragma unroll
-            for (int i0 = 0; i0 < NI; i0 += NB) {
-                float4 va[NB], vb[NB], vg[NB];
-#pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int idx = tid + (i0 + q) * C::NT;
-                    const int r = idx / Q;
-                    const int64_t nr = row0 + r;
-                    const bool okp = i0 + q < NI && idx < (L + 1) * Q && nr < rend && r >= 1 &&
-                                     r - 1 < len;
-                    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    const float* gp = a.gates + (size_t)nr * 4 * D + 4 * c4;
-                    va[q] = okp ? *(const float4*)(gp + 0 * D) : z4;
-                    vb[q] = okp ? *(const float4*)(gp + 1 * D) : z4;
-                    vg[q] = okp ? *(const float4*)(gp + 2 * D) : z4;
-                }
-#pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int idx = tid + (i0 + q) * C::NT;
-                    if (i0 + q >= NI || idx >= (L + 1) * Q) continue;
+                for (int i0 = 0; i0 < NI; ++i0) {
+                    const int idx = tid + i0 * C::NT;
+                    if (idx >= (L + 1) * Q) continue;
                     const int r = idx / Q;
                     float* lp = lst + r * C::HS + 4 * c4;
-                    if (fuse) {
-                        if (rowbad[r]) *(float4*)lp = make_float4(0.f, 0.f, 0.f, 0.f);
-                        if (r < len) *(float4*)(lcur + (size_t)(row0 + r) * D + 4 * c4) =
-                                         *(const float4*)lp;
-                    }
-                    if (r >= 1) {
-                        const float4 l4 = *(const float4*)lp;
-                        float* pr = ps + (r - 1) * C::PS + 4 * c4;
-                        *(float4*)(pr) = make_float4(va[q].x * l4.x, va[q].y * l4.y,
-                                                     va[q].z * l4.z, va[q].w * l4.w);   // U_z
-                        *(float4*)(pr + D) = make_float4(vb[q].x * l4.x, vb[q].y * l4.y,
-                                                         vb[q].z * l4.z, vb[q].w * l4.w);  // U_n
-                        *(float4*)(pr + 2 * D) = make_float4(vg[q].x * l4.x, vg[q].y * l4.y,
-                                                             vg[q].z * l4.z, vg[q].w * l4.w);  // U_r
-                    }
+                    if (rowbad[r]) *(float4*)lp = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (r < len) *(float4*)(lcur + (size_t)(row0 + r) * D + 4 * c4) =
+                                     *(const float4*)lp;
                 }
             }
             if (fuse && tid < 64) {
@@ -365,14 +357,18 @@ gru_adj_local_kernel(GruAdjArgs a) {
             for (int mb = 0; mb < C::MB; ++mb) {
                 if (mb + 1 < C::MB) load_block(mb + 1, zdn, gtn);
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                // VJP operand row (alpha, beta, gamma)_{t+1} * lambda_{t+1} of step t = row
+                // mb * 16 + u, formed from the gate rows in ps and the lambda row in lst
                 const float* prow = ps + (mb * 16 + u) * C::PS;
+                const float* lrow = lst + (mb * 16 + u + 1) * C::HS + 4 * g;
 #pragma unroll
                 for (int kb = 0; kb < 3 * D / 16; ++kb) {
-                    const float4 p4 = *(const float4*)(prow + 16 * kb + 4 * g);
-                    acc = mfma16x4(p4.x, bu[kb][0], acc);
-                    acc = mfma16x4(p4.y, bu[kb][1], acc);
-                    acc = mfma16x4(p4.z, bu[kb][2], acc);
-                    acc = mfma16x4(p4.w, bu[kb][3], acc);
+                    const float4 g4 = *(const float4*)(prow + 16 * kb + 4 * g);
+                    const float4 l4 = *(const float4*)(lrow + 16 * (kb % (D / 16)));
+                    acc = mfma16x4(g4.x * l4.x, bu[kb][0], acc);
+                    acc = mfma16x4(g4.y * l4.y, bu[kb][1], acc);
+                    acc = mfma16x4(g4.z * l4.z, bu[kb][2], acc);
+                    acc = mfma16x4(g4.w * l4.w, bu[kb][3], acc);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
