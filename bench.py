@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-6,
                     help="residual stopping tolerance (1e-6 keeps the error under 1e-5)")
+    ap.add_argument("--adj-tol", type=float, default=1e-5,
+                    help="stopping tolerance of the adjoint (max |rho| <= tol max(1, max |g|)); "
+                         "the workload's stated 1e-5, which keeps the gradients within 1e-5 of "
+                         "the FP64 oracle (the forward needs 1e-6 for its trajectory)")
     ap.add_argument("--seq-reps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--rows", action="store_true",
@@ -171,7 +175,8 @@ def main():
     # kernel; launches of iterations after the last sequence stopped return at once and are
     # not counted in the per-kernel averages.
     kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol, graph_iters=GRAPH_ITERS)
-    kw_f, kw_b, tuned = dict(kw), dict(kw), None
+    adj_tol = args.adj_tol
+    kw_f, kw_b, tuned = dict(kw), dict(kw, tol=adj_tol), None
     if args.tile == "auto":
         # one-time plan: the autotuner times the candidate tile / group lengths of both passes
         # on these inputs (8 iterations each); excluded from the timed region, reported
@@ -179,7 +184,8 @@ def main():
         tt0 = time.perf_counter()
         tf = pn.autotune("deer", x, s0, p, probe_iters=8, **kw)
         s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
-        tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8, **kw)
+        tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8,
+                         **dict(kw, tol=adj_tol))
         torch.cuda.synchronize()
         tuned = {"tune_ms": round((time.perf_counter() - tt0) * 1e3, 1),
                  "fwd": {k: tf[k] for k in ("tile", "group", "ms_per_iter", "from_cache")},
@@ -277,7 +283,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD, "cell": "gru", "D": D, "Dx": Dx, "B": B,
                    "T": work.T, "N": N, "method": "quasi-DEER fwd + exact quasi adjoint",
-                   "tol": args.tol, "loss": "sum_t ||s_t||^2", "graph_iters": GRAPH_ITERS},
+                   "tol": args.tol, "adj_tol": adj_tol, "loss": "sum_t ||s_t||^2",
+                   "graph_iters": GRAPH_ITERS},
         "iters_fwd": it_f, "iters_bwd": it_b,
         "kernel_ms": {k: {"total": round(v[0], 3), "launches": v[1]} for k, v in fam.items()},
         "sequential_gpu": {"value": round(seq_value, 1), "unit": "sequence-steps/s",
