@@ -14,9 +14,10 @@
 //     1. (k >= 1) apply the previous step: re-linearise at s^(k-1) and run the exact filter
 //        from the filtered state (m, P) entering the group, s^(k) = s^(k-1) + m (reset guard);
 //     2. linearise at s^(k) (FP32 MFMA GEMM for the pre-activations, residual, d_t);
-//     3. fold the steps' leaves into the group's element (one 16x16 inverse and nine 16x16
-//        products per step, products on FP32 MFMA 16x16x4, the inverse by Gauss-Jordan with
-//        partial pivoting in LDS);
+//     3. fold the steps' leaves into the group's element (per step six 16x16 products on
+//        FP32 MFMA 16x16x4 and one inverse of a symmetric positive definite matrix, by
+//        Gauss-Jordan in registers; the leaf's structure turns the element composition's
+//        general inverse into that one);
 //   carry pass, one workgroup per sequence: the filtered state entering every group, by
 //   applying the group elements in order from (m, P) = (0, 0).
 // Converged-prefix skipping (optional; convergence is causal, Prop. global_convergence): the
@@ -84,7 +85,8 @@ PN_DEV void mv16(float* y, const float* M, bool tm, const float* x, float alpha,
     __syncthreads();
 }
 
-// G = M^-1 (16x16 in LDS) by Gauss-Jordan with partial pivoting, held in registers: lane l
+// G = M^-1 (16x16 in LDS, any invertible M) by Gauss-Jordan with partial pivoting, held in
+// registers (the carry passes' (I + P J)^-1 and element compositions): lane l
 // keeps row r = l & 15 of [M | I], columns 8q .. 8q + 7 (q = l >> 4).  Rows are not swapped:
 // the pivot of column k is the unused row of largest |entry| (found by a rotate-and-max over
 // each 16-lane row of the wave; ties and the last 4 mantissa bits go to the higher row), and
@@ -131,6 +133,45 @@ PN_DEV void inv16(float* G, const float* M) {
     if (q >= 2) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) G[myk * ES + 8 * (q - 2) + j] = a[j];
+    }
+    __syncthreads();
+}
+
+// G = M^-1 for M symmetric positive definite with every eigenvalue >= 1 (I + kappa A C A^T,
+// lambda P- + I): Gauss-Jordan in the register layout of inv16 with the pivots taken in order
+// (no search: the leading pivots of such a matrix are >= 1), so row k of the inverse ends in
+// row k.
+PN_DEV void inv16_spd(float* G, const float* M) {
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    float a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int c = 8 * q + j;
+        a[j] = c < ED ? M[r * ES + c] : (c - ED == r ? 1.f : 0.f);
+    }
+#pragma unroll 2
+    for (int k = 0; k < ED; ++k) {
+        const int kq = k >> 3, kc = k & 7;
+        float ak = a[0];
+#pragma unroll
+        for (int j = 1; j < 8; ++j) ak = kc == j ? a[j] : ak;
+        const float piv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ak), 16 * kq + k));
+        const float fk = __int_as_float(
+            __builtin_amdgcn_ds_bpermute((r + 16 * kq) << 2, __float_as_int(ak)));
+        float prow[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            prow[j] = __int_as_float(
+                __builtin_amdgcn_ds_bpermute((16 * q + k) << 2, __float_as_int(a[j])));
+        const float inv = 1.f / piv;
+        const float g = -fk * inv;
+        const bool me = r == k;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = me ? a[j] * inv : fmaf(g, prow[j], a[j]);
+    }
+    if (q >= 2) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) G[r * ES + 8 * (q - 2) + j] = a[j];
     }
     __syncthreads();
 }
@@ -434,7 +475,7 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
                         Jj[r * ES + c] = lam * T2[r * ES + c] + (r == c ? 1.f : 0.f);
                     }
                     __syncthreads();
-                    inv16(Gm, Jj);                                  // Gamma
+                    inv16_spd(Gm, Jj);                              // Gamma
                     mm16(Pr, Gm, false, T2, false, 1.f, nullptr, 0.f);        // P = Gamma P-
                     for (int idx = l; idx < ED * ED; idx += 64) {              // symmetrise
                         const int r = idx / ED, c = idx % ED;
@@ -499,23 +540,31 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
                     have = true;
                     continue;
                 }
-                mm16(Jj, At, true, At, false, kap, nullptr, 0.f);     // J_j
-                mv16(vy, At, true, vx, kap, nullptr, 0.f);            // eta_j
-                mm16(T1, Ci, false, Jj, false, 1.f, nullptr, 1.f);    // I + C_i J_j
-                inv16(Gm, T1);                              // G
-                mm16(T2, At, false, Gm, false, s1, nullptr, 0.f);     // A_j G
-                // eta, J use the old A_i
-                mv16(vz, Jj, false, bi, -1.f, vy, 1.f);               // eta_j - J_j b_i
-                mv16(vz, Gm, true, vz, 1.f, nullptr, 0.f);            // G^T (.)
-                mv16(ei, Ai, true, vz, 1.f, ei, 1.f);                 // eta = A_i^T (.) + eta_i
-                mm16(T1, Jj, false, Ai, false, 1.f, nullptr, 0.f);    // J_j A_i
-                mm16(T1, Gm, true, T1, false, 1.f, nullptr, 0.f);     // G^T J_j A_i
-                mm16(Ji, Ai, true, T1, false, 1.f, Ji, 0.f);          // J = A_i^T (.) + J_i
-                mv16(vz, Ci, false, vy, 1.f, bi, 1.f);                // b_i + C_i eta_j
-                mv16(bi, T2, false, vz, 1.f, vx, -s1);                // b = A_j G (.) + b_j
-                mm16(T1, T2, false, Ci, false, 1.f, nullptr, 0.f);    // A_j G C_i
-                mm16(Ci, T1, false, At, true, s1, nullptr, s1);       // C = (.) A_j^T + C_j
-                mm16(Ai, T2, false, Ai, false, 1.f, nullptr, 0.f);    // A = A_j G A_i
+                // The leaf j = (s1 A_t, -s1 r, s1 I, kappa A_t^T r, kappa A_t^T A_t) after the
+                // element i.  With B = A_t A_i, M = A_t C_i A_t^T and H = (I + kappa M)^-1 (so
+                // that A_t (I + C_i J_j)^-1 = H A_t):
+                //   A = s1 H B,  C = s1^2 H M + s1 I,  J = kappa B^T H B + J_i,
+                //   b = s1 H (A_t b_i + kappa M r) - s1 r,  eta = kappa B^T H (r - A_t b_i) + eta_i
+                mm16(T1, At, false, Ai, false, 1.f, nullptr, 0.f);    // B = A_t A_i
+                mm16(T2, At, false, Ci, false, 1.f, nullptr, 0.f);    // A_t C_i
+                mm16(Jj, T2, false, At, true, 1.f, nullptr, 0.f);     // M = A_t C_i A_t^T
+                for (int idx = l; idx < ED * ED; idx += 64) {
+                    const int r = idx / ED, c = idx % ED;
+                    T2[r * ES + c] = kap * Jj[r * ES + c] + (r == c ? 1.f : 0.f);
+                }
+                __syncthreads();
+                inv16_spd(Gm, T2);                                     // H
+                mv16(vy, At, false, bi, 1.f, nullptr, 0.f);           // A_t b_i
+                mv16(vz, Jj, false, vx, kap, vy, 1.f);                // A_t b_i + kappa M r
+                mv16(bi, Gm, false, vz, s1, vx, -s1);                 // b
+                if (l < ED) vz[l] = vx[l] - vy[l];                    // r - A_t b_i
+                __syncthreads();
+                mv16(vz, Gm, false, vz, 1.f, nullptr, 0.f);           // H (.)
+                mv16(ei, T1, true, vz, kap, ei, 1.f);                 // eta
+                mm16(T2, Gm, false, T1, false, 1.f, nullptr, 0.f);    // H B
+                mm16(Ji, T1, true, T2, false, kap, Ji, 0.f);          // J
+                for (int idx = l; idx < EM; idx += 64) Ai[idx] = s1 * T2[idx];   // A
+                mm16(Ci, Gm, false, Jj, false, s1 * s1, nullptr, s1);  // C
             }
         }
         // ---- the group's element
@@ -562,12 +611,68 @@ PN_DEV int elk_open_start(const uint32_t* grmax, int g0, int G, float tol, int o
 // ---- quasi-ELK: the LGSSM on diag(A_t) (Ch. 4, "quasi-ELK") ----------------------------------
 // With a diagonal transition every unit is its own scalar LGSSM, so every quantity of the
 // filter -- the elements (A, b, C, eta, J), the filtered (m, P), Gamma -- is one number per unit
-// and the 16x16 products and inverses become scalar arithmetic.  Lane l works on unit l & 15
-// (the four 16-lane quarters of the wave hold the same values; the first writes them).
+// and the 16x16 products and inverses become scalar arithmetic.  Lane l works on unit l & 15 and
+// on steps 4q .. 4q+3 of a 16-step chunk (q = l >> 4, the rows the linearisation's MFMA leaves
+// in the lane): the quarters compose their steps' elements, scan them across the wave, and
+// replay their own steps from the state the earlier quarters leave.
 // Stored element: A, b, C, eta, J (16 each); filtered state: P, m.  KF = false (lambda = 0):
 // the element is (A, b) and the filter is m = a m - r (quasi-DEER).
 constexpr int EQ = 5 * ED;
 constexpr int EQC = 2 * ED;
+
+struct QElem {
+    float A, b, C, e, J;
+};
+
+template <bool KF>
+PN_DEV QElem qcompose(const QElem& i, const QElem& j) {     // i followed by j
+    if (!KF) return QElem{j.A * i.A, j.A * i.b + j.b, 0.f, 0.f, 0.f};
+    const float g = 1.f / (1.f + i.C * j.J);
+    const float ag = j.A * g;
+    QElem o;
+    o.A = ag * i.A;
+    o.b = ag * (i.b + i.C * j.e) + j.b;
+    o.C = ag * i.C * j.A + j.C;
+    o.e = i.A * g * (j.e - j.J * i.b) + i.e;
+    o.J = i.A * g * j.J * i.A + i.J;
+    return o;
+}
+
+template <bool KF>
+PN_DEV QElem qleaf(float at, float rt, float s1, float kap) {   // step with a = at, r = rt
+    if (!KF) return QElem{at, -rt, 0.f, 0.f, 0.f};
+    return QElem{s1 * at, -s1 * rt, s1, kap * at * rt, kap * at * at};
+}
+
+template <bool KF>
+PN_DEV void qapply(const QElem& e, float& m, float& P) {   // (m, P) <- e applied
+    if (!KF) {
+        m = e.A * m + e.b;
+        return;
+    }
+    const float g = 1.f / (1.f + P * e.J);
+    const float ag = e.A * g;
+    m = ag * (m + P * e.e) + e.b;
+    P = ag * P * e.A + e.C;
+}
+
+PN_DEV QElem qshfl(const QElem& x, int src) {
+    return QElem{__shfl(x.A, src), __shfl(x.b, src), __shfl(x.C, src), __shfl(x.e, src),
+                 __shfl(x.J, src)};
+}
+
+// Inclusive scan of the four 16-lane quarters' elements (quarter q holds steps 4q .. 4q+3 of a
+// chunk): quarter q ends with quarters 0 .. q composed in order.
+template <bool KF>
+PN_DEV QElem qscan_quarters(QElem x) {
+    const int l = threadIdx.x & 63, q = l >> 4;
+#pragma unroll
+    for (int d = 16; d <= 32; d <<= 1) {
+        const QElem y = qshfl(x, (l - d) & 63);
+        if (q * 16 >= d) x = qcompose<KF>(y, x);
+    }
+    return x;
+}
 
 template <int DX, bool MF, bool KF>
 __global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
@@ -590,7 +695,7 @@ __global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
     const float kap = lam / (1.f + lam);         // kappa
     const float* __restrict__ sprev = a.sbuf[(k_it + 1) & 1];   // s^(k-1)
     float* __restrict__ scur = a.sbuf[k_it & 1];                 // s^(k)
-    const int l = threadIdx.x, u = l & 15;
+    const int l = threadIdx.x, u = l & 15, q = l >> 4;
     const float* U = a.params + ED * ED;
     float blin[KT / 4];
     float bias_u;
@@ -623,15 +728,28 @@ __global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
             }
         }
         uint32_t rmax = 0;
-        int nreset = 0;
-        float m = 0.f, P = 0.f;                 // filtered state (replay)
+        int nreset = 0;                         // rows reset (counted by the u = 0 lanes)
+        float m = 0.f, P = 0.f;                 // filtered state entering the chunk (replay)
         if (fuse) {
             const float* cr = a.gcar + (size_t)gi * EQC;
             m = cr[ED + u];
             if (KF) P = cr[u];
         }
-        // the group's element, from the identity (A, b, C, eta, J) = (1, 0, 0, 0, 0)
-        float eA = 1.f, eb = 0.f, eC = 0.f, ee = 0.f, eJ = 0.f;
+        const QElem ident{1.f, 0.f, 0.f, 0.f, 0.f};
+        QElem eg = ident;                       // the group's element so far
+        // the steps of a chunk held by this lane: t = 4 q + i, i = 0..3 (the MFMA output rows
+        // of the linearisation); the element of those steps
+        auto quarter_elem = [&](int len, float (&at)[4], float (&rt)[4]) {
+            QElem x = ident;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = 4 * q + i;
+                at[i] = dsh[t * ED + u] * wd;
+                rt[i] = rsh[t * ED + u];
+                if (t < len) x = qcompose<KF>(x, qleaf<KF>(at[i], rt[i], s1, kap));
+            }
+            return x;
+        };
         for (int kt = 0; kt < gr.ntl; ++kt) {
             const TileInfo ti = a.tiles[gr.tile0 + kt];
             const int len = ti.len;
@@ -643,28 +761,44 @@ __global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
             __syncthreads();
 
             if (fuse) {
-                // ---- the previous iteration's step: the scalar filters from the entering (m, P)
+                // ---- the previous iteration's step: each quarter of the wave runs the scalar
+                // filters over its 4 steps from the state entering them (the chunk's entering
+                // state with the earlier quarters' elements applied)
                 linearise(first, len, false);
                 float hv = 0.f;
                 if (!first && l < ED) {
                     hv = sst[u] + m;                  // s^(k) of the row before the chunk
                     if (!(fabsf(hv) <= reset_abs)) badrow = 1;
                 }
-                for (int t = 0; t < len; ++t) {
-                    const float at = dsh[t * ED + u] * wd, rt = rsh[t * ED + u];
-                    if (KF) {
-                        const float pm = at * at * P + 1.f;             // P- = a^2 P + 1
-                        const float gam = 1.f / (lam * pm + 1.f);       // Gamma
-                        P = gam * pm;
-                        m = gam * (at * m - rt);
-                    } else {
-                        m = at * m - rt;
+                float at[4], rt[4];
+                const QElem inc = qscan_quarters<KF>(quarter_elem(len, at, rt));
+                QElem ex = qshfl(inc, (l - 16) & 63);
+                if (q == 0) ex = ident;
+                float mq = m, Pq = P;
+                qapply<KF>(ex, mq, Pq);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int t = 4 * q + i;
+                    const bool valid = t < len;
+                    if (valid) {
+                        if (KF) {
+                            const float pm = at[i] * at[i] * Pq + 1.f;   // P- = a^2 P + 1
+                            const float gam = 1.f / (lam * pm + 1.f);    // Gamma
+                            Pq = gam * pm;
+                            mq = gam * (at[i] * mq - rt[i]);
+                        } else {
+                            mq = at[i] * mq - rt[i];
+                        }
                     }
-                    const float v = sst[(t + 1) * SS + u] + m;
-                    const bool rb = __any(!(fabsf(v) <= reset_abs));
-                    if (l < ED) sst[(t + 1) * SS + u] = rb ? 0.f : v;
-                    nreset += rb ? 1 : 0;
+                    const float v = sst[(t + 1) * SS + u] + mq;
+                    const uint64_t bad = __ballot(valid && !(fabsf(v) <= reset_abs));
+                    const bool rb = ((bad >> (16 * q)) & 0xFFFFull) != 0;
+                    if (valid) sst[(t + 1) * SS + u] = rb ? 0.f : v;
+                    nreset += (rb && u == 0) ? 1 : 0;
                 }
+                // the state after the chunk's last step: quarter 3's (invalid steps are skipped)
+                m = __shfl(mq, 48 + u);
+                if (KF) P = __shfl(Pq, 48 + u);
                 __syncthreads();
                 if (!first && l < ED) sst[u] = badrow ? 0.f : hv;
                 __syncthreads();
@@ -675,40 +809,25 @@ __global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
                 }
             }
 
-            // ---- linearise at s^(k), then fold the chunk's leaves into the group's element
+            // ---- linearise at s^(k), then fold the chunk's leaves into the group's element:
+            // quarter elements, their scan (quarter 3 ends with the chunk's element)
             rmax = max(rmax, linearise(first, len, true));
-            for (int t = 0; t < len; ++t) {
-                const float at = dsh[t * ED + u] * wd, rt = rsh[t * ED + u];
-                if (!KF) {                            // (A, b) <- (a A, a b - r)
-                    eA = at * eA;
-                    eb = at * eb - rt;
-                    continue;
-                }
-                // leaf j = (s1 a, -s1 r, s1, kappa a r, kappa a^2), composed after the element
-                const float ja = s1 * at, jb = -s1 * rt, je = kap * at * rt, jj = kap * at * at;
-                const float g = 1.f / (1.f + eC * jj);
-                const float ag = ja * g;
-                const float ne = eA * g * (je - jj * eb) + ee;
-                const float nj = eA * g * jj * eA + eJ;
-                const float nb = ag * (eb + eC * je) + jb;
-                const float nc = ag * eC * ja + s1;
-                eA = ag * eA;
-                eb = nb;
-                eC = nc;
-                ee = ne;
-                eJ = nj;
-            }
+            float at[4], rt[4];
+            const QElem inc = qscan_quarters<KF>(quarter_elem(len, at, rt));
+            eg = qcompose<KF>(eg, qshfl(inc, 48 + u));
         }
         float* ge = a.gel + (size_t)gi * EQ;
         if (l < ED) {
-            ge[u] = eA;
-            ge[ED + u] = eb;
+            ge[u] = eg.A;
+            ge[ED + u] = eg.b;
             if (KF) {
-                ge[2 * ED + u] = eC;
-                ge[3 * ED + u] = ee;
-                ge[4 * ED + u] = eJ;
+                ge[2 * ED + u] = eg.C;
+                ge[3 * ED + u] = eg.e;
+                ge[4 * ED + u] = eg.J;
             }
         }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) nreset += __shfl_xor(nreset, off);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) {
@@ -726,24 +845,6 @@ __global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
 // thread then walks its segment again from that state and writes the state entering each group.
 constexpr int kQSeg = 64;
 constexpr int kQBatch = 8;                        // elements fetched together
-
-struct QElem {
-    float A, b, C, e, J;
-};
-
-template <bool KF>
-PN_DEV QElem qcompose(const QElem& i, const QElem& j) {     // i followed by j
-    if (!KF) return QElem{j.A * i.A, j.A * i.b + j.b, 0.f, 0.f, 0.f};
-    const float g = 1.f / (1.f + i.C * j.J);
-    const float ag = j.A * g;
-    QElem o;
-    o.A = ag * i.A;
-    o.b = ag * (i.b + i.C * j.e) + j.b;
-    o.C = ag * i.C * j.A + j.C;
-    o.e = i.A * g * (j.e - j.J * i.b) + i.e;
-    o.J = i.A * g * j.J * i.A + i.J;
-    return o;
-}
 
 template <bool KF>
 __global__ void __launch_bounds__(1024) elk_quasi_carry_kernel(const float* __restrict__ gel,
@@ -1355,7 +1456,7 @@ __global__ void __launch_bounds__(64) elk_smooth_kernel(ElkSmArgs a) {
                 mm16(Pp, T1, false, At, true, 1.f, nullptr, 1.f);         // P- = A P A^T + I
                 mv16(mp, At, false, m, 1.f, vx, 1.f);                     // m- = A m - r
                 if (!(first && t == 0)) {
-                    inv16(Pi, Pp);
+                    inv16_spd(Pi, Pp);                                    // (P-)^-1
                     mm16(T1, P, false, At, true, 1.f, nullptr, 0.f);      // P A^T
                     mm16(E, T1, false, Pi, false, 1.f, nullptr, 0.f);     // E_{t-1}
                     mv16(gv, E, false, mp, -1.f, m, 1.f);                 // g = m - E m-
@@ -1377,7 +1478,7 @@ __global__ void __launch_bounds__(64) elk_smooth_kernel(ElkSmArgs a) {
                     T1[r * ES + c] = lam * Pp[r * ES + c] + (r == c ? 1.f : 0.f);
                 }
                 __syncthreads();
-                inv16(Gm, T1);                                            // Gamma
+                inv16_spd(Gm, T1);                                        // Gamma
                 mm16(P, Gm, false, Pp, false, 1.f, nullptr, 0.f);         // P = Gamma P-
                 for (int idx = l; idx < ED * ED; idx += 64) {
                     const int r = idx / ED, c = idx % ED;
