@@ -138,40 +138,30 @@ PN_DEV void inv16(float* G, const float* M) {
 }
 
 // G = M^-1 for M symmetric positive definite with every eigenvalue >= 1 (I + kappa A C A^T,
-// lambda P- + I): Gauss-Jordan in the register layout of inv16 with the pivots taken in order
-// (no search: the leading pivots of such a matrix are >= 1), so row k of the inverse ends in
-// row k.
+// lambda P- + I, P-): Gauss-Jordan with the pivots taken in order (no search: the leading
+// pivots of such a matrix are >= 1).  Lane c (of each half wave) holds column c of [M | I] in
+// 16 registers, so pivot step k reads column k from lane k into scalar registers (readlane)
+// and every lane updates its column with them: no LDS round trip on the dependent chain.
+// Lanes 16 .. 31 end holding the columns of the inverse.
 PN_DEV void inv16_spd(float* G, const float* M) {
-    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
-    float a[8];
+    const int l = threadIdx.x & 63, c = l & 31;
+    float a[ED];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int c = 8 * q + j;
-        a[j] = c < ED ? M[r * ES + c] : (c - ED == r ? 1.f : 0.f);
-    }
-#pragma unroll 2
+    for (int r = 0; r < ED; ++r) a[r] = c < ED ? M[r * ES + c] : (c - ED == r ? 1.f : 0.f);
+#pragma unroll
     for (int k = 0; k < ED; ++k) {
-        const int kq = k >> 3, kc = k & 7;
-        float ak = a[0];
+        float f[ED];
 #pragma unroll
-        for (int j = 1; j < 8; ++j) ak = kc == j ? a[j] : ak;
-        const float piv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ak), 16 * kq + k));
-        const float fk = __int_as_float(
-            __builtin_amdgcn_ds_bpermute((r + 16 * kq) << 2, __float_as_int(ak)));
-        float prow[8];
+        for (int r = 0; r < ED; ++r)
+            f[r] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[r]), k));
+        const float inv = 1.f / f[k];
+        const float pk = a[k] * inv;
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            prow[j] = __int_as_float(
-                __builtin_amdgcn_ds_bpermute((16 * q + k) << 2, __float_as_int(a[j])));
-        const float inv = 1.f / piv;
-        const float g = -fk * inv;
-        const bool me = r == k;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = me ? a[j] * inv : fmaf(g, prow[j], a[j]);
+        for (int r = 0; r < ED; ++r) a[r] = r == k ? pk : fmaf(-f[r], pk, a[r]);
     }
-    if (q >= 2) {
+    if (l >= ED && l < 2 * ED) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) G[r * ES + 8 * (q - 2) + j] = a[j];
+        for (int r = 0; r < ED; ++r) G[r * ES + (c - ED)] = a[r];
     }
     __syncthreads();
 }
