@@ -90,6 +90,10 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
     // A operand of the compose: W with its K order permuted to the accumulator row order
     bf16x8 wa_bf[2];
     float wa_f[16];
+    // W[n][16 g .. 16 g + 15]: the lane's share of the mat-vecs of the replay and the q chain
+    float wrow[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) wrow[i] = Wm[n * TD + 16 * g + i];
     if (BF16) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -168,25 +172,26 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
                     hv = sst[n] + dvec[0][n];
                     if (!(fabsf(hv) <= reset_abs)) badrow[0] = 1;
                 }
+                // one wave: the LDS exchange of Delta between lanes needs no barrier (the wave's
+                // LDS operations complete in order); the wave barrier keeps the compiler from
+                // moving them across steps
                 for (int t = 0; t < len; ++t) {
                     const float* prev = dvec[t & 1];
-                    const float* wr = wl + n * WS + 16 * g;
                     float part = 0.f;
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) part += wr[i] * prev[16 * g + i];
+                    for (int i = 0; i < 16; ++i) part += wrow[i] * prev[16 * g + i];
                     part += __shfl_xor(part, 32);
                     const float dl = dsh[t * TD + n] * part + csh[t * TD + n];
                     const float v = sst[(t + 1) * SS + n] + dl;
-                    if (!(fabsf(v) <= reset_abs)) badrow[t + 1] = 1;
-                    __syncthreads();
-                    const bool rb = badrow[t + 1] != 0;
+                    const bool rb = __any(!(fabsf(v) <= reset_abs));
                     if (g == 0) {
                         dvec[(t + 1) & 1][n] = dl;
                         sst[(t + 1) * SS + n] = rb ? 0.f : v;
                     }
                     nreset += rb ? 1 : 0;
-                    __syncthreads();
+                    __builtin_amdgcn_wave_barrier();
                 }
+                __syncthreads();
                 if (g == 0) {
                     if (!first) sst[n] = badrow[0] ? 0.f : hv;
                     dvec[0][n] = dvec[len & 1][n];      // Delta at the chunk's last step
@@ -228,18 +233,17 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
                     for (int p = 0; p < 16; ++p)
                         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa_f[p], pacc[p], acc, 0, 0, 0);
                 }
-                // q chain
-                const float* wr = wl + n * WS + 16 * g;
+                // q chain (LDS exchange within the wave, as in the replay)
                 float part = 0.f;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) part += wr[i] * vec[16 * g + i];
+                for (int i = 0; i < 16; ++i) part += wrow[i] * vec[16 * g + i];
                 part += __shfl_xor(part, 32);
                 const float qn = dt[n] * part + csh[t * TD + n];
 #pragma unroll
                 for (int e = 0; e < 16; ++e) pacc[e] = dt[acc_row(g, e)] * acc[e];
-                __syncthreads();
+                __builtin_amdgcn_wave_barrier();
                 if (g == 0) vec[n] = qn;
-                __syncthreads();
+                __builtin_amdgcn_wave_barrier();
             }
         }
         // ---- the group's map: P row-major (P[r][c] at r * 32 + c), then q
