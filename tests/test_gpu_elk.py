@@ -96,11 +96,12 @@ def test_multichunk_converges_to_rollout(lib):
         assert _rel(s, ref) < 1e-5
 
 
-@pytest.mark.parametrize("lam", [1e-2, 1e-1, 1.0])
+@pytest.mark.parametrize("lam", [0.0, 1e-2, 1e-1, 1.0])
 def test_full_size(lib, lam):
     """Stated criterion: FP64 residual below tol = 1e-6.  The trajectory error is bounded by
     ||J^-1|| times the residual; on this weakly stable instance (g = 1.5) that factor is ~15,
-    so the trajectory is checked to 5e-5."""
+    so the trajectory is checked to 5e-5.  lambda = 0 is DEER with resets (the segmented
+    carry at this length)."""
     w = workloads.TANH16_ELK
     inst = workloads.make_instance(w, seed=0)
     cell = cells.TanhRNN(inst.params, w.D, w.Dx)
@@ -156,10 +157,10 @@ def test_quasi_elk_iterates_match_sequential_filter(lib, lam):
                 assert np.abs(s[a:e] - qd["s"]).max() < 2e-5
 
 
-@pytest.mark.parametrize("lam", [1e-2, 1.0])
+@pytest.mark.parametrize("lam", [0.0, 1e-2, 1.0])
 def test_quasi_elk_full_size(lib, lam):
     """quasi-ELK at full size: converges with an FP64 residual below 1e-6 (bar as
-    test_full_size)."""
+    test_full_size); lambda = 0 is quasi-DEER (several thousand iterations here)."""
     w = workloads.TANH16_ELK
     inst = workloads.make_instance(w, seed=0)
     cell = cells.TanhRNN(inst.params, w.D, w.Dx)
