@@ -1103,6 +1103,8 @@ struct ElkRunArgs {
     float* gcar;             // [ngroups][ECAR]
     float* rel;              // [B * nrun][EGEL] run elements
     float* rcar;             // [B * nrun][ECAR] state entering every run
+    float* rel2;             // [B * nrun2][EGEL] elements of the runs of runs (two levels)
+    float* rcar2;            // [B * nrun2][ECAR] state entering every run of runs
     const Ctrl* ctrl;
     SeqState* seq;
     const int32_t* group_start;
@@ -1111,33 +1113,55 @@ struct ElkRunArgs {
     int B;
     int nrun;                // runs per sequence slot (longest sequence)
     int rq;                  // groups per run
+    int nrun2;               // runs of runs per sequence slot (0: one level)
+    int rq2;                 // runs per run of runs
 };
 
+// The open groups of sequence b (from its first open group on) and their runs: first open
+// group gs, open count, runs.
+PN_DEV int elk_open_groups(const ElkRunArgs& a, int b, int* gs_out) {
+    const int g0 = a.group_start[b], G = a.group_start[b + 1] - g0;
+    const int gs = a.freeze ? elk_open_start(a.grmax, g0, G, a.ctrl->tol, a.seq[b].frozen) : 0;
+    *gs_out = gs;
+    return G - gs;
+}
+
+// Level 1 composes the group elements of a run, level 2 the run elements of a run of runs.
+template <int LEVEL>
 __global__ void __launch_bounds__(64) elk_run_fold_kernel(ElkRunArgs a) {
     __shared__ float A0[EM], C0[EM], J0[EM], A1[EM], C1[EM], J1[EM], T1[EM], T2[EM], Gm[EM];
     __shared__ float b0[ED], e0[ED], b1[ED], e1[ED], vz[ED];
     if (ld_i32(&a.ctrl->all_done)) return;
-    const int b = blockIdx.x / a.nrun, ri = blockIdx.x % a.nrun;
+    const int per = LEVEL == 1 ? a.nrun : a.nrun2;
+    const int b = blockIdx.x / per, ri = blockIdx.x % per;
     if (b >= a.B || a.seq[b].status != kActive) return;
-    const int g0 = a.group_start[b], G = a.group_start[b + 1] - g0;
-    const int gs = a.freeze ? elk_open_start(a.grmax, g0, G, a.ctrl->tol, a.seq[b].frozen) : 0;
-    const int lo = gs + ri * a.rq, hi = min(G, lo + a.rq);
+    int gs;
+    const int open = elk_open_groups(a, b, &gs);
+    const int n = LEVEL == 1 ? open : (open + a.rq - 1) / a.rq;   // elements of this level
+    const int rl = LEVEL == 1 ? a.rq : a.rq2;
+    const int lo = ri * rl, hi = min(n, lo + rl);
     if (lo >= hi) return;
+    const float* src = LEVEL == 1 ? a.gel + (size_t)(a.group_start[b] + gs) * EGEL
+                                  : a.rel + (size_t)b * a.nrun * EGEL;
+    float* dst = LEVEL == 1 ? a.rel + (size_t)blockIdx.x * EGEL : a.rel2 + (size_t)blockIdx.x * EGEL;
     const ElkElem acc{A0, C0, J0, b0, e0}, nx{A1, C1, J1, b1, e1};
     float r[kElemPer];
-    elem_fetch(r, a.gel + (size_t)(g0 + lo) * EGEL);
+    elem_fetch(r, src + (size_t)lo * EGEL);
     elem_to_lds(acc, r);
-    if (lo + 1 < hi) elem_fetch(r, a.gel + (size_t)(g0 + lo + 1) * EGEL);
+    if (lo + 1 < hi) elem_fetch(r, src + (size_t)(lo + 1) * EGEL);
     __syncthreads();
-    for (int gg = lo + 1; gg < hi; ++gg) {
+    for (int k = lo + 1; k < hi; ++k) {
         elem_to_lds(nx, r);
-        if (gg + 1 < hi) elem_fetch(r, a.gel + (size_t)(g0 + gg + 1) * EGEL);
+        if (k + 1 < hi) elem_fetch(r, src + (size_t)(k + 1) * EGEL);
         __syncthreads();
         elem_compose(acc, nx, T1, T2, Gm, vz);
     }
-    elem_store(a.rel + (size_t)blockIdx.x * EGEL, acc);
+    elem_store(dst, acc);
 }
 
+// One wave per sequence applies the top-level elements in order from (m, P) = (0, 0) and
+// writes the state entering each of them (LEVELS = 1: the runs; 2: the runs of runs).
+template <int LEVELS>
 __global__ void __launch_bounds__(64) elk_run_walk_kernel(ElkRunArgs a) {
     __shared__ float Ae[EM], Ce[EM], Je[EM], P[EM], T1[EM], Gm[EM];
     __shared__ float be[ED], ee[ED], m[ED], vz[ED];
@@ -1156,49 +1180,64 @@ __global__ void __launch_bounds__(64) elk_run_walk_kernel(ElkRunArgs a) {
             a.seq[b].frozen = gs;
         }
     }
-    const int nr = (G - gs + a.rq - 1) / a.rq;
+    const int nr1 = (G - gs + a.rq - 1) / a.rq;
+    const int nr = LEVELS == 1 ? nr1 : (nr1 + a.rq2 - 1) / a.rq2;
     const ElkElem e{Ae, Ce, Je, be, ee};
     for (int idx = l; idx < EM; idx += 64) P[idx] = 0.f;
     if (l < ED) m[l] = 0.f;
     float r[kElemPer];
-    const size_t base = (size_t)b * a.nrun;
-    if (nr > 0) elem_fetch(r, a.rel + base * EGEL);
+    const size_t base = (size_t)b * (LEVELS == 1 ? a.nrun : a.nrun2);
+    const float* el = LEVELS == 1 ? a.rel : a.rel2;
+    float* car = LEVELS == 1 ? a.rcar : a.rcar2;
+    if (nr > 0) elem_fetch(r, el + base * EGEL);
     __syncthreads();
     for (int ri = 0; ri < nr; ++ri) {
-        float* cr = a.rcar + (base + ri) * ECAR;
+        float* cr = car + (base + ri) * ECAR;
         store_mat(cr, P);
         if (l < ED) cr[ED * ED + l] = m[l];
         elem_to_lds(e, r);
-        if (ri + 1 < nr) elem_fetch(r, a.rel + (base + ri + 1) * EGEL);
+        if (ri + 1 < nr) elem_fetch(r, el + (base + ri + 1) * EGEL);
         __syncthreads();
         elem_apply(e, m, P, T1, Gm, vz);
     }
 }
 
+// Level 2 writes the state entering every run of a run of runs, level 1 the state entering
+// every group of a run, from the state entering the run (of runs).
+template <int LEVEL>
 __global__ void __launch_bounds__(64) elk_run_expand_kernel(ElkRunArgs a) {
     __shared__ float Ae[EM], Ce[EM], Je[EM], P[EM], T1[EM], Gm[EM];
     __shared__ float be[ED], ee[ED], m[ED], vz[ED];
     if (ld_i32(&a.ctrl->all_done)) return;
-    const int b = blockIdx.x / a.nrun, ri = blockIdx.x % a.nrun;
+    const int per = LEVEL == 1 ? a.nrun : a.nrun2;
+    const int b = blockIdx.x / per, ri = blockIdx.x % per;
     if (b >= a.B || a.seq[b].status != kActive) return;
     const int l = threadIdx.x;
     const int g0 = a.group_start[b], G = a.group_start[b + 1] - g0;
     const int gs = a.freeze ? a.seq[b].frozen : 0;      // written by the walk
-    const int lo = gs + ri * a.rq, hi = min(G, lo + a.rq);
+    const int open = G - gs;
+    const int n = LEVEL == 1 ? open : (open + a.rq - 1) / a.rq;
+    const int rl = LEVEL == 1 ? a.rq : a.rq2;
+    const int lo = ri * rl, hi = min(n, lo + rl);
     if (lo >= hi) return;
+    const float* src = LEVEL == 1 ? a.gel + (size_t)(g0 + gs) * EGEL
+                                  : a.rel + (size_t)b * a.nrun * EGEL;
+    float* out = LEVEL == 1 ? a.gcar + (size_t)(g0 + gs) * ECAR
+                            : a.rcar + (size_t)b * a.nrun * ECAR;
+    const float* cin = (LEVEL == 1 ? a.rcar : a.rcar2) + (size_t)blockIdx.x * ECAR;
     const ElkElem e{Ae, Ce, Je, be, ee};
-    fetch_mat(P, a.rcar + (size_t)blockIdx.x * ECAR);
-    if (l < ED) m[l] = a.rcar[(size_t)blockIdx.x * ECAR + ED * ED + l];
+    fetch_mat(P, cin);
+    if (l < ED) m[l] = cin[ED * ED + l];
     float r[kElemPer];
-    elem_fetch(r, a.gel + (size_t)(g0 + lo) * EGEL);
+    elem_fetch(r, src + (size_t)lo * EGEL);
     __syncthreads();
-    for (int gg = lo; gg < hi; ++gg) {
-        float* cr = a.gcar + (size_t)(g0 + gg) * ECAR;
+    for (int k = lo; k < hi; ++k) {
+        float* cr = out + (size_t)k * ECAR;
         store_mat(cr, P);
         if (l < ED) cr[ED * ED + l] = m[l];
-        if (gg + 1 == hi) break;                 // the run's last state is not needed
+        if (k + 1 == hi) break;                  // the last state is not needed
         elem_to_lds(e, r);
-        if (gg + 1 < hi) elem_fetch(r, a.gel + (size_t)(g0 + gg + 1) * EGEL);
+        if (k + 1 < hi) elem_fetch(r, src + (size_t)(k + 1) * EGEL);
         __syncthreads();
         elem_apply(e, m, P, T1, Gm, vz);
     }
@@ -1603,21 +1642,41 @@ struct ElkLayout {
     float* bcar;
     float* rel;              // three-phase carry: run elements and entering states
     float* rcar;
+    float* rel2;             // its second level (runs of runs)
+    float* rcar2;
     char* r64;
     size_t bytes;
 };
 
-// Groups per run of the three-phase carry for sequences of at most gmax groups (0: the
-// single-pass carry).  The run length balances the fold (RQ - 1 compositions, a composition
-// costing about 1.4 applications) and the expansion (RQ applications) against the walk
-// (gmax / RQ applications).
-static int elk_run_len(int gmax) {
-    if (gmax < 16) return 0;
-    return std::max(2, (int)std::lround(std::sqrt(gmax / 2.4)));
+// Runs of the carry in phases for sequences of at most gmax groups: none (gmax < 16, the
+// single-pass carry), one level of runs of rq groups, or two levels (runs of rq2 runs).  A
+// level of runs of r costs about 2.4 r element applications of dependent work (r - 1
+// compositions at about 1.4 applications each in the fold, r applications in the expansion),
+// the walk one application per top-level element, a second level two more launches (about
+// two applications).  cost: the plan's dependent work in applications.
+struct ElkRunPlan {
+    int rq = 0, nrun = 0, rq2 = 0, nrun2 = 0;
+    double cost = 0.0;
+};
+static ElkRunPlan elk_run_plan(int gmax) {
+    ElkRunPlan p;
+    p.cost = gmax;
+    if (gmax < 16) return p;
+    for (int r1 = 2; r1 <= 64; ++r1) {
+        const int n1 = (gmax + r1 - 1) / r1;
+        const double c1 = 2.4 * r1 + n1;
+        if (c1 < p.cost) p = ElkRunPlan{r1, n1, 0, 0, c1};
+        for (int r2 = 2; r2 <= 64 && r2 < n1; ++r2) {
+            const int n2 = (n1 + r2 - 1) / r2;
+            const double c2 = 2.4 * (r1 + r2) + n2 + 2.0;
+            if (c2 < p.cost) p = ElkRunPlan{r1, n1, r2, n2, c2};
+        }
+    }
+    return p;
 }
 
 static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngroups,
-                            bool smooth, int nrun_total) {
+                            bool smooth, int nrun_total, int nrun2_total = 0) {
     Carver c(ws);
     ElkLayout lay;
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
@@ -1630,6 +1689,8 @@ static ElkLayout elk_layout(void* ws, const HostBatch& hb, int ntiles, int ngrou
     lay.bcar = smooth ? c.take<float>((size_t)std::max(ngroups, 1) * ED) : nullptr;
     lay.rel = nrun_total ? c.take<float>((size_t)nrun_total * EGEL) : nullptr;
     lay.rcar = nrun_total ? c.take<float>((size_t)nrun_total * ECAR) : nullptr;
+    lay.rel2 = nrun2_total ? c.take<float>((size_t)nrun2_total * EGEL) : nullptr;
+    lay.rcar2 = nrun2_total ? c.take<float>((size_t)nrun2_total * ECAR) : nullptr;
     lay.r64 = c.take<char>(residual64_workspace(PN_CELL_TANH, ED, 16, hb));   // FP64 residual
     lay.bytes = c.bytes();
     return lay;
@@ -1670,11 +1731,9 @@ static int elk_group_tiles(const HostBatch& hb, const std::vector<int32_t>& ts, 
         const int ng = count_groups(ts, hb.B, gt);
         const double rounds = std::ceil((double)ng / resident);
         const int gmax = (maxc + gt - 1) / gt;
-        const int rq = kf ? elk_run_len(gmax) : 0;
         const double seg = std::ceil((double)gmax / kDSeg);      // segmented DEER carry
-        const double carry = rq                           ? 2.4 * rq + std::ceil((double)gmax / rq)
-                             : (!kf && elk_deer_segmented(gmax)) ? 4.0 * seg + kDSeg
-                                                              : gmax;
+        const double carry = kf ? elk_run_plan(gmax).cost
+                             : elk_deer_segmented(gmax) ? 4.0 * seg + kDSeg : gmax;
         const double cost = rounds * gt * kLocalPerCarry + carry;
         if (cost < best_cost) { best_cost = cost; best = gt; }
     }
@@ -1715,10 +1774,9 @@ size_t elk_workspace(int, int, const HostBatch& hb, const pn_opts& o) {
     for (int kf = 0; kf < 2; ++kf) {
         const int gt = elk_group_tiles(hb, ts, o.tile, kf != 0);
         const int gmax = elk_max_groups(hb, ts, gt);
-        const int rq = kf ? elk_run_len(gmax) : 0;
-        const int nrun = rq ? (gmax + rq - 1) / rq : 0;
+        const ElkRunPlan rp = kf ? elk_run_plan(gmax) : ElkRunPlan{};
         n = std::max(n, elk_layout(nullptr, hb, ts[hb.B], count_groups(ts, hb.B, gt),
-                                   o.smooth != 0, nrun * hb.B).bytes);
+                                   o.smooth != 0, rp.nrun * hb.B, rp.nrun2 * hb.B).bytes);
     }
     return n;
 }
@@ -1750,9 +1808,10 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const int gt = quasi ? elk_quasi_group_tiles(hb, ts, o.tile) : elk_group_tiles(hb, ts, o.tile, kf);
     const int ngroups = count_groups(ts, hb.B, gt);
     const int gmax = elk_max_groups(hb, ts, gt);
-    const int rq = kf && !quasi ? elk_run_len(gmax) : 0;    // three-phase carry, long sequences
-    const int nrun = rq ? (gmax + rq - 1) / rq : 0;
-    ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups, smooth, nrun * hb.B);
+    // carry in phases for long sequences (one or two levels of runs)
+    const ElkRunPlan rp = kf && !quasi ? elk_run_plan(gmax) : ElkRunPlan{};
+    const int rq = rp.rq, nrun = rp.nrun;
+    ElkLayout lay = elk_layout(ws, hb, ntiles, ngroups, smooth, nrun * hb.B, rp.nrun2 * hb.B);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, EL, false, max_iters, (float)o.tol,
                            (float)o.reset_abs, stream, gt));
@@ -1818,6 +1877,10 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     ra.B = hb.B;
     ra.nrun = nrun;
     ra.rq = rq;
+    ra.rel2 = lay.rel2;
+    ra.rcar2 = lay.rcar2;
+    ra.nrun2 = rp.nrun2;
+    ra.rq2 = rp.rq2;
     auto one_iter = [&](hipStream_t st) {
         prof_launch("elk_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s2, args);
@@ -1832,9 +1895,17 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
             });
         } else if (rq) {
             prof_launch("elk_carry", st, [&](hipStream_t s2) {
-                hipLaunchKernelGGL(elk_run_fold_kernel, dim3(hb.B * nrun), dim3(64), 0, s2, ra);
-                hipLaunchKernelGGL(elk_run_walk_kernel, dim3(hb.B), dim3(64), 0, s2, ra);
-                hipLaunchKernelGGL(elk_run_expand_kernel, dim3(hb.B * nrun), dim3(64), 0, s2, ra);
+                hipLaunchKernelGGL(elk_run_fold_kernel<1>, dim3(hb.B * nrun), dim3(64), 0, s2, ra);
+                if (rp.nrun2) {
+                    hipLaunchKernelGGL(elk_run_fold_kernel<2>, dim3(hb.B * rp.nrun2), dim3(64), 0,
+                                       s2, ra);
+                    hipLaunchKernelGGL(elk_run_walk_kernel<2>, dim3(hb.B), dim3(64), 0, s2, ra);
+                    hipLaunchKernelGGL(elk_run_expand_kernel<2>, dim3(hb.B * rp.nrun2), dim3(64),
+                                       0, s2, ra);
+                } else {
+                    hipLaunchKernelGGL(elk_run_walk_kernel<1>, dim3(hb.B), dim3(64), 0, s2, ra);
+                }
+                hipLaunchKernelGGL(elk_run_expand_kernel<1>, dim3(hb.B * nrun), dim3(64), 0, s2, ra);
             });
         } else
         prof_launch("elk_carry", st, [&](hipStream_t s2) {
