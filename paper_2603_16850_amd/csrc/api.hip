@@ -157,6 +157,18 @@ Route route_deer(const pn_cell_desc& c, const pn_opts& o) {
     return Route::None;
 }
 
+// GRU: iterated reverse diagonal scans with an exact VJP residual (damping as the forward);
+// tanh D = 32: reverse dense scans (FP32 or BF16 maps), undamped.
+Route route_adjoint(const pn_cell_desc& c, const pn_opts& o) {
+    if (c.dtype != PN_F32) return Route::None;
+    if (c.cell == PN_CELL_GRU && o.jac == PN_JAC_DIAG && gru_quasi_supported(c.D, c.Dx))
+        return Route::GruQuasi;
+    if (c.cell == PN_CELL_TANH && o.jac == PN_JAC_DENSE && o.damping == PN_DAMP_NONE &&
+        tanh_dense_supported(c.D, c.Dx))
+        return Route::TanhDense;
+    return Route::None;
+}
+
 }  // namespace
 
 extern "C" {
@@ -231,10 +243,10 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
             }
             break;
         case PN_OP_ADJOINT:
-            if (cell->cell == PN_CELL_GRU && cell->dtype == PN_F32 && o.jac == PN_JAC_DIAG &&
-                gru_quasi_supported(cell->D, cell->Dx)) {
-                *bytes = gru_adjoint_workspace(cell->D, cell->Dx, hb, o);
-                return PN_OK;
+            switch (route_adjoint(*cell, o)) {
+                case Route::GruQuasi: *bytes = gru_adjoint_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
+                case Route::TanhDense: *bytes = tanh_adjoint_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
+                default: break;
             }
             break;
         case PN_OP_SEQ:
@@ -372,19 +384,24 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
         set_error("converged-prefix skipping and the smoother are built for elk_solve only");
         return PN_ERR_UNSUPPORTED;
     }
-    if (!(cell->cell == PN_CELL_GRU && cell->dtype == PN_F32 && o.jac == PN_JAC_DIAG &&
-          gru_quasi_supported(cell->D, cell->Dx))) {
-        set_error("deer_adjoint not built for cell=%d D=%d Dx=%d dtype=%d jac=%d", cell->cell,
-                  cell->D, cell->Dx, cell->dtype, o.jac);
+    const Route r = route_adjoint(*cell, o);
+    if (r == Route::None) {
+        set_error("deer_adjoint not built for cell=%d D=%d Dx=%d dtype=%d jac=%d damping=%d",
+                  cell->cell, cell->D, cell->Dx, cell->dtype, o.jac, o.damping);
         return PN_ERR_UNSUPPORTED;
     }
     size_t need = 0;
     PN_TRY(pn_workspace_bytes(PN_OP_ADJOINT, cell, batch, &o, &need));
     PN_TRY(check_ws(workspace, workspace_bytes, need));
     bool conv = true;
-    PN_TRY(gru_adjoint(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
-                       (const float*)gs, (float*)gx, (float*)gs0, (float*)gparams, o, workspace,
-                       (hipStream_t)stream, info, &conv));
+    if (r == Route::GruQuasi)
+        PN_TRY(gru_adjoint(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
+                           (const float*)gs, (float*)gx, (float*)gs0, (float*)gparams, o,
+                           workspace, (hipStream_t)stream, info, &conv));
+    else
+        PN_TRY(tanh_adjoint(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
+                            (const float*)gs, (float*)gx, (float*)gs0, (float*)gparams, o,
+                            workspace, (hipStream_t)stream, info, &conv));
     return conv ? PN_OK : PN_NOT_CONVERGED;
 }
 

@@ -42,6 +42,14 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
                              const float* s0, float* s, const pn_opts& o, void* ws,
                              hipStream_t stream, pn_seq_info* info, bool* all_conv);
 
+// exact adjoint of the dense tanh-RNN: reverse dense scans (FP32 or BF16 maps, exact FP32
+// residual) + parameter gradients
+size_t tanh_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                       const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                       float* gparams, const pn_opts& o, void* ws, hipStream_t stream,
+                       pn_seq_info* info, bool* all_conv);
+
 // ELK, tanh-RNN, FP32
 bool elk_supported(int D, int Dx);
 size_t elk_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);

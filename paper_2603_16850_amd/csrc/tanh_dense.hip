@@ -419,4 +419,531 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
     return PN_OK;
 }
 
+// ==== adjoint ===================================================================================
+// Ch. 3, "Training and the backwards pass": lambda_t = g_t + A_{t+1}^T lambda_{t+1}, lambda_T = g_T,
+// where A_{t+1}^T = W^T diag(d_{t+1}) and d_t = 1 - f(s_{t-1}, x_t)^2 at the solution (eq. lil_j).
+// The reverse recurrence is solved by the forward Newton step run backwards in time, on the
+// same chunks, groups and dense carry:
+//   rho_t   = lambda_t - g_t - W^T (e_t * lambda_{t+1})    (exact FP32 residual, on MFMA)
+//   Delta_t = W^T (e_t * Delta_{t+1}) - rho_t,  lambda <- lambda + Delta,
+// with e_t = d_{t+1} (0 at the sequence end, where Delta_{T+1} = 0).  The recurrence is linear,
+// so with FP32 group maps one update lands on the adjoint up to rounding and the next iteration
+// only confirms the stopping test; with BF16 maps the update is approximate and the exact FP32
+// residual drives further updates to the same fixed point.  Stopping rule: max |rho| <=
+// tol * max(1, max |g|) over the sequence.  Then (eq. unrolled_bwds), with delta_t = d_t * lambda_t:
+//   dW = sum_t delta_t s_{t-1}^T,  dU = sum_t delta_t x_t^T,  db = sum_t delta_t,
+//   dx_t = U^T delta_t,  ds_0 = W^T delta_1.
+// Kernels: prep (d_t at the solution and max |g|, once), local (one per iteration, per group,
+// chunks taken from the sequence end), dense_carry over the reverse-ordered groups, grad
+// (per-workgroup partials of dW, dU, db on MFMA, dx, ds_0), reduce (FP64 sums of the partials).
+
+struct TanhAdjArgs {
+    const float* x;
+    const float* s0;
+    const float* s;
+    const float* gs;
+    const float* params;      // W (32x32) | U (32xDx) | b (32)
+    float* dd;                // [N][TD] d_t at the solution
+    float* lam[2];            // iteration k >= 1 writes lambda^(k) to lam[k & 1]; lambda^(0) = gs
+    float* gmap;              // [ngroups][GMAP] group maps of this iteration
+    const float* gcarry;      // [ngroups][TD] Delta at the step after every group (previous iteration)
+    uint32_t* gmax;           // [B] max |g| per sequence (float bits)
+    Ctrl* ctrl;
+    SeqState* seq;
+    const TileInfo* tiles;    // by slot: chunks taken from the sequence end
+    const GroupInfo* groups;
+    int ngroups;
+    int ntiles;
+    int B;
+    float* part;              // [grid][P] per-workgroup partial parameter gradients
+    float* gx;                // may be null
+    float* gs0;               // may be null
+};
+
+__global__ void tanh_adj_zero_kernel(uint32_t* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// d_t = 1 - tanh(W s_{t-1} + U x_t + b)^2 of every step (pre-activations on FP32 MFMA, one chunk
+// per pass of a single-wave workgroup) and max |g| of every sequence.
+template <int DX>
+__global__ void __launch_bounds__(64) tanh_adj_prep_kernel(TanhAdjArgs a) {
+    constexpr int SS = TD + 4, XS = DX + 4, KT = TD + DX, WS = KT + 4;
+    static_assert(KT % 2 == 0, "shape");
+    __shared__ __attribute__((aligned(16))) float hst[TL * SS];
+    __shared__ __attribute__((aligned(16))) float xst[TL * XS];
+    __shared__ __attribute__((aligned(16))) float wl[TD * WS];
+    const int l = threadIdx.x, n = l & 31, g = l >> 5;
+    const float* Wm = a.params;
+    const float* Um = Wm + TD * TD;
+    for (int idx = l; idx < TD * KT; idx += 64) {
+        const int r = idx / KT, c = idx % KT;
+        wl[r * WS + c] = c < TD ? Wm[r * TD + c] : Um[r * DX + (c - TD)];
+    }
+    const float bias_n = Um[TD * DX + n];
+    for (int slot = blockIdx.x; slot < a.ntiles; slot += gridDim.x) {
+        const TileInfo ti = a.tiles[slot];
+        const int len = ti.len, b = ti.b;
+        const int64_t row0 = ti.row0;
+        const bool first = (ti.flags & kTileTimeFirst) != 0;
+        __syncthreads();
+        for (int idx = l; idx < TL * (TD / 4); idx += 64) {
+            const int r = idx / (TD / 4), c4 = idx % (TD / 4);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < len) v = (r == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * TD + 4 * c4)
+                                               : *(const float4*)(a.s + (size_t)(row0 + r - 1) * TD + 4 * c4);
+            *(float4*)(hst + r * SS + 4 * c4) = v;
+        }
+        for (int idx = l; idx < TL * (DX / 4); idx += 64) {
+            const int r = idx / (DX / 4), c4 = idx % (DX / 4);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+            *(float4*)(xst + r * XS + 4 * c4) = v;
+        }
+        uint32_t gm = 0;
+        for (int idx = l; idx < len * TD; idx += 64) gm = max(gm, absbits(a.gs[(size_t)row0 * TD + idx]));
+        __syncthreads();
+        floatx16 acc = {};
+#pragma unroll
+        for (int p = 0; p < KT / 2; ++p) {
+            const int kk = 2 * p + g;
+            const float av = kk < TD ? hst[n * SS + kk] : xst[n * XS + (kk - TD)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, wl[n * WS + kk], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int t = acc_row(g, e);
+            const float f = tanhf_(acc[e] + bias_n);
+            if (t < len) a.dd[(size_t)(row0 + t) * TD + n] = 1.f - f * f;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) gm = max(gm, (uint32_t)__shfl_xor((int)gm, off));
+        if (l == 0) atomicMax(&a.gmax[b], gm);
+    }
+}
+
+// One adjoint iteration, one single-wave workgroup per group, the group's chunks from the
+// latest to the earliest in time:
+//   1. (k >= 1) apply the previous update: rho at lambda^(k-1) again, then the replay
+//      Delta_t = W^T (e_t * Delta_{t+1}) + c_t from the group's carry, lambda^(k) = lambda^(k-1)
+//      + Delta; write it;
+//   2. the residual at lambda^(k): c_t = -rho_t, max |rho|;
+//   3. compose the group's map Delta_first = P Delta_after + q in reverse time:
+//        P <- W^T (diag(e_t) P) on MFMA (BF16 operands with FP32 accumulation, or FP32),
+//        q <- W^T (e_t * q) + c_t in FP32.
+template <bool BF16>
+__global__ void __launch_bounds__(64) tanh_adj_local_kernel(TanhAdjArgs a) {
+    constexpr int SS = TD + 4;
+    __shared__ __attribute__((aligned(16))) float lst[(TL + 1) * SS];   // lambda rows 0 .. TL
+    __shared__ __attribute__((aligned(16))) float gst[TL * SS];
+    __shared__ __attribute__((aligned(16))) float est[TL * SS];         // e_t = d_{t+1}
+    __shared__ __attribute__((aligned(16))) float csh[TL * TD];         // c_t = -rho_t
+    __shared__ __attribute__((aligned(16))) float wl[TD * SS];          // W row-major
+    __shared__ __attribute__((aligned(16))) float vec[TD];              // q chain
+    __shared__ __attribute__((aligned(16))) float dvec[2][TD];          // Delta chain of the replay
+
+    if (ld_i32(&a.ctrl->all_done)) return;
+    const int k_it = a.ctrl->iter;
+    const bool fuse = k_it > 0;
+    const float* __restrict__ lprev = k_it <= 1 ? a.gs : a.lam[(k_it + 1) & 1];   // lambda^(k-1)
+    float* __restrict__ lcur = a.lam[k_it & 1];                                    // lambda^(k)
+    const int l = threadIdx.x;
+    const int n = l & 31, g = l >> 5;
+    const float* Wm = a.params;
+    for (int idx = l; idx < TD * TD; idx += 64) wl[(idx / TD) * SS + idx % TD] = Wm[idx];
+    // A operand of the compose: W^T with its K order permuted to the accumulator row order
+    bf16x8 wa_bf[2];
+    float wa_f[16];
+    // W[16 g .. 16 g + 15][n]: the lane's share of W^T v in the replay and the q chain
+    float wcol[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) wcol[i] = Wm[(16 * g + i) * TD + n];
+    if (BF16) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) wa_bf[h][jj] = (__bf16)Wm[acc_row(g, 8 * h + jj) * TD + n];
+    } else {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) wa_f[p] = Wm[acc_row(g, p) * TD + n];
+    }
+
+    // rho_t = lambda_t - g_t - W^T (e_t * lambda_{t+1}) of the staged chunk -> c = -rho in LDS;
+    // returns max |rho| over the valid steps
+    auto residual = [&](int len) -> uint32_t {
+        floatx16 acc = {};
+#pragma unroll
+        for (int p = 0; p < TD / 2; ++p) {
+            const int kk = 2 * p + g;
+            const float av = est[n * SS + kk] * lst[(n + 1) * SS + kk];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, wl[kk * SS + n], acc, 0, 0, 0);
+        }
+        uint32_t rm = 0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int t = acc_row(g, e);
+            const float rho = lst[t * SS + n] - gst[t * SS + n] - acc[e];
+            csh[t * TD + n] = -rho;
+            if (t < len) rm = max(rm, absbits(rho));
+        }
+        __syncthreads();
+        return rm;
+    };
+
+    for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+        const GroupInfo gr = a.groups[gi];
+        if (a.seq[gr.b].status != kActive) continue;
+        const int b = gr.b;
+        const float gscale = 1.f / fmaxf(1.f, __uint_as_float(a.gmax[b]));
+        float pacc[16];                        // P (rows acc_row(g, e) of column n)
+        float qreg = 0.f;                      // q[n] (lanes of g = 0)
+        uint32_t rmax = 0;
+        if (g == 0) dvec[0][n] = fuse ? a.gcarry[(size_t)gi * TD + n] : 0.f;
+        TileInfo tnext = a.tiles[gr.tile0];
+        for (int kt = 0; kt < gr.ntl; ++kt) {
+            const TileInfo ti = tnext;
+            if (kt + 1 < gr.ntl) tnext = a.tiles[gr.tile0 + kt + 1];   // read ahead
+            const int len = ti.len;
+            const int64_t row0 = ti.row0;
+            const bool last = (ti.flags & kTileScanFirst) != 0;        // chunk at the sequence end
+            const int nl = last ? len : len + 1;                       // lambda rows with the halo
+            const int ne = last ? len - 1 : len;                       // rows with a successor step
+            __syncthreads();
+            // ---- stage lambda^(k-1) (rows 0 .. len, row len being the first step of the next
+            // chunk in time), g and e of the chunk
+            for (int idx = l; idx < (TL + 1) * (TD / 4); idx += 64) {
+                const int r = idx / (TD / 4), c4 = idx % (TD / 4);
+                const size_t o = (size_t)(row0 + r) * TD + 4 * c4;
+                const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                *(float4*)(lst + r * SS + 4 * c4) = r < nl ? *(const float4*)(lprev + o) : z;
+                if (r < TL) {
+                    *(float4*)(gst + r * SS + 4 * c4) = r < len ? *(const float4*)(a.gs + o) : z;
+                    *(float4*)(est + r * SS + 4 * c4) = r < ne ? *(const float4*)(a.dd + o + TD) : z;
+                }
+            }
+            __syncthreads();
+
+            if (fuse) {
+                residual(len);                 // c of the previous iteration (at lambda^(k-1))
+                float hv = 0.f;                // lambda^(k) of the halo row
+                if (!last) hv = lst[len * SS + n] + dvec[0][n];
+                // one wave: the LDS exchange of Delta between lanes needs no barrier (the wave's
+                // LDS operations complete in order); the wave barrier keeps the compiler from
+                // moving them across steps
+                for (int it = 0; it < len; ++it) {
+                    const int t = len - 1 - it;
+                    const float* prev = dvec[it & 1];
+                    const float* et = est + t * SS;
+                    float part = 0.f;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) part += wcol[i] * (et[16 * g + i] * prev[16 * g + i]);
+                    part += __shfl_xor(part, 32);
+                    const float dl = part + csh[t * TD + n];
+                    if (g == 0) {
+                        dvec[(it + 1) & 1][n] = dl;
+                        lst[t * SS + n] += dl;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                __syncthreads();
+                if (g == 0) {
+                    if (!last) lst[len * SS + n] = hv;
+                    dvec[0][n] = dvec[len & 1][n];      // Delta at the chunk's first step
+                }
+                __syncthreads();
+                for (int idx = l; idx < len * (TD / 4); idx += 64) {
+                    const int r = idx / (TD / 4), c4 = idx % (TD / 4);
+                    *(float4*)(lcur + (size_t)(row0 + r) * TD + 4 * c4) =
+                        *(const float4*)(lst + r * SS + 4 * c4);
+                }
+            }
+
+            // ---- residual at lambda^(k) and the group's map, latest step first
+            rmax = max(rmax, residual(len));
+            int t0 = len - 1;
+            if (kt == 0) {
+                // P = W^T diag(e_{t0}), q = c_{t0}
+                const float en = est[t0 * SS + n];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) pacc[e] = wl[n * SS + acc_row(g, e)] * en;
+                qreg = csh[t0 * TD + n];
+                if (g == 0) vec[n] = qreg;
+                t0 -= 1;
+                __syncthreads();
+            }
+            for (int t = t0; t >= 0; --t) {
+                const float* et = est + t * SS;
+                floatx16 acc = {};
+                if (BF16) {
+                    bf16x8 b0, b1;
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) {
+                        b0[jj] = (__bf16)(et[acc_row(g, jj)] * pacc[jj]);
+                        b1[jj] = (__bf16)(et[acc_row(g, 8 + jj)] * pacc[8 + jj]);
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa_bf[0], b0, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa_bf[1], b1, acc, 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int p = 0; p < 16; ++p)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa_f[p], et[acc_row(g, p)] * pacc[p],
+                                                                   acc, 0, 0, 0);
+                }
+                float part = 0.f;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) part += wcol[i] * (et[16 * g + i] * vec[16 * g + i]);
+                part += __shfl_xor(part, 32);
+                qreg = part + csh[t * TD + n];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) pacc[e] = acc[e];
+                __builtin_amdgcn_wave_barrier();
+                if (g == 0) vec[n] = qreg;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        float* gm = a.gmap + (size_t)gi * GMAP;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) gm[acc_row(g, e) * TD + n] = pacc[e];
+        if (g == 0) gm[TD * TD + n] = qreg;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
+        if (l == 0) atomicMax(&a.seq[b].maxr, absbits(__uint_as_float(rmax) * gscale));
+    }
+}
+
+// Gradients from the final adjoint iterate: single-wave workgroups over the chunks; per chunk
+// delta = d * lambda (LDS), dW += delta^T [s_{t-1}], dU += delta^T [x_t] (FP32 MFMA, K = steps,
+// accumulated in registers over the workgroup's chunks), db, dx = delta U^T (MFMA, rows = steps),
+// ds_0 = W^T delta at a sequence's first step.  Partials: [dW | dU | db] per workgroup.
+template <int DX>
+__global__ void __launch_bounds__(64) tanh_adj_grad_kernel(TanhAdjArgs a) {
+    constexpr int SS = TD + 4, XS = DX + 4;
+    constexpr int P = TD * TD + TD * DX + TD;
+    __shared__ __attribute__((aligned(16))) float dst[TL * SS];
+    __shared__ __attribute__((aligned(16))) float hst[TL * SS];
+    __shared__ __attribute__((aligned(16))) float xst[TL * XS];
+    const int l = threadIdx.x, n = l & 31, g = l >> 5;
+    const float* Wm = a.params;
+    const float* Um = Wm + TD * TD;
+    // B operand of dx = delta U^T: U[k][n], k = 2 p + g
+    float ub[16];
+#pragma unroll
+    for (int p = 0; p < 16; ++p) ub[p] = n < DX ? Um[(2 * p + g) * DX + n] : 0.f;
+    floatx16 aw = {}, au = {};
+    float dbs = 0.f;
+    for (int slot = blockIdx.x; slot < a.ntiles; slot += gridDim.x) {
+        const TileInfo ti = a.tiles[slot];
+        const int len = ti.len, b = ti.b;
+        const int64_t row0 = ti.row0;
+        const bool first = (ti.flags & kTileTimeFirst) != 0;
+        const SeqState sq = a.seq[b];
+        const float* lam = sq.iters == 0 ? a.gs : a.lam[sq.parity];
+        __syncthreads();
+        for (int idx = l; idx < TL * (TD / 4); idx += 64) {
+            const int r = idx / (TD / 4), c4 = idx % (TD / 4);
+            const size_t o = (size_t)(row0 + r) * TD + 4 * c4;
+            float4 dv = make_float4(0.f, 0.f, 0.f, 0.f), hv = dv;
+            if (r < len) {
+                const float4 lv = *(const float4*)(lam + o), ev = *(const float4*)(a.dd + o);
+                dv = make_float4(lv.x * ev.x, lv.y * ev.y, lv.z * ev.z, lv.w * ev.w);
+                hv = (r == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * TD + 4 * c4)
+                                       : *(const float4*)(a.s + o - TD);
+            }
+            *(float4*)(dst + r * SS + 4 * c4) = dv;
+            *(float4*)(hst + r * SS + 4 * c4) = hv;
+        }
+        for (int idx = l; idx < TL * (DX / 4); idx += 64) {
+            const int r = idx / (DX / 4), c4 = idx % (DX / 4);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+            *(float4*)(xst + r * XS + 4 * c4) = v;
+        }
+        __syncthreads();
+        floatx16 ax = {};
+#pragma unroll
+        for (int p = 0; p < TL / 2; ++p) {
+            const int kk = 2 * p + g;                 // step (K of the parameter GEMMs)
+            const float dv = dst[kk * SS + n];        // delta_kk[n]
+            dbs += dv;
+            aw = __builtin_amdgcn_mfma_f32_32x32x2f32(dv, hst[kk * SS + n], aw, 0, 0, 0);
+            au = __builtin_amdgcn_mfma_f32_32x32x2f32(dv, n < DX ? xst[kk * XS + n] : 0.f, au, 0, 0, 0);
+            ax = __builtin_amdgcn_mfma_f32_32x32x2f32(dst[n * SS + kk], ub[p], ax, 0, 0, 0);
+        }
+        if (a.gx && n < DX) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int t = acc_row(g, e);
+                if (t < len) a.gx[(size_t)(row0 + t) * DX + n] = ax[e];
+            }
+        }
+        if (first && a.gs0 && g == 0) {
+            float v = 0.f;
+            for (int i = 0; i < TD; ++i) v += Wm[i * TD + n] * dst[i];
+            a.gs0[(size_t)b * TD + n] = v;
+        }
+    }
+    float* pp = a.part + (size_t)blockIdx.x * P;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = acc_row(g, e);
+        pp[i * TD + n] = aw[e];
+        if (n < DX) pp[TD * TD + i * DX + n] = au[e];
+    }
+    dbs += __shfl_xor(dbs, 32);
+    if (g == 0) pp[TD * TD + TD * DX + n] = dbs;
+}
+
+__global__ void tanh_adj_reduce_kernel(const float* part, int nparts, int P, float* out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int k = 0; k < nparts; ++k) acc += (double)part[(size_t)k * P + i];
+        out[i] = (float)acc;
+    }
+}
+
+__global__ void tanh_adj_gs0_clear_kernel(float* gs0, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) gs0[i] = 0.f;
+}
+
+struct TanhALayout {
+    IterState st;
+    float* dd;
+    float* lam[2];
+    float* gmap;
+    float* gcarry;
+    uint32_t* gmax;
+    float* part;
+    size_t bytes;
+};
+
+static int tanha_grad_grid(int ntiles) { return std::max(1, std::min(ntiles, 4 * cu_count())); }
+
+static TanhALayout tanha_layout(void* ws, int Dx, const HostBatch& hb, int ntiles, int ngroups) {
+    Carver c(ws);
+    TanhALayout lay;
+    carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
+    lay.dd = c.take<float>((size_t)hb.N * TD);
+    for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * TD);
+    lay.gmap = c.take<float>((size_t)std::max(ngroups, 1) * GMAP);
+    lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * TD);
+    lay.gmax = c.take<uint32_t>(std::max(hb.B, 1));
+    lay.part = c.take<float>((size_t)tanha_grad_grid(ntiles) * (TD * TD + TD * Dx + TD));
+    lay.bytes = c.bytes();
+    return lay;
+}
+
+typedef void (*TanhAKernel)(TanhAdjArgs);
+
+static int tanha_groups(const std::vector<int32_t>& ts, int B, int group, bool bf, int* gt,
+                        int* resident) {
+    const TanhAKernel k = bf ? tanh_adj_local_kernel<true> : tanh_adj_local_kernel<false>;
+    int occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k, 64, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    *resident = cu_count() * occ;
+    *gt = group > 0 ? group : tanhd_group_tiles(ts[B], *resident);
+    return count_groups(ts, B, *gt);
+}
+
+size_t tanh_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o) {
+    if (!tanh_dense_supported(D, Dx)) return 0;
+    const std::vector<int32_t> ts = tile_starts(hb, TL);
+    int gt, resident;
+    const int ngroups = tanha_groups(ts, hb.B, o.group, o.compose == PN_COMPOSE_BF16, &gt, &resident);
+    return tanha_layout(nullptr, Dx, hb, ts[hb.B], ngroups).bytes;
+}
+
+pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                       const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                       float* gparams, const pn_opts& o, void* ws, hipStream_t stream,
+                       pn_seq_info* info, bool* all_conv) {
+    const int Dx = cd.Dx;
+    if (!tanh_dense_supported(cd.D, Dx)) return PN_ERR_UNSUPPORTED;
+    const bool bf = o.compose == PN_COMPOSE_BF16;
+    const TanhAKernel local = bf ? tanh_adj_local_kernel<true> : tanh_adj_local_kernel<false>;
+    const TanhAKernel prep = Dx == 16 ? tanh_adj_prep_kernel<16> : tanh_adj_prep_kernel<32>;
+    const TanhAKernel grad = Dx == 16 ? tanh_adj_grad_kernel<16> : tanh_adj_grad_kernel<32>;
+    const std::vector<int32_t> ts = tile_starts(hb, TL);
+    const int ntiles = ts[hb.B];
+    int gt, resident;
+    const int ngroups = tanha_groups(ts, hb.B, o.group, bf, &gt, &resident);
+    TanhALayout lay = tanha_layout(ws, Dx, hb, ntiles, ngroups);
+    const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
+    PN_TRY(init_iter_state(lay.st, hb, ts, TL, true, max_iters, (float)o.tol, (float)o.reset_abs,
+                           stream, gt));
+    hipLaunchKernelGGL(tanh_adj_zero_kernel, dim3(1), dim3(256), 0, stream, lay.gmax, hb.B);
+    PN_HIP(hipGetLastError());
+
+    TanhAdjArgs args{};
+    args.x = x;
+    args.s0 = s0;
+    args.s = s;
+    args.gs = gs;
+    args.params = (const float*)cd.params;
+    args.dd = lay.dd;
+    for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
+    args.gmap = lay.gmap;
+    args.gcarry = lay.gcarry;
+    args.gmax = lay.gmax;
+    args.ctrl = lay.st.ctrl;
+    args.seq = lay.st.seq;
+    args.tiles = lay.st.tiles;
+    args.groups = lay.st.groups;
+    args.ngroups = ngroups;
+    args.ntiles = ntiles;
+    args.B = hb.B;
+    args.part = lay.part;
+    args.gx = gx;
+    args.gs0 = gs0;
+
+    if (ntiles > 0) {
+        prof_launch("tanh_adj_prep", stream, [&](hipStream_t s2) {
+            hipLaunchKernelGGL(prep, dim3(std::min(ntiles, 4 * cu_count())), dim3(64), 0, s2, args);
+        });
+        PN_HIP(hipGetLastError());
+    }
+    const int grid = std::max(1, std::min(ngroups, resident));
+    auto one_iter = [&](hipStream_t st) {
+        prof_launch("tanh_adj_local", st, [&](hipStream_t s2) {
+            hipLaunchKernelGGL(local, dim3(grid), dim3(64), 0, s2, args);
+        });
+        prof_launch("dense_carry", st, [&](hipStream_t s2) {
+            hipLaunchKernelGGL(dense_carry_kernel, dim3(std::max(1, hb.B)), dim3(256), 0, s2,
+                               (const float*)lay.gmap, lay.gcarry, (const Ctrl*)lay.st.ctrl,
+                               (const SeqState*)lay.st.seq, (const int32_t*)lay.st.group_start,
+                               hb.B);
+        });
+        launch_decide(lay.st, hb.B, st, true);
+    };
+    std::vector<uintptr_t> key = {0x7441u, (uintptr_t)local, (uintptr_t)grid, (uintptr_t)x,
+                                  (uintptr_t)s0, (uintptr_t)s, (uintptr_t)gs,
+                                  (uintptr_t)cd.params, (uintptr_t)ws, (uintptr_t)hb.B,
+                                  (uintptr_t)ntiles, (uintptr_t)ngroups};
+    PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
+                          stream));
+    int derr = 0;
+    PN_TRY(finish_iterations(lay.st, hb, TD, sizeof(float), nullptr, nullptr, stream, info,
+                             all_conv, &derr));
+    if (derr) {
+        set_error("device-side check failed in the dense tanh adjoint iteration");
+        return PN_ERR_INTERNAL;
+    }
+    if (gs0) {
+        hipLaunchKernelGGL(tanh_adj_gs0_clear_kernel, dim3(1), dim3(256), 0, stream, gs0, hb.B * TD);
+        PN_HIP(hipGetLastError());
+    }
+    const int gg = tanha_grad_grid(ntiles);
+    prof_launch("tanh_adj_grad", stream, [&](hipStream_t s2) {
+        hipLaunchKernelGGL(grad, dim3(gg), dim3(64), 0, s2, args);
+    });
+    PN_HIP(hipGetLastError());
+    const int P = TD * TD + TD * Dx + TD;
+    hipLaunchKernelGGL(tanh_adj_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, stream,
+                       (const float*)lay.part, gg, P, gparams);
+    PN_HIP(hipGetLastError());
+    PN_HIP(hipStreamSynchronize(stream));
+    prof_collect();
+    return PN_OK;
+}
+
 }  // namespace pn

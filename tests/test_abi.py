@@ -65,6 +65,12 @@ def test_workspace_query_on_host(lib):
     c, b, _ = _desc(cell="tanh", D=32, Dx=16)
     st, _ = _ws(lib, pn.OP_DEER, c, b, pn.make_opts(jac="dense", compose="bf16"))
     assert st == 0
+    # dense tanh adjoint: built undamped with dense Jacobians, FP32 or BF16 maps
+    for comp in ("native", "bf16"):
+        st, n3 = _ws(lib, pn.OP_ADJOINT, c, b, pn.make_opts(jac="dense", compose=comp))
+        assert st == 0 and n3 > 2 * 200 * 32 * 4
+    assert _ws(lib, pn.OP_ADJOINT, c, b, pn.make_opts(jac="diag"))[0] == -2
+    assert _ws(lib, pn.OP_ADJOINT, c, b, pn.make_opts(jac="dense", damping="scale"))[0] == -2
     c, b, _ = _desc(cell="tanh", D=16, Dx=16)
     st, _ = _ws(lib, pn.OP_ELK, c, b, pn.make_opts(jac="dense"))
     assert st == 0

@@ -93,6 +93,16 @@ def test_replay_gru_adjoint(lib):
 
 
 @pytest.mark.parametrize("compose", ["bf16", "native"])
+def test_replay_tanh_adjoint(lib, compose):
+    w = workloads.TANH32_DENSE_BF16.scaled(B=3, T=0)
+    inst = workloads.make_instance(w, seed=55, lengths=np.array([1000, 37, 2100]))
+    s, _ = lib.deer_solve(_t(inst.x), _t(inst.s0), _t(inst.params), cell="tanh",
+                          offsets=inst.offsets, jac="dense", tol=1e-6)
+    _run_fixed(lib, lib.OP_ADJOINT, "tanh", inst, w,
+               dict(jac="dense", compose=compose, tol=1e-6, graph_iters=2, group=2), s_traj=s)
+
+
+@pytest.mark.parametrize("compose", ["bf16", "native"])
 def test_replay_tanh_dense(lib, compose):
     w = workloads.TANH32_DENSE_BF16.scaled(B=3, T=0)
     inst = workloads.make_instance(w, seed=53, lengths=np.array([1000, 37, 2100]))
