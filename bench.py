@@ -411,6 +411,18 @@ def measure_rows(torch, pn, workloads):
         damp_k=0.2))
     r["scale_elk_k0.2"] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
                            "err_vs_sequential": rel(s, s_seq)}
+    # backward of the loss sum_t |s_t|^2 (g = 2 s): reverse dense scans, BF16 and FP32 maps
+    s, _ = pn.deer_solve(x, s0, p, cell="tanh", offsets=inst.offsets, jac="dense",
+                         compose="bf16", tol=1e-6)
+    gs = 2 * s
+    for comp in ("bf16", "native"):
+        ms, (gp, gx, g0, info) = _timed(torch, lambda: pn.deer_adjoint(
+            x, s0, p, s, gs, cell="tanh", offsets=inst.offsets, jac="dense", compose=comp,
+            tol=1e-6))
+        r[f"adjoint_{comp}"] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
+                                "converged": all(i["converged"] for i in info),
+                                "fwd_bwd_ms": round(ms + r["bf16"]["ms"], 3),
+                                "steps_per_s": round(inst.N / (ms * 1e-3), 1)}
     rows[w.name] = r
 
     done('section 2')

@@ -197,8 +197,13 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
      gx [N, Dx] = (df_t/dx_t)^T lambda_t   (may be NULL),
      gs0 [B, D] = A_1^T lambda_1           (may be NULL).
    With PN_JAC_DIAG the reverse recurrence is solved by iterated reverse scans with
-   diag(A_t) and an exact VJP residual (converges to the exact adjoint); info reports the
-   adjoint iterations.  Built: GRU, PN_JAC_DIAG, F32 (same shapes as deer_solve). */
+   diag(A_t) and an exact VJP residual (converges to the exact adjoint); with PN_JAC_DENSE
+   by reverse scans with the dense A_t^T = W^T diag(d_t) rebuilt on chip, composed in FP32
+   (PN_COMPOSE_NATIVE: one update reaches the adjoint) or BF16 (PN_COMPOSE_BF16: the exact
+   FP32 residual drives further updates).  Stopping rule of both: max |rho_t| <= tol *
+   max(1, max |g_t|) per sequence, rho_t = lambda_t - g_t - A_{t+1}^T lambda_{t+1}; info
+   reports the adjoint iterations.  Built: GRU, PN_JAC_DIAG, F32 (same shapes as
+   deer_solve); TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, no damping. */
 pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                        const void* s0, const void* s, const void* gs, void* gx, void* gs0,
                        void* gparams, const pn_opts* opts, void* workspace,

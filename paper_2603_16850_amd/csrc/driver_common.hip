@@ -250,6 +250,36 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
 }
 
 // One workgroup: apply the stopping test of iteration k to every active sequence.
+// ---- sum of per-workgroup partials ------------------------------------------------------------
+// out[i] = sum_k part[k * P + i] in FP64, rounded once to FP32.  A workgroup takes 64 columns and
+// splits the partials over 16 rows of threads (loads of a row are coalesced over the columns);
+// the 16 row sums are added in a fixed order, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(1024) partial_sum_kernel(const float* __restrict__ part,
+                                                            int nparts, int P,
+                                                            float* __restrict__ out) {
+    __shared__ double red[16][64];
+    const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + c;
+    double acc = 0.0;
+    if (i < P) {
+#pragma unroll 8
+        for (int k = r; k < nparts; k += 16) acc += (double)part[(size_t)k * P + i];
+    }
+    red[r][c] = acc;
+    __syncthreads();
+    if (r == 0 && i < P) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += red[q][c];
+        out[i] = (float)t;
+    }
+}
+
+void launch_partial_sum(const float* part, int nparts, int P, float* out, hipStream_t stream) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(partial_sum_kernel, dim3((P + 63) / 64), dim3(1024), 0, stream, part,
+                       nparts, P, out);
+}
+
 // resets_pending counts the rows reset while this iteration produced an iterate: the next
 // iterate s^(k+1) (kept only if the sequence goes on), or with `pending_current` the iterate
 // s^(k) just tested (always kept).

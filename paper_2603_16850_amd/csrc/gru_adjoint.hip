@@ -656,14 +656,6 @@ gru_adj_grad_kernel(GruAdjArgs a) {
     }
 }
 
-__global__ void gru_adj_reduce_kernel(const float* part, int nparts, int P, float* out) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int k = 0; k < nparts; ++k) acc += (double)part[(size_t)k * P + i];
-        out[i] = (float)acc;
-    }
-}
-
 // dL/ds_0 = A_1^T lambda_1 for every sequence (one workgroup per sequence).
 template <int D, int DX>
 __global__ void gru_adj_gs0_kernel(GruAdjArgs a) {
@@ -916,8 +908,7 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     });
     PN_HIP(hipGetLastError());
     const int P = 3 * D * Dx + 3 * D * D + 4 * D;
-    hipLaunchKernelGGL(gru_adj_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, stream,
-                       (const float*)lay.part, gg, P, gparams);
+    launch_partial_sum(lay.part, gg, P, gparams, stream);
     PN_HIP(hipGetLastError());
     if (gs0) {
         hipLaunchKernelGGL(kk.gs0, dim3(hb.B), dim3(std::max(64, D)), 0, stream, args);
@@ -985,8 +976,7 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     const int gg = grad_grid();
     hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, stream, args);
     const int P = 3 * D * Dx + 3 * D * D + 4 * D;
-    hipLaunchKernelGGL(gru_adj_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, stream,
-                       (const float*)lay.part, gg, P, gparams);
+    launch_partial_sum(lay.part, gg, P, gparams, stream);
     if (gs0) hipLaunchKernelGGL(kk.gs0, dim3(hb.B), dim3(std::max(64, D)), 0, stream, args);
     PN_HIP(hipGetLastError());
     PN_HIP(hipStreamSynchronize(stream));

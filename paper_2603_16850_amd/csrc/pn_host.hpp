@@ -120,6 +120,10 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
 // tested (solvers that form s^(k) at the start of iteration k), not to the next one.
 void launch_decide(const IterState& st, int B, hipStream_t stream, bool pending_current = false);
 
+// out[i] = sum over k < nparts of part[k * P + i] (FP64 sums in a fixed order, one FP32
+// rounding): the reduction of per-workgroup gradient partials.
+void launch_partial_sum(const float* part, int nparts, int P, float* out, hipStream_t stream);
+
 // Runs `one_iter` (which enqueues one iteration: main kernels + decide) until every
 // sequence is done, checking convergence on the host every `graph_iters` iterations;
 // with use_graph the batch of iterations is captured once and replayed.

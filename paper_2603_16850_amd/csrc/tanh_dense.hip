@@ -435,7 +435,7 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
 //   dx_t = U^T delta_t,  ds_0 = W^T delta_1.
 // Kernels: prep (d_t at the solution and max |g|, once), local (one per iteration, per group,
 // chunks taken from the sequence end), dense_carry over the reverse-ordered groups, grad
-// (per-workgroup partials of dW, dU, db on MFMA, dx, ds_0), reduce (FP64 sums of the partials).
+// (per-workgroup partials of dW, dU, db on MFMA, dx, ds_0), the FP64 sum of the partials.
 
 struct TanhAdjArgs {
     const float* x;
@@ -793,14 +793,6 @@ __global__ void __launch_bounds__(64) tanh_adj_grad_kernel(TanhAdjArgs a) {
     if (g == 0) pp[TD * TD + TD * DX + n] = dbs;
 }
 
-__global__ void tanh_adj_reduce_kernel(const float* part, int nparts, int P, float* out) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int k = 0; k < nparts; ++k) acc += (double)part[(size_t)k * P + i];
-        out[i] = (float)acc;
-    }
-}
-
 __global__ void tanh_adj_gs0_clear_kernel(float* gs0, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) gs0[i] = 0.f;
 }
@@ -816,7 +808,8 @@ struct TanhALayout {
     size_t bytes;
 };
 
-static int tanha_grad_grid(int ntiles) { return std::max(1, std::min(ntiles, 4 * cu_count())); }
+// Two single-wave workgroups per SIMD resident at once (the grad kernel's register budget).
+static int tanha_grad_grid(int ntiles) { return std::max(1, std::min(ntiles, 8 * cu_count())); }
 
 static TanhALayout tanha_layout(void* ws, int Dx, const HostBatch& hb, int ntiles, int ngroups) {
     Carver c(ws);
@@ -898,7 +891,7 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
 
     if (ntiles > 0) {
         prof_launch("tanh_adj_prep", stream, [&](hipStream_t s2) {
-            hipLaunchKernelGGL(prep, dim3(std::min(ntiles, 4 * cu_count())), dim3(64), 0, s2, args);
+            hipLaunchKernelGGL(prep, dim3(std::min(ntiles, 16 * cu_count())), dim3(64), 0, s2, args);
         });
         PN_HIP(hipGetLastError());
     }
@@ -938,8 +931,7 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
     });
     PN_HIP(hipGetLastError());
     const int P = TD * TD + TD * Dx + TD;
-    hipLaunchKernelGGL(tanh_adj_reduce_kernel, dim3((P + 255) / 256), dim3(256), 0, stream,
-                       (const float*)lay.part, gg, P, gparams);
+    launch_partial_sum(lay.part, gg, P, gparams, stream);
     PN_HIP(hipGetLastError());
     PN_HIP(hipStreamSynchronize(stream));
     prof_collect();
