@@ -415,6 +415,9 @@ def measure_rows(torch, pn, workloads):
     s, _ = pn.deer_solve(x, s0, p, cell="tanh", offsets=inst.offsets, jac="dense",
                          compose="bf16", tol=1e-6)
     gs = 2 * s
+    seq_bwd_ms, _ = _timed(torch, lambda: pn.seq_bptt(x, s0, p, s, gs, cell="tanh",
+                                                       offsets=inst.offsets))
+    r["sequential_bwd_ms"] = round(seq_bwd_ms, 3)
     for comp in ("bf16", "native"):
         ms, (gp, gx, g0, info) = _timed(torch, lambda: pn.deer_adjoint(
             x, s0, p, s, gs, cell="tanh", offsets=inst.offsets, jac="dense", compose=comp,
@@ -422,6 +425,7 @@ def measure_rows(torch, pn, workloads):
         r[f"adjoint_{comp}"] = {"ms": round(ms, 3), "iters_max": max(i["iters"] for i in info),
                                 "converged": all(i["converged"] for i in info),
                                 "fwd_bwd_ms": round(ms + r["bf16"]["ms"], 3),
+                                "speedup_vs_sequential": round(seq_bwd_ms / ms, 2),
                                 "steps_per_s": round(inst.N / (ms * 1e-3), 1)}
     rows[w.name] = r
 

@@ -216,7 +216,7 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
    step at a time, then the parallel gradient reductions -- with the outputs of deer_adjoint.
    Workspace from pn_workspace_bytes(PN_OP_SEQ, ...).  Built: GRU F32 (the deer_solve GRU
    shapes), TANH F32 ((D, Dx) in {(16,16), (32,16), (32,32), (64,32), (16,8), (4,4)}),
-   MEANFIELD F32 (D = Dx = 16). seq_bptt: GRU only. */
+   MEANFIELD F32 (D = Dx = 16). seq_bptt: GRU, and TANH F32 with D = 32, Dx in {16, 32}. */
 #define PN_OP_SEQ 4
 pn_status seq_rollout(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                       const void* s0, void* s, void* workspace, size_t workspace_bytes,

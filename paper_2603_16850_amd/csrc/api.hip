@@ -434,13 +434,18 @@ pn_status seq_bptt(const pn_cell_desc* cell, const pn_batch* batch, const void* 
         set_error("gradient arrays must be 16-byte aligned");
         return PN_ERR_INVALID_ARG;
     }
-    if (cell->dtype != PN_F32 || cell->cell != PN_CELL_GRU ||
-        !seq_supported(cell->cell, cell->D, cell->Dx)) {
+    const bool gru = cell->cell == PN_CELL_GRU && seq_supported(cell->cell, cell->D, cell->Dx);
+    const bool tanh = cell->cell == PN_CELL_TANH && tanh_dense_supported(cell->D, cell->Dx);
+    if (cell->dtype != PN_F32 || !(gru || tanh)) {
         set_error("seq_bptt not built for cell=%d D=%d Dx=%d dtype=%d", cell->cell, cell->D,
                   cell->Dx, cell->dtype);
         return PN_ERR_UNSUPPORTED;
     }
     PN_TRY(check_ws(workspace, workspace_bytes, seq_workspace(cell->cell, cell->D, cell->Dx, hb)));
+    if (tanh)
+        return tanh_seq_bptt(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
+                             (const float*)gs, (float*)gx, (float*)gs0, (float*)gparams,
+                             workspace, (hipStream_t)stream);
     return seq_bptt_run(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
                         (const float*)gs, (float*)gx, (float*)gs0, (float*)gparams, workspace,
                         (hipStream_t)stream);

@@ -249,7 +249,6 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
     return PN_OK;
 }
 
-// One workgroup: apply the stopping test of iteration k to every active sequence.
 // ---- sum of per-workgroup partials ------------------------------------------------------------
 // out[i] = sum_k part[k * P + i] in FP64, rounded once to FP32.  A workgroup takes 64 columns and
 // splits the partials over 16 rows of threads (loads of a row are coalesced over the columns);
@@ -280,6 +279,7 @@ void launch_partial_sum(const float* part, int nparts, int P, float* out, hipStr
                        nparts, P, out);
 }
 
+// One workgroup: apply the stopping test of iteration k to every active sequence.
 // resets_pending counts the rows reset while this iteration produced an iterate: the next
 // iterate s^(k+1) (kept only if the sequence goes on), or with `pending_current` the iterate
 // s^(k) just tested (always kept).

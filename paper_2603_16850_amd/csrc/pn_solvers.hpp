@@ -49,6 +49,9 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
                        const float* s0, const float* s, const float* gs, float* gx, float* gs0,
                        float* gparams, const pn_opts& o, void* ws, hipStream_t stream,
                        pn_seq_info* info, bool* all_conv);
+pn_status tanh_seq_bptt(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                        const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                        float* gparams, void* ws, hipStream_t stream);
 
 // ELK, tanh-RNN, FP32
 bool elk_supported(int D, int Dx);

@@ -199,11 +199,11 @@ size_t seq_workspace(int cell, int D, int Dx, const HostBatch& hb) {
     c.take<int64_t>(hb.B + 1);
     c.take<float>((size_t)hb.N * (cell == PN_CELL_GRU ? 3 * D : D));
     size_t n = c.bytes();
-    if (cell == PN_CELL_GRU) {
-        pn_opts o;
-        pn_default_opts(&o);
-        n = std::max(n, gru_adjoint_workspace(D, Dx, hb, o));
-    }
+    pn_opts o;
+    pn_default_opts(&o);
+    if (cell == PN_CELL_GRU) n = std::max(n, gru_adjoint_workspace(D, Dx, hb, o));
+    if (cell == PN_CELL_TANH && tanh_dense_supported(D, Dx))
+        n = std::max(n, tanh_adjoint_workspace(D, Dx, hb, o));
     return n;
 }
 

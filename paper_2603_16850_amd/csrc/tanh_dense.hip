@@ -500,8 +500,15 @@ __global__ void __launch_bounds__(64) tanh_adj_prep_kernel(TanhAdjArgs a) {
             if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
             *(float4*)(xst + r * XS + 4 * c4) = v;
         }
-        uint32_t gm = 0;
-        for (int idx = l; idx < len * TD; idx += 64) gm = max(gm, absbits(a.gs[(size_t)row0 * TD + idx]));
+        uint32_t gm = 0;                  // max |g| of the chunk: four float4 loads per lane in flight
+#pragma unroll
+        for (int q = 0; q < TL * (TD / 4) / 64; ++q) {
+            const int idx = l + 64 * q;
+            if (idx / (TD / 4) < len) {
+                const float4 v = *(const float4*)(a.gs + (size_t)row0 * TD + 4 * idx);
+                gm = max(max(gm, absbits(v.x)), max(absbits(v.y), max(absbits(v.z), absbits(v.w))));
+            }
+        }
         __syncthreads();
         floatx16 acc = {};
 #pragma unroll
@@ -797,6 +804,56 @@ __global__ void tanh_adj_gs0_clear_kernel(float* gs0, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) gs0[i] = 0.f;
 }
 
+// Sequential baseline of the adjoint: lambda_t = g_t + W^T (e_t * lambda_{t+1}) one step at a
+// time per sequence (one single-wave workgroup per sequence, lane j holds column j of W), g and
+// e staged in LDS 32 steps at a time; writes lambda to lam[1] and marks it as the final iterate.
+__global__ void __launch_bounds__(64) tanh_seq_adj_kernel(TanhAdjArgs a, const int64_t* offsets) {
+    constexpr int CH = 32;
+    __shared__ __attribute__((aligned(16))) float lb[2][TD];
+    __shared__ __attribute__((aligned(16))) float gch[CH][TD];
+    __shared__ __attribute__((aligned(16))) float ech[CH][TD];
+    const int b = blockIdx.x, j = threadIdx.x;
+    const int64_t r0 = offsets[b], T = offsets[b + 1] - r0;
+    float w[TD];                                  // column j of W
+#pragma unroll
+    for (int k = 0; k < TD; ++k) w[k] = j < TD ? a.params[k * TD + j] : 0.f;
+    if (j < TD) lb[0][j] = 0.f;
+    float* lam = a.lam[1];
+    for (int64_t it = 0; it < T; ++it) {
+        const int64_t t = T - 1 - it;
+        const int r = (int)(it % CH);
+        if (r == 0) {
+            __syncthreads();
+            for (int idx = j; idx < CH * TD; idx += 64) {
+                const int q = idx / TD, c = idx % TD;
+                const int64_t tt = t - q;
+                gch[q][c] = tt >= 0 ? a.gs[(size_t)(r0 + tt) * TD + c] : 0.f;
+                ech[q][c] = (tt >= 0 && tt + 1 < T) ? a.dd[(size_t)(r0 + tt + 1) * TD + c] : 0.f;
+            }
+            __syncthreads();
+        }
+        const int cur = (int)(it & 1);
+        if (j < TD) {
+            const float* ln = lb[cur];
+            const float* e = ech[r];
+            float acc = gch[r][j];
+#pragma unroll
+            for (int k = 0; k < TD; k += 4) {
+                const float4 l4 = *(const float4*)(ln + k), e4 = *(const float4*)(e + k);
+                acc += w[k] * (e4.x * l4.x) + w[k + 1] * (e4.y * l4.y) + w[k + 2] * (e4.z * l4.z) +
+                       w[k + 3] * (e4.w * l4.w);
+            }
+            lb[cur ^ 1][j] = acc;
+            lam[(size_t)(r0 + t) * TD + j] = acc;
+        }
+        __syncthreads();
+    }
+    if (j == 0 && T > 0) {
+        a.seq[b].iters = 1;
+        a.seq[b].parity = 1;
+    }
+}
+
 struct TanhALayout {
     IterState st;
     float* dd;
@@ -834,7 +891,9 @@ static int tanha_groups(const std::vector<int32_t>& ts, int B, int group, bool b
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k, 64, 0) != hipSuccess || occ < 1)
         occ = 1;
     *resident = cu_count() * occ;
-    *gt = group > 0 ? group : tanhd_group_tiles(ts[B], *resident);
+    // about one group per resident workgroup, at most 8 chunks: the adjoint's local pass runs
+    // only twice, so a shorter carry chain pays more than a second round of groups
+    *gt = group > 0 ? group : std::max(1, std::min(8, ts[B] / std::max(1, *resident)));
     return count_groups(ts, B, *gt);
 }
 
@@ -932,6 +991,54 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
     PN_HIP(hipGetLastError());
     const int P = TD * TD + TD * Dx + TD;
     launch_partial_sum(lay.part, gg, P, gparams, stream);
+    PN_HIP(hipGetLastError());
+    PN_HIP(hipStreamSynchronize(stream));
+    prof_collect();
+    return PN_OK;
+}
+
+// Sequential baseline of tanh_adjoint: the same outputs, the reverse recurrence walked step by
+// step (d_t and the gradient reductions are the parallel kernels above).
+pn_status tanh_seq_bptt(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                        const float* s0, const float* s, const float* gs, float* gx, float* gs0,
+                        float* gparams, void* ws, hipStream_t stream) {
+    const int Dx = cd.Dx;
+    if (!tanh_dense_supported(cd.D, Dx)) return PN_ERR_UNSUPPORTED;
+    const TanhAKernel prep = Dx == 16 ? tanh_adj_prep_kernel<16> : tanh_adj_prep_kernel<32>;
+    const TanhAKernel grad = Dx == 16 ? tanh_adj_grad_kernel<16> : tanh_adj_grad_kernel<32>;
+    const std::vector<int32_t> ts = tile_starts(hb, TL);
+    const int ntiles = ts[hb.B];
+    TanhALayout lay = tanha_layout(ws, Dx, hb, ntiles, 0);
+    PN_TRY(init_iter_state(lay.st, hb, ts, TL, true, 1, 1.f, 1e4f, stream));
+    hipLaunchKernelGGL(tanh_adj_zero_kernel, dim3(1), dim3(256), 0, stream, lay.gmax, hb.B);
+    TanhAdjArgs args{};
+    args.x = x;
+    args.s0 = s0;
+    args.s = s;
+    args.gs = gs;
+    args.params = (const float*)cd.params;
+    args.dd = lay.dd;
+    for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
+    args.gmax = lay.gmax;
+    args.ctrl = lay.st.ctrl;
+    args.seq = lay.st.seq;
+    args.tiles = lay.st.tiles;
+    args.ntiles = ntiles;
+    args.B = hb.B;
+    args.part = lay.part;
+    args.gx = gx;
+    args.gs0 = gs0;
+    if (ntiles > 0)
+        hipLaunchKernelGGL(prep, dim3(std::min(ntiles, 16 * cu_count())), dim3(64), 0, stream, args);
+    prof_launch("seq_adj", stream, [&](hipStream_t s2) {
+        hipLaunchKernelGGL(tanh_seq_adj_kernel, dim3(std::max(1, hb.B)), dim3(64), 0, s2, args,
+                           (const int64_t*)lay.st.offsets);
+    });
+    PN_HIP(hipGetLastError());
+    if (gs0) hipLaunchKernelGGL(tanh_adj_gs0_clear_kernel, dim3(1), dim3(256), 0, stream, gs0, hb.B * TD);
+    const int gg = tanha_grad_grid(ntiles);
+    hipLaunchKernelGGL(grad, dim3(gg), dim3(64), 0, stream, args);
+    launch_partial_sum(lay.part, gg, TD * TD + TD * Dx + TD, gparams, stream);
     PN_HIP(hipGetLastError());
     PN_HIP(hipStreamSynchronize(stream));
     prof_collect();

@@ -82,6 +82,15 @@ def test_many_groups_match_oracle(lib, compose, group):
     _check(cell, got, want)
 
 
+def test_sequential_baseline(lib):
+    """seq_bptt on the dense tanh cell (the reverse recurrence walked step by step) meets the
+    same bar against the oracle."""
+    inst, cell, s32, want = _case(32, [300, 1, 0, 131, 65], seed=20)
+    gp, gx, g0 = lib.seq_bptt(_t(inst.x), _t(inst.s0), _t(inst.params), _t(s32), _t(2 * s32),
+                              cell="tanh", offsets=inst.offsets)
+    _check(cell, tuple(v.cpu().double().numpy() for v in (gp, gx, g0)), want)
+
+
 def test_autograd_function_full_path(lib):
     """deer() forward (dense BF16 DEER) and its backward (this adjoint) against the oracle's
     rollout and adjoint."""
