@@ -1,5 +1,6 @@
 // Host helpers and control kernels shared by every iterative solver.
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 
@@ -182,16 +183,33 @@ __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offs
     }
 }
 
+namespace {
+// Thread-local pinned staging buffers, grown as needed and kept until the process ends.  Copies
+// from or to pinned memory are asynchronous DMA (a pageable copy stages through a driver buffer
+// and stalls the stream); a buffer is reused only by the next call on the same thread, after
+// the previous call synchronised its stream.
+void* pinned_staging(int which, size_t bytes) {
+    struct Buf { void* p = nullptr; size_t n = 0; };
+    static thread_local Buf bufs[2];
+    Buf& b = bufs[which];
+    if (b.n < bytes) {
+        if (b.p) (void)hipHostFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+        const size_t n = std::max(bytes, (size_t)64 << 10);
+        if (hipHostMalloc(&b.p, n, hipHostMallocDefault) != hipSuccess) return nullptr;
+        b.n = n;
+    }
+    return b.p;
+}
+}  // namespace
+
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
                           const std::vector<int32_t>& tstart, int L, bool reverse,
                           int max_iters, float tol, float reset_abs, hipStream_t stream,
                           int gt) {
-    PN_HIP(hipMemcpyAsync(st.offsets, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1),
-                          hipMemcpyHostToDevice, stream));
-    PN_HIP(hipMemcpyAsync(st.tile_start, tstart.data(), sizeof(int32_t) * (hb.B + 1),
-                          hipMemcpyHostToDevice, stream));
-    // host staging of the tables, kept alive until the next call on this thread, after which
-    // the copies have completed (every solver synchronises its stream before returning)
+    // the tables are built on the host and sent in one copy of the span they occupy in the
+    // workspace (offsets, tile_start, order, tiles, groups, group_start, carved in this order)
     static thread_local std::vector<int32_t> order;
     static thread_local std::vector<TileInfo> tiles;
     static thread_local std::vector<GroupInfo> groups;
@@ -225,23 +243,29 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
     for (int k = 0; k < maxt; ++k)
         for (int b = 0; b < hb.B; ++b)
             if (k < tstart[b + 1] - tstart[b]) order.push_back(tstart[b] + k);
-    if (ntiles > 0) {
-        PN_HIP(hipMemcpyAsync(st.order, order.data(), sizeof(int32_t) * order.size(),
-                              hipMemcpyHostToDevice, stream));
-        PN_HIP(hipMemcpyAsync(st.tiles, tiles.data(), sizeof(TileInfo) * tiles.size(),
-                              hipMemcpyHostToDevice, stream));
+    if (gt > 0 && (int)groups.size() != st.ngroups) {
+        set_error("internal: group table size %d, carved %d", (int)groups.size(), st.ngroups);
+        return PN_ERR_INTERNAL;
     }
+    char* const d0 = (char*)st.offsets;
+    const size_t span = (size_t)((char*)(st.group_start + hb.B + 1) - d0);
+    char* h = (char*)pinned_staging(0, span);
+    if (!h) {
+        set_error("hipHostMalloc of %zu bytes for the tile tables failed", span);
+        return PN_ERR_HIP;
+    }
+    auto put = [&](void* dev, const void* src, size_t n) {
+        if (n) std::memcpy(h + ((char*)dev - d0), src, n);
+    };
+    put(st.offsets, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1));
+    put(st.tile_start, tstart.data(), sizeof(int32_t) * (hb.B + 1));
+    put(st.order, order.data(), sizeof(int32_t) * order.size());
+    put(st.tiles, tiles.data(), sizeof(TileInfo) * tiles.size());
     if (gt > 0) {
-        if ((int)groups.size() != st.ngroups) {
-            set_error("internal: group table size %d, carved %d", (int)groups.size(), st.ngroups);
-            return PN_ERR_INTERNAL;
-        }
-        if (!groups.empty())
-            PN_HIP(hipMemcpyAsync(st.groups, groups.data(), sizeof(GroupInfo) * groups.size(),
-                                  hipMemcpyHostToDevice, stream));
-        PN_HIP(hipMemcpyAsync(st.group_start, gstart.data(), sizeof(int32_t) * (hb.B + 1),
-                              hipMemcpyHostToDevice, stream));
+        put(st.groups, groups.data(), sizeof(GroupInfo) * groups.size());
+        put(st.group_start, gstart.data(), sizeof(int32_t) * (hb.B + 1));
     }
+    PN_HIP(hipMemcpyAsync(d0, h, span, hipMemcpyHostToDevice, stream));
     int blocks = std::min(64, (hb.B + 255) / 256);
     hipLaunchKernelGGL(init_state_kernel, dim3(std::max(1, blocks)), dim3(256), 0, stream,
                        st.ctrl, st.seq, st.offsets, hb.B, max_iters, tol, reset_abs);
@@ -432,12 +456,18 @@ pn_status finish_iterations(const IterState& st, const HostBatch& hb, int D, siz
                                st.seq, st.offsets, D, (double*)s_user, (const double*)s_alt);
         PN_HIP(hipGetLastError());
     }
-    std::vector<SeqState> hs(hb.B);
-    Ctrl hc;
-    PN_HIP(hipMemcpyAsync(hs.data(), st.seq, sizeof(SeqState) * hb.B, hipMemcpyDeviceToHost,
-                          stream));
-    PN_HIP(hipMemcpyAsync(&hc, st.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    // control block and per-sequence states (carved next to each other) in one pinned copy
+    const size_t span = (size_t)((char*)(st.seq + hb.B) - (char*)st.ctrl);
+    char* h = (char*)pinned_staging(1, span);
+    if (!h) {
+        set_error("hipHostMalloc of %zu bytes for the solver state failed", span);
+        return PN_ERR_HIP;
+    }
+    PN_HIP(hipMemcpyAsync(h, st.ctrl, span, hipMemcpyDeviceToHost, stream));
     PN_HIP(hipStreamSynchronize(stream));
+    Ctrl hc;
+    std::memcpy(&hc, h, sizeof(Ctrl));
+    const SeqState* hs = (const SeqState*)(h + ((char*)st.seq - (char*)st.ctrl));
     bool allc = true;
     for (int b = 0; b < hb.B; ++b) {
         const bool conv = hs[b].status == kConverged;
