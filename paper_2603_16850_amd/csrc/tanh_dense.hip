@@ -35,9 +35,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // Row held by accumulator element e of lane group g in a 32x32 MFMA result.
 PN_DEV int acc_row(int g, int e) { return 8 * (e >> 2) + 4 * g + (e & 3); }
 
-constexpr int TD = 32;                       // state size handled by this kernel
+constexpr int TD_ = 32;
+// Stores column n of a 32x32 map held in accumulator layout (element e = row acc_row(g, e)) into
+// a column-major map: rows 8k + 4g .. 8k + 4g + 3 are consecutive, four float4 stores per lane.
+// Column-major maps let the carry's mat-vec read them with consecutive lanes on consecutive
+// LDS banks.
+PN_DEV void store_map_column(float* gm, const float* pacc, int n, int g) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        *(float4*)(gm + n * TD_ + 8 * k + 4 * g) =
+            make_float4(pacc[4 * k], pacc[4 * k + 1], pacc[4 * k + 2], pacc[4 * k + 3]);
+}
+
+constexpr int TD = TD_;                      // state size handled by this kernel
 constexpr int TL = 32;                       // chunk length (one MFMA row block)
-constexpr int GMAP = TD * TD + TD;           // floats per group map: P row-major, then q
+constexpr int GMAP = TD * TD + TD;           // floats per group map: P column-major, then q
 
 struct TanhDArgs {
     const float* x;
@@ -246,10 +258,9 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        // ---- the group's map: P row-major (P[r][c] at r * 32 + c), then q
+        // ---- the group's map: P column-major (P[r][c] at c * 32 + r), then q
         float* gm = a.gmap + (size_t)gi * GMAP;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) gm[acc_row(g, e) * TD + n] = pacc[e];
+        store_map_column(gm, pacc, n, g);
         if (g == 0) gm[TD * TD + n] = vec[n];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
@@ -262,9 +273,9 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
 
 // ---- carry pass: Delta_in(g+1) = P_g Delta_in(g) + q_g over the groups of a sequence -------
 // One workgroup of 256 threads per sequence.  The group maps are staged through LDS in batches
-// of CB groups, double-buffered: every thread loads the next batch while wave 0 runs the chain
-// over the current one.
-constexpr int CB = 6;
+// of CB groups, double-buffered: waves 1-3 load the next batch while wave 0 runs the chain over
+// the current one (wave 0 loads nothing, so its chain never waits on HBM).
+constexpr int CB = 12;
 
 __global__ void __launch_bounds__(256) dense_carry_kernel(const float* __restrict__ gmap,
                                                           float* __restrict__ gcarry,
@@ -278,17 +289,17 @@ __global__ void __launch_bounds__(256) dense_carry_kernel(const float* __restric
     const int tid = threadIdx.x;
     const int g0 = group_start[b], G = group_start[b + 1] - g0;
     const int nb = (G + CB - 1) / CB;
-    auto load = [&](int j, int p) {
+    auto load = [&](int j, int p, int t0, int nt) {
         const int nv = min(CB, G - j * CB) * (GMAP / 4);
         const float4* srcv = (const float4*)(gmap + (size_t)(g0 + j * CB) * GMAP);
-        for (int i = tid; i < nv; i += 256) ((float4*)buf[p])[i] = srcv[i];
+        for (int i = tid - t0; i < nv; i += nt) ((float4*)buf[p])[i] = srcv[i];
     };
-    if (nb > 0) load(0, 0);
+    if (nb > 0) load(0, 0, 0, 256);
     if (tid < TD) cv[0][tid] = 0.f;
     __syncthreads();
     int cur = 0;                               // wave 0 only
     for (int j = 0; j < nb; ++j) {
-        if (j + 1 < nb) load(j + 1, (j + 1) & 1);
+        if (j + 1 < nb && tid >= 64) load(j + 1, (j + 1) & 1, 64, 192);
         if (tid < 64) {
             const int n = tid & 31, g = tid >> 5;
             const int gcount = min(CB, G - j * CB);
@@ -298,7 +309,7 @@ __global__ void __launch_bounds__(256) dense_carry_kernel(const float* __restric
                 if (g == 0) gcarry[(size_t)(g0 + j * CB + q) * TD + n] = cv[cur][n];
                 float part = 0.f;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) part += P[n * TD + 16 * g + i] * cv[cur][16 * g + i];
+                for (int i = 0; i < 16; ++i) part += P[(16 * g + i) * TD + n] * cv[cur][16 * g + i];
                 part += __shfl_xor(part, 32);
                 if (g == 0) cv[cur ^ 1][n] = part + P[TD * TD + n];
                 __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the LDS write has landed
@@ -709,8 +720,7 @@ __global__ void __launch_bounds__(64) tanh_adj_local_kernel(TanhAdjArgs a) {
             }
         }
         float* gm = a.gmap + (size_t)gi * GMAP;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) gm[acc_row(g, e) * TD + n] = pacc[e];
+        store_map_column(gm, pacc, n, g);
         if (g == 0) gm[TD * TD + n] = qreg;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
