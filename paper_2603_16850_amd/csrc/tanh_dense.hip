@@ -289,17 +289,26 @@ __global__ void __launch_bounds__(256) dense_carry_kernel(const float* __restric
     const int tid = threadIdx.x;
     const int g0 = group_start[b], G = group_start[b + 1] - g0;
     const int nb = (G + CB - 1) / CB;
-    auto load = [&](int j, int p, int t0, int nt) {
-        const int nv = min(CB, G - j * CB) * (GMAP / 4);
+    // batch j into buffer p by waves w0 .. w0 + nw - 1: straight from HBM into LDS
+    // (global_load_lds, 16 B per lane to byte 16 * lane of a 1 KB slice), every slice of a wave
+    // in flight at once, then one wait
+    auto load = [&](int j, int p, int w0, int nw) {
+        const int nv = min(CB, G - j * CB) * (GMAP / 4);          // float4 in the batch
         const float4* srcv = (const float4*)(gmap + (size_t)(g0 + j * CB) * GMAP);
-        for (int i = tid - t0; i < nv; i += nt) ((float4*)buf[p])[i] = srcv[i];
+        const int ln = tid & 63;
+        for (int c = (tid >> 6) - w0; c * 64 < nv; c += nw)
+            if (c * 64 + ln < nv)
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(srcv + c * 64 + ln),
+                    (__attribute__((address_space(3))) void*)(buf[p] + c * 256), 16, 0, 0);
+        __builtin_amdgcn_s_waitcnt(0x0F70);                        // vmcnt(0)
     };
-    if (nb > 0) load(0, 0, 0, 256);
+    if (nb > 0) load(0, 0, 0, 4);
     if (tid < TD) cv[0][tid] = 0.f;
     __syncthreads();
     int cur = 0;                               // wave 0 only
     for (int j = 0; j < nb; ++j) {
-        if (j + 1 < nb && tid >= 64) load(j + 1, (j + 1) & 1, 64, 192);
+        if (j + 1 < nb && tid >= 64) load(j + 1, (j + 1) & 1, 1, 3);
         if (tid < 64) {
             const int n = tid & 31, g = tid >> 5;
             const int gcount = min(CB, G - j * CB);
