@@ -58,7 +58,8 @@ struct GruAdjArgs {
     float* lc[2];            // [N][D] additive part; iteration k writes lc[k & 1]
     float2* gagg;            // [ngroups][D] group maps
     const float* gcarry;     // [ngroups][D] carry into every group (previous iteration)
-    float* gmax;             // [B] max |g| per sequence (as float bits, via atomicMax)
+    float* gmax;             // [B] max |g| per sequence (as float bits)
+    uint32_t* cmax;          // [ntiles][D / 16] max |g| per tile and wave (float bits)
     Ctrl* ctrl;
     SeqState* seq;
     const int64_t* offsets;
@@ -179,8 +180,23 @@ gru_adj_prep_kernel(GruAdjArgs a) {
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) gm = max(gm, (uint32_t)__shfl_xor((int)gm, off));
-        if (l == 0) atomicMax((uint32_t*)&a.gmax[b], gm);
+        if (l == 0) a.cmax[(size_t)tile * C::NW + w] = gm;
     }
+}
+
+// max |g| of every sequence from the maxima of its tiles (one workgroup per sequence)
+template <int NW>
+__global__ void __launch_bounds__(256) gru_adj_gmax_kernel(GruAdjArgs a) {
+    __shared__ uint32_t red[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    uint32_t m = 0;
+    for (int k = a.tile_start[b] * NW + tid; k < a.tile_start[b + 1] * NW; k += 256)
+        m = max(m, a.cmax[k]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((tid & 63) == 0) red[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) ((uint32_t*)a.gmax)[b] = max(max(red[0], red[1]), max(red[2], red[3]));
 }
 
 // ---- one adjoint iteration ------------------------------------------------------------------
@@ -678,10 +694,6 @@ __global__ void gru_adj_gs0_kernel(GruAdjArgs a) {
     a.gs0[(size_t)b * D + j] = v;
 }
 
-__global__ void zero_u32_kernel(uint32_t* p, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
-}
-
 // ---- sequential adjoint (baseline): lambda_t = g_t + A_{t+1}^T lambda_{t+1}, one step at a
 // time per sequence; lanes 4j..4j+3 of a wave serve unit j (U_z^T, U_n^T, U_r^T columns).
 template <int D>
@@ -739,6 +751,7 @@ __global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, 
 struct GruALayout {
     IterState st;
     float *gates, *lam[2], *gmax, *part, *gcarry;
+    uint32_t* cmax;
     float2 *zd, *gagg;
     float *la, *lc[2];
     size_t bytes;
@@ -762,6 +775,7 @@ static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int 
     lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
     lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
     lay.gmax = c.take<float>(hb.B);
+    lay.cmax = c.take<uint32_t>((size_t)std::max(ntiles, 1) * (D / 16));
     const size_t P = 3 * (size_t)D * Dx + 3 * (size_t)D * D + 4 * (size_t)D;
     lay.part = c.take<float>((size_t)grad_grid() * P);
     lay.bytes = c.bytes();
@@ -773,6 +787,7 @@ struct GruAKernels {
     void (*iter)(GruAdjArgs);
     void (*grad)(GruAdjArgs);
     void (*gs0)(GruAdjArgs);
+    void (*gmax)(GruAdjArgs);
     int nt;
 };
 
@@ -783,6 +798,7 @@ static GruAKernels gruA_get() {
     k.iter = gru_adj_local_kernel<D, DX, kAdjL>;
     k.grad = gru_adj_grad_kernel<D, DX, kGradL, kAdjL / kGradL>;
     k.gs0 = gru_adj_gs0_kernel<D, DX>;
+    k.gmax = gru_adj_gmax_kernel<D / 16>;
     k.nt = 64 * (D / 16);
     return k;
 }
@@ -830,8 +846,6 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, max_iters, (float)o.tol,
                            (float)o.reset_abs, stream, gt));
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
-    PN_HIP(hipGetLastError());
 
     GruAdjArgs args;
     args.x = x;
@@ -848,6 +862,7 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.gagg = lay.gagg;
     args.gcarry = lay.gcarry;
     args.gmax = lay.gmax;
+    args.cmax = lay.cmax;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
     args.offsets = lay.st.offsets;
@@ -874,6 +889,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         });
         PN_HIP(hipGetLastError());
     }
+    hipLaunchKernelGGL(kk.gmax, dim3(hb.B), dim3(256), 0, stream, args);
+    PN_HIP(hipGetLastError());
     const int grid = std::max(1, std::min(ngroups, resident));
     // iteration k forms lambda^(k) in lam[k & 1] from lam[(k + 1) & 1] (k from the control
     // block), then the carries
@@ -940,7 +957,6 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     const int ntiles = ts[hb.B];
     GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, 0);
     PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, 1, 1.f, 1e4f, stream));
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)lay.gmax, hb.B);
     GruAdjArgs args{};
     args.x = x;
     args.s0 = s0;
@@ -951,6 +967,7 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.zd = lay.zd;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     args.gmax = lay.gmax;
+    args.cmax = lay.cmax;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
     args.offsets = lay.st.offsets;

@@ -468,6 +468,8 @@ struct TanhAdjArgs {
     float* gmap;              // [ngroups][GMAP] group maps of this iteration
     const float* gcarry;      // [ngroups][TD] Delta at the step after every group (previous iteration)
     uint32_t* gmax;           // [B] max |g| per sequence (float bits)
+    uint32_t* cmax;           // [ntiles] max |g| per chunk (float bits), by slot
+    const int32_t* tile_start; // [B + 1] chunk slots of every sequence
     Ctrl* ctrl;
     SeqState* seq;
     const TileInfo* tiles;    // by slot: chunks taken from the sequence end
@@ -480,25 +482,24 @@ struct TanhAdjArgs {
     float* gs0;               // may be null
 };
 
-__global__ void tanh_adj_zero_kernel(uint32_t* p, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
-}
-
 // d_t = 1 - tanh(W s_{t-1} + U x_t + b)^2 of every step (pre-activations on FP32 MFMA, one chunk
-// per pass of a single-wave workgroup) and max |g| of every sequence.
+// per single-wave workgroup, the B operand [W | U] read straight into registers) and max |g| of
+// every sequence.
 template <int DX>
 __global__ void __launch_bounds__(64) tanh_adj_prep_kernel(TanhAdjArgs a) {
-    constexpr int SS = TD + 4, XS = DX + 4, KT = TD + DX, WS = KT + 4;
+    constexpr int SS = TD + 4, XS = DX + 4, KT = TD + DX;
     static_assert(KT % 2 == 0, "shape");
     __shared__ __attribute__((aligned(16))) float hst[TL * SS];
     __shared__ __attribute__((aligned(16))) float xst[TL * XS];
-    __shared__ __attribute__((aligned(16))) float wl[TD * WS];
     const int l = threadIdx.x, n = l & 31, g = l >> 5;
     const float* Wm = a.params;
     const float* Um = Wm + TD * TD;
-    for (int idx = l; idx < TD * KT; idx += 64) {
-        const int r = idx / KT, c = idx % KT;
-        wl[r * WS + c] = c < TD ? Wm[r * TD + c] : Um[r * DX + (c - TD)];
+    // B operand: [W | U][n][kk], kk = 2 p + g
+    float bw[KT / 2];
+#pragma unroll
+    for (int p = 0; p < KT / 2; ++p) {
+        const int kk = 2 * p + g;
+        bw[p] = kk < TD ? Wm[n * TD + kk] : Um[n * DX + (kk - TD)];
     }
     const float bias_n = Um[TD * DX + n];
     for (int slot = blockIdx.x; slot < a.ntiles; slot += gridDim.x) {
@@ -507,14 +508,18 @@ __global__ void __launch_bounds__(64) tanh_adj_prep_kernel(TanhAdjArgs a) {
         const int64_t row0 = ti.row0;
         const bool first = (ti.flags & kTileTimeFirst) != 0;
         __syncthreads();
-        for (int idx = l; idx < TL * (TD / 4); idx += 64) {
+#pragma unroll
+        for (int q = 0; q < TL * (TD / 4) / 64; ++q) {
+            const int idx = l + 64 * q;
             const int r = idx / (TD / 4), c4 = idx % (TD / 4);
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (r < len) v = (r == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * TD + 4 * c4)
                                                : *(const float4*)(a.s + (size_t)(row0 + r - 1) * TD + 4 * c4);
             *(float4*)(hst + r * SS + 4 * c4) = v;
         }
-        for (int idx = l; idx < TL * (DX / 4); idx += 64) {
+#pragma unroll
+        for (int q = 0; q < TL * (DX / 4) / 64; ++q) {
+            const int idx = l + 64 * q;
             const int r = idx / (DX / 4), c4 = idx % (DX / 4);
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
@@ -535,7 +540,7 @@ __global__ void __launch_bounds__(64) tanh_adj_prep_kernel(TanhAdjArgs a) {
         for (int p = 0; p < KT / 2; ++p) {
             const int kk = 2 * p + g;
             const float av = kk < TD ? hst[n * SS + kk] : xst[n * XS + (kk - TD)];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, wl[n * WS + kk], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bw[p], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -545,8 +550,21 @@ __global__ void __launch_bounds__(64) tanh_adj_prep_kernel(TanhAdjArgs a) {
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) gm = max(gm, (uint32_t)__shfl_xor((int)gm, off));
-        if (l == 0) atomicMax(&a.gmax[b], gm);
+        if (l == 0) a.cmax[slot] = gm;
     }
+}
+
+// max |g| of every sequence from its chunks' maxima (one workgroup per sequence)
+__global__ void __launch_bounds__(256) tanh_adj_gmax_kernel(TanhAdjArgs a) {
+    __shared__ uint32_t red[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    uint32_t m = 0;
+    for (int k = a.tile_start[b] + tid; k < a.tile_start[b + 1]; k += 256) m = max(m, a.cmax[k]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((tid & 63) == 0) red[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) a.gmax[b] = max(max(red[0], red[1]), max(red[2], red[3]));
 }
 
 // One adjoint iteration, one single-wave workgroup per group, the group's chunks from the
@@ -880,6 +898,7 @@ struct TanhALayout {
     float* gmap;
     float* gcarry;
     uint32_t* gmax;
+    uint32_t* cmax;
     float* part;
     size_t bytes;
 };
@@ -896,6 +915,7 @@ static TanhALayout tanha_layout(void* ws, int Dx, const HostBatch& hb, int ntile
     lay.gmap = c.take<float>((size_t)std::max(ngroups, 1) * GMAP);
     lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * TD);
     lay.gmax = c.take<uint32_t>(std::max(hb.B, 1));
+    lay.cmax = c.take<uint32_t>(std::max(ntiles, 1));
     lay.part = c.take<float>((size_t)tanha_grad_grid(ntiles) * (TD * TD + TD * Dx + TD));
     lay.bytes = c.bytes();
     return lay;
@@ -942,8 +962,6 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
     PN_TRY(init_iter_state(lay.st, hb, ts, TL, true, max_iters, (float)o.tol, (float)o.reset_abs,
                            stream, gt));
-    hipLaunchKernelGGL(tanh_adj_zero_kernel, dim3(1), dim3(256), 0, stream, lay.gmax, hb.B);
-    PN_HIP(hipGetLastError());
 
     TanhAdjArgs args{};
     args.x = x;
@@ -956,6 +974,8 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.gmap = lay.gmap;
     args.gcarry = lay.gcarry;
     args.gmax = lay.gmax;
+    args.cmax = lay.cmax;
+    args.tile_start = lay.st.tile_start;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
     args.tiles = lay.st.tiles;
@@ -969,9 +989,13 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
 
     if (ntiles > 0) {
         prof_launch("tanh_adj_prep", stream, [&](hipStream_t s2) {
-            hipLaunchKernelGGL(prep, dim3(std::min(ntiles, 16 * cu_count())), dim3(64), 0, s2, args);
+            hipLaunchKernelGGL(prep, dim3(ntiles), dim3(64), 0, s2, args);
+            hipLaunchKernelGGL(tanh_adj_gmax_kernel, dim3(hb.B), dim3(256), 0, s2, args);
         });
         PN_HIP(hipGetLastError());
+    } else {
+        // no steps anywhere: every sequence stops at iteration 0 with a zero residual
+        hipLaunchKernelGGL(tanh_adj_gmax_kernel, dim3(hb.B), dim3(256), 0, stream, args);
     }
     const int grid = std::max(1, std::min(ngroups, resident));
     auto one_iter = [&](hipStream_t st) {
@@ -1029,7 +1053,6 @@ pn_status tanh_seq_bptt(const pn_cell_desc& cd, const HostBatch& hb, const float
     const int ntiles = ts[hb.B];
     TanhALayout lay = tanha_layout(ws, Dx, hb, ntiles, 0);
     PN_TRY(init_iter_state(lay.st, hb, ts, TL, true, 1, 1.f, 1e4f, stream));
-    hipLaunchKernelGGL(tanh_adj_zero_kernel, dim3(1), dim3(256), 0, stream, lay.gmax, hb.B);
     TanhAdjArgs args{};
     args.x = x;
     args.s0 = s0;
@@ -1039,6 +1062,8 @@ pn_status tanh_seq_bptt(const pn_cell_desc& cd, const HostBatch& hb, const float
     args.dd = lay.dd;
     for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
     args.gmax = lay.gmax;
+    args.cmax = lay.cmax;
+    args.tile_start = lay.st.tile_start;
     args.ctrl = lay.st.ctrl;
     args.seq = lay.st.seq;
     args.tiles = lay.st.tiles;
@@ -1048,7 +1073,7 @@ pn_status tanh_seq_bptt(const pn_cell_desc& cd, const HostBatch& hb, const float
     args.gx = gx;
     args.gs0 = gs0;
     if (ntiles > 0)
-        hipLaunchKernelGGL(prep, dim3(std::min(ntiles, 16 * cu_count())), dim3(64), 0, stream, args);
+        hipLaunchKernelGGL(prep, dim3(ntiles), dim3(64), 0, stream, args);
     prof_launch("seq_adj", stream, [&](hipStream_t s2) {
         hipLaunchKernelGGL(tanh_seq_adj_kernel, dim3(std::max(1, hb.B)), dim3(64), 0, s2, args,
                            (const int64_t*)lay.st.offsets);
