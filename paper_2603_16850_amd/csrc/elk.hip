@@ -822,7 +822,7 @@ __global__ void __launch_bounds__(64) elk_quasi_local_kernel(ElkArgs a) {
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) {
             a.grmax[gi] = rmax;
-            atomicMax(&a.seq[b].maxr, rmax);
+            if (a.freeze) atomicMax(&a.seq[b].maxr, rmax);   // else folded in by the carry pass
             if (nreset) atomicAdd(&a.seq[b].resets_pending, nreset);
         }
     }
@@ -863,6 +863,21 @@ __global__ void __launch_bounds__(1024) elk_quasi_carry_kernel(const float* __re
         }
         __syncthreads();
         gstart = gs_sh;
+    } else {
+        // the stopping test's max |r| of the sequence from its groups' maxima (the local pass
+        // writes one per group instead of contending for one word with an atomic per group)
+        uint32_t m = 0;
+        for (int k = tid; k < G; k += 1024) m = max(m, grmax[g0 + k]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+        if ((tid & 63) == 0) sc[tid >> 6][0].A = __uint_as_float(m);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t r = seq[b].maxr;
+            for (int w = 0; w < 16; ++w) r = max(r, __float_as_uint(sc[w][0].A));
+            seq[b].maxr = r;
+        }
+        __syncthreads();
     }
     const int per = (G - gstart + kQSeg - 1) / kQSeg;
     const int lo = gstart + sg * per, hi = min(G, lo + per);
