@@ -312,6 +312,7 @@ struct ElkArgs {
     uint32_t* grmax;         // [ngroups] residual bound of every group's latest iterate (bits)
     int ngroups;
     int freeze;              // converged-prefix skipping
+    int fold_rmax;           // nonzero: the carry pass folds grmax into the stopping residual
     float lam;
     int res64;               // nonzero: the stopping residual is evaluated in FP64
     int diag;                // nonzero: quasi-ELK, the LGSSM uses diag(A_t)
@@ -576,7 +577,7 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) {
             a.grmax[gi] = rmax;
-            atomicMax(&a.seq[b].maxr, rmax);
+            if (!a.fold_rmax) atomicMax(&a.seq[b].maxr, rmax);
             if (nreset) atomicAdd(&a.seq[b].resets_pending, nreset);
         }
     }
@@ -1347,6 +1348,21 @@ __global__ void __launch_bounds__(1024) elk_deer_seg_carry_kernel(
         }
         __syncthreads();
         gstart = gs_sh;
+    } else {
+        // the stopping test's max |r| of the sequence from its groups' maxima (see the local
+        // pass: it skips its per-group atomic when this pass runs without freezing)
+        uint32_t m = 0;
+        for (int k = tid; k < G; k += 1024) m = max(m, grmax[g0 + k]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+        if (l == 0) Sb[w][0] = __uint_as_float(m);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t rr = seq[b].maxr;
+            for (int v = 0; v < kDSeg; ++v) rr = max(rr, __float_as_uint(Sb[v][0]));
+            seq[b].maxr = rr;
+        }
+        __syncthreads();
     }
     const int per = (G - gstart + kDSeg - 1) / kDSeg;
     const int lo = gstart + w * per, hi = min(G, lo + per);
@@ -1847,6 +1863,8 @@ pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.grmax = lay.grmax;
     args.ngroups = ngroups;
     args.freeze = o.freeze_prefix ? 1 : 0;
+    // the segmented DEER carry folds the groups' residual maxima when it does not freeze
+    args.fold_rmax = (!kf && !smooth && !args.freeze && elk_deer_segmented(gmax)) ? 1 : 0;
     args.lam = (float)lambda;
     args.res64 = o.fp64_final_residual ? 1 : 0;
     args.diag = o.jac == PN_JAC_DIAG ? 1 : 0;
