@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--rows", action="store_true",
                     help="also measure the other workloads and method variants (adds a 'rows' "
                          "object to the line; a few minutes)")
+    ap.add_argument("--rows-sections", type=int, default=0,
+                    help="with --rows: measure only the first N sections (0 = all); section 2 is "
+                         "the dense tanh D = 32 forward and adjoint")
     ap.add_argument("--graphs", action="store_true",
                     help="also time the step with graph-captured iterations (not the value)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -303,7 +306,7 @@ def main():
         rec["cpu_single_core"] = cpu["single_core"]
         rec["err"] = errors(cpu, s, gp, gx, g0, s_seq)
     if args.rows:
-        rec["rows"] = measure_rows(torch, pn, workloads)
+        rec["rows"] = measure_rows(torch, pn, workloads, args.rows_sections)
     print(json.dumps(rec), flush=True)
 
 
@@ -365,16 +368,33 @@ def _timed(torch, fn, reps=3):
     return float(np.median(ts)), out
 
 
-def measure_rows(torch, pn, workloads):
+class _RowsDone(Exception):
+    pass
+
+
+def measure_rows(torch, pn, workloads, sections=0):
     """The other workloads and method variants: wall time per call, iterations, and the error
     against the sequential GPU rollout of the same FP32 inputs (max |s - s_seq| / max |s_seq|;
     on the chaotic tanh instance two FP32 evaluations differ by ~1e-5, and there the FP64
-    residual below tol is the criterion).  Inputs are seed 0 of each workload."""
+    residual below tol is the criterion).  Inputs are seed 0 of each workload.  `sections` > 0
+    stops after that many sections."""
     rows = {}
+    try:
+        _measure_rows(torch, pn, workloads, sections, rows)
+    except _RowsDone:
+        pass
+    return rows
+
+
+def _measure_rows(torch, pn, workloads, sections, rows):
     dev = "cuda"
+    count = [0]
 
     def done(name):
         print(f"rows: {name} done", file=sys.stderr, flush=True)
+        count[0] += 1
+        if sections and count[0] >= sections:
+            raise _RowsDone()
 
     def tens(inst, dtype=torch.float32):
         return tuple(torch.tensor(v, dtype=dtype, device=dev) for v in (inst.x, inst.s0, inst.params))
