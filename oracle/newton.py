@@ -27,7 +27,8 @@ Delta = 0 entering it (the solve restarts at the first open block, like a sequen
 Frozen states never change again, so their residuals stay below tol.
 
 The iteration count is the number of updates applied; the result is returned as soon as
-the stopping test passes on the current iterate.  By Prop. prop:global_convergence the
+the stopping test passes on the current iterate.  The default cap is T updates with the
+residual rule and T + 1 with the update-norm rule (the loop bound of Alg. alg:deer).  By Prop. prop:global_convergence the
 loop ends within T updates for every choice of A~_t (exact arithmetic).
 """
 import numpy as np
@@ -124,7 +125,13 @@ def newton(cell, x, s0, s_init=None, mode="dense", tol=1e-10, max_iters=None,
     x = np.asarray(x, np.float64)
     T, D = x.shape[0], cell.D
     s = np.zeros((T, D)) if s_init is None else np.array(s_init, np.float64)
-    max_iters = T if max_iters is None else int(max_iters)
+    # Alg. alg:deer runs i = 0..T, an update and then the error test each time: T + 1
+    # updates at most.  With the residual as the error, the exact trajectory (reached after
+    # at most T updates) already passes the test before the last one; with the update norm
+    # the (T+1)-th, zero update is what shows convergence.
+    if max_iters is None:
+        max_iters = T + 1 if stop == "delta" else T
+    max_iters = int(max_iters)
     hist = [s.copy()] if history else None
     norms = []
     resets = 0

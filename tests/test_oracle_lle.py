@@ -64,3 +64,41 @@ def test_meanfield_lle_grows_with_gain():
         out.append(lle.lle_estimate(lle.trajectory_jacobians(cell, x, s0, s),
                                     rng.standard_normal(16)))
     assert out[0] < 0 < out[1], out
+
+
+def test_meanfield_rollout_is_rnncell_in_tanh_coordinates():
+    """Ch. 5 defines the mean-field RNN by s_{t+1} = W tanh(s_t) + u_t (u_t = U x + b here).
+    With h_t = tanh(s_t) the same recurrence reads h_{t+1} = tanh(W h_t + u_t): a tanh RNN,
+    which torch.nn.RNNCell (h' = tanh(x W_ih^T + b_ih + h W_hh^T + b_hh)) evaluates
+    independently of the oracle.  A transposed W, or tanh applied after the coupling (which
+    would make s itself bounded by 1), fails this check."""
+    import torch
+
+    D, Dx, T = 7, 5, 60
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal((D, D)) * 1.3 / np.sqrt(D)
+    np.fill_diagonal(W, 0.0)
+    U = rng.standard_normal((D, Dx))
+    b = 0.2 * rng.standard_normal(D)
+    W[0, 1], W[1, 0] = 0.9, -0.4          # clearly non-symmetric
+    cell = cells.MeanFieldRNN(np.concatenate([W.ravel(), U.ravel(), b]), D, Dx)
+    x = rng.standard_normal((T, Dx))
+    s0 = 1.5 * rng.standard_normal(D)
+    s = rollout.rollout(cell, x, s0)
+    assert np.abs(s).max() > 1.0           # the state is a current, not a bounded rate
+
+    m = torch.nn.RNNCell(Dx, D, nonlinearity="tanh").double()
+    with torch.no_grad():
+        m.weight_hh.copy_(torch.tensor(W))
+        m.weight_ih.copy_(torch.tensor(U))
+        m.bias_ih.copy_(torch.tensor(b))
+        m.bias_hh.zero_()
+        h = torch.tanh(torch.tensor(s0))[None]
+        hs = []
+        for t in range(T):
+            h = m(torch.tensor(x[t])[None], h)
+            hs.append(h[0].numpy().copy())
+    np.testing.assert_allclose(np.tanh(s), np.array(hs), rtol=0, atol=1e-13)
+    # and the state itself: s_t = W h_{t-1} + U x_t + b with the library's h
+    hprev = np.concatenate([np.tanh(s0)[None], np.array(hs)[:-1]])
+    np.testing.assert_allclose(s, hprev @ W.T + x @ U.T + b, rtol=0, atol=1e-13)

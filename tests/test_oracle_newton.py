@@ -252,3 +252,40 @@ def test_damping_end_points(kind):
         a = newton.newton(cell, x, s0, mode=m, tol=1e-14, max_iters=2)["s"]
         b = newton.newton(cell, x, s0, mode=ref, tol=1e-14, max_iters=2)["s"]
         np.testing.assert_array_equal(a, b)
+
+
+def test_worked_doubling_example_update_norm_stop():
+    """stop="delta" (the Ch. 3 rule on the update norm) on the Appendix's doubling example:
+    the updates and the counts are worked by hand in the golden file; the loop must stop on
+    the first zero update, and never on the residual."""
+    g = _gold("worked_doubling.json")
+    cell = _scalar_affine(g["f_scale"])
+    x = np.zeros((2, 1))
+    init = np.array(g["init"])[:, None]
+    for mode, key in [("dense", "deer_updates_delta_stop"),
+                      ("jacobi", "jacobi_updates_delta_stop"),
+                      ("picard", "picard_updates_delta_stop")]:
+        out = newton.newton(cell, x, np.array([g["s0"]]), s_init=init, mode=mode, tol=1e-14,
+                            history=True, reset_abs=np.inf, stop="delta")
+        hist = [h[:, 0] for h in out["history"]]
+        updates = [(b - a).tolist() for a, b in zip(hist[:-1], hist[1:])]
+        assert updates == g[key], (mode, updates)
+        assert out["converged"] and out["iters"] == len(g[key])
+        assert out["s"][:, 0].tolist() == g["true"] and out["max_resid"] == 0.0
+
+
+def test_update_norm_stop_respects_cap_and_agrees_at_convergence():
+    """With the update-norm rule the loop still ends within T + 1 updates (one zero update
+    after the exact trajectory, Prop. global_convergence), and reaches the rollout."""
+    rng = np.random.default_rng(21)
+    T = 20
+    cell = _tanh(rng, 4, 2, g=2.5)
+    x = rng.normal(size=(T, cell.Dx))
+    s0 = rng.normal(size=4)
+    ref = rollout.rollout(cell, x, s0)
+    out = newton.newton(cell, x, s0, mode="jacobi", tol=1e-12, stop="delta", reset_abs=np.inf)
+    assert out["converged"] and out["iters"] <= T + 1
+    np.testing.assert_allclose(out["s"], ref, rtol=0, atol=1e-11)
+    capped = newton.newton(cell, x, s0, mode="jacobi", tol=1e-12, stop="delta",
+                           max_iters=3, reset_abs=np.inf)
+    assert not capped["converged"] and capped["iters"] == 3
