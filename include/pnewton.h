@@ -51,9 +51,9 @@ typedef enum {
     PN_ERR_INVALID_ARG = -1,
     PN_ERR_UNSUPPORTED = -2,     /* valid arguments, combination not built into the library */
     PN_ERR_WORKSPACE = -3,       /* workspace NULL or smaller than pn_workspace_bytes */
-    PN_ERR_NONFINITE_INPUT = -4,
+    PN_ERR_NONFINITE_INPUT = -4, /* opts->check_inputs found a NaN or infinity in an input */
     PN_ERR_HIP = -5,             /* a HIP runtime call failed */
-    PN_ERR_INTERNAL = -6         /* a device-side consistency check failed (e.g. look-back watchdog) */
+    PN_ERR_INTERNAL = -6         /* a host-side consistency check of the library failed (a bug) */
 } pn_status;
 
 typedef enum {
@@ -64,9 +64,18 @@ typedef enum {
                                    [b_z;b_r;b_n] (3D) | b_hn (D)                          */
     PN_CELL_TANH = 1,   /* f = tanh(W h + U x + b).
                            params: W (D x D) | U (D x Dx) | b (D)                         */
-    PN_CELL_MEANFIELD = 2 /* f = W tanh(h) + U x + b: the mean-field RNN of the
+    PN_CELL_MEANFIELD = 2, /* f = W tanh(h) + U x + b: the mean-field RNN of the
                            predictability experiments (Ch. 5), whose state is a current;
                            A = W diag(1 - tanh(h)^2).  params as PN_CELL_TANH           */
+    PN_CELL_AFFINE = 3, /* test cell, a linear dynamical system (Ch. 2, eq. lds):
+                           f = M h + N x + c, so A = M and one DEER update is exact (the
+                           residual's Jacobian is constant).  params: M (D x D) | N (D x Dx) |
+                           c (D)                                                           */
+    PN_CELL_AFFINE_STEPS = 4 /* test cell with a transition matrix per step:
+                           f_t = M_t h + N x_t + c (the input-dependent LDS of the group word
+                           problem, Ch. 6, Prop. cayley: permutation matrices M_t).  params:
+                           M_t of every row in batch order ([N, D, D], M_t of row offsets[b] +
+                           t - 1 for step t of sequence b) | N (D x Dx) | c (D)             */
 } pn_cell;
 
 typedef enum {
@@ -89,6 +98,16 @@ typedef enum {
 } pn_damping;
 
 typedef enum { PN_F32 = 0, PN_F64 = 1 } pn_dtype;
+
+typedef enum {
+    PN_STOP_RESID_INF = 0,  /* stop a sequence when max_t,d |r_t| < tol at the current iterate
+                               (ComputeError of Alg. alg:deer as the residual)             */
+    PN_STOP_DELTA_INF = 1   /* stop when the last update max_t,d |s^(i) - s^(i-1)| < tol (the
+                               update norm of the Ch. 3 GRU experiments); no sequence stops
+                               before its first update, and max_iters <= 0 means T + 1
+                               updates (Alg. alg:deer's loop bound i = 0..T: the zero update
+                               after the exact trajectory is what this rule sees)         */
+} pn_stop;
 
 typedef enum {
     PN_COMPOSE_NATIVE = 0,  /* dense scan products in the solve dtype                      */
@@ -139,6 +158,13 @@ typedef struct {
                                  Used by deer_solve (GRU diagonal, tanh dense) and
                                  deer_adjoint; elk_solve takes its group length as `tile`
                                  and requires 0 here.  pn_autotune measures it.            */
+    int32_t stop;             /* pn_stop (forward solves).  PN_STOP_DELTA_INF is built for
+                                 deer_solve on the GRU diagonal path and the affine cells;
+                                 other routes return PN_ERR_UNSUPPORTED for it             */
+    int32_t check_inputs;     /* 1: before solving, scan x, s0 and params (deer_adjoint also s
+                                 and gs) for NaN / infinity and return PN_ERR_NONFINITE_INPUT
+                                 if any is found (one extra pass over the inputs and a stream
+                                 synchronisation; the workspace grows by 256 bytes)        */
 } pn_opts;
 
 typedef struct {
@@ -156,7 +182,8 @@ typedef struct {
 #define PN_OP_RESIDUAL64 3
 
 /* Fill *opts with defaults: quasi (diag), native compose, tol 1e-5, max_iters = T,
-   graph_iters 4, reset_abs 1e4, graph capture on, tile 0, no damping (k = 0, clip [-1, 1]). */
+   graph_iters 4, reset_abs 1e4, graph capture on, tile 0, no damping (k = 0, clip [-1, 1]),
+   residual stopping rule, no input scan. */
 void pn_default_opts(pn_opts* opts);
 
 /* Bytes of device workspace `op` needs for these shapes (0 is possible).  *bytes is set on
@@ -173,6 +200,8 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
      GRU,  PN_JAC_DENSE, F64, 1 <= D <= 4, 1 <= Dx <= 16, no damping
      TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16, no damping or
            PN_DAMP_SCALE
+     AFFINE, AFFINE_STEPS, any jac, F32, 1 <= D <= 16, 1 <= Dx <= 64, no damping (the test
+           cells: the dense transition is M or M_t itself)
    Anything else returns PN_ERR_UNSUPPORTED. */
 pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                      const void* s0, void* s, const pn_opts* opts, void* workspace,
@@ -246,10 +275,18 @@ pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const
 /* Kernel timing with HIP events, for benchmarking.  Between pn_profile_begin() and
    pn_profile_end() the solvers called on this thread launch their iterations directly (no
    graph) and record a HIP event pair around every launch of their main kernels on the caller's
-   stream; pn_profile_read() returns the summed duration and launch count of a kernel family:
-   "gru_quasi_iter", "gru_adj_iter", "gru_adj_prep", "gru_adj_grad", "tanh_dense_iter",
-   "gru_dense64_solve", "elk_iter", "seq_rollout", "seq_adj".  Returns 0 if the family was
-   not launched. */
+   stream; pn_profile_read() returns the summed duration and launch count of a kernel family
+   (launches of iterations after the one that stopped the last sequence are not counted):
+     deer_solve GRU diagonal: "gru_quasi_local", "carry_scan";
+     deer_adjoint GRU: "gru_adj_prep", "gru_adj_local", "carry_scan", "gru_adj_grad";
+     deer_solve tanh dense: "tanh_dense_local", "dense_carry";
+     deer_adjoint tanh dense: "tanh_adj_prep", "tanh_adj_local", "dense_carry", "tanh_adj_grad";
+     deer_solve GRU FP64: "gru_dense64_solve";
+     elk_solve: "elk_local", "elk_carry", and with the smoother "elk_smooth",
+       "elk_back_carry", "elk_back_apply";
+     deer_solve affine cells: "affine_local", "affine_carry";
+     seq_rollout: "seq_rollout"; seq_bptt: "seq_adj".
+   Returns 0 if the family was not launched since pn_profile_begin(). */
 /* Scan-tile autotuner (batching, "scan tile sizes chosen by a project-written autotuner").
    pn_autotune times op (PN_OP_DEER, PN_OP_ELK or PN_OP_ADJOINT) on the caller's own inputs
    once per candidate (tile, group) -- a warm-up call, then a timed call of probe_iters

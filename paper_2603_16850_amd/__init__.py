@@ -14,10 +14,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpnewton.so")
 
 PN_OK, PN_NOT_CONVERGED = 0, 1
-CELLS = {"gru": 0, "tanh": 1, "meanfield": 2}
+CELLS = {"gru": 0, "tanh": 1, "meanfield": 2, "affine": 3, "affine_steps": 4}
 JACS = {"dense": 0, "diag": 1, "picard": 2, "jacobi": 3}
 DTYPES = {"f32": 0, "f64": 1}
 COMPOSE = {"native": 0, "bf16": 1}
+STOPS = {"resid": 0, "delta": 1}
 OP_DEER, OP_ELK, OP_ADJOINT, OP_RESIDUAL64, OP_SEQ, OP_LLE = 0, 1, 2, 3, 4, 5
 
 
@@ -39,7 +40,8 @@ class Opts(ctypes.Structure):
                 ("damping", ctypes.c_int32), ("damp_k", ctypes.c_float),
                 ("clip_lo", ctypes.c_float), ("clip_hi", ctypes.c_float),
                 ("freeze_prefix", ctypes.c_int32), ("smooth", ctypes.c_int32),
-                ("group", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("stop", ctypes.c_int32),
+                ("check_inputs", ctypes.c_int32)]
 
 
 TUNE_MAX_CAND = 32
@@ -164,9 +166,10 @@ DAMPING = {"none": 0, "scale": 1, "clip": 2}
 def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4,
               reset_abs=1e4, fp64_final_residual=False, use_graph=True, tile=0,
               damping="none", damp_k=0.0, clip=(-1.0, 1.0), freeze_prefix=False,
-              smooth=False, group=0):
+              smooth=False, group=0, stop="resid", check_inputs=False):
     """pn_opts; damping "scale" (scale-ELK, A~ <- (1 - damp_k) A~) or "clip" (clip-ELK,
-    diagonal A~ clipped to `clip`)."""
+    diagonal A~ clipped to `clip`); stop "resid" (max |r| < tol) or "delta" (max update <
+    tol); check_inputs scans the inputs for NaN / infinity first."""
     o = Opts()
     load().pn_default_opts(ctypes.byref(o))
     o.damping = DAMPING[damping]
@@ -184,6 +187,8 @@ def make_opts(jac="diag", compose="native", tol=1e-5, max_iters=0, graph_iters=4
     o.freeze_prefix = int(bool(freeze_prefix))
     o.smooth = int(bool(smooth))
     o.group = int(group)
+    o.stop = STOPS[stop]
+    o.check_inputs = int(bool(check_inputs))
     return o
 
 
@@ -202,9 +207,50 @@ class _Shapes:
                            if self.off is not None else None)
 
 
-def _shapes(cell, params, x, s0, offsets):
+def param_count(cell, D, Dx, N=0):
+    """Packed parameter count of a cell (the per-step affine cell holds N matrices)."""
+    if cell == "gru":
+        return 3 * D * Dx + 3 * D * D + 4 * D
+    if cell == "affine_steps":
+        return N * D * D + D * Dx + D
+    return D * D + D * Dx + D
+
+
+def _shapes(cell, params, x, s0, offsets, rows=()):
+    """Checks every tensor of a call against the shapes the C call will assume (the library
+    sees only pointers, so a mismatch here would become an out-of-bounds access there) and
+    builds its descriptors.  `rows`: further (tensor, name, columns) of shape [N, columns]."""
+    if cell not in CELLS:
+        raise ValueError(f"unknown cell {cell!r}")
+    if x.dim() != 2 or s0.dim() != 2:
+        raise ValueError("x must be [N, Dx] and s0 [B, D]")
     N, Dx = x.shape
     B, D = s0.shape
+    if offsets is not None:
+        off = np.asarray(offsets)
+        if off.ndim != 1 or off.size != B + 1:
+            raise ValueError(f"offsets must hold B + 1 = {B + 1} entries, got {off.size}")
+        if off[0] != 0 or np.any(np.diff(off) < 0):
+            raise ValueError("offsets must start at 0 and be non-decreasing")
+        if int(off[-1]) != N:
+            raise ValueError(f"offsets[-1] = {int(off[-1])} differs from x.shape[0] = {N}")
+    elif B < 1 or N % B:
+        raise ValueError(f"N = {N} steps do not split into B = {B} equal sequences")
+    want = param_count(cell, D, Dx, N)
+    if params.numel() != want:
+        raise ValueError(f"params holds {params.numel()} values; the {cell} cell with D = {D}, "
+                         f"Dx = {Dx} packs {want}")
+    for t, n in ((s0, "s0"), (params, "params")):
+        if t.dtype != x.dtype or t.device != x.device:
+            raise ValueError(f"{n} must have the dtype and device of x")
+    for t, n, cols in rows:
+        if t is None:
+            continue
+        if tuple(t.shape) != (N, cols):
+            raise ValueError(f"{n} must be [{N}, {cols}], got {list(t.shape)}")
+        if t.dtype != x.dtype or t.device != x.device:
+            raise ValueError(f"{n} must have the dtype and device of x")
+        _dev(t, n)
     return _Shapes(cell, params, D, Dx, _dtype_name(x), B, N, offsets)
 
 
@@ -290,7 +336,7 @@ def deer_solve(x, s0, params, cell="gru", offsets=None, s_init=None, **opt_kw):
     torch = _torch()
     for t, n in ((x, "x"), (s0, "s0"), (params, "params")):
         _dev(t, n)
-    sh = _shapes(cell, params, x, s0, offsets)
+    sh = _shapes(cell, params, x, s0, offsets, rows=[(s_init, "s_init", s0.shape[1])])
     opts = make_opts(**_auto_tile("deer", opt_kw, x, s0, params, cell, offsets, s=s_init))
     s = (torch.zeros((x.shape[0], s0.shape[1]), dtype=x.dtype, device=x.device)
          if s_init is None else _dev(s_init, "s_init").clone())
@@ -306,7 +352,7 @@ def elk_solve(x, s0, params, lam, cell="tanh", offsets=None, s_init=None, **opt_
     torch = _torch()
     for t, n in ((x, "x"), (s0, "s0"), (params, "params")):
         _dev(t, n)
-    sh = _shapes(cell, params, x, s0, offsets)
+    sh = _shapes(cell, params, x, s0, offsets, rows=[(s_init, "s_init", s0.shape[1])])
     opt_kw.setdefault("jac", "dense")
     opts = make_opts(**_auto_tile("elk", opt_kw, x, s0, params, cell, offsets, lam=lam,
                                   s=s_init))
@@ -326,7 +372,8 @@ def deer_adjoint(x, s0, params, s, gs, cell="gru", offsets=None, need_gx=True, n
     torch = _torch()
     for t, n in ((x, "x"), (s0, "s0"), (params, "params"), (s, "s"), (gs, "gs")):
         _dev(t, n)
-    sh = _shapes(cell, params, x, s0, offsets)
+    sh = _shapes(cell, params, x, s0, offsets, rows=[(s, "s", s0.shape[1]),
+                                                     (gs, "gs", s0.shape[1])])
     opts = make_opts(**_auto_tile("adjoint", opt_kw, x, s0, params, cell, offsets, s=s, gs=gs))
     gp = torch.empty_like(params)
     gx = torch.empty_like(x) if need_gx else None
@@ -342,6 +389,8 @@ def deer_adjoint(x, s0, params, s, gs, cell="gru", offsets=None, need_gx=True, n
 def seq_rollout(x, s0, params, cell="gru", offsets=None):
     """Sequential GPU baseline of the forward evaluation."""
     torch = _torch()
+    for t, n in ((x, "x"), (s0, "s0"), (params, "params")):
+        _dev(t, n)
     sh = _shapes(cell, params, x, s0, offsets)
     s = torch.empty((x.shape[0], s0.shape[1]), dtype=x.dtype, device=x.device)
     ws, nb = _workspace(OP_SEQ, sh, make_opts(), x.device)
@@ -353,7 +402,10 @@ def seq_rollout(x, s0, params, cell="gru", offsets=None):
 def seq_bptt(x, s0, params, s, gs, cell="gru", offsets=None):
     """Sequential GPU baseline of the backward pass; returns (gparams, gx, gs0)."""
     torch = _torch()
-    sh = _shapes(cell, params, x, s0, offsets)
+    for t, n in ((x, "x"), (s0, "s0"), (params, "params")):
+        _dev(t, n)
+    sh = _shapes(cell, params, x, s0, offsets, rows=[(s, "s", s0.shape[1]),
+                                                     (gs, "gs", s0.shape[1])])
     gp = torch.empty_like(params)
     gx = torch.empty_like(x)
     g0 = torch.empty_like(s0)
@@ -388,7 +440,9 @@ def lle_estimate(x, s0, params, s, u0, cell="meanfield", offsets=None):
     """Largest Lyapunov exponent along the trajectory s per sequence (list of floats)."""
     for t, n in ((x, "x"), (s0, "s0"), (params, "params"), (s, "s"), (u0, "u0")):
         _dev(t, n)
-    sh = _shapes(cell, params, x, s0, offsets)
+    sh = _shapes(cell, params, x, s0, offsets, rows=[(s, "s", s0.shape[1])])
+    if tuple(u0.shape) != tuple(s0.shape) or u0.dtype != x.dtype:
+        raise ValueError(f"u0 must be [B, D] = {list(s0.shape)} of the dtype of x")
     ws, nb = _workspace(OP_LLE, sh, make_opts(), x.device)
     out = (ctypes.c_double * sh.batch.B)()
     _check(load().pn_lle_estimate(ctypes.byref(sh.cell), ctypes.byref(sh.batch), _ptr(x),
@@ -397,7 +451,9 @@ def lle_estimate(x, s0, params, s, u0, cell="meanfield", offsets=None):
 
 
 def residual_f64(x, s0, params, s, cell="tanh", offsets=None):
-    sh = _shapes(cell, params, x, s0, offsets)
+    for t, n in ((x, "x"), (s0, "s0"), (params, "params"), (s, "s")):
+        _dev(t, n)
+    sh = _shapes(cell, params, x, s0, offsets, rows=[(s, "s", s0.shape[1])])
     opts = make_opts()
     ws, nb = _workspace(OP_RESIDUAL64, sh, opts, x.device)
     out = (ctypes.c_double * sh.batch.B)()

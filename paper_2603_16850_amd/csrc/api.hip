@@ -8,7 +8,7 @@
 using namespace pn;
 
 // layouts the Python binding mirrors with ctypes
-static_assert(sizeof(pn_opts) == 72, "pn_opts layout");
+static_assert(sizeof(pn_opts) == 80, "pn_opts layout");
 static_assert(sizeof(pn_cell_desc) == 24 && sizeof(pn_batch) == 24 && sizeof(pn_seq_info) == 24,
               "struct layouts");
 
@@ -26,8 +26,7 @@ pn_opts resolve_opts(const pn_opts* o) {
 
 pn_status check_cell(const pn_cell_desc* cell) {
     if (!cell) { set_error("cell descriptor is NULL"); return PN_ERR_INVALID_ARG; }
-    if (cell->cell != PN_CELL_GRU && cell->cell != PN_CELL_TANH &&
-        cell->cell != PN_CELL_MEANFIELD) {
+    if (cell->cell < PN_CELL_GRU || cell->cell > PN_CELL_AFFINE_STEPS) {
         set_error("unknown cell kind %d", cell->cell);
         return PN_ERR_INVALID_ARG;
     }
@@ -94,6 +93,14 @@ pn_status check_opts(const pn_opts& o) {
         set_error("smooth must be 0 or 1");
         return PN_ERR_INVALID_ARG;
     }
+    if (o.stop != PN_STOP_RESID_INF && o.stop != PN_STOP_DELTA_INF) {
+        set_error("unknown stop rule %d", o.stop);
+        return PN_ERR_INVALID_ARG;
+    }
+    if (o.check_inputs != 0 && o.check_inputs != 1) {
+        set_error("check_inputs must be 0 or 1");
+        return PN_ERR_INVALID_ARG;
+    }
     if (o.damping < PN_DAMP_NONE || o.damping > PN_DAMP_CLIP) {
         set_error("unknown damping %d", o.damping);
         return PN_ERR_INVALID_ARG;
@@ -141,9 +148,27 @@ pn_status check_ws(void* ws, size_t have, size_t need) {
 }
 
 // Which solver serves a deer_solve call.
-enum class Route { None, GruQuasi, GruDense64, TanhDense, Elk };
+enum class Route { None, GruQuasi, GruDense64, TanhDense, Elk, Affine };
+
+bool affine_cell(int cell) { return cell == PN_CELL_AFFINE || cell == PN_CELL_AFFINE_STEPS; }
+
+// Number of packed parameters of a cell (the affine cell with per-step matrices holds N of them).
+int64_t param_count(const pn_cell_desc& c, int64_t N) {
+    const int64_t D = c.D, Dx = c.Dx;
+    switch (c.cell) {
+        case PN_CELL_GRU: return 3 * D * Dx + 3 * D * D + 4 * D;
+        case PN_CELL_AFFINE_STEPS: return N * D * D + D * Dx + D;
+        default: return D * D + D * Dx + D;
+    }
+}
+
+// Bytes the input scan adds at the end of a workspace.
+constexpr size_t kCheckBytes = 256;
 
 Route route_deer(const pn_cell_desc& c, const pn_opts& o) {
+    if (affine_cell(c.cell) && c.dtype == PN_F32 && o.compose == PN_COMPOSE_NATIVE &&
+        o.damping == PN_DAMP_NONE && affine_supported(c.D, c.Dx))
+        return Route::Affine;
     if (c.cell == PN_CELL_GRU && c.dtype == PN_F32 && o.compose == PN_COMPOSE_NATIVE &&
         (o.jac == PN_JAC_DIAG || o.jac == PN_JAC_PICARD || o.jac == PN_JAC_JACOBI) &&
         gru_quasi_supported(c.D, c.Dx))
@@ -226,12 +251,20 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
     const pn_opts o = resolve_opts(opts);
     PN_TRY(check_opts(o));
     if (op & PN_OP_TUNE) return autotune_workspace(op & ~PN_OP_TUNE, *cell, *batch, hb, o, bytes);
+    if (o.check_inputs && (op == PN_OP_DEER || op == PN_OP_ELK || op == PN_OP_ADJOINT)) {
+        pn_opts plain = o;
+        plain.check_inputs = 0;
+        PN_TRY(pn_workspace_bytes(op, cell, batch, &plain, bytes));
+        *bytes = ((*bytes + 255) & ~size_t(255)) + kCheckBytes;
+        return PN_OK;
+    }
     switch (op) {
         case PN_OP_DEER:
             switch (route_deer(*cell, o)) {
                 case Route::GruQuasi: *bytes = gru_quasi_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 case Route::GruDense64: *bytes = gru_dense64_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 case Route::TanhDense: *bytes = tanh_dense_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
+                case Route::Affine: *bytes = affine_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 default: break;
             }
             break;
@@ -286,19 +319,38 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
     PN_TRY(check_opts(o));
     PN_TRY(check_ptrs({x, s0, s, cell->params}, hb));
     const Route r = route_deer(*cell, o);
-    if (o.freeze_prefix || o.smooth) {
-        set_error("converged-prefix skipping and the smoother are built for elk_solve only");
-        return PN_ERR_UNSUPPORTED;
-    }
     if (r == Route::None) {
         set_error("deer_solve not built for cell=%d D=%d Dx=%d dtype=%d jac=%d compose=%d",
                   cell->cell, cell->D, cell->Dx, cell->dtype, o.jac, o.compose);
+        return PN_ERR_UNSUPPORTED;
+    }
+    if (o.smooth) {
+        set_error("the smoother is built for elk_solve only");
+        return PN_ERR_UNSUPPORTED;
+    }
+    if (o.freeze_prefix && r != Route::GruQuasi) {
+        set_error("deer_solve skips converged prefixes on the GRU diagonal path only");
+        return PN_ERR_UNSUPPORTED;
+    }
+    if (o.stop == PN_STOP_DELTA_INF && r != Route::GruQuasi && r != Route::Affine) {
+        set_error("the update-norm stopping rule is built for the GRU diagonal path and the "
+                  "affine cells");
+        return PN_ERR_UNSUPPORTED;
+    }
+    if (o.stop == PN_STOP_DELTA_INF && o.freeze_prefix) {
+        set_error("converged-prefix skipping decides on residuals: use PN_STOP_RESID_INF");
         return PN_ERR_UNSUPPORTED;
     }
     size_t need = 0;
     PN_TRY(pn_workspace_bytes(PN_OP_DEER, cell, batch, &o, &need));
     PN_TRY(check_ws(workspace, workspace_bytes, need));
     hipStream_t st = (hipStream_t)stream;
+    if (o.check_inputs) {
+        const int64_t P = param_count(*cell, hb.N);
+        PN_TRY(check_finite({{x, hb.N * cell->Dx}, {s0, (int64_t)hb.B * cell->D},
+                             {cell->params, P}},
+                            cell->dtype, (int*)((char*)workspace + need - kCheckBytes), st));
+    }
     bool conv = true;
     switch (r) {
         case Route::GruQuasi:
@@ -312,6 +364,10 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
         case Route::TanhDense:
             PN_TRY(tanh_dense_forward(*cell, hb, (const float*)x, (const float*)s0, (float*)s, o,
                                       workspace, st, info, &conv));
+            break;
+        case Route::Affine:
+            PN_TRY(affine_forward(*cell, hb, (const float*)x, (const float*)s0, (float*)s, o,
+                                  workspace, st, info, &conv));
             break;
         default:
             return PN_ERR_INTERNAL;
@@ -341,6 +397,10 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
         set_error("the smoother does not combine with converged-prefix skipping");
         return PN_ERR_UNSUPPORTED;
     }
+    if (o.stop != PN_STOP_RESID_INF) {
+        set_error("elk_solve stops on the residual (PN_STOP_RESID_INF)");
+        return PN_ERR_UNSUPPORTED;
+    }
     if (o.group != 0) {
         set_error("elk_solve takes its group length as tile (group must be 0)");
         return PN_ERR_INVALID_ARG;
@@ -359,6 +419,11 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
     size_t need = 0;
     PN_TRY(pn_workspace_bytes(PN_OP_ELK, cell, batch, &o, &need));
     PN_TRY(check_ws(workspace, workspace_bytes, need));
+    if (o.check_inputs)
+        PN_TRY(check_finite({{x, hb.N * cell->Dx}, {s0, (int64_t)hb.B * cell->D},
+                             {cell->params, param_count(*cell, hb.N)}},
+                            cell->dtype, (int*)((char*)workspace + need - kCheckBytes),
+                            (hipStream_t)stream));
     bool conv = true;
     PN_TRY(elk_forward(*cell, hb, (const float*)x, (const float*)s0, (float*)s, lambda, o,
                        workspace, (hipStream_t)stream, info, &conv));
@@ -380,19 +445,33 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
         set_error("gradient arrays must be 16-byte aligned");
         return PN_ERR_INVALID_ARG;
     }
-    if (o.freeze_prefix || o.smooth) {
-        set_error("converged-prefix skipping and the smoother are built for elk_solve only");
-        return PN_ERR_UNSUPPORTED;
-    }
     const Route r = route_adjoint(*cell, o);
     if (r == Route::None) {
         set_error("deer_adjoint not built for cell=%d D=%d Dx=%d dtype=%d jac=%d damping=%d",
                   cell->cell, cell->D, cell->Dx, cell->dtype, o.jac, o.damping);
         return PN_ERR_UNSUPPORTED;
     }
+    if (o.smooth) {
+        set_error("the smoother is built for elk_solve only");
+        return PN_ERR_UNSUPPORTED;
+    }
+    if (o.freeze_prefix && r != Route::GruQuasi) {
+        set_error("deer_adjoint skips converged prefixes on the GRU diagonal path only");
+        return PN_ERR_UNSUPPORTED;
+    }
+    if (o.stop != PN_STOP_RESID_INF) {
+        set_error("deer_adjoint stops on its residual (PN_STOP_RESID_INF)");
+        return PN_ERR_UNSUPPORTED;
+    }
     size_t need = 0;
     PN_TRY(pn_workspace_bytes(PN_OP_ADJOINT, cell, batch, &o, &need));
     PN_TRY(check_ws(workspace, workspace_bytes, need));
+    if (o.check_inputs)
+        PN_TRY(check_finite({{x, hb.N * cell->Dx}, {s0, (int64_t)hb.B * cell->D},
+                             {s, hb.N * cell->D}, {gs, hb.N * cell->D},
+                             {cell->params, param_count(*cell, hb.N)}},
+                            cell->dtype, (int*)((char*)workspace + need - kCheckBytes),
+                            (hipStream_t)stream));
     bool conv = true;
     if (r == Route::GruQuasi)
         PN_TRY(gru_adjoint(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,

@@ -13,8 +13,10 @@
 namespace pn {
 
 // Scan of the group maps, one wave per (sequence, 4 units).  Sequences whose status is not
-// active are skipped; nothing runs when ctrl->all_done is set.
+// active are skipped; nothing runs when ctrl->all_done is set.  With grmax ([ngroups][nw]
+// residual maxima of the groups' waves, float bits) the sequence's converged prefix of groups
+// is frozen (SeqState::frozen) and the scan restarts after it.
 void launch_carry_scan(const float2* agg, float* carry, const IterState& st, int B, int D,
-                       hipStream_t stream);
+                       hipStream_t stream, const uint32_t* grmax = nullptr, int nw = 0);
 
 }  // namespace pn

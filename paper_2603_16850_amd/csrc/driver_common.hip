@@ -2,9 +2,11 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 
 #include "pn_host.hpp"
+#include "pn_solvers.hpp"
 
 namespace pn {
 
@@ -139,7 +141,6 @@ void carve_iter_state(Carver& c, IterState& st, int B, int ntiles, int ngroups) 
     st.seq = c.take<SeqState>(B);
     st.offsets = c.take<int64_t>(B + 1);
     st.tile_start = c.take<int32_t>(B + 1);
-    st.order = c.take<int32_t>(std::max(ntiles, 1));
     st.tiles = c.take<TileInfo>(std::max(ntiles, 1));
     st.groups = c.take<GroupInfo>(std::max(ngroups, 1));
     st.group_start = c.take<int32_t>(B + 1);
@@ -153,7 +154,7 @@ int count_groups(const std::vector<int32_t>& tstart, int B, int gt) {
 }
 
 __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offsets, int B,
-                                  int max_iters, float tol, float reset_abs) {
+                                  int max_iters, float tol, float reset_abs, int stop_delta) {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
         SeqState q;
         const bool empty = offsets[b + 1] == offsets[b];
@@ -166,19 +167,18 @@ __global__ void init_state_kernel(Ctrl* ctrl, SeqState* seq, const int64_t* offs
         q.final_resid = 0.0f;
         q.frozen = 0;
         q.frozen_prev = 0;
-        q.pad_ = 0;
+        q.maxd = 0;
         seq[b] = q;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Ctrl c;
         c.iter = 0;
         c.all_done = 0;
-        c.tile_counter = 0;
-        c.error = 0;
         c.max_iters = max_iters;
         c.tol = tol;
         c.reset_abs = reset_abs;
         c.done_iter = -1;
+        c.stop_delta = stop_delta;
         *ctrl = c;
     }
 }
@@ -207,15 +207,13 @@ void* pinned_staging(int which, size_t bytes) {
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
                           const std::vector<int32_t>& tstart, int L, bool reverse,
                           int max_iters, float tol, float reset_abs, hipStream_t stream,
-                          int gt) {
+                          int gt, int stop) {
     // the tables are built on the host and sent in one copy of the span they occupy in the
-    // workspace (offsets, tile_start, order, tiles, groups, group_start, carved in this order)
-    static thread_local std::vector<int32_t> order;
+    // workspace (offsets, tile_start, tiles, groups, group_start, carved in this order)
     static thread_local std::vector<TileInfo> tiles;
     static thread_local std::vector<GroupInfo> groups;
     static thread_local std::vector<int32_t> gstart;
     const int ntiles = tstart[hb.B];
-    order.clear();
     tiles.assign(ntiles, TileInfo{});
     groups.clear();
     gstart.assign(hb.B + 1, 0);
@@ -237,12 +235,6 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
         for (int k = 0; k < nt; k += g)
             groups.push_back(GroupInfo{b, tstart[b] + k, std::min(g, nt - k), gstart[b]});
     }
-    // interleaved processing order for the look-back scans
-    int maxt = 0;
-    for (int b = 0; b < hb.B; ++b) maxt = std::max(maxt, tstart[b + 1] - tstart[b]);
-    for (int k = 0; k < maxt; ++k)
-        for (int b = 0; b < hb.B; ++b)
-            if (k < tstart[b + 1] - tstart[b]) order.push_back(tstart[b] + k);
     if (gt > 0 && (int)groups.size() != st.ngroups) {
         set_error("internal: group table size %d, carved %d", (int)groups.size(), st.ngroups);
         return PN_ERR_INTERNAL;
@@ -259,7 +251,6 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
     };
     put(st.offsets, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1));
     put(st.tile_start, tstart.data(), sizeof(int32_t) * (hb.B + 1));
-    put(st.order, order.data(), sizeof(int32_t) * order.size());
     put(st.tiles, tiles.data(), sizeof(TileInfo) * tiles.size());
     if (gt > 0) {
         put(st.groups, groups.data(), sizeof(GroupInfo) * groups.size());
@@ -268,8 +259,54 @@ pn_status init_iter_state(const IterState& st, const HostBatch& hb,
     PN_HIP(hipMemcpyAsync(d0, h, span, hipMemcpyHostToDevice, stream));
     int blocks = std::min(64, (hb.B + 255) / 256);
     hipLaunchKernelGGL(init_state_kernel, dim3(std::max(1, blocks)), dim3(256), 0, stream,
-                       st.ctrl, st.seq, st.offsets, hb.B, max_iters, tol, reset_abs);
+                       st.ctrl, st.seq, st.offsets, hb.B, max_iters, tol, reset_abs,
+                       stop == PN_STOP_DELTA_INF ? 1 : 0);
     PN_HIP(hipGetLastError());
+    return PN_OK;
+}
+
+// ---- input scan for non-finite values (opts->check_inputs) ---------------------------------
+// flag |= 1 if any element of p[0 .. n) is NaN or infinite.  Grid-stride, one write per wave
+// that finds one.
+template <class T>
+__global__ void nonfinite_kernel(const T* __restrict__ p, int64_t n, int* flag) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(p[i]);
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+__global__ void clear_flag_kernel(int* flag) { *flag = 0; }
+
+pn_status check_finite(std::initializer_list<std::pair<const void*, int64_t>> arrays, int dtype,
+                       int* flag_dev, hipStream_t stream) {
+    static thread_local int* hflag = nullptr;
+    if (!hflag && hipHostMalloc((void**)&hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        hflag = nullptr;
+        set_error("hipHostMalloc of the input-check flag failed");
+        return PN_ERR_HIP;
+    }
+    // cleared by a kernel rather than a memset node, so the check stays capturable
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, stream, flag_dev);
+    for (const auto& a : arrays) {
+        if (!a.first || a.second <= 0) continue;
+        const int64_t n = a.second;
+        const int blocks = (int)std::min<int64_t>(2048, (n + 255) / 256);
+        if (dtype == PN_F64)
+            hipLaunchKernelGGL(nonfinite_kernel<double>, dim3(blocks), dim3(256), 0, stream,
+                               (const double*)a.first, n, flag_dev);
+        else
+            hipLaunchKernelGGL(nonfinite_kernel<float>, dim3(blocks), dim3(256), 0, stream,
+                               (const float*)a.first, n, flag_dev);
+    }
+    PN_HIP(hipGetLastError());
+    PN_HIP(hipMemcpyAsync(hflag, flag_dev, sizeof(int), hipMemcpyDeviceToHost, stream));
+    PN_HIP(hipStreamSynchronize(stream));
+    if (*hflag) {
+        set_error("an input holds a NaN or an infinity");
+        return PN_ERR_NONFINITE_INPUT;
+    }
     return PN_OK;
 }
 
@@ -303,7 +340,9 @@ void launch_partial_sum(const float* part, int nparts, int P, float* out, hipStr
                        nparts, P, out);
 }
 
-// One workgroup: apply the stopping test of iteration k to every active sequence.
+// One workgroup: apply the stopping test of iteration k to every active sequence.  The tested
+// quantity is the residual max of the iterate s^(k), or with the update-norm rule the max of
+// the update that formed it (never passed at k = 0, before any update).
 // resets_pending counts the rows reset while this iteration produced an iterate: the next
 // iterate s^(k+1) (kept only if the sequence goes on), or with `pending_current` the iterate
 // s^(k) just tested (always kept).
@@ -312,14 +351,16 @@ __global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B, int pending_curr
     const int k = ctrl->iter;
     const float tol = ctrl->tol;
     const int cap = ctrl->max_iters;
+    const bool by_delta = ctrl->stop_delta != 0;
     if (threadIdx.x == 0) any_active = 0;
     __syncthreads();
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
         SeqState q = seq[b];
         if (q.status == kActive) {
             const float m = __uint_as_float(q.maxr);
-            if (m < tol || k >= cap) {
-                q.status = (m < tol) ? kConverged : kCapped;
+            const bool pass = by_delta ? (k > 0 && __uint_as_float(q.maxd) < tol) : (m < tol);
+            if (pass || k >= cap) {
+                q.status = pass ? kConverged : kCapped;
                 q.iters = k;
                 q.parity = k & 1;
                 q.final_resid = m;
@@ -329,6 +370,7 @@ __global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B, int pending_curr
                 any_active = 1;
             }
             q.maxr = 0;
+            q.maxd = 0;
             q.resets_pending = 0;
             seq[b] = q;
         }
@@ -337,7 +379,6 @@ __global__ void decide_kernel(Ctrl* ctrl, SeqState* seq, int B, int pending_curr
     if (threadIdx.x == 0) {
         if (!any_active && !ctrl->all_done) ctrl->done_iter = k;
         ctrl->iter = k + 1;
-        ctrl->tile_counter = 0;
         ctrl->all_done = any_active ? 0 : 1;
     }
 }
@@ -350,11 +391,31 @@ void launch_decide(const IterState& st, int B, hipStream_t stream, bool pending_
 // ---- iteration loop with optional graph capture -------------------------------------------
 
 namespace {
+// Instantiated graphs of `n` iterations, kept per key (solver, kernels, buffers, shapes) so
+// that later calls on the same buffers skip instantiation.  A call always captures its own
+// iterations first and brings the cached executable up to date with hipGraphExecUpdate, so
+// the kernels run with exactly the arguments of this call (plan values and workspace offsets
+// that move with the shapes included) whether or not the key says everything; a capture whose
+// node structure differs (another plan) is instantiated afresh.  Executables are shared
+// pointers: an entry evicted from the cache is destroyed only after the last call holding it
+// has synchronised its stream and let go of it.
+struct ExecHolder {
+    hipGraphExec_t exec = nullptr;
+    ~ExecHolder() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+using ExecPtr = std::shared_ptr<ExecHolder>;
+struct CacheEntry {
+    ExecPtr exec;
+    uint64_t last_use = 0;
+};
 struct GraphCache {
     std::mutex mu;
-    std::map<std::vector<uintptr_t>, hipGraphExec_t> execs;
-    hipStream_t capture_stream = nullptr;
+    std::map<std::vector<uintptr_t>, CacheEntry> execs;
+    uint64_t tick = 0;
 };
+constexpr size_t kGraphCacheMax = 64;
 GraphCache& graph_cache() {
     static GraphCache* c = new GraphCache();   // lives until process exit
     return *c;
@@ -367,6 +428,56 @@ struct PinnedCtrl {
 Ctrl* pinned_ctrl() {
     static thread_local PinnedCtrl pc;
     return pc.p;
+}
+
+// Captures n iterations on this thread's capture stream.
+pn_status capture_iterations(int n, const std::function<void(hipStream_t)>& one_iter,
+                             hipGraph_t* graph) {
+    static thread_local hipStream_t cs = nullptr;
+    if (!cs) PN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    PN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < n; ++i) one_iter(cs);
+    PN_HIP(hipStreamEndCapture(cs, graph));
+    return PN_OK;
+}
+
+// The executable for this call's captured graph: the cached one of `key` updated to it, or a
+// new instantiation (then cached, evicting the least recently used entries beyond the limit).
+pn_status exec_for(const std::vector<uintptr_t>& key, hipGraph_t graph, ExecPtr* out) {
+    GraphCache& gc = graph_cache();
+    ExecPtr cand;
+    {
+        std::lock_guard<std::mutex> lock(gc.mu);
+        auto it = gc.execs.find(key);
+        if (it != gc.execs.end()) {
+            cand = it->second.exec;
+            it->second.last_use = ++gc.tick;
+        }
+    }
+    if (cand) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(cand->exec, graph, &err_node, &res) == hipSuccess &&
+            res == hipGraphExecUpdateSuccess) {
+            *out = cand;
+            return PN_OK;
+        }
+        (void)hipGetLastError();       // a failed update is not an error of the call
+    }
+    auto fresh = std::make_shared<ExecHolder>();
+    PN_HIP(hipGraphInstantiate(&fresh->exec, graph, nullptr, nullptr, 0));
+    {
+        std::lock_guard<std::mutex> lock(gc.mu);
+        gc.execs[key] = CacheEntry{fresh, ++gc.tick};
+        while (gc.execs.size() > kGraphCacheMax) {
+            auto oldest = gc.execs.begin();
+            for (auto it = gc.execs.begin(); it != gc.execs.end(); ++it)
+                if (it->second.last_use < oldest->second.last_use) oldest = it;
+            gc.execs.erase(oldest);    // destroyed when its last holder lets go
+        }
+    }
+    *out = fresh;
+    return PN_OK;
 }
 }  // namespace
 
@@ -381,38 +492,23 @@ pn_status run_iterations(const IterState& st, int max_launches, int graph_iters,
     }
     graph_iters = std::max(1, graph_iters);
     int launched = 0;
+    ExecPtr exec;       // this call's executable, held until the call returns
     while (launched < max_launches) {
         const int n = std::min(graph_iters, max_launches - launched);
         if (use_graph && n == graph_iters && !profiling()) {
-            hipGraphExec_t exec = nullptr;
-            {
-                GraphCache& gc = graph_cache();
-                std::lock_guard<std::mutex> lock(gc.mu);
+            if (!exec) {
                 int dev = 0;
                 PN_HIP(hipGetDevice(&dev));
                 std::vector<uintptr_t> key = graph_key;
                 key.push_back((uintptr_t)n);
                 key.push_back((uintptr_t)dev);
-                auto it = gc.execs.find(key);
-                if (it != gc.execs.end()) {
-                    exec = it->second;
-                } else {
-                    if (!gc.capture_stream)
-                        PN_HIP(hipStreamCreateWithFlags(&gc.capture_stream, hipStreamNonBlocking));
-                    hipGraph_t graph;
-                    PN_HIP(hipStreamBeginCapture(gc.capture_stream, hipStreamCaptureModeThreadLocal));
-                    for (int i = 0; i < n; ++i) one_iter(gc.capture_stream);
-                    PN_HIP(hipStreamEndCapture(gc.capture_stream, &graph));
-                    PN_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-                    PN_HIP(hipGraphDestroy(graph));
-                    if (gc.execs.size() > 64) {
-                        for (auto& kv : gc.execs) (void)hipGraphExecDestroy(kv.second);
-                        gc.execs.clear();
-                    }
-                    gc.execs[key] = exec;
-                }
+                hipGraph_t graph = nullptr;
+                PN_TRY(capture_iterations(n, one_iter, &graph));
+                const pn_status r = exec_for(key, graph, &exec);
+                (void)hipGraphDestroy(graph);
+                PN_TRY(r);
             }
-            PN_HIP(hipGraphLaunch(exec, stream));
+            PN_HIP(hipGraphLaunch(exec->exec, stream));
         } else {
             for (int i = 0; i < n; ++i) {
                 prof().cur_iter = launched + i;
@@ -425,7 +521,7 @@ pn_status run_iterations(const IterState& st, int max_launches, int graph_iters,
         PN_HIP(hipMemcpyAsync(hc, st.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
         PN_HIP(hipStreamSynchronize(stream));
         if (hc->all_done && profiling()) prof_drop_after(hc->done_iter);
-        if (hc->all_done || hc->error) break;
+        if (hc->all_done) break;
     }
     return PN_OK;
 }
@@ -443,7 +539,7 @@ __global__ void copy_odd_parity_kernel(const SeqState* seq, const int64_t* offse
 
 pn_status finish_iterations(const IterState& st, const HostBatch& hb, int D, size_t elem,
                             void* s_user, const void* s_alt, hipStream_t stream,
-                            pn_seq_info* info, bool* all_converged, int* device_error) {
+                            pn_seq_info* info, bool* all_converged) {
     if (s_alt) {
         const int64_t per = hb.Tmax * D;
         int gx = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (per + 255) / 256));
@@ -481,7 +577,6 @@ pn_status finish_iterations(const IterState& st, const HostBatch& hb, int D, siz
         }
     }
     *all_converged = allc;
-    *device_error = hc.error;
     prof_collect();
     return PN_OK;
 }

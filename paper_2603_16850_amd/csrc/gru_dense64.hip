@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(1024) gru_dense64_kernel(Dense64Args a) {
         q.final_resid = (float)final_r;
         q.frozen = 0;
         q.frozen_prev = 0;
-        q.pad_ = 0;
+        q.maxd = 0;
         a.seq[b] = q;
     }
 }

@@ -28,6 +28,7 @@
 #include "carry.hpp"
 #include "gru_common.hpp"
 #include "pn_host.hpp"
+#include "pn_solvers.hpp"
 
 namespace pn {
 
@@ -67,6 +68,9 @@ struct GruQArgs {
     const TileInfo* tiles;   // by slot
     const GroupInfo* groups; // by group slot
     int ngroups;
+    uint32_t* grmax;         // [ngroups][D / 16] residual max of each group's waves (bits),
+                             // written with converged-prefix skipping
+    int freeze;              // converged-prefix skipping on
     int mode;                // transition matrix: kTransDiag, kTransIdentity or kTransZero
     float dscale;            // scale damping: A~ <- dscale A~ (1 - k; 1 without damping)
     int clip;                // clip damping on: A~ <- min(max(A~, clo), chi)
@@ -88,6 +92,7 @@ gru_quasi_local_kernel(GruQArgs a) {
     const int k = a.ctrl->iter;
     const bool fuse = k > 0;
     const float reset_abs = a.ctrl->reset_abs;
+    const bool bydelta = a.ctrl->stop_delta != 0;
     const float* __restrict__ sprev = a.sbuf[(k + 1) & 1];   // s^(k-1)
     float* __restrict__ scur = a.sbuf[k & 1];                 // s^(k)
     const float2* __restrict__ lacp = a.lac[(k + 1) & 1];
@@ -108,6 +113,23 @@ gru_quasi_local_kernel(GruQArgs a) {
         const GroupInfo gr = a.groups[gi];
         if (a.seq[gr.b].status != kActive) continue;     // same on every thread
         const int b = gr.b;
+        // converged-prefix skipping: the sequence's leading groups [0, frozen) take no more
+        // updates; one frozen by the last carry pass gets s^(k) = s^(k-1) on its rows once
+        // (both iterate buffers then hold them) and is skipped from then on
+        bool halo_frozen = false;
+        if (a.freeze) {
+            const int li = gi - gr.gfirst, nf = a.seq[b].frozen;
+            if (li < nf) {
+                if (li >= a.seq[b].frozen_prev) {
+                    const TileInfo t0 = a.tiles[gr.tile0], t1 = a.tiles[gr.tile0 + gr.ntl - 1];
+                    const int64_t e0 = t0.row0 * (D / 4), e1 = (t1.row0 + t1.len) * (D / 4);
+                    for (int64_t e = e0 + tid; e < e1; e += C::NT)
+                        ((float4*)scur)[e] = ((const float4*)sprev)[e];
+                }
+                continue;
+            }
+            halo_frozen = li == nf && nf > 0;    // the row before the group does not move
+        }
         float Pa = 1.f, Pc = 0.f;        // map of the group's tiles before the current one
         uint32_t rmax = 0;
         TileInfo tnext = a.tiles[gr.tile0];
@@ -176,12 +198,20 @@ gru_quasi_local_kernel(GruQArgs a) {
                         if (idx < (L + 1) * Q) {
                             const int r = idx / Q;
                             float4 w4 = v[q];
-                            if (fuse && !(r == 0 && first)) {
+                            if (fuse && !(r == 0 && (first || (kt == 0 && halo_frozen)))) {
                                 const float4 cv = r == 0 ? chalo : cown;
-                                w4.x += p0[q].x * cv.x + p0[q].y;
-                                w4.y += p0[q].z * cv.y + p0[q].w;
-                                w4.z += p1[q].x * cv.z + p1[q].y;
-                                w4.w += p1[q].z * cv.w + p1[q].w;
+                                const float d0 = p0[q].x * cv.x + p0[q].y;
+                                const float d1 = p0[q].z * cv.y + p0[q].w;
+                                const float d2 = p1[q].x * cv.z + p1[q].y;
+                                const float d3 = p1[q].z * cv.w + p1[q].w;
+                                w4.x += d0;
+                                w4.y += d1;
+                                w4.z += d2;
+                                w4.w += d3;
+                                // update norm of the group's own rows (row 0 is the halo)
+                                if (bydelta && r > 0)
+                                    rmax = max(rmax, max(max(absbits(d0), absbits(d1)),
+                                                         max(absbits(d2), absbits(d3))));
                                 if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
                                     !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
                                     rowbad[r] = 1;
@@ -246,7 +276,7 @@ gru_quasi_local_kernel(GruQArgs a) {
                     if (first && tl == 0) dg = 0.f;
                     la[mb][i] = valid ? dg : 1.f;
                     lc[mb][i] = valid ? -res : 0.f;
-                    if (valid) rmax = max(rmax, absbits(res));
+                    if (valid && !bydelta) rmax = max(rmax, absbits(res));
                 }
             }
 
@@ -300,10 +330,14 @@ gru_quasi_local_kernel(GruQArgs a) {
                 }
         }
         if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
-        // residual max of the current iterate over the group, one atomic per wave
+        // residual max of the current iterate over the group (with the update-norm rule the
+        // max of the update that formed it), one atomic per wave
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
-        if (l == 0) atomicMax(&a.seq[b].maxr, rmax);
+        if (l == 0) {
+            atomicMax(bydelta ? &a.seq[b].maxd : &a.seq[b].maxr, rmax);
+            if (a.freeze) a.grmax[(size_t)gi * C::NW + w] = rmax;
+        }
     }
 }
 
@@ -315,10 +349,13 @@ struct GruQLayout {
     float2* lac[2];
     float2* gagg;
     float* gcarry;
+    uint32_t* grmax;    // converged-prefix skipping: [ngroups][D / 16]
+    void* r64;          // update-norm rule: the FP64 residual of the result
     size_t bytes;
 };
 
-static GruQLayout gruq_layout(void* ws, int D, const HostBatch& hb, int ntiles, int ngroups) {
+static GruQLayout gruq_layout(void* ws, int D, int Dx, const HostBatch& hb, int ntiles,
+                              int ngroups, const pn_opts& o) {
     Carver c(ws);
     GruQLayout lay;
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
@@ -326,6 +363,10 @@ static GruQLayout gruq_layout(void* ws, int D, const HostBatch& hb, int ntiles, 
     for (int p = 0; p < 2; ++p) lay.lac[p] = c.take<float2>((size_t)hb.N * D);
     lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
     lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
+    lay.grmax = o.freeze_prefix ? c.take<uint32_t>((size_t)std::max(ngroups, 1) * (D / 16))
+                                : nullptr;
+    lay.r64 = o.stop == PN_STOP_DELTA_INF
+                  ? c.take<char>(residual64_workspace(PN_CELL_GRU, D, Dx, hb)) : nullptr;
     lay.bytes = c.bytes();
     return lay;
 }
@@ -381,7 +422,7 @@ size_t gru_quasi_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o)
     const std::vector<int32_t> ts = tile_starts(hb, L);
     const int ntiles = ts[hb.B];
     const int gt = o.group > 0 ? o.group : gru_group_tiles(ntiles, gru_resident((const void*)kern, nt));
-    return gruq_layout(nullptr, D, hb, ntiles, count_groups(ts, hb.B, gt)).bytes;
+    return gruq_layout(nullptr, D, Dx, hb, ntiles, count_groups(ts, hb.B, gt), o).bytes;
 }
 
 pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
@@ -400,10 +441,13 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     const int resident = gru_resident((const void*)kern, nt);
     const int gt = o.group > 0 ? o.group : gru_group_tiles(ntiles, resident);
     const int ngroups = count_groups(ts, hb.B, gt);
-    GruQLayout lay = gruq_layout(ws, D, hb, ntiles, ngroups);
-    const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
+    GruQLayout lay = gruq_layout(ws, D, Dx, hb, ntiles, ngroups, o);
+    const bool bydelta = o.stop == PN_STOP_DELTA_INF;
+    // the update-norm rule sees convergence one update later: cap T + 1 (Alg. alg:deer)
+    const int max_iters = o.max_iters > 0 ? o.max_iters
+                                          : (int)std::max<int64_t>(1, hb.Tmax) + (bydelta ? 1 : 0);
     PN_TRY(init_iter_state(lay.st, hb, ts, L, false, max_iters, (float)o.tol,
-                           (float)o.reset_abs, stream, gt));
+                           (float)o.reset_abs, stream, gt, o.stop));
     const int grid = std::max(1, std::min(ngroups, resident));
 
     GruQArgs args;
@@ -418,6 +462,8 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
     args.tiles = lay.st.tiles;
     args.groups = lay.st.groups;
     args.ngroups = ngroups;
+    args.grmax = lay.grmax;
+    args.freeze = o.freeze_prefix ? 1 : 0;
     args.mode = o.jac == PN_JAC_PICARD ? kTransIdentity
               : o.jac == PN_JAC_JACOBI ? kTransZero : kTransDiag;
     args.sbuf[0] = s;
@@ -434,7 +480,7 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
             hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), 0, s2, args);
         });
         prof_launch("carry_scan", st, [&](hipStream_t s2) {
-            launch_carry_scan(lay.gagg, lay.gcarry, lay.st, hb.B, D, s2);
+            launch_carry_scan(lay.gagg, lay.gcarry, lay.st, hb.B, D, s2, lay.grmax, D / 16);
         });
         launch_decide(lay.st, hb.B, st, true);
     };
@@ -443,15 +489,16 @@ pn_status gru_quasi_forward(const pn_cell_desc& cd, const HostBatch& hb, const f
                                   (uintptr_t)ws, (uintptr_t)hb.B, (uintptr_t)ntiles,
                                   (uintptr_t)ngroups, (uintptr_t)args.mode,
                                   (uintptr_t)o.damping, float_bits(args.dscale),
-                                  float_bits(args.clo), float_bits(args.chi)};
+                                  float_bits(args.clo), float_bits(args.chi),
+                                  (uintptr_t)args.freeze, (uintptr_t)hb.N, lay.bytes};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key,
                           one_iter, stream));
-    int derr = 0;
-    PN_TRY(finish_iterations(lay.st, hb, D, sizeof(float), s, lay.salt, stream, info, all_conv,
-                             &derr));
-    if (derr) {
-        set_error("device-side check failed in the GRU quasi-DEER iteration");
-        return PN_ERR_INTERNAL;
+    PN_TRY(finish_iterations(lay.st, hb, D, sizeof(float), s, lay.salt, stream, info, all_conv));
+    if (bydelta && info) {
+        // the loop tested update norms; the reported residual is the FP64 one of the result
+        std::vector<double> r64(hb.B);
+        PN_TRY(residual64_run(cd, hb, x, s0, s, lay.r64, stream, r64.data()));
+        for (int b = 0; b < hb.B; ++b) info[b].max_resid = r64[b];
     }
     return PN_OK;
 }

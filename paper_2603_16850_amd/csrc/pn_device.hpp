@@ -1,12 +1,5 @@
-// Device-side building blocks shared by the gfx950 kernels.
-//
-// Cross-workgroup communication (the decoupled look-back of the scans) uses only relaxed
-// 32/64-bit atomic loads and stores at agent scope.  On gfx950 those bypass the per-XCD
-// L2 (which is not coherent between XCDs) without the L2 write-back / invalidate that an
-// agent-scope release/acquire fence costs.  No ordering between different words is needed
-// because every published word validates itself: a slot holds a signalling-NaN sentinel
-// until it is written, and no arithmetic result can equal that pattern (arithmetic NaNs are
-// quiet).  Payloads that could carry a NaN are canonicalised to the quiet NaN first.
+// Device-side building blocks shared by the gfx950 kernels: the solver state records, the
+// MFMA wrapper and the gate nonlinearities.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,10 +10,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 namespace pn {
-
-constexpr uint32_t kSent32 = 0x7FA5A5A5u;                  // signalling NaN: "not published"
-constexpr uint64_t kSent64 = 0x7FA5A5A57FA5A5A5ull;        // both halves the same pattern
-constexpr uint32_t kQNaN = 0x7FC00000u;
 
 // ---- per-sequence solver state (device) ---------------------------------------------------
 enum SeqStatus : int { kActive = 0, kConverged = 1, kCapped = 2 };
@@ -35,7 +24,8 @@ struct SeqState {
     float final_resid;  // max |r| of the final iterate
     int frozen;         // converged-prefix skipping: groups of the sequence frozen so far
     int frozen_prev;    // ... and before the latest update of `frozen`
-    int pad_;
+    uint32_t maxd;      // running max |s^(k) - s^(k-1)| of the update that formed the current
+                        // iterate (float bits; the update-norm stopping rule)
 };
 
 // One entry per tile, indexed by scan slot (see IterState::tiles).
@@ -63,40 +53,19 @@ struct GroupInfo {
 struct Ctrl {
     int iter;           // index k of the iterate the next main kernel linearises
     int all_done;       // 1 when no sequence is active
-    uint32_t tile_counter;
-    int error;          // nonzero: device-side check failed (look-back watchdog)
     int max_iters;
     float tol;
     float reset_abs;
     int done_iter;      // the iteration whose decision stopped the last sequence (-1 before)
+    int stop_delta;     // 1: the stopping test reads maxd (update norm) instead of maxr
 };
 
-// ---- atomics ------------------------------------------------------------------------------
-PN_DEV uint64_t ld_u64(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-PN_DEV void st_u64(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-PN_DEV uint32_t ld_u32(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-PN_DEV void st_u32(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// ---- control-block reads ------------------------------------------------------------------
+// The stop flag is written by the previous kernel of the stream; a relaxed agent-scope load
+// reads it past the non-coherent per-XCD L2.
 PN_DEV int ld_i32(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-PN_DEV float canon(float v) { return (v != v) ? __uint_as_float(kQNaN) : v; }
-
-PN_DEV uint64_t pack2(float lo, float hi) {
-    return (uint64_t)__float_as_uint(canon(lo)) | ((uint64_t)__float_as_uint(canon(hi)) << 32);
-}
-PN_DEV float lo_of(uint64_t v) { return __uint_as_float((uint32_t)v); }
-PN_DEV float hi_of(uint64_t v) { return __uint_as_float((uint32_t)(v >> 32)); }
-PN_DEV bool ready64(uint64_t v) { return (uint32_t)v != kSent32; }
-PN_DEV bool ready32(uint32_t v) { return v != kSent32; }
 
 // |v| as orderable bits; NaN counts as +inf so it never passes a stopping test.
 PN_DEV uint32_t absbits(float v) {

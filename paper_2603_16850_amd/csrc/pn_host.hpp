@@ -90,16 +90,13 @@ struct IterState {
     SeqState* seq;
     int64_t* offsets;      // device copy [B+1]
     int32_t* tile_start;   // device [B+1]
-    int32_t* order;        // device [ntiles]: processing order of tile slots
     TileInfo* tiles;       // device [ntiles]: every tile's geometry, indexed by slot
     GroupInfo* groups;     // device [ngroups], indexed by group slot
     int32_t* group_start;  // device [B+1]: group slots of sequence b
     int ngroups;
 };
 // Tile slots of sequence b are tile_start[b] .. tile_start[b+1]-1, numbered in the order a
-// sequence is scanned (from its start, or from its end for reverse scans).  Look-back scans
-// take slots in `order`: every sequence's first slot, then every sequence's second slot, ...
-// so the tiles running at once spread over the sequences and look-back chains stay short.
+// sequence is scanned (from its start, or from its end for reverse scans).
 // Groups cut each sequence's slots into runs of `gt` tiles (the last one shorter).
 void carve_iter_state(Carver& c, IterState& st, int B, int ntiles, int ngroups = 0);
 // Number of groups of `gt` tiles over the sequences of a batch.
@@ -113,7 +110,7 @@ int count_groups(const std::vector<int32_t>& tstart, int B, int gt);
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
                           const std::vector<int32_t>& tstart, int L, bool reverse,
                           int max_iters, float tol, float reset_abs, hipStream_t stream,
-                          int gt = 0);
+                          int gt = 0, int stop = PN_STOP_RESID_INF);
 
 // Launches the end-of-iteration decision kernel (stop tests, counters).
 // `pending_current`: the resets counted during the iteration belong to the iterate that was
@@ -136,6 +133,6 @@ pn_status run_iterations(const IterState& st, int max_launches, int graph_iters,
 // odd, and reads the per-sequence info back to the host.
 pn_status finish_iterations(const IterState& st, const HostBatch& hb, int D, size_t elem,
                             void* s_user, const void* s_alt, hipStream_t stream,
-                            pn_seq_info* info, bool* all_converged, int* device_error);
+                            pn_seq_info* info, bool* all_converged);
 
 }  // namespace pn

@@ -1,5 +1,8 @@
 // Solver drivers behind the C ABI (one translation unit each).
 #pragma once
+#include <initializer_list>
+#include <utility>
+
 #include "pn_host.hpp"
 
 namespace pn {
@@ -59,6 +62,17 @@ size_t elk_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
 pn_status elk_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
                       const float* s0, float* s, double lambda, const pn_opts& o, void* ws,
                       hipStream_t stream, pn_seq_info* info, bool* all_conv);
+
+// DEER / quasi-DEER / Picard / Jacobi on the affine test cells (D <= 16, FP32)
+bool affine_supported(int D, int Dx);
+size_t affine_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status affine_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                         const float* s0, float* s, const pn_opts& o, void* ws,
+                         hipStream_t stream, pn_seq_info* info, bool* all_conv);
+
+// opts->check_inputs: scans the arrays for NaN / infinity (flag: 4 bytes of device memory)
+pn_status check_finite(std::initializer_list<std::pair<const void*, int64_t>> arrays, int dtype,
+                       int* flag_dev, hipStream_t stream);
 
 // sequential baselines
 bool seq_supported(int cell, int D, int Dx);

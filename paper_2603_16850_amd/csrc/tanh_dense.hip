@@ -429,13 +429,7 @@ pn_status tanh_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const 
                                   (uintptr_t)ngroups, float_bits(args.dscale)};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
-    int derr = 0;
-    PN_TRY(finish_iterations(lay.st, hb, TD, sizeof(float), s, lay.salt, stream, info, all_conv,
-                             &derr));
-    if (derr) {
-        set_error("device-side check failed in the dense tanh iteration");
-        return PN_ERR_INTERNAL;
-    }
+    PN_TRY(finish_iterations(lay.st, hb, TD, sizeof(float), s, lay.salt, stream, info, all_conv));
     return PN_OK;
 }
 
@@ -1016,13 +1010,8 @@ pn_status tanh_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float*
                                   (uintptr_t)ntiles, (uintptr_t)ngroups};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
-    int derr = 0;
     PN_TRY(finish_iterations(lay.st, hb, TD, sizeof(float), nullptr, nullptr, stream, info,
-                             all_conv, &derr));
-    if (derr) {
-        set_error("device-side check failed in the dense tanh adjoint iteration");
-        return PN_ERR_INTERNAL;
-    }
+                             all_conv));
     if (gs0) {
         hipLaunchKernelGGL(tanh_adj_gs0_clear_kernel, dim3(1), dim3(256), 0, stream, gs0, hb.B * TD);
         PN_HIP(hipGetLastError());

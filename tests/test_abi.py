@@ -167,7 +167,7 @@ def test_binding_fails_loudly_without_library(tmp_path):
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(pn.Opts) == 72
+    assert ctypes.sizeof(pn.Opts) == 80
     assert ctypes.sizeof(pn.CellDesc) == 24 and ctypes.sizeof(pn.Batch) == 24
     assert ctypes.sizeof(pn.SeqInfo) == 24
 
@@ -220,9 +220,18 @@ def test_damping_routes(lib):
     c3, b3, _ = _desc(D=64, Dx=32)
     assert lib.deer_solve(ctypes.byref(c3), ctypes.byref(b3), *args, ctypes.byref(o), None, 0,
                           None, None) == -2
-    o = pn.make_opts(jac="diag", freeze_prefix=True)   # converged-prefix skipping: ELK only
+    # converged-prefix skipping: ELK and the GRU diagonal path (fails later, on the missing
+    # workspace); not on the dense tanh path, not with the update-norm rule
+    o = pn.make_opts(jac="diag", freeze_prefix=True)
     c2, b2, _ = _desc(D=64, Dx=32)
     assert lib.deer_solve(ctypes.byref(c2), ctypes.byref(b2), *args, ctypes.byref(o), None, 0,
+                          None, None) == -3
+    o = pn.make_opts(jac="diag", freeze_prefix=True, stop="delta")
+    assert lib.deer_solve(ctypes.byref(c2), ctypes.byref(b2), *args, ctypes.byref(o), None, 0,
+                          None, None) == -2
+    c4, b4, _ = _desc(cell="tanh", D=32, Dx=16)
+    o = pn.make_opts(jac="dense", freeze_prefix=True)
+    assert lib.deer_solve(ctypes.byref(c4), ctypes.byref(b4), *args, ctypes.byref(o), None, 0,
                           None, None) == -2
     for tile in (8, 24, 2048):          # ELK groups whole 16-step chunks, at most 64 of them
         o = pn.make_opts(jac="dense", tile=tile)
@@ -237,3 +246,89 @@ def test_damping_routes(lib):
     o = pn.make_opts(jac="dense", damping="scale", damp_k=0.2)
     assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0,
                           None, None) == -3
+
+
+def test_stop_rule_and_input_check_options(lib):
+    """pn_opts.stop and check_inputs: unknown values are invalid; the update-norm rule is
+    built for the GRU diagonal path and the affine cells only; the input scan adds 256 bytes
+    to the workspace."""
+    args = (ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    c, b, _ = _desc()
+    for field, bad in (("stop", 2), ("stop", -1), ("check_inputs", 2)):
+        o = pn.make_opts(jac="diag")
+        setattr(o, field, bad)
+        assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None,
+                              0, None, None) == -1
+    o = pn.make_opts(jac="diag", stop="delta")            # built: fails on the workspace
+    assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None, 0,
+                          None, None) == -3
+    ct, bt, _ = _desc(cell="tanh", D=32, Dx=16)
+    o = pn.make_opts(jac="dense", stop="delta")
+    assert lib.deer_solve(ctypes.byref(ct), ctypes.byref(bt), *args, ctypes.byref(o), None, 0,
+                          None, None) == -2
+    ce, be, _ = _desc(cell="tanh", D=16, Dx=16)
+    assert lib.elk_solve(ctypes.byref(ce), ctypes.byref(be), *args, ctypes.c_double(0.1),
+                         ctypes.byref(o), None, 0, None, None) == -2
+    o = pn.make_opts(jac="diag", stop="delta")
+    assert lib.deer_adjoint(ctypes.byref(c), ctypes.byref(b), *args, ctypes.c_void_p(16),
+                            None, None, ctypes.c_void_p(16), ctypes.byref(o), None, 0, None,
+                            None) == -2
+    for op in (pn.OP_DEER, pn.OP_ADJOINT):
+        _, n0 = _ws(lib, op, c, b, pn.make_opts(jac="diag"))
+        st, n1 = _ws(lib, op, c, b, pn.make_opts(jac="diag", check_inputs=True))
+        assert st == 0 and n1 == ((n0 + 255) // 256) * 256 + 256
+
+
+@pytest.mark.parametrize("cell", ["affine", "affine_steps"])
+def test_affine_cells_are_routed(lib, cell):
+    """The affine test cells: every transition mode is built for D <= 16 in FP32 (the calls
+    fail only on the missing workspace); D > 16, FP64 and damping are not built."""
+    args = (ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    for jac in ("dense", "diag", "picard", "jacobi"):
+        for D in (1, 5, 16):
+            c, b, _ = _desc(cell=cell, D=D, Dx=3)
+            o = pn.make_opts(jac=jac)
+            st, n = _ws(lib, pn.OP_DEER, c, b, o)
+            assert st == 0 and n > 0
+            assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o),
+                                  None, 0, None, None) == -3
+    for kw, mo in ((dict(D=17), {}), (dict(D=4, dtype="f64"), {}),
+                   (dict(D=4), dict(damping="scale", damp_k=0.5))):
+        c, b, _ = _desc(cell=cell, Dx=3, **kw)
+        o = pn.make_opts(jac="dense", **mo)
+        assert lib.deer_solve(ctypes.byref(c), ctypes.byref(b), *args, ctypes.byref(o), None,
+                              0, None, None) == -2
+
+
+def test_binding_checks_shapes_before_any_call():
+    """The binding checks the tensors against the shapes the C call assumes (the library sees
+    only pointers): offsets against x, s0, the packed parameter count, dtypes and devices,
+    and the [N, D] arrays."""
+    import torch
+    f32 = torch.float32       # explicit: another test module changes torch's default dtype
+    x = torch.zeros(100, 8, dtype=f32)
+    s0 = torch.zeros(2, 16, dtype=f32)
+    p = torch.zeros(pn.param_count("gru", 16, 8), dtype=f32)
+    sh = pn._shapes("gru", p, x, s0, [0, 40, 100])
+    assert sh.batch.B == 2 and sh.batch.N == 100
+    bad = [
+        dict(offsets=[0, 40, 99]),                    # offsets[-1] != N
+        dict(offsets=[0, 100]),                       # B + 1 entries
+        dict(offsets=[0, 60, 40, 100]),               # wrong count and decreasing
+        dict(offsets=None, x=torch.zeros(101, 8, dtype=f32)),   # N not split into B
+        dict(params=torch.zeros(p.numel() - 1, dtype=f32)),     # parameter count
+        dict(s0=torch.zeros(2, 16, dtype=torch.float64)),
+        dict(cell="bogus"),
+        dict(rows=[(torch.zeros(100, 15, dtype=f32), "s", 16)]),
+        dict(rows=[(torch.zeros(100, 16, dtype=torch.float64), "gs", 16)]),
+    ]
+    for kw in bad:
+        args = dict(cell="gru", params=p, x=x, s0=s0, offsets=[0, 40, 100])
+        args.update(kw)
+        rows = args.pop("rows", ())
+        with pytest.raises(ValueError):
+            pn._shapes(args["cell"], args["params"], args["x"], args["s0"], args["offsets"],
+                       rows=rows)
+    # the per-step affine cell packs one matrix per row
+    assert pn.param_count("affine_steps", 3, 2, N=10) == 10 * 9 + 6 + 3
+    assert pn.param_count("affine", 3, 2) == 9 + 6 + 3

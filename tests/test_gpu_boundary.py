@@ -1,0 +1,251 @@
+"""GPU: the boundary's test cells and options through the C ABI.
+
+* Affine cells (Ch. 2, eq. lds): one DEER update lands on the trajectory (the residual's
+  Jacobian is constant); with a diagonal M one quasi-DEER update does (eq. quasi_lds).
+* The group word problem (Ch. 6, Prop. cayley): the S5 permutation LDS is solved by one
+  Newton update, while the quasi, Picard and Jacobi transitions take many; with integer
+  states and permutation matrices every iterate is exact in FP32, so the iterates and the
+  iteration counts are compared with the FP64 oracle for equality.
+* The update-norm stopping rule (Ch. 3): counts and results against the oracle's loop.
+* check_inputs: a NaN or infinity in an input gives PN_ERR_NONFINITE_INPUT.
+* The kernel-family names pn_profile_read documents are the ones recorded.
+"""
+import numpy as np
+import pytest
+
+from oracle import cells, newton, rollout
+from paper_2603_16850_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.tensor(a, dtype=dtype or torch.float32, device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def _offsets(lens):
+    return np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+
+
+def _affine_instance(D, Dx, lens, seed, diagonal=False, norm=0.9):
+    rng = np.random.default_rng(seed)
+    if diagonal:
+        M = np.diag(rng.uniform(-norm, norm, D))
+    else:
+        M = rng.standard_normal((D, D))
+        M *= norm / np.linalg.norm(M, 2)
+    Nx = 0.3 * rng.standard_normal((D, Dx))
+    c = 0.1 * rng.standard_normal(D)
+    off = _offsets(lens)
+    x = rng.standard_normal((int(off[-1]), Dx))
+    s0 = 0.5 * rng.standard_normal((len(lens), D))
+    params = np.concatenate([M.ravel(), Nx.ravel(), c])
+    return params, x, s0, off
+
+
+def _s5_instance(lens, seed):
+    """Per-step permutation matrices of S5 acting on s_0 = (1, .., 5) (Prop. cayley: the
+    state is the running product in the tabular representation)."""
+    rng = np.random.default_rng(seed)
+    off = _offsets(lens)
+    N, D = int(off[-1]), 5
+    Mt = np.zeros((N, D, D))
+    for n in range(N):
+        Mt[n, np.arange(D), rng.permutation(D)] = 1.0
+    s0 = np.tile(np.arange(1.0, D + 1), (len(lens), 1))
+    x = np.zeros((N, 1))
+    params = np.concatenate([Mt.ravel(), np.zeros(D), np.zeros(D)])
+    return params, Mt, x, s0, off
+
+
+def _oracle_cell_steps(Mt_seq, D, Dx):
+    return cells.Affine(np.zeros(D * D + D * Dx + D), D, Dx, M_steps=Mt_seq)
+
+
+@pytest.mark.parametrize("D", [4, 16])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_affine_one_deer_update(lib, D, use_graph):
+    lens = [700, 1, 0, 333]
+    params, x, s0, off = _affine_instance(D, 3, lens, seed=60 + D)
+    s, info = lib.deer_solve(_t(x), _t(s0), _t(params), cell="affine", offsets=off,
+                             jac="dense", tol=1e-6, use_graph=use_graph)
+    cell = cells.Affine(params, D, 3)
+    ref = rollout.rollout_batch(cell, x, s0, off)
+    for b, i in enumerate(info):
+        assert i["converged"], (b, i)
+        assert i["iters"] == (1 if lens[b] else 0), (b, i)
+        assert i["max_resid"] < 1e-6
+    assert _rel(_np(s), ref) < 1e-5
+
+
+@pytest.mark.parametrize("jac", ["diag", "dense"])
+def test_diagonal_affine_one_quasi_update(lib, jac):
+    lens = [513, 64, 200]
+    params, x, s0, off = _affine_instance(8, 2, lens, seed=70, diagonal=True)
+    s, info = lib.deer_solve(_t(x), _t(s0), _t(params), cell="affine", offsets=off, jac=jac,
+                             tol=1e-6)
+    ref = rollout.rollout_batch(cells.Affine(params, 8, 2), x, s0, off)
+    assert all(i["converged"] and i["iters"] == 1 for i in info), info
+    assert _rel(_np(s), ref) < 1e-5
+
+
+def test_affine_quasi_iterates_match_oracle(lib):
+    """A non-diagonal M under the diagonal transition: every iterate equals the oracle's."""
+    lens = [300, 150]
+    params, x, s0, off = _affine_instance(6, 2, lens, seed=71, norm=0.8)
+    cell = cells.Affine(params, 6, 2)
+    for k in (1, 2, 4):
+        s, info = lib.deer_solve(_t(x), _t(s0), _t(params), cell="affine", offsets=off,
+                                 jac="diag", tol=1e-12, max_iters=k)
+        s = _np(s)
+        for b in range(2):
+            a, e = off[b], off[b + 1]
+            out = newton.newton(cell, x[a:e], s0[b], mode="diag", tol=1e-12, max_iters=k)
+            assert info[b]["iters"] == k and not info[b]["converged"]
+            assert np.abs(s[a:e] - out["s"]).max() < 1e-5 * max(1.0, np.abs(out["s"]).max())
+
+
+@pytest.mark.parametrize("jac", ["dense", "diag", "picard", "jacobi"])
+def test_s5_word_problem(lib, jac):
+    """Newton solves the S5 word problem in one update; the other fixed-point methods need
+    many.  Exact arithmetic on both sides: iterates and counts equal the oracle's."""
+    lens = [64, 40, 0, 17]
+    params, Mt, x, s0, off = _s5_instance(lens, seed=72)
+    s, info = lib.deer_solve(_t(x), _t(s0), _t(params), cell="affine_steps", offsets=off,
+                             jac=jac, tol=0.5)
+    s = _np(s)
+    for b, T in enumerate(lens):
+        if T == 0:
+            assert info[b]["converged"] and info[b]["iters"] == 0
+            continue
+        a, e = off[b], off[b + 1]
+        cell = _oracle_cell_steps(Mt[a:e], 5, 1)
+        ref = rollout.rollout(cell, x[a:e], s0[b])
+        out = newton.newton(cell, x[a:e], s0[b], mode=jac, tol=0.5)
+        assert info[b]["converged"] and out["converged"]
+        assert info[b]["iters"] == out["iters"], (b, info[b], out["iters"])
+        assert np.array_equal(s[a:e], ref)
+        if jac == "dense":
+            assert info[b]["iters"] == (1 if T else 0)
+    if jac == "jacobi":
+        assert info[0]["iters"] >= lens[0] // 2
+
+
+@pytest.mark.parametrize("jac", ["diag", "jacobi"])
+def test_s5_iterates_equal_oracle(lib, jac):
+    lens = [48, 30]
+    params, Mt, x, s0, off = _s5_instance(lens, seed=73)
+    for k in (1, 3, 7):
+        s, info = lib.deer_solve(_t(x), _t(s0), _t(params), cell="affine_steps", offsets=off,
+                                 jac=jac, tol=1e-3, max_iters=k)
+        s = _np(s)
+        for b in range(2):
+            a, e = off[b], off[b + 1]
+            out = newton.newton(_oracle_cell_steps(Mt[a:e], 5, 1), x[a:e], s0[b], mode=jac,
+                                tol=1e-3, max_iters=k)
+            assert info[b]["iters"] == out["iters"]
+            assert np.array_equal(s[a:e], out["s"]), (k, b)
+
+
+def test_update_norm_stop_affine(lib):
+    """stop = "delta": DEER on the S5 problem takes its exact update and then a zero one."""
+    lens = [64, 17]
+    params, Mt, x, s0, off = _s5_instance(lens, seed=74)
+    for jac in ("dense", "jacobi"):
+        s, info = lib.deer_solve(_t(x), _t(s0), _t(params), cell="affine_steps", offsets=off,
+                                 jac=jac, tol=0.5, stop="delta")
+        s = _np(s)
+        for b in range(2):
+            a, e = off[b], off[b + 1]
+            cell = _oracle_cell_steps(Mt[a:e], 5, 1)
+            out = newton.newton(cell, x[a:e], s0[b], mode=jac, tol=0.5, stop="delta")
+            assert info[b]["converged"] and info[b]["iters"] == out["iters"]
+            assert np.array_equal(s[a:e], out["s"])
+        if jac == "dense":
+            assert [i["iters"] for i in info] == [2, 2]
+
+
+def test_update_norm_stop_gru(lib):
+    """stop = "delta" on the GRU diagonal path: the iteration counts of the oracle's loop with
+    the same rule (within one: FP32 against FP64 near the threshold), the rollout within
+    1e-5, and the reported residual is the FP64 one of the result."""
+    w = workloads.GRU64_QUASI.scaled(T=0, B=3)
+    inst = workloads.make_instance(w, seed=75, lengths=np.array([900, 1, 257]))
+    cell = cells.GRU(inst.params, w.D, w.Dx)
+    s, info = lib.deer_solve(_t(inst.x), _t(inst.s0), _t(inst.params), cell="gru",
+                             offsets=inst.offsets, jac="diag", tol=1e-6, stop="delta")
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    assert _rel(_np(s), ref) < 1e-5
+    _, oinfo = newton.newton_batch(cell, inst.x, inst.s0, inst.offsets, mode="diag", tol=1e-6,
+                                   stop="delta")
+    for gi, oi in zip(info, oinfo):
+        assert gi["converged"] and abs(gi["iters"] - oi["iters"]) <= 1, (gi, oi["iters"])
+        assert 0 <= gi["max_resid"] < 1e-5
+
+
+@pytest.mark.parametrize("where", ["x", "params", "s0"])
+def test_check_inputs_rejects_nonfinite(lib, where):
+    import torch
+    w = workloads.GRU64_QUASI.scaled(T=300, B=2)
+    inst = workloads.make_instance(w, seed=76)
+    x, s0, p = _t(inst.x), _t(inst.s0), _t(inst.params)
+    clean = lib.deer_solve(x, s0, p, cell="gru", offsets=inst.offsets, tol=1e-6,
+                           check_inputs=True)
+    assert all(i["converged"] for i in clean[1])
+    bad = {"x": x, "params": p, "s0": s0}[where].clone()
+    bad.view(-1)[bad.numel() // 2] = float("nan") if where != "s0" else float("inf")
+    args = dict(x=x, s0=s0, p=p)
+    args[{"x": "x", "params": "p", "s0": "s0"}[where]] = bad
+    with pytest.raises(lib.PNError) as e:
+        lib.deer_solve(args["x"], args["s0"], args["p"], cell="gru", offsets=inst.offsets,
+                       tol=1e-6, check_inputs=True)
+    assert e.value.status == -4
+    # the adjoint scans its gradient input too
+    s = clean[0]
+    gs = 2 * s
+    gs.view(-1)[7] = float("nan")
+    with pytest.raises(lib.PNError) as e:
+        lib.deer_adjoint(x, s0, p, s, gs, cell="gru", offsets=inst.offsets, check_inputs=True)
+    assert e.value.status == -4
+    torch.cuda.synchronize()
+
+
+def test_profile_family_names(lib):
+    """Every family pn_profile_read documents for these routes is recorded after a solve."""
+    w = workloads.GRU48_RAGGED.scaled(B=2, T=600)
+    inst = workloads.make_instance(w, seed=77)
+    x, s0, p = _t(inst.x), _t(inst.s0), _t(inst.params)
+    wt = workloads.TANH32_DENSE_BF16.scaled(B=2, T=300)
+    it = workloads.make_instance(wt, seed=78)
+    xt, s0t, pt = _t(it.x), _t(it.s0), _t(it.params)
+    we = workloads.TANH16_ELK.scaled(B=1, T=200, gain=0.9)
+    ie = workloads.make_instance(we, seed=79)
+    xe, s0e, pe = _t(ie.x), _t(ie.s0), _t(ie.params)
+    params, xa, s0a, offa = _affine_instance(4, 2, [300], seed=80)
+    with lib.profile():
+        s, _ = lib.deer_solve(x, s0, p, cell="gru", offsets=inst.offsets, tol=1e-6)
+        lib.deer_adjoint(x, s0, p, s, 2 * s, cell="gru", offsets=inst.offsets)
+        st, _ = lib.deer_solve(xt, s0t, pt, cell="tanh", offsets=it.offsets, jac="dense",
+                               tol=1e-6)
+        lib.deer_adjoint(xt, s0t, pt, st, 2 * st, cell="tanh", offsets=it.offsets, jac="dense")
+        lib.elk_solve(xe, s0e, pe, 0.1, cell="tanh", offsets=ie.offsets, tol=1e-5, smooth=True)
+        lib.deer_solve(_t(xa), _t(s0a), _t(params), cell="affine", offsets=offa, jac="dense")
+        lib.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
+        lib.seq_bptt(x, s0, p, s, 2 * s, cell="gru", offsets=inst.offsets)
+        names = ["gru_quasi_local", "carry_scan", "gru_adj_prep", "gru_adj_local",
+                 "gru_adj_grad", "tanh_dense_local", "dense_carry", "tanh_adj_prep",
+                 "tanh_adj_local", "tanh_adj_grad", "elk_local", "elk_carry", "elk_smooth",
+                 "elk_back_carry", "elk_back_apply", "affine_local", "affine_carry",
+                 "seq_rollout", "seq_adj"]
+        got = {n: lib.profile.read(n) for n in names}
+    for n, (ms, k) in got.items():
+        assert k > 0 and ms > 0, n

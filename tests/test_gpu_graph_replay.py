@@ -119,3 +119,72 @@ def test_replay_elk(lib, lam, jac, tile):
     inst = workloads.make_instance(w, seed=54, lengths=np.array([1500, 20, 700]))
     _run_fixed(lib, lib.OP_ELK, "tanh", inst, w,
                dict(jac=jac, tol=1e-6, graph_iters=4, max_iters=16, tile=tile), lam=lam)
+
+
+def _solve_fixed(lib, op, cell, x, s0, p, s, ws, offsets, opts_kw, lam=0.0):
+    """One solve through the C ABI on caller-held buffers (views of fixed allocations), with
+    graph capture on, then the same with plain launches; returns both iterates and counts."""
+    import torch
+    pn = lib
+    sh = pn._shapes(cell, p, x, s0, offsets)
+    out = []
+    for use_graph in (True, False):
+        opts = pn.make_opts(use_graph=use_graph, **opts_kw)
+        need = ctypes.c_size_t(0)
+        assert pn.load().pn_workspace_bytes(op, ctypes.byref(sh.cell), ctypes.byref(sh.batch),
+                                            ctypes.byref(opts), ctypes.byref(need)) == 0
+        assert need.value + 256 <= ws.numel()
+        info = (pn.SeqInfo * sh.batch.B)()
+        s.zero_()
+        if op == pn.OP_DEER:
+            st = pn.load().deer_solve(ctypes.byref(sh.cell), ctypes.byref(sh.batch), pn._ptr(x),
+                                      pn._ptr(s0), pn._ptr(s), ctypes.byref(opts),
+                                      pn._aligned(ws), need.value, pn._stream(), info)
+        else:
+            st = pn.load().elk_solve(ctypes.byref(sh.cell), ctypes.byref(sh.batch), pn._ptr(x),
+                                     pn._ptr(s0), pn._ptr(s), ctypes.c_double(lam),
+                                     ctypes.byref(opts), pn._aligned(ws), need.value,
+                                     pn._stream(), info)
+        assert st >= 0, pn.load().pn_last_error()
+        torch.cuda.synchronize()
+        out.append((s.cpu().numpy().copy(), [i.iters for i in info]))
+        _eager_noise()
+    (sg, ig), (sp, ip) = out
+    assert ig == ip
+    assert np.array_equal(sg, sp)
+    return sg
+
+
+def test_replay_same_buffers_other_length(lib):
+    """The same buffers (views at the same addresses, the same workspace pointer) called with
+    two lengths that give the same tile and group counts (B = 1, T = 1000 and 1010 at 64-step
+    tiles): the workspace offsets of the second call differ, and its graph-launched result
+    must still equal its plain launches bit for bit."""
+    import torch
+    w = workloads.GRU48_RAGGED.scaled(B=1, T=0)
+    inst = workloads.make_instance(w, seed=56, lengths=np.array([1010]))
+    X, S0, P = _t(inst.x), _t(inst.s0), _t(inst.params)
+    S = torch.zeros(1010, w.D, device="cuda")
+    WS = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    res = {}
+    for T in (1000, 1010, 1000):
+        res[T] = _solve_fixed(lib, lib.OP_DEER, "gru", X[:T], S0, P, S[:T], WS,
+                              np.array([0, T]), dict(jac="diag", tol=1e-6, graph_iters=3,
+                                                     tile=64, group=4))
+    assert not np.array_equal(res[1000][:1000], np.zeros((1000, w.D)))
+
+
+def test_replay_elk_same_tiles_other_longest_sequence(lib):
+    """ELK on fixed buffers with two ragged batches of the same total length, chunk count
+    and group count but a different longest sequence (10 and 18 groups): the carry plan of
+    the second differs, and graph launches must still equal plain launches."""
+    import torch
+    w = workloads.TANH16_ELK.scaled(B=2, T=0, gain=0.9)
+    inst = workloads.make_instance(w, seed=57, lengths=np.array([320, 320]))
+    X, S0, P = _t(inst.x), _t(inst.s0), _t(inst.params)
+    S = torch.zeros(640, w.D, device="cuda")
+    WS = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    for lens in ((320, 320), (64, 576), (320, 320)):
+        off = np.concatenate([[0], np.cumsum(lens)])
+        _solve_fixed(lib, lib.OP_ELK, "tanh", X, S0, P, S, WS, off,
+                     dict(jac="dense", tol=1e-6, graph_iters=4, max_iters=12, tile=32), lam=0.1)

@@ -108,3 +108,26 @@ def test_damped_adjoint_gives_the_same_gradients(lib, damp):
     assert all(i["converged"] for i in info), info
     rel = lambda a, b: np.abs(a.cpu().double().numpy() - b).max() / np.abs(b).max()
     assert rel(gp, wp) < 1e-5 and rel(gx, wx) < 1e-5 and rel(g0, w0) < 1e-5
+
+
+@pytest.mark.parametrize("group", [1, 0])
+def test_adjoint_freeze_prefix(lib, group):
+    """Converged-prefix skipping in the adjoint's scan order (groups from the sequence end):
+    the gradients stay within the bar, and the iterations do not grow."""
+    w = workloads.GRU48_RAGGED.scaled(B=3, T=0)
+    inst = workloads.make_instance(w, seed=82, lengths=np.array([2100, 1, 640]))
+    cell = cells.GRU(inst.params, w.D, w.Dx)
+    s = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    s32 = s.astype(np.float32).astype(np.float64)
+    want = adjoint.adjoint_batch(cell, inst.x, inst.s0, s32, 2 * s32, inst.offsets)[1:]
+    out = {}
+    for fz in (False, True):
+        gp, gx, g0, info = lib.deer_adjoint(_t(inst.x), _t(inst.s0), _t(inst.params), _t(s32),
+                                            _t(2 * s32), cell="gru", offsets=inst.offsets,
+                                            jac="diag", tol=1e-6, freeze_prefix=fz,
+                                            group=group)
+        assert all(i["converged"] for i in info)
+        got = tuple(v.cpu().double().numpy() for v in (gp, gx, g0))
+        _check_grads(cell, got, want, 1e-5)
+        out[fz] = [i["iters"] for i in info]
+    assert all(a <= b + 1 for a, b in zip(out[True], out[False])), out

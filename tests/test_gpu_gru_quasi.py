@@ -225,3 +225,63 @@ def test_damped_transitions_match_sequential_loop(lib, damp, mode):
     ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
     assert all(i["converged"] for i in info)
     assert _rel(s, ref) < 1e-5
+
+
+def _freeze_safe_iters(cell, inst, block, tol, mode="diag"):
+    """Oracle iterates with converged-prefix skipping in blocks of `block` steps, and the
+    last iteration whose freeze decisions all lie at least 3% away from tol (FP32 and FP64
+    residuals agree on those); also the number of freeze events seen before it."""
+    hist, last, events = [], 10 ** 9, 0
+    for b in range(inst.offsets.size - 1):
+        a, e = inst.offsets[b], inst.offsets[b + 1]
+        out = newton.newton(cell, inst.x[a:e], inst.s0[b], mode=mode, tol=tol, history=True,
+                            freeze=block)
+        hist.append(out["history"])
+        for i, s in enumerate(out["history"]):
+            _, r = newton.linearize(cell, inst.x[a:e], inst.s0[b], s)
+            t0 = newton.frozen_prefix(r, block, tol)
+            margin = min(abs(np.log(np.abs(r[j:j + block]).max() / tol))
+                         for j in range(0, r.shape[0], block))
+            if margin < 0.03:
+                last = min(last, i)
+                break
+            events += 0 < t0 < r.shape[0]
+    return hist, last, events
+
+
+@pytest.mark.parametrize("tile,group,tol", [(32, 1, 1e-4), (32, 2, 1e-5)])
+def test_freeze_prefix_iterates_match_oracle(lib, tile, group, tol):
+    """Converged-prefix skipping on the GRU diagonal path (proof of Prop. global_convergence:
+    convergence is causal): per-iteration iterates equal the oracle's loop with the same
+    block length (tile x group steps) while the freeze decisions are unambiguous in FP32."""
+    w = workloads.GRU64_QUASI.scaled(T=0, B=3)
+    inst = workloads.make_instance(w, seed=81, lengths=np.array([1500, 70, 900]))
+    cell = cells.GRU(inst.params, w.D, w.Dx)
+    block = tile * group
+    hist, last, events = _freeze_safe_iters(cell, inst, block, tol)
+    nmax = max(len(h) for h in hist) - 1
+    ks = [k for k in range(1, nmax + 1) if k <= last]
+    assert events > 0 and ks, (events, last)
+    for k in ks:
+        s, info = _run(lib, inst, tol=tol, max_iters=k, tile=tile, group=group,
+                       freeze_prefix=True)
+        for b in range(3):
+            a, e = inst.offsets[b], inst.offsets[b + 1]
+            ref = hist[b][min(k, len(hist[b]) - 1)]
+            assert np.abs(s[a:e] - ref).max() < 2e-5, (k, b)
+            assert info[b]["iters"] == min(k, len(hist[b]) - 1)
+
+
+@pytest.mark.parametrize("name", ["gru64-quasi-f32", "gru48-ragged-quasi"])
+def test_freeze_prefix_full_size(lib, name):
+    """Full size with converged-prefix skipping: the rollout within 1e-5, the same iteration
+    counts as without it up to one."""
+    w = workloads.ALL[name]
+    inst = workloads.make_instance(w, seed=0)
+    cell = cells.GRU(inst.params, w.D, w.Dx)
+    s, info = _run(lib, inst, tol=ERR_TOL, freeze_prefix=True)
+    _, info0 = _run(lib, inst, tol=ERR_TOL)
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    assert all(i["converged"] for i in info)
+    assert _rel(s, ref) < 1e-5, _rel(s, ref)
+    assert all(abs(a["iters"] - b["iters"]) <= 1 for a, b in zip(info, info0))
