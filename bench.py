@@ -1,14 +1,19 @@
 """Benchmark: forward + backward of the parallel Newton path on one MI355X.
 
-One "step" is the whole hot path over the batch: quasi-DEER solve of the GRU recurrence
-(fused linearise + diagonal look-back scan per iteration, hipGraph-captured iterations),
-then the exact quasi adjoint for the loss sum_t ||s_t||^2 (iterated reverse scans) and the
-parameter / input / initial-state gradients.  Workload: GRU, D=64, Dx=32, B=16 sequences of
-T=65536 steps (1,048,576 sequence-steps), weights N(0, 1/D), inputs N(0, 1), s_0 = 0, guess 0.
+One "step" is the whole hot path over one batch: the quasi-DEER solve of the GRU recurrence
+(per iteration a fused linearise + diagonal group scan pass and the carry pass, iterations
+captured in HIP graphs, the library's default), then the exact quasi adjoint for the loss
+sum_t ||s_t||^2 (iterated reverse diagonal scans) and the parameter, input and initial-state
+gradients.  Headline workload: 256 GRU sequences, D = 48, Dx = 24, lengths uniform on
+512..32768 (about 4.26 M sequence-steps), weights N(0, 1/D), inputs N(0, 1), s_0 = 0, guess 0,
+scan tiles from the library's autotuner.  The same step on 16 sequences of 65,536 steps at
+D = 64, Dx = 32 is reported as a secondary object.
 
-Printed: one JSON line with the throughput (sequence-steps/s), the sequential GPU baseline on
-the same inputs, the dominant kernel's roofline (its duration measured with HIP events on the
-library's stream), the CPU oracle baseline and the error of the result against it.
+Printed: one JSON line -- throughput (sequence-steps/s) of the timed region, the sequential
+GPU rollout + backward on the same inputs, the error against the FP64 CPU oracle, the
+dominant kernel's roofline (its durations from HIP events in a separate profiled pass of one
+step, since events around single kernels need direct launches instead of graphs), and the
+CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--tol 1e-6] [--no-cpu]
 """
@@ -25,58 +30,66 @@ sys.path.insert(0, ROOT)
 
 GRAPH_ITERS = 4
 METRIC = "fwd+bwd sequence-steps/sec, Newton-scan vs sequential rollout, same GPU, err≤1e-5"
-WORKLOAD = "gru64-quasi-f32"
+WORKLOAD = "gru48-ragged-quasi"
+SECONDARY = "gru64-quasi-f32"
+ERR_BAR = 1e-5
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 
-
-# kernel families timed inside the solver calls (HIP events on the library's stream)
+# kernel families timed in the profiled pass (HIP events on the library's stream)
 FAMILIES = ("gru_quasi_local", "gru_adj_local", "carry_scan", "gru_adj_prep", "gru_adj_grad")
 
 
 def gate_gemm_flops(D, Dx):
-    """Algorithmic MFMA flops per step of the gate GEMM: z, r on [h; x], U_n h, W_n x."""
-    return 2 * D * (2 * (D + Dx) + D + Dx)
+    """Algorithmic MFMA flops per step of the forward gate GEMM: z and r on [h; x], U_n h,
+    W_n x, i.e. 2 * 3D (D + Dx) (the linearise count; the gate nonlinearities are VALU)."""
+    return 2 * 3 * D * (D + Dx)
 
 
 def vjp_gemm_flops(D):
-    """Algorithmic MFMA flops per step of the adjoint VJP [U_z; U_n; U_r]^T (3 D x D)."""
+    """Algorithmic MFMA flops per step of the adjoint VJP [U_z; U_n; U_r]^T (3D x D)."""
     return 2 * 3 * D * D
 
 
-def fwd_local_bytes(D, Dx):
-    """Algorithmic HBM bytes per step of one forward iteration (FP32): read s^(k-1), the
-    previous maps (la, lc) and x; write s^(k) and the new maps."""
-    return 4 * D + 8 * D + 4 * Dx + 4 * D + 8 * D
+def fwd_iter_bytes(D, Dx):
+    """Algorithmic HBM bytes per step of one fused forward iteration (linearise + scan + the
+    update in one pass, the minimum): read x (4 Dx) and the iterate (4 D), write the new
+    iterate (4 D)."""
+    return 4 * Dx + 8 * D
 
 
-def adj_local_bytes(D):
-    """Algorithmic HBM bytes per step of one adjoint iteration after the first (FP32): read
-    lambda^(k-1), the step map (la, written once, and lc of the previous iteration), the gate
-    values alpha, beta, gamma, the pair (z, diag A) and g; write lambda^(k) and the new lc."""
-    return 4 * D + 8 * D + 12 * D + 8 * D + 4 * D + 4 * D + 4 * D
+def adj_iter_bytes(D):
+    """Algorithmic HBM bytes per step of one adjoint iteration: the VJP operands lambda,
+    alpha, beta, gamma, z and g (24 D) and the diagonal scan's transition, additive term, old
+    and new iterate (16 D): 40 D (1.5 GiB + 1.07 GB per iteration at D = 64, N = 2^20)."""
+    return 40 * D
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gru64_hbm_traffic.txt")
+TRAFFIC_FILES = {WORKLOAD: os.path.join(ROOT, "profiles", "gru48_ragged_hbm_traffic.txt"),
+                 SECONDARY: os.path.join(ROOT, "profiles", "gru64_hbm_traffic.txt")}
 SOURCES = {"gru_quasi_local": ["gru_quasi.hip", "gru_common.hpp", "pn_device.hpp"],
            "gru_adj_local": ["gru_adjoint.hip", "gru_common.hpp", "pn_device.hpp"]}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the kernel's sources changed after the counters were taken."""
+def source_sha(kernel):
     import hashlib
-    try:
-        text = open(TRAFFIC_FILE).read()
-    except OSError:
-        return None
     h = hashlib.sha256()
     for f in SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2603_16850_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    sha, cur = h.hexdigest()[:16], None
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per working launch of `kernel` from the committed rocprofv3 counter summary
+    of `workload`, or None when the kernel's sources changed after the counters were taken."""
+    try:
+        text = open(TRAFFIC_FILES[workload]).read()
+    except (OSError, KeyError):
+        return None
+    sha, cur = source_sha(kernel), None
     for line in text.splitlines():
         line = line.strip()
         if line.startswith("kernel:"):
@@ -89,12 +102,13 @@ def measured_traffic(kernel):
     return None
 
 
-def roofline_of(kernel, D, Dx, N, avg_ms):
-    """Both ceilings of a launch over N steps; the binding one (longer time at peak) wins."""
+def roofline_of(kernel, D, Dx, units, avg_ms):
+    """Both ceilings of a launch over `units` sequence-steps; the binding one (the longer time
+    at peak) is reported."""
     if kernel == "gru_quasi_local":
-        flops, nbytes = gate_gemm_flops(D, Dx) * N, fwd_local_bytes(D, Dx) * N
+        flops, nbytes = gate_gemm_flops(D, Dx) * units, fwd_iter_bytes(D, Dx) * units
     else:
-        flops, nbytes = vjp_gemm_flops(D) * N, adj_local_bytes(D) * N
+        flops, nbytes = vjp_gemm_flops(D) * units, adj_iter_bytes(D) * units
     t_mfma = flops / (PEAK_FP32_TFLOPS * 1e12)
     t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
     if t_mfma >= t_hbm:
@@ -108,29 +122,144 @@ def roofline_of(kernel, D, Dx, N, avg_ms):
             "algorithmic_per_launch": nbytes}
 
 
+def run_workload(torch, pn, work, inst, args, steps, warmup):
+    """Tunes, warms up, times `steps` fwd+bwd steps on the default (graph) path, then one
+    profiled step for the kernel figures and the sequential GPU baseline."""
+    D, Dx, N = work.D, work.Dx, inst.N
+    dev = "cuda"
+    x = torch.tensor(inst.x, dtype=torch.float32, device=dev)
+    s0 = torch.tensor(inst.s0, dtype=torch.float32, device=dev)
+    p = torch.tensor(inst.params, dtype=torch.float32, device=dev)
+    kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol,
+              graph_iters=GRAPH_ITERS, freeze_prefix=args.freeze)
+    kw_f, kw_b = dict(kw), dict(kw, tol=args.adj_tol)
+    tuned = None
+    if args.tile == "auto":
+        # one-time plan: the autotuner times the candidate tile / group lengths of both passes
+        # on these inputs (8 iterations each); excluded from the timed region, reported
+        torch.cuda.synchronize()
+        tt0 = time.perf_counter()
+        tf = pn.autotune("deer", x, s0, p, probe_iters=8, **kw)
+        s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
+        tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8, **kw_b)
+        torch.cuda.synchronize()
+        tuned = {"tune_ms": round((time.perf_counter() - tt0) * 1e3, 1),
+                 "fwd": {k: tf[k] for k in ("tile", "group", "ms_per_iter", "from_cache")},
+                 "adj": {k: tb[k] for k in ("group", "ms_per_iter", "from_cache")}}
+        kw_f.update(tile=tf["tile"], group=tf["group"])
+        kw_b.update(group=tb["group"])
+        del s_tr
+    elif args.tile != "default":
+        L, G, GA = (int(v) for v in args.tile.split(","))
+        kw_f.update(tile=L, group=G)
+        kw_b.update(group=GA)
+        tuned = {"given": {"fwd_tile": L, "fwd_group": G, "adj_group": GA}}
+
+    def step():
+        s, finfo = pn.deer_solve(x, s0, p, **kw_f)
+        gp, gx, g0, binfo = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw_b)
+        return s, gp, gx, g0, finfo, binfo
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"bench: {work.name} warmup done", file=sys.stderr, flush=True)
+
+    # ---- timed region: K full steps on the library's default path (graph-captured
+    # iterations, the stopping state read every GRAPH_ITERS iterations)
+    step_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        out = step()              # the solvers return after their work finished
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s, gp, gx, g0, finfo, binfo = out
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    print(f"bench: {work.name} timed region done ({ms_per_step:.2f} ms/step)", file=sys.stderr,
+          flush=True)
+
+    # ---- one profiled step (direct launches, a HIP event pair around every kernel)
+    with pn.profile():
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        prof_ms = (time.perf_counter() - tp0) * 1e3
+        fam = {f: pn.profile.read(f) for f in FAMILIES}
+        idle = {f: pn.profile.read(f + "#idle") for f in ("gru_quasi_local", "gru_adj_local")}
+
+    # ---- sequential GPU baseline on the same inputs (one warm-up call, then timed)
+    def seq_step():
+        sq = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
+        pn.seq_bptt(x, s0, p, sq, 2.0 * sq, cell="gru", offsets=inst.offsets)
+        return sq
+    seq_step()
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    for _ in range(args.seq_reps):
+        s_seq = seq_step()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - ts0) * 1e3 / args.seq_reps
+    print(f"bench: {work.name} sequential baseline done ({seq_ms:.2f} ms)", file=sys.stderr,
+          flush=True)
+
+    it_f = [i["iters"] for i in finfo]
+    it_b = [i["iters"] for i in binfo]
+    lens = np.diff(inst.offsets)
+    kernels = {}
+    for name, its in (("gru_quasi_local", it_f), ("gru_adj_local", it_b)):
+        tot, n = fam[name]
+        # every sequence is worked on by the launches of iterations 0 .. iters (the last one
+        # tests the final iterate): units = sequence-steps processed per launch, averaged
+        units = float(np.sum((np.asarray(its) + 1) * lens)) / max(n, 1)
+        avg = tot / max(n, 1)
+        rl = roofline_of(name, D, Dx, units, avg)
+        idle_ms, idle_n = idle[name]
+        rl.update({"avg_launch_ms": round(avg, 4), "launches": n,
+                   "units_per_launch": round(units, 1),
+                   "avg_launch_ms_with_idle": round((tot + idle_ms) / max(n + idle_n, 1), 4),
+                   "idle_launches": idle_n,
+                   "traffic": measured_traffic(work.name, name), "source_sha": source_sha(name)})
+        kernels[name] = rl
+    dom = max(kernels, key=lambda k: fam[k][0])
+    converged = all(i["converged"] for i in finfo) and all(i["converged"] for i in binfo)
+    return {
+        "ms_per_step": ms_per_step, "step_ms": step_ms, "value": N / (ms_per_step * 1e-3),
+        "seq_ms": seq_ms, "iters_fwd": it_f, "iters_bwd": it_b, "converged": converged,
+        "kernels": kernels, "dominant": dom, "profiled_step_ms": prof_ms,
+        "kernel_ms": {k: {"total": round(v[0], 3), "launches": v[1]} for k, v in fam.items()},
+        "tuned": tuned, "out": (s, gp, gx, g0, s_seq), "kw_f": kw_f, "kw_b": kw_b,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-6,
-                    help="residual stopping tolerance (1e-6 keeps the error under 1e-5)")
+                    help="residual stopping tolerance of the forward (1e-6 keeps the trajectory "
+                         "error under 1e-5)")
     ap.add_argument("--adj-tol", type=float, default=1e-5,
                     help="stopping tolerance of the adjoint (max |rho| <= tol max(1, max |g|)); "
                          "the workload's stated 1e-5, which keeps the gradients within 1e-5 of "
-                         "the FP64 oracle (the forward needs 1e-6 for its trajectory)")
-    ap.add_argument("--seq-reps", type=int, default=1)
+                         "the FP64 oracle")
+    ap.add_argument("--freeze", action="store_true",
+                    help="converged-prefix skipping in both passes")
+    ap.add_argument("--seq-reps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary workload (16 x 65536 steps, D = 64)")
+    ap.add_argument("--secondary-steps", type=int, default=5)
     ap.add_argument("--rows", action="store_true",
                     help="also measure the other workloads and method variants (adds a 'rows' "
                          "object to the line; a few minutes)")
     ap.add_argument("--rows-sections", type=int, default=0,
                     help="with --rows: measure only the first N sections (0 = all); section 2 is "
                          "the dense tanh D = 32 forward and adjoint")
-    ap.add_argument("--graphs", action="store_true",
-                    help="also time the step with graph-captured iterations (not the value)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="accepted for older command lines; the 1 GiB copy always runs")
     ap.add_argument("--sweep-lle", action="store_true",
                     help="instead of the step: the mean-field RNN LLE-threshold sweep (one "
                          "JSON line per gain and length)")
@@ -157,10 +286,17 @@ def main():
         return
     work = workloads.ALL[WORKLOAD]
     inst = workloads.make_instance(work, seed=0)
-    D, Dx, B, N = work.D, work.Dx, work.B, inst.N
+    work2 = workloads.ALL[SECONDARY]
+    inst2 = None if args.no_secondary else workloads.make_instance(work2, seed=0)
 
     # the CPU oracle runs first, in worker processes forked before anything touches the GPU
-    cpu = None if args.no_cpu else cpu_oracle(inst)
+    cpu = cpu2 = None
+    if not args.no_cpu:
+        cpu = cpu_oracle(inst)
+        print(f"bench: CPU oracle of {work.name} done", file=sys.stderr, flush=True)
+        if inst2 is not None:
+            cpu2 = cpu_oracle(inst2)
+            print(f"bench: CPU oracle of {work2.name} done", file=sys.stderr, flush=True)
 
     import torch
     import paper_2603_16850_amd as pn
@@ -169,142 +305,71 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     pn.load()
-    dev = "cuda"
-    x = torch.tensor(inst.x, dtype=torch.float32, device=dev)
-    s0 = torch.tensor(inst.s0, dtype=torch.float32, device=dev)
-    p = torch.tensor(inst.params, dtype=torch.float32, device=dev)
-    # The host reads the stopping state every GRAPH_ITERS iterations.  Inside the timed region
-    # the iterations of a batch are launched back to back with a HIP event pair around each
-    # kernel; launches of iterations after the last sequence stopped return at once and are
-    # not counted in the per-kernel averages.
-    kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol, graph_iters=GRAPH_ITERS)
-    adj_tol = args.adj_tol
-    kw_f, kw_b, tuned = dict(kw), dict(kw, tol=adj_tol), None
-    if args.tile == "auto":
-        # one-time plan: the autotuner times the candidate tile / group lengths of both passes
-        # on these inputs (8 iterations each); excluded from the timed region, reported
-        torch.cuda.synchronize()
-        tt0 = time.perf_counter()
-        tf = pn.autotune("deer", x, s0, p, probe_iters=8, **kw)
-        s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
-        tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8,
-                         **dict(kw, tol=adj_tol))
-        torch.cuda.synchronize()
-        tuned = {"tune_ms": round((time.perf_counter() - tt0) * 1e3, 1),
-                 "fwd": {k: tf[k] for k in ("tile", "group", "ms_per_iter", "from_cache")},
-                 "adj": {k: tb[k] for k in ("group", "ms_per_iter", "from_cache")},
-                 "fwd_candidates": tf["candidates"], "adj_candidates": tb["candidates"]}
-        kw_f.update(tile=tf["tile"], group=tf["group"])
-        kw_b.update(group=tb["group"])
-        del s_tr
-    elif args.tile != "default":
-        L, G, GA = (int(v) for v in args.tile.split(","))
-        kw_f.update(tile=L, group=G)
-        kw_b.update(group=GA)
-        tuned = {"given": {"fwd_tile": L, "fwd_group": G, "adj_group": GA}}
 
-    def step():
-        s, finfo = pn.deer_solve(x, s0, p, **kw_f)
-        gp, gx, g0, binfo = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw_b)
-        return s, gp, gx, g0, finfo, binfo
+    r = run_workload(torch, pn, work, inst, args, args.steps, args.warmup)
+    s, gp, gx, g0, s_seq = r["out"]
+    err = errors(cpu, s, gp, gx, g0, s_seq) if cpu is not None else None
+    err_ok = None if err is None else all(err[k] <= ERR_BAR for k in ("s", "gparams", "gx", "gs0"))
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # ---- timed region: K full steps, kernel durations by HIP events on the library stream
-    step_ms = []
-    with pn.profile():
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ts = time.perf_counter()
-            out = step()          # the solvers return after their work finished
-            step_ms.append((time.perf_counter() - ts) * 1e3)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        fam = {f: pn.profile.read(f) for f in FAMILIES}
-    s, gp, gx, g0, finfo, binfo = out
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = N / (ms_per_step * 1e-3)
-
-    # ---- sequential GPU baseline on the same inputs
-    torch.cuda.synchronize()
-    ts0 = time.perf_counter()
-    for _ in range(args.seq_reps):
-        s_seq = pn.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
-        sg = pn.seq_bptt(x, s0, p, s_seq, 2.0 * s_seq, cell="gru", offsets=inst.offsets)
-    torch.cuda.synchronize()
-    ts1 = time.perf_counter()
-    seq_ms = (ts1 - ts0) * 1e3 / args.seq_reps
-    seq_value = N / (seq_ms * 1e-3)
-
-    # device-to-device copy of 1 GiB: the achievable HBM rate on this machine (read + write), and
-    # the reference dispatch for the FETCH_SIZE / WRITE_SIZE counter scaling
-    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    tc0 = time.perf_counter()
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    copy_gbs = 3 * 2 * a.numel() * 4 / (time.perf_counter() - tc0) / 1e9
-    del a, b
-
-    # ---- roofline of the dominant kernel (largest share of the measured kernel time).
-    # Launches that find every sequence stopped return at once; the average is taken over
-    # the launches that did an iteration (one per iteration of the longest sequence, plus
-    # the one that tests the last iterate).
-    it_f = [i["iters"] for i in finfo]
-    it_b = [i["iters"] for i in binfo]
-    dom = max(("gru_quasi_local", "gru_adj_local"), key=lambda f: fam[f][0])
-    dms, dn = fam[dom]
-    avg_ms = dms / max(dn, 1)
-    roofline = roofline_of(dom, D, Dx, N, avg_ms)
-    roofline.update({"traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 4),
-                     "launches": dn})
+    # the achievable HBM rate of a plain streaming copy on this device (project kernel)
+    copy_gbs = pn.copy_bandwidth(1 << 30, 5)
+    roofline = dict(r["kernels"][r["dominant"]])
     if roofline["bound"] == "hbm":
         roofline["frac_of_measured_copy"] = round(roofline["achieved"] / copy_gbs, 4)
-
-    # optionally the same step with the library's defaults (iterations captured in HIP graphs,
-    # stopping state read every 4 iterations), outside the timed region
-    ms_graph = None
-    if args.graphs:
-        torch.cuda.synchronize()
-        tg0 = time.perf_counter()
-        for _ in range(args.steps):
-            pn.deer_solve(x, s0, p, **dict(kw_f, graph_iters=4))
-            pn.deer_adjoint(x, s0, p, s, 2.0 * s, **dict(kw_b, graph_iters=4))
-        torch.cuda.synchronize()
-        ms_graph = round((time.perf_counter() - tg0) * 1e3 / args.steps, 3)
+    roofline["measured"] = ("HIP events on the library stream around every launch of one "
+                            "profiled step after the timed region (direct launches)")
 
     rec = {
-        "metric": METRIC, "value": round(value, 1), "unit": "sequence-steps/s",
+        "metric": METRIC, "value": round(r["value"], 1), "unit": "sequence-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": round(r["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "cell": "gru", "D": D, "Dx": Dx, "B": B,
-                   "T": work.T, "N": N, "method": "quasi-DEER fwd + exact quasi adjoint",
-                   "tol": args.tol, "adj_tol": adj_tol, "loss": "sum_t ||s_t||^2",
-                   "graph_iters": GRAPH_ITERS},
-        "iters_fwd": it_f, "iters_bwd": it_b,
-        "kernel_ms": {k: {"total": round(v[0], 3), "launches": v[1]} for k, v in fam.items()},
-        "sequential_gpu": {"value": round(seq_value, 1), "unit": "sequence-steps/s",
-                           "ms_per_step": round(seq_ms, 3)},
-        "speedup_vs_sequential": round(value / seq_value, 2),
-        "step_ms_median": round(float(np.median(step_ms)), 3),
-        "step_ms_iqr": round(float(np.percentile(step_ms, 75) - np.percentile(step_ms, 25)), 3),
-        "copy_bandwidth_gbs": round(copy_gbs, 1),
-        "ms_per_step_graphs": ms_graph,
+        "config": {"workload": WORKLOAD, "cell": "gru", "D": work.D, "Dx": work.Dx,
+                   "B": work.B, "T": f"U{{{work.t_min}..{work.t_max}}}", "N": inst.N,
+                   "method": "quasi-DEER fwd + exact quasi adjoint",
+                   "tol": args.tol, "adj_tol": args.adj_tol, "loss": "sum_t ||s_t||^2",
+                   "graph_iters": GRAPH_ITERS, "path": "hipGraph-captured iterations",
+                   "freeze_prefix": args.freeze},
+        "valid": bool(r["converged"] and (err_ok is not False)),
+        "converged": r["converged"], "err_ok": err_ok, "err": err,
+        "iters_fwd_max": max(r["iters_fwd"]), "iters_bwd_max": max(r["iters_bwd"]),
+        "iters_fwd_mean": round(float(np.mean(r["iters_fwd"])), 2),
+        "iters_bwd_mean": round(float(np.mean(r["iters_bwd"])), 2),
+        "step_ms_median": round(float(np.median(r["step_ms"])), 3),
+        "step_ms_iqr": round(float(np.percentile(r["step_ms"], 75)
+                                   - np.percentile(r["step_ms"], 25)), 3),
+        "sequential_gpu": {"value": round(inst.N / (r["seq_ms"] * 1e-3), 1),
+                           "unit": "sequence-steps/s", "ms_per_step": round(r["seq_ms"], 3),
+                           "kernels": "one wave per sequence: rollout, then backward"},
+        "speedup_vs_sequential": round(r["seq_ms"] / r["ms_per_step"], 3),
         "roofline": roofline,
-        "autotune": tuned,
+        "kernels": r["kernels"],
+        "kernel_ms_profiled_step": r["kernel_ms"],
+        "profiled_step_ms": round(r["profiled_step_ms"], 3),
+        "copy_bandwidth_gbs": round(copy_gbs, 1),
+        "autotune": r["tuned"],
     }
-
     if cpu is not None:
         rec["cpu_baseline"] = cpu["baseline"]
         rec["cpu_single_core"] = cpu["single_core"]
-        rec["err"] = errors(cpu, s, gp, gx, g0, s_seq)
+    del r
+    if inst2 is not None:
+        r2 = run_workload(torch, pn, work2, inst2, args, args.secondary_steps, 1)
+        s, gp, gx, g0, s_seq = r2["out"]
+        e2 = errors(cpu2, s, gp, gx, g0, s_seq) if cpu2 is not None else None
+        rec["secondary"] = {
+            "workload": SECONDARY, "D": work2.D, "Dx": work2.Dx, "B": work2.B, "T": work2.T,
+            "N": inst2.N, "steps": args.secondary_steps,
+            "value": round(r2["value"], 1), "unit": "sequence-steps/s",
+            "ms_per_step": round(r2["ms_per_step"], 3),
+            "sequential_ms": round(r2["seq_ms"], 3),
+            "speedup_vs_sequential": round(r2["seq_ms"] / r2["ms_per_step"], 3),
+            "converged": r2["converged"], "err": e2,
+            "iters_fwd_max": max(r2["iters_fwd"]), "iters_bwd_max": max(r2["iters_bwd"]),
+            "kernels": r2["kernels"], "dominant": r2["dominant"], "autotune": r2["tuned"],
+            "cpu_baseline": None if cpu2 is None else cpu2["baseline"],
+        }
+        del r2
     if args.rows:
         rec["rows"] = measure_rows(torch, pn, workloads, args.rows_sections)
     print(json.dumps(rec), flush=True)
@@ -605,7 +670,9 @@ def cpu_oracle(inst):
     cell = cells.GRU(inst.params, w.D, w.Dx)
     off = inst.offsets
     jobs = [(cell, inst.x[off[b]:off[b + 1]], inst.s0[b]) for b in range(w.B)]
-    ncores = max(1, min(16, os.cpu_count() or 1))
+    # one single-threaded worker per core, at most 16 (the host share of one GPU)
+    ncpu = os.cpu_count() or 1
+    ncores = max(1, min(16, ncpu))
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -632,13 +699,16 @@ def cpu_oracle(inst):
     gx = np.concatenate([r[2] for r in res])
     g0 = np.stack([r[3] for r in res])
     t_b = int(off[1] - off[0])
+    shape = (f"{w.B} x {w.T}" if w.T else
+             f"{w.B} sequences of U{{{w.t_min}..{w.t_max}}}, {inst.N} steps")
     return {
         "s": s, "gp": gp, "gx": gx, "g0": g0,
         "baseline": {"value": round(inst.N / dt, 1), "unit": "sequence-steps/s",
                      "cores": ncores, "kind": "oracle",
-                     "sample": f"whole workload ({w.B} x {w.T} steps): FP64 numpy sequential "
+                     "sample": f"whole workload ({shape}): FP64 numpy sequential "
                                f"rollout + sequential adjoint, one sequence per single-threaded "
-                               f"worker, {ncores} workers, {dt:.1f} s; CPU {model}"},
+                               f"worker, {ncores} workers ({ncpu} CPUs visible), {dt:.1f} s; "
+                               f"CPU {model}"},
         "single_core": {"value": round(t_b / dt1, 1), "unit": "sequence-steps/s", "cores": 1,
                         "sample": f"one sequence ({t_b} steps), {dt1:.1f} s"},
     }

@@ -276,7 +276,8 @@ pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const
    pn_profile_end() the solvers called on this thread launch their iterations directly (no
    graph) and record a HIP event pair around every launch of their main kernels on the caller's
    stream; pn_profile_read() returns the summed duration and launch count of a kernel family
-   (launches of iterations after the one that stopped the last sequence are not counted):
+   (launches of iterations after the one that stopped the last sequence return at once; they
+   are counted under the family name followed by "#idle"):
      deer_solve GRU diagonal: "gru_quasi_local", "carry_scan";
      deer_adjoint GRU: "gru_adj_prep", "gru_adj_local", "carry_scan", "gru_adj_grad";
      deer_solve tanh dense: "tanh_dense_local", "dense_carry";
@@ -328,6 +329,15 @@ pn_status pn_autotune(int op, const pn_cell_desc* cell, const pn_batch* batch,
                       void* stream, pn_tuned* out);
 /* Forget the in-process autotune results (the cache file is left as it is). */
 void pn_autotune_reset(void);
+
+/* Copy-bandwidth probe: copies `bytes` (a positive multiple of 16) from src to dst (device,
+   16-byte aligned, not overlapping) with a plain streaming kernel, once untimed and then
+   `reps` times between HIP events on `stream`, and returns in *gbs (host) the achieved rate
+   counting read plus write bytes (2 * bytes * reps / time).  It gives the HBM rate a simple
+   kernel reaches on the device, next to the published peak, and a dispatch of known size for
+   scaling the FETCH_SIZE / WRITE_SIZE counters (kernel copy_probe_kernel). */
+pn_status pn_copy_probe(const void* src, void* dst, size_t bytes, int reps, void* stream,
+                        double* gbs);
 
 void pn_profile_begin(void);
 void pn_profile_end(void);

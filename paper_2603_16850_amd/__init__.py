@@ -86,6 +86,8 @@ SIGNATURES = [
                                    ctypes.c_double, _P(Opts), ctypes.c_int32, _V,
                                    ctypes.c_size_t, _V, _P(Tuned)]),
     ("pn_autotune_reset", None, []),
+    ("pn_copy_probe", ctypes.c_int, [_V, _V, ctypes.c_size_t, ctypes.c_int, _V,
+                                     _P(ctypes.c_double)]),
     ("pn_profile_begin", None, []),
     ("pn_profile_end", None, []),
     ("pn_profile_read", ctypes.c_int, [ctypes.c_char_p, _P(ctypes.c_double),
@@ -414,6 +416,17 @@ def seq_bptt(x, s0, params, s, gs, cell="gru", offsets=None):
                            _ptr(s), _ptr(gs), _ptr(gx), _ptr(g0), _ptr(gp), _aligned(ws), nb,
                            _stream()))
     return gp, gx, g0
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """pn_copy_probe on two fresh device buffers: GB/s (read + write) of a streaming copy."""
+    torch = _torch()
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    out = ctypes.c_double(0.0)
+    _check(load().pn_copy_probe(_ptr(a), _ptr(b), int(nbytes), int(reps), _stream(),
+                                ctypes.byref(out)))
+    return out.value
 
 
 class profile:

@@ -84,13 +84,19 @@ void prof_launch(const char* family, hipStream_t stream,
 }
 
 // Launches of iterations after `last` found every sequence stopped and returned at once: they
-// are not counted.
+// are counted apart, under the family name with "#idle" appended.
 static void prof_drop_after(int last) {
     ProfRec& r = prof();
     std::vector<ProfPending> keep;
     for (auto& p : r.pending) {
         if (p.iter > last) {
-            (void)hipEventSynchronize(p.ev.second);
+            float ms = 0.f;
+            if (hipEventSynchronize(p.ev.second) == hipSuccess &&
+                hipEventElapsedTime(&ms, p.ev.first, p.ev.second) == hipSuccess) {
+                auto& t = r.totals[p.family + "#idle"];
+                t.first += ms;
+                t.second += 1;
+            }
             r.pool.push_back(p.ev);
         } else {
             keep.push_back(p);

@@ -721,55 +721,92 @@ __global__ void gru_adj_gs0_kernel(GruAdjArgs a) {
 }
 
 // ---- sequential adjoint (baseline): lambda_t = g_t + A_{t+1}^T lambda_{t+1}, one step at a
-// time per sequence; lanes 4j..4j+3 of a wave serve unit j (U_z^T, U_n^T, U_r^T columns).
+// time per sequence, one wave per sequence.  Lane j owns unit j and holds the columns j of
+// U_z, U_n and U_r in registers; per step it writes its three VJP operands alpha_j lambda_j,
+// beta_j lambda_j, gamma_j lambda_j to LDS, reads all 3 D of them back (a single wave's LDS
+// operations complete in order: no barrier) and forms
+//   (A_t^T lambda_t)_j = z_j lambda_j + sum_i (U_z[i][j] alpha_i + U_n[i][j] beta_i
+//                                               + U_r[i][j] gamma_i) lambda_i.
+// The per-step operands (g, alpha, beta, gamma, z) of the next PF steps are prefetched.
 template <int D>
-__global__ void __launch_bounds__(4 * D) gru_seq_adj_kernel(const float* gates, const float2* zd,
-                                                            const float* gs, const float* U,
-                                                            float* lam, const int64_t* offsets) {
-    constexpr int CH = 32;
-    __shared__ float prod[2][3][D];
-    __shared__ float gch[CH][4 * D];
-    __shared__ float zch[CH][D];
-    __shared__ float gsch[CH][D];
+__global__ void __launch_bounds__(64) gru_seq_adj_kernel(const float* __restrict__ gates,
+                                                         const float2* __restrict__ zd,
+                                                         const float* __restrict__ gs,
+                                                         const float* __restrict__ U,
+                                                         float* __restrict__ lam,
+                                                         const int64_t* __restrict__ offsets) {
+    static_assert(D % 4 == 0 && D <= 64, "one lane per unit");
+    constexpr int PF = 4;
+    __shared__ __attribute__((aligned(16))) float prod[2][3][D];
     const int b = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int j = tid >> 2, role = tid & 3, base = (tid & 63) & ~3;
+    const int j = threadIdx.x;
+    const bool act = j < D;
+    const int jj = act ? j : 0;
     const int64_t r0 = offsets[b], T = offsets[b + 1] - r0;
-    float w[D];
-    const int mrow = role == 0 ? 0 : (role == 1 ? 2 * D : D);   // U_z, U_n, U_r
+    if (T == 0) return;                      // nothing to walk (and no row to prefetch)
+    float wz[D], wn[D], wr[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) w[i] = role < 3 ? U[(mrow + i) * D + j] : 0.f;
-    const int plane = role;                                      // alpha, beta, gamma
-    float v = 0.f;                                               // A_{t+1}^T lambda_{t+1}
-    for (int64_t t = T - 1; t >= 0; --t) {
-        const int64_t cb = t - (t % CH);                         // chunk [cb, cb + CH)
-        if (t % CH == CH - 1 || t == T - 1) {
-            __syncthreads();
-            for (int idx = tid; idx < CH * 4 * D; idx += blockDim.x) {
-                const int r = idx / (4 * D), c = idx % (4 * D);
-                gch[r][c] = (cb + r < T) ? gates[(size_t)(r0 + cb + r) * 4 * D + c] : 0.f;
-            }
-            for (int idx = tid; idx < CH * D; idx += blockDim.x) {
-                const int r = idx / D, c = idx % D;
-                gsch[r][c] = (cb + r < T) ? gs[(size_t)(r0 + cb + r) * D + c] : 0.f;
-                zch[r][c] = (cb + r < T) ? zd[(size_t)(r0 + cb + r) * D + c].x : 0.f;
-            }
-            __syncthreads();
-        }
-        const int rr = (int)(t - cb);
-        const float lt = gsch[rr][j] + v;
-        const float z = zch[rr][j];
-        if (role == 0) lam[(size_t)(r0 + t) * D + j] = lt;
-        const int p = (int)(t & 1);
-        if (role < 3) prod[p][role][j] = gch[rr][plane * D + j] * lt;
-        __syncthreads();
-        float acc = 0.f;
-        if (role < 3) {
-#pragma unroll
-            for (int i = 0; i < D; ++i) acc += w[i] * prod[p][role][i];
-        }
-        v = z * lt + __shfl(acc, base) + __shfl(acc, base + 1) + __shfl(acc, base + 2);
+    for (int i = 0; i < D; ++i) {
+        wz[i] = U[(size_t)i * D + jj];               // U_z[i][j]
+        wr[i] = U[(size_t)(D + i) * D + jj];         // U_r[i][j]
+        wn[i] = U[(size_t)(2 * D + i) * D + jj];     // U_n[i][j]
     }
+    struct Ops { float g, al, be, ga, z; };          // g, alpha, beta, gamma, z of one step
+    auto fetch = [&](int64_t it) {
+        const int64_t row = r0 + (T - 1 - it);
+        const float* gr = gates + (size_t)row * 4 * D;
+        return Ops{gs[(size_t)row * D + jj], gr[jj], gr[D + jj], gr[2 * D + jj],
+                   zd[(size_t)row * D + jj].x};
+    };
+    float v = 0.f;                                   // A_{t+1}^T lambda_{t+1}
+    // reverse step it (t = T - 1 - it): lambda_t = g_t + v, then v <- A_t^T lambda_t
+    auto step = [&](int64_t it, const Ops& o) {
+        const int64_t t = T - 1 - it;
+        const float lt = o.g + v;
+        float* pb = &prod[it & 1][0][0];
+        if (act) {
+            lam[(size_t)(r0 + t) * D + j] = lt;
+            pb[j] = o.al * lt;
+            pb[D + j] = o.be * lt;
+            pb[2 * D + j] = o.ga * lt;
+        }
+        __builtin_amdgcn_wave_barrier();
+        float a0 = o.z * lt, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < D; k += 4) {
+            const float4 pz4 = *(const float4*)(pb + k);
+            const float4 pn4 = *(const float4*)(pb + D + k);
+            const float4 pr4 = *(const float4*)(pb + 2 * D + k);
+            a0 = fmaf(wz[k], pz4.x, a0);
+            a1 = fmaf(wn[k], pn4.x, a1);
+            a2 = fmaf(wr[k], pr4.x, a2);
+            a0 = fmaf(wz[k + 1], pz4.y, a0);
+            a1 = fmaf(wn[k + 1], pn4.y, a1);
+            a2 = fmaf(wr[k + 1], pr4.y, a2);
+            a0 = fmaf(wz[k + 2], pz4.z, a0);
+            a1 = fmaf(wn[k + 2], pn4.z, a1);
+            a2 = fmaf(wr[k + 2], pr4.z, a2);
+            a0 = fmaf(wz[k + 3], pz4.w, a0);
+            a1 = fmaf(wn[k + 3], pn4.w, a1);
+            a2 = fmaf(wr[k + 3], pr4.w, a2);
+        }
+        v = a0 + a1 + a2;
+        __builtin_amdgcn_wave_barrier();
+    };
+    const int64_t Tm = T - T % PF;
+    Ops ring[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) ring[i] = fetch(i < Tm ? i : 0);
+    for (int64_t it0 = 0; it0 < Tm; it0 += PF) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const Ops o = ring[i];
+            const int64_t itn = it0 + i + PF < Tm ? it0 + i + PF : it0 + i;
+            ring[i] = fetch(itn);
+            step(it0 + i, o);
+        }
+    }
+    for (int64_t it = Tm; it < T; ++it) step(it, fetch(it));
 }
 
 // ---- host driver ------------------------------------------------------------------------------
@@ -1007,7 +1044,7 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
                            dim3(kk.nt), 0, stream, args);
     const float* U = (const float*)cd.params + 3 * D * Dx;
     prof_launch("seq_adj", stream, [&](hipStream_t s2) {
-        hipLaunchKernelGGL(seqk, dim3(hb.B), dim3(4 * D), 0, s2, (const float*)lay.gates,
+        hipLaunchKernelGGL(seqk, dim3(hb.B), dim3(64), 0, s2, (const float*)lay.gates,
                            (const float2*)lay.zd, gs, U, lay.lam[0],
                            (const int64_t*)lay.st.offsets);
     });

@@ -2,9 +2,8 @@
 // Problem Statement "Unrolling an SSM"), one workgroup per sequence.
 //
 // As in library RNN layers, the input projections W x_t + b of every step are computed first
-// by a parallel kernel; the recurrence then only evaluates the h-dependent part.  For the GRU,
-// four lanes of one wave serve each unit (z, r and U_n h dot products, the fourth idle), meet
-// by cross-lane shuffles, and one barrier per step publishes the new state in LDS.
+// by a parallel kernel; the recurrence then only evaluates the h-dependent part, in one wave
+// per sequence with no workgroup barrier on the step chain.
 #include <algorithm>
 
 #include "pn_host.hpp"
@@ -44,102 +43,156 @@ __global__ void __launch_bounds__(256) xproj_kernel(const float* x, const float*
     }
 }
 
+// One wave per sequence, lane j owns unit j: the rows j of U_z, U_r and U_n live in the lane's
+// registers, the state is exchanged through LDS (a single wave's LDS operations complete in
+// order, so no barrier is needed), and the input projections of the next PF steps are
+// prefetched into registers while the current step computes.  Per step a lane issues 3 D
+// FMAs (three independent dot-product chains) and one LDS write; nothing else waits.
 template <int D>
-__global__ void __launch_bounds__(4 * D) gru_seq_kernel(const float* P, const float* s0,
-                                                        const float* U, const float* bhn,
-                                                        float* s, const int64_t* offsets) {
-    constexpr int CH = 32;
+__global__ void __launch_bounds__(64) gru_seq_kernel(const float* __restrict__ P,
+                                                     const float* __restrict__ s0,
+                                                     const float* __restrict__ U,
+                                                     const float* __restrict__ bhn,
+                                                     float* __restrict__ s,
+                                                     const int64_t* __restrict__ offsets) {
+    static_assert(D % 4 == 0 && D <= 64, "one lane per unit");
+    constexpr int PF = 4;                    // prefetch depth (steps)
     __shared__ __attribute__((aligned(16))) float hbuf[2][D];
-    __shared__ float pch[CH][3 * D];
     const int b = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int j = tid >> 2, role = tid & 3, base = (threadIdx.x & 63) & ~3;
+    const int j = threadIdx.x;
+    const bool act = j < D;
+    const int jj = act ? j : 0;
     const int64_t r0 = offsets[b], T = offsets[b + 1] - r0;
-    float w[D];
-    const int wrow = role == 0 ? j : (role == 1 ? D + j : 2 * D + j);   // U_z, U_r, U_n rows
+    if (T == 0) return;                      // nothing to walk (and no row to prefetch)
+    float wz[D], wr[D], wq[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) w[k] = role < 3 ? U[wrow * D + k] : 0.f;
-    const float b_hn = bhn[j];
-    if (tid < D) hbuf[0][tid] = s0[(size_t)b * D + tid];
-    __syncthreads();
-    for (int64_t t = 0; t < T; ++t) {
-        if (t % CH == 0) {
-            for (int idx = tid; idx < CH * 3 * D; idx += blockDim.x) {
-                const int r = idx / (3 * D), c = idx % (3 * D);
-                pch[r][c] = (t + r < T) ? P[(size_t)(r0 + t + r) * 3 * D + c] : 0.f;
-            }
-            __syncthreads();
-        }
-        const int cur = (int)(t & 1);
-        const float* h = hbuf[cur];
-        float acc = 0.f;
+    for (int k = 0; k < D; ++k) {
+        wz[k] = U[(size_t)jj * D + k];
+        wr[k] = U[(size_t)(D + jj) * D + k];
+        wq[k] = U[(size_t)(2 * D + jj) * D + k];
+    }
+    const float b_hn = bhn[jj];
+    float h = act ? s0[(size_t)b * D + j] : 0.f;
+    if (act) hbuf[0][j] = h;
+    float pz[PF], pr[PF], pn[PF];
+    // Step t: the gates from the state in hbuf[t & 1] and the projections (cz, cr, cn); the
+    // new state goes to hbuf[(t + 1) & 1] and to s.  Same gate arithmetic as the parallel
+    // solver's GRU kernels (exponential and hardware reciprocal).
+    auto step = [&](int64_t t, float cz, float cr, float cn) {
+        const float* hc = hbuf[t & 1];
+        float az0 = 0.f, ar0 = 0.f, aq0 = 0.f, az1 = 0.f, ar1 = 0.f, aq1 = 0.f;
 #pragma unroll
         for (int k = 0; k < D; k += 4) {
-            const float4 h4 = *(const float4*)(h + k);
-            acc += w[k] * h4.x + w[k + 1] * h4.y + w[k + 2] * h4.z + w[k + 3] * h4.w;
+            const float4 h4 = *(const float4*)(hc + k);
+            az0 = fmaf(wz[k], h4.x, az0);
+            ar0 = fmaf(wr[k], h4.x, ar0);
+            aq0 = fmaf(wq[k], h4.x, aq0);
+            az1 = fmaf(wz[k + 1], h4.y, az1);
+            ar1 = fmaf(wr[k + 1], h4.y, ar1);
+            aq1 = fmaf(wq[k + 1], h4.y, aq1);
+            az0 = fmaf(wz[k + 2], h4.z, az0);
+            ar0 = fmaf(wr[k + 2], h4.z, ar0);
+            aq0 = fmaf(wq[k + 2], h4.z, aq0);
+            az1 = fmaf(wz[k + 3], h4.w, az1);
+            ar1 = fmaf(wr[k + 3], h4.w, ar1);
+            aq1 = fmaf(wq[k + 3], h4.w, aq1);
         }
-        const float zp = __shfl(acc, base + 0), rp = __shfl(acc, base + 1),
-                    qp = __shfl(acc, base + 2);
-        if (role == 0) {
-            const float* pr = pch[t % CH];
-            const float z = sigmoidf_(zp + pr[j]);
-            const float r = sigmoidf_(rp + pr[D + j]);
-            const float q = qp + b_hn;
-            const float n = tanhf_(pr[2 * D + j] + r * q);
-            const float hn = (1.f - z) * n + z * h[j];
-            hbuf[cur ^ 1][j] = hn;
-            s[(size_t)(r0 + t) * D + j] = hn;
+        const float z = sigmoid_rcp(az0 + az1 + cz);
+        const float r = sigmoid_rcp(ar0 + ar1 + cr);
+        const float q = aq0 + aq1 + b_hn;
+        const float n = tanh_rcp(cn + r * q);
+        h = (1.f - z) * n + z * h;
+        if (act) {
+            hbuf[(t + 1) & 1][j] = h;
+            s[(size_t)(r0 + t) * D + j] = h;
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+    };
+    const int64_t Tm = T - T % PF;           // steps covered by whole prefetch rounds
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+        const float* row = P + (size_t)(r0 + (i < Tm ? i : 0)) * 3 * D;
+        pz[i] = row[jj];
+        pr[i] = row[D + jj];
+        pn[i] = row[2 * D + jj];
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t t0 = 0; t0 < Tm; t0 += PF) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const float cz = pz[i], cr = pr[i], cn = pn[i];
+            // the slot is free again: fetch step t + PF (clamped to a valid row at the end)
+            const int64_t tn = t0 + i + PF < Tm ? t0 + i + PF : t0 + i;
+            const float* row = P + (size_t)(r0 + tn) * 3 * D;
+            pz[i] = row[jj];
+            pr[i] = row[D + jj];
+            pn[i] = row[2 * D + jj];
+            step(t0 + i, cz, cr, cn);
+        }
+    }
+    for (int64_t t = Tm; t < T; ++t) {
+        const float* row = P + (size_t)(r0 + t) * 3 * D;
+        step(t, row[jj], row[D + jj], row[2 * D + jj]);
     }
 }
 
 // tanh-RNN (MF = false): s_t = tanh(W s_{t-1} + P_t); mean-field RNN (MF = true):
-// s_t = W tanh(s_{t-1}) + P_t, with tanh(s) kept in LDS as the next step's operand
+// s_t = W tanh(s_{t-1}) + P_t, with tanh(s) kept in LDS as the next step's operand.  One wave
+// per sequence, lane j owns unit j (row j of W in registers), the state exchanged through LDS
+// without barriers, the projections P of the next PF steps prefetched into registers.
 template <int D, bool MF>
-__global__ void __launch_bounds__(D < 64 ? 64 : D) tanh_seq_kernel(const float* P,
-                                                                   const float* s0,
-                                                                   const float* W, float* s,
-                                                                   const int64_t* offsets) {
-    constexpr int CH = 32;
+__global__ void __launch_bounds__(64) tanh_seq_kernel(const float* __restrict__ P,
+                                                      const float* __restrict__ s0,
+                                                      const float* __restrict__ W,
+                                                      float* __restrict__ s,
+                                                      const int64_t* __restrict__ offsets) {
+    static_assert(D % 4 == 0 && D <= 64, "one lane per unit");
+    constexpr int PF = 4;
     __shared__ __attribute__((aligned(16))) float hbuf[2][D];
-    __shared__ float pch[CH][D];
     const int b = blockIdx.x;
     const int j = threadIdx.x;
+    const bool act = j < D;
+    const int jj = act ? j : 0;
     const int64_t r0 = offsets[b], T = offsets[b + 1] - r0;
+    if (T == 0) return;                      // nothing to walk (and no row to prefetch)
     float w[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) w[k] = j < D ? W[j * D + k] : 0.f;
-    if (j < D) hbuf[0][j] = MF ? tanhf_(s0[(size_t)b * D + j]) : s0[(size_t)b * D + j];
-    __syncthreads();
-    for (int64_t t = 0; t < T; ++t) {
-        if (t % CH == 0) {
-            for (int idx = j; idx < CH * D; idx += blockDim.x) {
-                const int r = idx / D, c = idx % D;
-                pch[r][c] = (t + r < T) ? P[(size_t)(r0 + t + r) * D + c] : 0.f;
-            }
-            __syncthreads();
-        }
-        const int cur = (int)(t & 1);
-        if (j < D) {
-            const float* h = hbuf[cur];
-            float acc = pch[t % CH][j];
+    for (int k = 0; k < D; ++k) w[k] = W[(size_t)jj * D + k];
+    if (act) hbuf[0][j] = MF ? tanhf_(s0[(size_t)b * D + j]) : s0[(size_t)b * D + j];
+    auto step = [&](int64_t t, float pt) {
+        const float* hc = hbuf[t & 1];
+        float a0 = pt, a1 = 0.f;
 #pragma unroll
-            for (int k = 0; k < D; k += 4) {
-                const float4 h4 = *(const float4*)(h + k);
-                acc += w[k] * h4.x + w[k + 1] * h4.y + w[k + 2] * h4.z + w[k + 3] * h4.w;
-            }
-            if (MF) {
-                hbuf[cur ^ 1][j] = tanhf_(acc);
-                s[(size_t)(r0 + t) * D + j] = acc;
-            } else {
-                const float hn = tanhf_(acc);
-                hbuf[cur ^ 1][j] = hn;
-                s[(size_t)(r0 + t) * D + j] = hn;
-            }
+        for (int k = 0; k < D; k += 4) {
+            const float4 h4 = *(const float4*)(hc + k);
+            a0 = fmaf(w[k], h4.x, a0);
+            a1 = fmaf(w[k + 1], h4.y, a1);
+            a0 = fmaf(w[k + 2], h4.z, a0);
+            a1 = fmaf(w[k + 3], h4.w, a1);
         }
-        __syncthreads();
+        const float acc = a0 + a1;
+        const float sn = MF ? acc : tanhf_(acc);
+        if (act) {
+            hbuf[(t + 1) & 1][j] = MF ? tanhf_(acc) : sn;
+            s[(size_t)(r0 + t) * D + j] = sn;
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    const int64_t Tm = T - T % PF;
+    float pf[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) pf[i] = P[(size_t)(r0 + (i < Tm ? i : 0)) * D + jj];
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t t0 = 0; t0 < Tm; t0 += PF) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const float pt = pf[i];
+            const int64_t tn = t0 + i + PF < Tm ? t0 + i + PF : t0 + i;
+            pf[i] = P[(size_t)(r0 + tn) * D + jj];
+            step(t0 + i, pt);
+        }
     }
+    for (int64_t t = Tm; t < T; ++t) step(t, P[(size_t)(r0 + t) * D + jj]);
 }
 
 // ---- host -----------------------------------------------------------------------------------
@@ -158,7 +211,7 @@ static SeqKern seq_gru_get() {
     k.xproj = xproj_kernel<3 * D, DX>;
     k.O = 3 * D;
     k.gru = gru_seq_kernel<D>;
-    k.nt = 4 * D;
+    k.nt = 64;
     return k;
 }
 template <int D, int DX, bool MF = false>
@@ -167,7 +220,7 @@ static SeqKern seq_tanh_get() {
     k.xproj = xproj_kernel<D, DX>;
     k.O = D;
     k.tanh = tanh_seq_kernel<D, MF>;
-    k.nt = D < 64 ? 64 : D;
+    k.nt = 64;
     return k;
 }
 

@@ -836,49 +836,60 @@ __global__ void tanh_adj_gs0_clear_kernel(float* gs0, int n) {
 }
 
 // Sequential baseline of the adjoint: lambda_t = g_t + W^T (e_t * lambda_{t+1}) one step at a
-// time per sequence (one single-wave workgroup per sequence, lane j holds column j of W), g and
-// e staged in LDS 32 steps at a time; writes lambda to lam[1] and marks it as the final iterate.
+// time per sequence (one single-wave workgroup per sequence, lane j holds column j of W; the
+// products e_k lambda_k go through LDS without barriers), g and e of the next 4 steps
+// prefetched into registers; writes lambda to lam[1] and marks it as the final iterate.
 __global__ void __launch_bounds__(64) tanh_seq_adj_kernel(TanhAdjArgs a, const int64_t* offsets) {
-    constexpr int CH = 32;
-    __shared__ __attribute__((aligned(16))) float lb[2][TD];
-    __shared__ __attribute__((aligned(16))) float gch[CH][TD];
-    __shared__ __attribute__((aligned(16))) float ech[CH][TD];
+    constexpr int PF = 4;
+    __shared__ __attribute__((aligned(16))) float pb[2][TD];     // e_k lambda_k of the step
     const int b = blockIdx.x, j = threadIdx.x;
+    const bool act = j < TD;
+    const int jj = act ? j : 0;
     const int64_t r0 = offsets[b], T = offsets[b + 1] - r0;
+    if (T == 0) return;                      // nothing to walk (and no row to prefetch)
     float w[TD];                                  // column j of W
 #pragma unroll
-    for (int k = 0; k < TD; ++k) w[k] = j < TD ? a.params[k * TD + j] : 0.f;
-    if (j < TD) lb[0][j] = 0.f;
+    for (int k = 0; k < TD; ++k) w[k] = a.params[k * TD + jj];
     float* lam = a.lam[1];
-    for (int64_t it = 0; it < T; ++it) {
+    // operands of reverse step it (t = T - 1 - it): g_t and e_t = d_{t+1} (0 at the end)
+    auto fetch = [&](int64_t it) {
         const int64_t t = T - 1 - it;
-        const int r = (int)(it % CH);
-        if (r == 0) {
-            __syncthreads();
-            for (int idx = j; idx < CH * TD; idx += 64) {
-                const int q = idx / TD, c = idx % TD;
-                const int64_t tt = t - q;
-                gch[q][c] = tt >= 0 ? a.gs[(size_t)(r0 + tt) * TD + c] : 0.f;
-                ech[q][c] = (tt >= 0 && tt + 1 < T) ? a.dd[(size_t)(r0 + tt + 1) * TD + c] : 0.f;
-            }
-            __syncthreads();
-        }
-        const int cur = (int)(it & 1);
-        if (j < TD) {
-            const float* ln = lb[cur];
-            const float* e = ech[r];
-            float acc = gch[r][j];
+        return float2{a.gs[(size_t)(r0 + t) * TD + jj],
+                      it > 0 ? a.dd[(size_t)(r0 + t + 1) * TD + jj] : 0.f};
+    };
+    float lnext = 0.f;                            // lambda_{t+1}, lane j's entry
+    auto step = [&](int64_t it, float2 ge) {
+        const int64_t t = T - 1 - it;
+        float* pc = pb[it & 1];
+        if (act) pc[j] = ge.y * lnext;
+        __builtin_amdgcn_wave_barrier();
+        float a0 = ge.x, a1 = 0.f;
 #pragma unroll
-            for (int k = 0; k < TD; k += 4) {
-                const float4 l4 = *(const float4*)(ln + k), e4 = *(const float4*)(e + k);
-                acc += w[k] * (e4.x * l4.x) + w[k + 1] * (e4.y * l4.y) + w[k + 2] * (e4.z * l4.z) +
-                       w[k + 3] * (e4.w * l4.w);
-            }
-            lb[cur ^ 1][j] = acc;
-            lam[(size_t)(r0 + t) * TD + j] = acc;
+        for (int k = 0; k < TD; k += 4) {
+            const float4 p4 = *(const float4*)(pc + k);
+            a0 = fmaf(w[k], p4.x, a0);
+            a1 = fmaf(w[k + 1], p4.y, a1);
+            a0 = fmaf(w[k + 2], p4.z, a0);
+            a1 = fmaf(w[k + 3], p4.w, a1);
         }
-        __syncthreads();
+        lnext = a0 + a1;
+        if (act) lam[(size_t)(r0 + t) * TD + j] = lnext;
+        __builtin_amdgcn_wave_barrier();
+    };
+    const int64_t Tm = T - T % PF;
+    float2 ring[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) ring[i] = fetch(i < Tm ? i : 0);
+    for (int64_t it0 = 0; it0 < Tm; it0 += PF) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const float2 ge = ring[i];
+            const int64_t itn = it0 + i + PF < Tm ? it0 + i + PF : it0 + i;
+            ring[i] = fetch(itn);
+            step(it0 + i, ge);
+        }
     }
+    for (int64_t it = Tm; it < T; ++it) step(it, fetch(it));
     if (j == 0 && T > 0) {
         a.seq[b].iters = 1;
         a.seq[b].parity = 1;
