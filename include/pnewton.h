@@ -207,6 +207,20 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
                      const void* s0, void* s, const pn_opts* opts, void* workspace,
                      size_t workspace_bytes, void* stream, pn_seq_info* info);
 
+/* deer_solve without a workspace, for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid allocation).  Same arguments,
+   kernels and results as deer_solve; the scratch space is a static device array of
+   PN_NOALLOC_SCRATCH_BYTES per device, held until the process ends.  Shapes whose
+   pn_workspace_bytes(PN_OP_DEER, ...) exceeds it return PN_ERR_WORKSPACE.  The call allocates
+   nothing (no hipMalloc, no pinned host memory, no graph instantiation): iterations are
+   launched directly whatever opts->use_graph says, host readbacks go through pageable memory,
+   pn_profile_* timing is off.  Calls that overlap on one device share its scratch and race:
+   order them (one stream, or one host thread at a time per device). */
+#define PN_NOALLOC_SCRATCH_BYTES (64u << 20)
+pn_status deer_solve_noalloc(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
+                             const void* s0, void* s, const pn_opts* opts, void* stream,
+                             pn_seq_info* info);
+
 /* ELK (Ch. 4): each iteration replaces the Newton step by the filtered means of the LGSSM
    of Prop. prop:ELK with emission noise 1/lambda (lambda >= 0; lambda = 0 is DEER).  With
    PN_JAC_DIAG the LGSSM uses diag(A_t): quasi-ELK (Ch. 4, "quasi-ELK").

@@ -70,6 +70,8 @@ SIGNATURES = [
                                           _P(ctypes.c_size_t)]),
     ("deer_solve", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, _P(Opts), _V,
                                   ctypes.c_size_t, _V, _P(SeqInfo)]),
+    ("deer_solve_noalloc", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, _P(Opts), _V,
+                                          _P(SeqInfo)]),
     ("elk_solve", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, ctypes.c_double,
                                  _P(Opts), _V, ctypes.c_size_t, _V, _P(SeqInfo)]),
     ("deer_adjoint", ctypes.c_int, [_P(CellDesc), _P(Batch), _V, _V, _V, _V, _V, _V, _V,

@@ -60,12 +60,18 @@ ProfRec& prof() {
 }
 }  // namespace
 
-bool profiling() { return prof().on; }
+// No-allocation mode of the calling thread (the entry point that works from the library's
+// static scratch array): no pinned host buffers, no graph instantiation, no event timing.
+static thread_local bool g_noalloc = false;
+void set_noalloc(bool on) { g_noalloc = on; }
+bool noalloc() { return g_noalloc; }
+
+bool profiling() { return prof().on && !g_noalloc; }
 
 void prof_launch(const char* family, hipStream_t stream,
                  const std::function<void(hipStream_t)>& launch) {
     ProfRec& r = prof();
-    if (!r.on) {
+    if (!r.on || g_noalloc) {
         launch(stream);
         return;
     }
@@ -195,6 +201,13 @@ namespace {
 // and stalls the stream); a buffer is reused only by the next call on the same thread, after
 // the previous call synchronised its stream.
 void* pinned_staging(int which, size_t bytes) {
+    if (g_noalloc) {
+        // pageable host memory (plain host heap, no HIP allocation); the copies through it
+        // are staged by the runtime
+        static thread_local std::vector<char> pageable[2];
+        if (pageable[which].size() < bytes) pageable[which].resize(bytes);
+        return pageable[which].data();
+    }
     struct Buf { void* p = nullptr; size_t n = 0; };
     static thread_local Buf bufs[2];
     Buf& b = bufs[which];
@@ -287,12 +300,15 @@ __global__ void clear_flag_kernel(int* flag) { *flag = 0; }
 
 pn_status check_finite(std::initializer_list<std::pair<const void*, int64_t>> arrays, int dtype,
                        int* flag_dev, hipStream_t stream) {
-    static thread_local int* hflag = nullptr;
-    if (!hflag && hipHostMalloc((void**)&hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        hflag = nullptr;
+    static thread_local int* pinned_flag = nullptr;
+    static thread_local int pageable_flag = 0;
+    if (!g_noalloc && !pinned_flag &&
+        hipHostMalloc((void**)&pinned_flag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        pinned_flag = nullptr;
         set_error("hipHostMalloc of the input-check flag failed");
         return PN_ERR_HIP;
     }
+    int* hflag = g_noalloc ? &pageable_flag : pinned_flag;
     // cleared by a kernel rather than a memset node, so the check stays capturable
     hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, stream, flag_dev);
     for (const auto& a : arrays) {
@@ -432,6 +448,10 @@ struct PinnedCtrl {
     PinnedCtrl() { (void)hipHostMalloc((void**)&p, sizeof(Ctrl), hipHostMallocDefault); }
 };
 Ctrl* pinned_ctrl() {
+    if (g_noalloc) {
+        static thread_local Ctrl pageable;
+        return &pageable;
+    }
     static thread_local PinnedCtrl pc;
     return pc.p;
 }
@@ -501,7 +521,7 @@ pn_status run_iterations(const IterState& st, int max_launches, int graph_iters,
     ExecPtr exec;       // this call's executable, held until the call returns
     while (launched < max_launches) {
         const int n = std::min(graph_iters, max_launches - launched);
-        if (use_graph && n == graph_iters && !profiling()) {
+        if (use_graph && n == graph_iters && !profiling() && !g_noalloc) {
             if (!exec) {
                 int dev = 0;
                 PN_HIP(hipGetDevice(&dev));

@@ -65,6 +65,11 @@ struct Carver {
 
 int cu_count();
 
+// No-allocation mode of the calling thread: pageable host staging, direct launches, no event
+// timing (the static-scratch entry point sets it around its call).
+void set_noalloc(bool on);
+bool noalloc();
+
 // Event timing of kernel launches (pn_profile_begin / pn_profile_read).
 bool profiling();
 // Records an event pair around `launch(stream)` when profiling, else just launches.
