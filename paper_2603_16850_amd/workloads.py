@@ -8,7 +8,7 @@ Every draw uses ``numpy.random.default_rng(seed)`` (PCG64) in float64 and a fixe
   2. weights: GRU W_z, W_r, W_n (D x Dx) then U_z, U_r, U_n (D x D), all N(0, 1/D);
      tanh-RNN W (D x D) ~ N(0, g^2/D) then U (D x Dx) ~ N(0, 1/D);
   3. biases are zero (no draw);
-  4. inputs x [N, Dx] ~ N(0, 1), sequences back to back.
+  4. inputs x [N, Dx] ~ N(0, 1) (times the workload's input scale), sequences back to back.
 The initial state s_0 and the initial guess are zero.
 
 The mean-field RNN (cell "meanfield", Ch. 5 predictability experiments) draws W (D x D) ~
@@ -44,6 +44,7 @@ class Workload:
     tol: float = 1e-5
     lambdas: tuple = ()
     backward: bool = False
+    input_scale: float = 1.0  # inputs x ~ N(0, input_scale^2)
 
     def scaled(self, **kw):
         return replace(self, **kw)
@@ -61,6 +62,14 @@ TANH16_ELK = Workload("tanh16-elk-chaotic", "tanh", D=16, Dx=16, B=8, T=8192,
                       lambdas=(1e-2, 1e-1, 1.0))
 GRU48_RAGGED = Workload("gru48-ragged-quasi", "gru", D=48, Dx=24, B=256,
                         t_min=512, t_max=32768, jac="diag", tol=1e-5, backward=True)
+
+# The ELK workload in its chaotic regime.  At D = 16 the stated input drive (x ~ N(0, 1))
+# suppresses chaos (largest Lyapunov exponent -0.19 .. -0.30 for seeds 0-2), and with weaker
+# drive most draws of W at gain 1.5 settle to non-chaotic motion as well; with inputs scaled by
+# 0.1, seed CHAOTIC_SEED (the first of seeds 0..11 found with a positive exponent) gives
+# +0.018 .. +0.026 on all 8 sequences (Alg. alg:LLE_estimate on the FP64 rollout).
+TANH16_ELK_CHAOTIC = replace(TANH16_ELK, name="tanh16-elk-chaotic-lowdrive", input_scale=0.1)
+CHAOTIC_SEED = 9
 
 # The mean-field RNN of the LLE-threshold sweep (Ch. 5): DEER (ELK with lambda = 0), T = 1000
 # (the length the thesis highlights), the gain g swept per run.
@@ -128,5 +137,7 @@ def make_instance(work: Workload, seed: int = 0, lengths: Optional[np.ndarray] =
         s0 = rng.standard_normal(size=(lens.size, work.D))
         return Instance(work, params, x, s0, offsets, seed)
     x = rng.standard_normal(size=(int(offsets[-1]), work.Dx))
+    if work.input_scale != 1.0:
+        x = x * work.input_scale
     s0 = np.zeros((lens.size, work.D))
     return Instance(work, params, x, s0, offsets, seed)

@@ -275,3 +275,80 @@ def test_smoother_full_size_contracting(lib):
     assert max(i["max_resid"] for i in info) < w.tol
     ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
     assert _rel(s, ref) < 1e-5
+
+
+# ---- the chaotic regime (positive largest Lyapunov exponent) --------------------------------
+# The ELK workload with inputs scaled by 0.1 (workloads.TANH16_ELK_CHAOTIC, seed CHAOTIC_SEED)
+# has exponents +0.018 .. +0.026.  Parity follows the reading for several correct results:
+# the FP64 residual decides, and the trajectory is compared with the FP64 rollout only up to
+# the horizon over which FP32 round-off stays small.  The horizon is measured per sequence,
+# not taken from ln(1e-5 / eps) / lambda_LLE (about 200 steps): finite-time growth over the
+# first steps runs above the average exponent.  It is the first step at which a rollout
+# computed in FP32 leaves the FP64 rollout by more than 1e-6 (the bar, 1e-5, then has a
+# factor 10 of room).  The merit function's conditioning grows like exp(lambda_LLE T)
+# (Thm. PL-LLE), so in FP32 the methods converge on sequences of a few hundred steps and not
+# on the full 8192 steps, where they end at the iteration cap and say so.
+
+
+def _chaotic(T=None):
+    w = workloads.TANH16_ELK_CHAOTIC
+    if T is not None:
+        w = w.scaled(T=T)
+    inst = workloads.make_instance(w, seed=workloads.CHAOTIC_SEED)
+    return w, inst, cells.TanhRNN(inst.params, w.D, w.Dx)
+
+
+def _horizons(cell, inst, ref):
+    """Per sequence: the first step where an FP32 rollout departs from the FP64 one by 1e-6."""
+    f32 = np.float32
+    W, U, bb = cell.W.astype(f32), cell.U.astype(f32), cell.b.astype(f32)
+    out = []
+    for b in range(inst.offsets.size - 1):
+        a, e = inst.offsets[b], inst.offsets[b + 1]
+        h = inst.s0[b].astype(f32)
+        t_h = e - a
+        for t in range(e - a):
+            h = np.tanh(W @ h + U @ inst.x[a + t].astype(f32) + bb).astype(f32)
+            if np.abs(h.astype(np.float64) - ref[a + t]).max() > 1e-6:
+                t_h = t
+                break
+        out.append(t_h)
+    return out
+
+
+@pytest.mark.parametrize("lam,jac", [(1e-2, "dense"), (1e-1, "dense"), (1.0, "dense"),
+                                     (0.0, "dense"), (1e-1, "diag")])
+def test_chaotic_short_sequences_converge(lib, lam, jac):
+    """256 steps of the chaotic instance: every method reaches an FP64 residual below 1e-6,
+    and the trajectory equals the FP64 rollout to 1e-5 up to the horizon.  DEER does within
+    T iterations (Prop. global_convergence); the damped ELK steps and quasi-ELK move the
+    converged front more slowly here and get a cap of 16 T."""
+    w, inst, cell = _chaotic(T=256)
+    cap = 256 if lam == 0.0 else 16 * 256
+    s, info = _elk(lib, inst, lam, tol=w.tol, jac=jac, fp64_final_residual=True, max_iters=cap)
+    assert all(i["converged"] for i in info), [i["iters"] for i in info]
+    assert max(i["max_resid"] for i in info) < w.tol
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    hs = _horizons(cell, inst, ref)
+    assert min(hs) >= 10, hs
+    for b, t_h in enumerate(hs):
+        a = inst.offsets[b]
+        assert np.abs(s[a:a + t_h] - ref[a:a + t_h]).max() < 1e-5, (b, t_h)
+
+
+@pytest.mark.parametrize("lam", [1e-2, 0.0])
+def test_chaotic_full_size_reports_the_cap(lib, lam):
+    """8192 steps of the chaotic instance, capped at 384 iterations: not converged and said
+    so (PN_NOT_CONVERGED per sequence, the FP64 residual of the last iterate above tol),
+    resets counted; the horizon prefix equals the FP64 rollout (a converged prefix is kept)."""
+    w, inst, cell = _chaotic()
+    s, info = _elk(lib, inst, lam, tol=w.tol, max_iters=384, fp64_final_residual=True)
+    assert not any(i["converged"] for i in info)
+    assert all(i["iters"] == 384 for i in info)
+    assert all(i["max_resid"] > w.tol and np.isfinite(i["max_resid"]) for i in info)
+    assert all(i["resets"] >= 0 for i in info)
+    ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
+    hs = _horizons(cell, inst, ref)
+    for b, t_h in enumerate(hs):
+        a = inst.offsets[b]
+        assert np.abs(s[a:a + t_h] - ref[a:a + t_h]).max() < 1e-5, (b, t_h)

@@ -102,3 +102,16 @@ def test_meanfield_rollout_is_rnncell_in_tanh_coordinates():
     # and the state itself: s_t = W h_{t-1} + U x_t + b with the library's h
     hprev = np.concatenate([np.tanh(s0)[None], np.array(hs)[:-1]])
     np.testing.assert_allclose(s, hprev @ W.T + x @ U.T + b, rtol=0, atol=1e-13)
+
+
+def test_chaotic_elk_workload_has_positive_lle():
+    """The chaotic ELK workload (gain 1.5, inputs scaled by 0.1, its stated seed) is chaotic:
+    a positive largest Lyapunov exponent on its sequences (checked on two of them)."""
+    from paper_2603_16850_amd import workloads
+    w = workloads.TANH16_ELK_CHAOTIC
+    inst = workloads.make_instance(w, seed=workloads.CHAOTIC_SEED)
+    cell = cells.TanhRNN(inst.params, w.D, w.Dx)
+    for b in (0, 7):
+        a, e = inst.offsets[b], inst.offsets[b + 1]
+        s = rollout.rollout(cell, inst.x[a:e], inst.s0[b])
+        assert lle.trajectory_lle(cell, inst.x[a:e], inst.s0[b], s) > 0.01, b
