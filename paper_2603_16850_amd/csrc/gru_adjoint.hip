@@ -45,18 +45,18 @@ struct GruAdjArgs {
     const float* s;
     const float* gs;
     const float* params;
-    float* gates;            // [N][4][D]: alpha, beta, gamma, eps = (1 - z)(1 - n^2) at the
-                             // solution (z lives in zd)
-    float2* zd;              // [N][D]: (z_t, diag(A_t)) at the solution (the reverse scan's
-                             // per-step operands)
-    float* lam[2];           // ping-pong adjoint iterates; iteration k reads lam[k & 1]
-                             // (lambda^(0) = g is read from gs, not stored)
-    int lam0_is_g;           // nonzero: a sequence stopped at iteration 0 has lambda = g
-    float* la;               // [N][D] multiplicative part of every step's map relative to its
-                             // group.  The transitions diag(A_{t+1}) of the adjoint scan are
-                             // those of the solution and do not change between iterations, so
-                             // la is the same in every iteration: written by iteration 0 only.
-    float* lc[2];            // [N][D] additive part; iteration k writes lc[k & 1]
+    float* gates;            // [N][4][D]: alpha, beta, gamma, z at the solution (the VJP
+                             // operands of every adjoint iteration)
+    float* eps;              // [N][D]: (1 - z)(1 - n^2) at the solution (parameter gradients)
+    float* lam;              // [N][D] adjoint iterate: iteration k writes lambda^(k) on the rows
+                             // of the sequences it updates, so it ends holding each
+                             // sequence's final iterate
+    float* mu[2];            // ping-pong [N][D]: mu^(k) = lambda^(k-1) + lc^(k-1), the previous
+                             // iterate plus the carry-free part of its update; iteration k reads
+                             // mu[k & 1] (mu^(0) = g is read from gs) and writes mu[(k + 1) & 1]
+    float* gprod;            // [ngroups][D] product of the scan transitions over each group
+                             // (written by iteration 0: the transitions diag(A_{t+1}) are those
+                             // of the solution and do not change between iterations)
     float2* gagg;            // [ngroups][D] group maps
     const float* gcarry;     // [ngroups][D] carry into every group (previous iteration)
     float* gmax;             // [B] max |g| per sequence (as float bits)
@@ -81,7 +81,7 @@ struct GruAdjArgs {
     float* gparams;
 };
 
-// ---- prep: gate values and (z, diag A) at the solution, max |g| -------------------------
+// ---- prep: gate values at the solution, max |g| -------------------------------------------
 template <int D, int DX, int L>
 __global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gru_adj_prep_kernel(GruAdjArgs a) {
@@ -92,9 +92,6 @@ gru_adj_prep_kernel(GruAdjArgs a) {
     const int j = 16 * w + u;
     GruGates<D, DX> wg;
     wg.load(a.params, j, g);
-    const float* U = a.params + 3 * D * DX;
-    const float dUz = U[(0 * D + j) * D + j], dUr = U[(1 * D + j) * D + j],
-                dUn = U[(2 * D + j) * D + j];
     TileInfo tnext{};
     if ((int)blockIdx.x < a.ntiles) tnext = a.tiles[blockIdx.x];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
@@ -174,9 +171,8 @@ gru_adj_prep_kernel(GruAdjArgs a) {
                 gr[0 * D + j] = al;
                 gr[1 * D + j] = be;
                 gr[2 * D + j] = ga;
-                gr[3 * D + j] = e;
-                // diag(A_t)_j = z + alpha U_z[j][j] + beta U_n[j][j] + gamma U_r[j][j]
-                a.zd[row * D + j] = make_float2(p.z, p.z + al * dUz + be * dUn + ga * dUr);
+                gr[3 * D + j] = p.z;
+                a.eps[row * D + j] = e;
                 gm = max(gm, absbits(gvs[mb][i]));
             }
         }
@@ -202,31 +198,87 @@ __global__ void __launch_bounds__(256) gru_adj_gmax_kernel(GruAdjArgs a) {
 }
 
 // ---- one adjoint iteration ------------------------------------------------------------------
+// Reverse scan of one tile's steps held in the MFMA output layout (lane (u, g) of a wave holds
+// rows 16 mb + 4 g + i of its column), later steps first, composed with the map (Ra, Rc) of the
+// group's steps scanned before the tile.  On entry sa, sc hold every step's own map
+// Delta_t = sa Delta_{t+1} + sc; on return they hold the map from the Delta entering the group
+// to Delta_t, and (Ra, Rc) the map of the group's steps scanned so far, this tile included.
+// With WC false only the multiplicative parts are formed (sc and Rc are left alone).
+template <int MB, bool WC>
+PN_DEV void adj_tile_scan(float (&sa)[MB][4], float (&sc)[MB][4], float& Ra, float& Rc, int g,
+                          int u) {
+#pragma unroll
+    for (int mb = MB - 1; mb >= 0; --mb) {
+        float pa = 1.f, pc = 0.f;
+#pragma unroll
+        for (int i = 3; i >= 0; --i) {
+            if (WC) {
+                pc = sa[mb][i] * pc + sc[mb][i];
+                sc[mb][i] = pc;
+            }
+            pa = sa[mb][i] * pa;
+            sa[mb][i] = pa;
+        }
+        float Ia = pa, Ic = pc;
+        {
+            const float qa = __shfl_down(Ia, 16);
+            const float qc = WC ? __shfl_down(Ic, 16) : 0.f;
+            if (g <= 2) {
+                if (WC) Ic = Ia * qc + Ic;
+                Ia = Ia * qa;
+            }
+        }
+        {
+            const float qa = __shfl_down(Ia, 32);
+            const float qc = WC ? __shfl_down(Ic, 32) : 0.f;
+            if (g <= 1) {
+                if (WC) Ic = Ia * qc + Ic;
+                Ia = Ia * qa;
+            }
+        }
+        float Ea = __shfl_down(Ia, 16), Ec = WC ? __shfl_down(Ic, 16) : 0.f;
+        if (g == 3) { Ea = 1.f; Ec = 0.f; }
+        const float Ta = __shfl(Ia, u), Tc = WC ? __shfl(Ic, u) : 0.f;
+        const float Xa = Ea * Ra, Xc = Ea * Rc + Ec;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (WC) sc[mb][i] = sa[mb][i] * Xc + sc[mb][i];
+            sa[mb][i] = sa[mb][i] * Xa;
+        }
+        if (WC) Rc = Ta * Rc + Tc;
+        Ra = Ta * Ra;
+    }
+}
+
+// One Newton iteration of the adjoint over groups of tiles.  With la_t the product of the
+// scan's transitions from step t to the group's first scanned step and lc^(k)_t the scan of
+// -rho^(k) inside the group (the update for a zero carry), iteration k forms
+//   lambda^(k)_t = mu^(k)_t + la_t carry_g     (carry_g: the carry into the group, from the
+//                                               previous carry pass; reset guard per row)
+//   mu^(k+1)_t  = lambda^(k)_t + lc^(k)_t
+// and writes lambda^(k) and mu^(k+1).  la is recomputed in every iteration from the gate rows
+// that the VJP reads anyway (diag(A_{t+1})_j = z + alpha U_z[j][j] + beta U_n[j][j]
+// + gamma U_r[j][j]), so per step an iteration reads mu, the gate row of the successor step and
+// g, and writes lambda and mu.
 template <int D, int DX, int L>
 __global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gru_adj_local_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
+    constexpr int MB = C::MB;
     __shared__ __attribute__((aligned(16))) float ps[L * C::PS];
     __shared__ __attribute__((aligned(16))) float lst[(L + 1) * C::HS];   // lambda rows t0 .. t0+L
-
     __shared__ int rowbad[L + 1];
 
     if (ld_i32(&a.ctrl->all_done)) return;
-    // Iteration k first forms lambda^(k) = lambda^(k-1) + la carry + lc from the previous
-    // iteration's maps (k >= 1; lambda^(0) = g) with the reset guard, then linearises there.
     const int k = a.ctrl->iter;
     const bool fuse = k > 0;
     const float reset_abs = a.ctrl->reset_abs;
-    // lambda^(k-1) (lambda^(0) = g)
-    const float* __restrict__ lprev = k == 1 ? a.gs : a.lam[(k + 1) & 1];
-    float* __restrict__ lcur = a.lam[k & 1];                 // lambda^(k)
-    const float* __restrict__ lap = a.la;
-    const float* __restrict__ lcp = a.lc[(k + 1) & 1];
-    float* __restrict__ lcn = a.lc[k & 1];
+    const float* __restrict__ mu_in = fuse ? a.mu[k & 1] : a.gs;     // mu^(k) (mu^(0) = g)
+    float* __restrict__ mu_out = a.mu[(k + 1) & 1];                   // mu^(k+1)
+    float* __restrict__ lam = a.lam;
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
     const int j = 16 * w + u;
-    for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
 
     // B operands of [U_z; U_n; U_r] (3D x D), column j, same K permutation as GruGates
     const float* U = a.params + 3 * D * DX;
@@ -240,14 +292,16 @@ gru_adj_local_kernel(GruAdjArgs a) {
             const int base = (mat == 0 ? 0 : (mat == 1 ? 2 : 1)) * D;   // U_z, U_n, U_r rows
             bu[kb][i] = U[(base + ii) * D + j];
         }
+    const float dUz = U[(0 * D + j) * D + j], dUr = U[(1 * D + j) * D + j],
+                dUn = U[(2 * D + j) * D + j];
 
     for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
         const GroupInfo gr = a.groups[gi];
         if (a.seq[gr.b].status != kActive) continue;     // same on every thread
         const int b = gr.b;
         // converged-prefix skipping in scan order (the sequence's last groups in time first):
-        // a group frozen by the last carry pass takes lambda^(k) = lambda^(k-1) on its rows
-        // once, into both iterate buffers when lambda^(k-1) = g is not stored, and is skipped
+        // the carry into a group frozen by the last carry pass is zero, so its iterate is
+        // mu^(k); it goes into lambda and into both mu buffers once, and the group is skipped
         // from then on
         bool halo_frozen = false;
         if (a.freeze) {
@@ -257,9 +311,9 @@ gru_adj_local_kernel(GruAdjArgs a) {
                     const TileInfo t0 = a.tiles[gr.tile0 + gr.ntl - 1], t1 = a.tiles[gr.tile0];
                     const int64_t e0 = t0.row0 * (D / 4), e1 = (t1.row0 + t1.len) * (D / 4);
                     for (int64_t e = e0 + tid; e < e1; e += C::NT) {
-                        const float4 v = ((const float4*)lprev)[e];
-                        ((float4*)lcur)[e] = v;
-                        if (k == 1) ((float4*)a.lam[0])[e] = v;
+                        const float4 v = ((const float4*)mu_in)[e];
+                        ((float4*)lam)[e] = v;
+                        ((float4*)mu_out)[e] = v;
                     }
                 }
                 continue;
@@ -278,27 +332,39 @@ gru_adj_local_kernel(GruAdjArgs a) {
             const bool first = (ti.flags & kTileScanFirst) != 0;   // tile at the sequence end
             // one past the last row that has a successor step inside the sequence
             const int64_t rend = first ? row0 + len : row0 + L + 1;
-
-            // ---- stage lambda rows row0 .. row0+L, then the VJP operand rows ----
-            // Item (r, c4): lambda_{t0+r}[4 c4 .. 4 c4 + 3]; row L (when the tile is not the
-            // sequence's last) belongs to the next tile in time, scanned just before this one.
-            // A thread's float4 column c4 is the same for all its items.
-            constexpr int Q = D / 4;
-            static_assert(C::NT % Q == 0, "column per thread");
-            constexpr int NI = ((L + 1) * Q + C::NT - 1) / C::NT;
-            constexpr int NB = NI;     // one round trip per pass
-            const int c4 = tid % Q;
-            float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
+            const bool halo_moves = fuse && !first && !(kt == 0 && halo_frozen);
+            // carry terms of column j: into the own group, into the halo row's group, and the
+            // transition product from the halo row to its group's first scanned step (the
+            // group's earlier tiles for kt > 0: Pa; the whole previous group for kt = 0)
+            float cown = 0.f, chalo = 0.f, lah = 0.f;
             if (fuse) {      // in flight together with the staging loads below
-                cown = *(const float4*)(a.gcarry + (size_t)ti.gslot * D + 4 * c4);
-                if (!first)
-                    chalo = *(const float4*)(a.gcarry + (size_t)ti.hgslot * D + 4 * c4);
+                cown = a.gcarry[(size_t)ti.gslot * D + j];
+                if (halo_moves) {
+                    chalo = a.gcarry[(size_t)ti.hgslot * D + j];
+                    lah = kt == 0 ? a.gprod[(size_t)ti.hgslot * D + j] : Pa;
+                }
             }
             __syncthreads();                 // LDS of the previous tile consumed
+            for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
+            constexpr int Q = D / 4;
+            static_assert(C::NT % Q == 0, "column per thread");
+            // Lane offsets into the LDS tiles and the step rows, formed anew for every tile
+            // (hidden from the optimiser): hoisted out of the loops, one precomputed address
+            // per (row, operand) would stay live across the whole group loop.
+            int o_own = 4 * g * C::HS + j;           // lst: own row 4 g, column j
+            int o_gate = 4 * g * C::PS + j;          // ps: gate row of the step after row 4 g
+            int o_arow = u * C::PS + 4 * g;          // ps: VJP operand row u
+            int o_lrow = (u + 1) * C::HS + 4 * g;    // lst: lambda row u + 1
+            int o_row = 4 * g * D + j;               // [N][D] arrays: own row 4 g, column j
+            int o_grow = 16 * g * D + j;             // [N][4][D] gate rows: row 4 g, column j
+            int o_st = (tid / Q) * C::HS + 4 * (tid % Q);   // staging item 0 in lst
+            int o_sg = (tid / Q) * D + 4 * (tid % Q);       // staging item 0 in [N][D]
+            asm volatile("" : "+v"(o_own), "+v"(o_gate), "+v"(o_arow), "+v"(o_lrow), "+v"(o_row),
+                              "+v"(o_grow), "+v"(o_st), "+v"(o_sg));
             // The gate planes (alpha, beta, gamma) of rows row0 + 1 .. row0 + L go straight
             // from HBM into ps (row r - 1 for row row0 + r), one 3D-float row per instruction of
-            // 3D / 4 lanes (16 B each, lane i to byte 16 i of the row), issued before the lambda
-            // loads so that both are in flight together and no register holds them.  Rows past
+            // 3D / 4 lanes (16 B each, lane i to byte 16 i of the row), issued before the other
+            // loads so that all are in flight together and no register holds them.  Rows past
             // the sequence's last row with a successor read that row instead: their lambda row
             // is zero, so the products formed from them vanish.
             {
@@ -312,97 +378,130 @@ gru_adj_local_kernel(GruAdjArgs a) {
                             0, 0);
                 }
             }
+            // mu rows row0 .. row0 + L (item (r, c4): mu_{t0+r}[4 c4 .. 4 c4 + 3]; row L, when
+            // the tile is not the sequence's last, belongs to the next tile in time); item q of
+            // a thread is row tid / Q + q NT / Q
+            constexpr int NI = ((L + 1) * Q + C::NT - 1) / C::NT;
+            constexpr int RQ = C::NT / Q;
+            const float* mrow = mu_in + (size_t)row0 * D + o_sg;
+            float4 vl[NI];
 #pragma unroll
-            for (int i0 = 0; i0 < NI; i0 += NB) {
-                float4 vl[NB], p0[NB], p1[NB];
-#pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int idx = tid + (i0 + q) * C::NT;
-                    const int r = idx / Q;
-                    const int64_t nr = row0 + r;
-                    const bool okl = i0 + q < NI && idx < (L + 1) * Q && nr < rend;
-                    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    const size_t e = (size_t)nr * D + 4 * c4;
-                    vl[q] = okl ? *(const float4*)((fuse ? lprev : a.gs) + e) : z4;
-                    p0[q] = (okl && fuse) ? *(const float4*)(lap + e) : z4;
-                    p1[q] = (okl && fuse) ? *(const float4*)(lcp + e) : z4;
-                }
-#pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int idx = tid + (i0 + q) * C::NT;
-                    if (i0 + q >= NI || idx >= (L + 1) * Q) continue;
-                    const int r = idx / Q;
-                    float4 w4 = vl[q];
-                    if (fuse && !(r == L && kt == 0 && halo_frozen)) {
-                        const float4 cv = r < L ? cown : chalo;
-                        w4.x += p0[q].x * cv.x + p1[q].x;
-                        w4.y += p0[q].y * cv.y + p1[q].y;
-                        w4.z += p0[q].z * cv.z + p1[q].z;
-                        w4.w += p0[q].w * cv.w + p1[q].w;
-                        if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
-                            !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
-                            rowbad[r] = 1;
-                    }
-                    *(float4*)(lst + r * C::HS + 4 * c4) = w4;
-                }
+            for (int q = 0; q < NI; ++q) {
+                const int idx = tid + q * C::NT;
+                vl[q] = (idx < (L + 1) * Q && row0 + idx / Q < rend)
+                            ? *(const float4*)(mrow + q * RQ * D)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            // the gate rows were issued before the lambda loads, so they have landed once those
-            // have; the explicit wait also covers them for the barrier
-            __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt(0)
-            __syncthreads();
-            // reset guard and lambda^(k) of the own rows to HBM
-            if (fuse) {
+            // z of the successor step of every own row (g_t is loaded later, a block ahead)
+            float zv[MB][4];
+            const float* zrow = a.gates + (size_t)(row0 + 1) * 4 * D + 3 * D + o_grow;
 #pragma unroll
-                for (int i0 = 0; i0 < NI; ++i0) {
-                    const int idx = tid + i0 * C::NT;
-                    if (idx >= (L + 1) * Q) continue;
-                    const int r = idx / Q;
-                    float* lp = lst + r * C::HS + 4 * c4;
-                    if (rowbad[r]) *(float4*)lp = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (r < len) *(float4*)(lcur + (size_t)(row0 + r) * D + 4 * c4) =
-                                     *(const float4*)lp;
-                }
-            }
-            if (fuse && tid < 64) {
-                int nb = 0;
-                for (int base = 0; base < L; base += 64) {
-                    const int r = base + tid;
-                    nb += __popcll(__ballot(r < len && rowbad[r]));
-                }
-                if (tid == 0 && nb) atomicAdd(&a.seq[b].resets_pending, nb);
-            }
-            __syncthreads();
-            if (fuse)
-                for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
-
-            float la[C::MB][4], lc[C::MB][4];
-            // per-element operands of a 16-step block: (z, diag A) of step t+1 and g_t, loaded
-            // one block ahead so that their latency hides behind the previous block's MFMAs
-            float2 zdc[4], zdn[4];
-            float gtc[4], gtn[4];
-            auto load_block = [&](int mb, float2* zd, float* gt) {
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
-                    const int64_t row = row0 + tl;
-                    const bool valid = tl < len;
-                    const bool has_next = valid && row + 1 < rend;
-                    zd[i] = has_next ? a.zd[(size_t)(row + 1) * D + j] : make_float2(0.f, 0.f);
-                    gt[i] = valid ? a.gs[(size_t)row * D + j] : 0.f;
+                    zv[mb][i] = tl < len && row0 + tl + 1 < rend
+                                    ? zrow[(mb * 16 + i) * 4 * D] : 0.f;
+                }
+#pragma unroll
+            for (int q = 0; q < NI; ++q) {
+                const int idx = tid + q * C::NT;
+                if (idx < (L + 1) * Q) *(float4*)(lst + o_st + q * RQ * C::HS) = vl[q];
+            }
+            // the gate rows were issued before the other loads, so they have landed once those
+            // have; the explicit wait also covers them for the barrier
+            __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt(0)
+            __syncthreads();
+
+            // transitions dg_t = diag(A_{t+1}) of the own rows (damped or clipped as in the
+            // forward; a row without a successor has A = 0, an invalid row the identity), from
+            // the gate rows in ps; formed twice (for the update and for the scan) rather than
+            // kept in registers
+            auto transitions = [&](float (&dg)[MB][4]) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int tl = mb * 16 + 4 * g + i;
+                        const float* pr = ps + o_gate + (mb * 16 + i) * C::PS;   // step t + 1
+                        const bool has_next = tl < len && row0 + tl + 1 < rend;
+                        float d = has_next ? zv[mb][i] + pr[0] * dUz + pr[D] * dUn +
+                                                 pr[2 * D] * dUr
+                                           : 0.f;
+                        d *= a.dscale;
+                        if (a.clip) d = fminf(fmaxf(d, a.clo), a.chi);
+                        dg[mb][i] = tl < len ? d : 1.f;
+                    }
+            };
+            float la[MB][4], lc[MB][4];
+
+            if (fuse) {
+                // ---- lambda^(k) = mu^(k) + la carry, with the reset guard ----
+                float ra = Pa, rc = 0.f;
+                transitions(la);
+                adj_tile_scan<MB, false>(la, lc, ra, rc, g, u);
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int tl = mb * 16 + 4 * g + i;
+                        if (tl < len) {
+                            float* lp = lst + o_own + (mb * 16 + i) * C::HS;
+                            const float v = *lp + la[mb][i] * cown;
+                            *lp = v;
+                            if (!(fabsf(v) <= reset_abs)) rowbad[tl] = 1;
+                        }
+                    }
+                if (g == 0 && halo_moves) {
+                    float* lp = lst + L * C::HS + j;
+                    const float v = *lp + lah * chalo;
+                    *lp = v;
+                    if (!(fabsf(v) <= reset_abs)) rowbad[L] = 1;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int tl = mb * 16 + 4 * g + i;
+                        if (tl < len && rowbad[tl]) lst[o_own + (mb * 16 + i) * C::HS] = 0.f;
+                    }
+                if (g == 0 && halo_moves && rowbad[L]) lst[L * C::HS + j] = 0.f;
+                if (tid < 64) {
+                    int nb = 0;
+                    for (int base = 0; base < L; base += 64) {
+                        const int r = base + tid;
+                        nb += __popcll(__ballot(r < len && rowbad[r]));
+                    }
+                    if (tid == 0 && nb) atomicAdd(&a.seq[b].resets_pending, nb);
+                }
+                __syncthreads();
+            }
+
+            // ---- VJP, residual rho^(k) and its scan inside the tile ----
+            // g_t of a 16-step block, loaded one block ahead so that its latency hides behind
+            // the previous block's MFMAs
+            float gtc[4], gtn[4];
+            const float* grow = a.gs + (size_t)row0 * D + o_row;
+            auto load_g = [&](int mb, float* gt) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int tl = mb * 16 + 4 * g + i;
+                    gt[i] = tl < len ? grow[(mb * 16 + i) * D] : 0.f;
                 }
             };
-            load_block(0, zdc, gtc);
+            load_g(0, gtc);
 #pragma unroll
-            for (int mb = 0; mb < C::MB; ++mb) {
-                if (mb + 1 < C::MB) load_block(mb + 1, zdn, gtn);
+            for (int mb = 0; mb < MB; ++mb) {
+                if (mb + 1 < MB) load_g(mb + 1, gtn);
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                 // VJP operand row (alpha, beta, gamma)_{t+1} * lambda_{t+1} of step t = row
                 // mb * 16 + u, formed from the gate rows in ps and the lambda row in lst
-                const float* prow = ps + (mb * 16 + u) * C::PS;
-                const float* lrow = lst + (mb * 16 + u + 1) * C::HS + 4 * g;
+                const float* prow = ps + o_arow + mb * 16 * C::PS;
+                const float* lrow = lst + o_lrow + mb * 16 * C::HS;
 #pragma unroll
                 for (int kb = 0; kb < 3 * D / 16; ++kb) {
-                    const float4 g4 = *(const float4*)(prow + 16 * kb + 4 * g);
+                    const float4 g4 = *(const float4*)(prow + 16 * kb);
                     const float4 l4 = *(const float4*)(lrow + 16 * (kb % (D / 16)));
                     acc = mfma16x4(g4.x * l4.x, bu[kb][0], acc);
                     acc = mfma16x4(g4.y * l4.y, bu[kb][1], acc);
@@ -413,72 +512,36 @@ gru_adj_local_kernel(GruAdjArgs a) {
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
                     const bool valid = tl < len;
-                    const float lam_t = lst[tl * C::HS + j];
+                    const float* lp = lst + o_own + (mb * 16 + i) * C::HS;
+                    const float lam_t = lp[0];
                     // (A_{t+1}^T lambda_{t+1})_j = z_j lambda_j + [U_z; U_n; U_r]^T part (MFMA)
-                    const float vjp = zdc[i].x * lst[(tl + 1) * C::HS + j] + acc[i];
+                    const float vjp = zv[mb][i] * lp[C::HS] + acc[i];
                     const float rho = lam_t - gtc[i] - vjp;
-                    float dg = zdc[i].y * a.dscale;
-                    if (a.clip) dg = fminf(fmaxf(dg, a.clo), a.chi);
-                    la[mb][i] = valid ? dg : 1.f;
                     lc[mb][i] = valid ? -rho : 0.f;
                     if (valid) rmax = max(rmax, absbits(rho * gscale));
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    zdc[i] = zdn[i];
-                    gtc[i] = gtn[i];
-                }
+                for (int i = 0; i < 4; ++i) gtc[i] = gtn[i];
             }
-
-            // ---- reverse scan inside the tile (later steps first), composed with the map
-            // of the group's earlier (later-in-time) tiles ----
-            float Ra = Pa, Rc = Pc;
+            transitions(la);
+            adj_tile_scan<MB, true>(la, lc, Pa, Pc, g, u);
 #pragma unroll
-            for (int mb = C::MB - 1; mb >= 0; --mb) {
-                float pa = 1.f, pc = 0.f;
-#pragma unroll
-                for (int i = 3; i >= 0; --i) {
-                    pa = la[mb][i] * pa;
-                    pc = la[mb][i] * pc + lc[mb][i];
-                    la[mb][i] = pa;
-                    lc[mb][i] = pc;
-                }
-                float Ia = pa, Ic = pc;
-                {
-                    const float qa = __shfl_down(Ia, 16), qc = __shfl_down(Ic, 16);
-                    if (g <= 2) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
-                }
-                {
-                    const float qa = __shfl_down(Ia, 32), qc = __shfl_down(Ic, 32);
-                    if (g <= 1) { Ic = Ia * qc + Ic; Ia = Ia * qa; }
-                }
-                float Ea = __shfl_down(Ia, 16), Ec = __shfl_down(Ic, 16);
-                if (g == 3) { Ea = 1.f; Ec = 0.f; }
-                const float Ta = __shfl(Ia, u), Tc = __shfl(Ic, u);
-                const float Xa = Ea * Ra, Xc = Ea * Rc + Ec;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    lc[mb][i] = la[mb][i] * Xc + lc[mb][i];
-                    la[mb][i] = la[mb][i] * Xa;
-                }
-                Rc = Ta * Rc + Tc;
-                Ra = Ta * Ra;
-            }
-            Pa = Ra;
-            Pc = Rc;
-#pragma unroll
-            for (int mb = 0; mb < C::MB; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
                     if (tl < len) {
-                        const size_t e = (size_t)(row0 + tl) * D + j;
-                        if (!fuse) a.la[e] = la[mb][i];
-                        lcn[e] = lc[mb][i];
+                        const size_t e = (size_t)row0 * D + o_row + (mb * 16 + i) * D;
+                        const float lam_t = lst[o_own + (mb * 16 + i) * C::HS];
+                        lam[e] = lam_t;
+                        mu_out[e] = lam_t + lc[mb][i];
                     }
                 }
         }
-        if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
+        if (g == 0) {
+            a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
+            if (!fuse) a.gprod[(size_t)gi * D + j] = Pa;
+        }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, off));
         if (l == 0) {
@@ -544,7 +607,7 @@ gru_adj_grad_kernel(GruAdjArgs a) {
       const TileInfo ti = tnext;
       if (tile + (int)gridDim.x < a.ntiles) tnext = a.tiles[tile + gridDim.x];   // read ahead
       const int b = ti.b;
-      const float* lam = (a.lam0_is_g && a.seq[b].iters == 0) ? a.gs : a.lam[a.seq[b].parity];
+      const float* lam = a.lam;
       for (int sub = 0; sub < SUB; ++sub) {
         const int len = min(L, ti.len - sub * L);
         if (len <= 0) break;
@@ -569,7 +632,7 @@ gru_adj_grad_kernel(GruAdjArgs a) {
             va[i] = ok ? *(const float4*)(gr + 0 * D) : z4;
             vb[i] = ok ? *(const float4*)(gr + 1 * D) : z4;
             vg[i] = ok ? *(const float4*)(gr + 2 * D) : z4;
-            ve[i] = ok ? *(const float4*)(gr + 3 * D) : z4;
+            ve[i] = ok ? *(const float4*)(a.eps + row * D + 4 * c4) : z4;
             vh[i] = !ok ? z4
                         : (tl == 0 && first) ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
                                              : *(const float4*)(a.s + (row - 1) * D + 4 * c4);
@@ -706,11 +769,10 @@ __global__ void gru_adj_gs0_kernel(GruAdjArgs a) {
     if (j >= D) return;
     const int64_t r0 = a.offsets[b];
     if (a.offsets[b + 1] == r0) { a.gs0[(size_t)b * D + j] = 0.f; return; }
-    const float* lam = ((a.lam0_is_g && a.seq[b].iters == 0) ? a.gs : a.lam[a.seq[b].parity]) +
-                       (size_t)r0 * D;
+    const float* lam = a.lam + (size_t)r0 * D;
     const float* gr = a.gates + (size_t)r0 * 4 * D;
     const float* U = a.params + 3 * D * DX;
-    float v = a.zd[(size_t)r0 * D + j].x * lam[j];
+    float v = gr[3 * D + j] * lam[j];
     for (int i = 0; i < D; ++i) {
         const float li = lam[i];
         v += U[(0 * D + i) * D + j] * gr[i] * li          // U_z^T (alpha * lambda)
@@ -730,7 +792,6 @@ __global__ void gru_adj_gs0_kernel(GruAdjArgs a) {
 // The per-step operands (g, alpha, beta, gamma, z) of the next PF steps are prefetched.
 template <int D>
 __global__ void __launch_bounds__(64) gru_seq_adj_kernel(const float* __restrict__ gates,
-                                                         const float2* __restrict__ zd,
                                                          const float* __restrict__ gs,
                                                          const float* __restrict__ U,
                                                          float* __restrict__ lam,
@@ -755,8 +816,7 @@ __global__ void __launch_bounds__(64) gru_seq_adj_kernel(const float* __restrict
     auto fetch = [&](int64_t it) {
         const int64_t row = r0 + (T - 1 - it);
         const float* gr = gates + (size_t)row * 4 * D;
-        return Ops{gs[(size_t)row * D + jj], gr[jj], gr[D + jj], gr[2 * D + jj],
-                   zd[(size_t)row * D + jj].x};
+        return Ops{gs[(size_t)row * D + jj], gr[jj], gr[D + jj], gr[2 * D + jj], gr[3 * D + jj]};
     };
     float v = 0.f;                                   // A_{t+1}^T lambda_{t+1}
     // reverse step it (t = T - 1 - it): lambda_t = g_t + v, then v <- A_t^T lambda_t
@@ -813,10 +873,9 @@ __global__ void __launch_bounds__(64) gru_seq_adj_kernel(const float* __restrict
 
 struct GruALayout {
     IterState st;
-    float *gates, *lam[2], *gmax, *part, *gcarry;
+    float *gates, *eps, *lam, *mu[2], *gprod, *gmax, *part, *gcarry;
     uint32_t *cmax, *grmax;
-    float2 *zd, *gagg;
-    float *la, *lc[2];
+    float2* gagg;
     size_t bytes;
 };
 
@@ -831,12 +890,12 @@ static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int 
     GruALayout lay;
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.gates = c.take<float>((size_t)hb.N * 4 * D);
-    lay.zd = c.take<float2>((size_t)hb.N * D);
-    for (int p = 0; p < 2; ++p) lay.lam[p] = c.take<float>((size_t)hb.N * D);
-    lay.la = c.take<float>((size_t)hb.N * D);
-    for (int p = 0; p < 2; ++p) lay.lc[p] = c.take<float>((size_t)hb.N * D);
+    lay.eps = c.take<float>((size_t)hb.N * D);
+    lay.lam = c.take<float>((size_t)hb.N * D);
+    for (int p = 0; p < 2; ++p) lay.mu[p] = c.take<float>((size_t)hb.N * D);
     lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
     lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
+    lay.gprod = c.take<float>((size_t)std::max(ngroups, 1) * D);
     lay.gmax = c.take<float>(hb.B);
     lay.cmax = c.take<uint32_t>((size_t)std::max(ntiles, 1) * (D / 16));
     const size_t P = 3 * (size_t)D * Dx + 3 * (size_t)D * D + 4 * (size_t)D;
@@ -918,11 +977,10 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     args.gs = gs;
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
-    args.zd = lay.zd;
-    args.lam0_is_g = 1;
-    for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
-    args.la = lay.la;
-    for (int p = 0; p < 2; ++p) args.lc[p] = lay.lc[p];
+    args.eps = lay.eps;
+    args.lam = lay.lam;
+    for (int p = 0; p < 2; ++p) args.mu[p] = lay.mu[p];
+    args.gprod = lay.gprod;
     args.gagg = lay.gagg;
     args.gcarry = lay.gcarry;
     args.gmax = lay.gmax;
@@ -957,8 +1015,8 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     hipLaunchKernelGGL(kk.gmax, dim3(hb.B), dim3(256), 0, stream, args);
     PN_HIP(hipGetLastError());
     const int grid = std::max(1, std::min(ngroups, resident));
-    // iteration k forms lambda^(k) in lam[k & 1] from lam[(k + 1) & 1] (k from the control
-    // block), then the carries
+    // iteration k (k from the control block) forms lambda^(k) from mu[k & 1] and the carries
+    // of iteration k - 1, writes lambda^(k) and mu[(k + 1) & 1], then the carries
     auto one_iter = [&](hipStream_t st) {
         prof_launch("gru_adj_local", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(kk.iter, dim3(grid), dim3(kk.nt), 0, s2, args);
@@ -1004,8 +1062,7 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     const int D = cd.D, Dx = cd.Dx;
     GruAKernels kk;
     if (!gruA_lookup(D, Dx, &kk)) return PN_ERR_UNSUPPORTED;
-    void (*seqk)(const float*, const float2*, const float*, const float*, float*,
-                 const int64_t*) = nullptr;
+    void (*seqk)(const float*, const float*, const float*, float*, const int64_t*) = nullptr;
     switch (D) {
         case 16: seqk = gru_seq_adj_kernel<16>; break;
         case 32: seqk = gru_seq_adj_kernel<32>; break;
@@ -1024,8 +1081,8 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
     args.gs = gs;
     args.params = (const float*)cd.params;
     args.gates = lay.gates;
-    args.zd = lay.zd;
-    for (int p = 0; p < 2; ++p) args.lam[p] = lay.lam[p];
+    args.eps = lay.eps;
+    args.lam = lay.lam;
     args.gmax = lay.gmax;
     args.cmax = lay.cmax;
     args.ctrl = lay.st.ctrl;
@@ -1044,9 +1101,8 @@ pn_status seq_bptt_run(const pn_cell_desc& cd, const HostBatch& hb, const float*
                            dim3(kk.nt), 0, stream, args);
     const float* U = (const float*)cd.params + 3 * D * Dx;
     prof_launch("seq_adj", stream, [&](hipStream_t s2) {
-        hipLaunchKernelGGL(seqk, dim3(hb.B), dim3(64), 0, s2, (const float*)lay.gates,
-                           (const float2*)lay.zd, gs, U, lay.lam[0],
-                           (const int64_t*)lay.st.offsets);
+        hipLaunchKernelGGL(seqk, dim3(hb.B), dim3(64), 0, s2, (const float*)lay.gates, gs, U,
+                           lay.lam, (const int64_t*)lay.st.offsets);
     });
     PN_HIP(hipGetLastError());
     const int gg = grad_grid();
