@@ -158,6 +158,14 @@ gru_quasi_local_kernel(GruQArgs a) {
                     chalo = *(const float4*)(a.gcarry + (size_t)ti.hgslot * D + 4 * c4);
             }
             __syncthreads();                 // LDS of the previous tile consumed
+            // Lane offsets into the LDS tiles and the [N][D] rows, formed anew for every tile
+            // (hidden from the optimiser): hoisted out of the loops, one precomputed address
+            // per (row, operand) would stay live across the whole group loop.
+            int o_arow = u * C::HS;                  // hs / xs: GEMM operand row u (x: o_xrow)
+            int o_xrow = u * C::XS;
+            int o_own = 4 * g * C::HS + j;           // hs: row 4 g, column j
+            int o_row = 4 * g * D + j;               // [N][D] arrays: own row 4 g, column j
+            asm volatile("" : "+v"(o_arow), "+v"(o_xrow), "+v"(o_own), "+v"(o_row));
 #pragma unroll
             for (int i0 = 0; i0 < NI; i0 += NB) {
                 float4 v[NB], p0[NB], p1[NB];
@@ -256,12 +264,14 @@ gru_quasi_local_kernel(GruQArgs a) {
 #pragma unroll
             for (int mb = 0; mb < C::MB; ++mb) {
                 floatx4 az, ar, aq, an;
-                wg.gemm(hs + (mb * 16 + u) * C::HS, xs + (mb * 16 + u) * C::XS, g, az, ar, aq, an);
+                wg.gemm(hs + o_arow + mb * 16 * C::HS, xs + o_xrow + mb * 16 * C::XS, g, az, ar, aq,
+                        an);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;      // step index within the tile
-                    const float h = hs[tl * C::HS + j];      // s_{t-1}
-                    const float sc = hs[(tl + 1) * C::HS + j];   // s_t (current iterate)
+                    const float* hp = hs + o_own + (mb * 16 + i) * C::HS;
+                    const float h = hp[0];                   // s_{t-1}
+                    const float sc = hp[C::HS];              // s_t (current iterate)
                     const GruPoint p = gru_point(az[i], ar[i], aq[i], an[i], wg.b_z, wg.b_r,
                                                  wg.b_n, wg.b_hn);
                     const float f = (1.f - p.z) * p.n + p.z * h;
@@ -326,7 +336,8 @@ gru_quasi_local_kernel(GruQArgs a) {
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;
                     if (tl < len)
-                        lacn[(size_t)(row0 + tl) * D + j] = make_float2(la[mb][i], lc[mb][i]);
+                        lacn[(size_t)row0 * D + o_row + (mb * 16 + i) * D] =
+                            make_float2(la[mb][i], lc[mb][i]);
                 }
         }
         if (g == 0) a.gagg[(size_t)gi * D + j] = make_float2(Pa, Pc);
