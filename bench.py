@@ -61,10 +61,12 @@ def fwd_iter_bytes(D, Dx):
 
 
 def adj_iter_bytes(D):
-    """Algorithmic HBM bytes per step of one adjoint iteration: the VJP operands lambda,
-    alpha, beta, gamma, z and g (24 D) and the diagonal scan's transition, additive term, old
-    and new iterate (16 D): 40 D (1.5 GiB + 1.07 GB per iteration at D = 64, N = 2^20)."""
-    return 40 * D
+    """Algorithmic HBM bytes per step of one adjoint iteration: the successor step's gate row
+    (alpha, beta, gamma, z: 16 D), the stored mu = lambda + lc of the previous iteration and
+    g (8 D) read, the new mu and lambda written (8 D): 32 D.  The scan's transition is
+    recomputed from the gate row that the VJP reads anyway; storing it and the additive map
+    per step instead would move 40 D."""
+    return 32 * D
 
 
 TRAFFIC_FILES = {WORKLOAD: os.path.join(ROOT, "profiles", "gru48_ragged_hbm_traffic.txt"),

@@ -261,7 +261,8 @@ PN_DEV void adj_tile_scan(float (&sa)[MB][4], float (&sc)[MB][4], float& Ra, flo
 // + gamma U_r[j][j]), so per step an iteration reads mu, the gate row of the successor step and
 // g, and writes lambda and mu.
 template <int D, int DX, int L>
-__global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(64 * (D / 16))
+__attribute__((amdgpu_waves_per_eu(L <= 32 ? 3 : 2, L <= 32 ? 3 : 2)))
 gru_adj_local_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
     constexpr int MB = C::MB;
@@ -879,7 +880,7 @@ struct GruALayout {
     size_t bytes;
 };
 
-constexpr int kAdjL = 64;
+constexpr int kAdjL = 32;
 constexpr int kGradL = 32;
 
 static int grad_grid() { return 2 * cu_count(); }

@@ -78,7 +78,8 @@ struct GruQArgs {
 };
 
 template <int D, int DX, int L>
-__global__ void __launch_bounds__(64 * (D / 16)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(64 * (D / 16))
+__attribute__((amdgpu_waves_per_eu(L <= 32 ? 3 : 2, L <= 32 ? 3 : 2)))
 gru_quasi_local_kernel(GruQArgs a) {
     using C = GruQ<D, DX, L>;
     __shared__ __attribute__((aligned(16))) float hs[(L + 1) * C::HS];
@@ -149,7 +150,7 @@ gru_quasi_local_kernel(GruQArgs a) {
             constexpr int NSV = ((L + 1) * Q + C::NT - 1) / C::NT;
             constexpr int NXV = (L * QX + C::NT - 1) / C::NT;
             constexpr int NI = NSV + NXV;
-            constexpr int NB = 4;
+            constexpr int NB = L <= 32 ? 2 : 4;
             const int c4 = tid % Q;
             float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
             if (fuse) {      // in flight together with the staging loads below
@@ -165,7 +166,11 @@ gru_quasi_local_kernel(GruQArgs a) {
             int o_xrow = u * C::XS;
             int o_own = 4 * g * C::HS + j;           // hs: row 4 g, column j
             int o_row = 4 * g * D + j;               // [N][D] arrays: own row 4 g, column j
-            asm volatile("" : "+v"(o_arow), "+v"(o_xrow), "+v"(o_own), "+v"(o_row));
+            int o_st = (tid / Q) * C::HS + 4 * c4;   // staging: s item 0 in hs
+            int o_sg = (tid / Q) * D + 4 * c4;       // staging: s item 0 in [N][D]
+            asm volatile("" : "+v"(o_arow), "+v"(o_xrow), "+v"(o_own), "+v"(o_row), "+v"(o_st),
+                              "+v"(o_sg));
+            constexpr int RQ = C::NT / Q;            // s item i of a thread is row tid / Q + i RQ
 #pragma unroll
             for (int i0 = 0; i0 < NI; i0 += NB) {
                 float4 v[NB], p0[NB], p1[NB];
@@ -179,12 +184,11 @@ gru_quasi_local_kernel(GruQArgs a) {
                     if (i < NSV) {
                         const int idx = tid + i * C::NT;
                         const int r = idx / Q;
-                        const int64_t row = r == 0 ? row0 - 1 : row0 + r - 1;
                         const bool ok = idx < (L + 1) * Q && (r == 0 || r - 1 < len);
                         if (r == 0 && first) {
                             v[q] = *(const float4*)(a.s0 + (size_t)b * D + 4 * c4);
                         } else if (ok) {
-                            const size_t e = (size_t)row * D + 4 * c4;
+                            const size_t e = (size_t)(row0 - 1) * D + o_sg + i * RQ * D;
                             v[q] = *(const float4*)((fuse ? sprev : scur) + e);
                             if (fuse) {
                                 p0[q] = *(const float4*)(lacp + e);
@@ -224,7 +228,7 @@ gru_quasi_local_kernel(GruQArgs a) {
                                     !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
                                     rowbad[r] = 1;
                             }
-                            *(float4*)(hs + r * C::HS + 4 * c4) = w4;
+                            *(float4*)(hs + o_st + i * RQ * C::HS) = w4;
                         }
                     } else if (i < NI) {
                         const int idx = tid + (i - NSV) * C::NT;
