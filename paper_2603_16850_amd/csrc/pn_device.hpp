@@ -98,4 +98,21 @@ PN_DEV float tanh_rcp(float a) {
 
 PN_DEV int lane_id() { return __lane_id(); }
 
+// ---- cross-lane sums on the VALU ---------------------------------------------------------------
+// x + x of lane l ^ 32 (sum_halves) or lane l ^ 16 (sum_rows16), the same bits on both lanes
+// of a pair.  v_permlane32_swap / v_permlane16_swap exchange the two halves of the wave (the odd
+// and even 16-lane rows) between two registers; swapping x with itself leaves x of one lane of
+// the pair in each result register, and their sum does not depend on which.  Unlike a shuffle
+// (ds_bpermute) this does not go through the LDS unit.
+PN_DEV float sum_halves(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+PN_DEV float sum_rows16(float x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 }  // namespace pn

@@ -106,6 +106,20 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
     float wrow[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) wrow[i] = Wm[n * TD + 16 * g + i];
+    // (W v)[n] for v in LDS: the lane's 16 products in four independent partial sums, the two
+    // half-waves' halves added on the VALU (the same bits on both halves)
+    auto wdot = [&](const float* v) {
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+            const float4 q = *(const float4*)(v + 16 * g + i);
+            p0 += wrow[i] * q.x;
+            p1 += wrow[i + 1] * q.y;
+            p2 += wrow[i + 2] * q.z;
+            p3 += wrow[i + 3] * q.w;
+        }
+        return sum_halves((p0 + p1) + (p2 + p3));
+    };
     if (BF16) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -186,20 +200,14 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
                 }
                 // one wave: the LDS exchange of Delta between lanes needs no barrier (the wave's
                 // LDS operations complete in order); the wave barrier keeps the compiler from
-                // moving them across steps
+                // moving them across steps.  Both half-waves hold the same values and both
+                // write them (no divergent branch on the chain).
                 for (int t = 0; t < len; ++t) {
-                    const float* prev = dvec[t & 1];
-                    float part = 0.f;
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) part += wrow[i] * prev[16 * g + i];
-                    part += __shfl_xor(part, 32);
-                    const float dl = dsh[t * TD + n] * part + csh[t * TD + n];
+                    const float dl = dsh[t * TD + n] * wdot(dvec[t & 1]) + csh[t * TD + n];
                     const float v = sst[(t + 1) * SS + n] + dl;
                     const bool rb = __any(!(fabsf(v) <= reset_abs));
-                    if (g == 0) {
-                        dvec[(t + 1) & 1][n] = dl;
-                        sst[(t + 1) * SS + n] = rb ? 0.f : v;
-                    }
+                    dvec[(t + 1) & 1][n] = dl;
+                    sst[(t + 1) * SS + n] = rb ? 0.f : v;
                     nreset += rb ? 1 : 0;
                     __builtin_amdgcn_wave_barrier();
                 }
@@ -246,15 +254,11 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
                         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa_f[p], pacc[p], acc, 0, 0, 0);
                 }
                 // q chain (LDS exchange within the wave, as in the replay)
-                float part = 0.f;
-#pragma unroll
-                for (int i = 0; i < 16; ++i) part += wrow[i] * vec[16 * g + i];
-                part += __shfl_xor(part, 32);
-                const float qn = dt[n] * part + csh[t * TD + n];
+                const float qn = dt[n] * wdot(vec) + csh[t * TD + n];
 #pragma unroll
                 for (int e = 0; e < 16; ++e) pacc[e] = dt[acc_row(g, e)] * acc[e];
                 __builtin_amdgcn_wave_barrier();
-                if (g == 0) vec[n] = qn;
+                vec[n] = qn;
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -282,7 +286,7 @@ __global__ void __launch_bounds__(256) dense_carry_kernel(const float* __restric
                                                           const Ctrl* ctrl, const SeqState* seq,
                                                           const int32_t* group_start, int B) {
     __shared__ __attribute__((aligned(16))) float buf[2][CB * GMAP];
-    __shared__ float cv[2][TD];
+    __shared__ __attribute__((aligned(16))) float cv[2][TD];
     if (ld_i32(&ctrl->all_done)) return;
     const int b = blockIdx.x;
     if (b >= B || seq[b].status != kActive) return;       // same on every thread
@@ -316,11 +320,16 @@ __global__ void __launch_bounds__(256) dense_carry_kernel(const float* __restric
             for (int q = 0; q < gcount; ++q) {
                 const float* P = bb + q * GMAP;
                 if (g == 0) gcarry[(size_t)(g0 + j * CB + q) * TD + n] = cv[cur][n];
-                float part = 0.f;
+                float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) part += P[(16 * g + i) * TD + n] * cv[cur][16 * g + i];
-                part += __shfl_xor(part, 32);
-                if (g == 0) cv[cur ^ 1][n] = part + P[TD * TD + n];
+                for (int i = 0; i < 16; i += 4) {
+                    const float4 c = *(const float4*)(cv[cur] + 16 * g + i);
+                    p0 += P[(16 * g + i) * TD + n] * c.x;
+                    p1 += P[(16 * g + i + 1) * TD + n] * c.y;
+                    p2 += P[(16 * g + i + 2) * TD + n] * c.z;
+                    p3 += P[(16 * g + i + 3) * TD + n] * c.w;
+                }
+                cv[cur ^ 1][n] = sum_halves((p0 + p1) + (p2 + p3)) + P[TD * TD + n];
                 __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the LDS write has landed
                 __builtin_amdgcn_wave_barrier();
                 cur ^= 1;
@@ -597,6 +606,21 @@ __global__ void __launch_bounds__(64) tanh_adj_local_kernel(TanhAdjArgs a) {
     float wcol[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) wcol[i] = Wm[(16 * g + i) * TD + n];
+    // (W^T (e .* v))[n] for e, v in LDS: four independent partial sums, the half-waves' halves
+    // added on the VALU (the same bits on both halves)
+    auto wtdot = [&](const float* e, const float* v) {
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+            const float4 ee = *(const float4*)(e + 16 * g + i);
+            const float4 vv = *(const float4*)(v + 16 * g + i);
+            p0 += wcol[i] * (ee.x * vv.x);
+            p1 += wcol[i + 1] * (ee.y * vv.y);
+            p2 += wcol[i + 2] * (ee.z * vv.z);
+            p3 += wcol[i + 3] * (ee.w * vv.w);
+        }
+        return sum_halves((p0 + p1) + (p2 + p3));
+    };
     if (BF16) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -671,13 +695,7 @@ __global__ void __launch_bounds__(64) tanh_adj_local_kernel(TanhAdjArgs a) {
                 // moving them across steps
                 for (int it = 0; it < len; ++it) {
                     const int t = len - 1 - it;
-                    const float* prev = dvec[it & 1];
-                    const float* et = est + t * SS;
-                    float part = 0.f;
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) part += wcol[i] * (et[16 * g + i] * prev[16 * g + i]);
-                    part += __shfl_xor(part, 32);
-                    const float dl = part + csh[t * TD + n];
+                    const float dl = wtdot(est + t * SS, dvec[it & 1]) + csh[t * TD + n];
                     if (g == 0) {
                         dvec[(it + 1) & 1][n] = dl;
                         lst[t * SS + n] += dl;
@@ -728,11 +746,7 @@ __global__ void __launch_bounds__(64) tanh_adj_local_kernel(TanhAdjArgs a) {
                         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wa_f[p], et[acc_row(g, p)] * pacc[p],
                                                                    acc, 0, 0, 0);
                 }
-                float part = 0.f;
-#pragma unroll
-                for (int i = 0; i < 16; ++i) part += wcol[i] * (et[16 * g + i] * vec[16 * g + i]);
-                part += __shfl_xor(part, 32);
-                qreg = part + csh[t * TD + n];
+                qreg = wtdot(et, vec) + csh[t * TD + n];
 #pragma unroll
                 for (int e = 0; e < 16; ++e) pacc[e] = acc[e];
                 __builtin_amdgcn_wave_barrier();
