@@ -385,8 +385,7 @@ __global__ void __launch_bounds__(64, KF ? 2 : 4) elk_local_kernel(ElkArgs a) {
     auto row_dot = [&](const float (&av)[4], float v) {     // (A_t v)[u], v[k] held by lane k
         float p = av[0] * __shfl(v, 4 * q) + av[1] * __shfl(v, 4 * q + 1) +
                   av[2] * __shfl(v, 4 * q + 2) + av[3] * __shfl(v, 4 * q + 3);
-        p += __shfl_xor(p, 16);
-        p += __shfl_xor(p, 32);
+        p = sum_halves(sum_rows16(p));
         return p;
     };
 
@@ -1309,8 +1308,7 @@ __global__ void __launch_bounds__(64) elk_deer_carry_kernel(const float* __restr
         if (q == 0) gcar[(size_t)(g0 + gg) * ECAR + ED * ED + r] = m;
         float acc = ac.x * __shfl(m, 4 * q) + ac.y * __shfl(m, 4 * q + 1) +
                     ac.z * __shfl(m, 4 * q + 2) + ac.w * __shfl(m, 4 * q + 3);
-        acc += __shfl_xor(acc, 16);
-        acc += __shfl_xor(acc, 32);
+        acc = sum_halves(sum_rows16(acc));
         m = acc + bc;
     }
 }
@@ -1397,8 +1395,7 @@ __global__ void __launch_bounds__(1024) elk_deer_seg_carry_kernel(
             o = mfma16x4(ea[k].w, acc[3], o);
             float pb = ea[k].x * __shfl(bacc, 4 * q) + ea[k].y * __shfl(bacc, 4 * q + 1) +
                        ea[k].z * __shfl(bacc, 4 * q + 2) + ea[k].w * __shfl(bacc, 4 * q + 3);
-            pb += __shfl_xor(pb, 16);
-            pb += __shfl_xor(pb, 32);
+            pb = sum_halves(sum_rows16(pb));
             bacc = pb + eb[k];
             acc = o;
         }
@@ -1415,8 +1412,7 @@ __global__ void __launch_bounds__(1024) elk_deer_seg_carry_kernel(
             const float4 as = *(const float4*)(Sm[s] + r * kDStr + 4 * q);
             float v = as.x * __shfl(m, 4 * q) + as.y * __shfl(m, 4 * q + 1) +
                       as.z * __shfl(m, 4 * q + 2) + as.w * __shfl(m, 4 * q + 3);
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
+            v = sum_halves(sum_rows16(v));
             m = v + Sb[s][r];
         }
     }
@@ -1435,8 +1431,7 @@ __global__ void __launch_bounds__(1024) elk_deer_seg_carry_kernel(
             if (q == 0) gcar[(size_t)(g0 + base + k) * ECAR + ED * ED + r] = m;
             float v = ea[k].x * __shfl(m, 4 * q) + ea[k].y * __shfl(m, 4 * q + 1) +
                       ea[k].z * __shfl(m, 4 * q + 2) + ea[k].w * __shfl(m, 4 * q + 3);
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
+            v = sum_halves(sum_rows16(v));
             m = v + eb[k];
         }
     }
@@ -1591,8 +1586,7 @@ __global__ void __launch_bounds__(64) elk_back_carry_kernel(const float* __restr
         if (gg > 1) load(gg - 1, qn, vn);
         float acc = qc.x * __shfl(right, 4 * q) + qc.y * __shfl(right, 4 * q + 1) +
                     qc.z * __shfl(right, 4 * q + 2) + qc.w * __shfl(right, 4 * q + 3);
-        acc += __shfl_xor(acc, 16);
-        acc += __shfl_xor(acc, 32);
+        acc = sum_halves(sum_rows16(acc));
         right = acc + vc;                                  // m^s at the end of group gg - 1
         if (q == 0) bcar[(size_t)(g0 + gg - 1) * ED + r] = right;
     }
@@ -1648,8 +1642,7 @@ __global__ void __launch_bounds__(64) elk_back_apply_kernel(ElkBackArgs a) {
             if (t - 1 >= ra) load(t - 1, en, gn, sn);
             float acc = ec.x * __shfl(right, 4 * q) + ec.y * __shfl(right, 4 * q + 1) +
                         ec.z * __shfl(right, 4 * q + 2) + ec.w * __shfl(right, 4 * q + 3);
-            acc += __shfl_xor(acc, 16);
-            acc += __shfl_xor(acc, 32);
+            acc = sum_halves(sum_rows16(acc));
             right = acc + gc;                              // m^s_t
             const float v = sc + right;
             const bool bad = __any(q == 0 && !(fabsf(v) <= reset_abs));

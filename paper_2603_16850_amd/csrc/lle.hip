@@ -16,11 +16,7 @@ namespace {
 constexpr int LD = 16;
 
 // sum over the four column quarters of a row (lanes r, r + 16, r + 32, r + 48)
-PN_DEV float rowsum(float v) {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
-}
+PN_DEV float rowsum(float v) { return sum_halves(sum_rows16(v)); }
 // (M v)[r] for M's row slice m (columns 4q..4q+3) and v held as lane r's value
 PN_DEV float matvec(float4 m, float v, int q) {
     return rowsum(m.x * __shfl(v, 4 * q) + m.y * __shfl(v, 4 * q + 1) +
