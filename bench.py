@@ -124,7 +124,7 @@ def roofline_of(kernel, D, Dx, units, avg_ms):
             "algorithmic_per_launch": nbytes}
 
 
-def run_workload(torch, pn, work, inst, args, steps, warmup):
+def run_workload(torch, pn, work, inst, args, steps, warmup, tile):
     """Tunes, warms up, times `steps` fwd+bwd steps on the default (graph) path, then one
     profiled step for the kernel figures and the sequential GPU baseline."""
     D, Dx, N = work.D, work.Dx, inst.N
@@ -136,7 +136,7 @@ def run_workload(torch, pn, work, inst, args, steps, warmup):
               graph_iters=GRAPH_ITERS, freeze_prefix=args.freeze)
     kw_f, kw_b = dict(kw), dict(kw, tol=args.adj_tol)
     tuned = None
-    if args.tile == "auto":
+    if tile == "auto":
         # one-time plan: the autotuner times the candidate tile / group lengths of both passes
         # on these inputs (8 iterations each); excluded from the timed region, reported
         torch.cuda.synchronize()
@@ -151,8 +151,8 @@ def run_workload(torch, pn, work, inst, args, steps, warmup):
         kw_f.update(tile=tf["tile"], group=tf["group"])
         kw_b.update(group=tb["group"])
         del s_tr
-    elif args.tile != "default":
-        L, G, GA = (int(v) for v in args.tile.split(","))
+    elif tile != "default":
+        L, G, GA = (int(v) for v in tile.split(","))
         kw_f.update(tile=L, group=G)
         kw_b.update(group=GA)
         tuned = {"given": {"fwd_tile": L, "fwd_group": G, "adj_group": GA}}
@@ -272,6 +272,8 @@ def main():
                          "'default': the cost-model choice; 'L,G,GA': forward tile L and group "
                          "G, adjoint group GA as given (e.g. to replay a tuned choice under a "
                          "profiler without the tuning launches)")
+    ap.add_argument("--secondary-tile", default="auto",
+                    help="the same choice for the secondary workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -308,7 +310,7 @@ def main():
         sys.exit(2)
     pn.load()
 
-    r = run_workload(torch, pn, work, inst, args, args.steps, args.warmup)
+    r = run_workload(torch, pn, work, inst, args, args.steps, args.warmup, args.tile)
     s, gp, gx, g0, s_seq = r["out"]
     err = errors(cpu, s, gp, gx, g0, s_seq) if cpu is not None else None
     err_ok = None if err is None else all(err[k] <= ERR_BAR for k in ("s", "gparams", "gx", "gs0"))
@@ -356,7 +358,8 @@ def main():
         rec["cpu_single_core"] = cpu["single_core"]
     del r
     if inst2 is not None:
-        r2 = run_workload(torch, pn, work2, inst2, args, args.secondary_steps, 1)
+        r2 = run_workload(torch, pn, work2, inst2, args, args.secondary_steps, 1,
+                          args.secondary_tile)
         s, gp, gx, g0, s_seq = r2["out"]
         e2 = errors(cpu2, s, gp, gx, g0, s_seq) if cpu2 is not None else None
         rec["secondary"] = {
