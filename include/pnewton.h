@@ -345,11 +345,14 @@ pn_status pn_autotune(int op, const pn_cell_desc* cell, const pn_batch* batch,
 void pn_autotune_reset(void);
 
 /* Copy-bandwidth probe: copies `bytes` (a positive multiple of 16) from src to dst (device,
-   16-byte aligned, not overlapping) with a plain streaming kernel, once untimed and then
-   `reps` times between HIP events on `stream`, and returns in *gbs (host) the achieved rate
+   16-byte aligned, not overlapping) with plain streaming kernels — two forms (four 16-byte
+   loads in flight per thread; one per thread and iteration with non-temporal hints) on grids
+   of 1, 2, 3, 4, 6 and 8 workgroups of 256 threads per CU — each once untimed and then `reps`
+   times between HIP events on `stream`, and returns in *gbs (host) the best achieved rate
    counting read plus write bytes (2 * bytes * reps / time).  It gives the HBM rate a simple
-   kernel reaches on the device, next to the published peak, and a dispatch of known size for
-   scaling the FETCH_SIZE / WRITE_SIZE counters (kernel copy_probe_kernel). */
+   kernel reaches on the device, next to the published peak, and dispatches of known size for
+   scaling the FETCH_SIZE / WRITE_SIZE counters (kernels copy_probe_kernel<0>, <1>).  Runs 12
+   configurations: about 12 * (reps + 1) copies of `bytes`. */
 pn_status pn_copy_probe(const void* src, void* dst, size_t bytes, int reps, void* stream,
                         double* gbs);
 

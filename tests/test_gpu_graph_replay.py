@@ -188,3 +188,47 @@ def test_replay_elk_same_tiles_other_longest_sequence(lib):
         off = np.concatenate([[0], np.cumsum(lens)])
         _solve_fixed(lib, lib.OP_ELK, "tanh", X, S0, P, S, WS, off,
                      dict(jac="dense", tol=1e-6, graph_iters=4, max_iters=12, tile=32), lam=0.1)
+
+
+def test_two_threads_evicting_the_graph_cache(lib):
+    """Two host threads solve on their own buffers with 40 different lengths each, so that the
+    process-wide cache of instantiated iteration graphs (64 entries) evicts while the other
+    thread looks up, updates and launches its own executables; every result equals the same
+    solve made alone beforehand, bit for bit."""
+    import threading
+    import torch
+    w = workloads.GRU48_RAGGED.scaled(B=1, T=0)
+    lens = {0: list(range(100, 140)), 1: list(range(200, 240))}
+    kw = dict(cell="gru", jac="diag", tol=1e-6, graph_iters=2, tile=32, group=2)
+    inputs = {}
+    for k, ls in lens.items():
+        for T in ls:
+            inst = workloads.make_instance(w, seed=600 + T, lengths=np.array([T]))
+            inputs[(k, T)] = (_t(inst.x), _t(inst.s0), _t(inst.params), inst.offsets)
+    want = {}
+    for key, (x, s0, p, off) in inputs.items():
+        s, info = lib.deer_solve(x, s0, p, offsets=off, **kw)
+        want[key] = (s.cpu().numpy(), info[0]["iters"])
+    torch.cuda.synchronize()
+    got, errors = {}, []
+
+    def work(k):
+        try:
+            for T in lens[k]:
+                x, s0, p, off = inputs[(k, T)]
+                s, info = lib.deer_solve(x, s0, p, offsets=off, **kw)
+                torch.cuda.current_stream().synchronize()
+                got[(k, T)] = (s.cpu().numpy(), info[0]["iters"])
+        except Exception as e:      # reported by the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in lens]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    assert set(got) == set(want)
+    for key in want:
+        assert got[key][1] == want[key][1], key
+        assert np.array_equal(got[key][0], want[key][0]), key
