@@ -332,3 +332,24 @@ def test_binding_checks_shapes_before_any_call():
     # the per-step affine cell packs one matrix per row
     assert pn.param_count("affine_steps", 3, 2, N=10) == 10 * 9 + 6 + 3
     assert pn.param_count("affine", 3, 2) == 9 + 6 + 3
+
+
+def test_copy_probe_rejects_bad_arguments(lib):
+    """pn_copy_probe validates before any HIP call: NULL pointers, sizes that are not a positive
+    multiple of 16, misaligned pointers and reps < 1 are PN_ERR_INVALID_ARG."""
+    out = ctypes.c_double(-1.0)
+    ok = ctypes.c_void_p(1 << 20)
+    bad = [
+        (None, ok, 1024, 1, ctypes.byref(out)),
+        (ok, None, 1024, 1, ctypes.byref(out)),
+        (ok, ok, 1024, 1, None),
+        (ok, ok, 0, 1, ctypes.byref(out)),
+        (ok, ok, 1000, 1, ctypes.byref(out)),
+        (ctypes.c_void_p((1 << 20) + 4), ok, 1024, 1, ctypes.byref(out)),
+        (ok, ctypes.c_void_p((1 << 20) + 8), 1024, 1, ctypes.byref(out)),
+        (ok, ok, 1024, 0, ctypes.byref(out)),
+    ]
+    for src, dst, nbytes, reps, gbs in bad:
+        assert lib.pn_copy_probe(src, dst, nbytes, reps, None, gbs) == -1
+        assert b"pn_copy_probe" in lib.pn_last_error()
+    assert out.value == -1.0
