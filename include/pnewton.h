@@ -196,7 +196,7 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
    info: HOST array [B] (may be NULL).  Built combinations:
      GRU,  PN_JAC_DIAG / PN_JAC_PICARD / PN_JAC_JACOBI, F32, (D, Dx) in
            {(16,8), (16,16), (32,8), (32,16), (32,32), (48,24), (48,48), (64,16), (64,32),
-            (64,64)}, tile 0 (default), 32, 64 or 128, any damping
+            (64,64)}, tile 0 (default), 32, 64 or 128 (not 128 at (64,64)), any damping
      GRU,  PN_JAC_DENSE, F64, 1 <= D <= 4, 1 <= Dx <= 16, no damping
      TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16, no damping or
            PN_DAMP_SCALE

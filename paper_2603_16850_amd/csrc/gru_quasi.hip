@@ -3,10 +3,11 @@
 // Tiles are L consecutive steps; groups are runs of consecutive tiles of one sequence (see
 // IterState).  Iteration k:
 //   local pass (gru_quasi_local_kernel), one workgroup per group of tiles, tile by tile:
-//     1. stages s_{t-1}, s_t (L+1 rows) and x_t (L rows) in LDS.  For k >= 1 the rows of
-//        s^(k) are formed on the way in from s^(k-1) and the previous iteration's maps,
-//        s^(k)_t = s^(k-1)_t + la_t carry + lc_t, the reset guard applied (a row with a
-//        non-finite entry or one above reset_abs becomes 0), and written back;
+//     1. stages s_{t-1}, s_t (L+1 rows) and x_t (L rows) in LDS (the tile's rows of s, of
+//        the previous maps and of x are contiguous blocks, copied straight from HBM into
+//        LDS).  For k >= 1 the rows of s^(k) are formed from s^(k-1) and the previous
+//        iteration's maps, s^(k)_t = s^(k-1)_t + la_t carry + lc_t, the reset guard applied (a
+//        row with a non-finite entry or one above reset_abs becomes 0), and written back;
 //     2. evaluates the gate pre-activations of f(s_{t-1}, x_t) for the L steps as a small
 //        GEMM [L x (D+Dx)] x [(D+Dx) x 4 gate blocks] on FP32 MFMA (16x16x4), the weights
 //        held in registers for the whole kernel;
@@ -83,7 +84,9 @@ __attribute__((amdgpu_waves_per_eu(L <= 32 ? 3 : 2, L <= 32 ? 3 : 2)))
 gru_quasi_local_kernel(GruQArgs a) {
     using C = GruQ<D, DX, L>;
     __shared__ __attribute__((aligned(16))) float hs[(L + 1) * C::HS];
-    __shared__ __attribute__((aligned(16))) float xs[L * C::XS];
+    __shared__ __attribute__((aligned(16))) float xs[L * DX];           // x rows, unpadded
+    __shared__ __attribute__((aligned(16))) float sraw[(L + 1) * D];    // s rows as copied
+    __shared__ __attribute__((aligned(16))) float lraw[(L + 1) * 2 * D];// (la, lc) rows as copied
 
     __shared__ int rowbad[L + 1];
 
@@ -142,15 +145,14 @@ gru_quasi_local_kernel(GruQArgs a) {
             const bool first = (ti.flags & kTileTimeFirst) != 0;
 
             // ---- stage s rows row0-1 .. row0+L-1 (stage row r <-> s_{t0-1+r}) and x rows.
-            // Items 0 .. NSV-1 of a thread are float4s of s, the rest float4s of x, in
-            // batches whose loads are all issued before their LDS writes.  A thread's float4
-            // column c4 is the same for all its s items (NT is a multiple of D / 4).
-            constexpr int Q = D / 4, QX = DX / 4;
+            // The tile's rows of s, of the previous maps (la, lc) and of x are contiguous in
+            // HBM and go straight into LDS as whole blocks (global_load_lds, 1 KB per wave
+            // instruction, lane i's 16 B to byte 16 i of the slice), all in flight together;
+            // the update to s^(k) then runs LDS to LDS.  A thread's float4 column c4 is the same
+            // for all its s items (NT is a multiple of D / 4).
+            constexpr int Q = D / 4;
             static_assert(C::NT % Q == 0, "column per thread");
             constexpr int NSV = ((L + 1) * Q + C::NT - 1) / C::NT;
-            constexpr int NXV = (L * QX + C::NT - 1) / C::NT;
-            constexpr int NI = NSV + NXV;
-            constexpr int NB = L <= 32 ? 2 : 4;
             const int c4 = tid % Q;
             float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
             if (fuse) {      // in flight together with the staging loads below
@@ -163,79 +165,68 @@ gru_quasi_local_kernel(GruQArgs a) {
             // (hidden from the optimiser): hoisted out of the loops, one precomputed address
             // per (row, operand) would stay live across the whole group loop.
             int o_arow = u * C::HS;                  // hs / xs: GEMM operand row u (x: o_xrow)
-            int o_xrow = u * C::XS;
+            int o_xrow = u * DX;
             int o_own = 4 * g * C::HS + j;           // hs: row 4 g, column j
             int o_row = 4 * g * D + j;               // [N][D] arrays: own row 4 g, column j
             int o_st = (tid / Q) * C::HS + 4 * c4;   // staging: s item 0 in hs
-            int o_sg = (tid / Q) * D + 4 * c4;       // staging: s item 0 in [N][D]
-            asm volatile("" : "+v"(o_arow), "+v"(o_xrow), "+v"(o_own), "+v"(o_row), "+v"(o_st),
-                              "+v"(o_sg));
+            asm volatile("" : "+v"(o_arow), "+v"(o_xrow), "+v"(o_own), "+v"(o_row), "+v"(o_st));
             constexpr int RQ = C::NT / Q;            // s item i of a thread is row tid / Q + i RQ
+            {
+                // nbytes (a multiple of 16) from src to LDS dst, 1 KB per wave instruction
+                auto bulk = [&](float* dst, const float* src, int nbytes) {
+                    for (int c = w; c * 1024 < nbytes; c += C::NW) {
+                        const int off = c * 1024 + 16 * l;
+                        if (off < nbytes)
+                            __builtin_amdgcn_global_load_lds(
+                                (const void*)((const char*)src + off),
+                                (__attribute__((address_space(3))) void*)((char*)dst + c * 1024),
+                                16, 0, 0);
+                    }
+                };
+                // staged row 0 is the halo s_{t0-1}: s0 at a sequence's first tile
+                const int hr = first ? 1 : 0;
+                const int64_t srow = row0 - 1 + hr;
+                const int nrow = len + 1 - hr;
+                bulk(sraw + hr * D, (fuse ? sprev : scur) + (size_t)srow * D, nrow * D * 4);
+                if (fuse)
+                    bulk(lraw + hr * 2 * D, (const float*)(lacp + (size_t)srow * D),
+                         nrow * 2 * D * 4);
+                bulk(xs, a.x + (size_t)row0 * DX, len * DX * 4);
+                if (first && tid < Q)
+                    *(float4*)(sraw + 4 * tid) = *(const float4*)(a.s0 + (size_t)b * D + 4 * tid);
+                __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): the copies have landed
+            }
+            __syncthreads();
 #pragma unroll
-            for (int i0 = 0; i0 < NI; i0 += NB) {
-                float4 v[NB], p0[NB], p1[NB];
-#pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int i = i0 + q;
-                    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    v[q] = z4;
-                    p0[q] = z4;
-                    p1[q] = z4;
-                    if (i < NSV) {
-                        const int idx = tid + i * C::NT;
-                        const int r = idx / Q;
-                        const bool ok = idx < (L + 1) * Q && (r == 0 || r - 1 < len);
-                        if (r == 0 && first) {
-                            v[q] = *(const float4*)(a.s0 + (size_t)b * D + 4 * c4);
-                        } else if (ok) {
-                            const size_t e = (size_t)(row0 - 1) * D + o_sg + i * RQ * D;
-                            v[q] = *(const float4*)((fuse ? sprev : scur) + e);
-                            if (fuse) {
-                                p0[q] = *(const float4*)(lacp + e);
-                                p1[q] = *(const float4*)(lacp + e + 2);
-                            }
-                        }
-                    } else if (i < NI) {
-                        const int idx = tid + (i - NSV) * C::NT;
-                        const int r = idx / QX, cx = idx % QX;
-                        if (idx < L * QX && r < len)
-                            v[q] = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * cx);
+            for (int i = 0; i < NSV; ++i) {
+                const int idx = tid + i * C::NT;
+                if (idx >= (L + 1) * Q) continue;
+                const int r = idx / Q;
+                float4 w4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r == 0 || r - 1 < len) {
+                    w4 = *(const float4*)(sraw + r * D + 4 * c4);
+                    if (fuse && !(r == 0 && (first || (kt == 0 && halo_frozen)))) {
+                        const float4 cv = r == 0 ? chalo : cown;
+                        const float4 p0 = *(const float4*)(lraw + r * 2 * D + 8 * c4);
+                        const float4 p1 = *(const float4*)(lraw + r * 2 * D + 8 * c4 + 4);
+                        const float d0 = p0.x * cv.x + p0.y;
+                        const float d1 = p0.z * cv.y + p0.w;
+                        const float d2 = p1.x * cv.z + p1.y;
+                        const float d3 = p1.z * cv.w + p1.w;
+                        w4.x += d0;
+                        w4.y += d1;
+                        w4.z += d2;
+                        w4.w += d3;
+                        // update norm of the group's own rows (row 0 is the halo)
+                        if (bydelta && r > 0)
+                            rmax = max(rmax, max(max(absbits(d0), absbits(d1)),
+                                                 max(absbits(d2), absbits(d3))));
+                        if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
+                            !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
+                            rowbad[r] = 1;
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int i = i0 + q;
-                    if (i < NSV) {
-                        const int idx = tid + i * C::NT;
-                        if (idx < (L + 1) * Q) {
-                            const int r = idx / Q;
-                            float4 w4 = v[q];
-                            if (fuse && !(r == 0 && (first || (kt == 0 && halo_frozen)))) {
-                                const float4 cv = r == 0 ? chalo : cown;
-                                const float d0 = p0[q].x * cv.x + p0[q].y;
-                                const float d1 = p0[q].z * cv.y + p0[q].w;
-                                const float d2 = p1[q].x * cv.z + p1[q].y;
-                                const float d3 = p1[q].z * cv.w + p1[q].w;
-                                w4.x += d0;
-                                w4.y += d1;
-                                w4.z += d2;
-                                w4.w += d3;
-                                // update norm of the group's own rows (row 0 is the halo)
-                                if (bydelta && r > 0)
-                                    rmax = max(rmax, max(max(absbits(d0), absbits(d1)),
-                                                         max(absbits(d2), absbits(d3))));
-                                if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
-                                    !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
-                                    rowbad[r] = 1;
-                            }
-                            *(float4*)(hs + o_st + i * RQ * C::HS) = w4;
-                        }
-                    } else if (i < NI) {
-                        const int idx = tid + (i - NSV) * C::NT;
-                        if (idx < L * QX)
-                            *(float4*)(xs + (idx / QX) * C::XS + 4 * (idx % QX)) = v[q];
-                    }
-                }
+                *(float4*)(hs + o_st + i * RQ * C::HS) = w4;
             }
             __syncthreads();
             if (fuse) {
@@ -268,7 +259,7 @@ gru_quasi_local_kernel(GruQArgs a) {
 #pragma unroll
             for (int mb = 0; mb < C::MB; ++mb) {
                 floatx4 az, ar, aq, an;
-                wg.gemm(hs + o_arow + mb * 16 * C::HS, xs + o_xrow + mb * 16 * C::XS, g, az, ar, aq,
+                wg.gemm(hs + o_arow + mb * 16 * C::HS, xs + o_xrow + mb * 16 * DX, g, az, ar, aq,
                         an);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -397,7 +388,9 @@ static void gruq_get(GruQKernel* k, int* nt) {
 static bool gruq_lookup(int D, int Dx, int L, GruQKernel* k, int* nt) {
 #define PN_GQ(d, dx, ll) if (D == d && Dx == dx && L == ll) { gruq_get<d, dx, ll>(k, nt); return true; }
 #define PN_GQL(d, dx) PN_GQ(d, dx, 32) PN_GQ(d, dx, 64) PN_GQ(d, dx, 128)
-    PN_GQL(64, 32) PN_GQL(48, 24) PN_GQL(32, 16) PN_GQL(16, 8) PN_GQL(16, 16) PN_GQL(64, 64)
+    // (64, 64) has no 128-step tiles: their staging would exceed the 160 KB of LDS
+    PN_GQL(64, 32) PN_GQL(48, 24) PN_GQL(32, 16) PN_GQL(16, 8) PN_GQL(16, 16)
+    PN_GQ(64, 64, 32) PN_GQ(64, 64, 64)
     PN_GQL(32, 32) PN_GQL(48, 48) PN_GQL(64, 16) PN_GQL(32, 8)
 #undef PN_GQL
 #undef PN_GQ
