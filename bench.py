@@ -37,9 +37,11 @@ ERR_BAR = 1e-5
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 
 # kernel families timed in the profiled pass (HIP events on the library's stream)
-FAMILIES = ("gru_quasi_local", "gru_adj_local", "carry_scan", "gru_adj_prep", "gru_adj_grad")
+FAMILIES = ("gru_quasi_local", "gru_adj_local", "carry_scan", "gru_adj_prep", "gru_adj_grad",
+            "gru_adj_dchain", "gru_adj_dmap", "gru_adj_dwalk", "gru_adj_dcheck")
 
 
 def gate_gemm_flops(D, Dx):
@@ -69,10 +71,30 @@ def adj_iter_bytes(D):
     return 32 * D
 
 
+def dmap_flops(D):
+    """Algorithmic MFMA flops per step of the dense adjoint's map pass: the group map's
+    product A_t^T M with a D x D M, 2 D^3 (the z-diagonal term is a VALU scaling)."""
+    return 2 * D ** 3
+
+
+def dmap_bytes(D):
+    """Algorithmic HBM bytes per step of the map pass: the step's gate row (16 D); the maps
+    themselves are written once per group."""
+    return 16 * D
+
+
+def dchain_bytes(D):
+    """Algorithmic HBM bytes per step of a dense-adjoint chain pass, averaged over its two
+    launches: the gate row and g (20 D) read by both, lambda (4 D) written by the second."""
+    return 22 * D
+
+
 TRAFFIC_FILES = {WORKLOAD: os.path.join(ROOT, "profiles", "gru48_ragged_hbm_traffic.txt"),
                  SECONDARY: os.path.join(ROOT, "profiles", "gru64_hbm_traffic.txt")}
 SOURCES = {"gru_quasi_local": ["gru_quasi.hip", "gru_common.hpp", "pn_device.hpp"],
-           "gru_adj_local": ["gru_adjoint.hip", "gru_common.hpp", "pn_device.hpp"]}
+           "gru_adj_local": ["gru_adjoint.hip", "gru_common.hpp", "pn_device.hpp"],
+           "gru_adj_dchain": ["gru_adj_dense.hip", "gru_common.hpp", "pn_device.hpp"],
+           "gru_adj_dmap": ["gru_adj_dense.hip", "gru_common.hpp", "pn_device.hpp"]}
 
 
 def source_sha(kernel):
@@ -107,17 +129,22 @@ def measured_traffic(workload, kernel):
 def roofline_of(kernel, D, Dx, units, avg_ms):
     """Both ceilings of a launch over `units` sequence-steps; the binding one (the longer time
     at peak) is reported."""
+    peak = PEAK_FP32_TFLOPS
     if kernel == "gru_quasi_local":
         flops, nbytes = gate_gemm_flops(D, Dx) * units, fwd_iter_bytes(D, Dx) * units
+    elif kernel == "gru_adj_dmap":
+        flops, nbytes, peak = dmap_flops(D) * units, dmap_bytes(D) * units, PEAK_BF16_TFLOPS
+    elif kernel == "gru_adj_dchain":
+        flops, nbytes = vjp_gemm_flops(D) * units, dchain_bytes(D) * units
     else:
         flops, nbytes = vjp_gemm_flops(D) * units, adj_iter_bytes(D) * units
-    t_mfma = flops / (PEAK_FP32_TFLOPS * 1e12)
+    t_mfma = flops / (peak * 1e12)
     t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
     if t_mfma >= t_hbm:
         achieved = flops / (avg_ms * 1e-3) / 1e12
         return {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 2),
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "algorithmic_per_launch": flops}
+                "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "algorithmic_per_launch": flops}
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
@@ -135,6 +162,10 @@ def run_workload(torch, pn, work, inst, args, steps, warmup, tile):
     kw = dict(cell="gru", offsets=inst.offsets, jac="diag", tol=args.tol,
               graph_iters=GRAPH_ITERS, freeze_prefix=args.freeze)
     kw_f, kw_b = dict(kw), dict(kw, tol=args.adj_tol)
+    dense = args.adjoint == "dense"
+    if dense:
+        kw_b.update(jac="dense", compose="bf16")
+        kw_b.pop("freeze_prefix")
     tuned = None
     if tile == "auto":
         # one-time plan: the autotuner times the candidate tile / group lengths of both passes
@@ -142,15 +173,20 @@ def run_workload(torch, pn, work, inst, args, steps, warmup, tile):
         torch.cuda.synchronize()
         tt0 = time.perf_counter()
         tf = pn.autotune("deer", x, s0, p, probe_iters=8, **kw)
-        s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
-        tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8, **kw_b)
-        torch.cuda.synchronize()
-        tuned = {"tune_ms": round((time.perf_counter() - tt0) * 1e3, 1),
-                 "fwd": {k: tf[k] for k in ("tile", "group", "ms_per_iter", "from_cache")},
-                 "adj": {k: tb[k] for k in ("group", "ms_per_iter", "from_cache")}}
         kw_f.update(tile=tf["tile"], group=tf["group"])
-        kw_b.update(group=tb["group"])
-        del s_tr
+        tuned = {"fwd": {k: tf[k] for k in ("tile", "group", "ms_per_iter", "from_cache")}}
+        if dense:
+            # the dense reverse scan takes its group length from the batch size (about 32 K
+            # groups); nothing to tune per iteration
+            tuned["adj"] = {"group": "default"}
+        else:
+            s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
+            tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8, **kw_b)
+            tuned["adj"] = {k: tb[k] for k in ("group", "ms_per_iter", "from_cache")}
+            kw_b.update(group=tb["group"])
+            del s_tr
+        torch.cuda.synchronize()
+        tuned["tune_ms"] = round((time.perf_counter() - tt0) * 1e3, 1)
     elif tile != "default":
         L, G, GA = (int(v) for v in tile.split(","))
         kw_f.update(tile=L, group=G)
@@ -212,14 +248,19 @@ def run_workload(torch, pn, work, inst, args, steps, warmup, tile):
     it_b = [i["iters"] for i in binfo]
     lens = np.diff(inst.offsets)
     kernels = {}
-    for name, its in (("gru_quasi_local", it_f), ("gru_adj_local", it_b)):
+    adj_kernels = ("gru_adj_dmap", "gru_adj_dchain") if dense else ("gru_adj_local",)
+    for name in ("gru_quasi_local",) + adj_kernels:
         tot, n = fam[name]
-        # every sequence is worked on by the launches of iterations 0 .. iters (the last one
-        # tests the final iterate): units = sequence-steps processed per launch, averaged
-        units = float(np.sum((np.asarray(its) + 1) * lens)) / max(n, 1)
+        if name == "gru_quasi_local" or name == "gru_adj_local":
+            # every sequence is worked on by the launches of iterations 0 .. iters (the last
+            # one tests the final iterate): units = sequence-steps per launch, averaged
+            its = it_f if name == "gru_quasi_local" else it_b
+            units = float(np.sum((np.asarray(its) + 1) * lens)) / max(n, 1)
+        else:
+            units = float(N)           # each dense-adjoint launch walks every step once
         avg = tot / max(n, 1)
         rl = roofline_of(name, D, Dx, units, avg)
-        idle_ms, idle_n = idle[name]
+        idle_ms, idle_n = idle.get(name, (0.0, 0))
         rl.update({"avg_launch_ms": round(avg, 4), "launches": n,
                    "units_per_launch": round(units, 1),
                    "avg_launch_ms_with_idle": round((tot + idle_ms) / max(n + idle_n, 1), 4),
@@ -250,7 +291,13 @@ def main():
                          "the workload's stated 1e-5, which keeps the gradients within 1e-5 of "
                          "the FP64 oracle")
     ap.add_argument("--freeze", action="store_true",
-                    help="converged-prefix skipping in both passes")
+                    help="converged-prefix skipping in the forward (and in the adjoint with "
+                         "--adjoint diag)")
+    ap.add_argument("--adjoint", choices=("dense", "diag"), default="dense",
+                    help="'dense': the adjoint as one reverse dense scan (exact A_t^T inside "
+                         "groups of steps, per-group maps composed in BF16 on MFMA, carries "
+                         "refined by the exact residual); 'diag': iterated reverse diagonal "
+                         "scans with the exact VJP residual")
     ap.add_argument("--seq-reps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-secondary", action="store_true",
@@ -330,7 +377,10 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD, "cell": "gru", "D": work.D, "Dx": work.Dx,
                    "B": work.B, "T": f"U{{{work.t_min}..{work.t_max}}}", "N": inst.N,
-                   "method": "quasi-DEER fwd + exact quasi adjoint",
+                   "method": ("quasi-DEER fwd + exact adjoint as one reverse dense scan "
+                              "(BF16-composed group maps, FP32 chains)"
+                              if args.adjoint == "dense" else
+                              "quasi-DEER fwd + exact adjoint by iterated diagonal scans"),
                    "tol": args.tol, "adj_tol": args.adj_tol, "loss": "sum_t ||s_t||^2",
                    "graph_iters": GRAPH_ITERS, "path": "hipGraph-captured iterations",
                    "freeze_prefix": args.freeze},

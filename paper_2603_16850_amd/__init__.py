@@ -489,10 +489,10 @@ class DeerFunction:
 
             class _Fn(torch.autograd.Function):
                 @staticmethod
-                def forward(ctx, x, s0, params, cell, offsets, opt_kw):
+                def forward(ctx, x, s0, params, cell, offsets, opt_kw, adj_kw):
                     s, info = deer_solve(x, s0, params, cell=cell, offsets=offsets, **opt_kw)
                     ctx.save_for_backward(x, s0, params, s)
-                    ctx.cell, ctx.offsets, ctx.opt_kw = cell, offsets, opt_kw
+                    ctx.cell, ctx.offsets, ctx.adj_kw = cell, offsets, adj_kw
                     ctx.info = info
                     return s
 
@@ -501,13 +501,16 @@ class DeerFunction:
                     x, s0, params, s = ctx.saved_tensors
                     gp, gx, g0, _ = deer_adjoint(x, s0, params, s, gs.contiguous(),
                                                  cell=ctx.cell, offsets=ctx.offsets,
-                                                 **ctx.opt_kw)
-                    return gx, g0, gp, None, None, None
+                                                 **ctx.adj_kw)
+                    return gx, g0, gp, None, None, None, None
 
             cls._cls = _Fn
         return cls._cls
 
 
-def deer(x, s0, params, cell="gru", offsets=None, **opt_kw):
-    """Differentiable parallel-Newton evaluation of the recurrence (returns s [N, D])."""
-    return DeerFunction.get().apply(x, s0, params, cell, offsets, opt_kw)
+def deer(x, s0, params, cell="gru", offsets=None, adjoint=None, **opt_kw):
+    """Differentiable parallel-Newton evaluation of the recurrence (returns s [N, D]).
+    The backward pass calls deer_adjoint with the same options, updated by the dict
+    `adjoint` (e.g. dict(jac="dense", compose="bf16") for the GRU's dense reverse scan)."""
+    adj_kw = dict(opt_kw, **(adjoint or {}))
+    return DeerFunction.get().apply(x, s0, params, cell, offsets, opt_kw, adj_kw)

@@ -148,7 +148,7 @@ pn_status check_ws(void* ws, size_t have, size_t need) {
 }
 
 // Which solver serves a deer_solve call.
-enum class Route { None, GruQuasi, GruDense64, TanhDense, Elk, Affine };
+enum class Route { None, GruQuasi, GruDenseAdj, GruDense64, TanhDense, Elk, Affine };
 
 bool affine_cell(int cell) { return cell == PN_CELL_AFFINE || cell == PN_CELL_AFFINE_STEPS; }
 
@@ -188,6 +188,9 @@ Route route_adjoint(const pn_cell_desc& c, const pn_opts& o) {
     if (c.dtype != PN_F32) return Route::None;
     if (c.cell == PN_CELL_GRU && o.jac == PN_JAC_DIAG && gru_quasi_supported(c.D, c.Dx))
         return Route::GruQuasi;
+    if (c.cell == PN_CELL_GRU && o.jac == PN_JAC_DENSE && o.damping == PN_DAMP_NONE &&
+        gru_quasi_supported(c.D, c.Dx))
+        return Route::GruDenseAdj;
     if (c.cell == PN_CELL_TANH && o.jac == PN_JAC_DENSE && o.damping == PN_DAMP_NONE &&
         tanh_dense_supported(c.D, c.Dx))
         return Route::TanhDense;
@@ -277,7 +280,8 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
             break;
         case PN_OP_ADJOINT:
             switch (route_adjoint(*cell, o)) {
-                case Route::GruQuasi: *bytes = gru_adjoint_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
+                case Route::GruQuasi:
+                case Route::GruDenseAdj: *bytes = gru_adjoint_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 case Route::TanhDense: *bytes = tanh_adjoint_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 default: break;
             }
@@ -473,7 +477,7 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
                             cell->dtype, (int*)((char*)workspace + need - kCheckBytes),
                             (hipStream_t)stream));
     bool conv = true;
-    if (r == Route::GruQuasi)
+    if (r == Route::GruQuasi || r == Route::GruDenseAdj)
         PN_TRY(gru_adjoint(*cell, hb, (const float*)x, (const float*)s0, (const float*)s,
                            (const float*)gs, (float*)gx, (float*)gs0, (float*)gparams, o,
                            workspace, (hipStream_t)stream, info, &conv));

@@ -889,6 +889,7 @@ struct GruALayout {
     float *gates, *eps, *lam, *mu[2], *gprod, *gmax, *part, *gcarry;
     uint32_t *cmax, *grmax;
     float2* gagg;
+    void* dense;             // the dense scan's maps and carries (PN_JAC_DENSE only)
     size_t bytes;
 };
 
@@ -902,17 +903,21 @@ static int grad_grid() { return 2 * cu_count(); }
 static int prep_grid() { return 8 * cu_count(); }
 
 static GruALayout gruA_layout(void* ws, int D, int Dx, const HostBatch& hb, int ntiles,
-                              int ngroups, bool freeze = false) {
+                              int ngroups, bool freeze = false, bool dense = false) {
     Carver c(ws);
-    GruALayout lay;
+    GruALayout lay{};
     carve_iter_state(c, lay.st, hb.B, ntiles, ngroups);
     lay.gates = c.take<float>((size_t)hb.N * 4 * D);
     lay.eps = c.take<float>((size_t)hb.N * D);
     lay.lam = c.take<float>((size_t)hb.N * D);
-    for (int p = 0; p < 2; ++p) lay.mu[p] = c.take<float>((size_t)hb.N * D);
-    lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
-    lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
-    lay.gprod = c.take<float>((size_t)std::max(ngroups, 1) * D);
+    if (dense) {
+        lay.dense = c.take<char>(gru_adj_dense_bytes(D, ngroups, hb.B));
+    } else {
+        for (int p = 0; p < 2; ++p) lay.mu[p] = c.take<float>((size_t)hb.N * D);
+        lay.gagg = c.take<float2>((size_t)std::max(ngroups, 1) * D);
+        lay.gcarry = c.take<float>((size_t)std::max(ngroups, 1) * D);
+        lay.gprod = c.take<float>((size_t)std::max(ngroups, 1) * D);
+    }
     lay.gmax = c.take<float>(hb.B);
     lay.cmax = c.take<uint32_t>((size_t)std::max(ntiles, 1) * (D / 16));
     const size_t P = 3 * (size_t)D * Dx + 3 * (size_t)D * D + 4 * (size_t)D;
@@ -951,22 +956,35 @@ static bool gruA_lookup(int D, int Dx, GruAKernels* k) {
     return false;
 }
 
-// Tile groups of the adjoint iteration for this batch.
+// Tile groups of the adjoint iteration for this batch.  The dense scan walks each group's
+// steps one after the other (16 groups side by side per wave, one group per wave for the maps):
+// about 32 K groups fill the device, so its default group is N / 2^20 tiles (at least one).
 static int gruA_groups(const GruAKernels& kk, const std::vector<int32_t>& ts, int B, int group,
-                       int* gt, int* resident) {
+                       int* gt, int* resident, bool dense = false, int64_t N = 0) {
     *resident = gru_resident((const void*)kk.iter, kk.nt);
-    *gt = group > 0 ? group : gru_group_tiles(ts[B], *resident);
+    if (group > 0)
+        *gt = group;
+    else if (dense)
+        *gt = (int)std::min<int64_t>(64, std::max<int64_t>(1, (N + (1 << 19)) >> 20));
+    else
+        *gt = gru_group_tiles(ts[B], *resident);
     return count_groups(ts, B, *gt);
 }
 
 size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o) {
     GruAKernels kk;
     if (!gruA_lookup(D, Dx, &kk)) return 0;
+    const bool dense = o.jac == PN_JAC_DENSE;
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     int gt, resident;
-    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident);
-    return gruA_layout(nullptr, D, Dx, hb, ts[hb.B], ngroups, o.freeze_prefix != 0).bytes;
+    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident, dense, hb.N);
+    return gruA_layout(nullptr, D, Dx, hb, ts[hb.B], ngroups, o.freeze_prefix != 0, dense).bytes;
 }
+
+static pn_status gru_adj_gradients(const GruAKernels& kk, const GruAdjArgs& args,
+                                   const HostBatch& hb, int D, int Dx, const GruALayout& lay,
+                                   hipStream_t stream, pn_seq_info* info, bool* all_conv,
+                                   float* gs0);
 
 pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
                       const float* s0, const float* s, const float* gs, float* gx, float* gs0,
@@ -978,12 +996,18 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
         set_error("GRU adjoint not built for D=%d Dx=%d", D, Dx);
         return PN_ERR_UNSUPPORTED;
     }
+    const bool dense = o.jac == PN_JAC_DENSE;
+    if (dense && (o.freeze_prefix || o.damping != PN_DAMP_NONE)) {
+        set_error("the dense GRU adjoint takes no damping and no converged-prefix skipping");
+        return PN_ERR_UNSUPPORTED;
+    }
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     const int ntiles = ts[hb.B];
     int gt, resident;
-    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident);
-    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, ngroups, o.freeze_prefix != 0);
-    const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
+    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident, dense, hb.N);
+    GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, ngroups, o.freeze_prefix != 0, dense);
+    const int max_iters = o.max_iters > 0 ? o.max_iters
+                                          : (dense ? 8 : (int)std::max<int64_t>(1, hb.Tmax));
     PN_TRY(init_iter_state(lay.st, hb, ts, kAdjL, true, max_iters, (float)o.tol,
                            (float)o.reset_abs, stream, gt));
 
@@ -1031,6 +1055,12 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     }
     hipLaunchKernelGGL(kk.gmax, dim3(hb.B), dim3(256), 0, stream, args);
     PN_HIP(hipGetLastError());
+    if (dense) {
+        PN_TRY(gru_adj_dense_solve(D, lay.gates, gs, (const float*)cd.params + 3 * D * Dx,
+                                   lay.lam, lay.st, ngroups, hb.B, lay.gmax, (float)o.tol,
+                                   o.compose == PN_COMPOSE_BF16, max_iters, lay.dense, stream));
+        return gru_adj_gradients(kk, args, hb, D, Dx, lay, stream, info, all_conv, gs0);
+    }
     const int grid = std::max(1, std::min(ngroups, resident));
     // iteration k (k from the control block) forms lambda^(k) from mu[k & 1] and the carries
     // of iteration k - 1, writes lambda^(k) and mu[(k + 1) & 1], then the carries
@@ -1051,16 +1081,24 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
                                   float_bits(args.clo), float_bits(args.chi)};
     PN_TRY(run_iterations(lay.st, max_iters + 1, o.graph_iters, o.use_graph != 0, key, one_iter,
                           stream));
+    return gru_adj_gradients(kk, args, hb, D, Dx, lay, stream, info, all_conv, gs0);
+}
+
+// Per-sequence results, then the gradients from the final adjoint iterate (the same tile
+// table, two passes per tile).
+static pn_status gru_adj_gradients(const GruAKernels& kk, const GruAdjArgs& args,
+                                   const HostBatch& hb, int D, int Dx, const GruALayout& lay,
+                                   hipStream_t stream, pn_seq_info* info, bool* all_conv,
+                                   float* gs0) {
     PN_TRY(finish_iterations(lay.st, hb, D, sizeof(float), nullptr, nullptr, stream, info,
                              all_conv));
-    // gradients from the final adjoint iterate (the same tile table, two passes per tile)
     const int gg = grad_grid();
     prof_launch("gru_adj_grad", stream, [&](hipStream_t s2) {
         hipLaunchKernelGGL(kk.grad, dim3(gg), dim3(kk.nt), 0, s2, args);
     });
     PN_HIP(hipGetLastError());
     const int P = 3 * D * Dx + 3 * D * D + 4 * D;
-    launch_partial_sum(lay.part, gg, P, gparams, stream);
+    launch_partial_sum(lay.part, gg, P, args.gparams, stream);
     PN_HIP(hipGetLastError());
     if (gs0) {
         hipLaunchKernelGGL(kk.gs0, dim3(hb.B), dim3(std::max(64, D)), 0, stream, args);

@@ -31,6 +31,16 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
                       float* gparams, const pn_opts& o, void* ws, hipStream_t stream,
                       pn_seq_info* info, bool* all_conv);
 
+// the same adjoint as one reverse dense scan (GRU, D in {16, 32, 48, 64}): chains of FP32
+// VJPs inside groups of consecutive steps, per-group maps composed on MFMA (BF16 or FP32),
+// carries refined by the exact residual.  Needs the gate rows from the adjoint's prep pass
+// and its group table (groups of the tiles from each sequence's end); fills seq[] and lam.
+size_t gru_adj_dense_bytes(int D, int ngroups, int B);
+pn_status gru_adj_dense_solve(int D, const float* gates, const float* gs, const float* U,
+                              float* lam, const IterState& st, int ngroups, int B,
+                              const float* gmax, float tol, bool bf16, int max_passes,
+                              void* dense_ws, hipStream_t stream);
+
 // DEER, GRU, FP64, small dense D (whole solve in one workgroup per sequence)
 bool gru_dense64_supported(int D, int Dx);
 size_t gru_dense64_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
