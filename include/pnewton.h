@@ -241,12 +241,19 @@ pn_status elk_solve(const pn_cell_desc* cell, const pn_batch* batch, const void*
      gs0 [B, D] = A_1^T lambda_1           (may be NULL).
    With PN_JAC_DIAG the reverse recurrence is solved by iterated reverse scans with
    diag(A_t) and an exact VJP residual (converges to the exact adjoint); with PN_JAC_DENSE
-   by reverse scans with the dense A_t^T = W^T diag(d_t) rebuilt on chip, composed in FP32
+   by reverse scans with the dense transposed Jacobians (the DEER backward pass of Ch. 3):
+   for the tanh-RNN A_t^T = W^T diag(d_t) rebuilt on chip, composed in FP32
    (PN_COMPOSE_NATIVE: one update reaches the adjoint) or BF16 (PN_COMPOSE_BF16: the exact
-   FP32 residual drives further updates).  Stopping rule of both: max |rho_t| <= tol *
-   max(1, max |g_t|) per sequence, rho_t = lambda_t - g_t - A_{t+1}^T lambda_{t+1}; info
-   reports the adjoint iterations.  Built: GRU, PN_JAC_DIAG, F32 (same shapes as
-   deer_solve); TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, no damping. */
+   FP32 residual drives further updates); for the GRU a two-level scan over groups of
+   consecutive steps (opts->group tiles of 32 steps each, 0 = about N / 2^20 tiles): the
+   exact recurrence inside every group in FP32, the groups' maps (products of A_t^T)
+   composed in BF16 or FP32 on MFMA, the carries between groups refined while the residual
+   at the group boundaries fails the test (each refinement one more update; max_iters <= 0
+   means 8).  Stopping rule of all: max |rho_t| <= tol * max(1, max |g_t|) per sequence,
+   rho_t = lambda_t - g_t - A_{t+1}^T lambda_{t+1}; info reports the adjoint updates.
+   Built: GRU, F32, PN_JAC_DIAG (same shapes as deer_solve) and PN_JAC_DENSE (D in
+   {16, 32, 48, 64}, no damping, no prefix skipping); TANH, PN_JAC_DENSE, F32, D = 32,
+   Dx in {16, 32}, no damping. */
 pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                        const void* s0, const void* s, const void* gs, void* gx, void* gs0,
                        void* gparams, const pn_opts* opts, void* workspace,
