@@ -79,7 +79,7 @@ PN_DEV void group_rows(const DenseAdjArgs& a, int gi, int64_t& row_hi, int& len,
 // product's output rows are then again the lane's own rows, and no transpose is needed
 // between steps.  The A operands (the transposed U blocks in that order) sit in LDS, one
 // float4 (four K steps) per lane and read.
-template <int D, bool FROM_CARRY>
+template <int D>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(D <= 48 ? 2 : 1)))
 gru_adj_chain_kernel(DenseAdjArgs a) {
@@ -105,7 +105,7 @@ gru_adj_chain_kernel(DenseAdjArgs a) {
     int len = 0, b = 0;
     if (gi < a.ngroups) {
         group_rows(a, gi, row_hi, len, b);
-        if (FROM_CARRY && a.done[b]) len = 0;
+        if (a.done[b]) len = 0;
     }
     int nsteps = len;
 #pragma unroll
@@ -115,7 +115,7 @@ gru_adj_chain_kernel(DenseAdjArgs a) {
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (FROM_CARRY && len > 0) v = *(const float4*)(a.wcar + (size_t)gi * D + 16 * bi + 4 * g);
+        if (len > 0) v = *(const float4*)(a.wcar + (size_t)gi * D + 16 * bi + 4 * g);
         x[bi][0] = v.x;
         x[bi][1] = v.y;
         x[bi][2] = v.z;
@@ -157,7 +157,7 @@ gru_adj_chain_kernel(DenseAdjArgs a) {
             const float wv = r == 0 ? q.x : (r == 1 ? q.y : (r == 2 ? q.z : q.w));
             bop[s] = wv * lm[kb][r];
         }
-        if (FROM_CARRY && act) {
+        if (act) {
             float* lp = a.lam + (size_t)(row_hi - st) * D + 4 * g;
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi)
@@ -185,7 +185,7 @@ gru_adj_chain_kernel(DenseAdjArgs a) {
         }
     }
     if (len > 0) {
-        float* op = (FROM_CARRY ? a.wout : a.vbuf) + (size_t)gi * D + 4 * g;
+        float* op = a.wout + (size_t)gi * D + 4 * g;
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi)
             *(float4*)(op + 16 * bi) = make_float4(x[bi][0], x[bi][1], x[bi][2], x[bi][3]);
@@ -207,6 +207,7 @@ gru_adj_mprod_kernel(DenseAdjArgs a) {
     constexpr int NB = D / 16, NKK = (NB + 1) / 2;
     constexpr bool UREG = D <= 32;                 // U entries in registers (else from LDS)
     __shared__ __attribute__((aligned(16))) float4 uj[UREG ? 1 : 3 * NB * NB * 64];
+    __shared__ __attribute__((aligned(16))) float vsh[4 * D];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
     auto uval = [&](int m, int bo, int kb) {      // U_m[4g + r + 16kb][c + 16bo], r = 0..3
         const int blk = m == 0 ? 0 : (m == 1 ? 2 : 1);
@@ -265,26 +266,59 @@ gru_adj_mprod_kernel(DenseAdjArgs a) {
         for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) M[bi][cb][r] = (bi == cb && 4 * g + r == c) ? 1.f : 0.f;
-    float4 ga[4][NB];
+    float4 ga[4][NB], gv[NB];
     auto fetch = [&](int st) {
         const float* gr = a.gates + (size_t)(row_hi - st) * 4 * D + 4 * g;
+        const float* gp = a.gs + (size_t)(row_hi - st) * D + 4 * g;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int kb = 0; kb < NB; ++kb) {
 #pragma unroll
-            for (int kb = 0; kb < NB; ++kb) ga[m][kb] = *(const float4*)(gr + m * D + 16 * kb);
+            for (int m = 0; m < 4; ++m) ga[m][kb] = *(const float4*)(gr + m * D + 16 * kb);
+            gv[kb] = *(const float4*)(gp + 16 * kb);
+        }
+    };
+    // The affine part v of the map rides along in FP32 on the VALU: w <- A_t^T (g_t + w), w
+    // held like M's rows (rows 4g + r + 16 kb); the U terms are the FP32 entries of J summed
+    // over the lane's k and then over the four lane groups, handed back to the row layout
+    // through LDS.
+    float wv[NB][4];
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wv[kb][r] = 0.f;
+    float* vs = vsh + w * D;
+    auto jrow = [&](int bo, float (&J)[NB][4]) {     // J[kb][r] = U terms of A_t^T[c + 16bo][k]
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) {
+            const float4 u0 = uget(0, bo, kb), u1 = uget(1, bo, kb), u2 = uget(2, bo, kb);
+            const float4 al = ga[0][kb], be = ga[1][kb], gm = ga[2][kb];
+            J[kb][0] = fmaf(u2.x, gm.x, fmaf(u1.x, be.x, u0.x * al.x));
+            J[kb][1] = fmaf(u2.y, gm.y, fmaf(u1.y, be.y, u0.y * al.y));
+            J[kb][2] = fmaf(u2.z, gm.z, fmaf(u1.z, be.z, u0.z * al.z));
+            J[kb][3] = fmaf(u2.w, gm.w, fmaf(u1.w, be.w, u0.w * al.w));
+        }
     };
     // Mo = A_t^T Mi.  The z_i M[i][.] term is the accumulator's start value (exact FP32, the
     // lane's own entries); the products carry the U terms only.
     auto step = [&](const floatx4 (&Mi)[NB][NB], floatx4 (&Mo)[NB][NB], int st) {
+        float lm[NB][4], zl[NB][4], p[NB];
 #pragma unroll
-        for (int bo = 0; bo < NB; ++bo) {
-            const float4 z = ga[3][bo];
+        for (int kb = 0; kb < NB; ++kb) {
+            const float4 z = ga[3][kb];
+            lm[kb][0] = gv[kb].x + wv[kb][0];
+            lm[kb][1] = gv[kb].y + wv[kb][1];
+            lm[kb][2] = gv[kb].z + wv[kb][2];
+            lm[kb][3] = gv[kb].w + wv[kb][3];
+            zl[kb][0] = z.x * lm[kb][0];
+            zl[kb][1] = z.y * lm[kb][1];
+            zl[kb][2] = z.z * lm[kb][2];
+            zl[kb][3] = z.w * lm[kb][3];
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) {
-                Mo[bo][cb][0] = z.x * Mi[bo][cb][0];
-                Mo[bo][cb][1] = z.y * Mi[bo][cb][1];
-                Mo[bo][cb][2] = z.z * Mi[bo][cb][2];
-                Mo[bo][cb][3] = z.w * Mi[bo][cb][3];
+                Mo[kb][cb][0] = z.x * Mi[kb][cb][0];
+                Mo[kb][cb][1] = z.y * Mi[kb][cb][1];
+                Mo[kb][cb][2] = z.z * Mi[kb][cb][2];
+                Mo[kb][cb][3] = z.w * Mi[kb][cb][3];
             }
         }
         if constexpr (BF16) {
@@ -303,15 +337,13 @@ gru_adj_mprod_kernel(DenseAdjArgs a) {
 #pragma unroll
             for (int bo = 0; bo < NB; ++bo) {
                 float J[NB][4];
+                jrow(bo, J);
+                float pp = 0.f;
 #pragma unroll
-                for (int kb = 0; kb < NB; ++kb) {
-                    const float4 u0 = uget(0, bo, kb), u1 = uget(1, bo, kb), u2 = uget(2, bo, kb);
-                    const float4 al = ga[0][kb], be = ga[1][kb], gm = ga[2][kb];
-                    J[kb][0] = fmaf(u2.x, gm.x, fmaf(u1.x, be.x, u0.x * al.x));
-                    J[kb][1] = fmaf(u2.y, gm.y, fmaf(u1.y, be.y, u0.y * al.y));
-                    J[kb][2] = fmaf(u2.z, gm.z, fmaf(u1.z, be.z, u0.z * al.z));
-                    J[kb][3] = fmaf(u2.w, gm.w, fmaf(u1.w, be.w, u0.w * al.w));
-                }
+                for (int kb = 0; kb < NB; ++kb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) pp = fmaf(J[kb][r], lm[kb][r], pp);
+                p[bo] = pp;
 #pragma unroll
                 for (int kk = 0; kk < NKK; ++kk)
 #pragma unroll
@@ -321,7 +353,7 @@ gru_adj_mprod_kernel(DenseAdjArgs a) {
                     }
                 asm volatile("" ::: "memory");
             }
-            fetch(min(st + 1, len - 1));        // branch-free (the last step re-reads)
+            fetch(min(st + 1, len - 1));             // in flight during the products
 #pragma unroll
             for (int kk = 0; kk < NKK; ++kk)
 #pragma unroll
@@ -334,15 +366,13 @@ gru_adj_mprod_kernel(DenseAdjArgs a) {
 #pragma unroll
             for (int bo = 0; bo < NB; ++bo) {
                 float J[NB][4];
+                jrow(bo, J);
+                float pp = 0.f;
 #pragma unroll
-                for (int kb = 0; kb < NB; ++kb) {
-                    const float4 u0 = uget(0, bo, kb), u1 = uget(1, bo, kb), u2 = uget(2, bo, kb);
-                    const float4 al = ga[0][kb], be = ga[1][kb], gm = ga[2][kb];
-                    J[kb][0] = fmaf(u2.x, gm.x, fmaf(u1.x, be.x, u0.x * al.x));
-                    J[kb][1] = fmaf(u2.y, gm.y, fmaf(u1.y, be.y, u0.y * al.y));
-                    J[kb][2] = fmaf(u2.z, gm.z, fmaf(u1.z, be.z, u0.z * al.z));
-                    J[kb][3] = fmaf(u2.w, gm.w, fmaf(u1.w, be.w, u0.w * al.w));
-                }
+                for (int kb = 0; kb < NB; ++kb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) pp = fmaf(J[kb][r], lm[kb][r], pp);
+                p[bo] = pp;
 #pragma unroll
                 for (int kb = 0; kb < NB; ++kb)
 #pragma unroll
@@ -352,16 +382,39 @@ gru_adj_mprod_kernel(DenseAdjArgs a) {
                             Mo[bo][cb] = mfma16x4(J[kb][r], Mi[kb][cb][r], Mo[bo][cb]);
                 asm volatile("" ::: "memory");
             }
-            fetch(min(st + 1, len - 1));        // branch-free (the last step re-reads)
+            fetch(min(st + 1, len - 1));
         }
+        // U terms of row c + 16 bo summed over the four lane groups, then to the row layout
+#pragma unroll
+        for (int bo = 0; bo < NB; ++bo) p[bo] = sum_halves(sum_rows16(p[bo]));
+        if (g == 0) {
+#pragma unroll
+            for (int bo = 0; bo < NB; ++bo) vs[c + 16 * bo] = p[bo];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) {
+            const float4 q = *(const float4*)(vs + 16 * kb + 4 * g);
+            wv[kb][0] = zl[kb][0] + q.x;
+            wv[kb][1] = zl[kb][1] + q.y;
+            wv[kb][2] = zl[kb][2] + q.z;
+            wv[kb][3] = zl[kb][3] + q.w;
+        }
+        __builtin_amdgcn_wave_barrier();
     };
     fetch(0);
-    for (int st = 0; st < len; ++st) {
+    for (int st = 0; st < len; ++st) {              // (the last step's prefetch re-reads)
         step(M, Mn, st);
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) M[bi][cb] = Mn[bi][cb];
+    }
+    if (c == 0) {
+        float* vp = a.vbuf + (size_t)gi * D + 4 * g;
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb)
+            *(float4*)(vp + 16 * kb) = make_float4(wv[kb][0], wv[kb][1], wv[kb][2], wv[kb][3]);
     }
     float* mp = a.mbuf + (size_t)gi * D * D;
 #pragma unroll
@@ -423,32 +476,37 @@ __global__ void __launch_bounds__(64) gru_adj_dcarry_kernel(DenseAdjArgs a, int 
         radd[j] = CHECK ? a.wout[(size_t)(g0 + q) * D + ii] - a.wcar[(size_t)(g0 + q + 1) * D + ii]
                         : a.vbuf[(size_t)(g0 + q) * D + ii];
     };
+    // every load unconditional (clamped to the last map) so that the waits the compiler
+    // places keep PF maps in flight
 #pragma unroll
-    for (int j = 0; j < PF; ++j)
-        if (j < nq) fetch(j, j);
+    for (int j = 0; j < PF; ++j) fetch(min(j, nq - 1), j);
     float u = 0.f;                                 // w_q (walk) or delta_q (check)
     for (int q0 = 0; q0 < nq; q0 += PF) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int q = q0 + j;
-            if (q >= nq) break;
             if (act) ush[i] = u;
             __builtin_amdgcn_wave_barrier();
-            float y0 = 0.f, y1 = 0.f;
+            float y[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // short dependent chains
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 const float4 uv = *(const float4*)(ush + 4 * k);
-                y0 = fmaf(ring[j][k].x, uv.x, y0);
-                y1 = fmaf(ring[j][k].y, uv.y, y1);
-                y0 = fmaf(ring[j][k].z, uv.z, y0);
-                y1 = fmaf(ring[j][k].w, uv.w, y1);
+                const int h = 4 * (k & 1);
+                y[h + 0] = fmaf(ring[j][k].x, uv.x, y[h + 0]);
+                y[h + 1] = fmaf(ring[j][k].y, uv.y, y[h + 1]);
+                y[h + 2] = fmaf(ring[j][k].z, uv.z, y[h + 2]);
+                y[h + 3] = fmaf(ring[j][k].w, uv.w, y[h + 3]);
             }
             __builtin_amdgcn_wave_barrier();
-            u = y0 + y1 + radd[j];
-            float* wn = a.wcar + (size_t)(g0 + q + 1) * D + ii;
-            // check: wcar_{q+1} was read into radd before this write (only step q writes it)
-            if (act) *wn = CHECK ? *wn + u : u;
-            if (q + PF < nq) fetch(q + PF, j);
+            const float un = ((y[0] + y[4]) + (y[1] + y[5])) + ((y[2] + y[6]) + (y[3] + y[7])) +
+                             radd[j];
+            if (q < nq) {
+                u = un;
+                float* wn = a.wcar + (size_t)(g0 + q + 1) * D + ii;
+                // check: wcar_{q+1} was read into radd before this write (only step q writes it)
+                if (act) *wn = CHECK ? *wn + u : u;
+            }
+            fetch(min(q + PF, nq - 1), j);
         }
     }
 }
@@ -456,17 +514,12 @@ __global__ void __launch_bounds__(64) gru_adj_dcarry_kernel(DenseAdjArgs a, int 
 template <int D>
 pn_status dense_adj_run(const DenseAdjArgs& a, int B, bool bf16, int max_passes,
                         hipStream_t stream, int* passes) {
-    void (*chain0)(DenseAdjArgs) = gru_adj_chain_kernel<D, false>;
-    void (*chain1)(DenseAdjArgs) = gru_adj_chain_kernel<D, true>;
+    void (*chain)(DenseAdjArgs) = gru_adj_chain_kernel<D>;
     void (*mprod)(DenseAdjArgs) = bf16 ? gru_adj_mprod_kernel<D, true> : gru_adj_mprod_kernel<D, false>;
     void (*walk)(DenseAdjArgs, int, int) = gru_adj_dcarry_kernel<D, false>;
     void (*check)(DenseAdjArgs, int, int) = gru_adj_dcarry_kernel<D, true>;
     const int cgrid = std::max(1, (a.ngroups + 63) / 64);    // 4 waves x 16 groups
     const int mgrid = std::max(1, (a.ngroups + 3) / 4);      // 4 waves x 1 group
-    prof_launch("gru_adj_dchain", stream, [&](hipStream_t s2) {
-        hipLaunchKernelGGL(chain0, dim3(cgrid), dim3(256), 0, s2, a);
-    });
-    PN_HIP(hipGetLastError());
     prof_launch("gru_adj_dmap", stream, [&](hipStream_t s2) {
         hipLaunchKernelGGL(mprod, dim3(mgrid), dim3(256), 0, s2, a);
     });
@@ -479,7 +532,7 @@ pn_status dense_adj_run(const DenseAdjArgs& a, int B, bool bf16, int max_passes,
     *passes = 0;
     for (int p = 1; p <= max_passes; ++p) {
         prof_launch("gru_adj_dchain", stream, [&](hipStream_t s2) {
-            hipLaunchKernelGGL(chain1, dim3(cgrid), dim3(256), 0, s2, a);
+            hipLaunchKernelGGL(chain, dim3(cgrid), dim3(256), 0, s2, a);
         });
         PN_HIP(hipGetLastError());
         PN_HIP(hipMemsetAsync(a.nopen, 0, sizeof(int), stream));

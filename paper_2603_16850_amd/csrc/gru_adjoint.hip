@@ -20,6 +20,7 @@
 // with the carry pass over the group maps, grad (per-workgroup partial parameter gradients
 // on MFMA, dx), reduce, gs0.
 #include <algorithm>
+#include <cmath>
 
 #include "carry.hpp"
 #include "gru_common.hpp"
@@ -956,16 +957,36 @@ static bool gruA_lookup(int D, int Dx, GruAKernels* k) {
     return false;
 }
 
-// Tile groups of the adjoint iteration for this batch.  The dense scan walks each group's
-// steps one after the other (16 groups side by side per wave, one group per wave for the maps):
-// about 32 K groups fill the device, so its default group is N / 2^20 tiles (at least one).
+// Tile groups of the adjoint iteration for this batch.
+//
+// The dense scan's default group length balances its two sequential parts (measured on the
+// device): the chain pass walks 16 groups per wave and streams at a flat rate while every
+// SIMD holds as many of its waves as fit (two at D <= 48, one at D = 64: 32 K or 16 K
+// groups), slowing about as the square root of the shortfall below; the carry walk takes
+// about 0.5 us per group of the longest sequence.
+static int dense_group_tiles(const std::vector<int32_t>& ts, int B, int D, int64_t N) {
+    int tmax = 0;
+    for (int b = 0; b < B; ++b) tmax = std::max(tmax, ts[b + 1] - ts[b]);
+    const double chain_ms = (double)N * 24.0 * D / 3.8e9;       // bytes / (3.8 TB/s), in ms
+    const double full = D <= 48 ? 32768.0 : 16384.0;
+    int best = 1;
+    double best_ms = 1e30;
+    for (int gt = 1; gt <= 64; gt *= 2) {
+        const int ng = count_groups(ts, B, gt);
+        const double ms = chain_ms * std::sqrt(std::max(1.0, full / std::max(ng, 1))) +
+                          0.5e-3 * ((tmax + gt - 1) / gt);
+        if (ms < best_ms) best_ms = ms, best = gt;
+    }
+    return best;
+}
+
 static int gruA_groups(const GruAKernels& kk, const std::vector<int32_t>& ts, int B, int group,
-                       int* gt, int* resident, bool dense = false, int64_t N = 0) {
+                       int* gt, int* resident, bool dense = false, int64_t N = 0, int D = 0) {
     *resident = gru_resident((const void*)kk.iter, kk.nt);
     if (group > 0)
         *gt = group;
     else if (dense)
-        *gt = (int)std::min<int64_t>(64, std::max<int64_t>(1, (N + (1 << 19)) >> 20));
+        *gt = dense_group_tiles(ts, B, D, N);
     else
         *gt = gru_group_tiles(ts[B], *resident);
     return count_groups(ts, B, *gt);
@@ -977,7 +998,7 @@ size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& 
     const bool dense = o.jac == PN_JAC_DENSE;
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     int gt, resident;
-    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident, dense, hb.N);
+    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident, dense, hb.N, D);
     return gruA_layout(nullptr, D, Dx, hb, ts[hb.B], ngroups, o.freeze_prefix != 0, dense).bytes;
 }
 
@@ -1004,7 +1025,7 @@ pn_status gru_adjoint(const pn_cell_desc& cd, const HostBatch& hb, const float* 
     const std::vector<int32_t> ts = tile_starts(hb, kAdjL);
     const int ntiles = ts[hb.B];
     int gt, resident;
-    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident, dense, hb.N);
+    const int ngroups = gruA_groups(kk, ts, hb.B, o.group, &gt, &resident, dense, hb.N, D);
     GruALayout lay = gruA_layout(ws, D, Dx, hb, ntiles, ngroups, o.freeze_prefix != 0, dense);
     const int max_iters = o.max_iters > 0 ? o.max_iters
                                           : (dense ? 8 : (int)std::max<int64_t>(1, hb.Tmax));
