@@ -78,15 +78,15 @@ def dmap_flops(D):
 
 
 def dmap_bytes(D):
-    """Algorithmic HBM bytes per step of the map pass: the step's gate row (16 D); the maps
-    themselves are written once per group."""
-    return 16 * D
+    """Algorithmic HBM bytes per step of the map pass: the step's gate row (16 D) and g (4 D,
+    for the group's affine part); the maps themselves are written once per group."""
+    return 20 * D
 
 
 def dchain_bytes(D):
-    """Algorithmic HBM bytes per step of a dense-adjoint chain pass, averaged over its two
-    launches: the gate row and g (20 D) read by both, lambda (4 D) written by the second."""
-    return 22 * D
+    """Algorithmic HBM bytes per step of the dense adjoint's chain pass: the gate row and g
+    (20 D) read, lambda (4 D) written."""
+    return 24 * D
 
 
 TRAFFIC_FILES = {WORKLOAD: os.path.join(ROOT, "profiles", "gru48_ragged_hbm_traffic.txt"),

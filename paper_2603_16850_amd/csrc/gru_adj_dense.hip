@@ -38,7 +38,6 @@ namespace pn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-namespace {
 
 struct DenseAdjArgs {
     const float* gates;        // [N][4][D]: alpha, beta, gamma, z
@@ -61,7 +60,7 @@ struct DenseAdjArgs {
 };
 
 // rows [row_lo, row_hi] of group slot gi
-PN_DEV void group_rows(const DenseAdjArgs& a, int gi, int64_t& row_hi, int& len, int& b) {
+PN_DEV void dense_group_rows(const DenseAdjArgs& a, int gi, int64_t& row_hi, int& len, int& b) {
     const GroupInfo gr = a.groups[gi];
     const TileInfo t0 = a.tiles[gr.tile0];                  // latest tile of the group
     const TileInfo t1 = a.tiles[gr.tile0 + gr.ntl - 1];     // earliest
@@ -82,7 +81,7 @@ PN_DEV void group_rows(const DenseAdjArgs& a, int gi, int64_t& row_hi, int& len,
 template <int D>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(D <= 48 ? 2 : 1)))
-gru_adj_chain_kernel(DenseAdjArgs a) {
+gru_adj_dchain_kernel(DenseAdjArgs a) {
     constexpr int NB = D / 16, KQ = D / 4, NS = 3 * KQ, NQ = NS / 4;
     static_assert(D % 16 == 0, "D multiple of 16");
     __shared__ __attribute__((aligned(16))) float4 ua[NB * NQ * 64];
@@ -104,7 +103,7 @@ gru_adj_chain_kernel(DenseAdjArgs a) {
     int64_t row_hi = 0;
     int len = 0, b = 0;
     if (gi < a.ngroups) {
-        group_rows(a, gi, row_hi, len, b);
+        dense_group_rows(a, gi, row_hi, len, b);
         if (a.done[b]) len = 0;
     }
     int nsteps = len;
@@ -203,7 +202,7 @@ gru_adj_chain_kernel(DenseAdjArgs a) {
 template <int D, bool BF16>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(D <= 48 ? 2 : 1)))
-gru_adj_mprod_kernel(DenseAdjArgs a) {
+gru_adj_dmap_kernel(DenseAdjArgs a) {
     constexpr int NB = D / 16, NKK = (NB + 1) / 2;
     constexpr bool UREG = D <= 32;                 // U entries in registers (else from LDS)
     __shared__ __attribute__((aligned(16))) float4 uj[UREG ? 1 : 3 * NB * NB * 64];
@@ -258,7 +257,7 @@ gru_adj_mprod_kernel(DenseAdjArgs a) {
     if (gi >= a.ngroups) return;
     int64_t row_hi;
     int len, b;
-    group_rows(a, gi, row_hi, len, b);
+    dense_group_rows(a, gi, row_hi, len, b);
     floatx4 M[NB][NB], Mn[NB][NB];
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
@@ -512,10 +511,10 @@ __global__ void __launch_bounds__(64) gru_adj_dcarry_kernel(DenseAdjArgs a, int 
 }
 
 template <int D>
-pn_status dense_adj_run(const DenseAdjArgs& a, int B, bool bf16, int max_passes,
+static pn_status dense_adj_run(const DenseAdjArgs& a, int B, bool bf16, int max_passes,
                         hipStream_t stream, int* passes) {
-    void (*chain)(DenseAdjArgs) = gru_adj_chain_kernel<D>;
-    void (*mprod)(DenseAdjArgs) = bf16 ? gru_adj_mprod_kernel<D, true> : gru_adj_mprod_kernel<D, false>;
+    void (*chain)(DenseAdjArgs) = gru_adj_dchain_kernel<D>;
+    void (*mprod)(DenseAdjArgs) = bf16 ? gru_adj_dmap_kernel<D, true> : gru_adj_dmap_kernel<D, false>;
     void (*walk)(DenseAdjArgs, int, int) = gru_adj_dcarry_kernel<D, false>;
     void (*check)(DenseAdjArgs, int, int) = gru_adj_dcarry_kernel<D, true>;
     const int cgrid = std::max(1, (a.ngroups + 63) / 64);    // 4 waves x 16 groups
@@ -548,8 +547,6 @@ pn_status dense_adj_run(const DenseAdjArgs& a, int B, bool bf16, int max_passes,
     }
     return PN_OK;
 }
-
-}  // namespace
 
 size_t gru_adj_dense_bytes(int D, int ngroups, int B) {
     Carver c(nullptr);
