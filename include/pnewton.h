@@ -300,7 +300,9 @@ pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const
    (launches of iterations after the one that stopped the last sequence return at once; they
    are counted under the family name followed by "#idle"):
      deer_solve GRU diagonal: "gru_quasi_local", "carry_scan";
-     deer_adjoint GRU: "gru_adj_prep", "gru_adj_local", "carry_scan", "gru_adj_grad";
+     deer_adjoint GRU: "gru_adj_prep", "gru_adj_grad", and with PN_JAC_DIAG
+       "gru_adj_local", "carry_scan", with PN_JAC_DENSE "gru_adj_dmap", "gru_adj_dwalk",
+       "gru_adj_dchain", "gru_adj_dcheck";
      deer_solve tanh dense: "tanh_dense_local", "dense_carry";
      deer_adjoint tanh dense: "tanh_adj_prep", "tanh_adj_local", "dense_carry", "tanh_adj_grad";
      deer_solve GRU FP64: "gru_dense64_solve";

@@ -234,6 +234,8 @@ def test_profile_family_names(lib):
     with lib.profile():
         s, _ = lib.deer_solve(x, s0, p, cell="gru", offsets=inst.offsets, tol=1e-6)
         lib.deer_adjoint(x, s0, p, s, 2 * s, cell="gru", offsets=inst.offsets)
+        lib.deer_adjoint(x, s0, p, s, 2 * s, cell="gru", offsets=inst.offsets, jac="dense",
+                         compose="bf16")
         st, _ = lib.deer_solve(xt, s0t, pt, cell="tanh", offsets=it.offsets, jac="dense",
                                tol=1e-6)
         lib.deer_adjoint(xt, s0t, pt, st, 2 * st, cell="tanh", offsets=it.offsets, jac="dense")
@@ -242,7 +244,8 @@ def test_profile_family_names(lib):
         lib.seq_rollout(x, s0, p, cell="gru", offsets=inst.offsets)
         lib.seq_bptt(x, s0, p, s, 2 * s, cell="gru", offsets=inst.offsets)
         names = ["gru_quasi_local", "carry_scan", "gru_adj_prep", "gru_adj_local",
-                 "gru_adj_grad", "tanh_dense_local", "dense_carry", "tanh_adj_prep",
+                 "gru_adj_grad", "gru_adj_dmap", "gru_adj_dwalk", "gru_adj_dchain",
+                 "gru_adj_dcheck", "tanh_dense_local", "dense_carry", "tanh_adj_prep",
                  "tanh_adj_local", "tanh_adj_grad", "elk_local", "elk_carry", "elk_smooth",
                  "elk_back_carry", "elk_back_apply", "affine_local", "affine_carry",
                  "seq_rollout", "seq_adj"]
