@@ -223,59 +223,84 @@ void* pinned_staging(int which, size_t bytes) {
 }
 }  // namespace
 
+// Tile and group tables from the offsets, one thread per tile (and per group): the same
+// geometry the host used to build (a host loop over a large ragged batch's 10^5 tiles cost
+// about 2 ms per call while the device waited, plus a 4 MB upload).  Sequence b of slot i is
+// the last b with tile_start[b] <= i (empty sequences own no slot).
+__global__ void build_tables_kernel(const int64_t* __restrict__ offsets,
+                                    const int32_t* __restrict__ tstart,
+                                    const int32_t* __restrict__ gstart, int B, int L, int reverse,
+                                    int g, int ntiles, int ngroups, TileInfo* __restrict__ tiles,
+                                    GroupInfo* __restrict__ groups) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    auto owner = [&](const int32_t* start, int v) {
+        int lo = 0, hi = B - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    if (i < ntiles) {
+        const int b = owner(tstart, i);
+        const int nt = tstart[b + 1] - tstart[b], k = i - tstart[b];
+        const int lt = reverse ? nt - 1 - k : k;                     // tile index in time
+        TileInfo ti;
+        ti.slot = i;
+        ti.b = b;
+        ti.len = (int)min((int64_t)L, offsets[b + 1] - offsets[b] - (int64_t)lt * L);
+        ti.flags = (k == 0 ? kTileScanFirst : 0) | (lt == 0 ? kTileTimeFirst : 0);
+        ti.row0 = offsets[b] + (int64_t)lt * L;
+        ti.gslot = gstart[b] + k / g;
+        ti.hgslot = k > 0 ? gstart[b] + (k - 1) / g : -1;
+        tiles[i] = ti;
+    }
+    if (groups && i < ngroups) {
+        const int b = owner(gstart, i);
+        const int nt = tstart[b + 1] - tstart[b], j = i - gstart[b];
+        groups[i] = GroupInfo{b, tstart[b] + j * g, min(g, nt - j * g), gstart[b]};
+    }
+}
+
 pn_status init_iter_state(const IterState& st, const HostBatch& hb,
                           const std::vector<int32_t>& tstart, int L, bool reverse,
                           int max_iters, float tol, float reset_abs, hipStream_t stream,
                           int gt, int stop) {
-    // the tables are built on the host and sent in one copy of the span they occupy in the
-    // workspace (offsets, tile_start, tiles, groups, group_start, carved in this order)
-    static thread_local std::vector<TileInfo> tiles;
-    static thread_local std::vector<GroupInfo> groups;
+    // The host sends the offsets, the tile starts and the group starts (O(B) values); the
+    // tables themselves are built on the device.
     static thread_local std::vector<int32_t> gstart;
     const int ntiles = tstart[hb.B];
-    tiles.assign(ntiles, TileInfo{});
-    groups.clear();
     gstart.assign(hb.B + 1, 0);
     const int g = gt > 0 ? gt : 1;
-    for (int b = 0; b < hb.B; ++b) {
-        const int nt = tstart[b + 1] - tstart[b];
-        gstart[b + 1] = gstart[b] + (nt + g - 1) / g;
-        for (int k = 0; k < nt; ++k) {
-            TileInfo& ti = tiles[tstart[b] + k];
-            const int lt = reverse ? nt - 1 - k : k;      // tile index in time
-            ti.slot = tstart[b] + k;
-            ti.b = b;
-            ti.len = (int)std::min<int64_t>(L, hb.len(b) - (int64_t)lt * L);
-            ti.flags = (k == 0 ? kTileScanFirst : 0) | (lt == 0 ? kTileTimeFirst : 0);
-            ti.row0 = hb.offsets[b] + (int64_t)lt * L;
-            ti.gslot = gstart[b] + k / g;
-            ti.hgslot = k > 0 ? gstart[b] + (k - 1) / g : -1;
-        }
-        for (int k = 0; k < nt; k += g)
-            groups.push_back(GroupInfo{b, tstart[b] + k, std::min(g, nt - k), gstart[b]});
-    }
-    if (gt > 0 && (int)groups.size() != st.ngroups) {
-        set_error("internal: group table size %d, carved %d", (int)groups.size(), st.ngroups);
+    for (int b = 0; b < hb.B; ++b) gstart[b + 1] = gstart[b] + (tstart[b + 1] - tstart[b] + g - 1) / g;
+    const int ngroups = gt > 0 ? gstart[hb.B] : 0;
+    if (gt > 0 && ngroups != st.ngroups) {
+        set_error("internal: group table size %d, carved %d", ngroups, st.ngroups);
         return PN_ERR_INTERNAL;
     }
+    // offsets and tile_start are carved next to each other, group_start after the tables
     char* const d0 = (char*)st.offsets;
-    const size_t span = (size_t)((char*)(st.group_start + hb.B + 1) - d0);
-    char* h = (char*)pinned_staging(0, span);
+    const size_t head = (size_t)((char*)(st.tile_start + hb.B + 1) - d0);
+    const size_t gbytes = sizeof(int32_t) * (hb.B + 1);
+    char* h = (char*)pinned_staging(0, head + gbytes);
     if (!h) {
-        set_error("hipHostMalloc of %zu bytes for the tile tables failed", span);
+        set_error("hipHostMalloc of %zu bytes for the tile tables failed", head + gbytes);
         return PN_ERR_HIP;
     }
-    auto put = [&](void* dev, const void* src, size_t n) {
-        if (n) std::memcpy(h + ((char*)dev - d0), src, n);
-    };
-    put(st.offsets, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1));
-    put(st.tile_start, tstart.data(), sizeof(int32_t) * (hb.B + 1));
-    put(st.tiles, tiles.data(), sizeof(TileInfo) * tiles.size());
-    if (gt > 0) {
-        put(st.groups, groups.data(), sizeof(GroupInfo) * groups.size());
-        put(st.group_start, gstart.data(), sizeof(int32_t) * (hb.B + 1));
+    std::memcpy(h, hb.offsets.data(), sizeof(int64_t) * (hb.B + 1));
+    std::memcpy(h + ((char*)st.tile_start - d0), tstart.data(), sizeof(int32_t) * (hb.B + 1));
+    std::memcpy(h + head, gstart.data(), gbytes);
+    PN_HIP(hipMemcpyAsync(d0, h, head, hipMemcpyHostToDevice, stream));
+    PN_HIP(hipMemcpyAsync(st.group_start, h + head, gbytes, hipMemcpyHostToDevice, stream));
+    const int nthreads = std::max(ntiles, ngroups);
+    if (nthreads > 0) {
+        hipLaunchKernelGGL(build_tables_kernel, dim3((nthreads + 255) / 256), dim3(256), 0,
+                           stream, (const int64_t*)st.offsets, (const int32_t*)st.tile_start,
+                           (const int32_t*)st.group_start, hb.B, L, reverse ? 1 : 0, g, ntiles,
+                           ngroups, st.tiles, gt > 0 ? st.groups : nullptr);
+        PN_HIP(hipGetLastError());
     }
-    PN_HIP(hipMemcpyAsync(d0, h, span, hipMemcpyHostToDevice, stream));
     int blocks = std::min(64, (hb.B + 255) / 256);
     hipLaunchKernelGGL(init_state_kernel, dim3(std::max(1, blocks)), dim3(256), 0, stream,
                        st.ctrl, st.seq, st.offsets, hb.B, max_iters, tol, reset_abs,
