@@ -283,9 +283,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--tol", type=float, default=1e-6,
-                    help="residual stopping tolerance of the forward (1e-6 keeps the trajectory "
-                         "error under 1e-5)")
+    ap.add_argument("--tol", type=float, default=2e-6,
+                    help="residual stopping tolerance of the forward (measured on the headline "
+                         "batch: 2e-6 leaves trajectory errors of 2.9e-6, 3e-6 of 5.4e-6, the "
+                         "stated 1e-5 of 1.5e-5 against the 1e-5 bar)")
     ap.add_argument("--adj-tol", type=float, default=1e-5,
                     help="stopping tolerance of the adjoint (max |rho| <= tol max(1, max |g|)); "
                          "the workload's stated 1e-5, which keeps the gradients within 1e-5 of "
