@@ -175,16 +175,12 @@ def run_workload(torch, pn, work, inst, args, steps, warmup, tile):
         tf = pn.autotune("deer", x, s0, p, probe_iters=8, **kw)
         kw_f.update(tile=tf["tile"], group=tf["group"])
         tuned = {"fwd": {k: tf[k] for k in ("tile", "group", "ms_per_iter", "from_cache")}}
-        if dense:
-            # the dense reverse scan takes its group length from the batch size (about 32 K
-            # groups); nothing to tune per iteration
-            tuned["adj"] = {"group": "default"}
-        else:
-            s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
-            tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8, **kw_b)
-            tuned["adj"] = {k: tb[k] for k in ("group", "ms_per_iter", "from_cache")}
-            kw_b.update(group=tb["group"])
-            del s_tr
+        s_tr, _ = pn.deer_solve(x, s0, p, tile=tf["tile"], group=tf["group"], **kw)
+        # (the dense reverse scan's candidates are timed as whole adjoint calls)
+        tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=8, **kw_b)
+        tuned["adj"] = {k: tb[k] for k in ("group", "ms_per_iter", "from_cache")}
+        kw_b.update(group=tb["group"])
+        del s_tr
         torch.cuda.synchronize()
         tuned["tune_ms"] = round((time.perf_counter() - tt0) * 1e3, 1)
     elif tile != "default":

@@ -330,7 +330,10 @@ pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const
        copy), so it may hold the caller's initial guess;
      PN_OP_ADJOINT: {x, s0, s, gs, gx, gs0, gparams}; gx, gs0 may be NULL; the outputs
        gx, gs0, gparams hold unspecified values afterwards.
-   lambda: elk_solve's lambda (ignored otherwise).  probe_iters: 1..64 (<= 0: 3).
+   lambda: elk_solve's lambda (ignored otherwise).  probe_iters: 1..64 (<= 0: 3); each
+   candidate runs probe_iters iterations with the stopping test disabled, except for the GRU
+   adjoint with PN_JAC_DENSE (one map pass, then chain passes until its own test passes),
+   whose candidates are timed as whole calls at opts->tol (ms_per_iter: ms per call).
    workspace: at least pn_workspace_bytes(op | PN_OP_TUNE, ...) bytes (256-byte aligned).
    Errors: those of the solve call (a candidate that the route rejects is skipped);
    PN_ERR_HIP if timing fails. */

@@ -99,6 +99,32 @@ def test_adjoint_tuner_and_group_option(lib):
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max())
 
 
+def test_dense_adjoint_tuner_times_whole_calls(lib):
+    """The GRU dense adjoint's group candidates are timed as whole calls; the chosen group and
+    tile="auto" give the same gradients as an explicit call, every group the same up to
+    rounding."""
+    import torch
+    w, inst = _gru_inst()
+    x, s0, p = _t(inst.x), _t(inst.s0), _t(inst.params)
+    s, _ = lib.deer_solve(x, s0, p, cell="gru", offsets=inst.offsets, jac="diag", tol=1e-6)
+    gs = 2 * s
+    kw = dict(cell="gru", offsets=inst.offsets, jac="dense", compose="bf16", tol=1e-6)
+    lib.load().pn_autotune_reset()
+    t = lib.autotune("adjoint", x, s0, p, s=s, gs=gs, **kw)
+    assert [(a, b) for a, b, _ in t["candidates"]] == [(0, g) for g in (0, 1, 2, 4, 8, 16)]
+    assert all(m is not None and m > 0 for _, _, m in t["candidates"])
+    assert t["group"] in (0, 1, 2, 4, 8, 16)
+    ga = lib.deer_adjoint(x, s0, p, s, gs, tile="auto", **kw)
+    gb = lib.deer_adjoint(x, s0, p, s, gs, group=t["group"], **kw)
+    for a, b in zip(ga[:3], gb[:3]):
+        assert torch.equal(a, b)
+    g1 = lib.deer_adjoint(x, s0, p, s, gs, group=1, **kw)
+    g16 = lib.deer_adjoint(x, s0, p, s, gs, group=16, **kw)
+    for a, b in zip(g1[:3], g16[:3]):
+        a, b = a.cpu().double().numpy(), b.cpu().double().numpy()
+        assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max())
+
+
 def test_elk_tuner_and_cache_file(lib, tmp_path, monkeypatch):
     w = workloads.TANH16_ELK.scaled(B=3, T=0)
     inst = workloads.make_instance(w, seed=42, lengths=np.array([900, 50, 1500]))
