@@ -148,7 +148,7 @@ pn_status check_ws(void* ws, size_t have, size_t need) {
 }
 
 // Which solver serves a deer_solve call.
-enum class Route { None, GruQuasi, GruDenseAdj, GruDense64, TanhDense, Elk, Affine };
+enum class Route { None, GruQuasi, GruDenseAdj, GruDense64, TanhDense, MfDense, Elk, Affine };
 
 bool affine_cell(int cell) { return cell == PN_CELL_AFFINE || cell == PN_CELL_AFFINE_STEPS; }
 
@@ -179,6 +179,9 @@ Route route_deer(const pn_cell_desc& c, const pn_opts& o) {
     if (c.cell == PN_CELL_TANH && o.jac == PN_JAC_DENSE && c.dtype == PN_F32 &&
         o.damping != PN_DAMP_CLIP && tanh_dense_supported(c.D, c.Dx))
         return Route::TanhDense;
+    if (c.cell == PN_CELL_MEANFIELD && o.jac == PN_JAC_DENSE && c.dtype == PN_F32 &&
+        o.damping == PN_DAMP_NONE && mf_dense_supported(c.D, c.Dx))
+        return Route::MfDense;
     return Route::None;
 }
 
@@ -267,6 +270,7 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
                 case Route::GruQuasi: *bytes = gru_quasi_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 case Route::GruDense64: *bytes = gru_dense64_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 case Route::TanhDense: *bytes = tanh_dense_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
+                case Route::MfDense: *bytes = mf_dense_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 case Route::Affine: *bytes = affine_workspace(cell->D, cell->Dx, hb, o); return PN_OK;
                 default: break;
             }
@@ -368,6 +372,10 @@ pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void
         case Route::TanhDense:
             PN_TRY(tanh_dense_forward(*cell, hb, (const float*)x, (const float*)s0, (float*)s, o,
                                       workspace, st, info, &conv));
+            break;
+        case Route::MfDense:
+            PN_TRY(mf_dense_forward(*cell, hb, (const float*)x, (const float*)s0, (float*)s, o,
+                                    workspace, st, info, &conv));
             break;
         case Route::Affine:
             PN_TRY(affine_forward(*cell, hb, (const float*)x, (const float*)s0, (float*)s, o,

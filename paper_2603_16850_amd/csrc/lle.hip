@@ -86,7 +86,8 @@ __global__ void __launch_bounds__(64) lle_kernel(const float* __restrict__ x,
 }
 
 bool lle_supported(int cell, int D, int Dx) {
-    return (cell == PN_CELL_TANH || cell == PN_CELL_MEANFIELD) && D == LD && Dx == LD;
+    return ((cell == PN_CELL_TANH || cell == PN_CELL_MEANFIELD) && D == LD && Dx == LD) ||
+           (cell == PN_CELL_MEANFIELD && mf_dense_supported(D, Dx));
 }
 
 size_t lle_workspace(const HostBatch& hb) {
@@ -99,6 +100,7 @@ size_t lle_workspace(const HostBatch& hb) {
 pn_status lle_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x, const float* s0,
                   const float* s, const float* u0, void* ws, hipStream_t stream, double* lle) {
     if (hb.B == 0) return PN_OK;
+    if (cd.D != LD) return mf_lle_run(cd, hb, s0, s, u0, ws, stream, lle);
     Carver c(ws);
     int64_t* doff = c.take<int64_t>(hb.B + 1);
     double* out = c.take<double>(std::max(hb.B, 1));

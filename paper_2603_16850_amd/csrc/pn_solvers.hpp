@@ -66,6 +66,19 @@ pn_status tanh_seq_bptt(const pn_cell_desc& cd, const HostBatch& hb, const float
                         const float* s0, const float* s, const float* gs, float* gx, float* gs0,
                         float* gparams, void* ws, hipStream_t stream);
 
+// DEER for the mean-field cell at 16 < D <= 128 (two-level dense scan, FP32 residual, BF16 or
+// FP32 compose), its sequential rollout and LLE estimate
+bool mf_dense_supported(int D, int Dx);
+size_t mf_dense_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
+pn_status mf_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                           const float* s0, float* s, const pn_opts& o, void* ws,
+                           hipStream_t stream, pn_seq_info* info, bool* all_conv);
+size_t mf_seq_workspace(int D, const HostBatch& hb);
+pn_status mf_seq_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
+                     const float* s0, float* s, void* ws, hipStream_t stream);
+pn_status mf_lle_run(const pn_cell_desc& cd, const HostBatch& hb, const float* s0,
+                     const float* s, const float* u0, void* ws, hipStream_t stream, double* lle);
+
 // ELK, tanh-RNN, FP32
 bool elk_supported(int D, int Dx);
 size_t elk_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);

@@ -242,12 +242,14 @@ static bool seq_lookup(int cell, int D, int Dx, SeqKern* k) {
 
 bool seq_supported(int cell, int D, int Dx) {
     SeqKern k;
-    return seq_lookup(cell, D, Dx, &k);
+    return seq_lookup(cell, D, Dx, &k) || (cell == PN_CELL_MEANFIELD && mf_dense_supported(D, Dx));
 }
 
 size_t gru_adjoint_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o);
 
 size_t seq_workspace(int cell, int D, int Dx, const HostBatch& hb) {
+    SeqKern k;
+    if (cell == PN_CELL_MEANFIELD && !seq_lookup(cell, D, Dx, &k)) return mf_seq_workspace(D, hb);
     Carver c(nullptr);
     c.take<int64_t>(hb.B + 1);
     c.take<float>((size_t)hb.N * (cell == PN_CELL_GRU ? 3 * D : D));
@@ -263,7 +265,11 @@ size_t seq_workspace(int cell, int D, int Dx, const HostBatch& hb) {
 pn_status seq_rollout_run(const pn_cell_desc& cd, const HostBatch& hb, const float* x,
                           const float* s0, float* s, void* ws, hipStream_t stream) {
     SeqKern k;
-    if (!seq_lookup(cd.cell, cd.D, cd.Dx, &k)) return PN_ERR_UNSUPPORTED;
+    if (!seq_lookup(cd.cell, cd.D, cd.Dx, &k)) {
+        if (cd.cell == PN_CELL_MEANFIELD && mf_dense_supported(cd.D, cd.Dx))
+            return mf_seq_run(cd, hb, x, s0, s, ws, stream);
+        return PN_ERR_UNSUPPORTED;
+    }
     if (hb.N == 0) return PN_OK;
     const int D = cd.D, Dx = cd.Dx;
     Carver c(ws);

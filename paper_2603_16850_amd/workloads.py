@@ -75,6 +75,9 @@ CHAOTIC_SEED = 9
 # (the length the thesis highlights), the gain g swept per run.
 MEANFIELD16 = Workload("meanfield16-lle-sweep", "meanfield", D=16, Dx=16, B=1, T=1000,
                        gain=1.0, method="deer", jac="dense", tol=1e-5)
+# The same family at the thesis's state size D = 100 (one sequence per seed).
+MEANFIELD100 = Workload("meanfield100-lle-sweep", "meanfield", D=100, Dx=100, B=1, T=1000,
+                        gain=1.0, method="deer", jac="dense", tol=1e-5)
 
 ALL = {w.name: w for w in (GRU4_DENSE_F64, GRU64_QUASI, TANH32_DENSE_BF16, TANH16_ELK,
                            GRU48_RAGGED)}
