@@ -310,6 +310,9 @@ def main():
                     help="instead of the step: the mean-field RNN LLE-threshold sweep (one "
                          "JSON line per gain and length)")
     ap.add_argument("--sweep-seeds", type=int, default=3)
+    ap.add_argument("--sweep-dim", type=int, choices=(16, 100), default=16,
+                    help="state size of the mean-field sweep: 16 (ELK-kernel DEER) or the "
+                         "thesis's 100 (the two-level dense scan, FP32 and BF16 maps)")
     ap.add_argument("--tile", default="auto",
                     help="'auto': the forward and adjoint tile / group lengths chosen by the "
                          "library's autotuner before the warmup (reported, not timed); "
@@ -330,7 +333,7 @@ def main():
     if args.sweep_lle:
         import torch
         import paper_2603_16850_amd as pn
-        sweep_lle(torch, pn, workloads, args.sweep_seeds)
+        sweep_lle(torch, pn, workloads, args.sweep_seeds, args.sweep_dim)
         return
     work = workloads.ALL[WORKLOAD]
     inst = workloads.make_instance(work, seed=0)
@@ -427,7 +430,7 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def sweep_lle(torch, pn, workloads, seeds):
+def sweep_lle(torch, pn, workloads, seeds, dim=16):
     """The LLE-threshold experiment of Ch. 5 on the mean-field RNN (D = 16): for every gain g
     and length T, each seed draws its own W; the sequential GPU rollout gives the trajectory,
     the LLE is estimated along it on the GPU from three random unit vectors (averaged), and
@@ -438,30 +441,49 @@ def sweep_lle(torch, pn, workloads, seeds):
     for T, cap in ((1000, 1000), (10000, 400)):
         for g in gains:
             lles, iters, conv, deer_ms, seq_ms, errs = [], [], [], [], [], []
+            bf_ms, bf_iters = [], []
             for seed in range(seeds):
-                w = workloads.MEANFIELD16.scaled(gain=g, T=T)
+                base = workloads.MEANFIELD16 if dim == 16 else workloads.MEANFIELD100
+                w = base.scaled(gain=g, T=T)
                 inst = workloads.make_instance(w, seed=seed)
                 x, s0, p = (torch.tensor(v, dtype=torch.float32, device=dev)
                             for v in (inst.x, inst.s0, inst.params))
                 ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="meanfield",
                                                                  offsets=inst.offsets))
                 seq_ms.append(ms)
-                u = torch.tensor(np.random.default_rng(100 + seed).standard_normal((3, 16)),
+                u = torch.tensor(np.random.default_rng(100 + seed).standard_normal((3, dim)),
                                  dtype=torch.float32, device=dev)
                 lles.append(float(np.mean([pn.lle_estimate(x, s0, p, s_seq, u[i:i + 1],
                                                            cell="meanfield",
                                                            offsets=inst.offsets)[0]
                                            for i in range(3)])))
-                ms, (s, info) = _timed(torch, lambda: pn.elk_solve(
-                    x, s0, p, 0.0, cell="meanfield", offsets=inst.offsets, jac="dense",
-                    tol=w.tol, max_iters=cap), reps=1)
+                if dim == 16:      # DEER = ELK at lambda = 0 (the D = 16 matrix passes)
+                    run = lambda: pn.elk_solve(x, s0, p, 0.0, cell="meanfield",
+                                               offsets=inst.offsets, jac="dense", tol=w.tol,
+                                               max_iters=cap)
+                else:              # the two-level dense scan; FP32 maps: exact Newton steps
+                    run = lambda: pn.deer_solve(x, s0, p, cell="meanfield", offsets=inst.offsets,
+                                                jac="dense", compose="native", tol=w.tol,
+                                                max_iters=cap)
+                ms, (s, info) = _timed(torch, run, reps=1)
                 deer_ms.append(ms)
                 iters.append(info[0]["iters"])
                 conv.append(bool(info[0]["converged"]))
                 ref = s_seq.double()
                 errs.append(float((s.double() - ref).abs().max() / ref.abs().max()))
+                if dim != 16:      # the same with BF16 maps (quasi-Newton steps)
+                    ms, (_, bi) = _timed(torch, lambda: pn.deer_solve(
+                        x, s0, p, cell="meanfield", offsets=inst.offsets, jac="dense",
+                        compose="bf16", tol=w.tol, max_iters=cap), reps=1)
+                    bf_ms.append(ms)
+                    bf_iters.append(bi[0]["iters"])
+            extra = {} if dim == 16 else {
+                "bf16_maps": {"iters_mean": round(float(np.mean(bf_iters)), 1),
+                              "ms_mean": round(float(np.mean(bf_ms)), 3),
+                              "speedup_vs_sequential": round(float(np.mean(seq_ms) /
+                                                                   np.mean(bf_ms)), 3)}}
             print(json.dumps({
-                "sweep": "meanfield16-lle", "T": T, "g": g, "seeds": seeds,
+                "sweep": f"meanfield{dim}-lle", "T": T, "g": g, "seeds": seeds, **extra,
                 "lle_mean": round(float(np.mean(lles)), 4),
                 "lle_min": round(float(np.min(lles)), 4), "lle_max": round(float(np.max(lles)), 4),
                 "deer_iters_mean": round(float(np.mean(iters)), 1), "deer_iters_max": max(iters),

@@ -167,14 +167,25 @@ mf_map_kernel(MfArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) M[bi][cl][r] = (bi == 2 * w + cl && 4 * g + r == c) ? 1.f : 0.f;
     uint32_t mr = 0;
+    // the step's operands, loaded one step ahead: s_{t-1} (thread tid < D), s_t and U x_t + b
+    // (thread (mi, 0), mi < D)
+    float sp_n = 0.f, sc_n = 0.f, ub_n = 0.f;
+    auto fetch = [&](int st) {
+        const int64_t row = row_lo + st;
+        if (tid < D)
+            sp_n = (st == 0 && first) ? a.s0[(size_t)b * D + tid] : s[(size_t)(row - 1) * D + tid];
+        if (mh == 0 && mi < D) {
+            sc_n = s[(size_t)row * D + mi];
+            ub_n = a.ub[(size_t)row * D + mi];
+        }
+    };
+    fetch(0);
     __syncthreads();
     for (int st = 0; st < len; ++st) {
         const int64_t row = row_lo + st;
+        const float sp = sp_n, sc = sc_n, ubv = ub_n;
+        fetch(min(st + 1, len - 1));                      // (the last step re-reads)
         if (tid < MP) {                                   // tanh and d of s_{t-1}
-            float sp = 0.f;
-            if (tid < D)
-                sp = (st == 0 && first) ? a.s0[(size_t)b * D + tid]
-                                        : s[(size_t)(row - 1) * D + tid];
             const float t_ = tid < D ? tanhf_(sp) : 0.f;
             const float d_ = tid < D ? 1.f - t_ * t_ : 0.f;
             th[tid] = t_;
@@ -246,8 +257,8 @@ mf_map_kernel(MfArgs a) {
             for (int cl = 0; cl < 2; ++cl) M[bi][cl] = Mn[bi][cl];
         __syncthreads();                                  // th, dk, dv, vv read by everyone
         if (mh == 0 && mi < D) {
-            const float f = pf + a.ub[(size_t)row * D + mi];
-            const float r = s[(size_t)row * D + mi] - f;
+            const float f = pf + ubv;
+            const float r = sc - f;
             mr = max(mr, absbits(r));
             vv[mi] = pv - r;
             a.rd[((size_t)row * 2 + 0) * D + mi] = r;
@@ -270,53 +281,71 @@ mf_map_kernel(MfArgs a) {
 }
 
 // ---- walk: one workgroup per sequence (after the decision of this iteration) ----------------
-__global__ void __launch_bounds__(256) mf_walk_kernel(MfArgs a) {
+// Thread (i, p) = (tid >> 3, tid & 7) of 1024 holds columns 16p .. 16p + 15 of row i of the
+// next WPF maps (every load unconditional, clamped to the last map, so that the compiler's
+// waits keep them in flight): the walk is a chain of dependent mat-vecs.
+constexpr int WPF = 5;
+__global__ void __launch_bounds__(1024) mf_walk_kernel(MfArgs a) {
     __shared__ __attribute__((aligned(16))) float wsh[MP];
     if (ld_i32(&a.ctrl->all_done)) return;
     const int b = blockIdx.x;
     if (a.seq[b].status != kActive) return;
     const int g0 = a.group_start[b], G = a.group_start[b + 1] - g0;
-    const int tid = threadIdx.x, mi = tid >> 1, mh = tid & 1;
+    const int tid = threadIdx.x, mi = tid >> 3, mp = tid & 7;
     if (tid < MP) {
         wsh[tid] = 0.f;
         if (G > 0) a.wcar[(size_t)g0 * MP + tid] = 0.f;
     }
-    float4 cur[16], nxt[16];
-    auto fetch = [&](int q, float4 (&dst)[16]) {
-        const float* mp = a.mbuf + (size_t)(g0 + q) * MP * MP + (size_t)mi * MP + 64 * mh;
+    const int nq = G - 1;                                // maps applied
+    if (nq <= 0) return;                                 // (uniform)
+    float4 ring[WPF][4];
+    float rv[WPF];
+    auto fetch = [&](int q, int j) {
+        const float* mrow = a.mbuf + (size_t)(g0 + q) * MP * MP + (size_t)mi * MP + 16 * mp;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) dst[k] = *(const float4*)(mp + 4 * k);
+        for (int k = 0; k < 4; ++k) ring[j][k] = *(const float4*)(mrow + 4 * k);
+        rv[j] = a.vbuf[(size_t)(g0 + q) * MP + mi];
     };
-    if (G > 1) fetch(0, cur);
+#pragma unroll
+    for (int j = 0; j < WPF; ++j) fetch(min(j, nq - 1), j);
     __syncthreads();
-    for (int q = 0; q + 1 < G; ++q) {
-        fetch(min(q + 1, G - 2), nxt);                   // (the last fetch re-reads)
-        const float vq = a.vbuf[(size_t)(g0 + q) * MP + mi];
-        float p0 = 0.f, p1 = 0.f;
+    for (int q0 = 0; q0 < nq; q0 += WPF) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const float4 u = *(const float4*)(wsh + 64 * mh + 4 * k);
-            p0 = fmaf(cur[k].x, u.x, p0);
-            p1 = fmaf(cur[k].y, u.y, p1);
-            p0 = fmaf(cur[k].z, u.z, p0);
-            p1 = fmaf(cur[k].w, u.w, p1);
-        }
-        const float y = pair_sum(p0 + p1) + vq;
-        __syncthreads();
-        if (mh == 0) {
-            wsh[mi] = y;
-            a.wcar[(size_t)(g0 + q + 1) * MP + mi] = y;
-        }
-        __syncthreads();
+        for (int j = 0; j < WPF; ++j) {
+            const int q = q0 + j;
+            float p0 = 0.f, p1 = 0.f;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+            for (int k = 0; k < 4; ++k) {
+                const float4 u = *(const float4*)(wsh + 16 * mp + 4 * k);
+                p0 = fmaf(ring[j][k].x, u.x, p0);
+                p1 = fmaf(ring[j][k].y, u.y, p1);
+                p0 = fmaf(ring[j][k].z, u.z, p0);
+                p1 = fmaf(ring[j][k].w, u.w, p1);
+            }
+            float p = p0 + p1;
+            p += __shfl_xor(p, 1);
+            p += __shfl_xor(p, 2);
+            p += __shfl_xor(p, 4);
+            const float y = p + rv[j];
+            fetch(min(q + WPF, nq - 1), j);
+            __syncthreads();
+            if (q < nq && mp == 0) {
+                wsh[mi] = y;
+                a.wcar[(size_t)(g0 + q + 1) * MP + mi] = y;
+            }
+            __syncthreads();
+        }
     }
 }
 
 // ---- apply pass: one workgroup per group ------------------------------------------------------
+// s^(k+1)_t = s^(k)_t + Delta_t.  Reset guard (the heuristic of the other solvers): a step
+// whose new state has an entry that is not finite or exceeds reset_abs in magnitude is set to
+// zero, and the recurrence continues from the Delta that leads there.
 __global__ void __launch_bounds__(256) mf_apply_kernel(MfArgs a) {
     __shared__ __attribute__((aligned(16))) float dl[MP];
     __shared__ __attribute__((aligned(16))) float dd[MP];
+    __shared__ int bad[2];
     if (ld_i32(&a.ctrl->all_done)) return;
     const int gi = blockIdx.x;
     if (gi >= a.ngroups) return;                        // (an empty batch launches one)
@@ -326,6 +355,7 @@ __global__ void __launch_bounds__(256) mf_apply_kernel(MfArgs a) {
     mf_group_rows(a, gi, row_lo, len, b, first);
     if (a.seq[b].status != kActive) return;
     const int k1 = a.ctrl->iter;                        // the decision has counted iteration k
+    const float reset_abs = a.ctrl->reset_abs;
     const float* __restrict__ sold = a.sbuf[(k1 + 1) & 1];
     float* __restrict__ snew = a.sbuf[k1 & 1];
     const int D = a.D;
@@ -333,20 +363,48 @@ __global__ void __launch_bounds__(256) mf_apply_kernel(MfArgs a) {
     MfRow wr;
     wr.load(a.W, D, mi, mh);
     if (tid < MP) dl[tid] = a.wcar[(size_t)gi * MP + tid];
+    if (tid < 2) bad[tid] = 0;
+    int resets = 0;
+    // d_t (thread tid < D), r_t and s^(k)_t (thread (mi, 0)), one step ahead
+    float d_n = 0.f, r_n = 0.f, so_n = 0.f;
+    auto fetch = [&](int st) {
+        const int64_t row = row_lo + st;
+        if (tid < D) d_n = a.rd[((size_t)row * 2 + 1) * D + tid];
+        if (mh == 0 && mi < D) {
+            r_n = a.rd[((size_t)row * 2 + 0) * D + mi];
+            so_n = sold[(size_t)row * D + mi];
+        }
+    };
+    fetch(0);
     __syncthreads();
     for (int st = 0; st < len; ++st) {
         const int64_t row = row_lo + st;
-        if (tid < MP) dd[tid] = tid < D ? a.rd[((size_t)row * 2 + 1) * D + tid] * dl[tid] : 0.f;
+        const float dv_ = d_n, rv = r_n, so = so_n;
+        fetch(min(st + 1, len - 1));
+        if (tid < MP) dd[tid] = tid < D ? dv_ * dl[tid] : 0.f;
         __syncthreads();
         const float y = pair_sum(wr.dot(dd, mh));
-        __syncthreads();
+        float del = 0.f, sn = 0.f;
         if (mh == 0 && mi < D) {
-            const float del = y - a.rd[((size_t)row * 2 + 0) * D + mi];
-            dl[mi] = del;
-            snew[(size_t)row * D + mi] = sold[(size_t)row * D + mi] + del;
+            del = y - rv;
+            sn = so + del;
+            if (!(fabsf(sn) <= reset_abs)) bad[st & 1] = 1;   // NaN fails the test too
         }
+        if (tid == 0) bad[(st + 1) & 1] = 0;             // the next step's flag
+        __syncthreads();
+        const bool reset = bad[st & 1] != 0;
+        if (mh == 0 && mi < D) {
+            if (reset) {
+                sn = 0.f;
+                del = -so;
+            }
+            dl[mi] = del;
+            snew[(size_t)row * D + mi] = sn;
+        }
+        resets += reset ? 1 : 0;
         __syncthreads();
     }
+    if (tid == 0 && resets) atomicAdd(&a.seq[b].resets_pending, resets);
 }
 
 // ---- sequential rollout and LLE (one workgroup per sequence) ----------------------------------
@@ -452,13 +510,25 @@ MfLayout mf_layout(void* ws, int D, const HostBatch& hb, int ntiles, int ngroups
     return lay;
 }
 
-// Group length: the map and apply passes walk a group's steps one after another (about
-// 1.5 us per step together), the walk one group after another (about 1 us per group): L of
-// about sqrt(T) balances them.
-int mf_group_tiles(const HostBatch& hb, const pn_opts& o) {
+// Group length (measured per step and group at D = 100): the map and apply passes walk a
+// group's steps one after another, one workgroup per group and CU (about 2.5 us per step with
+// BF16 maps, 10 us with FP32 maps, in rounds of one group per CU), the walk one group after
+// another (about 0.9 us per group of the longest sequence).  The default minimises that
+// estimate over powers of two.
+int mf_group_tiles(const std::vector<int32_t>& ts, const HostBatch& hb, const pn_opts& o) {
     if (o.group > 0) return o.group;
-    const double L = std::sqrt((double)std::max<int64_t>(hb.Tmax, 1) / 1.5);
-    return (int)std::min<double>(64.0, std::max(1.0, std::round(L / kMfTile)));
+    int tmax = 0;
+    for (int b = 0; b < hb.B; ++b) tmax = std::max(tmax, ts[b + 1] - ts[b]);
+    const double step_us = o.compose == PN_COMPOSE_BF16 ? 2.5 : 10.0;
+    int best = 1;
+    double best_us = 1e300;
+    for (int gt = 1; gt <= 64; gt *= 2) {
+        const int ng = count_groups(ts, hb.B, gt);
+        const double rounds = std::ceil((double)std::max(ng, 1) / cu_count());
+        const double us = rounds * kMfTile * gt * step_us + 0.9 * ((tmax + gt - 1) / gt);
+        if (us < best_us) best_us = us, best = gt;
+    }
+    return best;
 }
 
 void mf_upload_offsets(int64_t* doff, const HostBatch& hb, hipStream_t stream) {
@@ -472,7 +542,7 @@ bool mf_dense_supported(int D, int Dx) { return D > 16 && D <= MP && Dx >= 1 && 
 size_t mf_dense_workspace(int D, int Dx, const HostBatch& hb, const pn_opts& o) {
     (void)Dx;
     const std::vector<int32_t> ts = tile_starts(hb, kMfTile);
-    const int gt = mf_group_tiles(hb, o);
+    const int gt = mf_group_tiles(ts, hb, o);
     return mf_layout(nullptr, D, hb, ts[hb.B], count_groups(ts, hb.B, gt)).bytes;
 }
 
@@ -486,7 +556,7 @@ pn_status mf_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const fl
     }
     const std::vector<int32_t> ts = tile_starts(hb, kMfTile);
     const int ntiles = ts[hb.B];
-    const int gt = mf_group_tiles(hb, o);
+    const int gt = mf_group_tiles(ts, hb, o);
     const int ngroups = count_groups(ts, hb.B, gt);
     MfLayout lay = mf_layout(ws, D, hb, ntiles, ngroups);
     const int max_iters = o.max_iters > 0 ? o.max_iters : (int)std::max<int64_t>(1, hb.Tmax);
@@ -529,7 +599,7 @@ pn_status mf_dense_forward(const pn_cell_desc& cd, const HostBatch& hb, const fl
         });
         launch_decide(lay.st, hb.B, st, true);
         prof_launch("mf_dense_walk", st, [&](hipStream_t s2) {
-            hipLaunchKernelGGL(mf_walk_kernel, dim3(hb.B), dim3(256), 0, s2, a);
+            hipLaunchKernelGGL(mf_walk_kernel, dim3(hb.B), dim3(1024), 0, s2, a);
         });
         prof_launch("mf_dense_apply", st, [&](hipStream_t s2) {
             hipLaunchKernelGGL(mf_apply_kernel, dim3(grid), dim3(256), 0, s2, a);
