@@ -200,8 +200,12 @@ pn_status pn_workspace_bytes(int op, const pn_cell_desc* cell, const pn_batch* b
      GRU,  PN_JAC_DENSE, F64, 1 <= D <= 4, 1 <= Dx <= 16, no damping
      TANH, PN_JAC_DENSE, F32, D = 32, Dx in {16, 32}, compose native or BF16, no damping or
            PN_DAMP_SCALE
+     MEANFIELD, PN_JAC_DENSE, F32, 16 < D <= 128, 1 <= Dx <= 1024, compose native or BF16,
+           no damping (a two-level dense scan: per-group maps on MFMA, FP32 residual and
+           chains, the reset guard; opts->group = tiles of 32 steps per group, 0 = cost model)
      AFFINE, AFFINE_STEPS, any jac, F32, 1 <= D <= 16, 1 <= Dx <= 64, no damping (the test
            cells: the dense transition is M or M_t itself)
+   (MEANFIELD at D = 16 runs DEER through elk_solve with lambda = 0.)
    Anything else returns PN_ERR_UNSUPPORTED. */
 pn_status deer_solve(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                      const void* s0, void* s, const pn_opts* opts, void* workspace,
@@ -266,7 +270,8 @@ pn_status deer_adjoint(const pn_cell_desc* cell, const pn_batch* batch, const vo
    step at a time, then the parallel gradient reductions -- with the outputs of deer_adjoint.
    Workspace from pn_workspace_bytes(PN_OP_SEQ, ...).  Built: GRU F32 (the deer_solve GRU
    shapes), TANH F32 ((D, Dx) in {(16,16), (32,16), (32,32), (64,32), (16,8), (4,4)}),
-   MEANFIELD F32 (D = Dx = 16). seq_bptt: GRU, and TANH F32 with D = 32, Dx in {16, 32}. */
+   MEANFIELD F32 (D = Dx = 16, and 16 < D <= 128 with 1 <= Dx <= 1024). seq_bptt: GRU, and
+   TANH F32 with D = 32, Dx in {16, 32}. */
 #define PN_OP_SEQ 4
 pn_status seq_rollout(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                       const void* s0, void* s, void* workspace, size_t workspace_bytes,
@@ -287,7 +292,8 @@ pn_status pn_residual_f64(const pn_cell_desc* cell, const pn_batch* batch, const
    s [N, D]: the trajectory (device); u0 [B, D]: starting vectors (device, normalised here,
    nonzero); lle: HOST array [B] (0 for an empty sequence).  Log stretches are summed in FP64.
    Workspace from pn_workspace_bytes(PN_OP_LLE, ...).  Built: TANH and MEANFIELD, F32,
-   D = Dx = 16.  A zero stretch (u mapped to 0) gives -inf for that sequence. */
+   D = Dx = 16; MEANFIELD, F32, 16 < D <= 128.  A zero stretch (u mapped to 0) gives -inf for
+   that sequence. */
 #define PN_OP_LLE 5
 pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const void* x,
                           const void* s0, const void* s, const void* u0, void* workspace,
