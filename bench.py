@@ -635,6 +635,20 @@ def _measure_rows(torch, pn, workloads, sections, rows):
         "ms": round(ms, 3), "sequential_ms": round(seq_ms, 3),
         "speedup_vs_sequential": round(seq_ms / ms, 2), "iters": info[0]["iters"],
         "err_vs_sequential": rel(s, s_seq)}
+    # the same at the thesis's D = 100: the two-level dense scan with BF16 and FP32 maps
+    wm = workloads.MEANFIELD100.scaled(gain=0.5, T=10000)
+    inst = workloads.make_instance(wm, seed=0)
+    x, s0, p = tens(inst)
+    seq_ms, s_seq = _timed(torch, lambda: pn.seq_rollout(x, s0, p, cell="meanfield",
+                                                         offsets=inst.offsets))
+    for comp in ("bf16", "native"):
+        ms, (s, info) = _timed(torch, lambda: pn.deer_solve(
+            x, s0, p, cell="meanfield", offsets=inst.offsets, jac="dense", compose=comp,
+            tol=wm.tol))
+        rows[f"meanfield100 g=0.5 T=10000 DEER {comp} maps"] = {
+            "ms": round(ms, 3), "sequential_ms": round(seq_ms, 3),
+            "speedup_vs_sequential": round(seq_ms / ms, 2), "iters": info[0]["iters"],
+            "err_vs_sequential": rel(s, s_seq)}
 
     done('section 5')
     # ragged GRU batch: forward + backward as the main line
@@ -647,7 +661,8 @@ def _measure_rows(torch, pn, workloads, sections, rows):
     tf = pn.autotune("deer", x, s0, p, probe_iters=6, **kw)
     kw_f = dict(kw, tile=tf["tile"], group=tf["group"])
     s_tr, _ = pn.deer_solve(x, s0, p, **kw_f)
-    kw_adj = dict(kw, tol=1e-5)       # the adjoint at the stated tolerance, as the main line
+    # the adjoint at the stated tolerance as one reverse dense scan, as the main line
+    kw_adj = dict(kw, tol=1e-5, jac="dense", compose="bf16")
     tb = pn.autotune("adjoint", x, s0, p, s=s_tr, gs=2.0 * s_tr, probe_iters=6, **kw_adj)
     kw_b = dict(kw_adj, group=tb["group"])
     torch.cuda.synchronize()
@@ -679,6 +694,16 @@ def _measure_rows(torch, pn, workloads, sections, rows):
                     "autotuned": {"fwd_tile": tf["tile"], "fwd_group": tf["group"],
                                   "adj_group": tb["group"], "tune_ms": round(tune_ms, 1)},
                     "fwd_bwd_ms_cost_model_tiles": round(ms_default, 3)}
+    # the same with the adjoint by iterated diagonal scans
+    kw_diag = dict(kw, tol=1e-5)
+
+    def fb_diag():
+        s, fi = pn.deer_solve(x, s0, p, **kw_f)
+        gp, gx, g0, bi = pn.deer_adjoint(x, s0, p, s, 2.0 * s, **kw_diag)
+        return bi
+    ms_diag, bi_diag = _timed(torch, fb_diag, reps=2)
+    rows[w.name]["fwd_bwd_ms_diag_adjoint"] = round(ms_diag, 3)
+    rows[w.name]["iters_bwd_max_diag_adjoint"] = max(i["iters"] for i in bi_diag)
 
     done('section 6')
     # transition variants on the GRU path (benchmark shapes, forward only)

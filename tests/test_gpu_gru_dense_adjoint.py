@@ -126,3 +126,18 @@ def test_autograd_with_the_dense_adjoint(lib):
     want = adjoint.adjoint_batch(cell, inst.x, inst.s0, sref, 2 * sref, inst.offsets)[1:]
     got = tuple(v.grad.cpu().double().numpy() for v in (p, x, s0))
     _check(cell, got, want, 1e-5)
+
+
+def test_dense_adjoint_empty_sequences(lib):
+    """A batch of empty sequences: nothing to solve, every sequence converged, zero gradients
+    (gs0 = A_1^T lambda_1 has no step to come from)."""
+    import torch
+    w = workloads.Workload("t", "gru", D=48, Dx=24, B=3, tol=1e-5)
+    inst = workloads.make_instance(w, seed=5, lengths=np.array([0, 0, 0]))
+    x = torch.zeros((1, 24), dtype=torch.float32, device="cuda")[:0]
+    s = torch.zeros((1, 48), dtype=torch.float32, device="cuda")[:0]
+    gp, gx, g0, info = lib.deer_adjoint(x, _t(inst.s0), _t(inst.params), s, s.clone(),
+                                        cell="gru", offsets=inst.offsets, jac="dense",
+                                        compose="bf16")
+    assert all(i["converged"] and i["iters"] <= 1 for i in info), info
+    assert float(gp.abs().max()) == 0.0 and float(g0.abs().max()) == 0.0
