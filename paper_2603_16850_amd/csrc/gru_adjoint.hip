@@ -83,88 +83,91 @@ struct GruAdjArgs {
 };
 
 // ---- prep: gate values at the solution, max |g| -------------------------------------------
+// Tiles are processed with their inputs double-buffered in LDS: the s rows (h of every step),
+// the x rows and the g rows of the next tile are copied from HBM straight into LDS
+// (global_load_lds, 16 B per lane) while the current tile is computed.
 template <int D, int DX, int L>
 __global__ void __launch_bounds__(64 * (D / 16))
 __attribute__((amdgpu_waves_per_eu(L <= 32 && D + DX <= 72 ? 3 : 2,
                                    L <= 32 && D + DX <= 72 ? 3 : 2)))
 gru_adj_prep_kernel(GruAdjArgs a) {
     using C = GruA<D, DX, L>;
-    __shared__ __attribute__((aligned(16))) float hs[L * C::HS];
-    __shared__ __attribute__((aligned(16))) float xs[L * C::XS];
+    constexpr int BUF = L * (2 * D + DX);        // [h rows | x rows | g rows], unpadded
+    __shared__ __attribute__((aligned(16))) float stg0[BUF];
+    __shared__ __attribute__((aligned(16))) float stg1[BUF];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, u = l & 15;
     const int j = 16 * w + u;
     GruGates<D, DX> wg;
     wg.load(a.params, j, g);
-    TileInfo tnext{};
-    if ((int)blockIdx.x < a.ntiles) tnext = a.tiles[blockIdx.x];
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const TileInfo ti = tnext;
-        if (tile + (int)gridDim.x < a.ntiles) tnext = a.tiles[tile + gridDim.x];   // read ahead
-        const int b = ti.b, len = ti.len;
-        const int64_t row0 = ti.row0;
-        const bool first = (ti.flags & kTileTimeFirst) != 0;
-        __syncthreads();
-        // stage row r <-> h of step t0 + r, and the x rows; all loads of a batch are issued
-        // before its LDS writes
-        constexpr int Q = D / 4, QX = DX / 4;
-        constexpr int NSV = (L * Q + C::NT - 1) / C::NT;
-        constexpr int NXV = (L * QX + C::NT - 1) / C::NT;
-        constexpr int NI = NSV + NXV;
-        constexpr int NB = 4;
-#pragma unroll
-        for (int i0 = 0; i0 < NI; i0 += NB) {
-            float4 v[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int i = i0 + q;
-                v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (i < NSV) {
-                    const int idx = tid + i * C::NT;
-                    const int r = idx / Q, c4 = idx % Q;
-                    if (idx < L * Q && r < len)
-                        v[q] = (r == 0 && first)
-                                   ? *(const float4*)(a.s0 + (size_t)b * D + 4 * c4)
-                                   : *(const float4*)(a.s + (size_t)(row0 + r - 1) * D + 4 * c4);
-                } else if (i < NI) {
-                    const int idx = tid + (i - NSV) * C::NT;
-                    const int r = idx / QX, c4 = idx % QX;
-                    if (idx < L * QX && r < len)
-                        v[q] = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int i = i0 + q;
-                if (i < NSV) {
-                    const int idx = tid + i * C::NT;
-                    if (idx < L * Q) *(float4*)(hs + (idx / Q) * C::HS + 4 * (idx % Q)) = v[q];
-                } else if (i < NI) {
-                    const int idx = tid + (i - NSV) * C::NT;
-                    if (idx < L * QX) *(float4*)(xs + (idx / QX) * C::XS + 4 * (idx % QX)) = v[q];
-                }
-            }
+    // nbytes (a multiple of 16) from src to LDS dst, 1 KB per wave instruction
+    auto bulk = [&](float* dst, const float* src, int nbytes) {
+        for (int c = w; c * 1024 < nbytes; c += C::NW) {
+            const int off = c * 1024 + 16 * l;
+            if (off < nbytes)
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)((const char*)src + off),
+                    (__attribute__((address_space(3))) void*)((char*)dst + c * 1024), 16, 0, 0);
         }
-        __syncthreads();
+    };
+    // row r of the h block is s_{t0 + r - 1}; a sequence's first step takes s0
+    auto issue = [&](const TileInfo& ti, float* buf) {
+        const int hr = (ti.flags & kTileTimeFirst) ? 1 : 0;
+        if (hr) bulk(buf, a.s0 + (size_t)ti.b * D, D * 4);
+        bulk(buf + hr * D, a.s + (size_t)(ti.row0 - 1 + hr) * D, (ti.len - hr) * D * 4);
+        bulk(buf + L * D, a.x + (size_t)ti.row0 * DX, ti.len * DX * 4);
+        bulk(buf + L * (D + DX), a.gs + (size_t)ti.row0 * D, ti.len * D * 4);
+    };
+    // the tile table is not written while the kernel runs: read it through the scalar cache
+    // (s_load), whose counter is not the one the copies into LDS advance
+    using CTile = const __attribute__((address_space(4))) TileInfo;
+    CTile* ctiles = (CTile*)a.tiles;
+    auto tiles = [&](int i) {
+        TileInfo r;
+        r.slot = ctiles[i].slot;
+        r.b = ctiles[i].b;
+        r.len = ctiles[i].len;
+        r.flags = ctiles[i].flags;
+        r.row0 = ctiles[i].row0;
+        r.gslot = ctiles[i].gslot;
+        r.hgslot = ctiles[i].hgslot;
+        return r;
+    };
+    int tile = blockIdx.x;
+    if (tile >= a.ntiles) return;
+    TileInfo ti = tiles(tile);
+    issue(ti, stg0);
+    TileInfo tn{};
+    if (tile + (int)gridDim.x < a.ntiles) tn = tiles(tile + gridDim.x);
+    // one tile: its inputs are in `hs`, the next tile's go to `nb` meanwhile.  The two buffers
+    // are distinct LDS objects and every use names one of them statically, so that the
+    // compiler can tell the reads of one from the copies into the other.
+    auto one = [&](const float* hs, float* nb) {
+        const float* xs = hs + L * D;
+        const float* gsl = xs + L * DX;
+        __builtin_amdgcn_s_waitcnt(0x0F70);       // vmcnt(0): this wave's copies have landed
+        __syncthreads();                          // every wave's; the other buffer is free
+        float2 xt[C::MB];                         // x row tails, read before the next copies
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb) xt[mb] = wg.xtail_of(xs + (mb * 16 + u) * DX, g);
+        if (tile + (int)gridDim.x < a.ntiles) issue(tn, nb);
+        const int len = ti.len;
+        const int64_t row0 = ti.row0;
+        int o_a = u * D, o_x = u * DX, o_own = 4 * g * D + j;
+        asm volatile("" : "+v"(o_a), "+v"(o_x), "+v"(o_own));
         uint32_t gm = 0;
-        float gvs[C::MB][4];       // g_t of this lane's steps, loaded ahead of the MFMAs
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int tl = mb * 16 + 4 * g + i;
-                gvs[mb][i] = tl < len ? a.gs[(size_t)(row0 + tl) * D + j] : 0.f;
-            }
 #pragma unroll
         for (int mb = 0; mb < C::MB; ++mb) {
             floatx4 az, ar, aq, an;
-            wg.gemm(hs + (mb * 16 + u) * C::HS, xs + (mb * 16 + u) * C::XS, g, az, ar, aq, an);
+            wg.gemm_xtail(hs + mb * 16 * D + o_a, xs + mb * 16 * DX + o_x, xt[mb], g, az, ar, aq,
+                          an);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int tl = mb * 16 + 4 * g + i;
                 if (tl >= len) continue;
                 const GruPoint p = gru_point(az[i], ar[i], aq[i], an[i], wg.b_z, wg.b_r, wg.b_n,
                                              wg.b_hn);
-                const float h = hs[tl * C::HS + j];
+                const float h = hs[mb * 16 * D + i * D + o_own];
+                const float gv = gsl[mb * 16 * D + i * D + o_own];
                 const float e = (1.f - p.z) * (1.f - p.n * p.n);
                 const size_t row = (size_t)(row0 + tl);
                 float* gr = a.gates + row * 4 * D;
@@ -176,12 +179,21 @@ gru_adj_prep_kernel(GruAdjArgs a) {
                 gr[2 * D + j] = ga;
                 gr[3 * D + j] = p.z;
                 a.eps[row * D + j] = e;
-                gm = max(gm, absbits(gvs[mb][i]));
+                gm = max(gm, absbits(gv));
             }
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) gm = max(gm, (uint32_t)__shfl_xor((int)gm, off));
         if (l == 0) a.cmax[(size_t)tile * C::NW + w] = gm;
+        ti = tn;
+        if (tile + 2 * (int)gridDim.x < a.ntiles) tn = tiles(tile + 2 * gridDim.x);
+        tile += gridDim.x;
+    };
+    while (true) {
+        one(stg0, stg1);
+        if (tile >= a.ntiles) break;
+        one(stg1, stg0);
+        if (tile >= a.ntiles) break;
     }
 }
 

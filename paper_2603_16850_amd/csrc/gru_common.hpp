@@ -60,6 +60,22 @@ struct GruGates {
     //   az = W_z x + U_z h,  ar = W_r x + U_r h,  aq = U_n h,  an = W_n x   (no biases)
     PN_DEV void gemm(const float* hrow, const float* xrow, int g, floatx4& az, floatx4& ar,
                      floatx4& aq, floatx4& an) const {
+        gemm_impl<false>(hrow, xrow, make_float2(0.f, 0.f), g, az, ar, aq, an);
+    }
+    // The same, with the lane's two x values of the row tail (DX % 16 == 8) read by the
+    // caller beforehand (`xtail`), so that no LDS read of x follows later copies into LDS.
+    PN_DEV void gemm_xtail(const float* hrow, const float* xrow, float2 xtail, int g,
+                           floatx4& az, floatx4& ar, floatx4& aq, floatx4& an) const {
+        gemm_impl<true>(hrow, xrow, xtail, g, az, ar, aq, an);
+    }
+    // the lane's x tail values, as gemm reads them
+    PN_DEV static float2 xtail_of(const float* xrow, int g) {
+        return KT ? *(const float2*)(xrow + 16 * KX + 2 * g) : make_float2(0.f, 0.f);
+    }
+
+    template <bool PRE>
+    PN_DEV void gemm_impl(const float* hrow, const float* xrow, float2 xtail, int g,
+                          floatx4& az, floatx4& ar, floatx4& aq, floatx4& an) const {
         az = floatx4{0.f, 0.f, 0.f, 0.f};
         ar = az;
         aq = az;
@@ -87,7 +103,7 @@ struct GruGates {
             }
         }
         if (KT) {
-            const float2 x2 = *(const float2*)(xrow + 16 * KX + 2 * g);
+            const float2 x2 = PRE ? xtail : xtail_of(xrow, g);
             const float xv[2] = {x2.x, x2.y};
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
