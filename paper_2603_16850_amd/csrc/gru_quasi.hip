@@ -89,6 +89,12 @@ gru_quasi_local_kernel(GruQArgs a) {
     __shared__ __attribute__((aligned(16))) float lraw[(L + 1) * 2 * D];// (la, lc) rows as copied
 
     __shared__ int rowbad[L + 1];
+    // With 32-step tiles the next tile's rows are copied while the current one is computed
+    // (PF): the staging buffers above then take the next tile's copies as soon as the update
+    // has read them, and the GEMM reads the tile's x rows from a copy of their own.
+    constexpr bool PF = L == 32;
+    __shared__ __attribute__((aligned(16))) float xcur[PF ? L * DX : 4];
+    __shared__ __attribute__((aligned(16))) float cgs[2 * D];          // carries: own, halo
 
     if (ld_i32(&a.ctrl->all_done)) return;
     // Iteration k first forms s^(k) = s^(k-1) + la carry + lc from the previous iteration's
@@ -136,6 +142,34 @@ gru_quasi_local_kernel(GruQArgs a) {
         }
         float Pa = 1.f, Pc = 0.f;        // map of the group's tiles before the current one
         uint32_t rmax = 0;
+        // nbytes (a multiple of 16) from src to LDS dst, 1 KB per wave instruction (lane i's
+        // 16 B to byte 16 i of the slice)
+        auto bulk = [&](float* dst, const float* src, int nbytes) {
+            for (int c = w; c * 1024 < nbytes; c += C::NW) {
+                const int off = c * 1024 + 16 * l;
+                if (off < nbytes)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)((const char*)src + off),
+                        (__attribute__((address_space(3))) void*)((char*)dst + c * 1024), 16, 0, 0);
+            }
+        };
+        // a tile's s rows row0-1 .. row0+len-1 (staged row 0 is the halo s_{t0-1}: s0 at a
+        // sequence's first tile), its (la, lc) rows and x rows, and the carries into its group
+        // and into the one before
+        auto issue = [&](const TileInfo& t) {
+            const bool tf = (t.flags & kTileTimeFirst) != 0;
+            const int hr = tf ? 1 : 0;
+            const int64_t srow = t.row0 - 1 + hr;
+            const int nrow = t.len + 1 - hr;
+            if (tf) bulk(sraw, a.s0 + (size_t)b * D, D * 4);
+            bulk(sraw + hr * D, (fuse ? sprev : scur) + (size_t)srow * D, nrow * D * 4);
+            if (fuse) {
+                bulk(lraw + hr * 2 * D, (const float*)(lacp + (size_t)srow * D), nrow * 2 * D * 4);
+                bulk(cgs, a.gcarry + (size_t)t.gslot * D, D * 4);
+                if (!tf) bulk(cgs + D, a.gcarry + (size_t)t.hgslot * D, D * 4);
+            }
+            bulk(xs, a.x + (size_t)t.row0 * DX, t.len * DX * 4);
+        };
         TileInfo tnext = a.tiles[gr.tile0];
         for (int kt = 0; kt < gr.ntl; ++kt) {
             const TileInfo ti = tnext;
@@ -146,21 +180,13 @@ gru_quasi_local_kernel(GruQArgs a) {
 
             // ---- stage s rows row0-1 .. row0+L-1 (stage row r <-> s_{t0-1+r}) and x rows.
             // The tile's rows of s, of the previous maps (la, lc) and of x are contiguous in
-            // HBM and go straight into LDS as whole blocks (global_load_lds, 1 KB per wave
-            // instruction, lane i's 16 B to byte 16 i of the slice), all in flight together;
-            // the update to s^(k) then runs LDS to LDS.  A thread's float4 column c4 is the same
-            // for all its s items (NT is a multiple of D / 4).
+            // HBM and go straight into LDS as whole blocks (global_load_lds), all in flight
+            // together; the update to s^(k) then runs LDS to LDS.  A thread's float4 column c4
+            // is the same for all its s items (NT is a multiple of D / 4).
             constexpr int Q = D / 4;
             static_assert(C::NT % Q == 0, "column per thread");
             constexpr int NSV = ((L + 1) * Q + C::NT - 1) / C::NT;
             const int c4 = tid % Q;
-            float4 cown = make_float4(0.f, 0.f, 0.f, 0.f), chalo = cown;
-            if (fuse) {      // in flight together with the staging loads below
-                cown = *(const float4*)(a.gcarry + (size_t)ti.gslot * D + 4 * c4);
-                if (!first && tid < Q)
-                    chalo = *(const float4*)(a.gcarry + (size_t)ti.hgslot * D + 4 * c4);
-            }
-            __syncthreads();                 // LDS of the previous tile consumed
             // Lane offsets into the LDS tiles and the [N][D] rows, formed anew for every tile
             // (hidden from the optimiser): hoisted out of the loops, one precomputed address
             // per (row, operand) would stay live across the whole group loop.
@@ -171,32 +197,12 @@ gru_quasi_local_kernel(GruQArgs a) {
             int o_st = (tid / Q) * C::HS + 4 * c4;   // staging: s item 0 in hs
             asm volatile("" : "+v"(o_arow), "+v"(o_xrow), "+v"(o_own), "+v"(o_row), "+v"(o_st));
             constexpr int RQ = C::NT / Q;            // s item i of a thread is row tid / Q + i RQ
-            {
-                // nbytes (a multiple of 16) from src to LDS dst, 1 KB per wave instruction
-                auto bulk = [&](float* dst, const float* src, int nbytes) {
-                    for (int c = w; c * 1024 < nbytes; c += C::NW) {
-                        const int off = c * 1024 + 16 * l;
-                        if (off < nbytes)
-                            __builtin_amdgcn_global_load_lds(
-                                (const void*)((const char*)src + off),
-                                (__attribute__((address_space(3))) void*)((char*)dst + c * 1024),
-                                16, 0, 0);
-                    }
-                };
-                // staged row 0 is the halo s_{t0-1}: s0 at a sequence's first tile
-                const int hr = first ? 1 : 0;
-                const int64_t srow = row0 - 1 + hr;
-                const int nrow = len + 1 - hr;
-                bulk(sraw + hr * D, (fuse ? sprev : scur) + (size_t)srow * D, nrow * D * 4);
-                if (fuse)
-                    bulk(lraw + hr * 2 * D, (const float*)(lacp + (size_t)srow * D),
-                         nrow * 2 * D * 4);
-                bulk(xs, a.x + (size_t)row0 * DX, len * DX * 4);
-                if (first && tid < Q)
-                    *(float4*)(sraw + 4 * tid) = *(const float4*)(a.s0 + (size_t)b * D + 4 * tid);
-                __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): the copies have landed
-            }
-            __syncthreads();
+            // with PF only a group's first tile is copied here, every later one while the
+            // previous tile was computed; without, every tile once the previous one is done
+            if (!PF) __syncthreads();
+            if (!PF || kt == 0) issue(ti);
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies have landed
+            __syncthreads();                      // every wave's; the previous tile is done
 #pragma unroll
             for (int i = 0; i < NSV; ++i) {
                 const int idx = tid + i * C::NT;
@@ -206,7 +212,7 @@ gru_quasi_local_kernel(GruQArgs a) {
                 if (r == 0 || r - 1 < len) {
                     w4 = *(const float4*)(sraw + r * D + 4 * c4);
                     if (fuse && !(r == 0 && (first || (kt == 0 && halo_frozen)))) {
-                        const float4 cv = r == 0 ? chalo : cown;
+                        const float4 cv = *(const float4*)(cgs + (r == 0 ? D : 0) + 4 * c4);
                         const float4 p0 = *(const float4*)(lraw + r * 2 * D + 8 * c4);
                         const float4 p1 = *(const float4*)(lraw + r * 2 * D + 8 * c4 + 4);
                         const float d0 = p0.x * cv.x + p0.y;
@@ -228,6 +234,9 @@ gru_quasi_local_kernel(GruQArgs a) {
                 }
                 *(float4*)(hs + o_st + i * RQ * C::HS) = w4;
             }
+            if (PF)
+                for (int e = tid; e < L * DX / 4; e += C::NT)
+                    ((float4*)xcur)[e] = ((const float4*)xs)[e];
             __syncthreads();
             if (fuse) {
                 // reset guard on the formed rows, then s^(k) of the tile's own rows to HBM
@@ -254,13 +263,18 @@ gru_quasi_local_kernel(GruQArgs a) {
                 for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
             }
 
+            // every wave is past its last read of the staging buffers: with PF the next tile's
+            // copies go in now and overlap the rest of this one (no fenced barrier follows
+            // before the next tile, which would wait for them)
+            if (PF && kt + 1 < gr.ntl) issue(tnext);
+
             // ---- gates by MFMA, then residual and leaves, per 16-step block ----
             float la[C::MB][4], lc[C::MB][4];
 #pragma unroll
             for (int mb = 0; mb < C::MB; ++mb) {
                 floatx4 az, ar, aq, an;
-                wg.gemm(hs + o_arow + mb * 16 * C::HS, xs + o_xrow + mb * 16 * DX, g, az, ar, aq,
-                        an);
+                wg.gemm(hs + o_arow + mb * 16 * C::HS, (PF ? xcur : xs) + o_xrow + mb * 16 * DX, g,
+                        az, ar, aq, an);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int tl = mb * 16 + 4 * g + i;      // step index within the tile
