@@ -89,6 +89,7 @@ gru_quasi_local_kernel(GruQArgs a) {
     __shared__ __attribute__((aligned(16))) float lraw[(L + 1) * 2 * D];// (la, lc) rows as copied
 
     __shared__ int rowbad[L + 1];
+    __shared__ int anybad[2];      // some row of the tile was reset (by tile parity)
     // With 32-step tiles the next tile's rows are copied while the current one is computed
     // (PF): the staging buffers above then take the next tile's copies as soon as the update
     // has read them, and the GEMM reads the tile's x rows from a copy of their own.
@@ -118,6 +119,8 @@ gru_quasi_local_kernel(GruQArgs a) {
     GruGates<D, DX> wg;   // this wave's weights (units j) as MFMA B operands
     wg.load(a.params, j, g);
     for (int r = tid; r <= L; r += C::NT) rowbad[r] = 0;
+    if (tid < 2) anybad[tid] = 0;
+    int tcount = 0;                // tiles done by this workgroup (parity of anybad)
 
     for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
         const GroupInfo gr = a.groups[gi];
@@ -203,6 +206,8 @@ gru_quasi_local_kernel(GruQArgs a) {
             if (!PF || kt == 0) issue(ti);
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies have landed
             __syncthreads();                      // every wave's; the previous tile is done
+            const int par = tcount++ & 1;
+            if (tid == 0) anybad[par ^ 1] = 0;    // the previous tile's flag, read by all
 #pragma unroll
             for (int i = 0; i < NSV; ++i) {
                 const int idx = tid + i * C::NT;
@@ -227,9 +232,14 @@ gru_quasi_local_kernel(GruQArgs a) {
                         if (bydelta && r > 0)
                             rmax = max(rmax, max(max(absbits(d0), absbits(d1)),
                                                  max(absbits(d2), absbits(d3))));
+                        // s^(k) of the tile's own rows to HBM; a row the reset guard
+                        // takes back is written again below
+                        if (r >= 1) *(float4*)(scur + (size_t)(row0 + r - 1) * D + 4 * c4) = w4;
                         if (!(fabsf(w4.x) <= reset_abs) || !(fabsf(w4.y) <= reset_abs) ||
-                            !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs))
+                            !(fabsf(w4.z) <= reset_abs) || !(fabsf(w4.w) <= reset_abs)) {
                             rowbad[r] = 1;
+                            anybad[par] = 1;
+                        }
                     }
                 }
                 *(float4*)(hs + o_st + i * RQ * C::HS) = w4;
@@ -238,17 +248,16 @@ gru_quasi_local_kernel(GruQArgs a) {
                 for (int e = tid; e < L * DX / 4; e += C::NT)
                     ((float4*)xcur)[e] = ((const float4*)xs)[e];
             __syncthreads();
-            if (fuse) {
-                // reset guard on the formed rows, then s^(k) of the tile's own rows to HBM
+            if (fuse && anybad[par]) {
+                // reset guard: the rows with a non-finite or too large entry restart from 0
 #pragma unroll
                 for (int i = 0; i < NSV; ++i) {
                     const int idx = tid + i * C::NT;
                     const int r = idx / Q;
-                    if (idx < (L + 1) * Q && (r == 0 || r - 1 < len)) {
-                        float* hp = hs + r * C::HS + 4 * c4;
-                        if (rowbad[r]) *(float4*)hp = make_float4(0.f, 0.f, 0.f, 0.f);
-                        if (r >= 1) *(float4*)(scur + (size_t)(row0 + r - 1) * D + 4 * c4) =
-                                        *(const float4*)hp;
+                    if (idx < (L + 1) * Q && (r == 0 || r - 1 < len) && rowbad[r]) {
+                        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                        *(float4*)(hs + r * C::HS + 4 * c4) = z4;
+                        if (r >= 1) *(float4*)(scur + (size_t)(row0 + r - 1) * D + 4 * c4) = z4;
                     }
                 }
                 if (tid < 64) {
