@@ -76,13 +76,15 @@ def test_graph_and_launch_agree(lib, use_graph):
     assert _rel(s1, s2) < 1e-6
 
 
-def test_iterates_match_sequential_newton(lib):
-    """After k updates the GPU iterate equals the oracle's k-th quasi-DEER iterate."""
+@pytest.mark.parametrize("tile,group", [(64, 0), (32, 4)])
+def test_iterates_match_sequential_newton(lib, tile, group):
+    """After k updates the GPU iterate equals the oracle's k-th quasi-DEER iterate (32-step
+    tiles: each tile's rows are copied while the previous tile of its group is computed)."""
     w = workloads.GRU64_QUASI.scaled(T=700, B=2)
     inst = workloads.make_instance(w, seed=2)
     cell = cells.GRU(inst.params, w.D, w.Dx)
     for k in (1, 2, 5):
-        s, info = _run(lib, inst, max_iters=k, tol=1e-12)
+        s, info = _run(lib, inst, max_iters=k, tol=1e-12, tile=tile, group=group)
         for b in range(2):
             a, e = inst.offsets[b], inst.offsets[b + 1]
             out = newton.newton(cell, inst.x[a:e], inst.s0[b], mode="diag", tol=1e-12,
@@ -102,7 +104,10 @@ def test_prefix_exact_after_k_iterations(lib):
         assert np.abs(s[:k] - ref[:k]).max() < 1e-6
 
 
-def test_reset_guard_recovers(lib):
+@pytest.mark.parametrize("tile,group", [(64, 0), (32, 4)])
+def test_reset_guard_recovers(lib, tile, group):
+    """Rows formed non-finite or too large restart from 0 (the reset pass runs only for the
+    tiles that have such a row) and the solve still reaches the rollout."""
     import torch
     w = workloads.GRU64_QUASI.scaled(T=500, B=2)
     inst = workloads.make_instance(w, seed=5)
@@ -113,9 +118,10 @@ def test_reset_guard_recovers(lib):
     init[700] = 1e30
     x, s0, p = _to(inst.x, torch), _to(inst.s0, torch), _to(inst.params, torch)
     s, info = lib.deer_solve(x, s0, p, cell="gru", offsets=inst.offsets, jac="diag",
-                             tol=ERR_TOL, s_init=_to(init, torch))
+                             tol=ERR_TOL, s_init=_to(init, torch), tile=tile, group=group)
     s = s.cpu().double().numpy()
     assert all(i["converged"] for i in info)
+    assert sum(i["resets"] for i in info) > 0
     assert _rel(s, ref) < 1e-5
 
 
@@ -127,13 +133,17 @@ def test_not_converged_reports_last_iterate(lib):
     assert np.isfinite(s).all()
 
 
-@pytest.mark.parametrize("name", ["gru64-quasi-f32", "gru48-ragged-quasi"])
-def test_full_size_matches_rollout(lib, name):
-    """The benchmark workloads at full size, default launch configuration."""
+@pytest.mark.parametrize("name,tile,group", [("gru64-quasi-f32", 0, 0),
+                                             ("gru48-ragged-quasi", 0, 0),
+                                             ("gru48-ragged-quasi", 32, 16)])
+def test_full_size_matches_rollout(lib, name, tile, group):
+    """The benchmark workloads at full size: default launch configuration, and the 32-step
+    tiles in groups of 16 that the benchmark's tuner picks for the ragged batch."""
     w = workloads.ALL[name]
     inst = workloads.make_instance(w, seed=0)
     cell = cells.GRU(inst.params, w.D, w.Dx)
-    s, info = _run(lib, inst, tol=ERR_TOL)
+    kw = dict(tile=tile, group=group) if tile else {}
+    s, info = _run(lib, inst, tol=ERR_TOL, **kw)
     ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
     assert all(i["converged"] for i in info)
     assert _rel(s, ref) < 1e-5, _rel(s, ref)
