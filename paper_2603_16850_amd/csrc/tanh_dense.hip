@@ -67,7 +67,8 @@ struct TanhDArgs {
 };
 
 template <int DX, bool BF16>
-__global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+tanh_dense_local_kernel(TanhDArgs a) {
     constexpr int SS = TD + 4, XS = DX + 4;
     constexpr int KT = TD + DX;               // linearise K
     static_assert(KT % 2 == 0, "shape");
@@ -170,21 +171,45 @@ __global__ void __launch_bounds__(64) tanh_dense_local_kernel(TanhDArgs a) {
             const int64_t row0 = ti.row0;
             const bool first = (ti.flags & kTileTimeFirst) != 0;
             __syncthreads();
-            // ---- stage s_{t-1}, s_t (of s^(k-1), or the guess s^(0)) and x_t
+            // ---- stage s_{t-1}, s_t (of s^(k-1), or the guess s^(0)) and x_t: every load of
+            // the chunk is issued before the first LDS write (one round trip, not one per row
+            // block)
             const float* src = fuse ? sprev : scur;
-            for (int idx = l; idx < (TL + 1) * (TD / 4); idx += 64) {
+            constexpr int NSI = ((TL + 1) * (TD / 4) + 63) / 64, NXI = (TL * (DX / 4) + 63) / 64;
+            float4 sv[NSI], xv[NXI];
+#pragma unroll
+            for (int q = 0; q < NSI; ++q) {
+                const int idx = l + 64 * q;
                 const int r = idx / (TD / 4), c4 = idx % (TD / 4);
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (r == 0) v = first ? *(const float4*)(a.s0 + (size_t)b * TD + 4 * c4)
-                                      : *(const float4*)(src + (size_t)(row0 - 1) * TD + 4 * c4);
-                else if (r - 1 < len) v = *(const float4*)(src + (size_t)(row0 + r - 1) * TD + 4 * c4);
-                *(float4*)(sst + r * SS + 4 * c4) = v;
+                if (idx < (TL + 1) * (TD / 4)) {
+                    if (r == 0) v = first ? *(const float4*)(a.s0 + (size_t)b * TD + 4 * c4)
+                                          : *(const float4*)(src + (size_t)(row0 - 1) * TD + 4 * c4);
+                    else if (r - 1 < len)
+                        v = *(const float4*)(src + (size_t)(row0 + r - 1) * TD + 4 * c4);
+                }
+                sv[q] = v;
             }
-            for (int idx = l; idx < TL * (DX / 4); idx += 64) {
+#pragma unroll
+            for (int q = 0; q < NXI; ++q) {
+                const int idx = l + 64 * q;
                 const int r = idx / (DX / 4), c4 = idx % (DX / 4);
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (r < len) v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
-                *(float4*)(xst + r * XS + 4 * c4) = v;
+                if (idx < TL * (DX / 4) && r < len)
+                    v = *(const float4*)(a.x + (size_t)(row0 + r) * DX + 4 * c4);
+                xv[q] = v;
+            }
+#pragma unroll
+            for (int q = 0; q < NSI; ++q) {
+                const int idx = l + 64 * q;
+                if (idx < (TL + 1) * (TD / 4))
+                    *(float4*)(sst + (idx / (TD / 4)) * SS + 4 * (idx % (TD / 4))) = sv[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NXI; ++q) {
+                const int idx = l + 64 * q;
+                if (idx < TL * (DX / 4))
+                    *(float4*)(xst + (idx / (DX / 4)) * XS + 4 * (idx % (DX / 4))) = xv[q];
             }
             if (l <= TL) badrow[l] = 0;
             __syncthreads();
