@@ -150,7 +150,8 @@ def test_full_size_matches_rollout(lib, name, tile, group):
 
 
 @pytest.mark.parametrize("mode", ["picard", "jacobi"])
-def test_fixed_point_modes_match_sequential_loop(lib, mode):
+@pytest.mark.parametrize("tile,group", [(64, 0), (32, 2)])
+def test_fixed_point_modes_match_sequential_loop(lib, mode, tile, group):
     """Picard (A~ = I) and Jacobi (A~ = 0) iterations, Table fxd_pt_sum: after k updates the
     GPU iterate equals the oracle's k-th iterate of the same method; ragged lengths spanning
     several tiles and a one-step sequence."""
@@ -160,7 +161,7 @@ def test_fixed_point_modes_match_sequential_loop(lib, mode):
     # Picard iterates of this GRU grow to ~1e3 within two updates and then hit the reset
     # guard, whose FP32 and FP64 decisions can differ; compare those relative to their size
     for k in ((1, 2) if mode == "picard" else (1, 2, 5)):
-        s, info = _run(lib, inst, max_iters=k, tol=1e-12, jac=mode)
+        s, info = _run(lib, inst, max_iters=k, tol=1e-12, jac=mode, tile=tile, group=group)
         for b in range(4):
             a, e = inst.offsets[b], inst.offsets[b + 1]
             out = newton.newton(cell, inst.x[a:e], inst.s0[b], mode=mode, tol=1e-12,
@@ -214,7 +215,8 @@ def test_jacobi_initialisation(lib):
 @pytest.mark.parametrize("damp,mode", [(dict(damping="scale", damp_k=0.3), "diagscale:0.3"),
                                        (dict(damping="clip", clip=(-0.5, 0.8)), "clip:-0.5:0.8"),
                                        (dict(damping="clip"), "clip")])
-def test_damped_transitions_match_sequential_loop(lib, damp, mode):
+@pytest.mark.parametrize("tile,group", [(64, 0), (32, 2)])
+def test_damped_transitions_match_sequential_loop(lib, damp, mode, tile, group):
     """scale-ELK and clip-ELK on the diagonal path (Sec. "Further extensions: scale- and
     clip-ELK"): iterates equal the oracle loop with the same damped transition, the first k
     steps are exact after k updates, and the loop converges to the rollout."""
@@ -222,7 +224,7 @@ def test_damped_transitions_match_sequential_loop(lib, damp, mode):
     inst = workloads.make_instance(w, seed=24, lengths=np.array([300, 65, 1, 130]))
     cell = cells.GRU(inst.params, w.D, w.Dx)
     for k in (1, 2, 5):
-        s, info = _run(lib, inst, max_iters=k, tol=1e-12, **damp)
+        s, info = _run(lib, inst, max_iters=k, tol=1e-12, tile=tile, group=group, **damp)
         for b in range(4):
             a, e = inst.offsets[b], inst.offsets[b + 1]
             out = newton.newton(cell, inst.x[a:e], inst.s0[b], mode=mode, tol=1e-12,
@@ -231,7 +233,7 @@ def test_damped_transitions_match_sequential_loop(lib, damp, mode):
             ref = rollout.rollout(cell, inst.x[a:e], inst.s0[b])
             kk = min(k, e - a)
             assert np.abs(s[a:a + kk] - ref[:kk]).max() < 1e-6
-    s, info = _run(lib, inst, tol=ERR_TOL, **damp)
+    s, info = _run(lib, inst, tol=ERR_TOL, tile=tile, group=group, **damp)
     ref = rollout.rollout_batch(cell, inst.x, inst.s0, inst.offsets)
     assert all(i["converged"] for i in info)
     assert _rel(s, ref) < 1e-5
