@@ -122,9 +122,35 @@ gru_quasi_local_kernel(GruQArgs a) {
     if (tid < 2) anybad[tid] = 0;
     int tcount = 0;                // tiles done by this workgroup (parity of anybad)
 
+    // The group and tile tables and the sequences' status are not written while the kernel
+    // runs: they are read through the scalar cache (s_load), whose short round trip is not
+    // added to every tile and whose counter is not the one the copies into LDS advance.
+    using CGroup = const __attribute__((address_space(4))) GroupInfo;
+    using CTile = const __attribute__((address_space(4))) TileInfo;
+    using CSeq = const __attribute__((address_space(4))) SeqState;
+    auto tile_at = [&](int i) {
+        CTile* ct = (CTile*)a.tiles + i;
+        TileInfo t;
+        t.slot = ct->slot;
+        t.b = ct->b;
+        t.len = ct->len;
+        t.flags = ct->flags;
+        t.row0 = ct->row0;
+        t.gslot = ct->gslot;
+        t.hgslot = ct->hgslot;
+        return t;
+    };
+
     for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
-        const GroupInfo gr = a.groups[gi];
-        if (a.seq[gr.b].status != kActive) continue;     // same on every thread
+        GroupInfo gr;
+        {
+            CGroup* cg = (CGroup*)a.groups + gi;
+            gr.b = cg->b;
+            gr.tile0 = cg->tile0;
+            gr.ntl = cg->ntl;
+            gr.gfirst = cg->gfirst;
+        }
+        if (((CSeq*)a.seq)[gr.b].status != kActive) continue;     // same on every thread
         const int b = gr.b;
         // converged-prefix skipping: the sequence's leading groups [0, frozen) take no more
         // updates; one frozen by the last carry pass gets s^(k) = s^(k-1) on its rows once
@@ -173,10 +199,10 @@ gru_quasi_local_kernel(GruQArgs a) {
             }
             bulk(xs, a.x + (size_t)t.row0 * DX, t.len * DX * 4);
         };
-        TileInfo tnext = a.tiles[gr.tile0];
+        TileInfo tnext = tile_at(gr.tile0);
         for (int kt = 0; kt < gr.ntl; ++kt) {
             const TileInfo ti = tnext;
-            if (kt + 1 < gr.ntl) tnext = a.tiles[gr.tile0 + kt + 1];   // read ahead
+            if (kt + 1 < gr.ntl) tnext = tile_at(gr.tile0 + kt + 1);   // read ahead
             const int len = ti.len;
             const int64_t row0 = ti.row0;
             const bool first = (ti.flags & kTileTimeFirst) != 0;
