@@ -339,7 +339,8 @@ pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const
    lambda: elk_solve's lambda (ignored otherwise).  probe_iters: 1..64 (<= 0: 3); each
    candidate runs probe_iters iterations with the stopping test disabled, except for the GRU
    adjoint with PN_JAC_DENSE (one map pass, then chain passes until its own test passes),
-   whose candidates are timed as whole calls at opts->tol (ms_per_iter: ms per call).
+   whose candidates (group 0, 1, 2, 3, 4, 5, 6, 8, 16) are timed as whole calls at opts->tol
+   (ms_per_iter: ms per call).
    workspace: at least pn_workspace_bytes(op | PN_OP_TUNE, ...) bytes (256-byte aligned).
    Errors: those of the solve call (a candidate that the route rejects is skipped);
    PN_ERR_HIP if timing fails. */

@@ -38,6 +38,10 @@ std::vector<Cand> candidates(int op, const pn_cell_desc& c, const pn_opts& o) {
         (o.jac == PN_JAC_DIAG || o.jac == PN_JAC_PICARD || o.jac == PN_JAC_JACOBI)) {
         for (int t : {32, 64, 128})
             for (int g : kGroups) v.push_back({t, g});
+    } else if (op == PN_OP_ADJOINT && c.cell == PN_CELL_GRU && o.jac == PN_JAC_DENSE) {
+        // the dense reverse scan's group length sets how many chain waves there are against
+        // the resident slots, so its optimum falls between the powers of two
+        for (int g : {0, 1, 2, 3, 4, 5, 6, 8, 16}) v.push_back({0, g});
     } else if ((op == PN_OP_DEER && c.cell == PN_CELL_TANH && o.jac == PN_JAC_DENSE &&
                 c.dtype == PN_F32) ||
                op == PN_OP_ADJOINT) {
