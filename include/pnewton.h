@@ -337,7 +337,8 @@ pn_status pn_lle_estimate(const pn_cell_desc* cell, const pn_batch* batch, const
      PN_OP_ADJOINT: {x, s0, s, gs, gx, gs0, gparams}; gx, gs0 may be NULL; the outputs
        gx, gs0, gparams hold unspecified values afterwards.
    lambda: elk_solve's lambda (ignored otherwise).  probe_iters: 1..64 (<= 0: 3); each
-   candidate runs probe_iters iterations with the stopping test disabled, except for the GRU
+   candidate runs once to warm up and twice timed (the faster counts), probe_iters
+   iterations with the stopping test disabled, except for the GRU
    adjoint with PN_JAC_DENSE (one map pass, then chain passes until its own test passes),
    whose candidates (group 0, 1, 2, 3, 4, 5, 6, 8, 16) are timed as whole calls at opts->tol
    (ms_per_iter: ms per call).
